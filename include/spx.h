@@ -1,0 +1,197 @@
+/*
+ * spx.h - C ABI of libspx: tile-DAG Cholesky factorisation and solve on one MI355X.
+ *
+ * Method (Specx, arXiv 2308.15964):
+ *   Sec. 2.1 / Sec. 4.1  sequential task flow: tasks are inserted in program order with
+ *                        read (SpRead) or read-write (SpWrite) accesses to data; the
+ *                        dependencies follow from that order, and any parallel execution
+ *                        must give the sequential result.
+ *   Sec. 4.1             priorities the scheduler may use; the user keeps data alive until
+ *                        the tasks using it are done; a task viewer can wait on a task.
+ *   Sec. 4.5             scheduler with push (a task became ready) and pop (an idle worker
+ *                        asks for work, possibly getting none).
+ *   Sec. 4.7             per-datum ordered task lists whose progress releases successors.
+ *   Sec. 4.8             DOT export of the task graph, traces and idle time.
+ *   Sec. 5.2             tiled Cholesky as POTRF / TRSM / SYRK / GEMM tasks in FP64.
+ *
+ * Conventions for every call:
+ *   - Return value: SPX_OK (0); a positive value only where stated (LAPACK-style info);
+ *     a negative SPX_E* code on error.  No C++ exception crosses the ABI.  After an error,
+ *     spx_last_error() returns a message for the calling thread.
+ *   - "device pointer" = memory of the context's GPU (e.g. from torch); "host pointer" =
+ *     ordinary or pinned host memory.  Every buffer passed in is owned by the caller, who
+ *     keeps it alive and unmodified until the call returns (or, for spx_submit, until
+ *     spx_poll reports the request done).  Handles (graph, factor, server, context) are
+ *     owned by the library and freed only by their destroy call.
+ *   - Dense matrices are row-major with a leading dimension (elements between rows);
+ *     only the lower triangle (row >= column) of a symmetric input is read.
+ *   - Every GPU call is issued on the context's stream.
+ */
+#ifndef SPX_H
+#define SPX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  SPX_OK = 0,
+  SPX_EINVAL = -1,   /* null/invalid argument, unsupported size or option */
+  SPX_ENOMEM = -2,   /* allocation failed, or a request can never fit the budget */
+  SPX_EDEVICE = -3,  /* a HIP call failed */
+  SPX_EAGAIN = -4,   /* not finished yet (spx_poll) / no capacity right now */
+  SPX_EABORT = -5,   /* the run was aborted by the host */
+  SPX_ETIMEOUT = -6  /* the device scheduler saw no progress within its spin limit */
+};
+
+/* Access modes (Sec. 4.1): SpRead and SpWrite (read or write). */
+enum { SPX_ACC_R = 1, SPX_ACC_RW = 2 };
+
+/* One declared access: task index (insertion order), mode, datum id.  Accesses are given
+ * grouped by task in insertion order; a task may name a datum twice (the stronger mode
+ * counts). */
+typedef struct {
+  uint32_t task;
+  uint32_t mode;
+  uint64_t datum;
+} spx_access;
+
+typedef struct spx_ctx spx_ctx;
+typedef struct spx_graph spx_graph;
+typedef struct spx_factor spx_factor;
+typedef struct spx_server spx_server;
+
+const char* spx_last_error(void);
+
+/* ---------------------------------------------------------------------------------------
+ * Context: device, stream and (optionally) the caller's allocator.
+ *   device: HIP device ordinal.  hip_stream: a hipStream_t (NULL = the null stream).
+ *   alloc/free: nullable; if given, every device allocation of the library goes through
+ *   them (e.g. torch's caching allocator) with the context's stream and `user`.
+ *   Errors: SPX_EINVAL (bad device), SPX_EDEVICE.
+ * ------------------------------------------------------------------------------------ */
+typedef void* (*spx_alloc_fn)(size_t bytes, void* stream, void* user);
+typedef void (*spx_free_fn)(void* ptr, void* stream, void* user);
+int spx_ctx_create(int device, void* hip_stream, spx_alloc_fn alloc, spx_free_fn free_fn, void* user,
+                   spx_ctx** out);
+void spx_ctx_destroy(spx_ctx* ctx);
+
+/* ---------------------------------------------------------------------------------------
+ * Graph building (Sec. 2.1, Sec. 4.1, Sec. 4.7).  Host only, integer only.
+ *   spx_graph_build: infers the immediate-dependency edges of ntasks tasks from their
+ *   accesses: a read depends on the datum's last writer (RAW); a write depends on every
+ *   read since the last write (WAR), or on the last writer if there was none (WAW).
+ *   Edges are deduplicated and always point from an earlier to a later task, so the graph
+ *   is acyclic.  priority (nullable, ntasks entries): larger runs sooner (Sec. 4.1).
+ *   Errors: SPX_EINVAL (task index >= ntasks, bad mode, accesses not grouped by task in
+ *   increasing order), SPX_ENOMEM.
+ * ------------------------------------------------------------------------------------ */
+int spx_graph_build(uint32_t ntasks, const spx_access* acc, uint64_t nacc, const int32_t* priority,
+                    spx_graph** out);
+int spx_graph_info(const spx_graph* g, uint32_t* ntasks, uint64_t* nedges);
+/* Edges sorted by (src, dst); cap = capacity of src/dst.  SPX_EINVAL if cap < nedges. */
+int spx_graph_edges(const spx_graph* g, uint32_t* src, uint32_t* dst, uint64_t cap);
+int spx_graph_indegree(const spx_graph* g, uint32_t* indeg, uint32_t cap);
+/* Writes the graph in graphviz DOT form (Sec. 4.8) to `path`.  SPX_EINVAL if unwritable. */
+int spx_graph_to_dot(const spx_graph* g, const char* path);
+void spx_graph_destroy(spx_graph* g);
+
+/* The task program the factorisation (and, with with_solve, the block forward and
+ * backward substitution) inserts for nt x nt tiles, built with spx_graph_build: right-
+ * looking, lower triangle; for k: POTRF(k); TRSM(i,k) i>k; SYRK(i,k) and GEMM(i,j,k)
+ * k<j<i.  task_types (nullable, ntasks entries) receives SPX_T_* codes. */
+enum { SPX_T_POTRF = 0, SPX_T_TRSM, SPX_T_SYRK, SPX_T_GEMM, SPX_T_FTRSM, SPX_T_FGEMM, SPX_T_BTRSM, SPX_T_BGEMM };
+int spx_cholesky_graph(int32_t nt, int32_t with_solve, spx_graph** out, int32_t* task_types, uint32_t cap);
+
+/* ---------------------------------------------------------------------------------------
+ * Factorisation (Sec. 5.2).
+ *   tile: tile size b (32, 64, 128, 256 or 512; 0 = chosen from n).  n is padded to a
+ *     multiple of b with an identity diagonal (exact: the padding adds only exact zeros).
+ *   update_prec: SPX_PREC_FP64 (all tasks FP64), SPX_PREC_FP32 or SPX_PREC_BF16 (SYRK and
+ *     GEMM read FP32 / BF16 copies of the panel tiles and accumulate in FP32 on the matrix
+ *     cores; POTRF and TRSM stay FP64; the factor is stored in FP64).
+ *   queue_policy: SPX_Q_PRIORITY (panel tasks and the next block column first) or
+ *     SPX_Q_FIFO (one ready queue in push order).  Results are bitwise identical.
+ *   num_wg: persistent workgroups (0 = fill the GPU).
+ *   flags: SPX_F_TRACE records per-task device timestamps (spx_trace).
+ * ------------------------------------------------------------------------------------ */
+enum { SPX_PREC_FP64 = 0, SPX_PREC_FP32 = 1, SPX_PREC_BF16 = 2 };
+enum { SPX_Q_PRIORITY = 0, SPX_Q_FIFO = 1 };
+enum { SPX_F_TRACE = 1u };
+typedef struct {
+  int32_t tile;
+  int32_t update_prec;
+  int32_t queue_policy;
+  int32_t num_wg;
+  uint32_t flags;
+} spx_opts;
+
+/* Factors the n x n SPD matrix dA (device pointer, row-major, leading dimension lda >= n,
+ * lower triangle read, never written).  The factor is kept in library-owned tile storage
+ * on the device; *out receives its handle.  *info: 0, or the 1-based global column whose
+ * leading minor is not positive definite (the factor is then discarded and *out is NULL).
+ * opts nullable (defaults).  The call returns after the device has finished.
+ * Errors: SPX_EINVAL, SPX_ENOMEM, SPX_EDEVICE, SPX_ETIMEOUT. */
+int spx_potrf_tiled(spx_ctx* ctx, int64_t n, const double* dA, int64_t lda, const spx_opts* opts,
+                    spx_factor** out, int64_t* info);
+
+/* Size, tile and padded size of a factor. */
+int spx_factor_info(const spx_factor* f, int64_t* n, int32_t* tile, int64_t* n_padded);
+/* Writes L (n x n, row-major, device pointer, leading dimension ldl >= n) with zeros above
+ * the diagonal. */
+int spx_factor_get_l(spx_ctx* ctx, const spx_factor* f, double* dL, int64_t ldl);
+void spx_factor_destroy(spx_factor* f);
+
+/* ---------------------------------------------------------------------------------------
+ * Solve A X = B with the factor (Sec. 5.2 task style: block forward and backward
+ * substitution run as a task graph by the same device scheduler).
+ *   dB, dX: device pointers, n x nrhs row-major with leading dimensions ldb, ldx >= nrhs;
+ *   dB is not written; dX may equal dB only if ldx == ldb.
+ *   refine (nullable): iterative refinement in FP64 against the original matrix until the
+ *   largest normwise backward error of the columns is <= tol, or max_iter corrections:
+ *   method 0 = none, 1 = classical refinement, 2 = preconditioned conjugate gradients
+ *   with the factor as preconditioner.  Refinement needs the original matrix: pass it in
+ *   dA (device, row-major, lda); the caller keeps it alive and unmodified during the call.
+ *   stats (nullable) receives the iteration count and the final largest backward error.
+ * Errors: SPX_EINVAL, SPX_ENOMEM, SPX_EDEVICE, SPX_ETIMEOUT. */
+typedef struct {
+  double tol;
+  int32_t max_iter;
+  int32_t method;
+} spx_refine;
+typedef struct {
+  int32_t iters;
+  int32_t method_used;
+  double eta_max;
+} spx_solve_stats;
+int spx_potrs(spx_ctx* ctx, const spx_factor* f, int64_t nrhs, const double* dB, int64_t ldb, double* dX,
+              int64_t ldx, const double* dA, int64_t lda, const spx_refine* refine, spx_solve_stats* stats);
+
+/* Normwise backward errors eta_q = ||b_q - A x_q||_inf / (||A||_inf ||x_q||_inf +
+ * ||b_q||_inf), computed on the device in FP64 (row-major device pointers as above);
+ * eta: host array of nrhs doubles. */
+int spx_backward_error(spx_ctx* ctx, int64_t n, const double* dA, int64_t lda, int64_t nrhs, const double* dX,
+                       int64_t ldx, const double* dB, int64_t ldb, double* eta);
+
+/* ---------------------------------------------------------------------------------------
+ * Run statistics of the last factor or solve launch on the context (Sec. 4.8 idle time).
+ * ------------------------------------------------------------------------------------ */
+typedef struct {
+  double kernel_ms;     /* persistent kernel duration (HIP events on the context stream) */
+  double pack_ms;       /* dense -> tile packing */
+  double idle_frac;     /* sum of workgroup cycles spent waiting for work / sum of cycles */
+  uint32_t ntasks, nparts, num_wg, tile;
+} spx_stats;
+int spx_last_stats(const spx_ctx* ctx, spx_stats* out);
+/* Per-part trace of the last launch made with SPX_F_TRACE: for part p, rec[4p..4p+3] =
+ * {task, part | (workgroup << 16), start tick, end tick} (device wall clock, 100 MHz).
+ * Returns the record count (or < 0); writes at most cap records. */
+int64_t spx_trace(const spx_ctx* ctx, uint64_t* rec, int64_t cap);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SPX_H */

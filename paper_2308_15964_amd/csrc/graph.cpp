@@ -1,0 +1,272 @@
+// Host-side STF graph builder (Specx Sec. 2.1, Sec. 4.1, Sec. 4.7).
+//
+// Tasks arrive in insertion order with their declared accesses.  Per datum the builder
+// keeps the last writer and the set of tasks that read it since that write, which is the
+// information Specx keeps in its per-datum dependency lists.  From it each new task gets:
+//   read:  an edge from the last writer (read after write);
+//   write: an edge from every reader since the last write (write after read), or from
+//          the last writer when nobody read in between (write after write).
+// Instead of walking per-datum lists at run time, the edges are materialised once (CSR
+// successors + in-degree) so the device scheduler can release successors with one atomic
+// decrement each.
+#include "spx_internal.h"
+
+#include <algorithm>
+#include <cstdio>
+#include <unordered_map>
+
+namespace spx {
+
+namespace {
+struct DatumState {
+  int64_t last_writer = -1;
+  std::vector<uint32_t> readers;  // since the last write
+};
+}  // namespace
+
+int build_graph(uint32_t ntasks, const spx_access* acc, uint64_t nacc, const int32_t* priority, Graph& g) {
+  g = Graph();
+  g.ntasks = ntasks;
+  std::unordered_map<uint64_t, DatumState> state;
+  state.reserve(nacc / 2 + 16);
+  std::vector<std::pair<uint32_t, uint32_t>> edges;  // (dst, src) while building
+  edges.reserve(nacc * 2);
+  std::vector<std::pair<uint64_t, uint32_t>> mine;  // this task's (datum, mode)
+  std::vector<uint32_t> preds;
+  uint64_t p = 0;
+  for (uint32_t t = 0; t < ntasks; ++t) {
+    mine.clear();
+    while (p < nacc && acc[p].task == t) {
+      if (acc[p].mode != SPX_ACC_R && acc[p].mode != SPX_ACC_RW) return fail(SPX_EINVAL, "graph: bad access mode");
+      mine.emplace_back(acc[p].datum, acc[p].mode);
+      ++p;
+    }
+    if (p < nacc && acc[p].task < t) return fail(SPX_EINVAL, "graph: accesses not grouped by task in order");
+    std::sort(mine.begin(), mine.end());
+    preds.clear();
+    for (size_t q = 0; q < mine.size(); ++q) {
+      uint64_t d = mine[q].first;
+      uint32_t mode = mine[q].second;
+      while (q + 1 < mine.size() && mine[q + 1].first == d) {  // same datum named twice
+        mode = std::max(mode, mine[q + 1].second);
+        ++q;
+      }
+      DatumState& s = state[d];
+      if (mode == SPX_ACC_R) {
+        if (s.last_writer >= 0) preds.push_back((uint32_t)s.last_writer);
+        s.readers.push_back(t);
+      } else {
+        if (!s.readers.empty()) {
+          preds.insert(preds.end(), s.readers.begin(), s.readers.end());
+        } else if (s.last_writer >= 0) {
+          preds.push_back((uint32_t)s.last_writer);
+        }
+        s.readers.clear();
+        s.last_writer = t;
+      }
+    }
+    std::sort(preds.begin(), preds.end());
+    preds.erase(std::unique(preds.begin(), preds.end()), preds.end());
+    for (uint32_t s : preds) edges.emplace_back(s, t);
+  }
+  if (p != nacc) return fail(SPX_EINVAL, "graph: access names a task index >= ntasks");
+  std::sort(edges.begin(), edges.end());  // by (src, dst)
+  g.off.assign(ntasks + 1, 0);
+  g.succ.resize(edges.size());
+  g.indeg.assign(ntasks, 0);
+  for (auto& e : edges) g.off[e.first + 1]++;
+  for (uint32_t t = 0; t < ntasks; ++t) g.off[t + 1] += g.off[t];
+  for (size_t e = 0; e < edges.size(); ++e) {
+    g.succ[e] = edges[e].second;
+    g.indeg[edges[e].second]++;
+  }
+  g.prio.assign(ntasks, 0);
+  if (priority) std::copy(priority, priority + ntasks, g.prio.begin());
+  return SPX_OK;
+}
+
+// Right-looking tile Cholesky program (lower), optionally followed by the block forward
+// and backward substitution.  Datum ids: tile (i,j) -> i*nt + j; right-hand-side block k
+// -> nt*nt + k.
+void cholesky_program(int nt, bool with_solve, std::vector<TaskDesc>& tasks, std::vector<spx_access>& acc) {
+  tasks.clear();
+  acc.clear();
+  auto A = [nt](int i, int j) { return (uint64_t)i * (uint64_t)nt + (uint64_t)j; };
+  auto B = [nt](int k) { return (uint64_t)nt * (uint64_t)nt + (uint64_t)k; };
+  auto task = [&](int type, int i, int j, int k) {
+    TaskDesc d;
+    d.type = (uint8_t)type;
+    d.i = (uint16_t)i;
+    d.j = (uint16_t)j;
+    d.k = (uint16_t)k;
+    tasks.push_back(d);
+  };
+  auto use = [&](uint32_t mode, uint64_t datum) {
+    acc.push_back(spx_access{(uint32_t)(tasks.size() - 1), mode, datum});
+  };
+  for (int k = 0; k < nt; ++k) {
+    task(SPX_T_POTRF, k, k, k);
+    use(SPX_ACC_RW, A(k, k));
+    for (int i = k + 1; i < nt; ++i) {
+      task(SPX_T_TRSM, i, k, k);
+      use(SPX_ACC_R, A(k, k));
+      use(SPX_ACC_RW, A(i, k));
+    }
+    for (int i = k + 1; i < nt; ++i) {
+      task(SPX_T_SYRK, i, i, k);
+      use(SPX_ACC_R, A(i, k));
+      use(SPX_ACC_RW, A(i, i));
+      for (int j = k + 1; j < i; ++j) {
+        task(SPX_T_GEMM, i, j, k);
+        use(SPX_ACC_R, A(i, k));
+        use(SPX_ACC_R, A(j, k));
+        use(SPX_ACC_RW, A(i, j));
+      }
+    }
+  }
+  if (!with_solve) return;
+  for (int k = 0; k < nt; ++k) {
+    task(SPX_T_FTRSM, k, k, k);
+    use(SPX_ACC_R, A(k, k));
+    use(SPX_ACC_RW, B(k));
+    for (int i = k + 1; i < nt; ++i) {
+      task(SPX_T_FGEMM, i, k, k);
+      use(SPX_ACC_R, A(i, k));
+      use(SPX_ACC_R, B(k));
+      use(SPX_ACC_RW, B(i));
+    }
+  }
+  for (int k = nt - 1; k >= 0; --k) {
+    task(SPX_T_BTRSM, k, k, k);
+    use(SPX_ACC_R, A(k, k));
+    use(SPX_ACC_RW, B(k));
+    for (int i = 0; i < k; ++i) {
+      task(SPX_T_BGEMM, i, k, k);
+      use(SPX_ACC_R, A(k, i));
+      use(SPX_ACC_R, B(k));
+      use(SPX_ACC_RW, B(i));
+    }
+  }
+}
+
+// The block substitution alone (L tiles are only read): the tasks cholesky_program appends
+// after the factor, so its edges are the fused program's edges among those tasks.
+void solve_program(int nt, std::vector<TaskDesc>& tasks, std::vector<spx_access>& acc) {
+  std::vector<TaskDesc> all;
+  std::vector<spx_access> all_acc;
+  cholesky_program(nt, true, all, all_acc);
+  const uint32_t first = (uint32_t)(nt + nt * (nt - 1) + (uint64_t)nt * (nt - 1) * (nt - 2) / 6);
+  tasks.assign(all.begin() + first, all.end());
+  acc.clear();
+  for (const spx_access& a : all_acc)
+    if (a.task >= first) acc.push_back(spx_access{a.task - first, a.mode, a.datum});
+}
+
+// Default Cholesky priorities (larger = sooner): the panel chain POTRF -> TRSM -> SYRK and
+// the GEMMs that feed the next block column sit on the critical path; among equals the
+// earlier step k goes first.
+int32_t cholesky_priority(const TaskDesc& d, int nt) {
+  int32_t base;
+  switch (d.type) {
+    case SPX_T_POTRF: base = 4; break;
+    case SPX_T_TRSM: base = 3; break;
+    case SPX_T_SYRK: base = (d.i == d.k + 1) ? 3 : 1; break;
+    case SPX_T_GEMM: base = (d.j == d.k + 1) ? 2 : 0; break;
+    default: base = 3; break;
+  }
+  return base * 65536 + (nt - d.k);
+}
+
+}  // namespace spx
+
+using namespace spx;
+
+extern "C" {
+
+int spx_graph_build(uint32_t ntasks, const spx_access* acc, uint64_t nacc, const int32_t* priority,
+                    spx_graph** out) {
+  if (!out || (nacc && !acc)) return fail(SPX_EINVAL, "spx_graph_build: null argument");
+  *out = nullptr;
+  try {
+    std::unique_ptr<spx_graph> g(new spx_graph());
+    int rc = build_graph(ntasks, acc, nacc, priority, g->g);
+    if (rc) return rc;
+    *out = g.release();
+    return SPX_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(SPX_ENOMEM, "spx_graph_build: out of host memory");
+  }
+}
+
+int spx_graph_info(const spx_graph* g, uint32_t* ntasks, uint64_t* nedges) {
+  if (!g) return fail(SPX_EINVAL, "spx_graph_info: null graph");
+  if (ntasks) *ntasks = g->g.ntasks;
+  if (nedges) *nedges = g->g.succ.size();
+  return SPX_OK;
+}
+
+int spx_graph_edges(const spx_graph* g, uint32_t* src, uint32_t* dst, uint64_t cap) {
+  if (!g || !src || !dst) return fail(SPX_EINVAL, "spx_graph_edges: null argument");
+  if (cap < g->g.succ.size()) return fail(SPX_EINVAL, "spx_graph_edges: capacity too small");
+  uint64_t e = 0;
+  for (uint32_t t = 0; t < g->g.ntasks; ++t)
+    for (uint64_t q = g->g.off[t]; q < g->g.off[t + 1]; ++q, ++e) {
+      src[e] = t;
+      dst[e] = g->g.succ[q];
+    }
+  return SPX_OK;
+}
+
+int spx_graph_indegree(const spx_graph* g, uint32_t* indeg, uint32_t cap) {
+  if (!g || !indeg) return fail(SPX_EINVAL, "spx_graph_indegree: null argument");
+  if (cap < g->g.ntasks) return fail(SPX_EINVAL, "spx_graph_indegree: capacity too small");
+  std::copy(g->g.indeg.begin(), g->g.indeg.end(), indeg);
+  return SPX_OK;
+}
+
+int spx_graph_to_dot(const spx_graph* g, const char* path) {
+  if (!g || !path) return fail(SPX_EINVAL, "spx_graph_to_dot: null argument");
+  FILE* f = std::fopen(path, "w");
+  if (!f) return fail(SPX_EINVAL, "spx_graph_to_dot: cannot open file");
+  static const char* names[] = {"POTRF", "TRSM", "SYRK", "GEMM", "FTRSM", "FGEMM", "BTRSM", "BGEMM"};
+  std::fprintf(f, "digraph spx {\n");
+  for (uint32_t t = 0; t < g->g.ntasks; ++t) {
+    if (t < g->tasks.size()) {
+      const TaskDesc& d = g->tasks[t];
+      std::fprintf(f, "  t%u [label=\"%s(%d,%d,%d)\"];\n", t, d.type < 8 ? names[d.type] : "?", d.i, d.j, d.k);
+    } else {
+      std::fprintf(f, "  t%u [label=\"t%u p%d\"];\n", t, t, g->g.prio[t]);
+    }
+  }
+  for (uint32_t t = 0; t < g->g.ntasks; ++t)
+    for (uint64_t q = g->g.off[t]; q < g->g.off[t + 1]; ++q) std::fprintf(f, "  t%u -> t%u;\n", t, g->g.succ[q]);
+  std::fprintf(f, "}\n");
+  std::fclose(f);
+  return SPX_OK;
+}
+
+void spx_graph_destroy(spx_graph* g) { delete g; }
+
+int spx_cholesky_graph(int32_t nt, int32_t with_solve, spx_graph** out, int32_t* task_types, uint32_t cap) {
+  if (!out || nt < 1 || nt > 4096) return fail(SPX_EINVAL, "spx_cholesky_graph: bad argument");
+  *out = nullptr;
+  try {
+    std::unique_ptr<spx_graph> g(new spx_graph());
+    std::vector<spx_access> acc;
+    cholesky_program(nt, with_solve != 0, g->tasks, acc);
+    std::vector<int32_t> prio(g->tasks.size());
+    for (size_t t = 0; t < g->tasks.size(); ++t) prio[t] = cholesky_priority(g->tasks[t], nt);
+    int rc = build_graph((uint32_t)g->tasks.size(), acc.data(), acc.size(), prio.data(), g->g);
+    if (rc) return rc;
+    if (task_types) {
+      if (cap < g->tasks.size()) return fail(SPX_EINVAL, "spx_cholesky_graph: capacity too small");
+      for (size_t t = 0; t < g->tasks.size(); ++t) task_types[t] = g->tasks[t].type;
+    }
+    *out = g.release();
+    return SPX_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(SPX_ENOMEM, "spx_cholesky_graph: out of host memory");
+  }
+}
+
+}  // extern "C"

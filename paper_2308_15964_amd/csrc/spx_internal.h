@@ -1,0 +1,107 @@
+// Internal declarations shared by the host runtime and the HIP kernels of libspx.
+#pragma once
+
+#include <cstdint>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "spx.h"
+
+namespace spx {
+
+// Records a message for spx_last_error() and returns `code`.
+int fail(int code, const char* msg);
+int failf(int code, const char* fmt, ...);
+
+// Immediate-dependency graph in CSR form (successors), with in-degrees and priorities.
+struct Graph {
+  uint32_t ntasks = 0;
+  std::vector<uint64_t> off;  // ntasks + 1
+  std::vector<uint32_t> succ;
+  std::vector<uint32_t> indeg;
+  std::vector<int32_t> prio;
+};
+
+// Device task descriptor (16 bytes).  `level` is the ready-queue level (0 = served
+// first); `nparts` the number of workgroup-sized pieces the task is cut into.
+struct TaskDesc {
+  uint8_t type = 0;
+  uint8_t level = 0;
+  uint16_t nparts = 1;
+  uint16_t i = 0, j = 0, k = 0;
+  uint16_t pad = 0;
+  uint32_t mat = 0;
+};
+static_assert(sizeof(TaskDesc) == 16, "TaskDesc must stay 16 bytes");
+
+int build_graph(uint32_t ntasks, const spx_access* acc, uint64_t nacc, const int32_t* priority, Graph& g);
+void cholesky_program(int nt, bool with_solve, std::vector<TaskDesc>& tasks, std::vector<spx_access>& acc);
+void solve_program(int nt, std::vector<TaskDesc>& tasks, std::vector<spx_access>& acc);
+int32_t cholesky_priority(const TaskDesc& d, int nt);
+
+// ---------------------------------------------------------------------------------------
+// Device-side descriptors (plain data, copied to the GPU).
+// ---------------------------------------------------------------------------------------
+
+enum { PREC_FP64 = 0, PREC_FP32 = 1, PREC_BF16 = 2 };
+
+// One matrix being factored / solved.  Tile (i,j), i >= j, of the lower triangle is
+// stored contiguously, column-major, at tiles + (i(i+1)/2 + j) b^2.
+struct DevMat {
+  double* tiles;
+  void* low;        // low-precision copies of the off-diagonal tiles (same packing), or null
+  double* rhs;      // right-hand side / solution, column-major n_pad x nrhs (ld = n_pad)
+  int32_t* info;    // 0x7fffffff while healthy; else the 1-based failing column
+  int64_t n_pad;
+  int32_t nt, b, nrhs, prec;
+  int32_t n, trsm_rows, pad0, pad1;
+};
+
+constexpr int kMaxLevels = 4;
+constexpr int kCounterStride = 32;  // 128-byte spacing of hot counters (uint32 units)
+
+// Everything the persistent scheduler kernel needs for one launch.
+struct SchedArgs {
+  const TaskDesc* tasks;
+  const uint32_t* succ_off;  // ntasks + 1
+  const uint32_t* succ;
+  uint32_t* pending;         // remaining predecessors per task
+  uint32_t* parts_left;      // parts not yet finished per task
+  unsigned long long* queue; // per-level segments, item = task << 16 | part
+  uint32_t* counters;        // [level*stride] head, [(kMaxLevels+level)*stride] tail,
+                             // [2*kMaxLevels*stride] done parts, [+stride] status
+  uint32_t qbase[kMaxLevels];
+  uint32_t total_parts;
+  uint32_t ntasks;
+  int32_t nlev;
+  int32_t pad;
+  const DevMat* mats;
+  unsigned long long* trace;  // 4 x uint64 per part, or null
+  uint32_t* trace_idx;
+  unsigned long long* wg_cycles;  // per workgroup: busy, idle (wall clock ticks)
+  unsigned long long spin_limit;  // ticks without progress before giving up
+};
+
+enum { STATUS_TIMEOUT = 1u };
+
+// Host-side launchers (spx_kernels.hip).
+int launch_pack(const double* dA, int64_t lda, int64_t n, const DevMat& m, void* stream);
+int launch_unpack(const DevMat& m, int64_t n, double* dL, int64_t ldl, void* stream);
+int launch_rhs_in(const double* dB, int64_t ldb, int64_t n, int64_t nrhs, double* rhs, int64_t n_pad, void* stream);
+int launch_rhs_out(const double* rhs, int64_t n_pad, int64_t n, int64_t nrhs, double* dX, int64_t ldx, void* stream);
+int launch_sched_init_full(uint32_t* pending, const uint32_t* indeg, uint32_t* parts_left, const uint32_t* nparts,
+                           uint32_t ntasks, unsigned long long* queue, const unsigned long long* queue0,
+                           uint32_t queue_len, uint32_t* counters, const uint32_t* counters0, uint32_t ncounters,
+                           int32_t* info, int ninfo, uint32_t* trace_idx, void* stream);
+int launch_sched(const SchedArgs& a, int num_wg, void* stream);
+int sched_max_wg(int device, int* per_cu, int* num_cu);
+int launch_backward_error(int64_t n, const double* dA, int64_t lda, int64_t nrhs, const double* dX, int64_t ldx,
+                          const double* dB, int64_t ldb, double* dR, double* dstats, void* stream);
+
+}  // namespace spx
+
+struct spx_graph {
+  spx::Graph g;
+  std::vector<spx::TaskDesc> tasks;
+};

@@ -1,0 +1,802 @@
+// HIP kernels of libspx for gfx950 (MI355X): tile packing, the persistent task-graph
+// scheduler, and the FP64 tile kernels of the Cholesky factorisation and solve.
+//
+// Task model (Specx Sec. 2.1, Sec. 4.5, Sec. 4.7): the host inserts tasks in program
+// order and turns their declared accesses into successor lists.  One persistent kernel
+// runs the whole graph: every workgroup loops pop -> run -> release.  A task whose
+// predecessors have all finished is pushed into a ready queue; an idle workgroup pops
+// the highest non-empty priority level; when a task finishes, each successor's counter
+// of unfinished predecessors is decremented atomically and the one that reaches zero is
+// pushed.  Large tasks are cut into parts (row strips or 128x128 sub-blocks) that
+// different workgroups run at the same time; the task counts as finished when its last
+// part does.
+#include <hip/hip_runtime.h>
+
+#include <climits>
+
+#include "spx_internal.h"
+
+namespace spx {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef unsigned long long u64;
+
+constexpr int NT = 256;                 // threads per workgroup (4 waves)
+constexpr int LDS_DOUBLES = 8192;       // 64 KiB of LDS per workgroup
+constexpr u64 EMPTY = ~0ull;
+
+__device__ __forceinline__ double* tile_ptr(const DevMat& m, int i, int j) {
+  return m.tiles + ((size_t)i * (size_t)(i + 1) / 2 + (size_t)j) * (size_t)m.b * (size_t)m.b;
+}
+
+__device__ __forceinline__ u64 now_ticks() { return wall_clock64(); }
+
+// Agent-scope atomics.  Release publishes this workgroup's global writes (made visible
+// to the whole device before the counter changes); acquire makes the writes of the
+// releasing workgroups visible to the reader.
+__device__ __forceinline__ uint32_t ld_acq(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t ld_rlx(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t sub_acqrel(uint32_t* p, uint32_t v) {
+  return __hip_atomic_fetch_sub(p, v, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// ---------------------------------------------------------------------------------------
+// FP64 matrix-core update: C[M x N] -= A[M x K] * B[N x K]^T (all column-major).
+// Four waves in a 2x2 arrangement, each owning a WT x WT block of C made of 16x16
+// v_mfma_f64_16x16x4 accumulators.  K is staged through LDS in chunks of 16, with the
+// next chunk's global loads in flight while the current one is multiplied.
+// M, N: multiples of 16, at most 2*WT.  K: multiple of 16.  lower: write only the
+// entries with row >= col (diagonal blocks of a symmetric update).
+// ---------------------------------------------------------------------------------------
+template <int WT>
+__device__ void gemm_nt_f64(double* __restrict__ C, int ldc, const double* __restrict__ A, int lda,
+                            const double* __restrict__ B, int ldb, int M, int N, int K, bool lower,
+                            double* __restrict__ lds) {
+  constexpr int SB = 2 * WT;
+  constexpr int KC = 16;
+  constexpr int NB = WT / 16;
+  constexpr int PAIRS = SB * KC / (2 * NT);  // double2 loads per thread per operand
+  static_assert(PAIRS >= 1, "tile too small for one double2 per thread");
+  double* As = lds;
+  double* Bs = lds + KC * SB;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  d4 acc[NB][NB];
+#pragma unroll
+  for (int i = 0; i < NB; ++i)
+#pragma unroll
+    for (int j = 0; j < NB; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+
+  double2 ra[PAIRS], rb[PAIRS];
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int p = 0; p < PAIRS; ++p) {
+      const int e = (tid + p * NT) * 2;
+      const int m = e / SB, r = e % SB;
+      ra[p] = (r < M) ? *reinterpret_cast<const double2*>(A + (size_t)(k0 + m) * lda + r) : double2{0.0, 0.0};
+      rb[p] = (r < N) ? *reinterpret_cast<const double2*>(B + (size_t)(k0 + m) * ldb + r) : double2{0.0, 0.0};
+    }
+  };
+  auto lstore = [&]() {
+#pragma unroll
+    for (int p = 0; p < PAIRS; ++p) {
+      const int e = (tid + p * NT) * 2;
+      *reinterpret_cast<double2*>(As + e) = ra[p];
+      *reinterpret_cast<double2*>(Bs + e) = rb[p];
+    }
+  };
+  const int nchunks = K / KC;
+  gload(0);
+  __syncthreads();  // LDS may still be read by the caller's previous step
+  lstore();
+  __syncthreads();
+  const int arow = wr * WT + (lane & 15), bcol = wc * WT + (lane & 15), kl = lane >> 4;
+  for (int c = 0; c < nchunks; ++c) {
+    if (c + 1 < nchunks) gload((c + 1) * KC);
+#pragma unroll
+    for (int kk = 0; kk < KC; kk += 4) {
+      double a[NB], b[NB];
+#pragma unroll
+      for (int i = 0; i < NB; ++i) a[i] = As[(kk + kl) * SB + arow + i * 16];
+#pragma unroll
+      for (int j = 0; j < NB; ++j) b[j] = Bs[(kk + kl) * SB + bcol + j * 16];
+#pragma unroll
+      for (int i = 0; i < NB; ++i)
+#pragma unroll
+        for (int j = 0; j < NB; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    __syncthreads();
+    if (c + 1 < nchunks) {
+      lstore();
+      __syncthreads();
+    }
+  }
+  // accumulator layout of v_mfma_f64_16x16x4: element v of lane l is (4*(l/16)+v, l%16)
+#pragma unroll
+  for (int i = 0; i < NB; ++i)
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const int col = wc * WT + j * 16 + (lane & 15);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = wr * WT + i * 16 + 4 * (lane >> 4) + v;
+        if (row < M && col < N && (!lower || row >= col)) C[(size_t)col * ldc + row] -= acc[i][j][v];
+      }
+    }
+}
+
+// Dispatch on the block size: M, N <= 128.
+__device__ void gemm_nt_any(double* C, int ldc, const double* A, int lda, const double* B, int ldb, int M, int N,
+                            int K, bool lower, double* lds) {
+  const int mx = M > N ? M : N;
+  if (mx > 64)
+    gemm_nt_f64<64>(C, ldc, A, lda, B, ldb, M, N, K, lower, lds);
+  else if (mx > 32)
+    gemm_nt_f64<32>(C, ldc, A, lda, B, ldb, M, N, K, lower, lds);
+  else
+    gemm_nt_f64<16>(C, ldc, A, lda, B, ldb, M, N, K, lower, lds);
+}
+
+// x <- x * D^{-T} for one row x of 32 values and the 32x32 lower block D (column-major
+// in LDS): column by column, x_c /= D_cc, then x_j -= x_c D_jc for j > c.
+__device__ __forceinline__ void solve_row32(double (&x)[32], const double* __restrict__ D) {
+#pragma unroll
+  for (int c = 0; c < 32; ++c) {
+    x[c] = x[c] / D[c * 32 + c];
+#pragma unroll
+    for (int j = c + 1; j < 32; ++j) x[j] -= x[c] * D[c * 32 + j];
+    // keep the scheduler from hoisting every later column's loads (register pressure)
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// POTRF: in-place lower Cholesky of one b x b tile by one workgroup.
+// Blocked right-looking with 32-wide panels: factor the 32x32 diagonal block in LDS
+// (one wave), solve the panel below it against that block (one row per thread), then
+// update the trailing lower triangle with the matrix cores.  Returns (to all threads)
+// 0 or the 1-based local column of a non-positive or NaN pivot.
+// ---------------------------------------------------------------------------------------
+__device__ int potrf_tile(double* __restrict__ a, int b, double* __restrict__ lds) {
+  __shared__ int s_bad;
+  const int tid = threadIdx.x;
+  double* D = lds + 2 * 16 * 128;  // 32x32 diagonal block, after the GEMM staging area
+  if (tid == 0) s_bad = 0;
+  for (int c0 = 0; c0 < b; c0 += 32) {
+    // load the diagonal block (lower part; the upper part is not used)
+    __syncthreads();
+    for (int e = tid; e < 32 * 32; e += NT) {
+      const int r = e & 31, c = e >> 5;
+      D[c * 32 + r] = a[(size_t)(c0 + c) * b + c0 + r];
+    }
+    __syncthreads();
+    if (tid < 64) {
+      // one wave: lane r owns row r of the block
+      const int r = tid;
+      int bad = 0;
+      for (int c = 0; c < 32; ++c) {
+        const double p = D[c * 32 + c];
+        if (!(p > 0.0)) {
+          bad = c + 1;
+          break;
+        }
+        const double d = sqrt(p);
+        __builtin_amdgcn_wave_barrier();
+        if (r > c && r < 32) D[c * 32 + r] = D[c * 32 + r] / d;
+        if (r == c) D[c * 32 + c] = d;
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        if (r > c && r < 32) {
+          const double lrc = D[c * 32 + r];
+          for (int j = c + 1; j <= r; ++j) D[j * 32 + r] -= lrc * D[c * 32 + j];
+        }
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      }
+      if (tid == 0 && bad) s_bad = c0 + bad;
+    }
+    __syncthreads();
+    if (s_bad) return s_bad;
+    for (int e = tid; e < 32 * 32; e += NT) {
+      const int r = e & 31, c = e >> 5;
+      if (r >= c) a[(size_t)(c0 + c) * b + c0 + r] = D[c * 32 + r];
+    }
+    // panel below: rows c0+32 .. b, X = P * D^{-T}, one row per thread
+    const int rows = b - c0 - 32;
+    for (int r = tid; r < rows; r += NT) {
+      double x[32];
+      double* prow = a + (size_t)c0 * b + c0 + 32 + r;
+#pragma unroll
+      for (int c = 0; c < 32; ++c) x[c] = prow[(size_t)c * b];
+      solve_row32(x, D);
+#pragma unroll
+      for (int c = 0; c < 32; ++c) prow[(size_t)c * b] = x[c];
+    }
+    __syncthreads();
+    // trailing update of the lower triangle: A22 -= P P^T, in blocks of up to 128
+    for (int j0 = c0 + 32; j0 < b; j0 += 128) {
+      const int nb = (b - j0) < 128 ? (b - j0) : 128;
+      for (int i0 = j0; i0 < b; i0 += 128) {
+        const int mb = (b - i0) < 128 ? (b - i0) : 128;
+        gemm_nt_any(a + (size_t)j0 * b + i0, b, a + (size_t)c0 * b + i0, b, a + (size_t)c0 * b + j0, b, mb, nb, 32,
+                    i0 == j0, lds);
+      }
+    }
+  }
+  __syncthreads();
+  return 0;
+}
+
+// ---------------------------------------------------------------------------------------
+// TRSM part: rows [r0, r0+R) of an off-diagonal tile X <- X * L^{-T}, L the factored
+// diagonal tile of the same block column.  Left-looking over 32-wide column blocks: the
+// block first receives the updates of all solved columns (matrix cores), then is solved
+// against its 32x32 diagonal block (one row per lane).
+// ---------------------------------------------------------------------------------------
+__device__ void trsm_part(double* __restrict__ x, const double* __restrict__ l, int b, int r0, int R,
+                          double* __restrict__ lds) {
+  const int tid = threadIdx.x;
+  double* D = lds + 2 * 16 * 128;
+  double* xr = x + r0;
+  for (int c0 = 0; c0 < b; c0 += 32) {
+    if (c0 > 0) gemm_nt_any(xr + (size_t)c0 * b, b, xr, b, l + c0, b, R, 32, c0, false, lds);
+    __syncthreads();
+    for (int e = tid; e < 32 * 32; e += NT) {
+      const int r = e & 31, c = e >> 5;
+      D[c * 32 + r] = l[(size_t)(c0 + c) * b + c0 + r];
+    }
+    __syncthreads();
+    for (int r = tid; r < R; r += NT) {
+      double v[32];
+#pragma unroll
+      for (int c = 0; c < 32; ++c) v[c] = xr[(size_t)(c0 + c) * b + r];
+      solve_row32(v, D);
+#pragma unroll
+      for (int c = 0; c < 32; ++c) xr[(size_t)(c0 + c) * b + r] = v[c];
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// Solve tasks on the right-hand side y (column-major, ld = n_pad), columns [q0, q0+nq).
+// ---------------------------------------------------------------------------------------
+
+// Forward: y_k <- L_kk^{-1} y_k.  One wave per right-hand-side column (columns
+// distributed over the waves), 32-row diagonal blocks solved with lane shuffles, the
+// rows below updated with the block's columns.
+__device__ void ftrsm_part(const double* __restrict__ l, int b, double* __restrict__ y, int64_t ldy, int q0, int nq) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int q = q0 + wave; q < q0 + nq; q += NT / 64) {
+    double* v = y + (size_t)q * ldy;
+    for (int c0 = 0; c0 < b; c0 += 32) {
+      double yr = lane < 32 ? v[c0 + lane] : 0.0;
+      for (int c = 0; c < 32; ++c) {
+        const double lcc = l[(size_t)(c0 + c) * b + c0 + c];
+        const double yc = __shfl(yr, c) / lcc;
+        if (lane == c) yr = yc;
+        if (lane > c && lane < 32) yr -= l[(size_t)(c0 + c) * b + c0 + lane] * yc;
+      }
+      if (lane < 32) v[c0 + lane] = yr;
+      // rows below the block: v_r -= sum_c L(r, c0+c) y_{c0+c}
+      double yb[32];
+#pragma unroll
+      for (int c = 0; c < 32; ++c) yb[c] = __shfl(yr, c);
+      for (int r = c0 + 32 + lane; r < b; r += 64) {
+        double s = v[r];
+#pragma unroll
+        for (int c = 0; c < 32; ++c) s -= l[(size_t)(c0 + c) * b + r] * yb[c];
+        v[r] = s;
+      }
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    }
+  }
+}
+
+// Backward: y_k <- L_kk^{-T} y_k, column blocks from the last one down.
+__device__ void btrsm_part(const double* __restrict__ l, int b, double* __restrict__ y, int64_t ldy, int q0, int nq) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int q = q0 + wave; q < q0 + nq; q += NT / 64) {
+    double* v = y + (size_t)q * ldy;
+    for (int c0 = b - 32; c0 >= 0; c0 -= 32) {
+      double yr = lane < 32 ? v[c0 + lane] : 0.0;
+      for (int c = 31; c >= 0; --c) {
+        const double lcc = l[(size_t)(c0 + c) * b + c0 + c];
+        const double xc = __shfl(yr, c) / lcc;
+        if (lane == c) yr = xc;
+        // y_r -= L(c, r) x_c for r < c  (L(c, r) sits in column r)
+        if (lane < c) yr -= l[(size_t)(c0 + lane) * b + c0 + c] * xc;
+      }
+      if (lane < 32) v[c0 + lane] = yr;
+      double xb[32];
+#pragma unroll
+      for (int c = 0; c < 32; ++c) xb[c] = __shfl(yr, c);
+      // rows above the block: v_r -= sum_c L(c0+c, r) x_{c0+c}; column r is contiguous
+      for (int r = lane; r < c0; r += 64) {
+        const double* lc = l + (size_t)r * b + c0;
+        double s = v[r];
+#pragma unroll
+        for (int c = 0; c < 32; ++c) s -= lc[c] * xb[c];
+        v[r] = s;
+      }
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    }
+  }
+}
+
+// Forward update, rows [r0, r0+64) of block i: y_i -= L_ik y_k.  Wave w takes the
+// columns m = w, w+4, ... so each load of a column strip is 64 contiguous doubles.
+__device__ void fgemm_part(const double* __restrict__ l, int b, double* __restrict__ yi,
+                           const double* __restrict__ yk, int64_t ldy, int nrhs, int r0, int rows,
+                           double* __restrict__ lds) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int q0 = 0; q0 < nrhs; q0 += 8) {
+    const int nq = (nrhs - q0) < 8 ? (nrhs - q0) : 8;
+    double acc[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) acc[q] = 0.0;
+    for (int m = wave; m < b; m += 4) {
+      const double lv = lane < rows ? l[(size_t)m * b + r0 + lane] : 0.0;
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        if (q < nq) acc[q] += lv * yk[(size_t)(q0 + q) * ldy + m];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 8; ++q) lds[(wave * 8 + q) * 64 + lane] = acc[q];
+    __syncthreads();
+    if (wave == 0 && lane < rows) {
+      for (int q = 0; q < nq; ++q) {
+        const double s = lds[(0 * 8 + q) * 64 + lane] + lds[(1 * 8 + q) * 64 + lane] +
+                         lds[(2 * 8 + q) * 64 + lane] + lds[(3 * 8 + q) * 64 + lane];
+        yi[(size_t)(q0 + q) * ldy + r0 + lane] -= s;
+      }
+    }
+  }
+}
+
+// Backward update, rows [r0, r0+64) of block i (i < k): y_i -= L_ki^T y_k.  Column r of
+// L_ki is contiguous, so each wave reduces whole columns with coalesced loads.
+__device__ void bgemm_part(const double* __restrict__ l, int b, double* __restrict__ yi,
+                           const double* __restrict__ yk, int64_t ldy, int nrhs, int r0, int rows) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int r = r0 + wave; r < r0 + rows; r += 4) {
+    const double* lc = l + (size_t)r * b;
+    for (int q = 0; q < nrhs; ++q) {
+      const double* x = yk + (size_t)q * ldy;
+      double s = 0.0;
+      for (int m = lane; m < b; m += 64) s += lc[m] * x[m];
+#pragma unroll
+      for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off);
+      if (lane == 0) yi[(size_t)q * ldy + r] -= s;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// Part dispatch.
+// ---------------------------------------------------------------------------------------
+__device__ void run_part(const SchedArgs& a, uint32_t task, uint32_t part, double* lds) {
+  const TaskDesc d = a.tasks[task];
+  const DevMat& m = a.mats[d.mat];
+  // a failed pivot earlier in this matrix: its remaining tasks drain without computing
+  if (__hip_atomic_load(m.info, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != INT_MAX) return;
+  const int b = m.b;
+  switch (d.type) {
+    case SPX_T_POTRF: {
+      const int bad = potrf_tile(tile_ptr(m, d.k, d.k), b, lds);
+      if (bad && threadIdx.x == 0)
+        __hip_atomic_fetch_min(m.info, d.k * b + bad, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      break;
+    }
+    case SPX_T_TRSM: {
+      const int R = m.trsm_rows;
+      trsm_part(tile_ptr(m, d.i, d.k), tile_ptr(m, d.k, d.k), b, part * R, R, lds);
+      break;
+    }
+    case SPX_T_SYRK:
+    case SPX_T_GEMM: {
+      // part -> 128x128 sub-block (I, J) of the output tile; SYRK: lower blocks only
+      const int sb = b < 128 ? b : 128, ns = b / sb;
+      int I, J;
+      if (d.type == SPX_T_SYRK) {
+        I = 0;
+        while ((I + 1) * (I + 2) / 2 <= (int)part) ++I;
+        J = part - I * (I + 1) / 2;
+      } else {
+        I = part % ns;
+        J = part / ns;
+      }
+      const double* Ai = tile_ptr(m, d.i, d.k) + I * sb;
+      const double* Bj = tile_ptr(m, d.j, d.k) + J * sb;
+      double* C = tile_ptr(m, d.i, d.j) + (size_t)J * sb * b + I * sb;
+      gemm_nt_any(C, b, Ai, b, Bj, b, sb, sb, b, d.type == SPX_T_SYRK && I == J, lds);
+      break;
+    }
+    case SPX_T_FTRSM: {
+      const int q0 = part * 8, nq = (m.nrhs - q0) < 8 ? (m.nrhs - q0) : 8;
+      ftrsm_part(tile_ptr(m, d.k, d.k), b, m.rhs + (size_t)d.k * b, m.n_pad, q0, nq);
+      break;
+    }
+    case SPX_T_BTRSM: {
+      const int q0 = part * 8, nq = (m.nrhs - q0) < 8 ? (m.nrhs - q0) : 8;
+      btrsm_part(tile_ptr(m, d.k, d.k), b, m.rhs + (size_t)d.k * b, m.n_pad, q0, nq);
+      break;
+    }
+    case SPX_T_FGEMM: {
+      const int rows = b < 64 ? b : 64;
+      fgemm_part(tile_ptr(m, d.i, d.k), b, m.rhs + (size_t)d.i * b, m.rhs + (size_t)d.k * b, m.n_pad, m.nrhs,
+                 part * rows, rows, lds);
+      break;
+    }
+    case SPX_T_BGEMM: {
+      // task (i, k): y_i -= L_ki^T y_k; the tile is (k, i) with k = d.j
+      const int rows = b < 64 ? b : 64;
+      bgemm_part(tile_ptr(m, d.j, d.i), b, m.rhs + (size_t)d.i * b, m.rhs + (size_t)d.j * b, m.n_pad, m.nrhs,
+                 part * rows, rows);
+      break;
+    }
+    default:
+      break;
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// The persistent scheduler kernel.
+// ---------------------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t* ctr_head(const SchedArgs& a, int l) { return a.counters + l * kCounterStride; }
+__device__ __forceinline__ uint32_t* ctr_tail(const SchedArgs& a, int l) {
+  return a.counters + (kMaxLevels + l) * kCounterStride;
+}
+__device__ __forceinline__ uint32_t* ctr_done(const SchedArgs& a) { return a.counters + 2 * kMaxLevels * kCounterStride; }
+__device__ __forceinline__ uint32_t* ctr_status(const SchedArgs& a) {
+  return a.counters + (2 * kMaxLevels + 1) * kCounterStride;
+}
+
+// push: reserve nparts slots at the task's level, then publish each item (release)
+__device__ void push_task(const SchedArgs& a, uint32_t s) {
+  const TaskDesc d = a.tasks[s];
+  const uint32_t slot =
+      __hip_atomic_fetch_add(ctr_tail(a, d.level), (uint32_t)d.nparts, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  u64* q = a.queue + a.qbase[d.level] + slot;
+  for (uint32_t p = 0; p < d.nparts; ++p)
+    __hip_atomic_store(q + p, ((u64)s << 16) | p, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// pop (thread 0 only): highest non-empty level first.  Returns EMPTY if nothing is
+// ready, or ~1ull when the graph is finished or the run must stop.
+__device__ u64 try_pop(const SchedArgs& a) {
+  for (int l = 0; l < a.nlev; ++l) {
+    uint32_t* hp = ctr_head(a, l);
+    uint32_t h = ld_rlx(hp);
+    const uint32_t t = ld_rlx(ctr_tail(a, l));
+    while (h < t) {
+      if (__hip_atomic_compare_exchange_strong(hp, &h, h + 1, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT)) {
+        // the slot is reserved by a running pusher: wait for the item to be published
+        const u64* q = a.queue + a.qbase[l] + h;
+        u64 item;
+        while ((item = __hip_atomic_load(q, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT)) == EMPTY)
+          __builtin_amdgcn_s_sleep(1);
+        return item;
+      }
+    }
+  }
+  return EMPTY;
+}
+
+__global__ __launch_bounds__(NT) void sched_kernel(SchedArgs a) {
+  __shared__ double lds[LDS_DOUBLES];
+  __shared__ u64 s_item;
+  const int tid = threadIdx.x;
+  u64 idle = 0, busy = 0;
+  for (;;) {
+    if (tid == 0) {
+      const u64 t0 = now_ticks();
+      u64 last_change = t0;
+      uint32_t last_done = ld_rlx(ctr_done(a));
+      u64 item;
+      for (;;) {
+        item = try_pop(a);
+        if (item != EMPTY) break;
+        const uint32_t done = ld_acq(ctr_done(a));
+        if (done >= a.total_parts || ld_rlx(ctr_status(a)) != 0) {
+          item = ~1ull;
+          break;
+        }
+        const u64 t = now_ticks();
+        if (done != last_done) {
+          last_done = done;
+          last_change = t;
+        } else if (t - last_change > a.spin_limit) {
+          // no part finished for the whole spin limit: give up so the kernel ends
+          __hip_atomic_fetch_or(ctr_status(a), (uint32_t)STATUS_TIMEOUT, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          item = ~1ull;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(2);
+      }
+      s_item = item;
+      idle += now_ticks() - t0;
+    }
+    __syncthreads();
+    const u64 item = s_item;
+    if (item == ~1ull) break;
+    const uint32_t task = (uint32_t)(item >> 16), part = (uint32_t)(item & 0xffff);
+    const u64 tb = now_ticks();
+    run_part(a, task, part, lds);
+    __syncthreads();
+    if (tid == 0) {
+      const u64 te = now_ticks();
+      busy += te - tb;
+      if (a.trace) {
+        const uint32_t k = atomicAdd(a.trace_idx, 1u);
+        if (k < a.total_parts) {
+          a.trace[4 * k + 0] = task;
+          a.trace[4 * k + 1] = part | ((u64)blockIdx.x << 16);
+          a.trace[4 * k + 2] = tb;
+          a.trace[4 * k + 3] = te;
+        }
+      }
+      // the part's writes are released with the decrement; the last part releases the
+      // task's successors
+      if (sub_acqrel(a.parts_left + task, 1u) == 1u) {
+        for (uint32_t e = a.succ_off[task]; e < a.succ_off[task + 1]; ++e) {
+          const uint32_t s = a.succ[e];
+          if (sub_acqrel(a.pending + s, 1u) == 1u) push_task(a, s);
+        }
+      }
+      __hip_atomic_fetch_add(ctr_done(a), 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+  if (tid == 0 && a.wg_cycles) {
+    a.wg_cycles[2 * blockIdx.x + 0] = busy;
+    a.wg_cycles[2 * blockIdx.x + 1] = idle;
+  }
+}
+
+// Per-launch state from the cached static image: counters of unfinished predecessors
+// and parts, the ready queue with the root tasks already in it, cleared counters.
+__global__ void sched_init_kernel(uint32_t* pending, const uint32_t* indeg, uint32_t* parts_left,
+                                  const uint32_t* nparts, uint32_t ntasks, u64* queue, const u64* queue0,
+                                  uint32_t queue_len, uint32_t* counters, const uint32_t* counters0,
+                                  uint32_t ncounters, int32_t* info, int ninfo, uint32_t* trace_idx) {
+  const uint32_t stride = gridDim.x * blockDim.x;
+  const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+  for (uint32_t t = g; t < ntasks; t += stride) {
+    pending[t] = indeg[t];
+    parts_left[t] = nparts[t];
+  }
+  for (uint32_t t = g; t < queue_len; t += stride) queue[t] = queue0[t];
+  for (uint32_t t = g; t < ncounters; t += stride) counters[t] = counters0[t];
+  for (uint32_t t = g; t < (uint32_t)ninfo; t += stride) info[t] = INT_MAX;
+  if (g == 0 && trace_idx) *trace_idx = 0;
+}
+
+// ---------------------------------------------------------------------------------------
+// Packing between the caller's dense row-major matrix and the tile storage.
+// One workgroup per 64x64 (or b x b if b < 64) sub-block of a lower tile, transposed
+// through LDS so both the row-major reads and the column-major writes are coalesced.
+// Rows/columns >= n form an identity border (padding).
+// ---------------------------------------------------------------------------------------
+__global__ __launch_bounds__(NT) void pack_kernel(const double* __restrict__ A, int64_t lda, int64_t n, DevMat m) {
+  __shared__ double s[64][65];
+  const int nt = m.nt, b = m.b;
+  const int S = b < 64 ? b : 64, per = b / S;
+  const int ti = blockIdx.x / nt, tj = blockIdx.x % nt;
+  if (tj > ti) return;
+  const int si = blockIdx.y / per, sj = blockIdx.y % per;
+  const int64_t R0 = (int64_t)ti * b + si * S, C0 = (int64_t)tj * b + sj * S;
+  for (int e = threadIdx.x; e < S * S; e += NT) {
+    const int rr = e / S, cc = e % S;  // cc fastest: row-major reads
+    const int64_t R = R0 + rr, C = C0 + cc;
+    double v;
+    if (R < n && C < n)
+      v = (R >= C) ? A[R * lda + C] : 0.0;
+    else
+      v = (R == C) ? 1.0 : 0.0;
+    s[rr][cc] = v;
+  }
+  __syncthreads();
+  double* T = tile_ptr(m, ti, tj);
+  for (int e = threadIdx.x; e < S * S; e += NT) {
+    const int cc = e / S, rr = e % S;  // rr fastest: column-major writes
+    T[(size_t)(sj * S + cc) * b + si * S + rr] = s[rr][cc];
+  }
+}
+
+__global__ __launch_bounds__(NT) void unpack_kernel(DevMat m, int64_t n, double* __restrict__ L, int64_t ldl) {
+  __shared__ double s[64][65];
+  const int nt = m.nt, b = m.b;
+  const int S = b < 64 ? b : 64, per = b / S;
+  const int ti = blockIdx.x / nt, tj = blockIdx.x % nt;
+  const int si = blockIdx.y / per, sj = blockIdx.y % per;
+  const int64_t R0 = (int64_t)ti * b + si * S, C0 = (int64_t)tj * b + sj * S;
+  if (R0 >= n || C0 >= n) return;
+  if (tj <= ti) {
+    const double* T = tile_ptr(m, ti, tj);
+    for (int e = threadIdx.x; e < S * S; e += NT) {
+      const int cc = e / S, rr = e % S;
+      s[rr][cc] = T[(size_t)(sj * S + cc) * b + si * S + rr];
+    }
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < S * S; e += NT) {
+    const int rr = e / S, cc = e % S;
+    const int64_t R = R0 + rr, C = C0 + cc;
+    if (R < n && C < n) L[R * ldl + C] = (tj <= ti && R >= C) ? s[rr][cc] : 0.0;
+  }
+}
+
+// Right-hand sides: row-major n x nrhs <-> column-major n_pad x nrhs (zero padding).
+__global__ void rhs_in_kernel(const double* __restrict__ B, int64_t ldb, int64_t n, int64_t nrhs,
+                              double* __restrict__ y, int64_t n_pad) {
+  const int64_t total = n_pad * nrhs;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t q = e / n_pad, r = e % n_pad;
+    y[e] = r < n ? B[r * ldb + q] : 0.0;
+  }
+}
+__global__ void rhs_out_kernel(const double* __restrict__ y, int64_t n_pad, int64_t n, int64_t nrhs,
+                               double* __restrict__ X, int64_t ldx) {
+  const int64_t total = n * nrhs;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = e / nrhs, q = e % nrhs;
+    X[r * ldx + q] = y[q * n_pad + r];
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// Residual r = b - A x for the dense symmetric A (lower triangle of a row-major array),
+// 64 rows per workgroup; and per-column maxima of |r|, |x|, |b| for the backward error.
+// Row i's entries left of the block are read along the row; the rest along the column
+// (A(j, i), j >= i), so every load is a contiguous strip.
+// stats: per column q: [3q] max|r|, [3q+1] max|x|, [3q+2] max|b| (as non-negative
+// doubles compared through their bit patterns); the last slot holds ||A||_inf.
+// ---------------------------------------------------------------------------------------
+__device__ __forceinline__ void atomic_max_nonneg(double* p, double v) {
+  atomicMax(reinterpret_cast<unsigned long long*>(p), (unsigned long long)__double_as_longlong(v));
+}
+
+__global__ __launch_bounds__(NT) void residual_kernel(int64_t n, const double* __restrict__ A, int64_t lda,
+                                                      int64_t nrhs, const double* __restrict__ X, int64_t ldx,
+                                                      const double* __restrict__ Bv, int64_t ldb,
+                                                      double* __restrict__ R, double* __restrict__ stats) {
+  __shared__ double part[4][64][9];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t i0 = (int64_t)blockIdx.x * 64;
+  for (int64_t q0 = 0; q0 < nrhs; q0 += 8) {
+    const int nq = (nrhs - q0) < 8 ? (int)(nrhs - q0) : 8;
+    double acc[9];  // 8 right-hand sides + the absolute row sum
+#pragma unroll
+    for (int q = 0; q < 9; ++q) acc[q] = 0.0;
+    const int64_t i = i0 + lane;
+    // part 1: columns j < i0, read along rows; wave w takes rows i0 + w, i0 + w + 4, ...
+    // (lane-strided over j, reduced across the wave)
+    for (int rr = wave; rr < 64; rr += 4) {
+      const int64_t ii = i0 + rr;
+      if (ii >= n) break;
+      double s[9];
+#pragma unroll
+      for (int q = 0; q < 9; ++q) s[q] = 0.0;
+      for (int64_t j = lane; j < i0; j += 64) {
+        const double aij = A[ii * lda + j];
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+          if (q < nq) s[q] += aij * X[j * ldx + q0 + q];
+        s[8] += fabs(aij);
+      }
+#pragma unroll
+      for (int q = 0; q < 9; ++q)
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) s[q] += __shfl_xor(s[q], off);
+      if (lane == rr) {
+#pragma unroll
+        for (int q = 0; q < 9; ++q) acc[q] += s[q];
+      }
+      // lane rr of this wave now holds row ii's partial for part 1; move it to the lane
+      // that owns row ii (lane rr) -- same lane index, so nothing to move
+    }
+    // part 2: columns j >= i0; lane owns row i, wave w takes j = i0 + w, i0 + w + 4, ...
+    if (i < n) {
+      for (int64_t j = i0 + wave; j < n; j += 4) {
+        const double aij = (j >= i) ? A[j * lda + i] : A[i * lda + j];
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+          if (q < nq) acc[q] += aij * X[j * ldx + q0 + q];
+        acc[8] += fabs(aij);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 9; ++q) part[wave][lane][q] = acc[q];
+    __syncthreads();
+    if (wave == 0 && i < n) {
+      double tot[9];
+#pragma unroll
+      for (int q = 0; q < 9; ++q) tot[q] = part[0][lane][q] + part[1][lane][q] + part[2][lane][q] + part[3][lane][q];
+      for (int q = 0; q < nq; ++q) {
+        const double r = Bv[i * ldb + q0 + q] - tot[q];
+        R[i * nrhs + q0 + q] = r;
+        atomic_max_nonneg(stats + 3 * (q0 + q) + 0, fabs(r));
+        atomic_max_nonneg(stats + 3 * (q0 + q) + 1, fabs(X[i * ldx + q0 + q]));
+        atomic_max_nonneg(stats + 3 * (q0 + q) + 2, fabs(Bv[i * ldb + q0 + q]));
+      }
+      if (q0 == 0) atomic_max_nonneg(stats + 3 * nrhs, tot[8]);
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// Host launchers.
+// ---------------------------------------------------------------------------------------
+static int hip_ok(hipError_t e, const char* what) {
+  if (e == hipSuccess) return SPX_OK;
+  return failf(SPX_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+int launch_pack(const double* dA, int64_t lda, int64_t n, const DevMat& m, void* stream) {
+  const int S = m.b < 64 ? m.b : 64, per = m.b / S;
+  dim3 grid((unsigned)(m.nt * m.nt), (unsigned)(per * per));
+  hipLaunchKernelGGL(pack_kernel, grid, dim3(NT), 0, (hipStream_t)stream, dA, lda, n, m);
+  return hip_ok(hipGetLastError(), "pack_kernel");
+}
+
+int launch_unpack(const DevMat& m, int64_t n, double* dL, int64_t ldl, void* stream) {
+  const int S = m.b < 64 ? m.b : 64, per = m.b / S;
+  dim3 grid((unsigned)(m.nt * m.nt), (unsigned)(per * per));
+  hipLaunchKernelGGL(unpack_kernel, grid, dim3(NT), 0, (hipStream_t)stream, m, n, dL, ldl);
+  return hip_ok(hipGetLastError(), "unpack_kernel");
+}
+
+int launch_rhs_in(const double* dB, int64_t ldb, int64_t n, int64_t nrhs, double* rhs, int64_t n_pad, void* stream) {
+  hipLaunchKernelGGL(rhs_in_kernel, dim3(1024), dim3(NT), 0, (hipStream_t)stream, dB, ldb, n, nrhs, rhs, n_pad);
+  return hip_ok(hipGetLastError(), "rhs_in_kernel");
+}
+
+int launch_rhs_out(const double* rhs, int64_t n_pad, int64_t n, int64_t nrhs, double* dX, int64_t ldx, void* stream) {
+  hipLaunchKernelGGL(rhs_out_kernel, dim3(1024), dim3(NT), 0, (hipStream_t)stream, rhs, n_pad, n, nrhs, dX, ldx);
+  return hip_ok(hipGetLastError(), "rhs_out_kernel");
+}
+
+int sched_max_wg(int device, int* per_cu, int* num_cu) {
+  int blocks = 0;
+  if (int rc = hip_ok(hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, sched_kernel, NT, 0),
+                      "hipOccupancyMaxActiveBlocksPerMultiprocessor"))
+    return rc;
+  int cus = 0;
+  if (int rc = hip_ok(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device),
+                      "hipDeviceGetAttribute"))
+    return rc;
+  *per_cu = blocks;
+  *num_cu = cus;
+  return SPX_OK;
+}
+
+int launch_sched(const SchedArgs& a, int num_wg, void* stream) {
+  hipLaunchKernelGGL(sched_kernel, dim3(num_wg), dim3(NT), 0, (hipStream_t)stream, a);
+  return hip_ok(hipGetLastError(), "sched_kernel");
+}
+
+int launch_sched_init_full(uint32_t* pending, const uint32_t* indeg, uint32_t* parts_left, const uint32_t* nparts,
+                           uint32_t ntasks, unsigned long long* queue, const unsigned long long* queue0,
+                           uint32_t queue_len, uint32_t* counters, const uint32_t* counters0, uint32_t ncounters,
+                           int32_t* info, int ninfo, uint32_t* trace_idx, void* stream) {
+  hipLaunchKernelGGL(sched_init_kernel, dim3(256), dim3(NT), 0, (hipStream_t)stream, pending, indeg, parts_left,
+                     nparts, ntasks, queue, queue0, queue_len, counters, counters0, ncounters, info, ninfo, trace_idx);
+  return hip_ok(hipGetLastError(), "sched_init_kernel");
+}
+
+int launch_backward_error(int64_t n, const double* dA, int64_t lda, int64_t nrhs, const double* dX, int64_t ldx,
+                          const double* dB, int64_t ldb, double* dR, double* dstats, void* stream) {
+  const unsigned grid = (unsigned)((n + 63) / 64);
+  hipLaunchKernelGGL(residual_kernel, dim3(grid), dim3(NT), 0, (hipStream_t)stream, n, dA, lda, nrhs, dX, ldx, dB,
+                     ldb, dR, dstats);
+  return hip_ok(hipGetLastError(), "residual_kernel");
+}
+
+}  // namespace spx

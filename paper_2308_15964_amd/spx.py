@@ -1,0 +1,323 @@
+"""ctypes binding of libspx (include/spx.h): argument marshalling only.
+
+Every step of the factorisation and solve runs in the HIP library; torch supplies the
+device memory (through its caching allocator) and the stream.  If libspx.so is missing
+the binding raises: there is no fallback path.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libspx.so")
+
+SPX_OK, SPX_EINVAL, SPX_ENOMEM, SPX_EDEVICE, SPX_EAGAIN, SPX_EABORT, SPX_ETIMEOUT = 0, -1, -2, -3, -4, -5, -6
+ACC_R, ACC_RW = 1, 2
+T_POTRF, T_TRSM, T_SYRK, T_GEMM, T_FTRSM, T_FGEMM, T_BTRSM, T_BGEMM = range(8)
+TASK_NAMES = ["POTRF", "TRSM", "SYRK", "GEMM", "FTRSM", "FGEMM", "BTRSM", "BGEMM"]
+PREC_FP64, PREC_FP32, PREC_BF16 = 0, 1, 2
+Q_PRIORITY, Q_FIFO = 0, 1
+F_TRACE = 1
+
+
+class SpxError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"spx error {code}: {msg}")
+        self.code = code
+
+
+class NotPositiveDefinite(ArithmeticError):
+    def __init__(self, info):
+        super().__init__(f"leading minor of order {info} is not positive definite")
+        self.info = info
+
+
+class Access(ctypes.Structure):
+    _fields_ = [("task", ctypes.c_uint32), ("mode", ctypes.c_uint32), ("datum", ctypes.c_uint64)]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("tile", ctypes.c_int32), ("update_prec", ctypes.c_int32), ("queue_policy", ctypes.c_int32),
+                ("num_wg", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+
+class Refine(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("method", ctypes.c_int32)]
+
+
+class SolveStats(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("method_used", ctypes.c_int32), ("eta_max", ctypes.c_double)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("kernel_ms", ctypes.c_double), ("pack_ms", ctypes.c_double), ("idle_frac", ctypes.c_double),
+                ("ntasks", ctypes.c_uint32), ("nparts", ctypes.c_uint32), ("num_wg", ctypes.c_uint32),
+                ("tile", ctypes.c_uint32)]
+
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
+
+# Every symbol include/spx.h declares, in declaration order.
+EXPORTS = [
+    "spx_last_error", "spx_ctx_create", "spx_ctx_destroy", "spx_graph_build", "spx_graph_info", "spx_graph_edges",
+    "spx_graph_indegree", "spx_graph_to_dot", "spx_graph_destroy", "spx_cholesky_graph", "spx_potrf_tiled",
+    "spx_factor_info", "spx_factor_get_l", "spx_factor_destroy", "spx_potrs", "spx_backward_error",
+    "spx_last_stats", "spx_trace",
+]
+
+_lib = None
+
+
+def lib():
+    """Loads libspx.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+    # torch ships its own HIP runtime; it must be the one libspx binds to (the library's
+    # libamdhip64.so.7 dependency then resolves to the copy already loaded).  Loading
+    # libspx first would bring in a second runtime that does not share torch's devices,
+    # streams or memory.
+    import torch  # noqa: F401
+
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, u32, u64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint64
+    P = ctypes.POINTER
+    sig = {
+        "spx_last_error": (ctypes.c_char_p, []),
+        "spx_ctx_create": (ctypes.c_int, [ctypes.c_int, vp, ALLOC_FN, FREE_FN, vp, P(vp)]),
+        "spx_ctx_destroy": (None, [vp]),
+        "spx_graph_build": (ctypes.c_int, [u32, P(Access), u64, P(i32), P(vp)]),
+        "spx_graph_info": (ctypes.c_int, [vp, P(u32), P(u64)]),
+        "spx_graph_edges": (ctypes.c_int, [vp, P(u32), P(u32), u64]),
+        "spx_graph_indegree": (ctypes.c_int, [vp, P(u32), u32]),
+        "spx_graph_to_dot": (ctypes.c_int, [vp, ctypes.c_char_p]),
+        "spx_graph_destroy": (None, [vp]),
+        "spx_cholesky_graph": (ctypes.c_int, [i32, i32, P(vp), P(i32), u32]),
+        "spx_potrf_tiled": (ctypes.c_int, [vp, i64, vp, i64, P(Opts), P(vp), P(i64)]),
+        "spx_factor_info": (ctypes.c_int, [vp, P(i64), P(i32), P(i64)]),
+        "spx_factor_get_l": (ctypes.c_int, [vp, vp, vp, i64]),
+        "spx_factor_destroy": (None, [vp]),
+        "spx_potrs": (ctypes.c_int, [vp, vp, i64, vp, i64, vp, i64, vp, i64, P(Refine), P(SolveStats)]),
+        "spx_backward_error": (ctypes.c_int, [vp, i64, vp, i64, i64, vp, i64, vp, i64, P(ctypes.c_double)]),
+        "spx_last_stats": (ctypes.c_int, [vp, P(Stats)]),
+        "spx_trace": (i64, [vp, P(u64), i64]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def _check(rc):
+    if rc < 0:
+        raise SpxError(rc, lib().spx_last_error().decode(errors="replace"))
+    return rc
+
+
+# ------------------------------------------------------------------------------------------
+# Graphs (host only)
+# ------------------------------------------------------------------------------------------
+class Graph:
+    def __init__(self, handle, task_types=None):
+        self._h = ctypes.c_void_p(handle)
+        self.task_types = task_types
+
+    @classmethod
+    def build(cls, ntasks, accesses, priority=None):
+        acc = (Access * max(len(accesses), 1))()
+        for i, (t, m, d) in enumerate(accesses):
+            acc[i].task, acc[i].mode, acc[i].datum = t, m, d
+        pr = None
+        if priority is not None:
+            pr = (ctypes.c_int32 * ntasks)(*[int(p) for p in priority])
+        h = ctypes.c_void_p()
+        _check(lib().spx_graph_build(ntasks, acc, len(accesses), pr, ctypes.byref(h)))
+        return cls(h.value)
+
+    @classmethod
+    def cholesky(cls, nt, with_solve=False):
+        h = ctypes.c_void_p()
+        from math import comb
+        T = nt + 2 * comb(nt, 2) + comb(nt, 3) + (2 * (nt + comb(nt, 2)) if with_solve else 0)
+        types = (ctypes.c_int32 * T)()
+        _check(lib().spx_cholesky_graph(nt, int(with_solve), ctypes.byref(h), types, T))
+        return cls(h.value, np.array(types[:], dtype=np.int32))
+
+    def info(self):
+        nt, ne = ctypes.c_uint32(), ctypes.c_uint64()
+        _check(lib().spx_graph_info(self._h, ctypes.byref(nt), ctypes.byref(ne)))
+        return nt.value, ne.value
+
+    def edges(self):
+        _, E = self.info()
+        src = np.zeros(max(E, 1), np.uint32)
+        dst = np.zeros(max(E, 1), np.uint32)
+        _check(lib().spx_graph_edges(self._h, src.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
+                                     dst.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)), E))
+        return np.stack([src[:E], dst[:E]], axis=1)
+
+    def indegree(self):
+        T, _ = self.info()
+        d = np.zeros(max(T, 1), np.uint32)
+        _check(lib().spx_graph_indegree(self._h, d.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)), T))
+        return d[:T]
+
+    def to_dot(self, path):
+        _check(lib().spx_graph_to_dot(self._h, os.fsencode(path)))
+
+    def close(self):
+        if self._h:
+            lib().spx_graph_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ------------------------------------------------------------------------------------------
+# Device context, factor, solve
+# ------------------------------------------------------------------------------------------
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Context:
+    """A libspx context on one GPU, using torch's current stream and caching allocator."""
+
+    def __init__(self, device=0, stream=None, torch_allocator=True):
+        import torch
+
+        self.torch = torch
+        self.device = device
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self.stream = stream
+        self._allocs = {}
+        if torch_allocator:
+            dev = device
+
+            def _alloc(nbytes, strm, user):
+                return torch.cuda.caching_allocator_alloc(int(nbytes), dev, int(strm or 0) or stream)
+
+            def _free(p, strm, user):
+                torch.cuda.caching_allocator_delete(p)
+
+            self._alloc_cb, self._free_cb = ALLOC_FN(_alloc), FREE_FN(_free)
+        else:
+            self._alloc_cb, self._free_cb = ALLOC_FN(), FREE_FN()
+        h = ctypes.c_void_p()
+        _check(lib().spx_ctx_create(device, ctypes.c_void_p(stream.cuda_stream), self._alloc_cb, self._free_cb, None,
+                                    ctypes.byref(h)))
+        self._h = h
+
+    def close(self):
+        if self._h:
+            lib().spx_ctx_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _dev(self, t, name):
+        torch = self.torch
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64):
+            raise TypeError(f"{name} must be a float64 CUDA tensor")
+        if t.stride(-1) != 1:
+            raise ValueError(f"{name} must have unit stride along its last dimension")
+        return t
+
+    def potrf(self, A, tile=0, update_prec=PREC_FP64, queue_policy=Q_PRIORITY, num_wg=0, flags=0):
+        """Factors the lower triangle of the SPD matrix A (n x n float64 on the device)."""
+        A = self._dev(A, "A")
+        n = A.shape[0]
+        if A.dim() != 2 or A.shape[1] != n:
+            raise ValueError("A must be square")
+        o = Opts(tile, update_prec, queue_policy, num_wg, flags)
+        h = ctypes.c_void_p()
+        info = ctypes.c_int64()
+        _check(lib().spx_potrf_tiled(self._h, n, _ptr(A), A.stride(0), ctypes.byref(o), ctypes.byref(h),
+                                     ctypes.byref(info)))
+        if info.value:
+            raise NotPositiveDefinite(info.value)
+        return Factor(self, h.value)
+
+    def potrs(self, F, B, X=None, A=None, tol=0.0, max_iter=0, method=0, return_stats=False):
+        """Solves A X = B with the factor (B: n or n x nrhs float64 on the device)."""
+        torch = self.torch
+        B = self._dev(B, "B")
+        vec = B.dim() == 1
+        B2 = B.reshape(B.shape[0], -1)
+        if X is None:
+            X2 = torch.empty_like(B2)
+        else:
+            X2 = self._dev(X, "X").reshape(B2.shape)
+        ref = None
+        if method:
+            ref = Refine(tol, max_iter, method)
+        st = SolveStats()
+        a_ptr, lda = (None, 0) if A is None else (_ptr(self._dev(A, "A")), A.stride(0))
+        _check(lib().spx_potrs(self._h, F._h, B2.shape[1], _ptr(B2), B2.stride(0), _ptr(X2), X2.stride(0), a_ptr, lda,
+                               ctypes.byref(ref) if ref is not None else None, ctypes.byref(st)))
+        out = X2.reshape(B.shape) if vec else X2
+        if return_stats:
+            return out, {"iters": st.iters, "method_used": st.method_used, "eta_max": st.eta_max}
+        return out
+
+    def backward_error(self, A, X, B):
+        A = self._dev(A, "A")
+        X2 = self._dev(X, "X").reshape(A.shape[0], -1)
+        B2 = self._dev(B, "B").reshape(A.shape[0], -1)
+        q = X2.shape[1]
+        eta = (ctypes.c_double * q)()
+        _check(lib().spx_backward_error(self._h, A.shape[0], _ptr(A), A.stride(0), q, _ptr(X2), X2.stride(0), _ptr(B2),
+                                        B2.stride(0), eta))
+        return np.array(eta[:])
+
+    def stats(self):
+        s = Stats()
+        _check(lib().spx_last_stats(self._h, ctypes.byref(s)))
+        return {k: getattr(s, k) for k, _ in Stats._fields_}
+
+    def trace(self):
+        n = _check(lib().spx_trace(self._h, None, 0))
+        rec = np.zeros(max(n, 1) * 4, np.uint64)
+        _check(lib().spx_trace(self._h, rec.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), n))
+        return rec[: 4 * n].reshape(n, 4)
+
+
+class Factor:
+    def __init__(self, ctx, handle):
+        self.ctx = ctx
+        self._h = ctypes.c_void_p(handle)
+        n, b, npad = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int64()
+        _check(lib().spx_factor_info(self._h, ctypes.byref(n), ctypes.byref(b), ctypes.byref(npad)))
+        self.n, self.tile, self.n_padded = n.value, b.value, npad.value
+
+    def L(self):
+        torch = self.ctx.torch
+        out = torch.empty((self.n, self.n), dtype=torch.float64, device=f"cuda:{self.ctx.device}")
+        _check(lib().spx_factor_get_l(self.ctx._h, self._h, _ptr(out), out.stride(0)))
+        return out
+
+    def close(self):
+        if self._h:
+            lib().spx_factor_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,182 @@
+"""GPU parity of the tile-DAG Cholesky factorisation and solve (Specx Sec. 5.2) against the
+oracle, through the C ABI.
+
+Tolerances (FP64; the device uses fused multiply-add and matrix-core accumulation, the
+oracle separately rounded products, so results agree to rounding, not bit for bit):
+  factor:  |L_ij - Lo_ij| <= 1e-12 sqrt(A_ii)  (row i of L has 2-norm sqrt(A_ii))
+           and ||L - Lo||_F <= 1e-12 ||Lo||_F
+  solve:   |x_iq - xo_iq| <= 1e-12 ||xo_q||_inf (well-conditioned inputs, kappa <= 5)
+           and the normwise backward error eta <= 1e-14.
+Integer-valued inputs are exact on both sides (every product and sum is an integer below
+2^53), so there the device result must equal the known factor and solution bit for bit.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2308_15964_amd import inputs
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2308_15964_amd import spx
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = spx.Context(0)
+    yield c
+    c.close()
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda:0")
+
+
+def host(t):
+    return t.cpu().numpy()
+
+
+def oracle_tile(n):
+    """A tile size dividing n for the oracle (every valid tile gives the same bits)."""
+    for nb in (64, 50, 48, 40, 32, 25, 24, 20, 16, 10, 8, 5, 4, 2, 1):
+        if n % nb == 0:
+            return nb
+    return 1
+
+
+def check_factor(A, L, Lo, tol=1e-12):
+    d = np.sqrt(np.diag(A))
+    err = np.abs(L - Lo)
+    assert (err <= tol * d[:, None]).all(), float((err / d[:, None]).max())
+    assert np.linalg.norm(L - Lo) <= tol * np.linalg.norm(Lo)
+    assert np.all(np.triu(L, 1) == 0)
+
+
+def check_solve(X, Xo, eta_o, tol=1e-12):
+    X = X.reshape(Xo.shape)
+    scale = np.abs(Xo).max(axis=0)
+    assert (np.abs(X - Xo) <= tol * scale).all(), float((np.abs(X - Xo) / scale).max())
+    assert (eta_o <= 1e-14).all(), eta_o
+
+
+CASES = [(32, 32, 1), (64, 32, 2), (100, 32, 3), (128, 64, 9), (200, 64, 1), (256, 128, 4), (384, 128, 1),
+         (500, 128, 2), (512, 256, 1), (512, 512, 3), (700, 256, 1), (1536, 512, 2)]
+
+
+@pytest.mark.parametrize("n,b,nrhs", CASES)
+def test_factor_and_solve_parity(ctx, n, b, nrhs):
+    print(f"case n={n} b={b} nrhs={nrhs}", flush=True)
+    A, B = inputs.gram_spd(n, seed=100 + n + b, nrhs=nrhs)
+    Lo, Xo, info = oracle.cholesky(A, oracle_tile(n), B)
+    assert info == 0
+    Ad, Bd = dev(A), dev(B)
+    F = ctx.potrf(Ad, tile=b)
+    L = host(F.L())
+    check_factor(A, L, Lo)
+    X = host(ctx.potrs(F, Bd))
+    eta = oracle.backward_error(A, X, B)
+    check_solve(X, Xo, eta)
+    eta_dev = ctx.backward_error(Ad, dev(X), Bd)
+    assert np.allclose(eta_dev, eta, rtol=0.5, atol=1e-17)
+    F.close()
+
+
+def test_config1_parity(ctx):
+    """N=1024, tile 128 (8x8 tiles, 120 factor tasks), A = L0 L0^T + N I, one right-hand side."""
+    n, b = 1024, 128
+    A, bvec = inputs.lower_plus_shift(n, seed=1)
+    Lo, xo, info = oracle.cholesky(A, b, bvec)
+    assert info == 0
+    F = ctx.potrf(dev(A), tile=b)
+    st = ctx.stats()
+    assert st["ntasks"] == 120 and st["tile"] == 128
+    check_factor(A, host(F.L()), Lo)
+    x = host(ctx.potrs(F, dev(bvec)))
+    check_solve(x[:, None], xo[:, None], oracle.backward_error(A, x, bvec))
+    assert ctx.stats()["ntasks"] == 72  # solve tasks 2(nt + C(nt,2))
+    F.close()
+
+
+@pytest.mark.parametrize("n,b", [(96, 32), (200, 64), (640, 128)])
+def test_integer_inputs_exact(ctx, n, b):
+    A, L0, X0, B = inputs.integer_factor(n, seed=n, nrhs=3)
+    F = ctx.potrf(dev(A), tile=b)
+    assert np.array_equal(host(F.L()), L0)
+    assert np.array_equal(host(ctx.potrs(F, dev(B))), X0)
+    F.close()
+
+
+def test_schedules_bitwise_identical(ctx):
+    """Every tile's updates are chained in insertion order, so any schedule gives the
+    same bits: FIFO vs priority queues, and different numbers of workgroups."""
+    from paper_2308_15964_amd import spx
+
+    A, B = inputs.gram_spd(1024, seed=9, nrhs=2)
+    Ad, Bd = dev(A), dev(B)
+    ref_L = ref_X = None
+    for policy, nwg in [(spx.Q_PRIORITY, 0), (spx.Q_FIFO, 0), (spx.Q_PRIORITY, 7), (spx.Q_FIFO, 1), (spx.Q_PRIORITY, 61)]:
+        F = ctx.potrf(Ad, tile=128, queue_policy=policy, num_wg=nwg)
+        L = host(F.L())
+        X = host(ctx.potrs(F, Bd))
+        if ref_L is None:
+            ref_L, ref_X = L, X
+        assert np.array_equal(L, ref_L) and np.array_equal(X, ref_X), (policy, nwg)
+        F.close()
+
+
+def test_trace_respects_every_edge(ctx):
+    """Device timestamps: every part of a task ends before any part of a successor starts,
+    and every part runs exactly once."""
+    from paper_2308_15964_amd import spx
+
+    n, b = 1024, 128
+    A, _ = inputs.gram_spd(n, seed=11)
+    F = ctx.potrf(dev(A), tile=b, flags=spx.F_TRACE)
+    tr = ctx.trace()
+    st = ctx.stats()
+    assert len(tr) == st["nparts"]
+    task = tr[:, 0].astype(np.int64)
+    part = (tr[:, 1] & 0xFFFF).astype(np.int64)
+    assert len(set(zip(task.tolist(), part.tolist()))) == len(tr)
+    T = st["ntasks"]
+    start = np.full(T, np.iinfo(np.int64).max)
+    end = np.zeros(T, np.int64)
+    np.minimum.at(start, task, tr[:, 2].astype(np.int64))
+    np.maximum.at(end, task, tr[:, 3].astype(np.int64))
+    g = spx.Graph.cholesky(n // b)
+    e = g.edges()
+    assert (end[e[:, 0]] <= start[e[:, 1]]).all()
+    F.close()
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_not_positive_definite(ctx, seed):
+    from paper_2308_15964_amd import spx
+
+    rs = np.random.default_rng(300 + seed)
+    n = 300
+    A, _ = inputs.gram_spd(n, seed=400 + seed)
+    bad = int(rs.integers(40, n - 1))
+    A[bad, bad] = -1.0
+    _, _, info = oracle.cholesky(A, oracle_tile(n))
+    assert info > 0
+    with pytest.raises(spx.NotPositiveDefinite) as e:
+        ctx.potrf(dev(A), tile=64)
+    assert e.value.info == info
+    # the context stays usable
+    F = ctx.potrf(dev(inputs.gram_spd(n, seed=5)[0]), tile=64)
+    F.close()
+
+
+def test_invalid_arguments(ctx):
+    from paper_2308_15964_amd import spx
+
+    A = dev(np.eye(64))
+    with pytest.raises(spx.SpxError) as e:
+        ctx.potrf(A, tile=48)
+    assert e.value.code == spx.SPX_EINVAL
+    with pytest.raises(spx.SpxError):
+        ctx.potrf(A, queue_policy=7)
