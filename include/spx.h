@@ -152,10 +152,13 @@ void spx_factor_destroy(spx_factor* f);
  *   dB is not written; dX may equal dB only if ldx == ldb.
  *   refine (nullable): iterative refinement in FP64 against the original matrix until the
  *   largest normwise backward error of the columns is <= tol, or max_iter corrections:
- *   method 0 = none, 1 = classical refinement, 2 = preconditioned conjugate gradients
- *   with the factor as preconditioner.  Refinement needs the original matrix: pass it in
- *   dA (device, row-major, lda); the caller keeps it alive and unmodified during the call.
- *   stats (nullable) receives the iteration count and the final largest backward error.
+ *   method 0 = none, 1 = classical refinement (r = b - A x in FP64 with the original
+ *   matrix, x += solve(L, r)), stopping early after two steps that fail to halve the
+ *   error.  Refinement needs the original matrix: pass it in dA (device, row-major, lda);
+ *   the caller keeps it alive and unmodified during the call; dX must not alias dB.
+ *   tol <= 0 means 1e-12, max_iter <= 0 means 50.
+ *   stats (nullable) receives the number of corrections and the final largest backward
+ *   error (-1 when not refining).
  * Errors: SPX_EINVAL, SPX_ENOMEM, SPX_EDEVICE, SPX_ETIMEOUT. */
 typedef struct {
   double tol;
@@ -175,6 +178,18 @@ int spx_potrs(spx_ctx* ctx, const spx_factor* f, int64_t nrhs, const double* dB,
  * eta: host array of nrhs doubles. */
 int spx_backward_error(spx_ctx* ctx, int64_t n, const double* dA, int64_t lda, int64_t nrhs, const double* dX,
                        int64_t ldx, const double* dB, int64_t ldb, double* eta);
+
+/* ---------------------------------------------------------------------------------------
+ * One task of the Cholesky / solve program (task types SPX_T_*, tile indices i, j, k as
+ * spx_cholesky_graph inserts them) run on caller-owned device storage, all of its parts
+ * in parallel: for tests of the tile kernels.
+ *   d_tiles: the lower tiles of an nt x nt tile matrix, tile (i,j), i >= j, b x b column-
+ *   major at d_tiles + (i(i+1)/2 + j) b^2 (device pointer).  d_rhs (nullable unless the
+ *   task is a solve task): nt*b x nrhs column-major.  *info: 0 or the 1-based global
+ *   column of a failed pivot (POTRF).  Errors: SPX_EINVAL (bad type, index or tile size).
+ * ------------------------------------------------------------------------------------ */
+int spx_run_task(spx_ctx* ctx, int32_t type, int32_t i, int32_t j, int32_t k, int32_t nt, int32_t b,
+                 double* d_tiles, double* d_rhs, int32_t nrhs, int64_t* info);
 
 /* ---------------------------------------------------------------------------------------
  * Run statistics of the last factor or solve launch on the context (Sec. 4.8 idle time).

@@ -60,6 +60,8 @@ def lib():
         L.orc_cholesky.restype = i64
         L.orc_cholesky.argtypes = [i64, ctypes.c_int, dp, dp, ctypes.c_int, ctypes.c_int, u64, ctypes.c_int,
                                    ctypes.POINTER(i64), i64, ctypes.POINTER(u32), ctypes.POINTER(i64)]
+        L.orc_run_task.restype = i64
+        L.orc_run_task.argtypes = [ctypes.c_int] * 4 + [dp, i64, ctypes.c_int, dp, ctypes.c_int]
         L.orc_factor_residual.restype = ctypes.c_double
         L.orc_factor_residual.argtypes = [dp, dp, i64]
         L.orc_factor_residual_probe.restype = ctypes.c_double
@@ -174,6 +176,20 @@ def cholesky(A, nb, B=None, order=ORDER_INSERTION, seed=0, nthreads=1, limit=0, 
     if return_order:
         out = out + (ordbuf[: nrun.value].copy(),)
     return out
+
+
+def run_task(name, i, j, k, M, nb, Y=None):
+    """Runs one task of the program on copies of the dense matrix M (n x n, all entries
+    used as stored: this is a kernel-level check, not the symmetric-input convention) and
+    of Y (n x nrhs).  Returns (M', Y', info)."""
+    a = np.asfortranarray(np.array(M, dtype=np.float64))
+    n = a.shape[0]
+    y = None if Y is None else np.asfortranarray(np.array(Y, dtype=np.float64).reshape(n, -1))
+    info = lib().orc_run_task(TASK_NAMES.index(name), i, j, k, _dp(a), n, nb, _dp(y) if y is not None else None,
+                              0 if y is None else y.shape[1])
+    if info < 0:
+        raise ValueError("bad task")
+    return np.ascontiguousarray(a), None if y is None else np.ascontiguousarray(y), int(info)
 
 
 def factor_residual(A, L):

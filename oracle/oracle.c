@@ -598,6 +598,15 @@ int64_t orc_cholesky(int64_t n, int nb, double* a, double* y, int nrhs, int orde
   return info;
 }
 
+/* Runs one task of the program (type codes as in orc_cholesky_program) on the dense
+ * column-major matrix a (n x n, ld = n, tile size nb) and right-hand side y (n x nrhs,
+ * ld = n).  Returns 0 or the 1-based global column of a failed pivot. */
+int64_t orc_run_task(int type, int i, int j, int k, double* a, int64_t n, int nb, double* y, int nrhs) {
+  if (!a || nb <= 0 || n % nb || type < 0 || type > T_BGEMM) return -1;
+  orc_task t = {type, i, j, k};
+  return run_task(&t, a, n, nb, y, nrhs);
+}
+
 /* The DAG of the Cholesky (+ solve) program as CSR-free edge arrays; returns the edge
  * count, or -1.  Same definition as orc_dag_edges, applied to orc_cholesky_program. */
 int64_t orc_cholesky_dag(int nt, int with_solve, uint32_t* src, uint32_t* dst, uint64_t cap,

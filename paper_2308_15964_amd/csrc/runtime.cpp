@@ -102,6 +102,7 @@ struct spx_ctx {
   size_t trace_cap = 0;  // parts
   int64_t trace_len = 0;
   std::vector<u64> host_cycles;
+  TaskDesc* dtask = nullptr;  // descriptor of single-task launches
 };
 
 struct spx_factor {
@@ -110,6 +111,7 @@ struct spx_factor {
   int32_t b = 0, nt = 0, prec = 0;
   double* tiles = nullptr;
   size_t tile_bytes = 0;
+  void* low = nullptr;  // FP32 / BF16 copies of the panel tiles (mixed precision)
 };
 
 namespace spx {
@@ -141,7 +143,7 @@ static int default_tile(int64_t n) {
 }
 
 // Parts per task for tile size b and right-hand-side count nrhs.
-static uint16_t parts_of(const TaskDesc& d, int b, int nrhs) {
+uint16_t parts_of(const TaskDesc& d, int b, int nrhs) {
   const int sb = b < 128 ? b : 128, ns = b / sb;
   const int rows = b < 64 ? b : 64;
   switch (d.type) {
@@ -398,6 +400,7 @@ void spx_ctx_destroy(spx_ctx* c) {
   dev_free(c, c->wg_cycles);
   dev_free(c, c->trace);
   dev_free(c, c->trace_idx);
+  dev_free(c, c->dtask);
   if (c->hmats) (void)hipHostFree(c->hmats);
   if (c->hinfo) (void)hipHostFree(c->hinfo);
   if (c->hcounters) (void)hipHostFree(c->hcounters);
@@ -417,7 +420,8 @@ int spx_potrf_tiled(spx_ctx* c, int64_t n, const double* dA, int64_t lda, const 
   const int policy = opts ? opts->queue_policy : SPX_Q_PRIORITY;
   if (policy != SPX_Q_PRIORITY && policy != SPX_Q_FIFO) return fail(SPX_EINVAL, "spx_potrf_tiled: bad queue policy");
   const int prec = opts ? opts->update_prec : SPX_PREC_FP64;
-  if (prec != SPX_PREC_FP64) return fail(SPX_EINVAL, "spx_potrf_tiled: this update precision is not available");
+  if (prec != SPX_PREC_FP64 && prec != SPX_PREC_FP32 && prec != SPX_PREC_BF16)
+    return fail(SPX_EINVAL, "spx_potrf_tiled: bad update precision");
   const int64_t nt = (n + b - 1) / b;
   if (nt > 2048) return fail(SPX_EINVAL, "spx_potrf_tiled: too many tiles");
   SPX_TRY(hipc(hipSetDevice(c->device), "hipSetDevice"));
@@ -431,15 +435,24 @@ int spx_potrf_tiled(spx_ctx* c, int64_t n, const double* dA, int64_t lda, const 
   f->tile_bytes = (size_t)(nt * (nt + 1) / 2) * (size_t)b * (size_t)b * sizeof(double);
   f->tiles = (double*)dev_alloc(c, f->tile_bytes);
   if (!f->tiles) return fail(SPX_ENOMEM, "spx_potrf_tiled: tile storage allocation failed");
+  if (prec != SPX_PREC_FP64) {
+    f->low = dev_alloc(c, f->tile_bytes / (prec == SPX_PREC_FP32 ? 2 : 4));
+    if (!f->low) {
+      dev_free(c, f->tiles);
+      return fail(SPX_ENOMEM, "spx_potrf_tiled: low-precision copy allocation failed");
+    }
+  }
   Image* im = nullptr;
   int rc = get_image(c, false, (int)nt, b, 0, policy, &im);
   if (!rc) rc = ensure_small_buffers(c, 1, 1, 0, false);
   if (rc) {
     dev_free(c, f->tiles);
+    dev_free(c, f->low);
     return rc;
   }
   DevMat m{};
   m.tiles = f->tiles;
+  m.low = f->low;
   m.info = c->dinfo;
   m.n_pad = f->n_pad;
   m.nt = (int32_t)nt;
@@ -459,11 +472,13 @@ int spx_potrf_tiled(spx_ctx* c, int64_t n, const double* dA, int64_t lda, const 
   }
   if (rc) {
     dev_free(c, f->tiles);
+    dev_free(c, f->low);
     return rc;
   }
   if (c->hinfo[0] != INT_MAX) {
     *info = c->hinfo[0];
     dev_free(c, f->tiles);
+    dev_free(c, f->low);
     return SPX_OK;
   }
   *out = f.release();
@@ -493,7 +508,50 @@ void spx_factor_destroy(spx_factor* f) {
   if (!f) return;
   (void)hipStreamSynchronize(f->ctx->stream);
   dev_free(f->ctx, f->tiles);
+  dev_free(f->ctx, f->low);
   delete f;
+}
+
+// Runs the solve graph of factor f on the column-major work buffer rhs (n_pad x nrhs).
+static int solve_on(spx_ctx* c, const spx_factor* f, int64_t nrhs, double* rhs) {
+  Image* im = nullptr;
+  SPX_TRY(get_image(c, true, f->nt, f->b, (int)nrhs, SPX_Q_PRIORITY, &im));
+  SPX_TRY(ensure_small_buffers(c, 1, 1, 0, false));
+  DevMat m{};
+  m.tiles = f->tiles;
+  m.rhs = rhs;
+  m.info = c->dinfo;
+  m.n_pad = f->n_pad;
+  m.nt = f->nt;
+  m.b = f->b;
+  m.nrhs = (int32_t)nrhs;
+  m.prec = PREC_FP64;  // the solve always reads the FP64 factor
+  m.n = (int32_t)f->n;
+  m.trsm_rows = 32;
+  c->hmats[0] = m;
+  return run_image(c, im, 1, nullptr, 0.0);
+}
+
+// r = b - A x and the per-column maxima for the backward error; returns eta per column in
+// eta (host) and the largest in *eta_max.
+static int residual_eta(spx_ctx* c, int64_t n, const double* dA, int64_t lda, int64_t nrhs, const double* dX,
+                        int64_t ldx, const double* dB, int64_t ldb, double* R, double* S, std::vector<double>& hs,
+                        double* eta, double* eta_max) {
+  const size_t sbytes = sizeof(double) * (size_t)(3 * nrhs + 1);
+  SPX_TRY(hipc(hipMemsetAsync(S, 0, sbytes, c->stream), "hipMemsetAsync"));
+  SPX_TRY(launch_backward_error(n, dA, lda, nrhs, dX, ldx, dB, ldb, R, S, c->stream));
+  hs.resize(3 * nrhs + 1);
+  SPX_TRY(hipc(hipMemcpyAsync(hs.data(), S, sbytes, hipMemcpyDeviceToHost, c->stream), "stats"));
+  SPX_TRY(hipc(hipStreamSynchronize(c->stream), "hipStreamSynchronize"));
+  const double anorm = hs[3 * nrhs];
+  double worst = 0.0;
+  for (int64_t q = 0; q < nrhs; ++q) {
+    const double e = hs[3 * q] / (anorm * hs[3 * q + 1] + hs[3 * q + 2]);
+    if (eta) eta[q] = e;
+    if (!(e <= worst)) worst = e;  // NaN propagates
+  }
+  *eta_max = worst;
+  return SPX_OK;
 }
 
 int spx_potrs(spx_ctx* c, const spx_factor* f, int64_t nrhs, const double* dB, int64_t ldb, double* dX, int64_t ldx,
@@ -501,39 +559,56 @@ int spx_potrs(spx_ctx* c, const spx_factor* f, int64_t nrhs, const double* dB, i
   if (!c || !f || !dB || !dX) return fail(SPX_EINVAL, "spx_potrs: null argument");
   if (nrhs < 1 || nrhs > 4096 || ldb < nrhs || ldx < nrhs) return fail(SPX_EINVAL, "spx_potrs: bad nrhs / ld");
   if (dX == dB && ldx != ldb) return fail(SPX_EINVAL, "spx_potrs: aliased X and B need equal leading dimensions");
-  if (refine && refine->method != 0) return fail(SPX_EINVAL, "spx_potrs: refinement is not available");
-  (void)dA;
-  (void)lda;
+  const int method = refine ? refine->method : 0;
+  if (method < 0 || method > 1) return fail(SPX_EINVAL, "spx_potrs: refinement method must be 0 or 1");
+  if (method && (!dA || lda < f->n)) return fail(SPX_EINVAL, "spx_potrs: refinement needs the original matrix");
+  if (method && dX == dB) return fail(SPX_EINVAL, "spx_potrs: refinement needs X distinct from B");
   SPX_TRY(hipc(hipSetDevice(c->device), "hipSetDevice"));
   double* rhs = (double*)dev_alloc(c, (size_t)f->n_pad * (size_t)nrhs * sizeof(double));
-  if (!rhs) return fail(SPX_ENOMEM, "spx_potrs: work buffer allocation failed");
-  Image* im = nullptr;
-  int rc = get_image(c, true, f->nt, f->b, (int)nrhs, SPX_Q_PRIORITY, &im);
-  if (!rc) rc = ensure_small_buffers(c, 1, 1, 0, false);
+  double* R = method ? (double*)dev_alloc(c, (size_t)f->n * (size_t)nrhs * sizeof(double)) : nullptr;
+  double* S = method ? (double*)dev_alloc(c, sizeof(double) * (size_t)(3 * nrhs + 1)) : nullptr;
+  int rc = (!rhs || (method && (!R || !S))) ? fail(SPX_ENOMEM, "spx_potrs: work buffer allocation failed") : SPX_OK;
   if (!rc) rc = launch_rhs_in(dB, ldb, f->n, nrhs, rhs, f->n_pad, c->stream);
-  if (!rc) {
-    DevMat m{};
-    m.tiles = f->tiles;
-    m.rhs = rhs;
-    m.info = c->dinfo;
-    m.n_pad = f->n_pad;
-    m.nt = f->nt;
-    m.b = f->b;
-    m.nrhs = (int32_t)nrhs;
-    m.prec = f->prec;
-    m.n = (int32_t)f->n;
-    m.trsm_rows = 32;
-    c->hmats[0] = m;
-    rc = run_image(c, im, 1, nullptr, 0.0);
+  if (!rc) rc = solve_on(c, f, nrhs, rhs);
+  if (!rc) rc = launch_rhs_out(rhs, f->n_pad, f->n, nrhs, dX, ldx, 0, c->stream);
+  int iters = 0;
+  double eta_max = -1.0;
+  double solve_ms = c->last.kernel_ms;
+  if (!rc && method == 1) {
+    // classical iterative refinement: r = b - A x in FP64 with the original matrix,
+    // d = solve(L, r), x += d, until the largest normwise backward error <= tol
+    std::vector<double> hs;
+    const double tol = refine->tol > 0 ? refine->tol : 1e-12;
+    const int max_iter = refine->max_iter > 0 ? refine->max_iter : 50;
+    double prev = INFINITY;
+    int slow = 0;
+    for (;;) {
+      rc = residual_eta(c, f->n, dA, lda, nrhs, dX, ldx, dB, ldb, R, S, hs, nullptr, &eta_max);
+      if (rc || eta_max <= tol || iters >= max_iter) break;
+      if (!(eta_max < 0.5 * prev)) {  // stagnation (or NaN): stop after two slow steps
+        if (++slow >= 2 || eta_max != eta_max) break;
+      } else {
+        slow = 0;
+      }
+      prev = eta_max;
+      rc = launch_rhs_in(R, nrhs, f->n, nrhs, rhs, f->n_pad, c->stream);
+      if (!rc) rc = solve_on(c, f, nrhs, rhs);
+      if (!rc) rc = launch_rhs_out(rhs, f->n_pad, f->n, nrhs, dX, ldx, 1, c->stream);
+      if (!rc) solve_ms += c->last.kernel_ms;
+      if (rc) break;
+      ++iters;
+    }
   }
-  if (!rc) rc = launch_rhs_out(rhs, f->n_pad, f->n, nrhs, dX, ldx, c->stream);
   if (!rc) rc = hipc(hipStreamSynchronize(c->stream), "hipStreamSynchronize");
   dev_free(c, rhs);
+  dev_free(c, R);
+  dev_free(c, S);
   if (rc) return rc;
+  c->last.kernel_ms = solve_ms;  // all solve launches of this call
   if (stats) {
-    stats->iters = 0;
-    stats->method_used = 0;
-    stats->eta_max = -1.0;
+    stats->iters = iters;
+    stats->method_used = method;
+    stats->eta_max = eta_max;
   }
   return SPX_OK;
 }
@@ -557,6 +632,62 @@ int spx_backward_error(spx_ctx* c, int64_t n, const double* dA, int64_t lda, int
   if (rc) return rc;
   const double anorm = hs[3 * nrhs];
   for (int64_t q = 0; q < nrhs; ++q) eta[q] = hs[3 * q] / (anorm * hs[3 * q + 1] + hs[3 * q + 2]);
+  return SPX_OK;
+}
+
+int spx_run_task(spx_ctx* c, int32_t type, int32_t i, int32_t j, int32_t k, int32_t nt, int32_t b, double* d_tiles,
+                 double* d_rhs, int32_t nrhs, int64_t* info) {
+  if (!c || !d_tiles || !info) return fail(SPX_EINVAL, "spx_run_task: null argument");
+  if (!valid_tile(b) || nt < 1 || nt > 2048) return fail(SPX_EINVAL, "spx_run_task: bad tile size or count");
+  if (type < SPX_T_POTRF || type > SPX_T_BGEMM) return fail(SPX_EINVAL, "spx_run_task: bad task type");
+  const bool solve = type >= SPX_T_FTRSM;
+  if (solve && (!d_rhs || nrhs < 1 || nrhs > 4096)) return fail(SPX_EINVAL, "spx_run_task: solve task needs rhs");
+  auto in = [nt](int x) { return x >= 0 && x < nt; };
+  bool ok = in(i) && in(j) && in(k);
+  switch (type) {
+    case SPX_T_POTRF: ok = ok && i == k && j == k; break;
+    case SPX_T_TRSM: ok = ok && i > k && j == k; break;
+    case SPX_T_SYRK: ok = ok && i > k && j == i; break;
+    case SPX_T_GEMM: ok = ok && i > j && j > k; break;
+    case SPX_T_FTRSM: case SPX_T_BTRSM: ok = ok && i == k && j == k; break;
+    case SPX_T_FGEMM: ok = ok && i > k && j == k; break;
+    case SPX_T_BGEMM: ok = ok && i < j && j == k; break;
+  }
+  if (!ok) return fail(SPX_EINVAL, "spx_run_task: tile indices do not fit the task type");
+  SPX_TRY(hipc(hipSetDevice(c->device), "hipSetDevice"));
+  SPX_TRY(ensure_small_buffers(c, 1, 1, 0, false));
+  if (!c->dtask) {
+    c->dtask = (TaskDesc*)dev_alloc(c, sizeof(TaskDesc));
+    if (!c->dtask) return fail(SPX_ENOMEM, "spx_run_task: allocation failed");
+  }
+  TaskDesc d;
+  d.type = (uint8_t)type;
+  d.i = (uint16_t)i;
+  d.j = (uint16_t)j;
+  d.k = (uint16_t)k;
+  d.nparts = parts_of(d, b, nrhs);
+  DevMat m{};
+  m.tiles = d_tiles;
+  m.rhs = d_rhs;
+  m.info = c->dinfo;
+  m.n_pad = (int64_t)nt * b;
+  m.nt = nt;
+  m.b = b;
+  m.nrhs = nrhs;
+  m.n = nt * b;
+  m.trsm_rows = 32;
+  c->hmats[0] = m;
+  const int32_t healthy = INT_MAX;
+  SPX_TRY(hipc(hipMemcpyAsync(c->dtask, &d, sizeof d, hipMemcpyHostToDevice, c->stream), "task upload"));
+  SPX_TRY(hipc(hipMemcpyAsync(c->dmats, c->hmats, sizeof(DevMat), hipMemcpyHostToDevice, c->stream), "upload"));
+  SPX_TRY(hipc(hipMemcpyAsync(c->dinfo, &healthy, 4, hipMemcpyHostToDevice, c->stream), "upload"));
+  SchedArgs a{};
+  a.tasks = c->dtask;
+  a.mats = c->dmats;
+  SPX_TRY(launch_one_task(a, d.nparts, c->stream));
+  SPX_TRY(hipc(hipMemcpyAsync(c->hinfo, c->dinfo, 4, hipMemcpyDeviceToHost, c->stream), "info"));
+  SPX_TRY(hipc(hipStreamSynchronize(c->stream), "hipStreamSynchronize"));
+  *info = c->hinfo[0] == INT_MAX ? 0 : c->hinfo[0];
   return SPX_OK;
 }
 

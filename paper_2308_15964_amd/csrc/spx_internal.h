@@ -89,12 +89,15 @@ enum { STATUS_TIMEOUT = 1u };
 int launch_pack(const double* dA, int64_t lda, int64_t n, const DevMat& m, void* stream);
 int launch_unpack(const DevMat& m, int64_t n, double* dL, int64_t ldl, void* stream);
 int launch_rhs_in(const double* dB, int64_t ldb, int64_t n, int64_t nrhs, double* rhs, int64_t n_pad, void* stream);
-int launch_rhs_out(const double* rhs, int64_t n_pad, int64_t n, int64_t nrhs, double* dX, int64_t ldx, void* stream);
+int launch_rhs_out(const double* rhs, int64_t n_pad, int64_t n, int64_t nrhs, double* dX, int64_t ldx, int accumulate,
+                   void* stream);
 int launch_sched_init_full(uint32_t* pending, const uint32_t* indeg, uint32_t* parts_left, const uint32_t* nparts,
                            uint32_t ntasks, unsigned long long* queue, const unsigned long long* queue0,
                            uint32_t queue_len, uint32_t* counters, const uint32_t* counters0, uint32_t ncounters,
                            int32_t* info, int ninfo, uint32_t* trace_idx, void* stream);
 int launch_sched(const SchedArgs& a, int num_wg, void* stream);
+int launch_one_task(const SchedArgs& a, int nparts, void* stream);
+uint16_t parts_of(const TaskDesc& d, int b, int nrhs);
 int sched_max_wg(int device, int* per_cu, int* num_cu);
 int launch_backward_error(int64_t n, const double* dA, int64_t lda, int64_t nrhs, const double* dX, int64_t ldx,
                           const double* dB, int64_t ldb, double* dR, double* dstats, void* stream);

@@ -115,7 +115,8 @@ __device__ void gemm_nt_f64(double* __restrict__ C, int ldc, const double* __res
       __syncthreads();
     }
   }
-  // accumulator layout of v_mfma_f64_16x16x4: element v of lane l is (4*(l/16)+v, l%16)
+  // accumulator layout of v_mfma_f64_16x16x4 (measured on gfx950): element v of lane l
+  // holds (row l/16 + 4v, column l%16) of the 16x16 block
 #pragma unroll
   for (int i = 0; i < NB; ++i)
 #pragma unroll
@@ -123,7 +124,7 @@ __device__ void gemm_nt_f64(double* __restrict__ C, int ldc, const double* __res
       const int col = wc * WT + j * 16 + (lane & 15);
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int row = wr * WT + i * 16 + 4 * (lane >> 4) + v;
+        const int row = wr * WT + i * 16 + (lane >> 4) + 4 * v;
         if (row < M && col < N && (!lower || row >= col)) C[(size_t)col * ldc + row] -= acc[i][j][v];
       }
     }
@@ -139,6 +140,181 @@ __device__ void gemm_nt_any(double* C, int ldc, const double* A, int lda, const 
     gemm_nt_f64<32>(C, ldc, A, lda, B, ldb, M, N, K, lower, lds);
   else
     gemm_nt_f64<16>(C, ldc, A, lda, B, ldb, M, N, K, lower, lds);
+}
+
+// ---------------------------------------------------------------------------------------
+// Mixed-precision updates: C (FP64) -= A * B^T with A, B low-precision copies of panel
+// tiles, products accumulated in FP32 on the matrix cores.  Same 2x2-wave arrangement as
+// the FP64 update.  M, N <= 2*WT (multiples of 16), K = tile size.
+// ---------------------------------------------------------------------------------------
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+
+// FP32 copies, column-major (like the FP64 tiles); v_mfma_f32_16x16x4f32, whose result
+// element v of lane l is (row 4*(l/16)+v, column l%16) of the 16x16 block.
+template <int WT>
+__device__ void gemm_nt_f32(double* __restrict__ C, int ldc, const float* __restrict__ A, int lda,
+                            const float* __restrict__ B, int ldb, int M, int N, int K, bool lower,
+                            double* __restrict__ lds_d) {
+  constexpr int SB = 2 * WT, KC = 32, NB = WT / 16;
+  constexpr int QUADS = SB * KC / (4 * NT);  // float4 loads per thread per operand
+  static_assert(QUADS >= 1, "tile too small");
+  float* As = reinterpret_cast<float*>(lds_d);
+  float* Bs = As + KC * SB;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  f4 acc[NB][NB];
+#pragma unroll
+  for (int i = 0; i < NB; ++i)
+#pragma unroll
+    for (int j = 0; j < NB; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+  float4 ra[QUADS], rb[QUADS];
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int p = 0; p < QUADS; ++p) {
+      const int e = (tid + p * NT) * 4;
+      const int m = e / SB, r = e % SB;
+      ra[p] = (r < M) ? *reinterpret_cast<const float4*>(A + (size_t)(k0 + m) * lda + r) : float4{0.f, 0.f, 0.f, 0.f};
+      rb[p] = (r < N) ? *reinterpret_cast<const float4*>(B + (size_t)(k0 + m) * ldb + r) : float4{0.f, 0.f, 0.f, 0.f};
+    }
+  };
+  auto lstore = [&]() {
+#pragma unroll
+    for (int p = 0; p < QUADS; ++p) {
+      const int e = (tid + p * NT) * 4;
+      *reinterpret_cast<float4*>(As + e) = ra[p];
+      *reinterpret_cast<float4*>(Bs + e) = rb[p];
+    }
+  };
+  const int nchunks = K / KC;
+  gload(0);
+  __syncthreads();
+  lstore();
+  __syncthreads();
+  const int arow = wr * WT + (lane & 15), bcol = wc * WT + (lane & 15), kl = lane >> 4;
+  for (int c = 0; c < nchunks; ++c) {
+    if (c + 1 < nchunks) gload((c + 1) * KC);
+#pragma unroll
+    for (int kk = 0; kk < KC; kk += 4) {
+      float a[NB], bq[NB];
+#pragma unroll
+      for (int i = 0; i < NB; ++i) a[i] = As[(kk + kl) * SB + arow + i * 16];
+#pragma unroll
+      for (int j = 0; j < NB; ++j) bq[j] = Bs[(kk + kl) * SB + bcol + j * 16];
+#pragma unroll
+      for (int i = 0; i < NB; ++i)
+#pragma unroll
+        for (int j = 0; j < NB; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], bq[j], acc[i][j], 0, 0, 0);
+    }
+    __syncthreads();
+    if (c + 1 < nchunks) {
+      lstore();
+      __syncthreads();
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < NB; ++i)
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const int col = wc * WT + j * 16 + (lane & 15);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = wr * WT + i * 16 + 4 * (lane >> 4) + v;
+        if (row < M && col < N && (!lower || row >= col)) C[(size_t)col * ldc + row] -= (double)acc[i][j][v];
+      }
+    }
+}
+
+// BF16 copies, row-major inside the tile (element (r, k) at r*ld + k) so that the eight
+// consecutive k a lane feeds to v_mfma_f32_16x16x32_bf16 are contiguous: lane l supplies
+// A[l%16][8(l/16) .. 8(l/16)+7] and B^T likewise; result layout as for the FP32 form.
+template <int WT>
+__device__ void gemm_nt_bf16(double* __restrict__ C, int ldc, const uint16_t* __restrict__ A, int lda,
+                             const uint16_t* __restrict__ B, int ldb, int M, int N, int K, bool lower,
+                             double* __restrict__ lds_d) {
+  constexpr int SB = 2 * WT, KC = 32, NB = WT / 16, LS = KC + 8;  // padded LDS row
+  constexpr int CH = SB * (KC / 8);                                 // 16-byte chunks per operand
+  constexpr int PER = (CH + NT - 1) / NT;
+  uint16_t* As = reinterpret_cast<uint16_t*>(lds_d);
+  uint16_t* Bs = As + SB * LS;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  f4 acc[NB][NB];
+#pragma unroll
+  for (int i = 0; i < NB; ++i)
+#pragma unroll
+    for (int j = 0; j < NB; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+  uint4 ra[PER], rb[PER];
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int p = 0; p < PER; ++p) {
+      const int e = tid + p * NT;  // chunk: row e / 4, k offset 8 (e % 4)
+      const int r = e >> 2, kq = (e & 3) * 8;
+      const uint4 z = {0u, 0u, 0u, 0u};
+      ra[p] = (e < CH && r < M) ? *reinterpret_cast<const uint4*>(A + (size_t)r * lda + k0 + kq) : z;
+      rb[p] = (e < CH && r < N) ? *reinterpret_cast<const uint4*>(B + (size_t)r * ldb + k0 + kq) : z;
+    }
+  };
+  auto lstore = [&]() {
+#pragma unroll
+    for (int p = 0; p < PER; ++p) {
+      const int e = tid + p * NT;
+      if (e < CH) {
+        const int r = e >> 2, kq = (e & 3) * 8;
+        *reinterpret_cast<uint4*>(As + r * LS + kq) = ra[p];
+        *reinterpret_cast<uint4*>(Bs + r * LS + kq) = rb[p];
+      }
+    }
+  };
+  const int nchunks = K / KC;
+  gload(0);
+  __syncthreads();
+  lstore();
+  __syncthreads();
+  const int arow = wr * WT + (lane & 15), bcol = wc * WT + (lane & 15), kq = 8 * (lane >> 4);
+  for (int c = 0; c < nchunks; ++c) {
+    if (c + 1 < nchunks) gload((c + 1) * KC);
+    bf8 a[NB], bq[NB];
+#pragma unroll
+    for (int i = 0; i < NB; ++i) a[i] = __builtin_bit_cast(bf8, *reinterpret_cast<const uint4*>(As + (arow + i * 16) * LS + kq));
+#pragma unroll
+    for (int j = 0; j < NB; ++j) bq[j] = __builtin_bit_cast(bf8, *reinterpret_cast<const uint4*>(Bs + (bcol + j * 16) * LS + kq));
+#pragma unroll
+    for (int i = 0; i < NB; ++i)
+#pragma unroll
+      for (int j = 0; j < NB; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], bq[j], acc[i][j], 0, 0, 0);
+    __syncthreads();
+    if (c + 1 < nchunks) {
+      lstore();
+      __syncthreads();
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < NB; ++i)
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const int col = wc * WT + j * 16 + (lane & 15);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = wr * WT + i * 16 + 4 * (lane >> 4) + v;
+        if (row < M && col < N && (!lower || row >= col)) C[(size_t)col * ldc + row] -= (double)acc[i][j][v];
+      }
+    }
+}
+
+// FP64 -> BF16, round to nearest even, directly from the double (no intermediate FP32
+// rounding).  Magnitudes below the FP32 normal range flush to a signed zero.
+__device__ __forceinline__ uint16_t to_bf16(double x) {
+  unsigned long long u = (unsigned long long)__double_as_longlong(x);
+  const unsigned long long sign = u >> 63;
+  u &= 0x7fffffffffffffffull;
+  if (u >= 0x7ff0000000000000ull) return (uint16_t)((sign << 15) | 0x7f80u | (u > 0x7ff0000000000000ull ? 0x40u : 0u));
+  const unsigned long long lsb = (u >> 45) & 1ull;
+  u += (1ull << 44) - 1ull + lsb;  // 45 dropped bits: round half to even
+  const int e = (int)(u >> 52) - 1023 + 127;
+  if (e <= 0) return (uint16_t)(sign << 15);
+  if (e >= 255) return (uint16_t)((sign << 15) | 0x7f80u);
+  return (uint16_t)((sign << 15) | ((unsigned)e << 7) | (unsigned)((u >> 45) & 0x7fu));
 }
 
 // x <- x * D^{-T} for one row x of 32 values and the 32x32 lower block D (column-major
@@ -238,7 +414,7 @@ __device__ int potrf_tile(double* __restrict__ a, int b, double* __restrict__ ld
 // against its 32x32 diagonal block (one row per lane).
 // ---------------------------------------------------------------------------------------
 __device__ void trsm_part(double* __restrict__ x, const double* __restrict__ l, int b, int r0, int R,
-                          double* __restrict__ lds) {
+                          void* __restrict__ low, int prec, double* __restrict__ lds) {
   const int tid = threadIdx.x;
   double* D = lds + 2 * 16 * 128;
   double* xr = x + r0;
@@ -257,6 +433,16 @@ __device__ void trsm_part(double* __restrict__ x, const double* __restrict__ l, 
       solve_row32(v, D);
 #pragma unroll
       for (int c = 0; c < 32; ++c) xr[(size_t)(c0 + c) * b + r] = v[c];
+      // mixed precision: the copy the updates read (FP32 column-major, BF16 row-major)
+      if (prec == PREC_FP32) {
+        float* lf = reinterpret_cast<float*>(low) + r0;
+#pragma unroll
+        for (int c = 0; c < 32; ++c) lf[(size_t)(c0 + c) * b + r] = (float)v[c];
+      } else if (prec == PREC_BF16) {
+        uint16_t* lh = reinterpret_cast<uint16_t*>(low) + (size_t)(r0 + r) * b + c0;
+#pragma unroll
+        for (int c = 0; c < 32; ++c) lh[c] = to_bf16(v[c]);
+      }
     }
     __syncthreads();
   }
@@ -395,7 +581,11 @@ __device__ void run_part(const SchedArgs& a, uint32_t task, uint32_t part, doubl
     }
     case SPX_T_TRSM: {
       const int R = m.trsm_rows;
-      trsm_part(tile_ptr(m, d.i, d.k), tile_ptr(m, d.k, d.k), b, part * R, R, lds);
+      const size_t off = ((size_t)d.i * (d.i + 1) / 2 + d.k) * (size_t)b * b;
+      void* low = m.prec == PREC_FP32   ? (void*)(reinterpret_cast<float*>(m.low) + off)
+                  : m.prec == PREC_BF16 ? (void*)(reinterpret_cast<uint16_t*>(m.low) + off)
+                                        : nullptr;
+      trsm_part(tile_ptr(m, d.i, d.k), tile_ptr(m, d.k, d.k), b, part * R, R, low, m.prec, lds);
       break;
     }
     case SPX_T_SYRK:
@@ -411,10 +601,29 @@ __device__ void run_part(const SchedArgs& a, uint32_t task, uint32_t part, doubl
         I = part % ns;
         J = part / ns;
       }
-      const double* Ai = tile_ptr(m, d.i, d.k) + I * sb;
-      const double* Bj = tile_ptr(m, d.j, d.k) + J * sb;
       double* C = tile_ptr(m, d.i, d.j) + (size_t)J * sb * b + I * sb;
-      gemm_nt_any(C, b, Ai, b, Bj, b, sb, sb, b, d.type == SPX_T_SYRK && I == J, lds);
+      const bool lower = d.type == SPX_T_SYRK && I == J;
+      const size_t oi = ((size_t)d.i * (d.i + 1) / 2 + d.k) * (size_t)b * b;
+      const size_t oj = ((size_t)d.j * (d.j + 1) / 2 + d.k) * (size_t)b * b;
+      if (m.prec == PREC_FP32) {
+        const float* lf = reinterpret_cast<const float*>(m.low);
+        const float* Ai = lf + oi + I * sb;
+        const float* Bj = lf + oj + J * sb;
+        if (sb > 64) gemm_nt_f32<64>(C, b, Ai, b, Bj, b, sb, sb, b, lower, lds);
+        else if (sb > 32) gemm_nt_f32<32>(C, b, Ai, b, Bj, b, sb, sb, b, lower, lds);
+        else gemm_nt_f32<16>(C, b, Ai, b, Bj, b, sb, sb, b, lower, lds);
+      } else if (m.prec == PREC_BF16) {
+        const uint16_t* lh = reinterpret_cast<const uint16_t*>(m.low);
+        const uint16_t* Ai = lh + oi + (size_t)I * sb * b;
+        const uint16_t* Bj = lh + oj + (size_t)J * sb * b;
+        if (sb > 64) gemm_nt_bf16<64>(C, b, Ai, b, Bj, b, sb, sb, b, lower, lds);
+        else if (sb > 32) gemm_nt_bf16<32>(C, b, Ai, b, Bj, b, sb, sb, b, lower, lds);
+        else gemm_nt_bf16<16>(C, b, Ai, b, Bj, b, sb, sb, b, lower, lds);
+      } else {
+        const double* Ai = tile_ptr(m, d.i, d.k) + I * sb;
+        const double* Bj = tile_ptr(m, d.j, d.k) + J * sb;
+        gemm_nt_any(C, b, Ai, b, Bj, b, sb, sb, b, lower, lds);
+      }
       break;
     }
     case SPX_T_FTRSM: {
@@ -559,6 +768,12 @@ __global__ __launch_bounds__(NT) void sched_kernel(SchedArgs a) {
   }
 }
 
+// One task, part blockIdx.x per workgroup (tests of the tile kernels).
+__global__ __launch_bounds__(NT) void one_task_kernel(SchedArgs a) {
+  __shared__ double lds[LDS_DOUBLES];
+  run_part(a, 0, blockIdx.x, lds);
+}
+
 // Per-launch state from the cached static image: counters of unfinished predecessors
 // and parts, the ready queue with the root tasks already in it, cleared counters.
 __global__ void sched_init_kernel(uint32_t* pending, const uint32_t* indeg, uint32_t* parts_left,
@@ -642,11 +857,14 @@ __global__ void rhs_in_kernel(const double* __restrict__ B, int64_t ldb, int64_t
   }
 }
 __global__ void rhs_out_kernel(const double* __restrict__ y, int64_t n_pad, int64_t n, int64_t nrhs,
-                               double* __restrict__ X, int64_t ldx) {
+                               double* __restrict__ X, int64_t ldx, int accumulate) {
   const int64_t total = n * nrhs;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
     const int64_t r = e / nrhs, q = e % nrhs;
-    X[r * ldx + q] = y[q * n_pad + r];
+    if (accumulate)
+      X[r * ldx + q] += y[q * n_pad + r];
+    else
+      X[r * ldx + q] = y[q * n_pad + r];
   }
 }
 
@@ -758,8 +976,10 @@ int launch_rhs_in(const double* dB, int64_t ldb, int64_t n, int64_t nrhs, double
   return hip_ok(hipGetLastError(), "rhs_in_kernel");
 }
 
-int launch_rhs_out(const double* rhs, int64_t n_pad, int64_t n, int64_t nrhs, double* dX, int64_t ldx, void* stream) {
-  hipLaunchKernelGGL(rhs_out_kernel, dim3(1024), dim3(NT), 0, (hipStream_t)stream, rhs, n_pad, n, nrhs, dX, ldx);
+int launch_rhs_out(const double* rhs, int64_t n_pad, int64_t n, int64_t nrhs, double* dX, int64_t ldx, int accumulate,
+                   void* stream) {
+  hipLaunchKernelGGL(rhs_out_kernel, dim3(1024), dim3(NT), 0, (hipStream_t)stream, rhs, n_pad, n, nrhs, dX, ldx,
+                     accumulate);
   return hip_ok(hipGetLastError(), "rhs_out_kernel");
 }
 
@@ -775,6 +995,11 @@ int sched_max_wg(int device, int* per_cu, int* num_cu) {
   *per_cu = blocks;
   *num_cu = cus;
   return SPX_OK;
+}
+
+int launch_one_task(const SchedArgs& a, int nparts, void* stream) {
+  hipLaunchKernelGGL(one_task_kernel, dim3(nparts), dim3(NT), 0, (hipStream_t)stream, a);
+  return hip_ok(hipGetLastError(), "one_task_kernel");
 }
 
 int launch_sched(const SchedArgs& a, int num_wg, void* stream) {

@@ -64,7 +64,7 @@ EXPORTS = [
     "spx_last_error", "spx_ctx_create", "spx_ctx_destroy", "spx_graph_build", "spx_graph_info", "spx_graph_edges",
     "spx_graph_indegree", "spx_graph_to_dot", "spx_graph_destroy", "spx_cholesky_graph", "spx_potrf_tiled",
     "spx_factor_info", "spx_factor_get_l", "spx_factor_destroy", "spx_potrs", "spx_backward_error",
-    "spx_last_stats", "spx_trace",
+    "spx_run_task", "spx_last_stats", "spx_trace",
 ]
 
 _lib = None
@@ -103,6 +103,7 @@ def lib():
         "spx_factor_destroy": (None, [vp]),
         "spx_potrs": (ctypes.c_int, [vp, vp, i64, vp, i64, vp, i64, vp, i64, P(Refine), P(SolveStats)]),
         "spx_backward_error": (ctypes.c_int, [vp, i64, vp, i64, i64, vp, i64, vp, i64, P(ctypes.c_double)]),
+        "spx_run_task": (ctypes.c_int, [vp, i32, i32, i32, i32, i32, i32, vp, vp, i32, P(i64)]),
         "spx_last_stats": (ctypes.c_int, [vp, P(Stats)]),
         "spx_trace": (i64, [vp, P(u64), i64]),
     }
@@ -201,7 +202,9 @@ class Context:
         if stream is None:
             stream = torch.cuda.current_stream(device)
         self.stream = stream
-        self._allocs = {}
+        import weakref
+
+        self._factors = weakref.WeakSet()
         if torch_allocator:
             dev = device
 
@@ -221,6 +224,8 @@ class Context:
 
     def close(self):
         if self._h:
+            for f in list(self._factors):  # a factor must not outlive its context
+                f.close()
             lib().spx_ctx_destroy(self._h)
             self._h = ctypes.c_void_p()
 
@@ -285,6 +290,14 @@ class Context:
                                         B2.stride(0), eta))
         return np.array(eta[:])
 
+    def run_task(self, type_, i, j, k, nt, b, tiles, rhs=None, nrhs=0):
+        """Runs one task on packed tile storage (see spx_run_task); returns info."""
+        tiles = self._dev(tiles, "tiles")
+        r = None if rhs is None else _ptr(self._dev(rhs, "rhs"))
+        info = ctypes.c_int64()
+        _check(lib().spx_run_task(self._h, type_, i, j, k, nt, b, _ptr(tiles), r, nrhs, ctypes.byref(info)))
+        return info.value
+
     def stats(self):
         s = Stats()
         _check(lib().spx_last_stats(self._h, ctypes.byref(s)))
@@ -301,6 +314,7 @@ class Factor:
     def __init__(self, ctx, handle):
         self.ctx = ctx
         self._h = ctypes.c_void_p(handle)
+        ctx._factors.add(self)
         n, b, npad = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int64()
         _check(lib().spx_factor_info(self._h, ctypes.byref(n), ctypes.byref(b), ctypes.byref(npad)))
         self.n, self.tile, self.n_padded = n.value, b.value, npad.value
@@ -312,9 +326,9 @@ class Factor:
         return out
 
     def close(self):
-        if self._h:
+        if self._h and self.ctx._h:
             lib().spx_factor_destroy(self._h)
-            self._h = ctypes.c_void_p()
+        self._h = ctypes.c_void_p()
 
     def __del__(self):
         try:
