@@ -143,12 +143,14 @@ static int default_tile(int64_t n) {
 }
 
 // Parts per task for tile size b and right-hand-side count nrhs.
+int trsm_rows_of(int b) { return b < 64 ? b : 64; }
+
 uint16_t parts_of(const TaskDesc& d, int b, int nrhs) {
   const int sb = b < 128 ? b : 128, ns = b / sb;
   const int rows = b < 64 ? b : 64;
   switch (d.type) {
     case SPX_T_POTRF: return 1;
-    case SPX_T_TRSM: return (uint16_t)(b / 32);
+    case SPX_T_TRSM: return (uint16_t)(b / trsm_rows_of(b));
     case SPX_T_SYRK: return (uint16_t)(ns * (ns + 1) / 2);
     case SPX_T_GEMM: return (uint16_t)(ns * ns);
     case SPX_T_FTRSM:
@@ -459,7 +461,7 @@ int spx_potrf_tiled(spx_ctx* c, int64_t n, const double* dA, int64_t lda, const 
   m.b = b;
   m.prec = prec;
   m.n = (int32_t)n;
-  m.trsm_rows = 32;
+  m.trsm_rows = trsm_rows_of(b);
   c->hmats[0] = m;
   rc = hipc(hipEventRecord(c->ev[2], c->stream), "hipEventRecord");
   if (!rc) rc = launch_pack(dA, lda, n, m, c->stream);
@@ -527,7 +529,7 @@ static int solve_on(spx_ctx* c, const spx_factor* f, int64_t nrhs, double* rhs) 
   m.nrhs = (int32_t)nrhs;
   m.prec = PREC_FP64;  // the solve always reads the FP64 factor
   m.n = (int32_t)f->n;
-  m.trsm_rows = 32;
+  m.trsm_rows = trsm_rows_of(f->b);
   c->hmats[0] = m;
   return run_image(c, im, 1, nullptr, 0.0);
 }
@@ -675,7 +677,7 @@ int spx_run_task(spx_ctx* c, int32_t type, int32_t i, int32_t j, int32_t k, int3
   m.b = b;
   m.nrhs = nrhs;
   m.n = nt * b;
-  m.trsm_rows = 32;
+  m.trsm_rows = trsm_rows_of(b);
   c->hmats[0] = m;
   const int32_t healthy = INT_MAX;
   SPX_TRY(hipc(hipMemcpyAsync(c->dtask, &d, sizeof d, hipMemcpyHostToDevice, c->stream), "task upload"));

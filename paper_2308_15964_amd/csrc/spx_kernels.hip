@@ -22,7 +22,8 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 typedef unsigned long long u64;
 
 constexpr int NT = 256;                 // threads per workgroup (4 waves)
-constexpr int LDS_DOUBLES = 8192;       // 64 KiB of LDS per workgroup
+constexpr int LDS_DOUBLES = 12288;      // 96 KiB of LDS per workgroup (one workgroup per CU)
+constexpr int LDS_D_OFF = 8192;         // 32x32 diagonal block, after the update staging area
 constexpr u64 EMPTY = ~0ull;
 
 __device__ __forceinline__ double* tile_ptr(const DevMat& m, int i, int j) {
@@ -47,9 +48,9 @@ __device__ __forceinline__ uint32_t sub_acqrel(uint32_t* p, uint32_t v) {
 // ---------------------------------------------------------------------------------------
 // FP64 matrix-core update: C[M x N] -= A[M x K] * B[N x K]^T (all column-major).
 // Four waves in a 2x2 arrangement, each owning a WT x WT block of C made of 16x16
-// v_mfma_f64_16x16x4 accumulators.  K is staged through LDS in chunks of 16, with the
+// v_mfma_f64_16x16x4 accumulators.  K is staged through LDS in chunks of 32, with the
 // next chunk's global loads in flight while the current one is multiplied.
-// M, N: multiples of 16, at most 2*WT.  K: multiple of 16.  lower: write only the
+// M, N: multiples of 16, at most 2*WT.  K: multiple of 32.  lower: write only the
 // entries with row >= col (diagonal blocks of a symmetric update).
 // ---------------------------------------------------------------------------------------
 template <int WT>
@@ -57,7 +58,7 @@ __device__ void gemm_nt_f64(double* __restrict__ C, int ldc, const double* __res
                             const double* __restrict__ B, int ldb, int M, int N, int K, bool lower,
                             double* __restrict__ lds) {
   constexpr int SB = 2 * WT;
-  constexpr int KC = 16;
+  constexpr int KC = 32;  // a 32-deep chunk: its MFMAs hide the next chunk's global loads
   constexpr int NB = WT / 16;
   constexpr int PAIRS = SB * KC / (2 * NT);  // double2 loads per thread per operand
   static_assert(PAIRS >= 1, "tile too small for one double2 per thread");
@@ -331,57 +332,150 @@ __device__ __forceinline__ void solve_row32(double (&x)[32], const double* __res
 }
 
 // ---------------------------------------------------------------------------------------
-// POTRF: in-place lower Cholesky of one b x b tile by one workgroup.
-// Blocked right-looking with 32-wide panels: factor the 32x32 diagonal block in LDS
-// (one wave), solve the panel below it against that block (one row per thread), then
-// update the trailing lower triangle with the matrix cores.  Returns (to all threads)
+// Tall FP64 update for the panel steps: C[M x 32] -= A[M x K] * B[32 x K]^T (column-major).
+// The 16-row blocks of C go round-robin to the four waves (block q to wave q % 4), each
+// wave keeping its blocks' two 16x16 accumulators per block in registers.  B (32 x 16 per
+// chunk) is double-buffered in LDS; A fragments come straight from global memory, one chunk
+// ahead in registers.  M: multiple of 16, at most 64 * NBMAX.  K: multiple of 16.
+// lower: write only row >= col (C starts on the diagonal).
+// ---------------------------------------------------------------------------------------
+template <int NBMAX>
+__device__ void gemm_tall32_f64(double* __restrict__ C, int ldc, const double* __restrict__ A, int lda,
+                                const double* __restrict__ B, int ldb, int M, int K, bool lower,
+                                double* __restrict__ lds) {
+  constexpr int KC = 16, KS = KC / 4;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int nblk = M >> 4, kl = lane >> 4, li = lane & 15;
+  d4 acc[NBMAX][2];
+#pragma unroll
+  for (int t = 0; t < NBMAX; ++t) acc[t][0] = acc[t][1] = d4{0.0, 0.0, 0.0, 0.0};
+  double an[NBMAX][KS], bn[2];
+  auto aload = [&](int k0) {
+#pragma unroll
+    for (int t = 0; t < NBMAX; ++t) {
+      const int q = wave + 4 * t;
+#pragma unroll
+      for (int s = 0; s < KS; ++s)
+        an[t][s] = q < nblk ? A[(size_t)(k0 + 4 * s + kl) * lda + 16 * q + li] : 0.0;
+    }
+  };
+  auto bload = [&](int k0) {  // element e = tid + 256 i of the 16 x 32 chunk: (k = e / 32, j = e % 32)
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int e = tid + NT * i;
+      bn[i] = B[(size_t)(k0 + (e >> 5)) * ldb + (e & 31)];
+    }
+  };
+  auto bstore = [&](double* dst) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i) dst[tid + NT * i] = bn[i];
+  };
+  const int nch = K / KC;
+  aload(0);
+  bload(0);
+  __syncthreads();  // the caller's previous use of LDS is over
+  bstore(lds);
+  __syncthreads();
+  for (int c = 0; c < nch; ++c) {
+    double acur[NBMAX][KS];
+#pragma unroll
+    for (int t = 0; t < NBMAX; ++t)
+#pragma unroll
+      for (int s = 0; s < KS; ++s) acur[t][s] = an[t][s];
+    const double* Bc = lds + (c & 1) * (KC * 32);
+    if (c + 1 < nch) {
+      aload((c + 1) * KC);
+      bload((c + 1) * KC);
+    }
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      const double b0 = Bc[(4 * s + kl) * 32 + li], b1 = Bc[(4 * s + kl) * 32 + 16 + li];
+#pragma unroll
+      for (int t = 0; t < NBMAX; ++t) {
+        if (wave + 4 * t < nblk) {
+          acc[t][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(acur[t][s], b0, acc[t][0], 0, 0, 0);
+          acc[t][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(acur[t][s], b1, acc[t][1], 0, 0, 0);
+        }
+      }
+    }
+    if (c + 1 < nch) bstore(lds + ((c + 1) & 1) * (KC * 32));
+    __syncthreads();
+  }
+#pragma unroll
+  for (int t = 0; t < NBMAX; ++t) {
+    const int q = wave + 4 * t;
+    if (q >= nblk) continue;
+#pragma unroll
+    for (int jb = 0; jb < 2; ++jb) {
+      const int col = 16 * jb + li;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = 16 * q + kl + 4 * v;  // FP64 accumulator layout: (l/16 + 4v, l%16)
+        if (!lower || row >= col) C[(size_t)col * ldc + row] -= acc[t][jb][v];
+      }
+    }
+  }
+}
+
+__device__ void gemm_tall32_any(double* C, int ldc, const double* A, int lda, const double* B, int ldb, int M, int K,
+                                bool lower, double* lds) {
+  if (K <= 0) return;
+  if (M <= 64)
+    gemm_tall32_f64<1>(C, ldc, A, lda, B, ldb, M, K, lower, lds);
+  else if (M <= 128)
+    gemm_tall32_f64<2>(C, ldc, A, lda, B, ldb, M, K, lower, lds);
+  else
+    gemm_tall32_f64<8>(C, ldc, A, lda, B, ldb, M, K, lower, lds);
+}
+
+// ---------------------------------------------------------------------------------------
+// POTRF: in-place lower Cholesky of one b x b tile by one workgroup.  Left-looking over
+// 32-wide panels: the panel (rows c0.., columns c0..c0+31) first receives the updates of
+// every factored column (tall matrix-core update, K = c0), then its 32x32 diagonal block is
+// factored in one wave (row r in lane r's registers, columns broadcast with lane shuffles)
+// and the rows below are solved against it (one row per thread).  Returns (to all threads)
 // 0 or the 1-based local column of a non-positive or NaN pivot.
 // ---------------------------------------------------------------------------------------
 __device__ int potrf_tile(double* __restrict__ a, int b, double* __restrict__ lds) {
   __shared__ int s_bad;
-  const int tid = threadIdx.x;
-  double* D = lds + 2 * 16 * 128;  // 32x32 diagonal block, after the GEMM staging area
+  const int tid = threadIdx.x, lane = tid & 63;
+  double* D = lds + LDS_D_OFF;
   if (tid == 0) s_bad = 0;
   for (int c0 = 0; c0 < b; c0 += 32) {
-    // load the diagonal block (lower part; the upper part is not used)
-    __syncthreads();
-    for (int e = tid; e < 32 * 32; e += NT) {
-      const int r = e & 31, c = e >> 5;
-      D[c * 32 + r] = a[(size_t)(c0 + c) * b + c0 + r];
-    }
+    gemm_tall32_any(a + (size_t)c0 * b + c0, b, a + c0, b, a + c0, b, b - c0, c0, true, lds);
     __syncthreads();
     if (tid < 64) {
-      // one wave: lane r owns row r of the block
-      const int r = tid;
-      int bad = 0;
+      double row[32];
+#pragma unroll
+      for (int j = 0; j < 32; ++j) row[j] = (lane < 32 && lane >= j) ? a[(size_t)(c0 + j) * b + c0 + lane] : 0.0;
+      int bad = 0;  // first failing column (the same in every lane); later steps are skipped
+#pragma unroll
       for (int c = 0; c < 32; ++c) {
-        const double p = D[c * 32 + c];
-        if (!(p > 0.0)) {
-          bad = c + 1;
-          break;
+        const double p = __shfl(row[c], c);
+        if (!bad && !(p > 0.0)) bad = c + 1;
+        const double d = bad ? 1.0 : sqrt(p);
+        const double lrc = bad ? row[c] : (lane > c ? row[c] / d : (lane == c ? d : 0.0));
+        row[c] = lrc;
+#pragma unroll
+        for (int j = c + 1; j < 32; ++j) {
+          const double ljc = __shfl(lrc, j);
+          if (!bad && lane >= j) row[j] -= lrc * ljc;
         }
-        const double d = sqrt(p);
-        __builtin_amdgcn_wave_barrier();
-        if (r > c && r < 32) D[c * 32 + r] = D[c * 32 + r] / d;
-        if (r == c) D[c * 32 + c] = d;
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-        if (r > c && r < 32) {
-          const double lrc = D[c * 32 + r];
-          for (int j = c + 1; j <= r; ++j) D[j * 32 + r] -= lrc * D[c * 32 + j];
-        }
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
       }
-      if (tid == 0 && bad) s_bad = c0 + bad;
+      if (lane < 32) {
+#pragma unroll
+        for (int j = 0; j < 32; ++j) D[j * 32 + lane] = row[j];
+      }
+      if (lane == 0 && bad) s_bad = c0 + bad;
+      if (!bad && lane < 32) {
+#pragma unroll
+        for (int j = 0; j < 32; ++j)
+          if (lane >= j) a[(size_t)(c0 + j) * b + c0 + lane] = row[j];
+      }
     }
     __syncthreads();
     if (s_bad) return s_bad;
-    for (int e = tid; e < 32 * 32; e += NT) {
-      const int r = e & 31, c = e >> 5;
-      if (r >= c) a[(size_t)(c0 + c) * b + c0 + r] = D[c * 32 + r];
-    }
-    // panel below: rows c0+32 .. b, X = P * D^{-T}, one row per thread
+    // rows below the diagonal block: X = P * D^{-T}, one row per thread
     const int rows = b - c0 - 32;
     for (int r = tid; r < rows; r += NT) {
       double x[32];
@@ -393,33 +487,24 @@ __device__ int potrf_tile(double* __restrict__ a, int b, double* __restrict__ ld
       for (int c = 0; c < 32; ++c) prow[(size_t)c * b] = x[c];
     }
     __syncthreads();
-    // trailing update of the lower triangle: A22 -= P P^T, in blocks of up to 128
-    for (int j0 = c0 + 32; j0 < b; j0 += 128) {
-      const int nb = (b - j0) < 128 ? (b - j0) : 128;
-      for (int i0 = j0; i0 < b; i0 += 128) {
-        const int mb = (b - i0) < 128 ? (b - i0) : 128;
-        gemm_nt_any(a + (size_t)j0 * b + i0, b, a + (size_t)c0 * b + i0, b, a + (size_t)c0 * b + j0, b, mb, nb, 32,
-                    i0 == j0, lds);
-      }
-    }
   }
-  __syncthreads();
   return 0;
 }
 
 // ---------------------------------------------------------------------------------------
 // TRSM part: rows [r0, r0+R) of an off-diagonal tile X <- X * L^{-T}, L the factored
 // diagonal tile of the same block column.  Left-looking over 32-wide column blocks: the
-// block first receives the updates of all solved columns (matrix cores), then is solved
-// against its 32x32 diagonal block (one row per lane).
+// block first receives the updates of all solved columns (tall matrix-core update), then is
+// solved against its 32x32 diagonal block (one row per thread).  In mixed precision the
+// solved rows are also written as the FP32 or BF16 copy the updates read.
 // ---------------------------------------------------------------------------------------
 __device__ void trsm_part(double* __restrict__ x, const double* __restrict__ l, int b, int r0, int R,
                           void* __restrict__ low, int prec, double* __restrict__ lds) {
   const int tid = threadIdx.x;
-  double* D = lds + 2 * 16 * 128;
+  double* D = lds + LDS_D_OFF;
   double* xr = x + r0;
   for (int c0 = 0; c0 < b; c0 += 32) {
-    if (c0 > 0) gemm_nt_any(xr + (size_t)c0 * b, b, xr, b, l + c0, b, R, 32, c0, false, lds);
+    gemm_tall32_any(xr + (size_t)c0 * b, b, xr, b, l + c0, b, R, c0, false, lds);
     __syncthreads();
     for (int e = tid; e < 32 * 32; e += NT) {
       const int r = e & 31, c = e >> 5;
@@ -433,7 +518,6 @@ __device__ void trsm_part(double* __restrict__ x, const double* __restrict__ l, 
       solve_row32(v, D);
 #pragma unroll
       for (int c = 0; c < 32; ++c) xr[(size_t)(c0 + c) * b + r] = v[c];
-      // mixed precision: the copy the updates read (FP32 column-major, BF16 row-major)
       if (prec == PREC_FP32) {
         float* lf = reinterpret_cast<float*>(low) + r0;
 #pragma unroll
@@ -453,22 +537,25 @@ __device__ void trsm_part(double* __restrict__ x, const double* __restrict__ l, 
 // ---------------------------------------------------------------------------------------
 
 // Forward: y_k <- L_kk^{-1} y_k.  One wave per right-hand-side column (columns
-// distributed over the waves), 32-row diagonal blocks solved with lane shuffles, the
-// rows below updated with the block's columns.
+// distributed over the waves).  Each 32x32 diagonal block is first loaded into registers
+// (lane r holds row r), so the 32-step substitution chain only uses lane shuffles; the
+// rows below are then updated with the block's 32 solved values.
 __device__ void ftrsm_part(const double* __restrict__ l, int b, double* __restrict__ y, int64_t ldy, int q0, int nq) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int q = q0 + wave; q < q0 + nq; q += NT / 64) {
     double* v = y + (size_t)q * ldy;
     for (int c0 = 0; c0 < b; c0 += 32) {
+      double lrow[32];
+#pragma unroll
+      for (int c = 0; c < 32; ++c) lrow[c] = (lane < 32 && lane >= c) ? l[(size_t)(c0 + c) * b + c0 + lane] : 0.0;
       double yr = lane < 32 ? v[c0 + lane] : 0.0;
+#pragma unroll
       for (int c = 0; c < 32; ++c) {
-        const double lcc = l[(size_t)(c0 + c) * b + c0 + c];
-        const double yc = __shfl(yr, c) / lcc;
-        if (lane == c) yr = yc;
-        if (lane > c && lane < 32) yr -= l[(size_t)(c0 + c) * b + c0 + lane] * yc;
+        if (lane == c) yr = yr / lrow[c];
+        const double yc = __shfl(yr, c);
+        if (lane > c) yr -= lrow[c] * yc;
       }
       if (lane < 32) v[c0 + lane] = yr;
-      // rows below the block: v_r -= sum_c L(r, c0+c) y_{c0+c}
       double yb[32];
 #pragma unroll
       for (int c = 0; c < 32; ++c) yb[c] = __shfl(yr, c);
@@ -483,25 +570,27 @@ __device__ void ftrsm_part(const double* __restrict__ l, int b, double* __restri
   }
 }
 
-// Backward: y_k <- L_kk^{-T} y_k, column blocks from the last one down.
+// Backward: y_k <- L_kk^{-T} y_k, column blocks from the last one down.  Lane r holds
+// column r of the diagonal block (contiguous in memory), i.e. L(c, r) for c >= r.
 __device__ void btrsm_part(const double* __restrict__ l, int b, double* __restrict__ y, int64_t ldy, int q0, int nq) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int q = q0 + wave; q < q0 + nq; q += NT / 64) {
     double* v = y + (size_t)q * ldy;
     for (int c0 = b - 32; c0 >= 0; c0 -= 32) {
+      double lcol[32];
+#pragma unroll
+      for (int c = 0; c < 32; ++c) lcol[c] = (lane < 32 && c >= lane) ? l[(size_t)(c0 + lane) * b + c0 + c] : 0.0;
       double yr = lane < 32 ? v[c0 + lane] : 0.0;
+#pragma unroll
       for (int c = 31; c >= 0; --c) {
-        const double lcc = l[(size_t)(c0 + c) * b + c0 + c];
-        const double xc = __shfl(yr, c) / lcc;
-        if (lane == c) yr = xc;
-        // y_r -= L(c, r) x_c for r < c  (L(c, r) sits in column r)
-        if (lane < c) yr -= l[(size_t)(c0 + lane) * b + c0 + c] * xc;
+        if (lane == c) yr = yr / lcol[c];
+        const double xc = __shfl(yr, c);
+        if (lane < c) yr -= lcol[c] * xc;  // L(c, lane) x_c
       }
       if (lane < 32) v[c0 + lane] = yr;
       double xb[32];
 #pragma unroll
       for (int c = 0; c < 32; ++c) xb[c] = __shfl(yr, c);
-      // rows above the block: v_r -= sum_c L(c0+c, r) x_{c0+c}; column r is contiguous
       for (int r = lane; r < c0; r += 64) {
         const double* lc = l + (size_t)r * b + c0;
         double s = v[r];
