@@ -112,6 +112,7 @@ struct spx_factor {
   double* tiles = nullptr;
   size_t tile_bytes = 0;
   void* low = nullptr;  // FP32 / BF16 copies of the panel tiles (mixed precision)
+  double* dinv = nullptr;  // inverses of the 32x32 diagonal blocks of the diagonal tiles
 };
 
 namespace spx {
@@ -437,10 +438,16 @@ int spx_potrf_tiled(spx_ctx* c, int64_t n, const double* dA, int64_t lda, const 
   f->tile_bytes = (size_t)(nt * (nt + 1) / 2) * (size_t)b * (size_t)b * sizeof(double);
   f->tiles = (double*)dev_alloc(c, f->tile_bytes);
   if (!f->tiles) return fail(SPX_ENOMEM, "spx_potrf_tiled: tile storage allocation failed");
+  f->dinv = (double*)dev_alloc(c, (size_t)f->n_pad * 32 * sizeof(double));
+  if (!f->dinv) {
+    dev_free(c, f->tiles);
+    return fail(SPX_ENOMEM, "spx_potrf_tiled: block inverse allocation failed");
+  }
   if (prec != SPX_PREC_FP64) {
     f->low = dev_alloc(c, f->tile_bytes / (prec == SPX_PREC_FP32 ? 2 : 4));
     if (!f->low) {
       dev_free(c, f->tiles);
+      dev_free(c, f->dinv);
       return fail(SPX_ENOMEM, "spx_potrf_tiled: low-precision copy allocation failed");
     }
   }
@@ -450,11 +457,13 @@ int spx_potrf_tiled(spx_ctx* c, int64_t n, const double* dA, int64_t lda, const 
   if (rc) {
     dev_free(c, f->tiles);
     dev_free(c, f->low);
+    dev_free(c, f->dinv);
     return rc;
   }
   DevMat m{};
   m.tiles = f->tiles;
   m.low = f->low;
+  m.dinv = f->dinv;
   m.info = c->dinfo;
   m.n_pad = f->n_pad;
   m.nt = (int32_t)nt;
@@ -475,12 +484,14 @@ int spx_potrf_tiled(spx_ctx* c, int64_t n, const double* dA, int64_t lda, const 
   if (rc) {
     dev_free(c, f->tiles);
     dev_free(c, f->low);
+    dev_free(c, f->dinv);
     return rc;
   }
   if (c->hinfo[0] != INT_MAX) {
     *info = c->hinfo[0];
     dev_free(c, f->tiles);
     dev_free(c, f->low);
+    dev_free(c, f->dinv);
     return SPX_OK;
   }
   *out = f.release();
@@ -511,6 +522,7 @@ void spx_factor_destroy(spx_factor* f) {
   (void)hipStreamSynchronize(f->ctx->stream);
   dev_free(f->ctx, f->tiles);
   dev_free(f->ctx, f->low);
+  dev_free(f->ctx, f->dinv);
   delete f;
 }
 
@@ -521,6 +533,7 @@ static int solve_on(spx_ctx* c, const spx_factor* f, int64_t nrhs, double* rhs) 
   SPX_TRY(ensure_small_buffers(c, 1, 1, 0, false));
   DevMat m{};
   m.tiles = f->tiles;
+  m.dinv = f->dinv;
   m.rhs = rhs;
   m.info = c->dinfo;
   m.n_pad = f->n_pad;
@@ -668,8 +681,21 @@ int spx_run_task(spx_ctx* c, int32_t type, int32_t i, int32_t j, int32_t k, int3
   d.j = (uint16_t)j;
   d.k = (uint16_t)k;
   d.nparts = parts_of(d, b, nrhs);
+  // block inverses of the diagonal tile the task reads (written by a POTRF task itself)
+  double* dinv = (double*)dev_alloc(c, (size_t)nt * 32 * b * sizeof(double));
+  if (!dinv) return fail(SPX_ENOMEM, "spx_run_task: allocation failed");
+  const bool reads_diag = type == SPX_T_TRSM || type == SPX_T_FTRSM || type == SPX_T_BTRSM;
+  if (reads_diag) {
+    const double* lkk = d_tiles + ((size_t)k * (k + 1) / 2 + k) * (size_t)b * b;
+    int rc = launch_tile_inverses(lkk, b, dinv + (size_t)k * 32 * b, c->stream);
+    if (rc) {
+      dev_free(c, dinv);
+      return rc;
+    }
+  }
   DevMat m{};
   m.tiles = d_tiles;
+  m.dinv = dinv;
   m.rhs = d_rhs;
   m.info = c->dinfo;
   m.n_pad = (int64_t)nt * b;
@@ -680,15 +706,17 @@ int spx_run_task(spx_ctx* c, int32_t type, int32_t i, int32_t j, int32_t k, int3
   m.trsm_rows = trsm_rows_of(b);
   c->hmats[0] = m;
   const int32_t healthy = INT_MAX;
-  SPX_TRY(hipc(hipMemcpyAsync(c->dtask, &d, sizeof d, hipMemcpyHostToDevice, c->stream), "task upload"));
-  SPX_TRY(hipc(hipMemcpyAsync(c->dmats, c->hmats, sizeof(DevMat), hipMemcpyHostToDevice, c->stream), "upload"));
-  SPX_TRY(hipc(hipMemcpyAsync(c->dinfo, &healthy, 4, hipMemcpyHostToDevice, c->stream), "upload"));
+  int rc = hipc(hipMemcpyAsync(c->dtask, &d, sizeof d, hipMemcpyHostToDevice, c->stream), "task upload");
+  if (!rc) rc = hipc(hipMemcpyAsync(c->dmats, c->hmats, sizeof(DevMat), hipMemcpyHostToDevice, c->stream), "upload");
+  if (!rc) rc = hipc(hipMemcpyAsync(c->dinfo, &healthy, 4, hipMemcpyHostToDevice, c->stream), "upload");
   SchedArgs a{};
   a.tasks = c->dtask;
   a.mats = c->dmats;
-  SPX_TRY(launch_one_task(a, d.nparts, c->stream));
-  SPX_TRY(hipc(hipMemcpyAsync(c->hinfo, c->dinfo, 4, hipMemcpyDeviceToHost, c->stream), "info"));
-  SPX_TRY(hipc(hipStreamSynchronize(c->stream), "hipStreamSynchronize"));
+  if (!rc) rc = launch_one_task(a, d.nparts, c->stream);
+  if (!rc) rc = hipc(hipMemcpyAsync(c->hinfo, c->dinfo, 4, hipMemcpyDeviceToHost, c->stream), "info");
+  if (!rc) rc = hipc(hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+  dev_free(c, dinv);
+  if (rc) return rc;
   *info = c->hinfo[0] == INT_MAX ? 0 : c->hinfo[0];
   return SPX_OK;
 }

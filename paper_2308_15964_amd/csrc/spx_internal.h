@@ -52,6 +52,7 @@ struct DevMat {
   double* tiles;
   void* low;        // low-precision copies of the off-diagonal tiles (same packing), or null
   double* rhs;      // right-hand side / solution, column-major n_pad x nrhs (ld = n_pad)
+  double* dinv;     // inverses of the 32x32 diagonal blocks of each diagonal tile (32 b per tile)
   int32_t* info;    // 0x7fffffff while healthy; else the 1-based failing column
   int64_t n_pad;
   int32_t nt, b, nrhs, prec;
@@ -97,6 +98,7 @@ int launch_sched_init_full(uint32_t* pending, const uint32_t* indeg, uint32_t* p
                            int32_t* info, int ninfo, uint32_t* trace_idx, void* stream);
 int launch_sched(const SchedArgs& a, int num_wg, void* stream);
 int launch_one_task(const SchedArgs& a, int nparts, void* stream);
+int launch_tile_inverses(const double* l, int b, double* dinv, void* stream);
 uint16_t parts_of(const TaskDesc& d, int b, int nrhs);
 int sched_max_wg(int device, int* per_cu, int* num_cu);
 int launch_backward_error(int64_t n, const double* dA, int64_t lda, int64_t nrhs, const double* dX, int64_t ldx,

@@ -32,6 +32,9 @@ __device__ __forceinline__ double* tile_ptr(const DevMat& m, int i, int j) {
 
 __device__ __forceinline__ u64 now_ticks() { return wall_clock64(); }
 
+// Inverses of the 32x32 diagonal blocks of diagonal tile k: b/32 column-major blocks.
+__device__ __forceinline__ double* dinv_ptr(const DevMat& m, int k) { return m.dinv + (size_t)k * 32 * m.b; }
+
 // Agent-scope atomics.  Release publishes this workgroup's global writes (made visible
 // to the whole device before the counter changes); acquire makes the writes of the
 // releasing workgroups visible to the reader.
@@ -318,16 +321,77 @@ __device__ __forceinline__ uint16_t to_bf16(double x) {
   return (uint16_t)((sign << 15) | ((unsigned)e << 7) | (unsigned)((u >> 45) & 0x7fu));
 }
 
-// x <- x * D^{-T} for one row x of 32 values and the 32x32 lower block D (column-major
-// in LDS): column by column, x_c /= D_cc, then x_j -= x_c D_jc for j > c.
-__device__ __forceinline__ void solve_row32(double (&x)[32], const double* __restrict__ D) {
+// Value of v in lane `src` (a compile-time constant after unrolling), read through the
+// scalar unit: no LDS round trip on the sequential chain.
+__device__ __forceinline__ double lane_bcast(double v, int src) {
+  const long long u = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(u & 0xffffffffll), src);
+  const int hi = __builtin_amdgcn_readlane((int)(u >> 32), src);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// One wave factors the 32x32 lower block D (column-major in LDS, D(r, j) at D[j*32 + r]) and
+// writes its inverse to Z (column-major, zeros above the diagonal).  Lane r keeps row r in
+// registers; every value a step needs from another lane is broadcast through the scalar
+// unit, so a column step costs one sqrt, one division and a few dependent operations.
+// Returns the 1-based column of the first non-positive or NaN pivot (then D and Z are not
+// written), or 0; the same value in every lane.
+__device__ int factor_inverse32(double* __restrict__ D, double* __restrict__ Z) {
+  const int lane = threadIdx.x & 63;
+  double row[32];
+#pragma unroll
+  for (int j = 0; j < 32; ++j) row[j] = (lane < 32 && lane >= j) ? D[j * 32 + lane] : 0.0;
+  int bad = 0;
 #pragma unroll
   for (int c = 0; c < 32; ++c) {
-    x[c] = x[c] / D[c * 32 + c];
+    const double p = lane_bcast(row[c], c);
+    if (!bad && !(p > 0.0)) bad = c + 1;
+    const double d = bad ? 1.0 : sqrt(p);
+    const double lrc = lane > c ? row[c] / d : (lane == c ? d : 0.0);
+    row[c] = lrc;
 #pragma unroll
-    for (int j = c + 1; j < 32; ++j) x[j] -= x[c] * D[c * 32 + j];
-    // keep the scheduler from hoisting every later column's loads (register pressure)
-    __builtin_amdgcn_sched_barrier(0);
+    for (int j = c + 1; j < 32; ++j) row[j] -= lrc * lane_bcast(lrc, j);  // zero above the diagonal
+  }
+  if (bad) return bad;
+  if (lane < 32) {
+#pragma unroll
+    for (int j = 0; j < 32; ++j) D[j * 32 + lane] = lane >= j ? row[j] : 0.0;
+  }
+  // inverse: lane c holds column c of L^{-1}, by forward substitution L z = e_c
+  double z[32];
+#pragma unroll
+  for (int m = 0; m < 32; ++m) z[m] = (m == lane) ? 1.0 : 0.0;
+#pragma unroll
+  for (int p = 0; p < 32; ++p) {
+    z[p] = z[p] / lane_bcast(row[p], p);
+#pragma unroll
+    for (int m = p + 1; m < 32; ++m) z[m] -= lane_bcast(row[p], m) * z[p];
+  }
+  if (lane < 32) {
+#pragma unroll
+    for (int m = 0; m < 32; ++m) Z[lane * 32 + m] = m >= lane ? z[m] : 0.0;
+  }
+  return 0;
+}
+
+// One wave inverts an already factored 32x32 lower block L (LDS, column-major) into Z.
+__device__ void inverse32(const double* __restrict__ L, double* __restrict__ Z) {
+  const int lane = threadIdx.x & 63;
+  double row[32];
+#pragma unroll
+  for (int j = 0; j < 32; ++j) row[j] = (lane < 32 && lane >= j) ? L[j * 32 + lane] : 0.0;
+  double z[32];
+#pragma unroll
+  for (int m = 0; m < 32; ++m) z[m] = (m == lane) ? 1.0 : 0.0;
+#pragma unroll
+  for (int p = 0; p < 32; ++p) {
+    z[p] = z[p] / lane_bcast(row[p], p);
+#pragma unroll
+    for (int m = p + 1; m < 32; ++m) z[m] -= lane_bcast(row[p], m) * z[p];
+  }
+  if (lane < 32) {
+#pragma unroll
+    for (int m = 0; m < 32; ++m) Z[lane * 32 + m] = m >= lane ? z[m] : 0.0;
   }
 }
 
@@ -336,20 +400,24 @@ __device__ __forceinline__ void solve_row32(double (&x)[32], const double* __res
 // The 16-row blocks of C go round-robin to the four waves (block q to wave q % 4), each
 // wave keeping its blocks' two 16x16 accumulators per block in registers.  B (32 x 16 per
 // chunk) is double-buffered in LDS; A fragments come straight from global memory, one chunk
-// ahead in registers.  M: multiple of 16, at most 64 * NBMAX.  K: multiple of 16.
-// lower: write only row >= col (C starts on the diagonal).
+// ahead in registers; the chunk is deeper when each wave has fewer row blocks, so every
+// chunk carries enough matrix-core work to cover the next chunk's loads.  M: multiple of
+// 16, at most 64 * NBMAX.  K: multiple of 64 / NBMAX (of 16 for NBMAX >= 8).
+// lower: write only row >= col (C starts on the diagonal).  ASSIGN: C = A * B^T instead; C
+// may then be A itself, since each wave reads all of its rows before writing them.
 // ---------------------------------------------------------------------------------------
-template <int NBMAX>
+template <int NBMAX, bool ASSIGN>
 __device__ void gemm_tall32_f64(double* __restrict__ C, int ldc, const double* __restrict__ A, int lda,
                                 const double* __restrict__ B, int ldb, int M, int K, bool lower,
                                 double* __restrict__ lds) {
-  constexpr int KC = 16, KS = KC / 4;
+  constexpr int KC = NBMAX >= 8 ? 16 : (NBMAX >= 2 ? 32 : 64), KS = KC / 4;  // more depth for fewer blocks
+  constexpr int BPT = KC * 32 / NT;                                            // B elements per thread
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int nblk = M >> 4, kl = lane >> 4, li = lane & 15;
   d4 acc[NBMAX][2];
 #pragma unroll
   for (int t = 0; t < NBMAX; ++t) acc[t][0] = acc[t][1] = d4{0.0, 0.0, 0.0, 0.0};
-  double an[NBMAX][KS], bn[2];
+  double an[NBMAX][KS], bn[BPT];
   auto aload = [&](int k0) {
 #pragma unroll
     for (int t = 0; t < NBMAX; ++t) {
@@ -359,16 +427,16 @@ __device__ void gemm_tall32_f64(double* __restrict__ C, int ldc, const double* _
         an[t][s] = q < nblk ? A[(size_t)(k0 + 4 * s + kl) * lda + 16 * q + li] : 0.0;
     }
   };
-  auto bload = [&](int k0) {  // element e = tid + 256 i of the 16 x 32 chunk: (k = e / 32, j = e % 32)
+  auto bload = [&](int k0) {  // element e = tid + 256 i of the KC x 32 chunk: (k = e / 32, j = e % 32)
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
+    for (int i = 0; i < BPT; ++i) {
       const int e = tid + NT * i;
       bn[i] = B[(size_t)(k0 + (e >> 5)) * ldb + (e & 31)];
     }
   };
   auto bstore = [&](double* dst) {
 #pragma unroll
-    for (int i = 0; i < 2; ++i) dst[tid + NT * i] = bn[i];
+    for (int i = 0; i < BPT; ++i) dst[tid + NT * i] = bn[i];
   };
   const int nch = K / KC;
   aload(0);
@@ -411,7 +479,11 @@ __device__ void gemm_tall32_f64(double* __restrict__ C, int ldc, const double* _
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int row = 16 * q + kl + 4 * v;  // FP64 accumulator layout: (l/16 + 4v, l%16)
-        if (!lower || row >= col) C[(size_t)col * ldc + row] -= acc[t][jb][v];
+        if (lower && row < col) continue;
+        if (ASSIGN)
+          C[(size_t)col * ldc + row] = acc[t][jb][v];
+        else
+          C[(size_t)col * ldc + row] -= acc[t][jb][v];
       }
     }
   }
@@ -419,73 +491,63 @@ __device__ void gemm_tall32_f64(double* __restrict__ C, int ldc, const double* _
 
 __device__ void gemm_tall32_any(double* C, int ldc, const double* A, int lda, const double* B, int ldb, int M, int K,
                                 bool lower, double* lds) {
-  if (K <= 0) return;
-  if (M <= 64)
-    gemm_tall32_f64<1>(C, ldc, A, lda, B, ldb, M, K, lower, lds);
-  else if (M <= 128)
-    gemm_tall32_f64<2>(C, ldc, A, lda, B, ldb, M, K, lower, lds);
+  if (K <= 0 || M <= 0) return;
+  if (M <= 64 && K % 64 == 0)
+    gemm_tall32_f64<1, false>(C, ldc, A, lda, B, ldb, M, K, lower, lds);
+  else if (M <= 128 && K % 32 == 0)
+    gemm_tall32_f64<2, false>(C, ldc, A, lda, B, ldb, M, K, lower, lds);
+  else if (M <= 256 && K % 32 == 0)
+    gemm_tall32_f64<4, false>(C, ldc, A, lda, B, ldb, M, K, lower, lds);
   else
-    gemm_tall32_f64<8>(C, ldc, A, lda, B, ldb, M, K, lower, lds);
+    gemm_tall32_f64<8, false>(C, ldc, A, lda, B, ldb, M, K, lower, lds);
+}
+
+// X[M x 32] <- X * Li^T in place, Li a 32x32 block inverse (column-major, ld 32).
+__device__ void apply_inv_tall(double* X, int ldx, const double* Li, int M, double* lds) {
+  if (M <= 0) return;
+  if (M <= 128)
+    gemm_tall32_f64<2, true>(X, ldx, X, ldx, Li, 32, M, 32, false, lds);
+  else
+    gemm_tall32_f64<8, true>(X, ldx, X, ldx, Li, 32, M, 32, false, lds);
 }
 
 // ---------------------------------------------------------------------------------------
 // POTRF: in-place lower Cholesky of one b x b tile by one workgroup.  Left-looking over
 // 32-wide panels: the panel (rows c0.., columns c0..c0+31) first receives the updates of
-// every factored column (tall matrix-core update, K = c0), then its 32x32 diagonal block is
-// factored in one wave (row r in lane r's registers, columns broadcast with lane shuffles)
-// and the rows below are solved against it (one row per thread).  Returns (to all threads)
-// 0 or the 1-based local column of a non-positive or NaN pivot.
+// every factored column (tall matrix-core update, K = c0); one wave then factors its 32x32
+// diagonal block in LDS and inverts it; the rows below are multiplied by the transposed
+// inverse on the matrix cores (K = 32).  The inverses of the diagonal blocks are stored in
+// dinv (b/32 column-major 32x32 blocks) for the TRSM and solve tasks.  Returns (to all
+// threads) 0 or the 1-based local column of a non-positive or NaN pivot.
 // ---------------------------------------------------------------------------------------
-__device__ int potrf_tile(double* __restrict__ a, int b, double* __restrict__ lds) {
+__device__ int potrf_tile(double* __restrict__ a, int b, double* __restrict__ dinv, double* __restrict__ lds) {
   __shared__ int s_bad;
-  const int tid = threadIdx.x, lane = tid & 63;
+  const int tid = threadIdx.x;
   double* D = lds + LDS_D_OFF;
-  if (tid == 0) s_bad = 0;
+  double* Z = D + 1024;
   for (int c0 = 0; c0 < b; c0 += 32) {
     gemm_tall32_any(a + (size_t)c0 * b + c0, b, a + c0, b, a + c0, b, b - c0, c0, true, lds);
     __syncthreads();
+    for (int e = tid; e < 1024; e += NT) {
+      const int r = e & 31, j = e >> 5;
+      D[e] = r >= j ? a[(size_t)(c0 + j) * b + c0 + r] : 0.0;
+    }
+    if (tid == 0) s_bad = 0;
+    __syncthreads();
     if (tid < 64) {
-      double row[32];
-#pragma unroll
-      for (int j = 0; j < 32; ++j) row[j] = (lane < 32 && lane >= j) ? a[(size_t)(c0 + j) * b + c0 + lane] : 0.0;
-      int bad = 0;  // first failing column (the same in every lane); later steps are skipped
-#pragma unroll
-      for (int c = 0; c < 32; ++c) {
-        const double p = __shfl(row[c], c);
-        if (!bad && !(p > 0.0)) bad = c + 1;
-        const double d = bad ? 1.0 : sqrt(p);
-        const double lrc = bad ? row[c] : (lane > c ? row[c] / d : (lane == c ? d : 0.0));
-        row[c] = lrc;
-#pragma unroll
-        for (int j = c + 1; j < 32; ++j) {
-          const double ljc = __shfl(lrc, j);
-          if (!bad && lane >= j) row[j] -= lrc * ljc;
-        }
-      }
-      if (lane < 32) {
-#pragma unroll
-        for (int j = 0; j < 32; ++j) D[j * 32 + lane] = row[j];
-      }
-      if (lane == 0 && bad) s_bad = c0 + bad;
-      if (!bad && lane < 32) {
-#pragma unroll
-        for (int j = 0; j < 32; ++j)
-          if (lane >= j) a[(size_t)(c0 + j) * b + c0 + lane] = row[j];
-      }
+      const int bad = factor_inverse32(D, Z);
+      if (bad && tid == 0) s_bad = c0 + bad;
     }
     __syncthreads();
     if (s_bad) return s_bad;
-    // rows below the diagonal block: X = P * D^{-T}, one row per thread
-    const int rows = b - c0 - 32;
-    for (int r = tid; r < rows; r += NT) {
-      double x[32];
-      double* prow = a + (size_t)c0 * b + c0 + 32 + r;
-#pragma unroll
-      for (int c = 0; c < 32; ++c) x[c] = prow[(size_t)c * b];
-      solve_row32(x, D);
-#pragma unroll
-      for (int c = 0; c < 32; ++c) prow[(size_t)c * b] = x[c];
+    double* dblk = dinv + (size_t)c0 * 32;
+    for (int e = tid; e < 1024; e += NT) {
+      const int r = e & 31, j = e >> 5;
+      if (r >= j) a[(size_t)(c0 + j) * b + c0 + r] = D[e];
+      dblk[e] = Z[e];
     }
+    __syncthreads();
+    apply_inv_tall(a + (size_t)c0 * b + c0 + 32, b, dblk, b - c0 - 32, lds);
     __syncthreads();
   }
   return 0;
@@ -493,42 +555,61 @@ __device__ int potrf_tile(double* __restrict__ a, int b, double* __restrict__ ld
 
 // ---------------------------------------------------------------------------------------
 // TRSM part: rows [r0, r0+R) of an off-diagonal tile X <- X * L^{-T}, L the factored
-// diagonal tile of the same block column.  Left-looking over 32-wide column blocks: the
-// block first receives the updates of all solved columns (tall matrix-core update), then is
-// solved against its 32x32 diagonal block (one row per thread).  In mixed precision the
-// solved rows are also written as the FP32 or BF16 copy the updates read.
+// diagonal tile of the same block column, dinv the inverses of its 32x32 diagonal blocks.
+// Left-looking over 32-wide column blocks: the block first receives the updates of all
+// solved columns (tall matrix-core update, K = c0), then is multiplied by the transposed
+// block inverse (K = 32).  In mixed precision the solved block is also written as the FP32
+// or BF16 copy the updates read.
 // ---------------------------------------------------------------------------------------
-__device__ void trsm_part(double* __restrict__ x, const double* __restrict__ l, int b, int r0, int R,
-                          void* __restrict__ low, int prec, double* __restrict__ lds) {
+__device__ void trsm_part(double* __restrict__ x, const double* __restrict__ l, const double* __restrict__ dinv,
+                          int b, int r0, int R, void* __restrict__ low, int prec, double* __restrict__ lds) {
   const int tid = threadIdx.x;
-  double* D = lds + LDS_D_OFF;
   double* xr = x + r0;
   for (int c0 = 0; c0 < b; c0 += 32) {
     gemm_tall32_any(xr + (size_t)c0 * b, b, xr, b, l + c0, b, R, c0, false, lds);
     __syncthreads();
-    for (int e = tid; e < 32 * 32; e += NT) {
-      const int r = e & 31, c = e >> 5;
-      D[c * 32 + r] = l[(size_t)(c0 + c) * b + c0 + r];
-    }
+    apply_inv_tall(xr + (size_t)c0 * b, b, dinv + (size_t)c0 * 32, R, lds);
     __syncthreads();
-    for (int r = tid; r < R; r += NT) {
-      double v[32];
-#pragma unroll
-      for (int c = 0; c < 32; ++c) v[c] = xr[(size_t)(c0 + c) * b + r];
-      solve_row32(v, D);
-#pragma unroll
-      for (int c = 0; c < 32; ++c) xr[(size_t)(c0 + c) * b + r] = v[c];
-      if (prec == PREC_FP32) {
-        float* lf = reinterpret_cast<float*>(low) + r0;
-#pragma unroll
-        for (int c = 0; c < 32; ++c) lf[(size_t)(c0 + c) * b + r] = (float)v[c];
-      } else if (prec == PREC_BF16) {
-        uint16_t* lh = reinterpret_cast<uint16_t*>(low) + (size_t)(r0 + r) * b + c0;
-#pragma unroll
-        for (int c = 0; c < 32; ++c) lh[c] = to_bf16(v[c]);
+    if (prec == PREC_FP32) {
+      float* lf = reinterpret_cast<float*>(low) + r0;
+      for (int e = tid; e < 32 * R; e += NT) {
+        const int r = e % R, c = e / R;
+        lf[(size_t)(c0 + c) * b + r] = (float)xr[(size_t)(c0 + c) * b + r];
+      }
+    } else if (prec == PREC_BF16) {
+      uint16_t* lh = reinterpret_cast<uint16_t*>(low);
+      for (int e = tid; e < 32 * R; e += NT) {
+        const int c = e & 31, r = e >> 5;
+        lh[(size_t)(r0 + r) * b + c0 + c] = to_bf16(xr[(size_t)(c0 + c) * b + r]);
       }
     }
-    __syncthreads();
+  }
+}
+
+// Inverses of the 32x32 diagonal blocks of an already factored diagonal tile (one block
+// per wave), for callers that run a TRSM or solve task on a factor they supplied.
+__device__ void tile_inverses(const double* __restrict__ l, int b, double* __restrict__ dinv, double* lds) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double* D = lds + wave * 2048;
+  double* Z = D + 1024;
+  for (int c0 = 32 * wave; c0 < b; c0 += 32 * (NT / 64)) {
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+      const int e = lane + 64 * t, r = e & 31, j = e >> 5;
+      D[e] = r >= j ? l[(size_t)(c0 + j) * b + c0 + r] : 0.0;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    inverse32(D, Z);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+    for (int t = 0; t < 16; ++t) dinv[(size_t)c0 * 32 + lane + 64 * t] = Z[lane + 64 * t];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
 }
 
@@ -536,118 +617,162 @@ __device__ void trsm_part(double* __restrict__ x, const double* __restrict__ l, 
 // Solve tasks on the right-hand side y (column-major, ld = n_pad), columns [q0, q0+nq).
 // ---------------------------------------------------------------------------------------
 
-// Forward: y_k <- L_kk^{-1} y_k.  One wave per right-hand-side column (columns
-// distributed over the waves).  Each 32x32 diagonal block is first loaded into registers
-// (lane r holds row r), so the 32-step substitution chain only uses lane shuffles; the
-// rows below are then updated with the block's 32 solved values.
-__device__ void ftrsm_part(const double* __restrict__ l, int b, double* __restrict__ y, int64_t ldy, int q0, int nq) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int q = q0 + wave; q < q0 + nq; q += NT / 64) {
-    double* v = y + (size_t)q * ldy;
-    for (int c0 = 0; c0 < b; c0 += 32) {
-      double lrow[32];
+// Forward: y_k <- L_kk^{-1} y_k for the columns [q0, q0+nq) (nq <= 8), block by block:
+// the 32-row block is multiplied by its diagonal inverse (thread (q, r) computes row r of
+// column q), then every thread updates rows below the block with the 32 solved values.
+__device__ void ftrsm_part(const double* __restrict__ l, const double* __restrict__ dinv, int b,
+                           double* __restrict__ y, int64_t ldy, int q0, int nq, double* __restrict__ lds) {
+  const int tid = threadIdx.x;
+  double* Li = lds;          // 32x32 block inverse
+  double* yo = lds + 1024;   // [8][32] block values before the multiply
+  double* yb = lds + 1280;   // [8][32] solved block values
+  const int q = tid >> 5, r = tid & 31;
+  for (int c0 = 0; c0 < b; c0 += 32) {
+    for (int e = tid; e < 1024; e += NT) Li[e] = dinv[(size_t)c0 * 32 + e];
+    if (q < nq) yo[q * 32 + r] = y[(size_t)(q0 + q) * ldy + c0 + r];
+    __syncthreads();
+    if (q < nq) {
+      double s = 0.0;
+      for (int c = 0; c <= r; ++c) s += Li[c * 32 + r] * yo[q * 32 + c];
+      yb[q * 32 + r] = s;
+      y[(size_t)(q0 + q) * ldy + c0 + r] = s;
+    }
+    __syncthreads();
+    for (int rr = c0 + 32 + tid; rr < b; rr += NT) {
+      double acc[8];
 #pragma unroll
-      for (int c = 0; c < 32; ++c) lrow[c] = (lane < 32 && lane >= c) ? l[(size_t)(c0 + c) * b + c0 + lane] : 0.0;
-      double yr = lane < 32 ? v[c0 + lane] : 0.0;
-#pragma unroll
+      for (int u = 0; u < 8; ++u) acc[u] = 0.0;
+#pragma unroll 8
       for (int c = 0; c < 32; ++c) {
-        if (lane == c) yr = yr / lrow[c];
-        const double yc = __shfl(yr, c);
-        if (lane > c) yr -= lrow[c] * yc;
-      }
-      if (lane < 32) v[c0 + lane] = yr;
-      double yb[32];
+        const double lv = l[(size_t)(c0 + c) * b + rr];
 #pragma unroll
-      for (int c = 0; c < 32; ++c) yb[c] = __shfl(yr, c);
-      for (int r = c0 + 32 + lane; r < b; r += 64) {
-        double s = v[r];
-#pragma unroll
-        for (int c = 0; c < 32; ++c) s -= l[(size_t)(c0 + c) * b + r] * yb[c];
-        v[r] = s;
+        for (int u = 0; u < 8; ++u) acc[u] += lv * yb[u * 32 + c];
       }
-      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      for (int u = 0; u < nq; ++u) y[(size_t)(q0 + u) * ldy + rr] -= acc[u];
     }
+    __syncthreads();
   }
 }
 
-// Backward: y_k <- L_kk^{-T} y_k, column blocks from the last one down.  Lane r holds
-// column r of the diagonal block (contiguous in memory), i.e. L(c, r) for c >= r.
-__device__ void btrsm_part(const double* __restrict__ l, int b, double* __restrict__ y, int64_t ldy, int q0, int nq) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int q = q0 + wave; q < q0 + nq; q += NT / 64) {
-    double* v = y + (size_t)q * ldy;
-    for (int c0 = b - 32; c0 >= 0; c0 -= 32) {
-      double lcol[32];
-#pragma unroll
-      for (int c = 0; c < 32; ++c) lcol[c] = (lane < 32 && c >= lane) ? l[(size_t)(c0 + lane) * b + c0 + c] : 0.0;
-      double yr = lane < 32 ? v[c0 + lane] : 0.0;
-#pragma unroll
-      for (int c = 31; c >= 0; --c) {
-        if (lane == c) yr = yr / lcol[c];
-        const double xc = __shfl(yr, c);
-        if (lane < c) yr -= lcol[c] * xc;  // L(c, lane) x_c
-      }
-      if (lane < 32) v[c0 + lane] = yr;
-      double xb[32];
-#pragma unroll
-      for (int c = 0; c < 32; ++c) xb[c] = __shfl(yr, c);
-      for (int r = lane; r < c0; r += 64) {
-        const double* lc = l + (size_t)r * b + c0;
-        double s = v[r];
-#pragma unroll
-        for (int c = 0; c < 32; ++c) s -= lc[c] * xb[c];
-        v[r] = s;
-      }
-      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+// Backward: y_k <- L_kk^{-T} y_k, blocks from the last one down: x_blk = Li^T y_blk, then
+// rows above the block are updated with L(c0+c, r) (column r of L, contiguous).
+__device__ void btrsm_part(const double* __restrict__ l, const double* __restrict__ dinv, int b,
+                           double* __restrict__ y, int64_t ldy, int q0, int nq, double* __restrict__ lds) {
+  const int tid = threadIdx.x;
+  double* Li = lds;
+  double* yo = lds + 1024;
+  double* xb = lds + 1280;
+  const int q = tid >> 5, r = tid & 31;
+  for (int c0 = b - 32; c0 >= 0; c0 -= 32) {
+    for (int e = tid; e < 1024; e += NT) Li[e] = dinv[(size_t)c0 * 32 + e];
+    if (q < nq) yo[q * 32 + r] = y[(size_t)(q0 + q) * ldy + c0 + r];
+    __syncthreads();
+    if (q < nq) {
+      double s = 0.0;
+      for (int c = r; c < 32; ++c) s += Li[r * 32 + c] * yo[q * 32 + c];  // Li(c, r)
+      xb[q * 32 + r] = s;
+      y[(size_t)(q0 + q) * ldy + c0 + r] = s;
     }
+    __syncthreads();
+    for (int rr = tid; rr < c0; rr += NT) {
+      const double* lc = l + (size_t)rr * b + c0;
+      double acc[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc[u] = 0.0;
+#pragma unroll 8
+      for (int c = 0; c < 32; ++c) {
+        const double lv = lc[c];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc[u] += lv * xb[u * 32 + c];
+      }
+      for (int u = 0; u < nq; ++u) y[(size_t)(q0 + u) * ldy + rr] -= acc[u];
+    }
+    __syncthreads();
   }
 }
 
-// Forward update, rows [r0, r0+64) of block i: y_i -= L_ik y_k.  Wave w takes the
-// columns m = w, w+4, ... so each load of a column strip is 64 contiguous doubles.
+// Forward update, rows [r0, r0+rows) of block i: y_i -= L_ik y_k.  y_k (8 columns at a
+// time) is staged in LDS; wave w sums over m in its quarter of the block, eight loads of
+// 64 contiguous doubles in flight, and the four partial sums are added through LDS.
 __device__ void fgemm_part(const double* __restrict__ l, int b, double* __restrict__ yi,
                            const double* __restrict__ yk, int64_t ldy, int nrhs, int r0, int rows,
                            double* __restrict__ lds) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  double* ys = lds;             // [8][b]
+  double* part = lds + 8 * 512; // [4][8][64]
+  const int mq = b / 4;
   for (int q0 = 0; q0 < nrhs; q0 += 8) {
     const int nq = (nrhs - q0) < 8 ? (nrhs - q0) : 8;
+    __syncthreads();
+    for (int e = tid; e < 8 * b; e += NT) {
+      const int q = e / b, m = e % b;
+      ys[e] = q < nq ? yk[(size_t)(q0 + q) * ldy + m] : 0.0;
+    }
+    __syncthreads();
     double acc[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) acc[q] = 0.0;
-    for (int m = wave; m < b; m += 4) {
-      const double lv = lane < rows ? l[(size_t)m * b + r0 + lane] : 0.0;
+    if (lane < rows) {
+#pragma unroll 8
+      for (int m = wave * mq; m < (wave + 1) * mq; ++m) {
+        const double lv = l[(size_t)m * b + r0 + lane];
 #pragma unroll
-      for (int q = 0; q < 8; ++q)
-        if (q < nq) acc[q] += lv * yk[(size_t)(q0 + q) * ldy + m];
+        for (int q = 0; q < 8; ++q) acc[q] += lv * ys[q * b + m];
+      }
     }
-    __syncthreads();
 #pragma unroll
-    for (int q = 0; q < 8; ++q) lds[(wave * 8 + q) * 64 + lane] = acc[q];
+    for (int q = 0; q < 8; ++q) part[(wave * 8 + q) * 64 + lane] = acc[q];
     __syncthreads();
     if (wave == 0 && lane < rows) {
       for (int q = 0; q < nq; ++q) {
-        const double s = lds[(0 * 8 + q) * 64 + lane] + lds[(1 * 8 + q) * 64 + lane] +
-                         lds[(2 * 8 + q) * 64 + lane] + lds[(3 * 8 + q) * 64 + lane];
+        const double s = part[(0 * 8 + q) * 64 + lane] + part[(1 * 8 + q) * 64 + lane] +
+                         part[(2 * 8 + q) * 64 + lane] + part[(3 * 8 + q) * 64 + lane];
         yi[(size_t)(q0 + q) * ldy + r0 + lane] -= s;
       }
     }
   }
 }
 
-// Backward update, rows [r0, r0+64) of block i (i < k): y_i -= L_ki^T y_k.  Column r of
-// L_ki is contiguous, so each wave reduces whole columns with coalesced loads.
+// Backward update, rows [r0, r0+rows) of block i (i < k): y_i -= L_ki^T y_k.  Column r of
+// L_ki is contiguous: each wave reduces four columns at once (lane-strided coalesced loads,
+// then a wave reduction), with y_k staged in LDS.
 __device__ void bgemm_part(const double* __restrict__ l, int b, double* __restrict__ yi,
-                           const double* __restrict__ yk, int64_t ldy, int nrhs, int r0, int rows) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int r = r0 + wave; r < r0 + rows; r += 4) {
-    const double* lc = l + (size_t)r * b;
-    for (int q = 0; q < nrhs; ++q) {
-      const double* x = yk + (size_t)q * ldy;
-      double s = 0.0;
-      for (int m = lane; m < b; m += 64) s += lc[m] * x[m];
+                           const double* __restrict__ yk, int64_t ldy, int nrhs, int r0, int rows,
+                           double* __restrict__ lds) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  double* ys = lds;  // [8][b]
+  for (int q0 = 0; q0 < nrhs; q0 += 8) {
+    const int nq = (nrhs - q0) < 8 ? (nrhs - q0) : 8;
+    __syncthreads();
+    for (int e = tid; e < 8 * b; e += NT) {
+      const int q = e / b, m = e % b;
+      ys[e] = q < nq ? yk[(size_t)(q0 + q) * ldy + m] : 0.0;
+    }
+    __syncthreads();
+    for (int rr = 4 * wave; rr < rows; rr += 16) {  // rows rr..rr+3 (rows is a multiple of 16 or 32)
+      double acc[4][8];
 #pragma unroll
-      for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off);
-      if (lane == 0) yi[(size_t)q * ldy + r] -= s;
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int q = 0; q < 8; ++q) acc[u][q] = 0.0;
+      for (int m = lane; m < b; m += 64) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const double lv = l[(size_t)(r0 + rr + u) * b + m];
+#pragma unroll
+          for (int q = 0; q < 8; ++q) acc[u][q] += lv * ys[q * b + m];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+#pragma unroll
+          for (int off = 32; off >= 1; off >>= 1) acc[u][q] += __shfl_xor(acc[u][q], off);
+      if (lane == 0) {
+        for (int u = 0; u < 4; ++u)
+          for (int q = 0; q < nq; ++q) yi[(size_t)(q0 + q) * ldy + r0 + rr + u] -= acc[u][q];
+      }
     }
   }
 }
@@ -663,7 +788,7 @@ __device__ void run_part(const SchedArgs& a, uint32_t task, uint32_t part, doubl
   const int b = m.b;
   switch (d.type) {
     case SPX_T_POTRF: {
-      const int bad = potrf_tile(tile_ptr(m, d.k, d.k), b, lds);
+      const int bad = potrf_tile(tile_ptr(m, d.k, d.k), b, dinv_ptr(m, d.k), lds);
       if (bad && threadIdx.x == 0)
         __hip_atomic_fetch_min(m.info, d.k * b + bad, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       break;
@@ -674,7 +799,7 @@ __device__ void run_part(const SchedArgs& a, uint32_t task, uint32_t part, doubl
       void* low = m.prec == PREC_FP32   ? (void*)(reinterpret_cast<float*>(m.low) + off)
                   : m.prec == PREC_BF16 ? (void*)(reinterpret_cast<uint16_t*>(m.low) + off)
                                         : nullptr;
-      trsm_part(tile_ptr(m, d.i, d.k), tile_ptr(m, d.k, d.k), b, part * R, R, low, m.prec, lds);
+      trsm_part(tile_ptr(m, d.i, d.k), tile_ptr(m, d.k, d.k), dinv_ptr(m, d.k), b, part * R, R, low, m.prec, lds);
       break;
     }
     case SPX_T_SYRK:
@@ -717,12 +842,12 @@ __device__ void run_part(const SchedArgs& a, uint32_t task, uint32_t part, doubl
     }
     case SPX_T_FTRSM: {
       const int q0 = part * 8, nq = (m.nrhs - q0) < 8 ? (m.nrhs - q0) : 8;
-      ftrsm_part(tile_ptr(m, d.k, d.k), b, m.rhs + (size_t)d.k * b, m.n_pad, q0, nq);
+      ftrsm_part(tile_ptr(m, d.k, d.k), dinv_ptr(m, d.k), b, m.rhs + (size_t)d.k * b, m.n_pad, q0, nq, lds);
       break;
     }
     case SPX_T_BTRSM: {
       const int q0 = part * 8, nq = (m.nrhs - q0) < 8 ? (m.nrhs - q0) : 8;
-      btrsm_part(tile_ptr(m, d.k, d.k), b, m.rhs + (size_t)d.k * b, m.n_pad, q0, nq);
+      btrsm_part(tile_ptr(m, d.k, d.k), dinv_ptr(m, d.k), b, m.rhs + (size_t)d.k * b, m.n_pad, q0, nq, lds);
       break;
     }
     case SPX_T_FGEMM: {
@@ -735,7 +860,7 @@ __device__ void run_part(const SchedArgs& a, uint32_t task, uint32_t part, doubl
       // task (i, k): y_i -= L_ki^T y_k; the tile is (k, i) with k = d.j
       const int rows = b < 64 ? b : 64;
       bgemm_part(tile_ptr(m, d.j, d.i), b, m.rhs + (size_t)d.i * b, m.rhs + (size_t)d.j * b, m.n_pad, m.nrhs,
-                 part * rows, rows);
+                 part * rows, rows, lds);
       break;
     }
     default:
@@ -861,6 +986,11 @@ __global__ __launch_bounds__(NT) void sched_kernel(SchedArgs a) {
 __global__ __launch_bounds__(NT) void one_task_kernel(SchedArgs a) {
   __shared__ double lds[LDS_DOUBLES];
   run_part(a, 0, blockIdx.x, lds);
+}
+
+__global__ __launch_bounds__(NT) void tile_inverses_kernel(const double* l, int b, double* dinv) {
+  __shared__ double lds[4 * 2048];
+  tile_inverses(l, b, dinv, lds);
 }
 
 // Per-launch state from the cached static image: counters of unfinished predecessors
@@ -1084,6 +1214,11 @@ int sched_max_wg(int device, int* per_cu, int* num_cu) {
   *per_cu = blocks;
   *num_cu = cus;
   return SPX_OK;
+}
+
+int launch_tile_inverses(const double* l, int b, double* dinv, void* stream) {
+  hipLaunchKernelGGL(tile_inverses_kernel, dim3(1), dim3(NT), 0, (hipStream_t)stream, l, b, dinv);
+  return hip_ok(hipGetLastError(), "tile_inverses_kernel");
 }
 
 int launch_one_task(const SchedArgs& a, int nparts, void* stream) {

@@ -8,8 +8,9 @@ Workloads (all synthetic; the paper names no dataset for its Cholesky runs):
   * lower_plus_shift   A = L0 L0^T + n I, L0 = tril(U[-1,1]) (diagonal included), b ~ U[-1,1]
   * gram_spd           A = G G^T / n + I, G ~ N(0,1); eigenvalues in about [1, 5]
   * known_factor       A = L0 L0^T with L0_ii = n + U[0,1], off-diagonal U[-1,1]
-  * integer_factor     A = L0 L0^T with small-integer L0 and diagonal in {1,2,4}: every
-                       intermediate of an in-place Cholesky is then an exact integer
+  * integer_factor     A = L0 L0^T with small-integer L0 and diagonal in {1,2,4} (or unit
+                       diagonal and entries in {-1,0,1}): every intermediate of an
+                       in-place Cholesky is then an exact integer
   * haar_spd           A = Q diag(s) Q^T, Q Haar (QR of a Gaussian matrix with the signs
                        of diag(R) folded in), s log-uniform on [1, kappa] with both
                        endpoints pinned, symmetrised
@@ -59,8 +60,17 @@ def known_factor(n, seed=3):
     return L0 @ L0.T, L0
 
 
-def integer_factor(n, seed=4, nrhs=2):
+def integer_factor(n, seed=4, nrhs=2, unit=False):
+    """unit=True: unit diagonal and off-diagonal entries in {-1, 0, 1} (a quarter each
+    sign); then the inverse of every 32x32 diagonal block is also an integer matrix
+    (entries below 2^31), so block-inverse based solves stay exact too."""
     g = rng(seed)
+    if unit:
+        L0 = np.tril(g.choice([-1.0, 0.0, 0.0, 1.0], (n, n)), -1)
+        L0[np.diag_indices(n)] = 1.0
+        X0 = g.integers(-5, 6, (n, nrhs)).astype(np.float64)
+        A = L0 @ L0.T
+        return A, L0, X0, A @ X0
     L0 = np.tril(g.integers(-3, 4, (n, n)).astype(np.float64), -1)
     L0[np.diag_indices(n)] = g.choice([1.0, 2.0, 4.0], n)
     X0 = g.integers(-5, 6, (n, nrhs)).astype(np.float64)

@@ -7,8 +7,10 @@ oracle separately rounded products, so results agree to rounding, not bit for bi
            and ||L - Lo||_F <= 1e-12 ||Lo||_F
   solve:   |x_iq - xo_iq| <= 1e-12 ||xo_q||_inf (well-conditioned inputs, kappa <= 5)
            and the normwise backward error eta <= 1e-14.
-Integer-valued inputs are exact on both sides (every product and sum is an integer below
-2^53), so there the device result must equal the known factor and solution bit for bit.
+Integer-valued inputs (unit-diagonal factor with entries in {-1,0,1}) are exact on both
+sides: every product and sum, and every entry of the inverted 32x32 diagonal blocks the
+device multiplies by, is an integer below 2^53, so the device result must equal the known
+factor and solution bit for bit.
 """
 import numpy as np
 import pytest
@@ -104,7 +106,7 @@ def test_config1_parity(ctx):
 
 @pytest.mark.parametrize("n,b", [(96, 32), (200, 64), (640, 128)])
 def test_integer_inputs_exact(ctx, n, b):
-    A, L0, X0, B = inputs.integer_factor(n, seed=n, nrhs=3)
+    A, L0, X0, B = inputs.integer_factor(n, seed=n, nrhs=3, unit=True)
     F = ctx.potrf(dev(A), tile=b)
     assert np.array_equal(host(F.L()), L0)
     assert np.array_equal(host(ctx.potrs(F, dev(B))), X0)

@@ -3,8 +3,8 @@ POTRF/TRSM in FP64) and FP64 iterative refinement, through the C ABI.
 
 The low-precision factor itself is not compared with the oracle entry by entry (it is a
 different, rounded computation: parity unpinned).  Pinned instead:
-  * integer inputs (small-integer factor, diagonal in {1,2,4}): every product and sum is
-    an exact small integer in FP32 and BF16 too, so the mixed factor equals L0 bit for bit;
+  * integer inputs (unit-diagonal factor with entries in {-1,0,1}): every product and sum
+    is an exact small integer in FP32 and BF16 too, so the mixed factor equals L0 bit for bit;
   * the refined solution reaches eta <= 1e-12 (oracle's compensated backward error) and
     its forward error against the oracle's FP64 solution is <= kappa * 1e-12;
   * the factor residual is of the order of the low precision's unit roundoff.
@@ -37,7 +37,7 @@ def dev(x):
 @pytest.mark.parametrize("prec", [1, 2])
 @pytest.mark.parametrize("n,b", [(200, 64), (640, 128), (1024, 256)])
 def test_integer_inputs_exact_mixed(ctx, prec, n, b):
-    A, L0, X0, B = inputs.integer_factor(n, seed=n + prec, nrhs=2)
+    A, L0, X0, B = inputs.integer_factor(n, seed=n + prec, nrhs=2, unit=True)
     F = ctx.potrf(dev(A), tile=b, update_prec=prec)
     assert np.array_equal(F.L().cpu().numpy(), L0)
     assert np.array_equal(ctx.potrs(F, dev(B)).cpu().numpy(), X0)
