@@ -99,11 +99,17 @@ int spx_graph_indegree(const spx_graph* g, uint32_t* indeg, uint32_t cap);
 int spx_graph_to_dot(const spx_graph* g, const char* path);
 void spx_graph_destroy(spx_graph* g);
 
-/* The task program the factorisation (and, with with_solve, the block forward and
+/* The task program the factorisation (and, with with_solve bit 0, the block forward and
  * backward substitution) inserts for nt x nt tiles, built with spx_graph_build: right-
  * looking, lower triangle; for k: POTRF(k); TRSM(i,k) i>k; SYRK(i,k) and GEMM(i,j,k)
- * k<j<i.  task_types (nullable, ntasks entries) receives SPX_T_* codes. */
-enum { SPX_T_POTRF = 0, SPX_T_TRSM, SPX_T_SYRK, SPX_T_GEMM, SPX_T_FTRSM, SPX_T_FGEMM, SPX_T_BTRSM, SPX_T_BGEMM };
+ * k<j<i.  with_solve bit 1 adds the LOAD task in front (and, with bit 0, STORE at the end)
+ * as the batched calls run it.  Datum ids: tile (i,j) -> i*nt + j, right-hand-side block
+ * k -> nt*nt + k.  task_types (nullable, ntasks entries) receives SPX_T_* codes. */
+enum { SPX_T_POTRF = 0, SPX_T_TRSM, SPX_T_SYRK, SPX_T_GEMM, SPX_T_FTRSM, SPX_T_FGEMM, SPX_T_BTRSM, SPX_T_BGEMM,
+       SPX_T_LOAD, SPX_T_STORE };
+/* SPX_T_LOAD / SPX_T_STORE appear only in the graphs of the batched and served calls: the
+ * first task of each matrix copies its dense input (and right-hand sides) into tile
+ * storage, writing every tile; the last one reads the solution blocks and writes X. */
 int spx_cholesky_graph(int32_t nt, int32_t with_solve, spx_graph** out, int32_t* task_types, uint32_t cap);
 
 /* ---------------------------------------------------------------------------------------
@@ -190,6 +196,49 @@ int spx_backward_error(spx_ctx* ctx, int64_t n, const double* dA, int64_t lda, i
  * ------------------------------------------------------------------------------------ */
 int spx_run_task(spx_ctx* ctx, int32_t type, int32_t i, int32_t j, int32_t k, int32_t nt, int32_t b,
                  double* d_tiles, double* d_rhs, int32_t nrhs, int64_t* info);
+
+/* ---------------------------------------------------------------------------------------
+ * Batched factorisation and solve: many independent matrices in ONE persistent launch
+ * (Sec. 4.1: one engine runs several task graphs).  Each matrix contributes its own task
+ * graph (LOAD, the factor program, for spx_posv_batched the block substitution, STORE);
+ * the graphs are concatenated into one device image with no edges between matrices, so
+ * workgroups move freely between matrices while every matrix keeps its own dependency
+ * order.  Results are bitwise identical to spx_potrf_tiled / spx_potrs on each matrix with
+ * the same tile size.
+ *   count: number of matrices (1..1<<20).  n, lda, nrhs, ldb, ldx: host arrays of count
+ *   entries.  dA, dB, dX: host arrays of count device pointers (row-major, as for the
+ *   single-matrix calls; dA and dB are read only; dX may not alias dB).
+ *   opts: tile > 0 forces one tile size for every matrix; tile <= 0 takes each matrix's
+ *   tile from the context's tile table for opts->update_prec (spx_set_tile_table or
+ *   spx_autotune_batched), else from a size rule.  update_prec as for spx_potrf_tiled
+ *   (no refinement here: the FP32 / BF16 runs report the backward error they reach).
+ *   info: host array of count entries: 0, or the 1-based failing column of that matrix
+ *   (its X is then not written).  A failure of one matrix does not stop the others.
+ *   spx_potrf_batched returns one factor handle per matrix in out (NULL where info > 0),
+ *   usable with spx_potrs and spx_factor_get_l; spx_posv_batched keeps no factor.
+ * Errors: SPX_EINVAL, SPX_ENOMEM, SPX_EDEVICE, SPX_ETIMEOUT. */
+int spx_posv_batched(spx_ctx* ctx, int32_t count, const int64_t* n, const double* const* dA, const int64_t* lda,
+                     const int64_t* nrhs, const double* const* dB, const int64_t* ldb, double* const* dX,
+                     const int64_t* ldx, const spx_opts* opts, int64_t* info);
+int spx_potrf_batched(spx_ctx* ctx, int32_t count, const int64_t* n, const double* const* dA, const int64_t* lda,
+                      const spx_opts* opts, spx_factor** out, int64_t* info);
+
+/* Tile table of the context for update precision prec: a matrix of size n takes the tile
+ * of the first entry with n <= n_max[i] (n_max increasing), else of the last entry.
+ * count 0 clears the table (the size rule applies again).  tile[i] in {32,...,512}. */
+int spx_set_tile_table(spx_ctx* ctx, int32_t prec, int32_t count, const int64_t* n_max, const int32_t* tile);
+/* Tile the context would use for a matrix of size n at precision prec. */
+int spx_tile_for(const spx_ctx* ctx, int32_t prec, int64_t n, int32_t* tile);
+
+/* Autotuner: for each probe size sizes[i] (increasing), times spx_posv_batched on `copies`
+ * synthetic diagonally dominant SPD matrices of that size with nrhs right-hand sides, for
+ * every candidate tile in {32, 64, 128, 256, 512} not above the size rounded up to a power
+ * of two, and keeps the fastest (best kernel time of `reps` launches after one warm-up).
+ * best_tile: count entries; ms (nullable): nsizes x 5 kernel times in candidate order (0
+ * for a skipped candidate).  The result becomes the context's tile table for prec, with
+ * n_max = sizes; the caller may persist it and restore it with spx_set_tile_table. */
+int spx_autotune_batched(spx_ctx* ctx, int32_t prec, int32_t nsizes, const int64_t* sizes, int32_t nrhs,
+                         int32_t copies, int32_t reps, int32_t* best_tile, double* ms);
 
 /* ---------------------------------------------------------------------------------------
  * Run statistics of the last factor or solve launch on the context (Sec. 4.8 idle time).

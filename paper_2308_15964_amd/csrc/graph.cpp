@@ -162,6 +162,36 @@ void solve_program(int nt, std::vector<TaskDesc>& tasks, std::vector<spx_access>
     if (a.task >= first) acc.push_back(spx_access{a.task - first, a.mode, a.datum});
 }
 
+// Program of one matrix in a batched or served graph: LOAD writes every tile (and the
+// right-hand-side blocks), so each tile's first update depends on it; STORE reads the
+// solution blocks after the backward substitution.
+void io_program(int nt, bool with_solve, std::vector<TaskDesc>& tasks, std::vector<spx_access>& acc) {
+  std::vector<TaskDesc> body;
+  std::vector<spx_access> body_acc;
+  cholesky_program(nt, with_solve, body, body_acc);
+  auto A = [nt](int i, int j) { return (uint64_t)i * (uint64_t)nt + (uint64_t)j; };
+  auto B = [nt](int k) { return (uint64_t)nt * (uint64_t)nt + (uint64_t)k; };
+  tasks.clear();
+  acc.clear();
+  TaskDesc load;
+  load.type = SPX_T_LOAD;
+  load.i = (uint16_t)nt;  // one part per tile row (plus one for the right-hand sides)
+  tasks.push_back(load);
+  for (int i = 0; i < nt; ++i)
+    for (int j = 0; j <= i; ++j) acc.push_back(spx_access{0, SPX_ACC_RW, A(i, j)});
+  if (with_solve)
+    for (int k = 0; k < nt; ++k) acc.push_back(spx_access{0, SPX_ACC_RW, B(k)});
+  tasks.insert(tasks.end(), body.begin(), body.end());
+  for (const spx_access& a : body_acc) acc.push_back(spx_access{a.task + 1, a.mode, a.datum});
+  if (with_solve) {
+    TaskDesc store;
+    store.type = SPX_T_STORE;
+    const uint32_t t = (uint32_t)tasks.size();
+    tasks.push_back(store);
+    for (int k = 0; k < nt; ++k) acc.push_back(spx_access{t, SPX_ACC_R, B(k)});
+  }
+}
+
 // Default Cholesky priorities (larger = sooner): the panel chain POTRF -> TRSM -> SYRK and
 // the GEMMs that feed the next block column sit on the critical path; among equals the
 // earlier step k goes first.
@@ -172,6 +202,8 @@ int32_t cholesky_priority(const TaskDesc& d, int nt) {
     case SPX_T_TRSM: base = 3; break;
     case SPX_T_SYRK: base = (d.i == d.k + 1) ? 3 : 1; break;
     case SPX_T_GEMM: base = (d.j == d.k + 1) ? 2 : 0; break;
+    case SPX_T_LOAD: base = 0; break;   // a new matrix starts when nothing urgent is ready
+    case SPX_T_STORE: base = 4; break;
     default: base = 3; break;
   }
   return base * 65536 + (nt - d.k);
@@ -228,12 +260,12 @@ int spx_graph_to_dot(const spx_graph* g, const char* path) {
   if (!g || !path) return fail(SPX_EINVAL, "spx_graph_to_dot: null argument");
   FILE* f = std::fopen(path, "w");
   if (!f) return fail(SPX_EINVAL, "spx_graph_to_dot: cannot open file");
-  static const char* names[] = {"POTRF", "TRSM", "SYRK", "GEMM", "FTRSM", "FGEMM", "BTRSM", "BGEMM"};
+  static const char* names[] = {"POTRF", "TRSM", "SYRK", "GEMM", "FTRSM", "FGEMM", "BTRSM", "BGEMM", "LOAD", "STORE"};
   std::fprintf(f, "digraph spx {\n");
   for (uint32_t t = 0; t < g->g.ntasks; ++t) {
     if (t < g->tasks.size()) {
       const TaskDesc& d = g->tasks[t];
-      std::fprintf(f, "  t%u [label=\"%s(%d,%d,%d)\"];\n", t, d.type < 8 ? names[d.type] : "?", d.i, d.j, d.k);
+      std::fprintf(f, "  t%u [label=\"%s(%d,%d,%d)\"];\n", t, d.type < 10 ? names[d.type] : "?", d.i, d.j, d.k);
     } else {
       std::fprintf(f, "  t%u [label=\"t%u p%d\"];\n", t, t, g->g.prio[t]);
     }
@@ -248,12 +280,16 @@ int spx_graph_to_dot(const spx_graph* g, const char* path) {
 void spx_graph_destroy(spx_graph* g) { delete g; }
 
 int spx_cholesky_graph(int32_t nt, int32_t with_solve, spx_graph** out, int32_t* task_types, uint32_t cap) {
-  if (!out || nt < 1 || nt > 4096) return fail(SPX_EINVAL, "spx_cholesky_graph: bad argument");
+  if (!out || nt < 1 || nt > 4096 || with_solve < 0 || with_solve > 3)
+    return fail(SPX_EINVAL, "spx_cholesky_graph: bad argument");
   *out = nullptr;
   try {
     std::unique_ptr<spx_graph> g(new spx_graph());
     std::vector<spx_access> acc;
-    cholesky_program(nt, with_solve != 0, g->tasks, acc);
+    if (with_solve & 2)
+      io_program(nt, (with_solve & 1) != 0, g->tasks, acc);
+    else
+      cholesky_program(nt, with_solve != 0, g->tasks, acc);
     std::vector<int32_t> prio(g->tasks.size());
     for (size_t t = 0; t < g->tasks.size(); ++t) prio[t] = cholesky_priority(g->tasks[t], nt);
     int rc = build_graph((uint32_t)g->tasks.size(), acc.data(), acc.size(), prio.data(), g->g);

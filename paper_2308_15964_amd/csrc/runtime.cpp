@@ -73,6 +73,12 @@ struct Image {
 
 constexpr uint32_t kNumCounters = (2 * kMaxLevels + 2) * kCounterStride;
 
+// Task program of one matrix with its dependency graph (built once per shape).
+struct Program {
+  std::vector<TaskDesc> tasks;
+  Graph g;
+};
+
 }  // namespace spx
 
 using namespace spx;
@@ -87,6 +93,11 @@ struct spx_ctx {
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   spx_stats last{};
   std::map<std::string, Image*> images;
+  std::map<std::string, std::unique_ptr<Program>> programs;
+  // images of batched launches: few, large, keyed by the whole shape list (oldest evicted)
+  std::vector<std::pair<std::string, Image*>> batch_images;
+  // tile table per update precision: (n_max, tile), n_max increasing
+  std::vector<std::pair<int64_t, int>> tile_table[3];
   // small per-launch buffers
   DevMat* dmats = nullptr;
   size_t dmats_cap = 0;
@@ -133,6 +144,29 @@ static void dev_free(spx_ctx* c, void* p) {
     (void)hipFree(p);
 }
 
+static int get_program(spx_ctx* c, char kind, int nt, const Program** out) {
+  const std::string key = std::string(1, kind) + ":" + std::to_string(nt);
+  auto it = c->programs.find(key);
+  if (it != c->programs.end()) {
+    *out = it->second.get();
+    return SPX_OK;
+  }
+  std::unique_ptr<Program> pr(new Program());
+  std::vector<spx_access> acc;
+  switch (kind) {
+    case 'F': cholesky_program(nt, false, pr->tasks, acc); break;
+    case 'S': solve_program(nt, pr->tasks, acc); break;
+    case 'L': io_program(nt, false, pr->tasks, acc); break;
+    default: io_program(nt, true, pr->tasks, acc); break;
+  }
+  std::vector<int32_t> prio(pr->tasks.size());
+  for (size_t t = 0; t < pr->tasks.size(); ++t) prio[t] = cholesky_priority(pr->tasks[t], nt);
+  SPX_TRY(build_graph((uint32_t)pr->tasks.size(), acc.data(), acc.size(), prio.data(), pr->g));
+  *out = pr.get();
+  c->programs[key] = std::move(pr);
+  return SPX_OK;
+}
+
 static int valid_tile(int b) { return b == 32 || b == 64 || b == 128 || b == 256 || b == 512; }
 
 static int default_tile(int64_t n) {
@@ -158,6 +192,8 @@ uint16_t parts_of(const TaskDesc& d, int b, int nrhs) {
     case SPX_T_BTRSM: return (uint16_t)((nrhs + 7) / 8);
     case SPX_T_FGEMM:
     case SPX_T_BGEMM: return (uint16_t)(b / rows);
+    case SPX_T_LOAD: return (uint16_t)(d.i + (nrhs > 0 ? 1 : 0));
+    case SPX_T_STORE: return 1;
   }
   return 1;
 }
@@ -169,59 +205,75 @@ static int level_of(int32_t prio, int policy) {
   return l < 0 ? 0 : (l > kMaxLevels - 1 ? kMaxLevels - 1 : l);
 }
 
-// Builds (or returns the cached) device image of the factor (solve == false) or solve
-// program for nt x nt tiles of size b.
-static int get_image(spx_ctx* c, bool solve, int nt, int b, int nrhs, int policy, Image** out) {
-  char key[96];
-  const int rhs_parts = (nrhs + 7) / 8;
-  std::snprintf(key, sizeof key, "%c:%d:%d:%d:%d", solve ? 'S' : 'F', nt, b, solve ? rhs_parts : 0, policy);
-  auto it = c->images.find(key);
-  if (it != c->images.end()) {
-    *out = it->second;
-    return SPX_OK;
+// kind 'F': factor; 'S': substitution alone; 'L': LOAD + factor; 'P': LOAD + factor +
+// substitution + STORE.
+static int get_program(spx_ctx* c, char kind, int nt, const Program** out);
+
+// One matrix's share of an image: its program, descriptor index, tile size and
+// right-hand-side count (parts per task depend on both).
+struct Piece {
+  const Program* p;
+  uint32_t mat;
+  int b, nrhs;
+};
+
+// Uploads the concatenation of the pieces' graphs (no edges between pieces) as one
+// device image.
+static int make_image(spx_ctx* c, const std::vector<Piece>& pieces, int policy, Image** out) {
+  uint64_t T64 = 0, E64 = 0;
+  for (const Piece& pc : pieces) {
+    T64 += pc.p->g.ntasks;
+    E64 += pc.p->g.succ.size();
   }
-  std::vector<TaskDesc> tasks;
-  std::vector<spx_access> acc;
-  if (solve)
-    solve_program(nt, tasks, acc);
-  else
-    cholesky_program(nt, false, tasks, acc);
-  std::vector<int32_t> prio(tasks.size());
-  for (size_t t = 0; t < tasks.size(); ++t) prio[t] = cholesky_priority(tasks[t], nt);
-  Graph g;
-  SPX_TRY(build_graph((uint32_t)tasks.size(), acc.data(), acc.size(), prio.data(), g));
-  const uint32_t T = g.ntasks;
+  if (T64 >= (1ull << 32) - 1 || E64 >= (1ull << 32) - 1) return fail(SPX_EINVAL, "task graph too large");
+  const uint32_t T = (uint32_t)T64;
+  const size_t E = (size_t)E64;
   std::unique_ptr<Image> im(new Image());
   im->ntasks = T;
   im->nlev = policy == SPX_Q_FIFO ? 1 : kMaxLevels;
-  std::vector<uint32_t> nparts(T);
-  uint32_t per_level[kMaxLevels] = {0, 0, 0, 0};
-  for (uint32_t t = 0; t < T; ++t) {
-    tasks[t].nparts = parts_of(tasks[t], b, nrhs);
-    tasks[t].level = (uint8_t)level_of(prio[t], policy);
-    tasks[t].mat = 0;
-    nparts[t] = tasks[t].nparts;
-    per_level[tasks[t].level] += nparts[t];
-    im->total_parts += nparts[t];
+  std::vector<TaskDesc> tasks(T);
+  std::vector<uint32_t> off32(T + 1), succ(std::max<size_t>(E, 1)), indeg(T), nparts(T);
+  uint64_t per_level[kMaxLevels] = {0, 0, 0, 0};
+  uint32_t t0 = 0;
+  size_t e0 = 0;
+  for (const Piece& pc : pieces) {
+    const Program& pr = *pc.p;
+    for (uint32_t t = 0; t < pr.g.ntasks; ++t) {
+      TaskDesc d = pr.tasks[t];
+      d.nparts = parts_of(d, pc.b, pc.nrhs);
+      d.level = (uint8_t)level_of(pr.g.prio[t], policy);
+      d.mat = pc.mat;
+      tasks[t0 + t] = d;
+      nparts[t0 + t] = d.nparts;
+      indeg[t0 + t] = pr.g.indeg[t];
+      off32[t0 + t] = (uint32_t)(e0 + pr.g.off[t]);
+      per_level[d.level] += d.nparts;
+    }
+    for (size_t e = 0; e < pr.g.succ.size(); ++e) succ[e0 + e] = t0 + pr.g.succ[e];
+    t0 += pr.g.ntasks;
+    e0 += pr.g.succ.size();
   }
-  for (int l = 1; l < kMaxLevels; ++l) im->qbase[l] = im->qbase[l - 1] + per_level[l - 1];
+  off32[T] = (uint32_t)E;
+  uint64_t total = 0;
+  for (int l = 0; l < kMaxLevels; ++l) total += per_level[l];
+  if (total >= (1ull << 32) - 1) return fail(SPX_EINVAL, "task graph too large");
+  im->total_parts = (uint32_t)total;
+  for (int l = 1; l < kMaxLevels; ++l) im->qbase[l] = im->qbase[l - 1] + (uint32_t)per_level[l - 1];
   std::vector<u64> queue0(im->total_parts, ~0ull);
   std::vector<uint32_t> counters0(kNumCounters, 0);
   for (uint32_t t = 0; t < T; ++t) {
-    if (g.indeg[t] != 0) continue;
+    if (indeg[t] != 0) continue;
     const int l = tasks[t].level;
     uint32_t& tail = counters0[(kMaxLevels + l) * kCounterStride];
     for (uint32_t p = 0; p < nparts[t]; ++p) queue0[im->qbase[l] + tail + p] = ((u64)t << 16) | p;
     tail += nparts[t];
   }
-  std::vector<uint32_t> off32(T + 1);
-  for (uint32_t t = 0; t <= T; ++t) off32[t] = (uint32_t)g.off[t];
   // layout
   auto align = [](size_t x) { return (x + 255) & ~(size_t)255; };
   size_t o = 0;
   const size_t o_tasks = o; o = align(o + sizeof(TaskDesc) * T);
   const size_t o_off = o; o = align(o + 4 * (size_t)(T + 1));
-  const size_t o_succ = o; o = align(o + 4 * (size_t)std::max<size_t>(g.succ.size(), 1));
+  const size_t o_succ = o; o = align(o + 4 * succ.size());
   const size_t o_indeg = o; o = align(o + 4 * (size_t)T);
   const size_t o_np = o; o = align(o + 4 * (size_t)T);
   const size_t o_q0 = o; o = align(o + 8 * (size_t)im->total_parts);
@@ -249,8 +301,8 @@ static int get_image(spx_ctx* c, bool solve, int nt, int b, int nrhs, int policy
   std::vector<char> host(static_bytes, 0);
   std::memcpy(host.data() + o_tasks, tasks.data(), sizeof(TaskDesc) * T);
   std::memcpy(host.data() + o_off, off32.data(), 4 * (size_t)(T + 1));
-  if (!g.succ.empty()) std::memcpy(host.data() + o_succ, g.succ.data(), 4 * g.succ.size());
-  std::memcpy(host.data() + o_indeg, g.indeg.data(), 4 * (size_t)T);
+  std::memcpy(host.data() + o_succ, succ.data(), 4 * succ.size());
+  std::memcpy(host.data() + o_indeg, indeg.data(), 4 * (size_t)T);
   std::memcpy(host.data() + o_np, nparts.data(), 4 * (size_t)T);
   std::memcpy(host.data() + o_q0, queue0.data(), 8 * (size_t)im->total_parts);
   std::memcpy(host.data() + o_c0, counters0.data(), 4 * (size_t)kNumCounters);
@@ -260,8 +312,27 @@ static int get_image(spx_ctx* c, bool solve, int nt, int b, int nrhs, int policy
     dev_free(c, im->block);
     return rc;
   }
-  *out = im.get();
-  c->images[key] = im.release();
+  *out = im.release();
+  return SPX_OK;
+}
+
+// Builds (or returns the cached) device image of the factor (solve == false) or solve
+// program for nt x nt tiles of size b.
+static int get_image(spx_ctx* c, bool solve, int nt, int b, int nrhs, int policy, Image** out) {
+  char key[96];
+  const int rhs_parts = (nrhs + 7) / 8;
+  std::snprintf(key, sizeof key, "%c:%d:%d:%d:%d", solve ? 'S' : 'F', nt, b, solve ? rhs_parts : 0, policy);
+  auto it = c->images.find(key);
+  if (it != c->images.end()) {
+    *out = it->second;
+    return SPX_OK;
+  }
+  const Program* pr = nullptr;
+  SPX_TRY(get_program(c, solve ? 'S' : 'F', nt, &pr));
+  Image* im = nullptr;
+  SPX_TRY(make_image(c, {Piece{pr, 0, b, nrhs}}, policy, &im));
+  c->images[key] = im;
+  *out = im;
   return SPX_OK;
 }
 
@@ -365,11 +436,289 @@ static int run_image(spx_ctx* c, Image* im, int nmats, const spx_opts* o, double
   return SPX_OK;
 }
 
+static int tile_for_n(const spx_ctx* c, int prec, int64_t n) {
+  const auto& t = c->tile_table[prec];
+  if (t.empty()) return default_tile(n);
+  for (const auto& e : t)
+    if (n <= e.first) return e.second;
+  return t.back().second;
+}
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Batched factorisation (and with solve: substitution and STORE) of `count` matrices in
+// one launch.  fout (factor-only calls): receives one handle per healthy matrix.
+static int batched(spx_ctx* c, int count, const int64_t* n, const double* const* dA, const int64_t* lda,
+                   const int64_t* nrhs, const double* const* dB, const int64_t* ldb, double* const* dX,
+                   const int64_t* ldx, const spx_opts* o, bool solve, spx_factor** fout, int64_t* info) {
+  const char* who = solve ? "spx_posv_batched" : "spx_potrf_batched";
+  if (!c || !n || !dA || !lda || !info || (solve && (!nrhs || !dB || !ldb || !dX || !ldx)) || (!solve && !fout))
+    return failf(SPX_EINVAL, "%s: null argument", who);
+  if (count < 1 || count > (1 << 20)) return failf(SPX_EINVAL, "%s: count must be in [1, 2^20]", who);
+  const int prec = o ? o->update_prec : SPX_PREC_FP64;
+  if (prec != SPX_PREC_FP64 && prec != SPX_PREC_FP32 && prec != SPX_PREC_BF16)
+    return failf(SPX_EINVAL, "%s: bad update precision", who);
+  const int policy = o ? o->queue_policy : SPX_Q_PRIORITY;
+  if (policy != SPX_Q_PRIORITY && policy != SPX_Q_FIFO) return failf(SPX_EINVAL, "%s: bad queue policy", who);
+  if (o && o->tile > 0 && !valid_tile(o->tile)) return failf(SPX_EINVAL, "%s: bad tile size", who);
+  std::vector<int> bs(count), nts(count), qs(count, 0);
+  for (int m = 0; m < count; ++m) {
+    if (n[m] < 1 || lda[m] < n[m] || !dA[m]) return failf(SPX_EINVAL, "%s: matrix %d: bad n, lda or pointer", who, m);
+    if (solve) {
+      if (nrhs[m] < 1 || nrhs[m] > 4096 || ldb[m] < nrhs[m] || ldx[m] < nrhs[m] || !dB[m] || !dX[m])
+        return failf(SPX_EINVAL, "%s: matrix %d: bad right-hand sides", who, m);
+      if ((const double*)dX[m] == dB[m]) return failf(SPX_EINVAL, "%s: matrix %d: X aliases B", who, m);
+      qs[m] = (int)nrhs[m];
+    }
+    bs[m] = (o && o->tile > 0) ? o->tile : tile_for_n(c, prec, n[m]);
+    const int64_t nt = (n[m] + bs[m] - 1) / bs[m];
+    if (nt > 2048) return failf(SPX_EINVAL, "%s: matrix %d: too many tiles", who, m);
+    nts[m] = (int)nt;
+  }
+  SPX_TRY(hipc(hipSetDevice(c->device), "hipSetDevice"));
+  // storage: one workspace for the whole batch (posv) or one factor per matrix (potrf)
+  std::vector<size_t> off_t(count), off_d(count), off_r(count), off_l(count);
+  size_t ws = 0;
+  for (int m = 0; m < count; ++m) {
+    const size_t b = bs[m], nt = nts[m], npad = nt * b;
+    const size_t tb = nt * (nt + 1) / 2 * b * b * sizeof(double);
+    off_t[m] = ws; ws = align256(ws + tb);
+    off_d[m] = ws; ws = align256(ws + npad * 32 * sizeof(double));
+    off_r[m] = ws; ws = align256(ws + npad * (size_t)qs[m] * sizeof(double));
+    off_l[m] = ws; ws = align256(ws + (prec == SPX_PREC_FP64 ? 0 : tb / (prec == SPX_PREC_FP32 ? 2 : 4)));
+  }
+  char* block = nullptr;
+  std::vector<std::unique_ptr<spx_factor>> fs;
+  auto release = [&]() {
+    if (block) dev_free(c, block);
+    for (auto& f : fs)
+      if (f) {
+        dev_free(c, f->tiles);
+        dev_free(c, f->low);
+        dev_free(c, f->dinv);
+        f.reset();
+      }
+  };
+  if (solve) {
+    block = (char*)dev_alloc(c, ws);
+    if (!block) return failf(SPX_ENOMEM, "%s: workspace allocation failed (%zu bytes)", who, ws);
+  } else {
+    fs.resize(count);
+    for (int m = 0; m < count; ++m) {
+      std::unique_ptr<spx_factor> f(new spx_factor());
+      f->ctx = c;
+      f->n = n[m];
+      f->b = bs[m];
+      f->nt = nts[m];
+      f->n_pad = (int64_t)nts[m] * bs[m];
+      f->prec = prec;
+      f->tile_bytes = (size_t)nts[m] * (nts[m] + 1) / 2 * (size_t)bs[m] * bs[m] * sizeof(double);
+      f->tiles = (double*)dev_alloc(c, f->tile_bytes);
+      f->dinv = (double*)dev_alloc(c, (size_t)f->n_pad * 32 * sizeof(double));
+      if (prec != SPX_PREC_FP64) f->low = dev_alloc(c, f->tile_bytes / (prec == SPX_PREC_FP32 ? 2 : 4));
+      const bool ok = f->tiles && f->dinv && (prec == SPX_PREC_FP64 || f->low);
+      fs[m] = std::move(f);
+      if (!ok) {
+        release();
+        return failf(SPX_ENOMEM, "%s: factor storage allocation failed", who);
+      }
+    }
+  }
+  // image: concatenated per-matrix programs
+  std::string key = solve ? "P" : "L";
+  key += ":" + std::to_string(policy);
+  std::vector<Piece> pieces(count);
+  for (int m = 0; m < count; ++m) {
+    const Program* pr = nullptr;
+    int rc = get_program(c, solve ? 'P' : 'L', nts[m], &pr);
+    if (rc) {
+      release();
+      return rc;
+    }
+    pieces[m] = Piece{pr, (uint32_t)m, bs[m], qs[m]};
+    key += "," + std::to_string(nts[m]) + "/" + std::to_string(bs[m]) + "/" + std::to_string((qs[m] + 7) / 8);
+  }
+  Image* im = nullptr;
+  for (auto& kv : c->batch_images)
+    if (kv.first == key) im = kv.second;
+  if (!im) {
+    int rc = make_image(c, pieces, policy, &im);
+    if (rc) {
+      release();
+      return rc;
+    }
+    if (c->batch_images.size() >= 4) {
+      (void)hipStreamSynchronize(c->stream);
+      dev_free(c, c->batch_images.front().second->block);
+      delete c->batch_images.front().second;
+      c->batch_images.erase(c->batch_images.begin());
+    }
+    c->batch_images.emplace_back(key, im);
+  }
+  int rc = ensure_small_buffers(c, count, 1, 0, false);
+  if (rc) {
+    release();
+    return rc;
+  }
+  for (int m = 0; m < count; ++m) {
+    DevMat d{};
+    if (solve) {
+      d.tiles = (double*)(block + off_t[m]);
+      d.dinv = (double*)(block + off_d[m]);
+      d.rhs = (double*)(block + off_r[m]);
+      d.low = prec == SPX_PREC_FP64 ? nullptr : (void*)(block + off_l[m]);
+      d.B = dB[m];
+      d.X = dX[m];
+      d.ldb = ldb[m];
+      d.ldx = ldx[m];
+    } else {
+      d.tiles = fs[m]->tiles;
+      d.dinv = fs[m]->dinv;
+      d.low = fs[m]->low;
+    }
+    d.info = c->dinfo + m;
+    d.n_pad = (int64_t)nts[m] * bs[m];
+    d.nt = nts[m];
+    d.b = bs[m];
+    d.nrhs = qs[m];
+    d.prec = prec;
+    d.n = (int32_t)n[m];
+    d.trsm_rows = trsm_rows_of(bs[m]);
+    d.A = dA[m];
+    d.lda = lda[m];
+    c->hmats[m] = d;
+  }
+  rc = run_image(c, im, count, o, 0.0);
+  if (!rc) c->last.tile = (o && o->tile > 0) ? (uint32_t)o->tile : 0u;
+  if (rc) {
+    (void)hipStreamSynchronize(c->stream);
+    release();
+    return rc;
+  }
+  for (int m = 0; m < count; ++m) {
+    info[m] = c->hinfo[m] == INT_MAX ? 0 : c->hinfo[m];
+    if (!solve) {
+      if (info[m] == 0) {
+        fout[m] = fs[m].release();
+      } else {
+        fout[m] = nullptr;
+        dev_free(c, fs[m]->tiles);
+        dev_free(c, fs[m]->low);
+        dev_free(c, fs[m]->dinv);
+        fs[m].reset();
+      }
+    }
+  }
+  if (block) dev_free(c, block);
+  return SPX_OK;
+}
+
 }  // namespace spx
 
 extern "C" {
 
 const char* spx_last_error(void) { return g_err.c_str(); }
+
+int spx_posv_batched(spx_ctx* c, int32_t count, const int64_t* n, const double* const* dA, const int64_t* lda,
+                     const int64_t* nrhs, const double* const* dB, const int64_t* ldb, double* const* dX,
+                     const int64_t* ldx, const spx_opts* opts, int64_t* info) {
+  try {
+    return batched(c, count, n, dA, lda, nrhs, dB, ldb, dX, ldx, opts, true, nullptr, info);
+  } catch (const std::bad_alloc&) {
+    return fail(SPX_ENOMEM, "spx_posv_batched: out of host memory");
+  }
+}
+
+int spx_potrf_batched(spx_ctx* c, int32_t count, const int64_t* n, const double* const* dA, const int64_t* lda,
+                      const spx_opts* opts, spx_factor** out, int64_t* info) {
+  if (out && count > 0)
+    for (int m = 0; m < count; ++m) out[m] = nullptr;
+  try {
+    return batched(c, count, n, dA, lda, nullptr, nullptr, nullptr, nullptr, nullptr, opts, false, out, info);
+  } catch (const std::bad_alloc&) {
+    return fail(SPX_ENOMEM, "spx_potrf_batched: out of host memory");
+  }
+}
+
+int spx_set_tile_table(spx_ctx* c, int32_t prec, int32_t count, const int64_t* n_max, const int32_t* tile) {
+  if (!c || prec < 0 || prec > 2 || count < 0 || (count > 0 && (!n_max || !tile)))
+    return fail(SPX_EINVAL, "spx_set_tile_table: bad argument");
+  std::vector<std::pair<int64_t, int>> t;
+  for (int i = 0; i < count; ++i) {
+    if (!valid_tile(tile[i]) || n_max[i] < 1 || (i > 0 && n_max[i] <= n_max[i - 1]))
+      return fail(SPX_EINVAL, "spx_set_tile_table: tiles must be valid and n_max increasing");
+    t.emplace_back(n_max[i], tile[i]);
+  }
+  c->tile_table[prec] = t;
+  return SPX_OK;
+}
+
+int spx_tile_for(const spx_ctx* c, int32_t prec, int64_t n, int32_t* tile) {
+  if (!c || !tile || prec < 0 || prec > 2 || n < 1) return fail(SPX_EINVAL, "spx_tile_for: bad argument");
+  *tile = tile_for_n(c, prec, n);
+  return SPX_OK;
+}
+
+int spx_autotune_batched(spx_ctx* c, int32_t prec, int32_t nsizes, const int64_t* sizes, int32_t nrhs,
+                         int32_t copies, int32_t reps, int32_t* best_tile, double* ms) {
+  static const int cand[5] = {32, 64, 128, 256, 512};
+  if (!c || !sizes || !best_tile || prec < 0 || prec > 2 || nsizes < 1 || nrhs < 1 || nrhs > 4096 || copies < 1 ||
+      reps < 1)
+    return fail(SPX_EINVAL, "spx_autotune_batched: bad argument");
+  for (int i = 0; i < nsizes; ++i)
+    if (sizes[i] < 1 || sizes[i] > 65536 || (i > 0 && sizes[i] <= sizes[i - 1]))
+      return fail(SPX_EINVAL, "spx_autotune_batched: sizes must be increasing, in [1, 65536]");
+  SPX_TRY(hipc(hipSetDevice(c->device), "hipSetDevice"));
+  std::vector<int64_t> nmax(nsizes);
+  std::vector<int32_t> best(nsizes);
+  for (int i = 0; i < nsizes; ++i) {
+    const int64_t sz = sizes[i];
+    int64_t p2 = 32;
+    while (p2 < sz) p2 *= 2;
+    double* A = (double*)dev_alloc(c, (size_t)(sz * sz) * sizeof(double));
+    double* B = (double*)dev_alloc(c, (size_t)(sz * nrhs) * sizeof(double));
+    double* X = (double*)dev_alloc(c, (size_t)(sz * nrhs) * copies * sizeof(double));
+    int rc = (!A || !B || !X) ? fail(SPX_ENOMEM, "spx_autotune_batched: allocation failed") : SPX_OK;
+    if (!rc) rc = launch_spd_fill(A, sz, (uint32_t)i, c->stream);
+    if (!rc) rc = hipc(hipMemsetAsync(B, 0, (size_t)(sz * nrhs) * sizeof(double), c->stream), "hipMemsetAsync");
+    std::vector<int64_t> nv(copies, sz), ldv(copies, sz), qv(copies, nrhs), ldq(copies, nrhs), info(copies);
+    std::vector<const double*> av(copies, A), bv(copies, B);
+    std::vector<double*> xv(copies);
+    for (int m = 0; m < copies; ++m) xv[m] = X + (size_t)m * sz * nrhs;
+    double best_ms = INFINITY;
+    int best_b = default_tile(sz);
+    for (int ci = 0; ci < 5 && !rc; ++ci) {
+      const int b = cand[ci];
+      if (ms) ms[i * 5 + ci] = 0.0;
+      if (b > p2) continue;
+      spx_opts o{};
+      o.tile = b;
+      o.update_prec = prec;
+      double t = INFINITY;
+      for (int r = 0; r <= reps && !rc; ++r) {
+        rc = batched(c, copies, nv.data(), av.data(), ldv.data(), qv.data(), bv.data(), ldq.data(), xv.data(),
+                     ldq.data(), &o, true, nullptr, info.data());
+        if (!rc && r > 0) t = std::min(t, c->last.kernel_ms);
+      }
+      if (rc) break;
+      if (ms) ms[i * 5 + ci] = t;
+      if (t < best_ms) {
+        best_ms = t;
+        best_b = b;
+      }
+    }
+    (void)hipStreamSynchronize(c->stream);
+    dev_free(c, A);
+    dev_free(c, B);
+    dev_free(c, X);
+    if (rc) return rc;
+    nmax[i] = sz;
+    best[i] = best_b;
+    best_tile[i] = best_b;
+  }
+  return spx_set_tile_table(c, prec, nsizes, nmax.data(), best.data());
+}
+
 
 int spx_ctx_create(int device, void* hip_stream, spx_alloc_fn alloc, spx_free_fn free_fn, void* user, spx_ctx** out) {
   if (!out) return fail(SPX_EINVAL, "spx_ctx_create: null out");
@@ -395,6 +744,10 @@ void spx_ctx_destroy(spx_ctx* c) {
   if (!c) return;
   (void)hipStreamSynchronize(c->stream);
   for (auto& kv : c->images) {
+    dev_free(c, kv.second->block);
+    delete kv.second;
+  }
+  for (auto& kv : c->batch_images) {
     dev_free(c, kv.second->block);
     delete kv.second;
   }

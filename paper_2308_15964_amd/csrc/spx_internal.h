@@ -39,6 +39,8 @@ int build_graph(uint32_t ntasks, const spx_access* acc, uint64_t nacc, const int
 void cholesky_program(int nt, bool with_solve, std::vector<TaskDesc>& tasks, std::vector<spx_access>& acc);
 void solve_program(int nt, std::vector<TaskDesc>& tasks, std::vector<spx_access>& acc);
 int32_t cholesky_priority(const TaskDesc& d, int nt);
+// LOAD, the factor program (and with_solve: the substitution), STORE (with_solve only).
+void io_program(int nt, bool with_solve, std::vector<TaskDesc>& tasks, std::vector<spx_access>& acc);
 
 // ---------------------------------------------------------------------------------------
 // Device-side descriptors (plain data, copied to the GPU).
@@ -57,6 +59,11 @@ struct DevMat {
   int64_t n_pad;
   int32_t nt, b, nrhs, prec;
   int32_t n, trsm_rows, pad0, pad1;
+  // caller's dense arrays, used by the LOAD / STORE tasks of batched and served graphs
+  const double* A;  // n x n row-major, lower triangle read
+  const double* B;  // n x nrhs row-major
+  double* X;        // n x nrhs row-major
+  int64_t lda, ldb, ldx;
 };
 
 constexpr int kMaxLevels = 4;
@@ -101,6 +108,7 @@ int launch_one_task(const SchedArgs& a, int nparts, void* stream);
 int launch_tile_inverses(const double* l, int b, double* dinv, void* stream);
 uint16_t parts_of(const TaskDesc& d, int b, int nrhs);
 int sched_max_wg(int device, int* per_cu, int* num_cu);
+int launch_spd_fill(double* A, int64_t n, uint32_t seed, void* stream);
 int launch_backward_error(int64_t n, const double* dA, int64_t lda, int64_t nrhs, const double* dX, int64_t ldx,
                           const double* dB, int64_t ldb, double* dR, double* dstats, void* stream);
 

@@ -777,6 +777,30 @@ __device__ void bgemm_part(const double* __restrict__ l, int b, double* __restri
   }
 }
 
+// Sub-block (si, sj) of size S x S of tile (ti, tj); s: 64 x 65 doubles of LDS.
+__device__ void pack_block(const double* __restrict__ A, int64_t lda, int64_t n, const DevMat& m, int ti, int tj,
+                           int si, int sj, int S, double* __restrict__ s) {
+  const int b = m.b;
+  const int64_t R0 = (int64_t)ti * b + si * S, C0 = (int64_t)tj * b + sj * S;
+  for (int e = threadIdx.x; e < S * S; e += NT) {
+    const int rr = e / S, cc = e % S;  // cc fastest: row-major reads
+    const int64_t R = R0 + rr, C = C0 + cc;
+    double v;
+    if (R < n && C < n)
+      v = (R >= C) ? A[R * lda + C] : 0.0;
+    else
+      v = (R == C) ? 1.0 : 0.0;
+    s[rr * 65 + cc] = v;
+  }
+  __syncthreads();
+  double* T = tile_ptr(m, ti, tj);
+  for (int e = threadIdx.x; e < S * S; e += NT) {
+    const int cc = e / S, rr = e % S;  // rr fastest: column-major writes
+    T[(size_t)(sj * S + cc) * b + si * S + rr] = s[rr * 65 + cc];
+  }
+  __syncthreads();
+}
+
 // ---------------------------------------------------------------------------------------
 // Part dispatch.
 // ---------------------------------------------------------------------------------------
@@ -861,6 +885,29 @@ __device__ void run_part(const SchedArgs& a, uint32_t task, uint32_t part, doubl
       const int rows = b < 64 ? b : 64;
       bgemm_part(tile_ptr(m, d.j, d.i), b, m.rhs + (size_t)d.i * b, m.rhs + (size_t)d.j * b, m.n_pad, m.nrhs,
                  part * rows, rows, lds);
+      break;
+    }
+    case SPX_T_LOAD: {
+      if ((int)part < m.nt) {
+        // tile row `part`: every tile (part, tj), tj <= part, in S x S sub-blocks
+        const int S = b < 64 ? b : 64, per = b / S;
+        for (int tj = 0; tj <= (int)part; ++tj)
+          for (int q = 0; q < per * per; ++q) pack_block(m.A, m.lda, m.n, m, part, tj, q / per, q % per, S, lds);
+      } else {
+        const int64_t total = m.n_pad * m.nrhs;
+        for (int64_t e = threadIdx.x; e < total; e += NT) {
+          const int64_t q = e / m.n_pad, r = e % m.n_pad;
+          m.rhs[e] = r < m.n ? m.B[r * m.ldb + q] : 0.0;
+        }
+      }
+      break;
+    }
+    case SPX_T_STORE: {
+      const int64_t total = (int64_t)m.n * m.nrhs;
+      for (int64_t e = threadIdx.x; e < total; e += NT) {
+        const int64_t r = e / m.nrhs, q = e % m.nrhs;
+        m.X[r * m.ldx + q] = m.rhs[q * m.n_pad + r];
+      }
       break;
     }
     default:
@@ -1018,28 +1065,31 @@ __global__ void sched_init_kernel(uint32_t* pending, const uint32_t* indeg, uint
 // Rows/columns >= n form an identity border (padding).
 // ---------------------------------------------------------------------------------------
 __global__ __launch_bounds__(NT) void pack_kernel(const double* __restrict__ A, int64_t lda, int64_t n, DevMat m) {
-  __shared__ double s[64][65];
+  __shared__ double s[64 * 65];
   const int nt = m.nt, b = m.b;
   const int S = b < 64 ? b : 64, per = b / S;
   const int ti = blockIdx.x / nt, tj = blockIdx.x % nt;
   if (tj > ti) return;
-  const int si = blockIdx.y / per, sj = blockIdx.y % per;
-  const int64_t R0 = (int64_t)ti * b + si * S, C0 = (int64_t)tj * b + sj * S;
-  for (int e = threadIdx.x; e < S * S; e += NT) {
-    const int rr = e / S, cc = e % S;  // cc fastest: row-major reads
-    const int64_t R = R0 + rr, C = C0 + cc;
-    double v;
-    if (R < n && C < n)
-      v = (R >= C) ? A[R * lda + C] : 0.0;
-    else
-      v = (R == C) ? 1.0 : 0.0;
-    s[rr][cc] = v;
-  }
-  __syncthreads();
-  double* T = tile_ptr(m, ti, tj);
-  for (int e = threadIdx.x; e < S * S; e += NT) {
-    const int cc = e / S, rr = e % S;  // rr fastest: column-major writes
-    T[(size_t)(sj * S + cc) * b + si * S + rr] = s[rr][cc];
+  pack_block(A, lda, n, m, ti, tj, blockIdx.y / per, blockIdx.y % per, S, s);
+}
+
+// Diagonally dominant SPD test matrix (row-major n x n, both triangles): off-diagonal
+// entries uniform in [-1, 1) / n from a hash of (min(i,j), max(i,j), seed), diagonal 2.
+__global__ void spd_fill_kernel(double* __restrict__ A, int64_t n, uint32_t seed) {
+  const int64_t total = n * n;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e / n, j = e % n;
+    if (i == j) {
+      A[e] = 2.0;
+      continue;
+    }
+    uint64_t h = ((uint64_t)(i < j ? i : j) << 32) ^ (uint64_t)(i < j ? j : i) ^ ((uint64_t)seed << 56);
+    h ^= h >> 33;
+    h *= 0xff51afd7ed558ccdull;
+    h ^= h >> 33;
+    h *= 0xc4ceb9fe1a85ec53ull;
+    h ^= h >> 33;
+    A[e] = ((double)(h >> 11) * 0x1.0p-53 * 2.0 - 1.0) / (double)n;
   }
 }
 
@@ -1181,6 +1231,11 @@ int launch_pack(const double* dA, int64_t lda, int64_t n, const DevMat& m, void*
   dim3 grid((unsigned)(m.nt * m.nt), (unsigned)(per * per));
   hipLaunchKernelGGL(pack_kernel, grid, dim3(NT), 0, (hipStream_t)stream, dA, lda, n, m);
   return hip_ok(hipGetLastError(), "pack_kernel");
+}
+
+int launch_spd_fill(double* A, int64_t n, uint32_t seed, void* stream) {
+  hipLaunchKernelGGL(spd_fill_kernel, dim3(1024), dim3(NT), 0, (hipStream_t)stream, A, n, seed);
+  return hip_ok(hipGetLastError(), "spd_fill_kernel");
 }
 
 int launch_unpack(const DevMat& m, int64_t n, double* dL, int64_t ldl, void* stream) {

@@ -14,8 +14,9 @@ LIB_PATH = os.path.join(_HERE, "libspx.so")
 
 SPX_OK, SPX_EINVAL, SPX_ENOMEM, SPX_EDEVICE, SPX_EAGAIN, SPX_EABORT, SPX_ETIMEOUT = 0, -1, -2, -3, -4, -5, -6
 ACC_R, ACC_RW = 1, 2
-T_POTRF, T_TRSM, T_SYRK, T_GEMM, T_FTRSM, T_FGEMM, T_BTRSM, T_BGEMM = range(8)
-TASK_NAMES = ["POTRF", "TRSM", "SYRK", "GEMM", "FTRSM", "FGEMM", "BTRSM", "BGEMM"]
+T_POTRF, T_TRSM, T_SYRK, T_GEMM, T_FTRSM, T_FGEMM, T_BTRSM, T_BGEMM, T_LOAD, T_STORE = range(10)
+TASK_NAMES = ["POTRF", "TRSM", "SYRK", "GEMM", "FTRSM", "FGEMM", "BTRSM", "BGEMM", "LOAD", "STORE"]
+TILE_CANDIDATES = [32, 64, 128, 256, 512]
 PREC_FP64, PREC_FP32, PREC_BF16 = 0, 1, 2
 Q_PRIORITY, Q_FIFO = 0, 1
 F_TRACE = 1
@@ -64,7 +65,8 @@ EXPORTS = [
     "spx_last_error", "spx_ctx_create", "spx_ctx_destroy", "spx_graph_build", "spx_graph_info", "spx_graph_edges",
     "spx_graph_indegree", "spx_graph_to_dot", "spx_graph_destroy", "spx_cholesky_graph", "spx_potrf_tiled",
     "spx_factor_info", "spx_factor_get_l", "spx_factor_destroy", "spx_potrs", "spx_backward_error",
-    "spx_run_task", "spx_last_stats", "spx_trace",
+    "spx_run_task", "spx_posv_batched", "spx_potrf_batched", "spx_set_tile_table", "spx_tile_for",
+    "spx_autotune_batched", "spx_last_stats", "spx_trace",
 ]
 
 _lib = None
@@ -104,6 +106,12 @@ def lib():
         "spx_potrs": (ctypes.c_int, [vp, vp, i64, vp, i64, vp, i64, vp, i64, P(Refine), P(SolveStats)]),
         "spx_backward_error": (ctypes.c_int, [vp, i64, vp, i64, i64, vp, i64, vp, i64, P(ctypes.c_double)]),
         "spx_run_task": (ctypes.c_int, [vp, i32, i32, i32, i32, i32, i32, vp, vp, i32, P(i64)]),
+        "spx_posv_batched": (ctypes.c_int, [vp, i32, P(i64), P(vp), P(i64), P(i64), P(vp), P(i64), P(vp), P(i64),
+                                             P(Opts), P(i64)]),
+        "spx_potrf_batched": (ctypes.c_int, [vp, i32, P(i64), P(vp), P(i64), P(Opts), P(vp), P(i64)]),
+        "spx_set_tile_table": (ctypes.c_int, [vp, i32, i32, P(i64), P(i32)]),
+        "spx_tile_for": (ctypes.c_int, [vp, i32, i64, P(i32)]),
+        "spx_autotune_batched": (ctypes.c_int, [vp, i32, i32, P(i64), i32, i32, i32, P(i32), P(ctypes.c_double)]),
         "spx_last_stats": (ctypes.c_int, [vp, P(Stats)]),
         "spx_trace": (i64, [vp, P(u64), i64]),
     }
@@ -142,12 +150,14 @@ class Graph:
         return cls(h.value)
 
     @classmethod
-    def cholesky(cls, nt, with_solve=False):
+    def cholesky(cls, nt, with_solve=False, io=False):
         h = ctypes.c_void_p()
         from math import comb
         T = nt + 2 * comb(nt, 2) + comb(nt, 3) + (2 * (nt + comb(nt, 2)) if with_solve else 0)
+        if io:
+            T += 2 if with_solve else 1
         types = (ctypes.c_int32 * T)()
-        _check(lib().spx_cholesky_graph(nt, int(with_solve), ctypes.byref(h), types, T))
+        _check(lib().spx_cholesky_graph(nt, int(bool(with_solve)) | (2 if io else 0), ctypes.byref(h), types, T))
         return cls(h.value, np.array(types[:], dtype=np.int32))
 
     def info(self):
@@ -297,6 +307,79 @@ class Context:
         info = ctypes.c_int64()
         _check(lib().spx_run_task(self._h, type_, i, j, k, nt, b, _ptr(tiles), r, nrhs, ctypes.byref(info)))
         return info.value
+
+    # -------------------------------------------------------------- batched (one launch)
+    def _batch_arrays(self, As, Bs=None, Xs=None):
+        k = len(As)
+        i64a = ctypes.c_int64 * k
+        vpa = ctypes.c_void_p * k
+        n = i64a(*[a.shape[0] for a in As])
+        lda = i64a(*[a.stride(0) for a in As])
+        pa = vpa(*[a.data_ptr() for a in As])
+        for a in As:
+            self._dev(a, "A")
+            if a.dim() != 2 or a.shape[0] != a.shape[1]:
+                raise ValueError("every A must be square")
+        out = [n, pa, lda]
+        if Bs is not None:
+            out += [i64a(*[b.shape[1] for b in Bs]), vpa(*[b.data_ptr() for b in Bs]), i64a(*[b.stride(0) for b in Bs]),
+                    vpa(*[x.data_ptr() for x in Xs]), i64a(*[x.stride(0) for x in Xs])]
+        return out
+
+    def posv_batched(self, As, Bs, tile=0, update_prec=PREC_FP64, queue_policy=Q_PRIORITY, num_wg=0, flags=0,
+                     Xs=None):
+        """Factors and solves every (A_i, B_i) in one launch; returns (Xs, info array).
+        B_i: n_i x q_i float64 on the device (2-D)."""
+        torch = self.torch
+        if len(As) != len(Bs) or not As:
+            raise ValueError("need equally many matrices and right-hand sides")
+        Bs = [self._dev(b, "B") for b in Bs]
+        if any(b.dim() != 2 or b.shape[0] != a.shape[0] for a, b in zip(As, Bs)):
+            raise ValueError("B_i must be n_i x q_i")
+        if Xs is None:
+            Xs = [torch.empty_like(b) for b in Bs]
+        n, pa, lda, q, pb, ldb, px, ldx = self._batch_arrays(As, Bs, Xs)
+        info = (ctypes.c_int64 * len(As))()
+        o = Opts(tile, update_prec, queue_policy, num_wg, flags)
+        _check(lib().spx_posv_batched(self._h, len(As), n, pa, lda, q, pb, ldb, px, ldx, ctypes.byref(o), info))
+        return Xs, np.array(info[:], dtype=np.int64)
+
+    def potrf_batched(self, As, tile=0, update_prec=PREC_FP64, queue_policy=Q_PRIORITY, num_wg=0, flags=0):
+        """Factors every A_i in one launch; returns (list of Factor or None, info array)."""
+        if not As:
+            raise ValueError("empty batch")
+        n, pa, lda = self._batch_arrays(As)
+        k = len(As)
+        hs = (ctypes.c_void_p * k)()
+        info = (ctypes.c_int64 * k)()
+        o = Opts(tile, update_prec, queue_policy, num_wg, flags)
+        _check(lib().spx_potrf_batched(self._h, k, n, pa, lda, ctypes.byref(o), hs, info))
+        fs = [Factor(self, h) if h else None for h in hs]
+        return fs, np.array(info[:], dtype=np.int64)
+
+    def set_tile_table(self, prec, table):
+        """table: list of (n_max, tile), n_max increasing ([] clears)."""
+        k = len(table)
+        nm = (ctypes.c_int64 * max(k, 1))(*[int(a) for a, _ in table])
+        tl = (ctypes.c_int32 * max(k, 1))(*[int(b) for _, b in table])
+        _check(lib().spx_set_tile_table(self._h, prec, k, nm, tl))
+
+    def tile_for(self, prec, n):
+        t = ctypes.c_int32()
+        _check(lib().spx_tile_for(self._h, prec, n, ctypes.byref(t)))
+        return t.value
+
+    def autotune_batched(self, sizes, prec=PREC_FP64, nrhs=4, copies=256, reps=2):
+        """Times every candidate tile per probe size (see spx_autotune_batched); the result
+        becomes the context's table.  Returns {"prec", "table": [(n_max, tile)], "ms": ...}."""
+        k = len(sizes)
+        sz = (ctypes.c_int64 * k)(*[int(s) for s in sizes])
+        best = (ctypes.c_int32 * k)()
+        ms = (ctypes.c_double * (5 * k))()
+        _check(lib().spx_autotune_batched(self._h, prec, k, sz, nrhs, copies, reps, best, ms))
+        return {"prec": prec, "nrhs": nrhs, "copies": copies,
+                "table": [(int(s), int(b)) for s, b in zip(sizes, best)],
+                "ms": {int(s): dict(zip(TILE_CANDIDATES, ms[5 * i:5 * i + 5])) for i, s in enumerate(sizes)}}
 
     def stats(self):
         s = Stats()

@@ -82,3 +82,30 @@ def test_empty_graph():
     assert g.info() == (0, 0)
     g = spx.Graph.build(4, [])
     assert g.info() == (4, 0) and g.indegree().tolist() == [0, 0, 0, 0]
+
+
+@pytest.mark.parametrize("nt", [1, 2, 3, 6, 9])
+@pytest.mark.parametrize("with_solve", [False, True])
+def test_batched_member_graph_bit_exact(nt, with_solve):
+    """The program one matrix contributes to a batched launch: LOAD (writes every datum the
+    factor / solve touches) in front, STORE (reads the solution blocks) at the end.  Its
+    edges must equal the pairwise definition applied to that access list."""
+    tasks, acc = oracle.cholesky_program(nt, with_solve)
+    data = sorted({d for _, _, d in acc})
+    rhs = sorted({d for t, m, d in acc if tasks[t][0] == "FTRSM" and m == spx.ACC_RW})
+    prog = [(0, spx.ACC_RW, d) for d in data] + [(t + 1, m, d) for t, m, d in acc]
+    T = len(tasks) + 1
+    if with_solve:
+        prog += [(T, spx.ACC_R, d) for d in rhs]
+        T += 1
+    want, kinds = oracle.dag_edges(T, prog)
+    g = spx.Graph.cholesky(nt, with_solve, io=True)
+    assert g.info() == (T, len(want))
+    assert np.array_equal(g.edges(), want)
+    names = [spx.TASK_NAMES[t] for t in g.task_types]
+    assert names[0] == "LOAD" and (names[-1] == "STORE") == with_solve
+    assert names[1:T - (1 if with_solve else 0)] == [t[0] for t in tasks]
+    indeg = g.indegree()
+    assert indeg[0] == 0 and (indeg[1:] > 0).all()  # one root per matrix: its LOAD
+    if with_solve:
+        assert indeg[-1] == nt  # the last write of each solution block
