@@ -224,7 +224,9 @@ int spx_potrf_batched(spx_ctx* ctx, int32_t count, const int64_t* n, const doubl
                       const spx_opts* opts, spx_factor** out, int64_t* info);
 
 /* Tile table of the context for update precision prec: a matrix of size n takes the tile
- * of the first entry with n <= n_max[i] (n_max increasing), else of the last entry.
+ * of the first entry with n <= n_max[i] (n_max increasing); above the last entry, and
+ * with no table, a size rule applies (32 below 128, 64 below 512, 128 below 2048, 256
+ * below 8192, else 512).
  * count 0 clears the table (the size rule applies again).  tile[i] in {32,...,512}. */
 int spx_set_tile_table(spx_ctx* ctx, int32_t prec, int32_t count, const int64_t* n_max, const int32_t* tile);
 /* Tile the context would use for a matrix of size n at precision prec. */
@@ -239,6 +241,79 @@ int spx_tile_for(const spx_ctx* ctx, int32_t prec, int64_t n, int32_t* tile);
  * n_max = sizes; the caller may persist it and restore it with spx_set_tile_table. */
 int spx_autotune_batched(spx_ctx* ctx, int32_t prec, int32_t nsizes, const int64_t* sizes, int32_t nrhs,
                          int32_t copies, int32_t reps, int32_t* best_tile, double* ms);
+
+/* ---------------------------------------------------------------------------------------
+ * Serving: SPD solve requests of mixed sizes, admitted by an HBM budget and run with
+ * continuous batching.  The server owns `lanes` worker threads, each with its own HIP
+ * stream and context.  Admission is first-fit over the queue of waiting requests in
+ * arrival order (a request that does not fit yet does not block smaller ones behind it)
+ * against the byte budget (factor tiles, block inverses, low-precision copies, right-hand
+ * side work arrays, and device copies of host inputs).  An idle lane takes every admitted
+ * request of one mode (up to max_batch) and runs them as ONE batched launch; requests that
+ * arrive meanwhile are admitted as memory frees up and start on the next idle lane, so
+ * their work overlaps on the device with the batches already running.
+ *   mode SPX_MODE_FP64: FP64 factor + solve (spx_posv_batched), then the backward error.
+ *   mode SPX_MODE_MIXED: FP32-update factor (spx_potrf_batched), then FP64 classical
+ *   iterative refinement to tol (spx_potrs method 1); if that fails to converge the request
+ *   is redone in FP64 (method_used = 0 reports the fallback).
+ * The result of a request does not depend on what else is in the same batch or lane: a
+ * batched member runs the same kernels in the same dependency order as when alone.
+ *   A, B, X: n x n, n x nrhs, n x nrhs row-major with leading dimensions lda, ldb, ldx;
+ *   where = 0: host memory (copied in and out by the lane; pinned memory copies faster),
+ *   where = 1: device memory of the context's GPU.  The caller keeps them alive and A, B
+ *   unmodified until spx_poll returns SPX_OK for the ticket (or the server is destroyed).
+ *   tol <= 0 means 1e-12.  tag: returned in the result.
+ * spx_submit never blocks: it records the request and returns a ticket; SPX_ENOMEM if the
+ * request can never fit the budget; SPX_EINVAL for bad arguments.
+ * spx_poll: SPX_OK with *out filled (the ticket is then released), SPX_EAGAIN if not
+ * done, SPX_EINVAL for an unknown ticket.  out->status: SPX_OK, SPX_EDEVICE, ... for the
+ * request itself; out->info > 0: not positive definite at that column.
+ * Times (seconds on the server's steady clock, spx_server_now): submit, admission, start
+ * of the launch that ran it, result available (X written back).
+ * spx_server_destroy: requests not yet started end with status SPX_EABORT; running
+ * batches finish first. */
+enum { SPX_MODE_FP64 = 0, SPX_MODE_MIXED = 1 };
+typedef struct {
+  int64_t n, nrhs;
+  const double* A;
+  const double* B;
+  double* X;
+  int64_t lda, ldb, ldx;
+  int32_t mode;
+  int32_t where;
+  double tol;
+  uint64_t tag;
+} spx_request;
+typedef struct {
+  int32_t status;
+  int32_t iters;
+  int32_t method_used;
+  int32_t tile;
+  int64_t info;
+  double eta_max;
+  double t_submit, t_admit, t_start, t_done;
+  uint64_t tag;
+  int32_t batch_size;
+  int32_t lane;
+} spx_result;
+typedef struct {
+  int32_t lanes;      /* worker lanes (streams); <= 0: 2 */
+  int32_t max_batch;  /* requests per launch; <= 0: 4096 */
+  int32_t num_wg;     /* workgroups per launch; <= 0: fill the GPU */
+  int32_t pad;
+} spx_server_opts;
+typedef struct {
+  uint64_t submitted, completed, rejected, launches;
+  uint64_t bytes_in_use, bytes_peak;
+  uint64_t max_running;  /* most requests running at once over all lanes */
+  double busy_s;         /* summed lane busy time */
+} spx_server_stats;
+int spx_server_create(spx_ctx* ctx, size_t hbm_budget_bytes, const spx_server_opts* opts, spx_server** out);
+int spx_submit(spx_server* s, const spx_request* req, uint64_t* ticket);
+int spx_poll(spx_server* s, uint64_t ticket, spx_result* out);
+double spx_server_now(const spx_server* s);
+int spx_server_get_stats(spx_server* s, spx_server_stats* out);
+void spx_server_destroy(spx_server* s);
 
 /* ---------------------------------------------------------------------------------------
  * Run statistics of the last factor or solve launch on the context (Sec. 4.8 idle time).

@@ -9,7 +9,7 @@ CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libspx.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["graph.cpp", "runtime.cpp", "spx_kernels.hip"]
+SOURCES = ["graph.cpp", "runtime.cpp", "server.cpp", "spx_kernels.hip"]
 # -packed-fp32-ops: keep the compiler from emitting packed FP32 VALU instructions.
 DEVICE_FLAGS = ["--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-I", os.path.join(ROOT, "include"), "-I", CSRC]
@@ -25,7 +25,7 @@ def build(verbose=False):
         if src.endswith(".hip"):
             cmd[1:1] = DEVICE_FLAGS
         else:
-            cmd[1:1] = ["-D__HIP_PLATFORM_AMD__"]
+            cmd[1:1] = ["-D__HIP_PLATFORM_AMD__", "-pthread"]
         if verbose:
             print(" ".join(cmd))
         r = subprocess.run(cmd, capture_output=True, text=True)
@@ -34,7 +34,7 @@ def build(verbose=False):
             raise RuntimeError("compile failed: " + src)
         objs.append(obj)
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, *DEVICE_FLAGS, "-shared", "-fPIC", "-o", tmp, *objs]
+    cmd = [HIPCC, *DEVICE_FLAGS, "-shared", "-fPIC", "-pthread", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)

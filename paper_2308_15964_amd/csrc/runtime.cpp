@@ -441,10 +441,17 @@ static int tile_for_n(const spx_ctx* c, int prec, int64_t n) {
   if (t.empty()) return default_tile(n);
   for (const auto& e : t)
     if (n <= e.first) return e.second;
-  return t.back().second;
+  return default_tile(n);
 }
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+int ctx_device(const spx_ctx* c) { return c->device; }
+
+int ctx_copy_tile_tables(const spx_ctx* from, spx_ctx* to) {
+  for (int p = 0; p < 3; ++p) to->tile_table[p] = from->tile_table[p];
+  return SPX_OK;
+}
 
 // Batched factorisation (and with solve: substitution and STORE) of `count` matrices in
 // one launch.  fout (factor-only calls): receives one handle per healthy matrix.

@@ -1,0 +1,426 @@
+// Serving loop of libspx: admission of SPD solve requests by an HBM budget and continuous
+// batching over worker lanes (one HIP stream and context each).  Every batch a lane takes
+// runs as one persistent-kernel launch over all of its requests' task graphs (Specx
+// Sec. 4.1: one engine, several graphs), so the device work of the requests in a batch
+// overlaps, and batches of different lanes overlap with each other.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <climits>
+#include <cmath>
+#include <condition_variable>
+#include <deque>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "spx_internal.h"
+
+namespace spx {
+namespace {
+
+enum ReqState { WAITING, ADMITTED, RUNNING, DONE };
+
+struct Req {
+  spx_request r;
+  size_t bytes = 0;
+  int tile = 0;
+  ReqState state = WAITING;
+  spx_result res{};
+};
+
+struct Lane {
+  spx_ctx* ctx = nullptr;
+  hipStream_t stream = nullptr;
+  std::thread th;
+};
+
+// Stream-ordered device allocations from the device's default memory pool, so lanes do
+// not serialise on the allocator and freed blocks are reused.
+void* pool_alloc(size_t bytes, void* stream, void*) {
+  void* p = nullptr;
+  if (hipMallocAsync(&p, bytes, (hipStream_t)stream) != hipSuccess) return nullptr;
+  return p;
+}
+void pool_free(void* p, void* stream, void*) { (void)hipFreeAsync(p, (hipStream_t)stream); }
+
+}  // namespace
+}  // namespace spx
+
+using namespace spx;
+
+struct spx_server {
+  int device = 0;
+  size_t budget = 0;
+  spx_server_opts opts{};
+  std::chrono::steady_clock::time_point t0;
+  std::mutex mu;
+  std::condition_variable cv;
+  bool stop = false;
+  uint64_t next_ticket = 1;
+  std::unordered_map<uint64_t, Req> reqs;
+  std::deque<uint64_t> waiting;   // arrival order
+  std::deque<uint64_t> admitted;  // admission order
+  std::vector<Lane> lanes;
+  spx_server_stats st{};
+  uint64_t running = 0;
+  spx_ctx* tuner = nullptr;  // holds the tile tables (copied from the creating context)
+
+  double now() const { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); }
+};
+
+namespace spx {
+namespace {
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Device bytes a request holds while it runs (what the batched calls and the refinement
+// allocate for it, plus device copies of host inputs).
+size_t request_bytes(const spx_request& r, int b) {
+  const size_t n = (size_t)r.n, q = (size_t)r.nrhs, nt = (n + b - 1) / b, npad = nt * b;
+  const size_t tiles = nt * (nt + 1) / 2 * (size_t)b * b * 8;
+  size_t s = align256(tiles) + align256(npad * 32 * 8) + align256(npad * q * 8);
+  if (r.mode == SPX_MODE_MIXED) s += align256(tiles / 2) + 2 * align256(n * q * 8) + align256(npad * q * 8);
+  if (r.where == 0) s += align256(n * n * 8) + align256(n * q * 8) + align256(n * q * 8);
+  return s;
+}
+
+// Moves waiting requests that fit into the admitted queue (first fit, arrival order).
+void admit(spx_server* s) {
+  for (auto it = s->waiting.begin(); it != s->waiting.end();) {
+    Req& q = s->reqs[*it];
+    if (s->st.bytes_in_use + q.bytes <= s->budget) {
+      s->st.bytes_in_use += q.bytes;
+      s->st.bytes_peak = std::max<uint64_t>(s->st.bytes_peak, s->st.bytes_in_use);
+      q.state = ADMITTED;
+      q.res.t_admit = s->now();
+      s->admitted.push_back(*it);
+      it = s->waiting.erase(it);
+    } else {
+      ++it;
+    }
+  }
+}
+
+struct Work {
+  uint64_t ticket;
+  spx_request r;
+  int tile;
+  spx_result res{};
+  // device views
+  const double* A = nullptr;
+  const double* B = nullptr;
+  double* X = nullptr;
+  int64_t lda = 0, ldb = 0, ldx = 0;
+  void* own[3] = {nullptr, nullptr, nullptr};
+};
+
+int hip_status(hipError_t e) { return e == hipSuccess ? SPX_OK : SPX_EDEVICE; }
+
+// Runs one batch (all of one mode) on a lane.
+void run_batch(spx_server* s, Lane& ln, int lane_id, std::vector<Work>& w) {
+  spx_ctx* c = ln.ctx;
+  hipStream_t st = ln.stream;
+  const int K = (int)w.size();
+  const double t_start = s->now();
+  for (auto& x : w) {
+    x.res.t_start = t_start;
+    x.res.batch_size = K;
+    x.res.lane = lane_id;
+    x.res.tile = x.tile;
+    x.res.status = SPX_OK;
+  }
+  // inputs on the device
+  int rc = SPX_OK;
+  for (auto& x : w) {
+    const size_t n = (size_t)x.r.n, q = (size_t)x.r.nrhs;
+    if (x.r.where == 1) {
+      x.A = x.r.A;
+      x.B = x.r.B;
+      x.X = x.r.X;
+      x.lda = x.r.lda;
+      x.ldb = x.r.ldb;
+      x.ldx = x.r.ldx;
+      continue;
+    }
+    x.own[0] = pool_alloc(n * n * 8, st, nullptr);
+    x.own[1] = pool_alloc(n * q * 8, st, nullptr);
+    x.own[2] = pool_alloc(n * q * 8, st, nullptr);
+    if (!x.own[0] || !x.own[1] || !x.own[2]) {
+      rc = SPX_ENOMEM;
+      break;
+    }
+    x.A = (const double*)x.own[0];
+    x.B = (const double*)x.own[1];
+    x.X = (double*)x.own[2];
+    x.lda = (int64_t)n;
+    x.ldb = x.ldx = (int64_t)q;
+    rc = hip_status(hipMemcpy2DAsync(x.own[0], n * 8, x.r.A, (size_t)x.r.lda * 8, n * 8, n, hipMemcpyHostToDevice, st));
+    if (!rc)
+      rc = hip_status(
+          hipMemcpy2DAsync(x.own[1], q * 8, x.r.B, (size_t)x.r.ldb * 8, q * 8, n, hipMemcpyHostToDevice, st));
+    if (rc) break;
+  }
+  std::vector<int64_t> n(K), lda(K), q(K), ldb(K), ldx(K), info(K, 0);
+  std::vector<const double*> A(K), B(K);
+  std::vector<double*> X(K);
+  for (int i = 0; i < K; ++i) {
+    n[i] = w[i].r.n;
+    q[i] = w[i].r.nrhs;
+    A[i] = w[i].A;
+    B[i] = w[i].B;
+    X[i] = w[i].X;
+    lda[i] = w[i].lda;
+    ldb[i] = w[i].ldb;
+    ldx[i] = w[i].ldx;
+  }
+  spx_opts o{};
+  o.num_wg = s->opts.num_wg;
+  const bool mixed = w[0].r.mode == SPX_MODE_MIXED;
+  if (!rc && !mixed) {
+    o.update_prec = SPX_PREC_FP64;
+    rc = spx_posv_batched(c, K, n.data(), A.data(), lda.data(), q.data(), B.data(), ldb.data(), X.data(), ldx.data(),
+                          &o, info.data());
+    for (int i = 0; !rc && i < K; ++i) {
+      w[i].res.info = info[i];
+      w[i].res.method_used = 0;
+      if (info[i]) continue;
+      std::vector<double> eta(q[i]);
+      rc = spx_backward_error(c, n[i], A[i], lda[i], q[i], X[i], ldx[i], B[i], ldb[i], eta.data());
+      double e = 0;
+      for (double v : eta) e = std::max(e, v);
+      w[i].res.eta_max = e;
+    }
+  } else if (!rc) {
+    o.update_prec = SPX_PREC_FP32;
+    std::vector<spx_factor*> f(K, nullptr);
+    rc = spx_potrf_batched(c, K, n.data(), A.data(), lda.data(), &o, f.data(), info.data());
+    for (int i = 0; !rc && i < K; ++i) {
+      w[i].res.info = info[i];
+      spx_refine ref{w[i].r.tol > 0 ? w[i].r.tol : 1e-12, 50, 1};
+      spx_solve_stats ss{};
+      bool ok = false;
+      if (f[i]) {
+        rc = spx_potrs(c, f[i], q[i], B[i], ldb[i], X[i], ldx[i], A[i], lda[i], &ref, &ss);
+        ok = !rc && ss.eta_max <= ref.tol;
+        w[i].res.iters = ss.iters;
+        w[i].res.eta_max = ss.eta_max;
+        w[i].res.method_used = 1;
+      }
+      if (!rc && (!f[i] || !ok)) {
+        // the low-precision factor broke down or refinement stalled: FP64 instead
+        spx_opts o64 = o;
+        o64.update_prec = SPX_PREC_FP64;
+        spx_factor* g = nullptr;
+        int64_t inf = 0;
+        rc = spx_potrf_tiled(c, n[i], A[i], lda[i], &o64, &g, &inf);
+        w[i].res.info = inf;
+        w[i].res.method_used = 0;
+        if (!rc && g) {
+          rc = spx_potrs(c, g, q[i], B[i], ldb[i], X[i], ldx[i], A[i], lda[i], &ref, &ss);
+          w[i].res.iters = ss.iters;
+          w[i].res.eta_max = ss.eta_max;
+        }
+        spx_factor_destroy(g);
+      }
+    }
+    for (auto* g : f) spx_factor_destroy(g);
+  }
+  // results back to the caller
+  for (auto& x : w) {
+    if (rc || x.r.where == 1 || x.res.info) continue;
+    const size_t nn = (size_t)x.r.n, qq = (size_t)x.r.nrhs;
+    rc = hip_status(hipMemcpy2DAsync(x.r.X, (size_t)x.r.ldx * 8, x.X, qq * 8, qq * 8, nn, hipMemcpyDeviceToHost, st));
+    if (rc) break;
+  }
+  const int rc_sync = hip_status(hipStreamSynchronize(st));
+  if (!rc) rc = rc_sync;
+  for (auto& x : w)
+    for (void* p : x.own)
+      if (p) pool_free(p, st, nullptr);
+  const double t_done = s->now();
+  for (auto& x : w) {
+    if (rc) x.res.status = rc;
+    x.res.t_done = t_done;
+  }
+}
+
+void lane_main(spx_server* s, int id) {
+  Lane& ln = s->lanes[id];
+  (void)hipSetDevice(s->device);
+  for (;;) {
+    std::vector<Work> w;
+    {
+      std::unique_lock<std::mutex> lk(s->mu);
+      s->cv.wait(lk, [&] { return s->stop || !s->admitted.empty(); });
+      if (s->admitted.empty()) return;  // stopping and nothing admitted
+      const int mode = s->reqs[s->admitted.front()].r.mode;
+      for (auto it = s->admitted.begin(); it != s->admitted.end() && (int)w.size() < s->opts.max_batch;) {
+        Req& q = s->reqs[*it];
+        if (q.r.mode != mode) {
+          ++it;
+          continue;
+        }
+        q.state = RUNNING;
+        Work x;
+        x.ticket = *it;
+        x.r = q.r;
+        x.tile = q.tile;
+        x.res = q.res;
+        w.push_back(x);
+        it = s->admitted.erase(it);
+      }
+      s->running += w.size();
+      s->st.max_running = std::max<uint64_t>(s->st.max_running, s->running);
+      s->st.launches++;
+    }
+    const double t0 = s->now();
+    run_batch(s, ln, id, w);
+    {
+      std::lock_guard<std::mutex> lk(s->mu);
+      s->st.busy_s += s->now() - t0;
+      s->running -= w.size();
+      for (auto& x : w) {
+        Req& q = s->reqs[x.ticket];
+        q.res = x.res;
+        q.state = DONE;
+        s->st.bytes_in_use -= q.bytes;
+        s->st.completed++;
+      }
+      admit(s);
+    }
+    s->cv.notify_all();
+  }
+}
+
+}  // namespace
+}  // namespace spx
+
+extern "C" {
+
+int spx_server_create(spx_ctx* ctx, size_t hbm_budget_bytes, const spx_server_opts* opts, spx_server** out) {
+  if (!ctx || !out || hbm_budget_bytes == 0) return fail(SPX_EINVAL, "spx_server_create: bad argument");
+  *out = nullptr;
+  std::unique_ptr<spx_server> s(new spx_server());
+  s->device = ctx_device(ctx);
+  s->budget = hbm_budget_bytes;
+  if (opts) s->opts = *opts;
+  if (s->opts.lanes <= 0) s->opts.lanes = 2;
+  if (s->opts.lanes > 8) return fail(SPX_EINVAL, "spx_server_create: at most 8 lanes");
+  if (s->opts.max_batch <= 0) s->opts.max_batch = 4096;
+  s->t0 = std::chrono::steady_clock::now();
+  if (hipSetDevice(s->device) != hipSuccess) return fail(SPX_EDEVICE, "spx_server_create: hipSetDevice failed");
+  hipMemPool_t pool;
+  if (hipDeviceGetDefaultMemPool(&pool, s->device) == hipSuccess) {
+    uint64_t keep = UINT64_MAX;  // keep freed blocks for reuse instead of returning them
+    (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+  }
+  s->lanes.resize(s->opts.lanes);
+  for (auto& ln : s->lanes) {
+    int rc = hipStreamCreateWithFlags(&ln.stream, hipStreamNonBlocking) == hipSuccess ? SPX_OK : SPX_EDEVICE;
+    if (!rc) rc = spx_ctx_create(s->device, ln.stream, pool_alloc, pool_free, nullptr, &ln.ctx);
+    if (!rc) rc = ctx_copy_tile_tables(ctx, ln.ctx);
+    if (rc) {
+      for (auto& l2 : s->lanes) {
+        if (l2.ctx) spx_ctx_destroy(l2.ctx);
+        if (l2.stream) (void)hipStreamDestroy(l2.stream);
+      }
+      return rc == SPX_EDEVICE ? fail(SPX_EDEVICE, "spx_server_create: lane set-up failed") : rc;
+    }
+  }
+  s->tuner = s->lanes[0].ctx;
+  spx_server* raw = s.release();
+  for (int i = 0; i < (int)raw->lanes.size(); ++i) raw->lanes[i].th = std::thread(lane_main, raw, i);
+  *out = raw;
+  return SPX_OK;
+}
+
+int spx_submit(spx_server* s, const spx_request* r, uint64_t* ticket) {
+  if (!s || !r || !ticket) return fail(SPX_EINVAL, "spx_submit: null argument");
+  if (r->n < 1 || r->n > 65536 || r->nrhs < 1 || r->nrhs > 4096 || !r->A || !r->B || !r->X || r->lda < r->n ||
+      r->ldb < r->nrhs || r->ldx < r->nrhs || (r->mode != SPX_MODE_FP64 && r->mode != SPX_MODE_MIXED) ||
+      (r->where != 0 && r->where != 1) || (const double*)r->X == r->B)
+    return fail(SPX_EINVAL, "spx_submit: bad request");
+  int32_t b = 0;
+  const int rc = spx_tile_for(s->tuner, r->mode == SPX_MODE_MIXED ? SPX_PREC_FP32 : SPX_PREC_FP64, r->n, &b);
+  if (rc) return rc;
+  const size_t bytes = request_bytes(*r, b);
+  if (bytes > s->budget) {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->st.rejected++;
+    return failf(SPX_ENOMEM, "spx_submit: request needs %zu bytes, budget is %zu", bytes, s->budget);
+  }
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->stop) return fail(SPX_EABORT, "spx_submit: server is shutting down");
+    const uint64_t t = s->next_ticket++;
+    Req& q = s->reqs[t];
+    q.r = *r;
+    q.bytes = bytes;
+    q.tile = b;
+    q.res.tag = r->tag;
+    q.res.t_submit = s->now();
+    s->waiting.push_back(t);
+    s->st.submitted++;
+    *ticket = t;
+    admit(s);
+  }
+  s->cv.notify_all();
+  return SPX_OK;
+}
+
+int spx_poll(spx_server* s, uint64_t ticket, spx_result* out) {
+  if (!s || !out) return fail(SPX_EINVAL, "spx_poll: null argument");
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto it = s->reqs.find(ticket);
+  if (it == s->reqs.end()) return fail(SPX_EINVAL, "spx_poll: unknown ticket");
+  if (it->second.state != DONE) return SPX_EAGAIN;
+  *out = it->second.res;
+  s->reqs.erase(it);
+  return SPX_OK;
+}
+
+double spx_server_now(const spx_server* s) { return s ? s->now() : -1.0; }
+
+int spx_server_get_stats(spx_server* s, spx_server_stats* out) {
+  if (!s || !out) return fail(SPX_EINVAL, "spx_server_get_stats: null argument");
+  std::lock_guard<std::mutex> lk(s->mu);
+  *out = s->st;
+  return SPX_OK;
+}
+
+void spx_server_destroy(spx_server* s) {
+  if (!s) return;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stop = true;
+    const double t = s->now();
+    for (uint64_t id : s->waiting) {
+      Req& q = s->reqs[id];
+      q.state = DONE;
+      q.res.status = SPX_EABORT;
+      q.res.t_done = t;
+    }
+    for (uint64_t id : s->admitted) {
+      Req& q = s->reqs[id];
+      q.state = DONE;
+      q.res.status = SPX_EABORT;
+      q.res.t_done = t;
+    }
+    s->waiting.clear();
+    s->admitted.clear();
+  }
+  s->cv.notify_all();
+  for (auto& ln : s->lanes)
+    if (ln.th.joinable()) ln.th.join();
+  for (auto& ln : s->lanes) {
+    spx_ctx_destroy(ln.ctx);
+    (void)hipStreamSynchronize(ln.stream);
+    (void)hipStreamDestroy(ln.stream);
+  }
+  delete s;
+}
+
+}  // extern "C"

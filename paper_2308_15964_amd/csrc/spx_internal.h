@@ -112,6 +112,10 @@ int launch_spd_fill(double* A, int64_t n, uint32_t seed, void* stream);
 int launch_backward_error(int64_t n, const double* dA, int64_t lda, int64_t nrhs, const double* dX, int64_t ldx,
                           const double* dB, int64_t ldb, double* dR, double* dstats, void* stream);
 
+// Context internals the serving loop needs.
+int ctx_device(const spx_ctx* c);
+int ctx_copy_tile_tables(const spx_ctx* from, spx_ctx* to);
+
 }  // namespace spx
 
 struct spx_graph {

@@ -57,6 +57,34 @@ class Stats(ctypes.Structure):
                 ("tile", ctypes.c_uint32)]
 
 
+MODE_FP64, MODE_MIXED = 0, 1
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("nrhs", ctypes.c_int64), ("A", ctypes.c_void_p), ("B", ctypes.c_void_p),
+                ("X", ctypes.c_void_p), ("lda", ctypes.c_int64), ("ldb", ctypes.c_int64), ("ldx", ctypes.c_int64),
+                ("mode", ctypes.c_int32), ("where", ctypes.c_int32), ("tol", ctypes.c_double), ("tag", ctypes.c_uint64)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("iters", ctypes.c_int32), ("method_used", ctypes.c_int32),
+                ("tile", ctypes.c_int32), ("info", ctypes.c_int64), ("eta_max", ctypes.c_double),
+                ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double), ("t_start", ctypes.c_double),
+                ("t_done", ctypes.c_double), ("tag", ctypes.c_uint64), ("batch_size", ctypes.c_int32),
+                ("lane", ctypes.c_int32)]
+
+
+class ServerOpts(ctypes.Structure):
+    _fields_ = [("lanes", ctypes.c_int32), ("max_batch", ctypes.c_int32), ("num_wg", ctypes.c_int32),
+                ("pad", ctypes.c_int32)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64), ("rejected", ctypes.c_uint64),
+                ("launches", ctypes.c_uint64), ("bytes_in_use", ctypes.c_uint64), ("bytes_peak", ctypes.c_uint64),
+                ("max_running", ctypes.c_uint64), ("busy_s", ctypes.c_double)]
+
+
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
 FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
 
@@ -66,7 +94,8 @@ EXPORTS = [
     "spx_graph_indegree", "spx_graph_to_dot", "spx_graph_destroy", "spx_cholesky_graph", "spx_potrf_tiled",
     "spx_factor_info", "spx_factor_get_l", "spx_factor_destroy", "spx_potrs", "spx_backward_error",
     "spx_run_task", "spx_posv_batched", "spx_potrf_batched", "spx_set_tile_table", "spx_tile_for",
-    "spx_autotune_batched", "spx_last_stats", "spx_trace",
+    "spx_autotune_batched", "spx_server_create", "spx_submit", "spx_poll", "spx_server_now",
+    "spx_server_get_stats", "spx_server_destroy", "spx_last_stats", "spx_trace",
 ]
 
 _lib = None
@@ -112,6 +141,12 @@ def lib():
         "spx_set_tile_table": (ctypes.c_int, [vp, i32, i32, P(i64), P(i32)]),
         "spx_tile_for": (ctypes.c_int, [vp, i32, i64, P(i32)]),
         "spx_autotune_batched": (ctypes.c_int, [vp, i32, i32, P(i64), i32, i32, i32, P(i32), P(ctypes.c_double)]),
+        "spx_server_create": (ctypes.c_int, [vp, ctypes.c_size_t, P(ServerOpts), P(vp)]),
+        "spx_submit": (ctypes.c_int, [vp, P(Request), P(u64)]),
+        "spx_poll": (ctypes.c_int, [vp, u64, P(Result)]),
+        "spx_server_now": (ctypes.c_double, [vp]),
+        "spx_server_get_stats": (ctypes.c_int, [vp, P(ServerStats)]),
+        "spx_server_destroy": (None, [vp]),
         "spx_last_stats": (ctypes.c_int, [vp, P(Stats)]),
         "spx_trace": (i64, [vp, P(u64), i64]),
     }
@@ -412,6 +447,80 @@ class Factor:
         if self._h and self.ctx._h:
             lib().spx_factor_destroy(self._h)
         self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Serving loop (spx_server_*): submit SPD solve requests, poll for results.
+
+    Tensors passed to submit() must stay alive and unmodified until the ticket is done;
+    the server keeps a reference to them until poll() returns the result."""
+
+    def __init__(self, ctx, hbm_budget_bytes, lanes=2, max_batch=0, num_wg=0):
+        self.ctx = ctx
+        h = ctypes.c_void_p()
+        o = ServerOpts(lanes, max_batch, num_wg, 0)
+        _check(lib().spx_server_create(ctx._h, int(hbm_budget_bytes), ctypes.byref(o), ctypes.byref(h)))
+        self._h = h
+        self._keep = {}
+
+    def submit(self, A, B, X, mode=MODE_FP64, tol=0.0, tag=0):
+        """A: n x n, B and X: n x nrhs float64, all on the device or all on the host
+        (host tensors are best pinned).  Returns the ticket."""
+        torch = self.ctx.torch
+        ts = (A, B, X)
+        if not all(isinstance(t, torch.Tensor) and t.dtype == torch.float64 and t.dim() == 2 and t.stride(1) == 1
+                   for t in ts):
+            raise TypeError("A, B, X must be 2-D float64 tensors with unit column stride")
+        where = 1 if A.is_cuda else 0
+        if any(t.is_cuda != A.is_cuda for t in ts):
+            raise ValueError("A, B and X must all be on the device or all on the host")
+        r = Request(A.shape[0], B.shape[1], A.data_ptr(), B.data_ptr(), X.data_ptr(), A.stride(0), B.stride(0),
+                    X.stride(0), mode, where, tol, tag)
+        t = ctypes.c_uint64()
+        _check(lib().spx_submit(self._h, ctypes.byref(r), ctypes.byref(t)))
+        self._keep[t.value] = ts
+        return t.value
+
+    def poll(self, ticket):
+        """None while running, else a dict with the result (the ticket is then released)."""
+        r = Result()
+        rc = lib().spx_poll(self._h, ticket, ctypes.byref(r))
+        if rc == SPX_EAGAIN:
+            return None
+        _check(rc)
+        self._keep.pop(ticket, None)
+        return {k: getattr(r, k) for k, _ in Result._fields_}
+
+    def wait(self, ticket, timeout=600.0):
+        import time
+        t0 = time.monotonic()
+        while True:
+            r = self.poll(ticket)
+            if r is not None:
+                return r
+            if time.monotonic() - t0 > timeout:
+                raise TimeoutError(f"ticket {ticket} not done after {timeout} s")
+            time.sleep(0.0002)
+
+    def now(self):
+        return lib().spx_server_now(self._h)
+
+    def stats(self):
+        s = ServerStats()
+        _check(lib().spx_server_get_stats(self._h, ctypes.byref(s)))
+        return {k: getattr(s, k) for k, _ in ServerStats._fields_}
+
+    def close(self):
+        if self._h:
+            lib().spx_server_destroy(self._h)
+            self._h = ctypes.c_void_p()
+            self._keep.clear()
 
     def __del__(self):
         try:

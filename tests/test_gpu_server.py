@@ -1,0 +1,172 @@
+"""Serving loop (spx_server_create / spx_submit / spx_poll): admission by an HBM budget,
+continuous batching over lanes, and results that do not depend on the mix.
+
+Pins:
+  * FP64 mode: each result matches the oracle (1e-12 relative, eta <= 1e-14) and is
+    bitwise equal whether the request ran alone or inside a batch with other requests
+    (a batched member runs the same tile kernels in the same dependency order);
+  * mixed mode (FP32 updates + FP64 refinement): eta <= 1e-12 by the oracle's compensated
+    backward error, alone == in the mix bit for bit;
+  * admission: peak bytes in use never exceed the budget; a request larger than the
+    budget is refused at submission.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2308_15964_amd import inputs
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2308_15964_amd import spx
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = spx.Context(0)
+    yield c
+    c.close()
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda:0")
+
+
+def mixture(count, seed, kappa=None):
+    rs = np.random.default_rng(seed)
+    out = []
+    for m in range(count):
+        n = int(rs.integers(16, 400))
+        q = int(rs.integers(1, 6))
+        if kappa is None:
+            A, B = inputs.gram_spd(n, seed=seed * 1000 + m, nrhs=q)
+        else:
+            A, B = inputs.reflector_spd(n, kappa, seed=seed * 1000 + m, nrhs=q)
+        out.append((A, B))
+    return out
+
+
+def run_all(srv, items, mode, tol=0.0, host=False):
+    """Submits every (A, B) at once; returns (X list, result list) in submission order."""
+    tickets, outs = [], []
+    for A, B in items:
+        if host:
+            Ad = torch.from_numpy(np.ascontiguousarray(A)).pin_memory()
+            Bd = torch.from_numpy(np.ascontiguousarray(B)).pin_memory()
+            X = torch.empty(B.shape, dtype=torch.float64).pin_memory()
+        else:
+            Ad, Bd = dev(A), dev(B)
+            X = torch.empty_like(Bd)
+        tickets.append(srv.submit(Ad, Bd, X, mode=mode, tol=tol))
+        outs.append(X)
+    res = [srv.wait(t) for t in tickets]
+    return [x.cpu().numpy() for x in outs], res
+
+
+def test_fp64_alone_equals_mix_and_oracle(ctx):
+    from paper_2308_15964_amd import spx
+
+    srv = spx.Server(ctx, 8 << 30, lanes=2)
+    target = inputs.gram_spd(300, seed=42, nrhs=3)
+    [x_alone], [r_alone] = run_all(srv, [target], spx.MODE_FP64)
+    assert r_alone["status"] == 0 and r_alone["info"] == 0 and r_alone["batch_size"] == 1
+    items = mixture(30, seed=5)
+    items.insert(17, target)
+    xs, rs = run_all(srv, items, spx.MODE_FP64)
+    assert all(r["status"] == 0 and r["info"] == 0 for r in rs)
+    assert np.array_equal(xs[17], x_alone)
+    assert max(r["batch_size"] for r in rs) > 1  # requests shared launches
+    for (A, B), X, r in zip(items, xs, rs):
+        _, Xo, _ = oracle.cholesky(A, A.shape[0], B)
+        assert np.abs(X - Xo).max() <= 1e-12 * np.abs(Xo).max()
+        assert r["eta_max"] <= 1e-14
+        assert r["t_submit"] <= r["t_admit"] <= r["t_start"] <= r["t_done"]
+    st = srv.stats()
+    assert st["completed"] == st["submitted"] == 32 and st["bytes_in_use"] == 0
+    srv.close()
+
+
+def test_mixed_refined_alone_equals_mix(ctx):
+    from paper_2308_15964_amd import spx
+
+    srv = spx.Server(ctx, 8 << 30, lanes=3)
+    target = inputs.reflector_spd(257, 1e5, seed=9, nrhs=2)
+    [x_alone], [r_alone] = run_all(srv, [target], spx.MODE_MIXED, tol=1e-12)
+    items = mixture(20, seed=6, kappa=1e4)
+    items.insert(3, target)
+    xs, rs = run_all(srv, items, spx.MODE_MIXED, tol=1e-12)
+    assert np.array_equal(xs[3], x_alone)
+    for (A, B), X, r in zip(items, xs, rs):
+        assert r["status"] == 0 and r["info"] == 0
+        eta = oracle.backward_error(A, X, B)
+        assert eta.max() <= 1e-12 and r["eta_max"] <= 1e-12, (eta.max(), r)
+        assert r["method_used"] == 1 and r["iters"] >= 1
+    srv.close()
+
+
+def test_host_memory_requests_match_device(ctx):
+    from paper_2308_15964_amd import spx
+
+    srv = spx.Server(ctx, 4 << 30, lanes=2)
+    items = mixture(6, seed=7)
+    xd, _ = run_all(srv, items, spx.MODE_FP64)
+    xh, rh = run_all(srv, items, spx.MODE_FP64, host=True)
+    assert all(r["status"] == 0 for r in rh)
+    for a, b in zip(xd, xh):
+        assert np.array_equal(a, b)
+    srv.close()
+
+
+def test_budget_admission(ctx):
+    from paper_2308_15964_amd import spx
+
+    items = [inputs.gram_spd(384, seed=70 + i, nrhs=2) for i in range(8)]
+    budget = 6 << 20  # about two requests of this size at once
+    srv = spx.Server(ctx, budget, lanes=2)
+    xs, rs = run_all(srv, items, spx.MODE_FP64)
+    assert all(r["status"] == 0 for r in rs)
+    st = srv.stats()
+    assert 0 < st["bytes_peak"] <= budget
+    assert any(r["t_admit"] > r["t_submit"] for r in rs)  # some waited for memory
+    big = dev(inputs.gram_spd(2048, seed=1)[0])
+    with pytest.raises(spx.SpxError) as e:
+        srv.submit(big, dev(np.ones((2048, 1))), torch.empty((2048, 1), dtype=torch.float64, device="cuda:0"))
+    assert e.value.code == spx.SPX_ENOMEM
+    for (A, B), X in zip(items, xs):
+        _, Xo, _ = oracle.cholesky(A, A.shape[0], B)
+        assert np.abs(X - Xo).max() <= 1e-12 * np.abs(Xo).max()
+    srv.close()
+
+
+def test_not_pd_request_and_errors(ctx):
+    from paper_2308_15964_amd import spx
+
+    srv = spx.Server(ctx, 2 << 30)
+    items = mixture(4, seed=8)
+    A_bad = items[1][0].copy()
+    A_bad[10, 10] = -5.0
+    items[1] = (A_bad, items[1][1])
+    xs, rs = run_all(srv, items, spx.MODE_FP64)
+    assert rs[1]["info"] == 11
+    assert [r["info"] for i, r in enumerate(rs) if i != 1] == [0, 0, 0]
+    with pytest.raises(spx.SpxError):
+        srv.poll(123456789)
+    srv.close()
+
+
+def test_destroy_with_requests_in_flight(ctx):
+    from paper_2308_15964_amd import spx
+
+    srv = spx.Server(ctx, 1 << 30, lanes=1)
+    items = mixture(12, seed=9)
+    keep = []
+    for A, B in items:
+        Ad, Bd = dev(A), dev(B)
+        X = torch.empty_like(Bd)
+        keep.append((Ad, Bd, X))
+        srv.submit(Ad, Bd, X)
+    srv.close()  # running batches finish, the rest end aborted; no hang, no fault
+    torch.cuda.synchronize()
