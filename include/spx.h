@@ -223,6 +223,22 @@ int spx_posv_batched(spx_ctx* ctx, int32_t count, const int64_t* n, const double
 int spx_potrf_batched(spx_ctx* ctx, int32_t count, const int64_t* n, const double* const* dA, const int64_t* lda,
                       const spx_opts* opts, spx_factor** out, int64_t* info);
 
+/* Batched solves with existing factors (one launch per sweep over all systems): X_m =
+ * A_m^{-1} B_m through f[m].  refine (nullable) as for spx_potrs: with method 1 every
+ * refinement step is one batched residual launch over the systems not yet converged and
+ * one batched solve launch adding the corrections.  dA/lda (nullable unless refining):
+ * the original matrices; when given, stats[m].eta_max receives the final backward error
+ * of system m (else -1).  stats: count entries or NULL.  X_m must not alias B_m. */
+int spx_potrs_batched(spx_ctx* ctx, int32_t count, spx_factor* const* f, const int64_t* nrhs,
+                      const double* const* dB, const int64_t* ldb, double* const* dX, const int64_t* ldx,
+                      const double* const* dA, const int64_t* lda, const spx_refine* refine,
+                      spx_solve_stats* stats);
+/* Largest normwise backward error of each system (one launch): eta_max host array. */
+int spx_backward_error_batched(spx_ctx* ctx, int32_t count, const int64_t* n, const double* const* dA,
+                               const int64_t* lda, const int64_t* nrhs, const double* const* dX,
+                               const int64_t* ldx, const double* const* dB, const int64_t* ldb,
+                               double* eta_max);
+
 /* Tile table of the context for update precision prec: a matrix of size n takes the tile
  * of the first entry with n <= n_max[i] (n_max increasing); above the last entry, and
  * with no table, a size rule applies (32 below 128, 64 below 512, 128 below 2048, 256
@@ -249,13 +265,16 @@ int spx_autotune_batched(spx_ctx* ctx, int32_t prec, int32_t nsizes, const int64
  * arrival order (a request that does not fit yet does not block smaller ones behind it)
  * against the byte budget (factor tiles, block inverses, low-precision copies, right-hand
  * side work arrays, and device copies of host inputs).  An idle lane takes every admitted
- * request of one mode (up to max_batch) and runs them as ONE batched launch; requests that
+ * request of one mode (and, for mixed, one tolerance; up to max_batch) and runs them as ONE
+ * batched launch (mixed: one factor launch, then one residual and one solve launch per
+ * refinement sweep over the systems not yet converged); requests that
  * arrive meanwhile are admitted as memory frees up and start on the next idle lane, so
  * their work overlaps on the device with the batches already running.
  *   mode SPX_MODE_FP64: FP64 factor + solve (spx_posv_batched), then the backward error.
  *   mode SPX_MODE_MIXED: FP32-update factor (spx_potrf_batched), then FP64 classical
- *   iterative refinement to tol (spx_potrs method 1); if that fails to converge the request
- *   is redone in FP64 (method_used = 0 reports the fallback).
+ *   iterative refinement to tol (spx_potrs_batched method 1); a request whose low-precision
+ *   factor breaks down or whose refinement does not reach tol is redone in FP64
+ *   (method_used = 0 reports the fallback).
  * The result of a request does not depend on what else is in the same batch or lane: a
  * batched member runs the same kernels in the same dependency order as when alone.
  *   A, B, X: n x n, n x nrhs, n x nrhs row-major with leading dimensions lda, ldb, ldx;

@@ -192,6 +192,27 @@ void io_program(int nt, bool with_solve, std::vector<TaskDesc>& tasks, std::vect
   }
 }
 
+void solve_io_program(int nt, std::vector<TaskDesc>& tasks, std::vector<spx_access>& acc) {
+  std::vector<TaskDesc> body;
+  std::vector<spx_access> body_acc;
+  solve_program(nt, body, body_acc);
+  auto B = [nt](int k) { return (uint64_t)nt * (uint64_t)nt + (uint64_t)k; };
+  tasks.clear();
+  acc.clear();
+  TaskDesc load;
+  load.type = SPX_T_LOAD;
+  load.j = 1;  // right-hand sides only: one part
+  tasks.push_back(load);
+  for (int k = 0; k < nt; ++k) acc.push_back(spx_access{0, SPX_ACC_RW, B(k)});
+  tasks.insert(tasks.end(), body.begin(), body.end());
+  for (const spx_access& a : body_acc) acc.push_back(spx_access{a.task + 1, a.mode, a.datum});
+  TaskDesc store;
+  store.type = SPX_T_STORE;
+  const uint32_t t = (uint32_t)tasks.size();
+  tasks.push_back(store);
+  for (int k = 0; k < nt; ++k) acc.push_back(spx_access{t, SPX_ACC_R, B(k)});
+}
+
 // Default Cholesky priorities (larger = sooner): the panel chain POTRF -> TRSM -> SYRK and
 // the GEMMs that feed the next block column sit on the critical path; among equals the
 // earlier step k goes first.

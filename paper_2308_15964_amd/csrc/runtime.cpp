@@ -157,6 +157,7 @@ static int get_program(spx_ctx* c, char kind, int nt, const Program** out) {
     case 'F': cholesky_program(nt, false, pr->tasks, acc); break;
     case 'S': solve_program(nt, pr->tasks, acc); break;
     case 'L': io_program(nt, false, pr->tasks, acc); break;
+    case 'Q': solve_io_program(nt, pr->tasks, acc); break;
     default: io_program(nt, true, pr->tasks, acc); break;
   }
   std::vector<int32_t> prio(pr->tasks.size());
@@ -446,6 +447,131 @@ static int tile_for_n(const spx_ctx* c, int prec, int64_t n) {
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// Cached image of a batched launch (a few, keyed by the whole shape list; oldest evicted).
+static int get_batch_image(spx_ctx* c, const std::string& key, const std::vector<Piece>& pieces, int policy,
+                           Image** out) {
+  for (auto& kv : c->batch_images)
+    if (kv.first == key) {
+      *out = kv.second;
+      return SPX_OK;
+    }
+  Image* im = nullptr;
+  SPX_TRY(make_image(c, pieces, policy, &im));
+  if (c->batch_images.size() >= 4) {
+    (void)hipStreamSynchronize(c->stream);
+    dev_free(c, c->batch_images.front().second->block);
+    delete c->batch_images.front().second;
+    c->batch_images.erase(c->batch_images.begin());
+  }
+  c->batch_images.emplace_back(key, im);
+  *out = im;
+  return SPX_OK;
+}
+
+// One launch solving L_m L_m^T Y = B_m for the matrices in idx (factor f[m]); STORE
+// writes Y to X_m, or adds it when accumulate is set.
+static int batched_solve(spx_ctx* c, const std::vector<int>& idx, const spx_factor* const* f, const int64_t* q,
+                         const double* const* B, const int64_t* ldb, double* const* X, const int64_t* ldx,
+                         bool accumulate) {
+  const int K = (int)idx.size();
+  if (K == 0) return SPX_OK;
+  std::vector<size_t> off(K);
+  size_t ws = 0;
+  std::string key = "Q";
+  std::vector<Piece> pieces(K);
+  for (int j = 0; j < K; ++j) {
+    const spx_factor* g = f[idx[j]];
+    off[j] = ws;
+    ws = align256(ws + (size_t)g->n_pad * (size_t)q[idx[j]] * sizeof(double));
+    const Program* pr = nullptr;
+    SPX_TRY(get_program(c, 'Q', g->nt, &pr));
+    pieces[j] = Piece{pr, (uint32_t)j, g->b, (int)q[idx[j]]};
+    key += "," + std::to_string(g->nt) + "/" + std::to_string(g->b) + "/" + std::to_string((q[idx[j]] + 7) / 8);
+  }
+  Image* im = nullptr;
+  SPX_TRY(get_batch_image(c, key, pieces, SPX_Q_PRIORITY, &im));
+  SPX_TRY(ensure_small_buffers(c, K, 1, 0, false));
+  char* block = (char*)dev_alloc(c, ws);
+  if (!block) return fail(SPX_ENOMEM, "batched solve: workspace allocation failed");
+  for (int j = 0; j < K; ++j) {
+    const int m = idx[j];
+    const spx_factor* g = f[m];
+    DevMat d{};
+    d.tiles = g->tiles;
+    d.dinv = g->dinv;
+    d.rhs = (double*)(block + off[j]);
+    d.info = c->dinfo + j;
+    d.n_pad = g->n_pad;
+    d.nt = g->nt;
+    d.b = g->b;
+    d.nrhs = (int32_t)q[m];
+    d.prec = PREC_FP64;
+    d.n = (int32_t)g->n;
+    d.trsm_rows = trsm_rows_of(g->b);
+    d.B = B[m];
+    d.ldb = ldb[m];
+    d.X = X[m];
+    d.ldx = ldx[m];
+    d.store_acc = accumulate ? 1 : 0;
+    c->hmats[j] = d;
+  }
+  int rc = run_image(c, im, K, nullptr, 0.0);
+  dev_free(c, block);
+  return rc;
+}
+
+// Normwise backward errors of the systems in idx (one launch): R_m = B_m - A_m X_m is
+// written to R[m] (n x q row-major) and eta[m] receives the largest column error.
+static int batched_eta(spx_ctx* c, const std::vector<int>& idx, const int64_t* n, const double* const* A,
+                       const int64_t* lda, const int64_t* q, const double* const* X, const int64_t* ldx,
+                       const double* const* B, const int64_t* ldb, double* const* R, double* eta) {
+  const int K = (int)idx.size();
+  if (K == 0) return SPX_OK;
+  std::vector<ResDesc> rd(K);
+  std::vector<uint32_t> prefix(K + 1, 0);
+  std::vector<size_t> soff(K);
+  size_t nstat = 0;
+  for (int j = 0; j < K; ++j) {
+    const int m = idx[j];
+    soff[j] = nstat;
+    nstat += 3 * (size_t)q[m] + 1;
+    prefix[j + 1] = prefix[j] + (uint32_t)((n[m] + 63) / 64);
+  }
+  const size_t rd_bytes = align256(sizeof(ResDesc) * K), pf_bytes = align256(4 * (size_t)(K + 1));
+  char* block = (char*)dev_alloc(c, rd_bytes + pf_bytes + nstat * sizeof(double));
+  if (!block) return fail(SPX_ENOMEM, "batched residual: allocation failed");
+  double* S = (double*)(block + rd_bytes + pf_bytes);
+  for (int j = 0; j < K; ++j) {
+    const int m = idx[j];
+    rd[j] = ResDesc{n[m], lda[m], q[m], ldx[m], ldb[m], A[m], X[m], B[m], R[m], S + soff[j]};
+  }
+  std::vector<double> hs(nstat);
+  int rc = hipc(hipMemcpyAsync(block, rd.data(), sizeof(ResDesc) * K, hipMemcpyHostToDevice, c->stream), "upload");
+  if (!rc)
+    rc = hipc(hipMemcpyAsync(block + rd_bytes, prefix.data(), 4 * (size_t)(K + 1), hipMemcpyHostToDevice, c->stream),
+              "upload");
+  if (!rc) rc = hipc(hipMemsetAsync(S, 0, nstat * sizeof(double), c->stream), "hipMemsetAsync");
+  if (!rc)
+    rc = launch_backward_error_batched((const ResDesc*)block, (const uint32_t*)(block + rd_bytes), K, prefix[K],
+                                       c->stream);
+  if (!rc) rc = hipc(hipMemcpyAsync(hs.data(), S, nstat * sizeof(double), hipMemcpyDeviceToHost, c->stream), "stats");
+  if (!rc) rc = hipc(hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+  dev_free(c, block);
+  if (rc) return rc;
+  for (int j = 0; j < K; ++j) {
+    const int m = idx[j];
+    const double* h = hs.data() + soff[j];
+    const double anorm = h[3 * q[m]];
+    double worst = 0.0;
+    for (int64_t k = 0; k < q[m]; ++k) {
+      const double e = h[3 * k] / (anorm * h[3 * k + 1] + h[3 * k + 2]);
+      if (!(e <= worst)) worst = e;
+    }
+    eta[m] = worst;
+  }
+  return SPX_OK;
+}
+
 int ctx_device(const spx_ctx* c) { return c->device; }
 
 int ctx_copy_tile_tables(const spx_ctx* from, spx_ctx* to) {
@@ -546,23 +672,8 @@ static int batched(spx_ctx* c, int count, const int64_t* n, const double* const*
     key += "," + std::to_string(nts[m]) + "/" + std::to_string(bs[m]) + "/" + std::to_string((qs[m] + 7) / 8);
   }
   Image* im = nullptr;
-  for (auto& kv : c->batch_images)
-    if (kv.first == key) im = kv.second;
-  if (!im) {
-    int rc = make_image(c, pieces, policy, &im);
-    if (rc) {
-      release();
-      return rc;
-    }
-    if (c->batch_images.size() >= 4) {
-      (void)hipStreamSynchronize(c->stream);
-      dev_free(c, c->batch_images.front().second->block);
-      delete c->batch_images.front().second;
-      c->batch_images.erase(c->batch_images.begin());
-    }
-    c->batch_images.emplace_back(key, im);
-  }
-  int rc = ensure_small_buffers(c, count, 1, 0, false);
+  int rc = get_batch_image(c, key, pieces, policy, &im);
+  if (!rc) rc = ensure_small_buffers(c, count, 1, 0, false);
   if (rc) {
     release();
     return rc;
@@ -644,6 +755,121 @@ int spx_potrf_batched(spx_ctx* c, int32_t count, const int64_t* n, const double*
     return batched(c, count, n, dA, lda, nullptr, nullptr, nullptr, nullptr, nullptr, opts, false, out, info);
   } catch (const std::bad_alloc&) {
     return fail(SPX_ENOMEM, "spx_potrf_batched: out of host memory");
+  }
+}
+
+int spx_potrs_batched(spx_ctx* c, int32_t count, spx_factor* const* f, const int64_t* nrhs, const double* const* dB,
+                      const int64_t* ldb, double* const* dX, const int64_t* ldx, const double* const* dA,
+                      const int64_t* lda, const spx_refine* refine, spx_solve_stats* stats) {
+  if (!c || !f || !nrhs || !dB || !ldb || !dX || !ldx || count < 1 || count > (1 << 20))
+    return fail(SPX_EINVAL, "spx_potrs_batched: bad argument");
+  const int method = refine ? refine->method : 0;
+  if (method < 0 || method > 1) return fail(SPX_EINVAL, "spx_potrs_batched: refinement method must be 0 or 1");
+  const bool want_eta = dA != nullptr;
+  if (method && !want_eta) return fail(SPX_EINVAL, "spx_potrs_batched: refinement needs the original matrices");
+  if (want_eta && !lda) return fail(SPX_EINVAL, "spx_potrs_batched: lda missing");
+  for (int m = 0; m < count; ++m) {
+    if (!f[m] || !dB[m] || !dX[m] || nrhs[m] < 1 || nrhs[m] > 4096 || ldb[m] < nrhs[m] || ldx[m] < nrhs[m] ||
+        (const double*)dX[m] == dB[m] || (want_eta && (!dA[m] || lda[m] < f[m]->n)))
+      return failf(SPX_EINVAL, "spx_potrs_batched: system %d: bad argument", m);
+  }
+  try {
+    SPX_TRY(hipc(hipSetDevice(c->device), "hipSetDevice"));
+    std::vector<int> all(count);
+    for (int m = 0; m < count; ++m) all[m] = m;
+    double ms = 0.0;
+    SPX_TRY(batched_solve(c, all, f, nrhs, dB, ldb, dX, ldx, false));
+    ms += c->last.kernel_ms;
+    std::vector<int> iters(count, 0);
+    std::vector<double> eta(count, -1.0);
+    if (want_eta) {
+      std::vector<int64_t> n(count), q1(count);
+      size_t rtot = 0;
+      std::vector<size_t> roff(count);
+      for (int m = 0; m < count; ++m) {
+        n[m] = f[m]->n;
+        roff[m] = rtot;
+        rtot = align256(rtot + (size_t)n[m] * (size_t)nrhs[m] * sizeof(double));
+      }
+      char* rblock = (char*)dev_alloc(c, rtot);
+      if (!rblock) return fail(SPX_ENOMEM, "spx_potrs_batched: residual allocation failed");
+      std::vector<double*> R(count);
+      std::vector<const double*> Rc(count);
+      for (int m = 0; m < count; ++m) {
+        R[m] = (double*)(rblock + roff[m]);
+        Rc[m] = R[m];
+        q1[m] = nrhs[m];
+      }
+      const double tol = (refine && refine->tol > 0) ? refine->tol : 1e-12;
+      const int max_iter = (refine && refine->max_iter > 0) ? refine->max_iter : 50;
+      std::vector<double> prev(count, INFINITY);
+      std::vector<int> slow(count, 0);
+      std::vector<int> active = all;
+      int rc = SPX_OK;
+      for (;;) {
+        rc = batched_eta(c, active, n.data(), dA, lda, nrhs, (const double* const*)dX, ldx, dB, ldb, R.data(),
+                         eta.data());
+        if (rc || !method) break;
+        std::vector<int> next;
+        for (int m : active) {
+          if (eta[m] <= tol || iters[m] >= max_iter) continue;
+          if (!(eta[m] < 0.5 * prev[m])) {  // stagnation (or NaN): stop after two slow steps
+            if (++slow[m] >= 2 || eta[m] != eta[m]) continue;
+          } else {
+            slow[m] = 0;
+          }
+          prev[m] = eta[m];
+          next.push_back(m);
+        }
+        if (next.empty()) break;
+        rc = batched_solve(c, next, f, nrhs, Rc.data(), q1.data(), dX, ldx, true);
+        if (rc) break;
+        ms += c->last.kernel_ms;
+        for (int m : next) ++iters[m];
+        active.swap(next);
+      }
+      dev_free(c, rblock);
+      if (rc) return rc;
+    }
+    c->last.kernel_ms = ms;
+    if (stats)
+      for (int m = 0; m < count; ++m) stats[m] = spx_solve_stats{iters[m], method, eta[m]};
+    return SPX_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(SPX_ENOMEM, "spx_potrs_batched: out of host memory");
+  }
+}
+
+int spx_backward_error_batched(spx_ctx* c, int32_t count, const int64_t* n, const double* const* dA,
+                               const int64_t* lda, const int64_t* nrhs, const double* const* dX, const int64_t* ldx,
+                               const double* const* dB, const int64_t* ldb, double* eta_max) {
+  if (!c || !n || !dA || !lda || !nrhs || !dX || !ldx || !dB || !ldb || !eta_max || count < 1 || count > (1 << 20))
+    return fail(SPX_EINVAL, "spx_backward_error_batched: bad argument");
+  for (int m = 0; m < count; ++m)
+    if (n[m] < 1 || lda[m] < n[m] || nrhs[m] < 1 || ldx[m] < nrhs[m] || ldb[m] < nrhs[m] || !dA[m] || !dX[m] ||
+        !dB[m])
+      return failf(SPX_EINVAL, "spx_backward_error_batched: system %d: bad argument", m);
+  try {
+    SPX_TRY(hipc(hipSetDevice(c->device), "hipSetDevice"));
+    size_t rtot = 0;
+    std::vector<size_t> roff(count);
+    for (int m = 0; m < count; ++m) {
+      roff[m] = rtot;
+      rtot = align256(rtot + (size_t)n[m] * (size_t)nrhs[m] * sizeof(double));
+    }
+    char* rblock = (char*)dev_alloc(c, rtot);
+    if (!rblock) return fail(SPX_ENOMEM, "spx_backward_error_batched: allocation failed");
+    std::vector<double*> R(count);
+    std::vector<int> all(count);
+    for (int m = 0; m < count; ++m) {
+      R[m] = (double*)(rblock + roff[m]);
+      all[m] = m;
+    }
+    int rc = batched_eta(c, all, n, dA, lda, nrhs, dX, ldx, dB, ldb, R.data(), eta_max);
+    dev_free(c, rblock);
+    return rc;
+  } catch (const std::bad_alloc&) {
+    return fail(SPX_ENOMEM, "spx_backward_error_batched: out of host memory");
   }
 }
 

@@ -179,54 +179,87 @@ void run_batch(spx_server* s, Lane& ln, int lane_id, std::vector<Work>& w) {
   spx_opts o{};
   o.num_wg = s->opts.num_wg;
   const bool mixed = w[0].r.mode == SPX_MODE_MIXED;
-  if (!rc && !mixed) {
-    o.update_prec = SPX_PREC_FP64;
-    rc = spx_posv_batched(c, K, n.data(), A.data(), lda.data(), q.data(), B.data(), ldb.data(), X.data(), ldx.data(),
-                          &o, info.data());
-    for (int i = 0; !rc && i < K; ++i) {
-      w[i].res.info = info[i];
-      w[i].res.method_used = 0;
-      if (info[i]) continue;
-      std::vector<double> eta(q[i]);
-      rc = spx_backward_error(c, n[i], A[i], lda[i], q[i], X[i], ldx[i], B[i], ldb[i], eta.data());
-      double e = 0;
-      for (double v : eta) e = std::max(e, v);
-      w[i].res.eta_max = e;
+  // FP64 factor + solve of the systems in `sel`, then their backward errors
+  auto fp64 = [&](const std::vector<int>& sel) -> int {
+    if (sel.empty()) return SPX_OK;
+    const int k = (int)sel.size();
+    std::vector<int64_t> n2(k), lda2(k), q2(k), ldb2(k), ldx2(k), info2(k);
+    std::vector<const double*> A2(k), B2(k);
+    std::vector<double*> X2(k);
+    for (int j = 0; j < k; ++j) {
+      const int i = sel[j];
+      n2[j] = n[i], lda2[j] = lda[i], q2[j] = q[i], ldb2[j] = ldb[i], ldx2[j] = ldx[i];
+      A2[j] = A[i], B2[j] = B[i], X2[j] = X[i];
     }
+    spx_opts o64 = o;
+    o64.update_prec = SPX_PREC_FP64;
+    int r = spx_posv_batched(c, k, n2.data(), A2.data(), lda2.data(), q2.data(), B2.data(), ldb2.data(), X2.data(),
+                             ldx2.data(), &o64, info2.data());
+    if (r) return r;
+    std::vector<int> ok;
+    for (int j = 0; j < k; ++j) {
+      w[sel[j]].res.info = info2[j];
+      w[sel[j]].res.method_used = 0;
+      if (!info2[j]) ok.push_back(j);
+    }
+    if (ok.empty()) return SPX_OK;
+    const int kk = (int)ok.size();
+    std::vector<int64_t> n3(kk), lda3(kk), q3(kk), ldb3(kk), ldx3(kk);
+    std::vector<const double*> A3(kk), B3(kk), X3(kk);
+    std::vector<double> eta(kk);
+    for (int t = 0; t < kk; ++t) {
+      const int j = ok[t];
+      n3[t] = n2[j], lda3[t] = lda2[j], q3[t] = q2[j], ldb3[t] = ldb2[j], ldx3[t] = ldx2[j];
+      A3[t] = A2[j], B3[t] = B2[j], X3[t] = X2[j];
+    }
+    r = spx_backward_error_batched(c, kk, n3.data(), A3.data(), lda3.data(), q3.data(), X3.data(), ldx3.data(),
+                                   B3.data(), ldb3.data(), eta.data());
+    for (int t = 0; !r && t < kk; ++t) w[sel[ok[t]]].res.eta_max = eta[t];
+    return r;
+  };
+  if (!rc && !mixed) {
+    std::vector<int> all(K);
+    for (int i = 0; i < K; ++i) all[i] = i;
+    rc = fp64(all);
   } else if (!rc) {
+    // FP32-update factor, then batched FP64 refinement; what does not converge is redone
+    // in FP64
     o.update_prec = SPX_PREC_FP32;
     std::vector<spx_factor*> f(K, nullptr);
     rc = spx_potrf_batched(c, K, n.data(), A.data(), lda.data(), &o, f.data(), info.data());
-    for (int i = 0; !rc && i < K; ++i) {
-      w[i].res.info = info[i];
-      spx_refine ref{w[i].r.tol > 0 ? w[i].r.tol : 1e-12, 50, 1};
-      spx_solve_stats ss{};
-      bool ok = false;
-      if (f[i]) {
-        rc = spx_potrs(c, f[i], q[i], B[i], ldb[i], X[i], ldx[i], A[i], lda[i], &ref, &ss);
-        ok = !rc && ss.eta_max <= ref.tol;
-        w[i].res.iters = ss.iters;
-        w[i].res.eta_max = ss.eta_max;
-        w[i].res.method_used = 1;
+    std::vector<int> good, redo;
+    for (int i = 0; !rc && i < K; ++i) (f[i] ? good : redo).push_back(i);
+    if (!rc && !good.empty()) {
+      const int k = (int)good.size();
+      std::vector<spx_factor*> f2(k);
+      std::vector<int64_t> lda2(k), q2(k), ldb2(k), ldx2(k);
+      std::vector<const double*> A2(k), B2(k);
+      std::vector<double*> X2(k);
+      std::vector<spx_solve_stats> ss(k);
+      for (int j = 0; j < k; ++j) {
+        const int i = good[j];
+        f2[j] = f[i], lda2[j] = lda[i], q2[j] = q[i], ldb2[j] = ldb[i], ldx2[j] = ldx[i];
+        A2[j] = A[i], B2[j] = B[i], X2[j] = X[i];
       }
-      if (!rc && (!f[i] || !ok)) {
-        // the low-precision factor broke down or refinement stalled: FP64 instead
-        spx_opts o64 = o;
-        o64.update_prec = SPX_PREC_FP64;
-        spx_factor* g = nullptr;
-        int64_t inf = 0;
-        rc = spx_potrf_tiled(c, n[i], A[i], lda[i], &o64, &g, &inf);
-        w[i].res.info = inf;
-        w[i].res.method_used = 0;
-        if (!rc && g) {
-          rc = spx_potrs(c, g, q[i], B[i], ldb[i], X[i], ldx[i], A[i], lda[i], &ref, &ss);
-          w[i].res.iters = ss.iters;
-          w[i].res.eta_max = ss.eta_max;
-        }
-        spx_factor_destroy(g);
+      const double tol = w[good[0]].r.tol > 0 ? w[good[0]].r.tol : 1e-12;
+      spx_refine ref{tol, 50, 1};
+      rc = spx_potrs_batched(c, k, f2.data(), q2.data(), B2.data(), ldb2.data(), X2.data(), ldx2.data(), A2.data(),
+                             lda2.data(), &ref, ss.data());
+      for (int j = 0; !rc && j < k; ++j) {
+        Work& x = w[good[j]];
+        const double tj = x.r.tol > 0 ? x.r.tol : 1e-12;
+        x.res.info = 0;
+        x.res.iters = ss[j].iters;
+        x.res.eta_max = ss[j].eta_max;
+        x.res.method_used = 1;
+        if (!(ss[j].eta_max <= tj)) redo.push_back(good[j]);
       }
     }
     for (auto* g : f) spx_factor_destroy(g);
+    if (!rc && !redo.empty()) {
+      std::sort(redo.begin(), redo.end());
+      rc = fp64(redo);
+    }
   }
   // results back to the caller
   for (auto& x : w) {
@@ -256,10 +289,12 @@ void lane_main(spx_server* s, int id) {
       std::unique_lock<std::mutex> lk(s->mu);
       s->cv.wait(lk, [&] { return s->stop || !s->admitted.empty(); });
       if (s->admitted.empty()) return;  // stopping and nothing admitted
-      const int mode = s->reqs[s->admitted.front()].r.mode;
+      const spx_request& head = s->reqs[s->admitted.front()].r;
+      const int mode = head.mode;
+      const double tol = head.tol;
       for (auto it = s->admitted.begin(); it != s->admitted.end() && (int)w.size() < s->opts.max_batch;) {
         Req& q = s->reqs[*it];
-        if (q.r.mode != mode) {
+        if (q.r.mode != mode || (mode == SPX_MODE_MIXED && q.r.tol != tol)) {
           ++it;
           continue;
         }

@@ -41,6 +41,8 @@ void solve_program(int nt, std::vector<TaskDesc>& tasks, std::vector<spx_access>
 int32_t cholesky_priority(const TaskDesc& d, int nt);
 // LOAD, the factor program (and with_solve: the substitution), STORE (with_solve only).
 void io_program(int nt, bool with_solve, std::vector<TaskDesc>& tasks, std::vector<spx_access>& acc);
+// LOAD of the right-hand sides only (TaskDesc.j = 1), the substitution, STORE.
+void solve_io_program(int nt, std::vector<TaskDesc>& tasks, std::vector<spx_access>& acc);
 
 // ---------------------------------------------------------------------------------------
 // Device-side descriptors (plain data, copied to the GPU).
@@ -58,7 +60,9 @@ struct DevMat {
   int32_t* info;    // 0x7fffffff while healthy; else the 1-based failing column
   int64_t n_pad;
   int32_t nt, b, nrhs, prec;
-  int32_t n, trsm_rows, pad0, pad1;
+  int32_t n, trsm_rows;
+  int32_t store_acc;  // STORE adds the solution to X instead of overwriting it
+  int32_t pad1;
   // caller's dense arrays, used by the LOAD / STORE tasks of batched and served graphs
   const double* A;  // n x n row-major, lower triangle read
   const double* B;  // n x nrhs row-major
@@ -109,6 +113,17 @@ int launch_tile_inverses(const double* l, int b, double* dinv, void* stream);
 uint16_t parts_of(const TaskDesc& d, int b, int nrhs);
 int sched_max_wg(int device, int* per_cu, int* num_cu);
 int launch_spd_fill(double* A, int64_t n, uint32_t seed, void* stream);
+// Residuals of many systems in one launch: row block blk of matrix m for prefix[m] <=
+// blk < prefix[m+1] (prefix: count + 1 entries, device).
+struct ResDesc {
+  int64_t n, lda, nrhs, ldx, ldb;
+  const double* A;
+  const double* X;
+  const double* B;
+  double* R;      // n x nrhs row-major
+  double* stats;  // 3 nrhs + 1, cleared by the caller
+};
+int launch_backward_error_batched(const ResDesc* d, const uint32_t* prefix, int count, uint32_t nblocks, void* stream);
 int launch_backward_error(int64_t n, const double* dA, int64_t lda, int64_t nrhs, const double* dX, int64_t ldx,
                           const double* dB, int64_t ldb, double* dR, double* dstats, void* stream);
 

@@ -888,7 +888,7 @@ __device__ void run_part(const SchedArgs& a, uint32_t task, uint32_t part, doubl
       break;
     }
     case SPX_T_LOAD: {
-      if ((int)part < m.nt) {
+      if (d.j == 0 && (int)part < m.nt) {
         // tile row `part`: every tile (part, tj), tj <= part, in S x S sub-blocks
         const int S = b < 64 ? b : 64, per = b / S;
         for (int tj = 0; tj <= (int)part; ++tj)
@@ -906,7 +906,10 @@ __device__ void run_part(const SchedArgs& a, uint32_t task, uint32_t part, doubl
       const int64_t total = (int64_t)m.n * m.nrhs;
       for (int64_t e = threadIdx.x; e < total; e += NT) {
         const int64_t r = e / m.nrhs, q = e % m.nrhs;
-        m.X[r * m.ldx + q] = m.rhs[q * m.n_pad + r];
+        if (m.store_acc)
+          m.X[r * m.ldx + q] += m.rhs[q * m.n_pad + r];
+        else
+          m.X[r * m.ldx + q] = m.rhs[q * m.n_pad + r];
       }
       break;
     }
@@ -1149,13 +1152,11 @@ __device__ __forceinline__ void atomic_max_nonneg(double* p, double v) {
   atomicMax(reinterpret_cast<unsigned long long*>(p), (unsigned long long)__double_as_longlong(v));
 }
 
-__global__ __launch_bounds__(NT) void residual_kernel(int64_t n, const double* __restrict__ A, int64_t lda,
-                                                      int64_t nrhs, const double* __restrict__ X, int64_t ldx,
-                                                      const double* __restrict__ Bv, int64_t ldb,
-                                                      double* __restrict__ R, double* __restrict__ stats) {
-  __shared__ double part[4][64][9];
+__device__ void residual_rows(int64_t n, const double* __restrict__ A, int64_t lda, int64_t nrhs,
+                              const double* __restrict__ X, int64_t ldx, const double* __restrict__ Bv, int64_t ldb,
+                              double* __restrict__ R, double* __restrict__ stats, int64_t i0,
+                              double (*part)[64][9]) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int64_t i0 = (int64_t)blockIdx.x * 64;
   for (int64_t q0 = 0; q0 < nrhs; q0 += 8) {
     const int nq = (nrhs - q0) < 8 ? (int)(nrhs - q0) : 8;
     double acc[9];  // 8 right-hand sides + the absolute row sum
@@ -1216,6 +1217,28 @@ __global__ __launch_bounds__(NT) void residual_kernel(int64_t n, const double* _
     }
     __syncthreads();
   }
+}
+
+__global__ __launch_bounds__(NT) void residual_kernel(int64_t n, const double* __restrict__ A, int64_t lda,
+                                                      int64_t nrhs, const double* __restrict__ X, int64_t ldx,
+                                                      const double* __restrict__ Bv, int64_t ldb,
+                                                      double* __restrict__ R, double* __restrict__ stats) {
+  __shared__ double part[4][64][9];
+  residual_rows(n, A, lda, nrhs, X, ldx, Bv, ldb, R, stats, (int64_t)blockIdx.x * 64, part);
+}
+
+__global__ __launch_bounds__(NT) void residual_batched_kernel(const ResDesc* __restrict__ d,
+                                                              const uint32_t* __restrict__ prefix, int count) {
+  __shared__ double part[4][64][9];
+  const uint32_t blk = blockIdx.x;
+  int lo = 0, hi = count - 1;  // last m with prefix[m] <= blk
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (prefix[mid] <= blk) lo = mid; else hi = mid - 1;
+  }
+  const ResDesc r = d[lo];
+  residual_rows(r.n, r.A, r.lda, r.nrhs, r.X, r.ldx, r.B, r.ldb, r.R, r.stats, (int64_t)(blk - prefix[lo]) * 64,
+                part);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -1301,6 +1324,13 @@ int launch_backward_error(int64_t n, const double* dA, int64_t lda, int64_t nrhs
   hipLaunchKernelGGL(residual_kernel, dim3(grid), dim3(NT), 0, (hipStream_t)stream, n, dA, lda, nrhs, dX, ldx, dB,
                      ldb, dR, dstats);
   return hip_ok(hipGetLastError(), "residual_kernel");
+}
+
+int launch_backward_error_batched(const ResDesc* d, const uint32_t* prefix, int count, uint32_t nblocks,
+                                  void* stream) {
+  if (nblocks == 0) return SPX_OK;
+  hipLaunchKernelGGL(residual_batched_kernel, dim3(nblocks), dim3(NT), 0, (hipStream_t)stream, d, prefix, count);
+  return hip_ok(hipGetLastError(), "residual_batched_kernel");
 }
 
 }  // namespace spx

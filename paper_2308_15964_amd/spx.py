@@ -93,7 +93,8 @@ EXPORTS = [
     "spx_last_error", "spx_ctx_create", "spx_ctx_destroy", "spx_graph_build", "spx_graph_info", "spx_graph_edges",
     "spx_graph_indegree", "spx_graph_to_dot", "spx_graph_destroy", "spx_cholesky_graph", "spx_potrf_tiled",
     "spx_factor_info", "spx_factor_get_l", "spx_factor_destroy", "spx_potrs", "spx_backward_error",
-    "spx_run_task", "spx_posv_batched", "spx_potrf_batched", "spx_set_tile_table", "spx_tile_for",
+    "spx_run_task", "spx_posv_batched", "spx_potrf_batched", "spx_potrs_batched", "spx_backward_error_batched",
+    "spx_set_tile_table", "spx_tile_for",
     "spx_autotune_batched", "spx_server_create", "spx_submit", "spx_poll", "spx_server_now",
     "spx_server_get_stats", "spx_server_destroy", "spx_last_stats", "spx_trace",
 ]
@@ -138,6 +139,10 @@ def lib():
         "spx_posv_batched": (ctypes.c_int, [vp, i32, P(i64), P(vp), P(i64), P(i64), P(vp), P(i64), P(vp), P(i64),
                                              P(Opts), P(i64)]),
         "spx_potrf_batched": (ctypes.c_int, [vp, i32, P(i64), P(vp), P(i64), P(Opts), P(vp), P(i64)]),
+        "spx_potrs_batched": (ctypes.c_int, [vp, i32, P(vp), P(i64), P(vp), P(i64), P(vp), P(i64), P(vp), P(i64),
+                                              P(Refine), P(SolveStats)]),
+        "spx_backward_error_batched": (ctypes.c_int, [vp, i32, P(i64), P(vp), P(i64), P(i64), P(vp), P(i64), P(vp),
+                                                       P(i64), P(ctypes.c_double)]),
         "spx_set_tile_table": (ctypes.c_int, [vp, i32, i32, P(i64), P(i32)]),
         "spx_tile_for": (ctypes.c_int, [vp, i32, i64, P(i32)]),
         "spx_autotune_batched": (ctypes.c_int, [vp, i32, i32, P(i64), i32, i32, i32, P(i32), P(ctypes.c_double)]),
@@ -391,6 +396,39 @@ class Context:
         _check(lib().spx_potrf_batched(self._h, k, n, pa, lda, ctypes.byref(o), hs, info))
         fs = [Factor(self, h) if h else None for h in hs]
         return fs, np.array(info[:], dtype=np.int64)
+
+    def potrs_batched(self, Fs, Bs, As=None, tol=0.0, max_iter=0, method=0, Xs=None):
+        """Solves with existing factors in batched launches (optionally refined against the
+        original matrices As).  Returns (Xs, stats list)."""
+        torch = self.torch
+        k = len(Fs)
+        if k == 0 or len(Bs) != k or (As is not None and len(As) != k):
+            raise ValueError("need one right-hand side (and matrix) per factor")
+        Bs = [self._dev(b, "B") for b in Bs]
+        if Xs is None:
+            Xs = [torch.empty_like(b) for b in Bs]
+        i64a, vpa = ctypes.c_int64 * k, ctypes.c_void_p * k
+        fh = vpa(*[f._h.value for f in Fs])
+        q = i64a(*[b.shape[1] for b in Bs])
+        pb, ldb = vpa(*[b.data_ptr() for b in Bs]), i64a(*[b.stride(0) for b in Bs])
+        px, ldx = vpa(*[x.data_ptr() for x in Xs]), i64a(*[x.stride(0) for x in Xs])
+        pa = lda = None
+        if As is not None:
+            pa, lda = vpa(*[self._dev(a, "A").data_ptr() for a in As]), i64a(*[a.stride(0) for a in As])
+        ref = Refine(tol, max_iter, method)
+        st = (SolveStats * k)()
+        _check(lib().spx_potrs_batched(self._h, k, fh, q, pb, ldb, px, ldx, pa, lda, ctypes.byref(ref), st))
+        return Xs, [{"iters": s.iters, "method_used": s.method_used, "eta_max": s.eta_max} for s in st]
+
+    def backward_error_batched(self, As, Xs, Bs):
+        k = len(As)
+        i64a, vpa = ctypes.c_int64 * k, ctypes.c_void_p * k
+        eta = (ctypes.c_double * k)()
+        _check(lib().spx_backward_error_batched(
+            self._h, k, i64a(*[a.shape[0] for a in As]), vpa(*[a.data_ptr() for a in As]),
+            i64a(*[a.stride(0) for a in As]), i64a(*[b.shape[1] for b in Bs]), vpa(*[x.data_ptr() for x in Xs]),
+            i64a(*[x.stride(0) for x in Xs]), vpa(*[b.data_ptr() for b in Bs]), i64a(*[b.stride(0) for b in Bs]), eta))
+        return np.array(eta[:])
 
     def set_tile_table(self, prec, table):
         """table: list of (n_max, tile), n_max increasing ([] clears)."""

@@ -157,3 +157,28 @@ def test_batched_argument_errors(ctx):
         ctx.posv_batched([Ad], [Bd], tile=48)
     with pytest.raises(ValueError):
         ctx.posv_batched([], [])
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_potrs_batched_matches_single_and_refines(ctx, prec):
+    items = [inputs.reflector_spd(n, 1e4, seed=400 + n, nrhs=q) for n, q in ((40, 1), (130, 3), (257, 2), (390, 9))]
+    As = [dev(A) for A, _ in items]
+    Bs = [dev(B) for _, B in items]
+    fs, info = ctx.potrf_batched(As, tile=64, update_prec=prec)
+    assert (info == 0).all()
+    # plain batched solve == single solves, bit for bit
+    Xs, st = ctx.potrs_batched(fs, Bs)
+    for F, Bd, X, s in zip(fs, Bs, Xs, st):
+        assert np.array_equal(X.cpu().numpy(), ctx.potrs(F, Bd).cpu().numpy())
+        assert s["eta_max"] == -1.0
+    # refined batched solve == single refined solves (same steps, same launches per system)
+    Xr, st = ctx.potrs_batched(fs, Bs, As=As, tol=1e-12, method=1)
+    for (A, B), F, Ad, Bd, X, s in zip(items, fs, As, Bs, Xr, st):
+        X1, s1 = ctx.potrs(F, Bd, A=Ad, tol=1e-12, method=1, return_stats=True)
+        assert np.array_equal(X.cpu().numpy(), X1.cpu().numpy())
+        assert s["iters"] == s1["iters"] and s["eta_max"] == s1["eta_max"]
+        assert oracle.backward_error(A, X.cpu().numpy(), B).max() <= 1e-12
+    eta = ctx.backward_error_batched(As, Xr, Bs)
+    assert np.array_equal(eta, np.array([s["eta_max"] for s in st]))
+    for F in fs:
+        F.close()
