@@ -56,6 +56,9 @@ struct Image {
   uint32_t ntasks = 0, total_parts = 0;
   int nlev = 1;
   uint32_t qbase[kMaxLevels] = {0, 0, 0, 0};
+  uint32_t qcap[kMaxLevels] = {0, 0, 0, 0};
+  uint32_t nroots = 0;
+  int nshards = 1;
   void* block = nullptr;  // one allocation for every array below
   size_t bytes = 0;
   TaskDesc* tasks = nullptr;
@@ -63,7 +66,7 @@ struct Image {
   uint32_t* succ = nullptr;
   uint32_t* indeg = nullptr;
   uint32_t* nparts = nullptr;
-  u64* queue0 = nullptr;
+  u64* roots = nullptr;  // (queue slot, item) pairs of the root tasks' parts
   uint32_t* counters0 = nullptr;
   uint32_t* pending = nullptr;
   uint32_t* parts_left = nullptr;
@@ -71,7 +74,6 @@ struct Image {
   uint32_t* counters = nullptr;
 };
 
-constexpr uint32_t kNumCounters = (2 * kMaxLevels + 2) * kCounterStride;
 
 // Task program of one matrix with its dependency graph (built once per shape).
 struct Program {
@@ -221,6 +223,10 @@ struct Piece {
 // Uploads the concatenation of the pieces' graphs (no edges between pieces) as one
 // device image.
 static int make_image(spx_ctx* c, const std::vector<Piece>& pieces, int policy, Image** out) {
+  // one ready queue per level keeps one matrix's tasks in global push order (its critical
+  // path runs through the oldest bulk updates); independent matrices need no such order,
+  // and sharded queues spread the pops of their many small tasks
+  const int nshards = pieces.size() > 1 ? kShards : 1;
   uint64_t T64 = 0, E64 = 0;
   for (const Piece& pc : pieces) {
     T64 += pc.p->g.ntasks;
@@ -257,18 +263,28 @@ static int make_image(spx_ctx* c, const std::vector<Piece>& pieces, int policy, 
   off32[T] = (uint32_t)E;
   uint64_t total = 0;
   for (int l = 0; l < kMaxLevels; ++l) total += per_level[l];
-  if (total >= (1ull << 32) - 1) return fail(SPX_EINVAL, "task graph too large");
+  if (total * kShards >= (1ull << 32) - 1) return fail(SPX_EINVAL, "task graph too large");
   im->total_parts = (uint32_t)total;
-  for (int l = 1; l < kMaxLevels; ++l) im->qbase[l] = im->qbase[l - 1] + (uint32_t)per_level[l - 1];
-  std::vector<u64> queue0(im->total_parts, ~0ull);
+  for (int l = 0; l < kMaxLevels; ++l) im->qcap[l] = (uint32_t)per_level[l];
+  for (int l = 1; l < kMaxLevels; ++l) im->qbase[l] = im->qbase[l - 1] + im->qcap[l - 1];
+  // root parts are dealt round-robin over the shards of their level
+  std::vector<u64> roots;
   std::vector<uint32_t> counters0(kNumCounters, 0);
+  uint32_t deal = 0;
   for (uint32_t t = 0; t < T; ++t) {
     if (indeg[t] != 0) continue;
     const int l = tasks[t].level;
-    uint32_t& tail = counters0[(kMaxLevels + l) * kCounterStride];
-    for (uint32_t p = 0; p < nparts[t]; ++p) queue0[im->qbase[l] + tail + p] = ((u64)t << 16) | p;
-    tail += nparts[t];
+    for (uint32_t p = 0; p < nparts[t]; ++p) {
+      const int sh = (int)(deal++ % nshards);
+      uint32_t& tail = counters0[ctr_tail_idx(l, sh)];
+      roots.push_back((u64)im->qbase[l] * kShards + (u64)sh * im->qcap[l] + tail);
+      roots.push_back(((u64)t << 16) | p);
+      ++tail;
+    }
   }
+  im->nroots = (uint32_t)(roots.size() / 2);
+  im->nshards = nshards;
+  if (roots.empty()) roots.assign(2, 0);
   // layout
   auto align = [](size_t x) { return (x + 255) & ~(size_t)255; };
   size_t o = 0;
@@ -277,12 +293,12 @@ static int make_image(spx_ctx* c, const std::vector<Piece>& pieces, int policy, 
   const size_t o_succ = o; o = align(o + 4 * succ.size());
   const size_t o_indeg = o; o = align(o + 4 * (size_t)T);
   const size_t o_np = o; o = align(o + 4 * (size_t)T);
-  const size_t o_q0 = o; o = align(o + 8 * (size_t)im->total_parts);
+  const size_t o_q0 = o; o = align(o + 8 * roots.size());
   const size_t o_c0 = o; o = align(o + 4 * (size_t)kNumCounters);
   const size_t static_bytes = o;
   const size_t o_pend = o; o = align(o + 4 * (size_t)T);
   const size_t o_pl = o; o = align(o + 4 * (size_t)T);
-  const size_t o_q = o; o = align(o + 8 * (size_t)im->total_parts);
+  const size_t o_q = o; o = align(o + 8 * (size_t)im->total_parts * kShards);
   const size_t o_c = o; o = align(o + 4 * (size_t)kNumCounters);
   im->bytes = o;
   im->block = dev_alloc(c, o);
@@ -293,7 +309,7 @@ static int make_image(spx_ctx* c, const std::vector<Piece>& pieces, int policy, 
   im->succ = (uint32_t*)(base + o_succ);
   im->indeg = (uint32_t*)(base + o_indeg);
   im->nparts = (uint32_t*)(base + o_np);
-  im->queue0 = (u64*)(base + o_q0);
+  im->roots = (u64*)(base + o_q0);
   im->counters0 = (uint32_t*)(base + o_c0);
   im->pending = (uint32_t*)(base + o_pend);
   im->parts_left = (uint32_t*)(base + o_pl);
@@ -305,7 +321,7 @@ static int make_image(spx_ctx* c, const std::vector<Piece>& pieces, int policy, 
   std::memcpy(host.data() + o_succ, succ.data(), 4 * succ.size());
   std::memcpy(host.data() + o_indeg, indeg.data(), 4 * (size_t)T);
   std::memcpy(host.data() + o_np, nparts.data(), 4 * (size_t)T);
-  std::memcpy(host.data() + o_q0, queue0.data(), 8 * (size_t)im->total_parts);
+  std::memcpy(host.data() + o_q0, roots.data(), 8 * roots.size());
   std::memcpy(host.data() + o_c0, counters0.data(), 4 * (size_t)kNumCounters);
   // synchronous copy: the host vector is freed on return
   int rc = hipc(hipMemcpy(im->block, host.data(), static_bytes, hipMemcpyHostToDevice), "image upload");
@@ -384,8 +400,8 @@ static int run_image(spx_ctx* c, Image* im, int nmats, const spx_opts* o, double
   SPX_TRY(hipc(hipMemcpyAsync(c->dmats, c->hmats, sizeof(DevMat) * nmats, hipMemcpyHostToDevice, c->stream),
                "descriptor upload"));
   SPX_TRY(launch_sched_init_full(im->pending, im->indeg, im->parts_left, im->nparts, im->ntasks, im->queue,
-                                 im->queue0, im->total_parts, im->counters, im->counters0, kNumCounters, c->dinfo,
-                                 nmats, trace ? c->trace_idx : nullptr, c->stream));
+                                 im->total_parts * kShards, im->roots, im->nroots, im->counters, im->counters0,
+                                 kNumCounters, c->dinfo, nmats, trace ? c->trace_idx : nullptr, c->stream));
   SchedArgs a{};
   a.tasks = im->tasks;
   a.succ_off = im->succ_off;
@@ -394,10 +410,14 @@ static int run_image(spx_ctx* c, Image* im, int nmats, const spx_opts* o, double
   a.parts_left = im->parts_left;
   a.queue = im->queue;
   a.counters = im->counters;
-  for (int l = 0; l < kMaxLevels; ++l) a.qbase[l] = im->qbase[l];
+  for (int l = 0; l < kMaxLevels; ++l) {
+    a.qbase[l] = im->qbase[l];
+    a.qcap[l] = im->qcap[l];
+  }
   a.total_parts = im->total_parts;
   a.ntasks = im->ntasks;
   a.nlev = im->nlev;
+  a.nshards = im->nshards;
   a.mats = c->dmats;
   a.trace = trace ? c->trace : nullptr;
   a.trace_idx = trace ? c->trace_idx : nullptr;
@@ -428,12 +448,16 @@ static int run_image(spx_ctx* c, Image* im, int nmats, const spx_opts* o, double
   c->last.nparts = im->total_parts;
   c->last.num_wg = (uint32_t)num_wg;
   c->trace_len = trace ? im->total_parts : 0;
-  const uint32_t status = c->hcounters[(2 * kMaxLevels + 1) * kCounterStride];
-  const uint32_t done = c->hcounters[2 * kMaxLevels * kCounterStride];
+  const uint32_t status = c->hcounters[kStatusIdx];
+  uint64_t done = 0;  // parts taken from the queues; a normal exit means all of them ran
+  for (int l = 0; l < kMaxLevels; ++l)
+    for (int sh = 0; sh < kShards; ++sh) done += c->hcounters[ctr_head_idx(l, sh)];
   if (status & STATUS_TIMEOUT)
-    return failf(SPX_ETIMEOUT, "device scheduler made no progress (%u of %u parts done)", done, im->total_parts);
+    return failf(SPX_ETIMEOUT, "device scheduler made no progress (%llu of %u parts started)",
+                 (unsigned long long)done, im->total_parts);
   if (done != im->total_parts)
-    return failf(SPX_EDEVICE, "device scheduler ended early (%u of %u parts done)", done, im->total_parts);
+    return failf(SPX_EDEVICE, "device scheduler ended early (%llu of %u parts started)", (unsigned long long)done,
+                 im->total_parts);
   return SPX_OK;
 }
 

@@ -71,7 +71,15 @@ struct DevMat {
 };
 
 constexpr int kMaxLevels = 4;
+constexpr int kShards = 8;          // ready queues per priority level (one per XCD-sized group of workgroups)
 constexpr int kCounterStride = 32;  // 128-byte spacing of hot counters (uint32 units)
+// Counter layout: head and tail of every (level, shard) queue, then the status word.
+constexpr uint32_t ctr_head_idx(int l, int s) { return (uint32_t)(l * kShards + s) * kCounterStride; }
+constexpr uint32_t ctr_tail_idx(int l, int s) {
+  return (uint32_t)((kMaxLevels + l) * kShards + s) * kCounterStride;
+}
+constexpr uint32_t kStatusIdx = 2u * kMaxLevels * kShards * kCounterStride;
+constexpr uint32_t kNumCounters = kStatusIdx + kCounterStride;
 
 // Everything the persistent scheduler kernel needs for one launch.
 struct SchedArgs {
@@ -80,14 +88,15 @@ struct SchedArgs {
   const uint32_t* succ;
   uint32_t* pending;         // remaining predecessors per task
   uint32_t* parts_left;      // parts not yet finished per task
-  unsigned long long* queue; // per-level segments, item = task << 16 | part
-  uint32_t* counters;        // [level*stride] head, [(kMaxLevels+level)*stride] tail,
-                             // [2*kMaxLevels*stride] done parts, [+stride] status
+  unsigned long long* queue; // item = task << 16 | part; queue (l, s) holds qcap[l] slots
+                             // at qbase[l] * kShards + s * qcap[l]
+  uint32_t* counters;        // ctr_head_idx / ctr_tail_idx / kStatusIdx
   uint32_t qbase[kMaxLevels];
+  uint32_t qcap[kMaxLevels];
   uint32_t total_parts;
   uint32_t ntasks;
   int32_t nlev;
-  int32_t pad;
+  int32_t nshards;  // queues in use per level (1..kShards); the image's roots use the same count
   const DevMat* mats;
   unsigned long long* trace;  // 4 x uint64 per part, or null
   uint32_t* trace_idx;
@@ -103,10 +112,12 @@ int launch_unpack(const DevMat& m, int64_t n, double* dL, int64_t ldl, void* str
 int launch_rhs_in(const double* dB, int64_t ldb, int64_t n, int64_t nrhs, double* rhs, int64_t n_pad, void* stream);
 int launch_rhs_out(const double* rhs, int64_t n_pad, int64_t n, int64_t nrhs, double* dX, int64_t ldx, int accumulate,
                    void* stream);
+// roots: nroots pairs (queue slot, item) written after the queue is cleared.
 int launch_sched_init_full(uint32_t* pending, const uint32_t* indeg, uint32_t* parts_left, const uint32_t* nparts,
-                           uint32_t ntasks, unsigned long long* queue, const unsigned long long* queue0,
-                           uint32_t queue_len, uint32_t* counters, const uint32_t* counters0, uint32_t ncounters,
-                           int32_t* info, int ninfo, uint32_t* trace_idx, void* stream);
+                           uint32_t ntasks, unsigned long long* queue, uint32_t queue_len,
+                           const unsigned long long* roots, uint32_t nroots, uint32_t* counters,
+                           const uint32_t* counters0, uint32_t ncounters, int32_t* info, int ninfo,
+                           uint32_t* trace_idx, void* stream);
 int launch_sched(const SchedArgs& a, int num_wg, void* stream);
 int launch_one_task(const SchedArgs& a, int nparts, void* stream);
 int launch_tile_inverses(const double* l, int b, double* dinv, void* stream);

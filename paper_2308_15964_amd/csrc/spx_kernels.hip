@@ -35,17 +35,9 @@ __device__ __forceinline__ u64 now_ticks() { return wall_clock64(); }
 // Inverses of the 32x32 diagonal blocks of diagonal tile k: b/32 column-major blocks.
 __device__ __forceinline__ double* dinv_ptr(const DevMat& m, int k) { return m.dinv + (size_t)k * 32 * m.b; }
 
-// Agent-scope atomics.  Release publishes this workgroup's global writes (made visible
-// to the whole device before the counter changes); acquire makes the writes of the
-// releasing workgroups visible to the reader.
-__device__ __forceinline__ uint32_t ld_acq(const uint32_t* p) {
-  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-}
+// Relaxed agent-scope load of a scheduler counter (ordering comes from explicit fences).
 __device__ __forceinline__ uint32_t ld_rlx(const uint32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ uint32_t sub_acqrel(uint32_t* p, uint32_t v) {
-  return __hip_atomic_fetch_sub(p, v, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -921,80 +913,135 @@ __device__ void run_part(const SchedArgs& a, uint32_t task, uint32_t part, doubl
 // ---------------------------------------------------------------------------------------
 // The persistent scheduler kernel.
 // ---------------------------------------------------------------------------------------
-__device__ __forceinline__ uint32_t* ctr_head(const SchedArgs& a, int l) { return a.counters + l * kCounterStride; }
-__device__ __forceinline__ uint32_t* ctr_tail(const SchedArgs& a, int l) {
-  return a.counters + (kMaxLevels + l) * kCounterStride;
-}
-__device__ __forceinline__ uint32_t* ctr_done(const SchedArgs& a) { return a.counters + 2 * kMaxLevels * kCounterStride; }
-__device__ __forceinline__ uint32_t* ctr_status(const SchedArgs& a) {
-  return a.counters + (2 * kMaxLevels + 1) * kCounterStride;
+__device__ __forceinline__ uint32_t* ctr_head(const SchedArgs& a, int l, int s) { return a.counters + ctr_head_idx(l, s); }
+__device__ __forceinline__ uint32_t* ctr_tail(const SchedArgs& a, int l, int s) { return a.counters + ctr_tail_idx(l, s); }
+__device__ __forceinline__ uint32_t* ctr_status(const SchedArgs& a) { return a.counters + kStatusIdx; }
+__device__ __forceinline__ u64* queue_of(const SchedArgs& a, int l, int s) {
+  return a.queue + (size_t)a.qbase[l] * kShards + (size_t)s * a.qcap[l];
 }
 
-// push: reserve nparts slots at the task's level, then publish each item (release)
-__device__ void push_task(const SchedArgs& a, uint32_t s) {
+// Memory ordering.  All counter and queue updates are relaxed; visibility of tile data
+// comes from agent-scope fences, which on this chip write back (release) or invalidate
+// (acquire) the XCD's L2, so they are kept to the minimum:
+//   * a finished part: one release fence, then its decrement of the task's parts_left;
+//   * the task's last part: an acquire fence (the other parts' writes, through the release
+//     sequence of parts_left), a release fence, then relaxed decrements of the successors'
+//     pending counters and relaxed pushes;
+//   * a popped part: the task's pending counter is read (it is 0: the value the last
+//     predecessor's decrement wrote, at the end of the release sequence every predecessor
+//     joined), then one acquire fence makes every predecessor's writes visible.
+__device__ __forceinline__ void fence_rel() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
+__device__ __forceinline__ void fence_acq() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
+__device__ __forceinline__ uint32_t sub_rlx(uint32_t* p, uint32_t v) {
+  return __hip_atomic_fetch_sub(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// push into the pushing workgroup's own shard: reserve nparts slots, then fill them
+__device__ void push_task(const SchedArgs& a, uint32_t s, int home) {
   const TaskDesc d = a.tasks[s];
-  const uint32_t slot =
-      __hip_atomic_fetch_add(ctr_tail(a, d.level), (uint32_t)d.nparts, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  u64* q = a.queue + a.qbase[d.level] + slot;
+  const uint32_t slot = __hip_atomic_fetch_add(ctr_tail(a, d.level, home), (uint32_t)d.nparts, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+  u64* q = queue_of(a, d.level, home) + slot;
   for (uint32_t p = 0; p < d.nparts; ++p)
-    __hip_atomic_store(q + p, ((u64)s << 16) | p, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(q + p, ((u64)s << 16) | p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// pop (thread 0 only): highest non-empty level first.  Returns EMPTY if nothing is
-// ready, or ~1ull when the graph is finished or the run must stop.
-__device__ u64 try_pop(const SchedArgs& a) {
-  for (int l = 0; l < a.nlev; ++l) {
-    uint32_t* hp = ctr_head(a, l);
-    uint32_t h = ld_rlx(hp);
-    const uint32_t t = ld_rlx(ctr_tail(a, l));
+// pop, run by all 64 lanes of wave 0: lane i reads the head and tail of queue (level
+// i / S, shard (home + i) % S) for the S shards in use, all in one round trip; the lowest
+// lane with
+// a non-empty queue (highest priority level, own shard first) claims a slot with a
+// compare-and-swap.  Returns the item (the same in every lane), or EMPTY; *saw tells
+// whether some queue looked non-empty (a lost race: scan again at once) and *taken is
+// the number of parts taken from all queues so far (never more than the true count).
+__device__ u64 pop_wave(const SchedArgs& a, int home, bool* saw, uint32_t* taken) {
+  const int lane = threadIdx.x & 63, S = a.nshards;
+  const bool valid = lane < a.nlev * S;
+  const int l = lane / S, sh = (home + lane % S) % S;
+  uint32_t h = 0, t = 0;
+  if (valid) {
+    h = ld_rlx(ctr_head(a, l, sh));
+    t = ld_rlx(ctr_tail(a, l, sh));
+  }
+  uint32_t sum = h;
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) sum += __shfl_xor(sum, off);
+  *taken = sum;
+  const unsigned long long mask = __ballot(valid && h < t);
+  *saw = mask != 0ull;
+  if (!mask) return EMPTY;
+  const int win = __ffsll((long long)mask) - 1;
+  u64 item = EMPTY;
+  if (lane == win) {
+    // retry with the head each failed compare-and-swap returns (no reload of the other
+    // counters) while this queue still looks non-empty
     while (h < t) {
-      if (__hip_atomic_compare_exchange_strong(hp, &h, h + 1, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+      if (__hip_atomic_compare_exchange_strong(ctr_head(a, l, sh), &h, h + 1, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
                                                __HIP_MEMORY_SCOPE_AGENT)) {
-        // the slot is reserved by a running pusher: wait for the item to be published
-        const u64* q = a.queue + a.qbase[l] + h;
-        u64 item;
-        while ((item = __hip_atomic_load(q, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT)) == EMPTY)
+        // the slot is reserved by a running pusher: wait for the item to be written
+        const u64* q = queue_of(a, l, sh) + h;
+        while ((item = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) == EMPTY)
           __builtin_amdgcn_s_sleep(1);
-        return item;
+        break;
       }
     }
   }
-  return EMPTY;
+  const uint32_t lo = __shfl((uint32_t)item, win), hi = __shfl((uint32_t)(item >> 32), win);
+  return ((u64)hi << 32) | lo;
 }
 
 __global__ __launch_bounds__(NT) void sched_kernel(SchedArgs a) {
   __shared__ double lds[LDS_DOUBLES];
   __shared__ u64 s_item;
   const int tid = threadIdx.x;
+  const int home = blockIdx.x % a.nshards;
   u64 idle = 0, busy = 0;
   for (;;) {
-    if (tid == 0) {
+    if (tid < 64) {
       const u64 t0 = now_ticks();
       u64 last_change = t0;
-      uint32_t last_done = ld_rlx(ctr_done(a));
+      uint32_t last_taken = 0xffffffffu;
       u64 item;
+      int naps = 0;
       for (;;) {
-        item = try_pop(a);
+        bool saw;
+        uint32_t taken;
+        item = pop_wave(a, home, &saw, &taken);
         if (item != EMPTY) break;
-        const uint32_t done = ld_acq(ctr_done(a));
-        if (done >= a.total_parts || ld_rlx(ctr_status(a)) != 0) {
+        if (saw) {  // the queue emptied under us: scan again after a short pause
+          __builtin_amdgcn_s_sleep(1);
+          continue;
+        }
+        const uint32_t status = __builtin_amdgcn_readfirstlane(ld_rlx(ctr_status(a)));
+        if (taken >= a.total_parts || status != 0) {
           item = ~1ull;
           break;
         }
         const u64 t = now_ticks();
-        if (done != last_done) {
-          last_done = done;
+        if (taken != last_taken) {
+          last_taken = taken;
           last_change = t;
         } else if (t - last_change > a.spin_limit) {
-          // no part finished for the whole spin limit: give up so the kernel ends
-          __hip_atomic_fetch_or(ctr_status(a), (uint32_t)STATUS_TIMEOUT, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          // no part started for the whole spin limit: give up so the kernel ends
+          if (tid == 0)
+            __hip_atomic_fetch_or(ctr_status(a), (uint32_t)STATUS_TIMEOUT, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           item = ~1ull;
           break;
         }
-        __builtin_amdgcn_s_sleep(2);
+        // back off (up to about 1.7 us) while the queues stay empty: every scan is 64
+        // uncached loads, and hundreds of idle workgroups polling would take memory
+        // bandwidth from the ones running the critical path
+        if (naps < 5) ++naps;
+        for (int z = 0; z < (1 << naps); ++z) __builtin_amdgcn_s_sleep(2);
       }
-      s_item = item;
-      idle += now_ticks() - t0;
+      if (tid == 0) {
+        if (item != ~1ull) {
+          const uint32_t* pend = a.pending + (uint32_t)(item >> 16);
+          while (ld_rlx(pend) != 0u) __builtin_amdgcn_s_sleep(1);
+          fence_acq();
+        }
+        s_item = item;
+        idle += now_ticks() - t0;
+      }
     }
     __syncthreads();
     const u64 item = s_item;
@@ -1015,15 +1062,15 @@ __global__ __launch_bounds__(NT) void sched_kernel(SchedArgs a) {
           a.trace[4 * k + 3] = te;
         }
       }
-      // the part's writes are released with the decrement; the last part releases the
-      // task's successors
-      if (sub_acqrel(a.parts_left + task, 1u) == 1u) {
+      fence_rel();
+      if (sub_rlx(a.parts_left + task, 1u) == 1u) {
+        fence_acq();
+        fence_rel();
         for (uint32_t e = a.succ_off[task]; e < a.succ_off[task + 1]; ++e) {
           const uint32_t s = a.succ[e];
-          if (sub_acqrel(a.pending + s, 1u) == 1u) push_task(a, s);
+          if (sub_rlx(a.pending + s, 1u) == 1u) push_task(a, s, home);
         }
       }
-      __hip_atomic_fetch_add(ctr_done(a), 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     }
   }
   if (tid == 0 && a.wg_cycles) {
@@ -1044,21 +1091,27 @@ __global__ __launch_bounds__(NT) void tile_inverses_kernel(const double* l, int 
 }
 
 // Per-launch state from the cached static image: counters of unfinished predecessors
-// and parts, the ready queue with the root tasks already in it, cleared counters.
+// and parts, cleared queues and counters (the root parts are written by roots_kernel,
+// launched after this one).
 __global__ void sched_init_kernel(uint32_t* pending, const uint32_t* indeg, uint32_t* parts_left,
-                                  const uint32_t* nparts, uint32_t ntasks, u64* queue, const u64* queue0,
-                                  uint32_t queue_len, uint32_t* counters, const uint32_t* counters0,
-                                  uint32_t ncounters, int32_t* info, int ninfo, uint32_t* trace_idx) {
+                                  const uint32_t* nparts, uint32_t ntasks, u64* queue, uint32_t queue_len,
+                                  uint32_t* counters, const uint32_t* counters0, uint32_t ncounters, int32_t* info,
+                                  int ninfo, uint32_t* trace_idx) {
   const uint32_t stride = gridDim.x * blockDim.x;
   const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
   for (uint32_t t = g; t < ntasks; t += stride) {
     pending[t] = indeg[t];
     parts_left[t] = nparts[t];
   }
-  for (uint32_t t = g; t < queue_len; t += stride) queue[t] = queue0[t];
+  for (uint32_t t = g; t < queue_len; t += stride) queue[t] = EMPTY;
   for (uint32_t t = g; t < ncounters; t += stride) counters[t] = counters0[t];
   for (uint32_t t = g; t < (uint32_t)ninfo; t += stride) info[t] = INT_MAX;
   if (g == 0 && trace_idx) *trace_idx = 0;
+}
+
+__global__ void roots_kernel(u64* queue, const u64* roots, uint32_t nroots) {
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < nroots; r += stride) queue[roots[2 * r]] = roots[2 * r + 1];
 }
 
 // ---------------------------------------------------------------------------------------
@@ -1310,12 +1363,16 @@ int launch_sched(const SchedArgs& a, int num_wg, void* stream) {
 }
 
 int launch_sched_init_full(uint32_t* pending, const uint32_t* indeg, uint32_t* parts_left, const uint32_t* nparts,
-                           uint32_t ntasks, unsigned long long* queue, const unsigned long long* queue0,
-                           uint32_t queue_len, uint32_t* counters, const uint32_t* counters0, uint32_t ncounters,
-                           int32_t* info, int ninfo, uint32_t* trace_idx, void* stream) {
-  hipLaunchKernelGGL(sched_init_kernel, dim3(256), dim3(NT), 0, (hipStream_t)stream, pending, indeg, parts_left,
-                     nparts, ntasks, queue, queue0, queue_len, counters, counters0, ncounters, info, ninfo, trace_idx);
-  return hip_ok(hipGetLastError(), "sched_init_kernel");
+                           uint32_t ntasks, unsigned long long* queue, uint32_t queue_len,
+                           const unsigned long long* roots, uint32_t nroots, uint32_t* counters,
+                           const uint32_t* counters0, uint32_t ncounters, int32_t* info, int ninfo,
+                           uint32_t* trace_idx, void* stream) {
+  hipLaunchKernelGGL(sched_init_kernel, dim3(1024), dim3(NT), 0, (hipStream_t)stream, pending, indeg, parts_left,
+                     nparts, ntasks, queue, queue_len, counters, counters0, ncounters, info, ninfo, trace_idx);
+  const int rc = hip_ok(hipGetLastError(), "sched_init_kernel");
+  if (rc) return rc;
+  hipLaunchKernelGGL(roots_kernel, dim3(256), dim3(NT), 0, (hipStream_t)stream, queue, roots, nroots);
+  return hip_ok(hipGetLastError(), "roots_kernel");
 }
 
 int launch_backward_error(int64_t n, const double* dA, int64_t lda, int64_t nrhs, const double* dX, int64_t ldx,
