@@ -123,16 +123,22 @@ int spx_cholesky_graph(int32_t nt, int32_t with_solve, spx_graph** out, int32_t*
  *     SPX_Q_FIFO (one ready queue in push order).  Results are bitwise identical.
  *   num_wg: persistent workgroups (0 = fill the GPU).
  *   flags: SPX_F_TRACE records per-task device timestamps (spx_trace).
+ *     SPX_F_SCALED factors D^{-1/2} A D^{-1/2} + shift I instead of A (D = diag(A)):
+ *     a stabilised low-precision factor that spx_potrs uses as a preconditioner (the
+ *     factor keeps D^{-1/2} and applies it around every solve).  spx_factor_get_l then
+ *     returns the factor of the scaled, shifted matrix.  Single-matrix calls only.
  * ------------------------------------------------------------------------------------ */
 enum { SPX_PREC_FP64 = 0, SPX_PREC_FP32 = 1, SPX_PREC_BF16 = 2 };
 enum { SPX_Q_PRIORITY = 0, SPX_Q_FIFO = 1 };
-enum { SPX_F_TRACE = 1u };
+enum { SPX_F_TRACE = 1u, SPX_F_SCALED = 2u };
 typedef struct {
   int32_t tile;
   int32_t update_prec;
   int32_t queue_policy;
   int32_t num_wg;
   uint32_t flags;
+  int32_t pad;
+  double shift; /* with SPX_F_SCALED only */
 } spx_opts;
 
 /* Factors the n x n SPD matrix dA (device pointer, row-major, leading dimension lda >= n,
@@ -160,7 +166,10 @@ void spx_factor_destroy(spx_factor* f);
  *   largest normwise backward error of the columns is <= tol, or max_iter corrections:
  *   method 0 = none, 1 = classical refinement (r = b - A x in FP64 with the original
  *   matrix, x += solve(L, r)), stopping early after two steps that fail to halve the
- *   error.  Refinement needs the original matrix: pass it in dA (device, row-major, lda);
+ *   error; 2 = preconditioned conjugate gradients in FP64 on A with the factor as the
+ *   preconditioner (every column its own recurrence; the true residual b - A x is
+ *   recomputed each iteration; stops after 10 iterations without a new best error).  A
+ *   factor made with SPX_F_SCALED is applied as D^{-1/2} (L L^T)^{-1} D^{-1/2}.  Refinement needs the original matrix: pass it in dA (device, row-major, lda);
  *   the caller keeps it alive and unmodified during the call; dX must not alias dB.
  *   tol <= 0 means 1e-12, max_iter <= 0 means 50.
  *   stats (nullable) receives the number of corrections and the final largest backward

@@ -126,6 +126,8 @@ struct spx_factor {
   size_t tile_bytes = 0;
   void* low = nullptr;  // FP32 / BF16 copies of the panel tiles (mixed precision)
   double* dinv = nullptr;  // inverses of the 32x32 diagonal blocks of the diagonal tiles
+  double* dscale = nullptr;  // D^{-1/2} (n_pad) of a factor of the scaled, shifted matrix
+  double shift = 0.0;
 };
 
 namespace spx {
@@ -618,6 +620,7 @@ static int batched(spx_ctx* c, int count, const int64_t* n, const double* const*
   const int policy = o ? o->queue_policy : SPX_Q_PRIORITY;
   if (policy != SPX_Q_PRIORITY && policy != SPX_Q_FIFO) return failf(SPX_EINVAL, "%s: bad queue policy", who);
   if (o && o->tile > 0 && !valid_tile(o->tile)) return failf(SPX_EINVAL, "%s: bad tile size", who);
+  if (o && (o->flags & SPX_F_SCALED)) return failf(SPX_EINVAL, "%s: scaled factors are single-matrix only", who);
   std::vector<int> bs(count), nts(count), qs(count, 0);
   for (int m = 0; m < count; ++m) {
     if (n[m] < 1 || lda[m] < n[m] || !dA[m]) return failf(SPX_EINVAL, "%s: matrix %d: bad n, lda or pointer", who, m);
@@ -1037,6 +1040,8 @@ int spx_potrf_tiled(spx_ctx* c, int64_t n, const double* dA, int64_t lda, const 
     return fail(SPX_EINVAL, "spx_potrf_tiled: bad update precision");
   const int64_t nt = (n + b - 1) / b;
   if (nt > 2048) return fail(SPX_EINVAL, "spx_potrf_tiled: too many tiles");
+  const bool scaled = opts && (opts->flags & SPX_F_SCALED);
+  if (scaled && !(opts->shift >= 0.0)) return fail(SPX_EINVAL, "spx_potrf_tiled: shift must be >= 0");
   SPX_TRY(hipc(hipSetDevice(c->device), "hipSetDevice"));
   std::unique_ptr<spx_factor> f(new spx_factor());
   f->ctx = c;
@@ -1061,13 +1066,23 @@ int spx_potrf_tiled(spx_ctx* c, int64_t n, const double* dA, int64_t lda, const 
       return fail(SPX_ENOMEM, "spx_potrf_tiled: low-precision copy allocation failed");
     }
   }
-  Image* im = nullptr;
-  int rc = get_image(c, false, (int)nt, b, 0, policy, &im);
-  if (!rc) rc = ensure_small_buffers(c, 1, 1, 0, false);
-  if (rc) {
+  auto drop = [&]() {
     dev_free(c, f->tiles);
     dev_free(c, f->low);
     dev_free(c, f->dinv);
+    dev_free(c, f->dscale);
+  };
+  Image* im = nullptr;
+  int rc = get_image(c, false, (int)nt, b, 0, policy, &im);
+  if (!rc) rc = ensure_small_buffers(c, 1, 1, 0, false);
+  if (!rc && scaled) {
+    f->shift = opts->shift;
+    f->dscale = (double*)dev_alloc(c, (size_t)f->n_pad * sizeof(double));
+    rc = f->dscale ? launch_diag_scale(dA, lda, n, f->dscale, f->n_pad, c->stream)
+                   : fail(SPX_ENOMEM, "spx_potrf_tiled: scale allocation failed");
+  }
+  if (rc) {
+    drop();
     return rc;
   }
   DevMat m{};
@@ -1081,6 +1096,8 @@ int spx_potrf_tiled(spx_ctx* c, int64_t n, const double* dA, int64_t lda, const 
   m.prec = prec;
   m.n = (int32_t)n;
   m.trsm_rows = trsm_rows_of(b);
+  m.dscale = f->dscale;
+  m.shift = f->shift;
   c->hmats[0] = m;
   rc = hipc(hipEventRecord(c->ev[2], c->stream), "hipEventRecord");
   if (!rc) rc = launch_pack(dA, lda, n, m, c->stream);
@@ -1092,16 +1109,12 @@ int spx_potrf_tiled(spx_ctx* c, int64_t n, const double* dA, int64_t lda, const 
     c->last.tile = (uint32_t)b;
   }
   if (rc) {
-    dev_free(c, f->tiles);
-    dev_free(c, f->low);
-    dev_free(c, f->dinv);
+    drop();
     return rc;
   }
   if (c->hinfo[0] != INT_MAX) {
     *info = c->hinfo[0];
-    dev_free(c, f->tiles);
-    dev_free(c, f->low);
-    dev_free(c, f->dinv);
+    drop();
     return SPX_OK;
   }
   *out = f.release();
@@ -1133,6 +1146,7 @@ void spx_factor_destroy(spx_factor* f) {
   dev_free(f->ctx, f->tiles);
   dev_free(f->ctx, f->low);
   dev_free(f->ctx, f->dinv);
+  dev_free(f->ctx, f->dscale);
   delete f;
 }
 
@@ -1179,36 +1193,82 @@ static int residual_eta(spx_ctx* c, int64_t n, const double* dA, int64_t lda, in
   return SPX_OK;
 }
 
+// Y = M^{-1} R for the n x nrhs row-major R (ld ldr) into Y (ld ldy; accumulate: Y +=),
+// M = L L^T, or D^{1/2} L L^T D^{1/2} for a scaled factor; rhs: n_pad x nrhs work.
+static int apply_inverse(spx_ctx* c, const spx_factor* f, int64_t nrhs, const double* R, int64_t ldr, double* Y,
+                         int64_t ldy, int accumulate, double* rhs, double* ms) {
+  SPX_TRY(launch_rhs_in(R, ldr, f->n, nrhs, rhs, f->n_pad, f->dscale, c->stream));
+  SPX_TRY(solve_on(c, f, nrhs, rhs));
+  *ms += c->last.kernel_ms;
+  return launch_rhs_out(rhs, f->n_pad, f->n, nrhs, Y, ldy, accumulate, f->dscale, c->stream);
+}
+
+// Column sums of U .* V (n x q row-major), reduced on the host in a fixed order.
+static int dot_cols(spx_ctx* c, int64_t n, int64_t q, const double* U, const double* V, double* partial,
+                    std::vector<double>& hp, double* out) {
+  int nthr = 0;
+  SPX_TRY(launch_dot_cols(n, q, U, V, partial, &nthr, c->stream));
+  hp.resize(nthr);
+  SPX_TRY(hipc(hipMemcpyAsync(hp.data(), partial, sizeof(double) * nthr, hipMemcpyDeviceToHost, c->stream), "dot"));
+  SPX_TRY(hipc(hipStreamSynchronize(c->stream), "hipStreamSynchronize"));
+  for (int64_t k = 0; k < q; ++k) out[k] = 0.0;
+  for (int g = 0; g < nthr; ++g) out[g % q] += hp[g];
+  return SPX_OK;
+}
+
 int spx_potrs(spx_ctx* c, const spx_factor* f, int64_t nrhs, const double* dB, int64_t ldb, double* dX, int64_t ldx,
               const double* dA, int64_t lda, const spx_refine* refine, spx_solve_stats* stats) {
   if (!c || !f || !dB || !dX) return fail(SPX_EINVAL, "spx_potrs: null argument");
   if (nrhs < 1 || nrhs > 4096 || ldb < nrhs || ldx < nrhs) return fail(SPX_EINVAL, "spx_potrs: bad nrhs / ld");
   if (dX == dB && ldx != ldb) return fail(SPX_EINVAL, "spx_potrs: aliased X and B need equal leading dimensions");
   const int method = refine ? refine->method : 0;
-  if (method < 0 || method > 1) return fail(SPX_EINVAL, "spx_potrs: refinement method must be 0 or 1");
+  if (method < 0 || method > 2) return fail(SPX_EINVAL, "spx_potrs: refinement method must be 0, 1 or 2");
   if (method && (!dA || lda < f->n)) return fail(SPX_EINVAL, "spx_potrs: refinement needs the original matrix");
   if (method && dX == dB) return fail(SPX_EINVAL, "spx_potrs: refinement needs X distinct from B");
   SPX_TRY(hipc(hipSetDevice(c->device), "hipSetDevice"));
-  double* rhs = (double*)dev_alloc(c, (size_t)f->n_pad * (size_t)nrhs * sizeof(double));
-  double* R = method ? (double*)dev_alloc(c, (size_t)f->n * (size_t)nrhs * sizeof(double)) : nullptr;
-  double* S = method ? (double*)dev_alloc(c, sizeof(double) * (size_t)(3 * nrhs + 1)) : nullptr;
-  int rc = (!rhs || (method && (!R || !S))) ? fail(SPX_ENOMEM, "spx_potrs: work buffer allocation failed") : SPX_OK;
-  if (!rc) rc = launch_rhs_in(dB, ldb, f->n, nrhs, rhs, f->n_pad, c->stream);
-  if (!rc) rc = solve_on(c, f, nrhs, rhs);
-  if (!rc) rc = launch_rhs_out(rhs, f->n_pad, f->n, nrhs, dX, ldx, 0, c->stream);
+  const int64_t n = f->n, q = nrhs;
+  const size_t vec = (size_t)n * (size_t)q * sizeof(double);
+  std::vector<void*> bufs;
+  auto get = [&](size_t bytes) {
+    void* p = dev_alloc(c, bytes);
+    bufs.push_back(p);
+    return (double*)p;
+  };
+  double* rhs = get((size_t)f->n_pad * (size_t)q * sizeof(double));
+  double* R = method ? get(vec) : nullptr;
+  double* S = method ? get(sizeof(double) * (size_t)(3 * q + 1)) : nullptr;
+  double *Z = nullptr, *P = nullptr, *NQ = nullptr, *zero = nullptr, *part = nullptr, *alpha = nullptr;
+  double* X = dX;  // PCG works on a dense n x q copy when X has a wider leading dimension
+  int64_t ldw = ldx;
+  if (method == 2) {
+    if (ldx != q) {
+      X = get(vec);
+      ldw = q;
+    }
+    Z = get(vec);
+    P = get(vec);
+    NQ = get(vec);
+    zero = get(vec);
+    part = get(sizeof(double) * 256 * 256);
+    alpha = get(sizeof(double) * (size_t)q);
+  }
+  int rc = SPX_OK;
+  for (void* p : bufs)
+    if (!p) rc = fail(SPX_ENOMEM, "spx_potrs: work buffer allocation failed");
+  double solve_ms = 0.0;
+  if (!rc) rc = apply_inverse(c, f, q, dB, ldb, X, ldw, 0, rhs, &solve_ms);
   int iters = 0;
   double eta_max = -1.0;
-  double solve_ms = c->last.kernel_ms;
+  const double tol = (refine && refine->tol > 0) ? refine->tol : 1e-12;
+  const int max_iter = (refine && refine->max_iter > 0) ? refine->max_iter : 50;
+  std::vector<double> hs;
   if (!rc && method == 1) {
     // classical iterative refinement: r = b - A x in FP64 with the original matrix,
-    // d = solve(L, r), x += d, until the largest normwise backward error <= tol
-    std::vector<double> hs;
-    const double tol = refine->tol > 0 ? refine->tol : 1e-12;
-    const int max_iter = refine->max_iter > 0 ? refine->max_iter : 50;
+    // d = M^{-1} r, x += d, until the largest normwise backward error <= tol
     double prev = INFINITY;
     int slow = 0;
     for (;;) {
-      rc = residual_eta(c, f->n, dA, lda, nrhs, dX, ldx, dB, ldb, R, S, hs, nullptr, &eta_max);
+      rc = residual_eta(c, n, dA, lda, q, dX, ldx, dB, ldb, R, S, hs, nullptr, &eta_max);
       if (rc || eta_max <= tol || iters >= max_iter) break;
       if (!(eta_max < 0.5 * prev)) {  // stagnation (or NaN): stop after two slow steps
         if (++slow >= 2 || eta_max != eta_max) break;
@@ -1216,18 +1276,60 @@ int spx_potrs(spx_ctx* c, const spx_factor* f, int64_t nrhs, const double* dB, i
         slow = 0;
       }
       prev = eta_max;
-      rc = launch_rhs_in(R, nrhs, f->n, nrhs, rhs, f->n_pad, c->stream);
-      if (!rc) rc = solve_on(c, f, nrhs, rhs);
-      if (!rc) rc = launch_rhs_out(rhs, f->n_pad, f->n, nrhs, dX, ldx, 1, c->stream);
-      if (!rc) solve_ms += c->last.kernel_ms;
+      rc = apply_inverse(c, f, q, R, q, dX, ldx, 1, rhs, &solve_ms);
       if (rc) break;
       ++iters;
     }
+  } else if (!rc && method == 2) {
+    // preconditioned conjugate gradients on A x = b, one recurrence per column, started
+    // from x0 = M^{-1} b; the true residual replaces the recurrence every iteration
+    std::vector<double> rho(q), pq(q), rz(q), a(q), hp;
+    double best = INFINITY;
+    int since_best = 0;
+    rc = hipc(hipMemsetAsync(zero, 0, vec, c->stream), "hipMemsetAsync");
+    if (!rc) rc = residual_eta(c, n, dA, lda, q, X, ldw, dB, ldb, R, S, hs, nullptr, &eta_max);
+    if (!rc && !(eta_max <= tol)) {
+      rc = apply_inverse(c, f, q, R, q, Z, q, 0, rhs, &solve_ms);
+      if (!rc) rc = hipc(hipMemcpyAsync(P, Z, vec, hipMemcpyDeviceToDevice, c->stream), "copy");
+      if (!rc) rc = dot_cols(c, n, q, R, Z, part, hp, rho.data());
+      while (!rc && iters < max_iter) {
+        // NQ = 0 - A P
+        double unused = 0.0;
+        rc = residual_eta(c, n, dA, lda, q, P, q, zero, q, NQ, S, hs, nullptr, &unused);
+        if (!rc) rc = dot_cols(c, n, q, P, NQ, part, hp, pq.data());
+        if (rc) break;
+        for (int64_t k = 0; k < q; ++k) a[k] = (pq[k] != 0.0 && rho[k] != 0.0) ? rho[k] / -pq[k] : 0.0;
+        rc = hipc(hipMemcpyAsync(alpha, a.data(), sizeof(double) * q, hipMemcpyHostToDevice, c->stream), "alpha");
+        if (!rc) rc = launch_axpy_cols(n, q, alpha, P, X, 0, c->stream);  // x += alpha p
+        if (rc) break;
+        ++iters;
+        rc = residual_eta(c, n, dA, lda, q, X, ldw, dB, ldb, R, S, hs, nullptr, &eta_max);
+        if (rc || eta_max <= tol) break;
+        if (eta_max < best) {
+          best = eta_max;
+          since_best = 0;
+        } else if (++since_best >= 10 || eta_max != eta_max) {
+          break;
+        }
+        rc = apply_inverse(c, f, q, R, q, Z, q, 0, rhs, &solve_ms);
+        if (!rc) rc = dot_cols(c, n, q, R, Z, part, hp, rz.data());
+        if (rc) break;
+        for (int64_t k = 0; k < q; ++k) {
+          a[k] = rho[k] != 0.0 ? rz[k] / rho[k] : 0.0;
+          rho[k] = rz[k];
+        }
+        rc = hipc(hipMemcpyAsync(alpha, a.data(), sizeof(double) * q, hipMemcpyHostToDevice, c->stream), "beta");
+        if (!rc) rc = launch_axpy_cols(n, q, alpha, Z, P, 1, c->stream);  // p = z + beta p
+      }
+    }
+    if (!rc && X != dX)
+      rc = hipc(hipMemcpy2DAsync(dX, (size_t)ldx * 8, X, (size_t)q * 8, (size_t)q * 8, (size_t)n, hipMemcpyDeviceToDevice,
+                                 c->stream),
+                "copy");
   }
   if (!rc) rc = hipc(hipStreamSynchronize(c->stream), "hipStreamSynchronize");
-  dev_free(c, rhs);
-  dev_free(c, R);
-  dev_free(c, S);
+  (void)hipStreamSynchronize(c->stream);
+  for (void* p : bufs) dev_free(c, p);
   if (rc) return rc;
   c->last.kernel_ms = solve_ms;  // all solve launches of this call
   if (stats) {

@@ -64,6 +64,8 @@ struct DevMat {
   int32_t store_acc;  // STORE adds the solution to X instead of overwriting it
   int32_t pad1;
   // caller's dense arrays, used by the LOAD / STORE tasks of batched and served graphs
+  const double* dscale;  // packing: A(i,j) d_i d_j (+ shift on the diagonal), or null
+  double shift;
   const double* A;  // n x n row-major, lower triangle read
   const double* B;  // n x nrhs row-major
   double* X;        // n x nrhs row-major
@@ -109,9 +111,19 @@ enum { STATUS_TIMEOUT = 1u };
 // Host-side launchers (spx_kernels.hip).
 int launch_pack(const double* dA, int64_t lda, int64_t n, const DevMat& m, void* stream);
 int launch_unpack(const DevMat& m, int64_t n, double* dL, int64_t ldl, void* stream);
-int launch_rhs_in(const double* dB, int64_t ldb, int64_t n, int64_t nrhs, double* rhs, int64_t n_pad, void* stream);
+// scale (nullable): row r is multiplied by scale[r] on the way in / out.
+int launch_rhs_in(const double* dB, int64_t ldb, int64_t n, int64_t nrhs, double* rhs, int64_t n_pad,
+                  const double* scale, void* stream);
 int launch_rhs_out(const double* rhs, int64_t n_pad, int64_t n, int64_t nrhs, double* dX, int64_t ldx, int accumulate,
-                   void* stream);
+                   const double* scale, void* stream);
+// d[i] = 1 / sqrt(A(i,i)) for i < n, 1 for n <= i < n_pad.
+int launch_diag_scale(const double* dA, int64_t lda, int64_t n, double* d, int64_t n_pad, void* stream);
+// Column sums of U .* V (n x q row-major, ld q), deterministic: partial[g] for g < nthreads
+// (nthreads returned, a multiple of q); the host adds partial[c], partial[c + q], ... in order.
+int launch_dot_cols(int64_t n, int64_t q, const double* U, const double* V, double* partial, int* nthreads,
+                    void* stream);
+// mode 0: Y += alpha_c X;  mode 1: Y = X + alpha_c Y  (n x q row-major, alpha: q on the device).
+int launch_axpy_cols(int64_t n, int64_t q, const double* alpha, const double* X, double* Y, int mode, void* stream);
 // roots: nroots pairs (queue slot, item) written after the queue is cleared.
 int launch_sched_init_full(uint32_t* pending, const uint32_t* indeg, uint32_t* parts_left, const uint32_t* nparts,
                            uint32_t ntasks, unsigned long long* queue, uint32_t queue_len,

@@ -778,10 +778,15 @@ __device__ void pack_block(const double* __restrict__ A, int64_t lda, int64_t n,
     const int rr = e / S, cc = e % S;  // cc fastest: row-major reads
     const int64_t R = R0 + rr, C = C0 + cc;
     double v;
-    if (R < n && C < n)
+    if (R < n && C < n) {
       v = (R >= C) ? A[R * lda + C] : 0.0;
-    else
+      if (m.dscale) {
+        v = v * m.dscale[R] * m.dscale[C];
+        if (R == C) v += m.shift;
+      }
+    } else {
       v = (R == C) ? 1.0 : 0.0;
+    }
     s[rr * 65 + cc] = v;
   }
   __syncthreads();
@@ -948,12 +953,15 @@ __device__ void push_task(const SchedArgs& a, uint32_t s, int home) {
 
 // pop, run by all 64 lanes of wave 0: lane i reads the head and tail of queue (level
 // i / S, shard (home + i) % S) for the S shards in use, all in one round trip; the lowest
-// lane with
-// a non-empty queue (highest priority level, own shard first) claims a slot with a
-// compare-and-swap.  Returns the item (the same in every lane), or EMPTY; *saw tells
-// whether some queue looked non-empty (a lost race: scan again at once) and *taken is
-// the number of parts taken from all queues so far (never more than the true count).
-__device__ u64 pop_wave(const SchedArgs& a, int home, bool* saw, uint32_t* taken) {
+// lane with a non-empty queue (highest priority level, own shard first) claims slots with
+// a compare-and-swap, retried in place with the head it returns.  From the two bulk
+// levels it claims several parts at once while the queue is long (fewer operations on
+// the shared head, whose compare-and-swaps serialise); from the critical levels one.
+// Writes up to kClaim items to items[] (lane 0's copy) and returns their number (the same
+// in every lane); *saw tells whether some queue looked non-empty and *taken is the number
+// of parts taken from all queues so far (never more than the true count).
+constexpr int kClaim = 4;
+__device__ int pop_wave(const SchedArgs& a, int home, bool* saw, uint32_t* taken, u64* items) {
   const int lane = threadIdx.x & 63, S = a.nshards;
   const bool valid = lane < a.nlev * S;
   const int l = lane / S, sh = (home + lane % S) % S;
@@ -968,30 +976,48 @@ __device__ u64 pop_wave(const SchedArgs& a, int home, bool* saw, uint32_t* taken
   *taken = sum;
   const unsigned long long mask = __ballot(valid && h < t);
   *saw = mask != 0ull;
-  if (!mask) return EMPTY;
+  if (!mask) return 0;
   const int win = __ffsll((long long)mask) - 1;
-  u64 item = EMPTY;
+  int k = 0;
+  u64 it[kClaim];
+#pragma unroll
+  for (int i = 0; i < kClaim; ++i) it[i] = EMPTY;
   if (lane == win) {
-    // retry with the head each failed compare-and-swap returns (no reload of the other
-    // counters) while this queue still looks non-empty
+    const bool bulk = a.nlev > 2 && l >= a.nlev - 2;
     while (h < t) {
-      if (__hip_atomic_compare_exchange_strong(ctr_head(a, l, sh), &h, h + 1, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+      const uint32_t avail = t - h;
+      const uint32_t want = bulk ? (avail >= 192u ? 4u : avail >= 128u ? 3u : avail >= 64u ? 2u : 1u) : 1u;
+      if (__hip_atomic_compare_exchange_strong(ctr_head(a, l, sh), &h, h + want, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
                                                __HIP_MEMORY_SCOPE_AGENT)) {
-        // the slot is reserved by a running pusher: wait for the item to be written
+        // the slots are reserved by running pushers: wait for the items to be written
         const u64* q = queue_of(a, l, sh) + h;
-        while ((item = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) == EMPTY)
-          __builtin_amdgcn_s_sleep(1);
+#pragma unroll
+        for (int i = 0; i < kClaim; ++i) {
+          if (i < (int)want) {
+            u64 v;
+            while ((v = __hip_atomic_load(q + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) == EMPTY)
+              __builtin_amdgcn_s_sleep(1);
+            it[i] = v;
+          }
+        }
+        k = (int)want;
         break;
       }
     }
   }
-  const uint32_t lo = __shfl((uint32_t)item, win), hi = __shfl((uint32_t)(item >> 32), win);
-  return ((u64)hi << 32) | lo;
+  k = __shfl(k, win);
+#pragma unroll
+  for (int i = 0; i < kClaim; ++i) {
+    const uint32_t lo = __shfl((uint32_t)it[i], win), hi = __shfl((uint32_t)(it[i] >> 32), win);
+    items[i] = ((u64)hi << 32) | lo;
+  }
+  return k;
 }
 
 __global__ __launch_bounds__(NT) void sched_kernel(SchedArgs a) {
   __shared__ double lds[LDS_DOUBLES];
-  __shared__ u64 s_item;
+  __shared__ u64 s_items[kClaim];
+  __shared__ int s_n;
   const int tid = threadIdx.x;
   const int home = blockIdx.x % a.nshards;
   u64 idle = 0, busy = 0;
@@ -1000,20 +1026,20 @@ __global__ __launch_bounds__(NT) void sched_kernel(SchedArgs a) {
       const u64 t0 = now_ticks();
       u64 last_change = t0;
       uint32_t last_taken = 0xffffffffu;
-      u64 item;
-      int naps = 0;
+      u64 items[kClaim];
+      int n = 0, naps = 0;
       for (;;) {
         bool saw;
         uint32_t taken;
-        item = pop_wave(a, home, &saw, &taken);
-        if (item != EMPTY) break;
+        n = pop_wave(a, home, &saw, &taken, items);
+        if (n > 0) break;
         if (saw) {  // the queue emptied under us: scan again after a short pause
           __builtin_amdgcn_s_sleep(1);
           continue;
         }
         const uint32_t status = __builtin_amdgcn_readfirstlane(ld_rlx(ctr_status(a)));
         if (taken >= a.total_parts || status != 0) {
-          item = ~1ull;
+          n = -1;
           break;
         }
         const u64 t = now_ticks();
@@ -1024,7 +1050,7 @@ __global__ __launch_bounds__(NT) void sched_kernel(SchedArgs a) {
           // no part started for the whole spin limit: give up so the kernel ends
           if (tid == 0)
             __hip_atomic_fetch_or(ctr_status(a), (uint32_t)STATUS_TIMEOUT, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          item = ~1ull;
+          n = -1;
           break;
         }
         // back off (up to about 1.7 us) while the queues stay empty: every scan is 64
@@ -1034,41 +1060,45 @@ __global__ __launch_bounds__(NT) void sched_kernel(SchedArgs a) {
         for (int z = 0; z < (1 << naps); ++z) __builtin_amdgcn_s_sleep(2);
       }
       if (tid == 0) {
-        if (item != ~1ull) {
-          const uint32_t* pend = a.pending + (uint32_t)(item >> 16);
+        for (int i = 0; i < n; ++i) {
+          const uint32_t* pend = a.pending + (uint32_t)(items[i] >> 16);
           while (ld_rlx(pend) != 0u) __builtin_amdgcn_s_sleep(1);
-          fence_acq();
+          s_items[i] = items[i];
         }
-        s_item = item;
+        if (n > 0) fence_acq();
+        s_n = n;
         idle += now_ticks() - t0;
       }
     }
     __syncthreads();
-    const u64 item = s_item;
-    if (item == ~1ull) break;
-    const uint32_t task = (uint32_t)(item >> 16), part = (uint32_t)(item & 0xffff);
-    const u64 tb = now_ticks();
-    run_part(a, task, part, lds);
-    __syncthreads();
-    if (tid == 0) {
-      const u64 te = now_ticks();
-      busy += te - tb;
-      if (a.trace) {
-        const uint32_t k = atomicAdd(a.trace_idx, 1u);
-        if (k < a.total_parts) {
-          a.trace[4 * k + 0] = task;
-          a.trace[4 * k + 1] = part | ((u64)blockIdx.x << 16);
-          a.trace[4 * k + 2] = tb;
-          a.trace[4 * k + 3] = te;
+    const int n = s_n;
+    if (n < 0) break;
+    for (int i = 0; i < n; ++i) {
+      const u64 item = s_items[i];
+      const uint32_t task = (uint32_t)(item >> 16), part = (uint32_t)(item & 0xffff);
+      const u64 tb = now_ticks();
+      run_part(a, task, part, lds);
+      __syncthreads();
+      if (tid == 0) {
+        const u64 te = now_ticks();
+        busy += te - tb;
+        if (a.trace) {
+          const uint32_t k = atomicAdd(a.trace_idx, 1u);
+          if (k < a.total_parts) {
+            a.trace[4 * k + 0] = task;
+            a.trace[4 * k + 1] = part | ((u64)blockIdx.x << 16);
+            a.trace[4 * k + 2] = tb;
+            a.trace[4 * k + 3] = te;
+          }
         }
-      }
-      fence_rel();
-      if (sub_rlx(a.parts_left + task, 1u) == 1u) {
-        fence_acq();
         fence_rel();
-        for (uint32_t e = a.succ_off[task]; e < a.succ_off[task + 1]; ++e) {
-          const uint32_t s = a.succ[e];
-          if (sub_rlx(a.pending + s, 1u) == 1u) push_task(a, s, home);
+        if (sub_rlx(a.parts_left + task, 1u) == 1u) {
+          fence_acq();
+          fence_rel();
+          for (uint32_t e = a.succ_off[task]; e < a.succ_off[task + 1]; ++e) {
+            const uint32_t s = a.succ[e];
+            if (sub_rlx(a.pending + s, 1u) == 1u) push_task(a, s, home);
+          }
         }
       }
     }
@@ -1172,24 +1202,52 @@ __global__ __launch_bounds__(NT) void unpack_kernel(DevMat m, int64_t n, double*
   }
 }
 
-// Right-hand sides: row-major n x nrhs <-> column-major n_pad x nrhs (zero padding).
+// Right-hand sides: row-major n x nrhs <-> column-major n_pad x nrhs (zero padding),
+// optionally scaling row r by scale[r].
 __global__ void rhs_in_kernel(const double* __restrict__ B, int64_t ldb, int64_t n, int64_t nrhs,
-                              double* __restrict__ y, int64_t n_pad) {
+                              double* __restrict__ y, int64_t n_pad, const double* __restrict__ scale) {
   const int64_t total = n_pad * nrhs;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
     const int64_t q = e / n_pad, r = e % n_pad;
-    y[e] = r < n ? B[r * ldb + q] : 0.0;
+    const double v = r < n ? B[r * ldb + q] : 0.0;
+    y[e] = (scale && r < n) ? v * scale[r] : v;
   }
 }
 __global__ void rhs_out_kernel(const double* __restrict__ y, int64_t n_pad, int64_t n, int64_t nrhs,
-                               double* __restrict__ X, int64_t ldx, int accumulate) {
+                               double* __restrict__ X, int64_t ldx, int accumulate, const double* __restrict__ scale) {
   const int64_t total = n * nrhs;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
     const int64_t r = e / nrhs, q = e % nrhs;
+    const double v = scale ? y[q * n_pad + r] * scale[r] : y[q * n_pad + r];
     if (accumulate)
-      X[r * ldx + q] += y[q * n_pad + r];
+      X[r * ldx + q] += v;
     else
-      X[r * ldx + q] = y[q * n_pad + r];
+      X[r * ldx + q] = v;
+  }
+}
+
+__global__ void diag_scale_kernel(const double* __restrict__ A, int64_t lda, int64_t n, double* __restrict__ d,
+                                  int64_t n_pad) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_pad; i += (int64_t)gridDim.x * blockDim.x)
+    d[i] = i < n ? 1.0 / sqrt(A[i * lda + i]) : 1.0;
+}
+
+// Thread g (of nthr, a multiple of q) sums U .* V over the elements g, g + nthr, ...: all
+// of one column (g mod q).
+__global__ void dot_cols_kernel(int64_t total, int64_t nthr, const double* __restrict__ U,
+                                const double* __restrict__ V, double* __restrict__ partial) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= nthr) return;
+  double acc = 0.0;
+  for (int64_t e = g; e < total; e += nthr) acc += U[e] * V[e];
+  partial[g] = acc;
+}
+
+__global__ void axpy_cols_kernel(int64_t total, int64_t q, const double* __restrict__ alpha,
+                                 const double* __restrict__ X, double* __restrict__ Y, int mode) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const double a = alpha[e % q];
+    Y[e] = mode == 0 ? Y[e] + a * X[e] : X[e] + a * Y[e];
   }
 }
 
@@ -1321,15 +1379,37 @@ int launch_unpack(const DevMat& m, int64_t n, double* dL, int64_t ldl, void* str
   return hip_ok(hipGetLastError(), "unpack_kernel");
 }
 
-int launch_rhs_in(const double* dB, int64_t ldb, int64_t n, int64_t nrhs, double* rhs, int64_t n_pad, void* stream) {
-  hipLaunchKernelGGL(rhs_in_kernel, dim3(1024), dim3(NT), 0, (hipStream_t)stream, dB, ldb, n, nrhs, rhs, n_pad);
+int launch_rhs_in(const double* dB, int64_t ldb, int64_t n, int64_t nrhs, double* rhs, int64_t n_pad,
+                  const double* scale, void* stream) {
+  hipLaunchKernelGGL(rhs_in_kernel, dim3(1024), dim3(NT), 0, (hipStream_t)stream, dB, ldb, n, nrhs, rhs, n_pad, scale);
   return hip_ok(hipGetLastError(), "rhs_in_kernel");
 }
 
+int launch_diag_scale(const double* dA, int64_t lda, int64_t n, double* d, int64_t n_pad, void* stream) {
+  hipLaunchKernelGGL(diag_scale_kernel, dim3(256), dim3(NT), 0, (hipStream_t)stream, dA, lda, n, d, n_pad);
+  return hip_ok(hipGetLastError(), "diag_scale_kernel");
+}
+
+int launch_dot_cols(int64_t n, int64_t q, const double* U, const double* V, double* partial, int* nthreads,
+                    void* stream) {
+  const int64_t cap = 256 * NT;
+  if (q < 1 || q > cap) return fail(SPX_EINVAL, "dot_cols: too many columns");
+  const int64_t nthr = (cap / q) * q;
+  *nthreads = (int)nthr;
+  hipLaunchKernelGGL(dot_cols_kernel, dim3((unsigned)((nthr + NT - 1) / NT)), dim3(NT), 0, (hipStream_t)stream,
+                     n * q, nthr, U, V, partial);
+  return hip_ok(hipGetLastError(), "dot_cols_kernel");
+}
+
+int launch_axpy_cols(int64_t n, int64_t q, const double* alpha, const double* X, double* Y, int mode, void* stream) {
+  hipLaunchKernelGGL(axpy_cols_kernel, dim3(1024), dim3(NT), 0, (hipStream_t)stream, n * q, q, alpha, X, Y, mode);
+  return hip_ok(hipGetLastError(), "axpy_cols_kernel");
+}
+
 int launch_rhs_out(const double* rhs, int64_t n_pad, int64_t n, int64_t nrhs, double* dX, int64_t ldx, int accumulate,
-                   void* stream) {
+                   const double* scale, void* stream) {
   hipLaunchKernelGGL(rhs_out_kernel, dim3(1024), dim3(NT), 0, (hipStream_t)stream, rhs, n_pad, n, nrhs, dX, ldx,
-                     accumulate);
+                     accumulate, scale);
   return hip_ok(hipGetLastError(), "rhs_out_kernel");
 }
 

@@ -19,7 +19,7 @@ TASK_NAMES = ["POTRF", "TRSM", "SYRK", "GEMM", "FTRSM", "FGEMM", "BTRSM", "BGEMM
 TILE_CANDIDATES = [32, 64, 128, 256, 512]
 PREC_FP64, PREC_FP32, PREC_BF16 = 0, 1, 2
 Q_PRIORITY, Q_FIFO = 0, 1
-F_TRACE = 1
+F_TRACE, F_SCALED = 1, 2
 
 
 class SpxError(RuntimeError):
@@ -40,7 +40,8 @@ class Access(ctypes.Structure):
 
 class Opts(ctypes.Structure):
     _fields_ = [("tile", ctypes.c_int32), ("update_prec", ctypes.c_int32), ("queue_policy", ctypes.c_int32),
-                ("num_wg", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+                ("num_wg", ctypes.c_int32), ("flags", ctypes.c_uint32), ("pad", ctypes.c_int32),
+                ("shift", ctypes.c_double)]
 
 
 class Refine(ctypes.Structure):
@@ -293,13 +294,16 @@ class Context:
             raise ValueError(f"{name} must have unit stride along its last dimension")
         return t
 
-    def potrf(self, A, tile=0, update_prec=PREC_FP64, queue_policy=Q_PRIORITY, num_wg=0, flags=0):
-        """Factors the lower triangle of the SPD matrix A (n x n float64 on the device)."""
+    def potrf(self, A, tile=0, update_prec=PREC_FP64, queue_policy=Q_PRIORITY, num_wg=0, flags=0, shift=None):
+        """Factors the lower triangle of the SPD matrix A (n x n float64 on the device).
+        shift (not None): factor D^-1/2 A D^-1/2 + shift I instead (a preconditioner)."""
         A = self._dev(A, "A")
         n = A.shape[0]
         if A.dim() != 2 or A.shape[1] != n:
             raise ValueError("A must be square")
-        o = Opts(tile, update_prec, queue_policy, num_wg, flags)
+        if shift is not None:
+            flags |= F_SCALED
+        o = Opts(tile, update_prec, queue_policy, num_wg, flags, 0, float(shift or 0.0))
         h = ctypes.c_void_p()
         info = ctypes.c_int64()
         _check(lib().spx_potrf_tiled(self._h, n, _ptr(A), A.stride(0), ctypes.byref(o), ctypes.byref(h),

@@ -113,3 +113,56 @@ def test_refinement_argument_checks(ctx):
     X, st = ctx.potrs(F, Bd, A=Ad, tol=1e-12, method=1, return_stats=True)
     assert st["eta_max"] <= 1e-14 and st["iters"] == 0  # FP64 factor: already converged
     F.close()
+
+
+def test_scaled_shifted_factor_parity(ctx):
+    """SPX_F_SCALED factors D^-1/2 A D^-1/2 + shift I: against the oracle's factor of that
+    matrix formed on the host with the same operation order (1/sqrt of the diagonal, then
+    A_ij d_i d_j, then the shift)."""
+    n, shift = 300, 0.25
+    A, _ = inputs.haar_spd(n, 1e3, seed=21)
+    d = 1.0 / np.sqrt(np.diag(A))
+    As = A * d[:, None] * d[None, :]
+    As[np.diag_indices(n)] += shift
+    Lo, _, info = oracle.cholesky(As, n)
+    assert info == 0
+    F = ctx.potrf(dev(A), tile=64, shift=shift)
+    L = F.L().cpu().numpy()
+    dd = np.sqrt(np.diag(As))
+    assert (np.abs(L - Lo) <= 1e-12 * dd[:, None]).all()
+    F.close()
+
+
+@pytest.mark.parametrize("kappa,shift", [(1e4, 1e-3), (1e6, 1e-2)])
+def test_bf16_scaled_pcg_to_1e12(ctx, kappa, shift):
+    """BF16 updates break down on ill-conditioned inputs; the scaled, shifted BF16 factor
+    as a preconditioner for FP64 conjugate gradients still reaches eta <= 1e-12."""
+    from paper_2308_15964_amd import spx
+
+    n, b, nrhs = 1024, 128, 3
+    print(f"bf16 pcg kappa={kappa}", flush=True)
+    A, B = inputs.haar_spd(n, kappa, seed=31, nrhs=nrhs)
+    _, Xo, _ = oracle.cholesky(A, b, B)
+    Ad, Bd = dev(A), dev(B)
+    F = ctx.potrf(Ad, tile=b, update_prec=spx.PREC_BF16, shift=shift)
+    X, st = ctx.potrs(F, Bd, A=Ad, tol=1e-12, max_iter=400, method=2, return_stats=True)
+    X = X.cpu().numpy()
+    eta = oracle.backward_error(A, X, B)
+    assert eta.max() <= 1e-12 and st["eta_max"] <= 1e-12, (eta, st)
+    assert 1 <= st["iters"] <= 400
+    fwd = np.abs(X - Xo).max(axis=0) / np.abs(Xo).max(axis=0)
+    assert fwd.max() <= kappa * 1e-12
+    F.close()
+
+
+def test_pcg_with_exact_factor_converges_at_once(ctx):
+    A, B = inputs.gram_spd(500, seed=41, nrhs=2)
+    Ad, Bd = dev(A), dev(B)
+    F = ctx.potrf(Ad, tile=128)
+    X, st = ctx.potrs(F, Bd, A=Ad, tol=1e-12, method=2, return_stats=True)
+    assert st["iters"] == 0 and st["eta_max"] <= 1e-14
+    # wide leading dimension of X: the dense work copy is written back
+    Xw = torch.zeros((500, 5), dtype=torch.float64, device="cuda:0")
+    X2 = ctx.potrs(F, Bd, X=Xw[:, :2], A=Ad, tol=1e-12, method=2)
+    assert np.array_equal(X2.cpu().numpy(), X.cpu().numpy())
+    F.close()
