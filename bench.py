@@ -4,10 +4,19 @@ One step = the whole hot path on one synthetic SPD matrix already resident in HB
 the dense matrix into tiles, run the factor task graph (POTRF / TRSM / SYRK / GEMM) in
 one persistent kernel, then run the solve task graph for the right-hand side.
 
-Workload: N = 16384, tile 512 (32 x 32 tiles, 5984 factor tasks), FP64,
+Headline workload: N = 16384, tile 512 (32 x 32 tiles, 5984 factor tasks), FP64,
 A = G G^T / N + I with G iid N(0,1) (seeded), one right-hand side iid N(0,1).
+value = (N^3/3 + 2 N^2 nrhs) flop per step / measured step time.
 
-Prints one JSON line.  value = (N^3/3 + 2 N^2 nrhs) flop per step / measured step time.
+The same JSON line also carries the other measured paths (each skippable):
+  mixed    N = 32768, tile 512, 16 right-hand sides, A = Q diag(s) Q^T with kappa 1e4:
+           plain FP64 vs FP32 updates + FP64 refinement vs BF16 updates (+ refinement,
+           or the scaled, shifted BF16 factor as a PCG preconditioner), each to 1e-12
+  batched  4096 matrices, N uniform in [32, 512], 1-8 right-hand sides, one launch, FP64
+           and FP32 updates, autotuned tiles
+  serving  Poisson stream of SPD solve requests (N log-uniform in [64, 8192], 1-64
+           right-hand sides, kappa log-uniform in [1e1, 1e6]) at 2000 requests/s,
+           plain FP64 vs mixed + refinement: solves/s, p50/p99 latency
 """
 import argparse
 import json
@@ -31,6 +40,14 @@ def parse():
     p.add_argument("--nrhs", type=int, default=1)
     p.add_argument("--seed", type=int, default=2)
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--skip-mixed", action="store_true")
+    p.add_argument("--skip-batched", action="store_true")
+    p.add_argument("--skip-serving", action="store_true")
+    p.add_argument("--mixed-n", type=int, default=32768)
+    p.add_argument("--batch-count", type=int, default=4096)
+    p.add_argument("--serve-requests", type=int, default=4000)
+    p.add_argument("--serve-rate", type=float, default=2000.0)
+    p.add_argument("--serve-lanes", type=int, default=2)
     return p.parse_args()
 
 
@@ -71,6 +88,210 @@ def cpu_baseline(A_host, n, tile):
     return {"value": sample_flop / dt / 1e12, "unit": "TFLOP/s", "cores": cores, "kind": "oracle",
             "sample": f"first block-column step (k=0) of the N={n} tile-{tile} factor graph: {limit} tasks, "
                       f"{sample_flop:.3e} flop, {dt:.1f} s on {cores} host threads"}
+
+
+def orthogonal_spd(n, kappa, seed, nrhs, device, k=16):
+    """A = Q diag(s) Q^T on the device, Q a product of k seeded Householder reflectors
+    (exactly orthogonal; a stand-in for a Haar matrix at sizes where its QR is too
+    costly), s log-uniform on [1, kappa] with both endpoints present; B iid N(0,1)."""
+    import numpy as np
+    import torch
+
+    from paper_2308_15964_amd import inputs
+
+    g = np.random.default_rng(seed)
+    s = inputs.log_spectrum(n, kappa, g)
+    V = torch.from_numpy(inputs.reflectors(n, k, g)).to(device)
+    A = torch.diag(torch.from_numpy(s).to(device))
+    for i in range(k - 1, -1, -1):  # A <- H A H, H = I - 2 v v^T, as two rank-1 updates
+        v = V[:, i]
+        u = A @ v
+        w = 2 * u - 2 * torch.dot(v, u) * v
+        A.addr_(v, w, alpha=-1.0).addr_(w, v, alpha=-1.0)
+    A = ((A + A.T) / 2).contiguous()
+    B = torch.from_numpy(g.standard_normal((n, nrhs))).to(device)
+    torch.cuda.synchronize()
+    return A, B
+
+
+def bench_mixed(ctx, n, tile=512, nrhs=16, kappa=1e4, seed=3):
+    """Time to a 1e-12 backward error for every column: FP64 vs FP32 / BF16 updates."""
+    import torch
+
+    from paper_2308_15964_amd import spx
+
+    A, B = orthogonal_spd(n, kappa, seed, nrhs, "cuda:0")
+    flop = n ** 3 / 3.0
+    res = {"workload": f"N={n}, tile {tile}, {nrhs} RHS, A = Q diag(s) Q^T (Q: 16 Householder reflectors), "
+                       f"s log-uniform on [1, {kappa:g}], tol 1e-12"}
+
+    def run(prec, method, shift=None):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        try:
+            F = ctx.potrf(A, tile=tile, update_prec=prec, shift=shift)
+        except spx.NotPositiveDefinite as e:
+            return {"breakdown_column": int(e.info)}
+        fs = ctx.stats()
+        X, st = ctx.potrs(F, B, A=A, tol=1e-12, max_iter=200, method=method, return_stats=True)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        F.close()
+        eta = float(ctx.backward_error(A, X, B).max())
+        return {"time_ms": round(dt * 1e3, 2), "factor_kernel_ms": round(fs["kernel_ms"], 2),
+                "factor_tflops": round(flop / fs["kernel_ms"] / 1e9, 3), "eff_tflops": round(flop / dt / 1e12, 3),
+                "iters": st["iters"], "method": ["none", "IR", "PCG"][st["method_used"]], "eta_max": eta,
+                "converged": eta <= 1e-12}
+
+    run(0, 1)  # warm-up (image build, allocator)
+    res["fp64"] = run(0, 1)
+    res["fp32_ir"] = run(1, 1)
+    r = run(2, 1)
+    if r.get("converged"):
+        res["bf16"] = dict(r, note="BF16 updates + classical refinement")
+    else:
+        res["bf16_plain"] = r
+        for theta in (1e-3, 1e-2, 1e-1):  # shift escalated x10 until the PCG converges
+            r = run(2, 2, shift=theta)
+            if r.get("converged"):
+                break
+        res["bf16"] = dict(r, note=f"scaled BF16 factor of D^-1/2 A D^-1/2 + {theta:g} I as FP64 PCG "
+                                   f"preconditioner")
+    for k in ("fp32_ir", "bf16"):
+        if res[k].get("time_ms") and res["fp64"].get("time_ms"):
+            res[k]["speedup_vs_fp64"] = round(res["fp64"]["time_ms"] / res[k]["time_ms"], 3)
+    del A, B
+    torch.cuda.empty_cache()
+    return res
+
+
+def bench_batched(ctx, count, seed=7):
+    """4096 independent systems in one persistent launch, tiles from the autotuner."""
+    import numpy as np
+    import torch
+
+    from paper_2308_15964_amd import autotune, inputs, spx
+
+    ns, qs = inputs.batch_sizes(count, seed=seed)
+    As, Bs = [], []
+    for m, (n, q) in enumerate(zip(ns, qs)):
+        G, B = inputs.gram_factor_G(int(n), seed=seed * 100000 + m, nrhs=int(q))
+        Gd = torch.from_numpy(G).cuda()
+        A = Gd @ Gd.T.contiguous() / int(n)
+        A.diagonal().add_(1.0)
+        As.append(A)
+        Bs.append(torch.from_numpy(B).cuda())
+    torch.cuda.synchronize()
+    nf = ns.astype(np.float64)
+    flop = float((nf ** 3 / 3 + 2 * nf ** 2 * qs).sum())
+    bytes_min = float((2 * nf ** 2 * 8).sum())  # read the lower A, write L (both at least once)
+    t_floor = max(flop / (PEAK_FP64_TFLOPS * 1e12), bytes_min / 8e12)
+    cache = os.path.join(os.environ.get("XDG_CACHE_HOME", os.path.expanduser("~/.cache")), "spx_tiles.json")
+    os.makedirs(os.path.dirname(cache), exist_ok=True)
+    res = {"workload": f"{count} matrices, N uniform in [32, 512], 1-8 RHS, A = G G^T/N + I, one launch",
+           "sum_flop": flop, "sum_bytes_min": bytes_min}
+    for prec, name in ((spx.PREC_FP64, "fp64"), (spx.PREC_FP32, "fp32_updates")):
+        entry = autotune.ensure(ctx, prec, cache)
+        Xs, info = ctx.posv_batched(As, Bs, update_prec=prec)
+        kms = []
+        for _ in range(3):
+            Xs, info = ctx.posv_batched(As, Bs, update_prec=prec, Xs=Xs)
+            kms.append(ctx.stats()["kernel_ms"])
+        st = ctx.stats()
+        eta = ctx.backward_error_batched(As, Xs, Bs)
+        km = float(np.median(kms))
+        res[name] = {"kernel_ms": round(km, 3), "tflops": round(flop / km / 1e9, 3),
+                     "frac_of_max_flop_or_hbm_bound": round(t_floor * 1e3 / km, 4),
+                     "idle_frac": round(st["idle_frac"], 4), "ntasks": st["ntasks"],
+                     "failed": int((info != 0).sum()), "eta_max": float(eta.max()),
+                     "tile_table": entry["table"]}
+    del As, Bs
+    torch.cuda.empty_cache()
+    return res
+
+
+def bench_serving(ctx, count, rate, lanes, seed=8):
+    """Poisson request stream through the serving loop, plain FP64 vs mixed + IR.
+    Inputs are device-resident: request i uses the leading N x N block of a seeded
+    8192 x 8192 master matrix of its condition-number bucket (12 buckets, log-spaced over
+    [1e1, 1e6]; eigenvalues 1 and kappa placed first so every leading block keeps both),
+    and the leading N x nrhs block of one right-hand-side master.  Latency = result in
+    device memory - scheduled arrival."""
+    import math
+
+    import numpy as np
+    import torch
+
+    from paper_2308_15964_amd import inputs, spx
+
+    NMAX, QMAX, NB = 8192, 64, 12
+    dev = "cuda:0"
+    kap = np.exp(np.linspace(math.log(1e1), math.log(1e6), NB))
+    g = np.random.default_rng(seed * 7919)
+    masters = []
+    for k in kap:
+        s = np.exp(g.uniform(0.0, math.log(k), NMAX))
+        s[0], s[1] = 1.0, k
+        V = torch.from_numpy(inputs.reflectors(NMAX, 8, g)).to(dev)
+        A = torch.diag(torch.from_numpy(s).to(dev))
+        for i in range(7, -1, -1):
+            v = V[:, i]
+            u = A @ v
+            w = 2 * u - 2 * torch.dot(v, u) * v
+            A.addr_(v, w, alpha=-1.0).addr_(w, v, alpha=-1.0)
+        masters.append(((A + A.T) / 2).contiguous())
+    Bm = torch.from_numpy(g.standard_normal((NMAX, QMAX))).to(dev)
+    st = inputs.request_stream(count=count, rate=rate, seed=seed)
+    ns, qs, ks = st["n"], st["nrhs"], st["kappa"]
+    lk = (np.log(ks) - math.log(1e1)) / (math.log(1e6) - math.log(1e1)) * (NB - 1)
+    bucket = np.clip(np.rint(lk).astype(int), 0, NB - 1)
+    nf = ns.astype(np.float64)
+    flop = float((nf ** 3 / 3 + 2 * nf ** 2 * qs).sum())
+    res = {"workload": f"{count} requests at {rate:g}/s (Poisson), N log-uniform in [64, 8192], 1-64 RHS, "
+                       f"kappa log-uniform in [1e1, 1e6], 200 GB budget, {lanes} lanes", "sum_flop": flop}
+    for mode, name in ((spx.MODE_FP64, "fp64"), (spx.MODE_MIXED, "mixed_ir")):
+        Xs = [torch.empty((int(n), int(q)), dtype=torch.float64, device=dev) for n, q in zip(ns, qs)]
+        torch.cuda.synchronize()
+        srv = spx.Server(ctx, 200 << 30, lanes=lanes)
+        for n in (64, 512, 2048, 8192):  # warm-up: graph images and pool memory
+            X = torch.empty((n, 4), dtype=torch.float64, device=dev)
+            srv.wait(srv.submit(masters[0][:n, :n], Bm[:n, :4], X, mode=mode))
+        t0 = time.perf_counter()
+        s0 = srv.now()
+        pend, out, lag = {}, [None] * count, np.zeros(count)
+        i = 0
+        while i < count or pend:
+            now = time.perf_counter() - t0
+            while i < count and st["t"][i] <= now:
+                n, q = int(ns[i]), int(qs[i])
+                tk = srv.submit(masters[bucket[i]][:n, :n], Bm[:n, :q], Xs[i], mode=mode, tol=1e-12, tag=i)
+                lag[i] = (time.perf_counter() - t0) - st["t"][i]
+                pend[tk] = i
+                i += 1
+            for tk in list(pend):
+                r = srv.poll(tk)
+                if r is not None:
+                    out[pend.pop(tk)] = r
+            time.sleep(0.0002)
+        lat = np.array([r["t_done"] - r["t_submit"] for r in out]) + lag
+        span = max(r["t_done"] for r in out) - s0
+        sst = srv.stats()
+        srv.close()
+        res[name] = {"solves_per_s": round(count / span, 2), "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 2),
+                     "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 2), "makespan_s": round(span, 3),
+                     "eff_tflops": round(flop / span / 1e12, 3),
+                     "eta_max": float(max(r["eta_max"] for r in out)),
+                     "failed": sum(1 for r in out if r["status"] != 0 or r["info"] != 0),
+                     "fp64_fallbacks": sum(1 for r in out if mode == spx.MODE_MIXED and r["method_used"] == 0),
+                     "mean_batch": round(float(np.mean([r["batch_size"] for r in out])), 1),
+                     "launches": sst["launches"], "max_running": sst["max_running"],
+                     "peak_gib": round(sst["bytes_peak"] / 2 ** 30, 2)}
+        del Xs
+    if res["fp64"]["solves_per_s"]:
+        res["mixed_vs_fp64_solves_per_s"] = round(res["mixed_ir"]["solves_per_s"] / res["fp64"]["solves_per_s"], 3)
+    del masters, Bm
+    torch.cuda.empty_cache()
+    return res
 
 
 def main():
@@ -145,6 +366,19 @@ def main():
     if not args.no_cpu_baseline:
         A_host = A.cpu().numpy()
         out["cpu_baseline"] = cpu_baseline(A_host, n, b)
+        del A_host
+    del A, B, X
+    torch.cuda.empty_cache()
+    if not args.skip_mixed:
+        print("bench: mixed precision", file=sys.stderr, flush=True)
+        out["mixed"] = bench_mixed(ctx, args.mixed_n)
+    if not args.skip_batched:
+        print("bench: batched", file=sys.stderr, flush=True)
+        out["batched"] = bench_batched(ctx, args.batch_count)
+    if not args.skip_serving:
+        print("bench: serving", file=sys.stderr, flush=True)
+        out["serving"] = bench_serving(ctx, args.serve_requests, args.serve_rate, args.serve_lanes)
+    ctx.close()
     print(json.dumps(out), flush=True)
 
 

@@ -175,7 +175,7 @@ void io_program(int nt, bool with_solve, std::vector<TaskDesc>& tasks, std::vect
   acc.clear();
   TaskDesc load;
   load.type = SPX_T_LOAD;
-  load.i = (uint16_t)nt;  // one part per tile row (plus one for the right-hand sides)
+  load.i = (uint16_t)nt;  // parts: one per lower tile (plus one for the right-hand sides)
   tasks.push_back(load);
   for (int i = 0; i < nt; ++i)
     for (int j = 0; j <= i; ++j) acc.push_back(spx_access{0, SPX_ACC_RW, A(i, j)});
@@ -214,8 +214,9 @@ void solve_io_program(int nt, std::vector<TaskDesc>& tasks, std::vector<spx_acce
 }
 
 // Default Cholesky priorities (larger = sooner): the panel chain POTRF -> TRSM -> SYRK and
-// the GEMMs that feed the next block column sit on the critical path; among equals the
-// earlier step k goes first.
+// the GEMMs that feed the next block column sit on the critical path, as do the diagonal
+// solves and the update of the next block in the substitution; among equals the earlier
+// step k goes first.
 int32_t cholesky_priority(const TaskDesc& d, int nt) {
   int32_t base;
   switch (d.type) {
@@ -225,6 +226,11 @@ int32_t cholesky_priority(const TaskDesc& d, int nt) {
     case SPX_T_GEMM: base = (d.j == d.k + 1) ? 2 : 0; break;
     case SPX_T_LOAD: base = 0; break;   // a new matrix starts when nothing urgent is ready
     case SPX_T_STORE: base = 4; break;
+    // substitution: the diagonal solves and the update of the next block form the chain
+    case SPX_T_FTRSM:
+    case SPX_T_BTRSM: base = 4; break;
+    case SPX_T_FGEMM: base = (d.i == d.k + 1) ? 3 : 1; break;
+    case SPX_T_BGEMM: base = (d.i + 1 == d.k) ? 3 : 1; break;
     default: base = 3; break;
   }
   return base * 65536 + (nt - d.k);

@@ -197,7 +197,11 @@ uint16_t parts_of(const TaskDesc& d, int b, int nrhs) {
     case SPX_T_BTRSM: return (uint16_t)((nrhs + 7) / 8);
     case SPX_T_FGEMM:
     case SPX_T_BGEMM: return (uint16_t)(b / rows);
-    case SPX_T_LOAD: return (uint16_t)(d.i + (nrhs > 0 ? 1 : 0));
+    case SPX_T_LOAD: {
+      if (d.j) return 1;  // right-hand sides only
+      const int ntiles = d.i * (d.i + 1) / 2;
+      return (uint16_t)((ntiles <= kLoadTileParts ? ntiles : d.i) + (nrhs > 0 ? 1 : 0));
+    }
     case SPX_T_STORE: return 1;
   }
   return 1;

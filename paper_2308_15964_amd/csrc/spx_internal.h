@@ -72,6 +72,8 @@ struct DevMat {
   int64_t lda, ldb, ldx;
 };
 
+// A LOAD task has one part per lower tile while they fit the 16-bit part index.
+constexpr int kLoadTileParts = 65534;
 constexpr int kMaxLevels = 4;
 constexpr int kShards = 8;          // ready queues per priority level (one per XCD-sized group of workgroups)
 constexpr int kCounterStride = 32;  // 128-byte spacing of hot counters (uint32 units)

@@ -609,83 +609,147 @@ __device__ void tile_inverses(const double* __restrict__ l, int b, double* __res
 // Solve tasks on the right-hand side y (column-major, ld = n_pad), columns [q0, q0+nq).
 // ---------------------------------------------------------------------------------------
 
-// Forward: y_k <- L_kk^{-1} y_k for the columns [q0, q0+nq) (nq <= 8), block by block:
-// the 32-row block is multiplied by its diagonal inverse (thread (q, r) computes row r of
-// column q), then every thread updates rows below the block with the 32 solved values.
+// Forward substitution of one diagonal tile for up to 8 right-hand sides: y_k <- L_kk^{-1}
+// y_k, block by block (32 rows) with the inverted 32x32 diagonal blocks: y_blk <- Li y_blk,
+// then the rows below lose L(rows, blk) y_blk.  The whole block of right-hand sides stays in
+// LDS; thread t owns rows t and t + 256 of the trailing update, whose L strip for the next
+// block is loaded into registers while the current block is solved, and the next block
+// inverse is loaded into the other half of a double buffer.  Only the block-inverse
+// products change the arithmetic order relative to a substitution.
 __device__ void ftrsm_part(const double* __restrict__ l, const double* __restrict__ dinv, int b,
                            double* __restrict__ y, int64_t ldy, int q0, int nq, double* __restrict__ lds) {
   const int tid = threadIdx.x;
-  double* Li = lds;          // 32x32 block inverse
-  double* yo = lds + 1024;   // [8][32] block values before the multiply
-  double* yb = lds + 1280;   // [8][32] solved block values
+  double* ys = lds;            // [8][b] right-hand sides
+  double* Lb = lds + 8 * 512;  // two 32x32 block inverses
+  double* yb = Lb + 2048;      // [8][32] the block just solved
   const int q = tid >> 5, r = tid & 31;
-  for (int c0 = 0; c0 < b; c0 += 32) {
-    for (int e = tid; e < 1024; e += NT) Li[e] = dinv[(size_t)c0 * 32 + e];
-    if (q < nq) yo[q * 32 + r] = y[(size_t)(q0 + q) * ldy + c0 + r];
-    __syncthreads();
-    if (q < nq) {
-      double s = 0.0;
-      for (int c = 0; c <= r; ++c) s += Li[c * 32 + r] * yo[q * 32 + c];
-      yb[q * 32 + r] = s;
-      y[(size_t)(q0 + q) * ldy + c0 + r] = s;
-    }
-    __syncthreads();
-    for (int rr = c0 + 32 + tid; rr < b; rr += NT) {
-      double acc[8];
+  for (int e = tid; e < 8 * b; e += NT) {
+    const int qq = e / b, m = e % b;
+    ys[e] = qq < nq ? y[(size_t)(q0 + qq) * ldy + m] : 0.0;
+  }
+  for (int e = tid; e < 1024; e += NT) Lb[e] = dinv[e];
+  double lv[2][32];
+  auto load_strip = [&](int c0) {
 #pragma unroll
-      for (int u = 0; u < 8; ++u) acc[u] = 0.0;
-#pragma unroll 8
-      for (int c = 0; c < 32; ++c) {
-        const double lv = l[(size_t)(c0 + c) * b + rr];
+    for (int j = 0; j < 2; ++j) {
+      const int row = tid + NT * j;
+      if (row >= c0 + 32 && row < b) {
 #pragma unroll
-        for (int u = 0; u < 8; ++u) acc[u] += lv * yb[u * 32 + c];
+        for (int c = 0; c < 32; ++c) lv[j][c] = l[(size_t)(c0 + c) * b + row];
       }
-      for (int u = 0; u < nq; ++u) y[(size_t)(q0 + u) * ldy + rr] -= acc[u];
+    }
+  };
+  load_strip(0);
+  int buf = 0;
+  for (int c0 = 0; c0 < b; c0 += 32) {
+    __syncthreads();  // block c0 of ys and the inverse in Lb[buf] are ready
+    if (c0 + 32 < b)
+      for (int e = tid; e < 1024; e += NT) Lb[(buf ^ 1) * 1024 + e] = dinv[(size_t)(c0 + 32) * 32 + e];
+    const double* Li = Lb + buf * 1024;
+    if (q < nq) {
+      double sacc = 0.0;
+      for (int c = 0; c <= r; ++c) sacc += Li[c * 32 + r] * ys[q * b + c0 + c];
+      yb[q * 32 + r] = sacc;
     }
     __syncthreads();
+    if (q < nq) ys[q * b + c0 + r] = yb[q * 32 + r];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int row = tid + NT * j;
+      if (row >= c0 + 32 && row < b) {
+        double acc[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc[u] = 0.0;
+#pragma unroll
+        for (int c = 0; c < 32; ++c)
+#pragma unroll
+          for (int u = 0; u < 8; ++u) acc[u] += lv[j][c] * yb[u * 32 + c];
+        for (int u = 0; u < nq; ++u) ys[u * b + row] -= acc[u];
+      }
+    }
+    if (c0 + 32 < b) load_strip(c0 + 32);
+    buf ^= 1;
+  }
+  __syncthreads();
+  for (int e = tid; e < nq * b; e += NT) {
+    const int qq = e / b, m = e % b;
+    y[(size_t)(q0 + qq) * ldy + m] = ys[e];
   }
 }
 
 // Backward: y_k <- L_kk^{-T} y_k, blocks from the last one down: x_blk = Li^T y_blk, then
-// rows above the block are updated with L(c0+c, r) (column r of L, contiguous).
+// the rows above lose L(blk, rows)^T x_blk.  Row t's strip L(c0 .. c0+31, t) is contiguous
+// (column t of the tile); otherwise as the forward substitution.
 __device__ void btrsm_part(const double* __restrict__ l, const double* __restrict__ dinv, int b,
                            double* __restrict__ y, int64_t ldy, int q0, int nq, double* __restrict__ lds) {
   const int tid = threadIdx.x;
-  double* Li = lds;
-  double* yo = lds + 1024;
-  double* xb = lds + 1280;
+  double* ys = lds;
+  double* Lb = lds + 8 * 512;
+  double* yb = Lb + 2048;
   const int q = tid >> 5, r = tid & 31;
-  for (int c0 = b - 32; c0 >= 0; c0 -= 32) {
-    for (int e = tid; e < 1024; e += NT) Li[e] = dinv[(size_t)c0 * 32 + e];
-    if (q < nq) yo[q * 32 + r] = y[(size_t)(q0 + q) * ldy + c0 + r];
-    __syncthreads();
-    if (q < nq) {
-      double s = 0.0;
-      for (int c = r; c < 32; ++c) s += Li[r * 32 + c] * yo[q * 32 + c];  // Li(c, r)
-      xb[q * 32 + r] = s;
-      y[(size_t)(q0 + q) * ldy + c0 + r] = s;
-    }
-    __syncthreads();
-    for (int rr = tid; rr < c0; rr += NT) {
-      const double* lc = l + (size_t)rr * b + c0;
-      double acc[8];
+  for (int e = tid; e < 8 * b; e += NT) {
+    const int qq = e / b, m = e % b;
+    ys[e] = qq < nq ? y[(size_t)(q0 + qq) * ldy + m] : 0.0;
+  }
+  for (int e = tid; e < 1024; e += NT) Lb[e] = dinv[(size_t)(b - 32) * 32 + e];
+  double lv[2][32];
+  auto load_strip = [&](int c0) {
 #pragma unroll
-      for (int u = 0; u < 8; ++u) acc[u] = 0.0;
-#pragma unroll 8
-      for (int c = 0; c < 32; ++c) {
-        const double lv = lc[c];
+    for (int j = 0; j < 2; ++j) {
+      const int row = tid + NT * j;
+      if (row < c0) {
+        const double2* src = reinterpret_cast<const double2*>(l + (size_t)row * b + c0);
 #pragma unroll
-        for (int u = 0; u < 8; ++u) acc[u] += lv * xb[u * 32 + c];
+        for (int c = 0; c < 16; ++c) {
+          const double2 v = src[c];
+          lv[j][2 * c] = v.x;
+          lv[j][2 * c + 1] = v.y;
+        }
       }
-      for (int u = 0; u < nq; ++u) y[(size_t)(q0 + u) * ldy + rr] -= acc[u];
+    }
+  };
+  load_strip(b - 32);
+  int buf = 0;
+  for (int c0 = b - 32; c0 >= 0; c0 -= 32) {
+    __syncthreads();
+    if (c0 > 0)
+      for (int e = tid; e < 1024; e += NT) Lb[(buf ^ 1) * 1024 + e] = dinv[(size_t)(c0 - 32) * 32 + e];
+    const double* Li = Lb + buf * 1024;
+    if (q < nq) {
+      double sacc = 0.0;
+      for (int c = r; c < 32; ++c) sacc += Li[r * 32 + c] * ys[q * b + c0 + c];  // Li(c, r)
+      yb[q * 32 + r] = sacc;
     }
     __syncthreads();
+    if (q < nq) ys[q * b + c0 + r] = yb[q * 32 + r];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int row = tid + NT * j;
+      if (row < c0) {
+        double acc[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc[u] = 0.0;
+#pragma unroll
+        for (int c = 0; c < 32; ++c)
+#pragma unroll
+          for (int u = 0; u < 8; ++u) acc[u] += lv[j][c] * yb[u * 32 + c];
+        for (int u = 0; u < nq; ++u) ys[u * b + row] -= acc[u];
+      }
+    }
+    if (c0 > 0) load_strip(c0 - 32);
+    buf ^= 1;
+  }
+  __syncthreads();
+  for (int e = tid; e < nq * b; e += NT) {
+    const int qq = e / b, m = e % b;
+    y[(size_t)(q0 + qq) * ldy + m] = ys[e];
   }
 }
 
 // Forward update, rows [r0, r0+rows) of block i: y_i -= L_ik y_k.  y_k (8 columns at a
-// time) is staged in LDS; wave w sums over m in its quarter of the block, eight loads of
-// 64 contiguous doubles in flight, and the four partial sums are added through LDS.
+// time) is staged in LDS; wave w sums over m in its quarter of the block (lane = row, 16
+// loads of 64 contiguous doubles in flight), the four partial sums are added through LDS,
+// and each row's old values are all read before any is written back.
 __device__ void fgemm_part(const double* __restrict__ l, int b, double* __restrict__ yi,
                            const double* __restrict__ yk, int64_t ldy, int nrhs, int r0, int rows,
                            double* __restrict__ lds) {
@@ -705,7 +769,7 @@ __device__ void fgemm_part(const double* __restrict__ l, int b, double* __restri
 #pragma unroll
     for (int q = 0; q < 8; ++q) acc[q] = 0.0;
     if (lane < rows) {
-#pragma unroll 8
+#pragma unroll 16
       for (int m = wave * mq; m < (wave + 1) * mq; ++m) {
         const double lv = l[(size_t)m * b + r0 + lane];
 #pragma unroll
@@ -716,23 +780,31 @@ __device__ void fgemm_part(const double* __restrict__ l, int b, double* __restri
     for (int q = 0; q < 8; ++q) part[(wave * 8 + q) * 64 + lane] = acc[q];
     __syncthreads();
     if (wave == 0 && lane < rows) {
-      for (int q = 0; q < nq; ++q) {
-        const double s = part[(0 * 8 + q) * 64 + lane] + part[(1 * 8 + q) * 64 + lane] +
-                         part[(2 * 8 + q) * 64 + lane] + part[(3 * 8 + q) * 64 + lane];
-        yi[(size_t)(q0 + q) * ldy + r0 + lane] -= s;
+      double old[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) old[q] = q < nq ? yi[(size_t)(q0 + q) * ldy + r0 + lane] : 0.0;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const double sum = part[(0 * 8 + q) * 64 + lane] + part[(1 * 8 + q) * 64 + lane] +
+                           part[(2 * 8 + q) * 64 + lane] + part[(3 * 8 + q) * 64 + lane];
+        if (q < nq) yi[(size_t)(q0 + q) * ldy + r0 + lane] = old[q] - sum;
       }
     }
   }
 }
 
-// Backward update, rows [r0, r0+rows) of block i (i < k): y_i -= L_ki^T y_k.  Column r of
-// L_ki is contiguous: each wave reduces four columns at once (lane-strided coalesced loads,
-// then a wave reduction), with y_k staged in LDS.
+// Backward update, rows [r0, r0+rows) of block i (i < k): y_i -= L_ki^T y_k.  Output row r
+// is the dot product of column r of L_ki (contiguous) with y_k: lane = row, wave w sums
+// its quarter of the column with 32-byte loads (the other lanes' rows are 4 KiB away, so
+// each lane streams its own cache lines), y_k staged in LDS and read by all lanes at the
+// same index; the quarters are added through LDS as in the forward update.
 __device__ void bgemm_part(const double* __restrict__ l, int b, double* __restrict__ yi,
                            const double* __restrict__ yk, int64_t ldy, int nrhs, int r0, int rows,
                            double* __restrict__ lds) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  double* ys = lds;  // [8][b]
+  double* ys = lds;              // [8][b]
+  double* part = lds + 8 * 512;  // [4][8][64]
+  const int mq = b / 4;
   for (int q0 = 0; q0 < nrhs; q0 += 8) {
     const int nq = (nrhs - q0) < 8 ? (nrhs - q0) : 8;
     __syncthreads();
@@ -741,29 +813,32 @@ __device__ void bgemm_part(const double* __restrict__ l, int b, double* __restri
       ys[e] = q < nq ? yk[(size_t)(q0 + q) * ldy + m] : 0.0;
     }
     __syncthreads();
-    for (int rr = 4 * wave; rr < rows; rr += 16) {  // rows rr..rr+3 (rows is a multiple of 16 or 32)
-      double acc[4][8];
+    double acc[8];
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int q = 0; q < 8; ++q) acc[u][q] = 0.0;
-      for (int m = lane; m < b; m += 64) {
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const double lv = l[(size_t)(r0 + rr + u) * b + m];
-#pragma unroll
-          for (int q = 0; q < 8; ++q) acc[u][q] += lv * ys[q * b + m];
-        }
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
+    for (int q = 0; q < 8; ++q) acc[q] = 0.0;
+    if (lane < rows) {
+      const double4* col = reinterpret_cast<const double4*>(l + (size_t)(r0 + lane) * b + wave * mq);
+#pragma unroll 8
+      for (int m4 = 0; m4 < mq / 4; ++m4) {
+        const double4 v = col[m4];
+        const int m = wave * mq + 4 * m4;
 #pragma unroll
         for (int q = 0; q < 8; ++q)
+          acc[q] += v.x * ys[q * b + m] + v.y * ys[q * b + m + 1] + v.z * ys[q * b + m + 2] + v.w * ys[q * b + m + 3];
+      }
+    }
 #pragma unroll
-          for (int off = 32; off >= 1; off >>= 1) acc[u][q] += __shfl_xor(acc[u][q], off);
-      if (lane == 0) {
-        for (int u = 0; u < 4; ++u)
-          for (int q = 0; q < nq; ++q) yi[(size_t)(q0 + q) * ldy + r0 + rr + u] -= acc[u][q];
+    for (int q = 0; q < 8; ++q) part[(wave * 8 + q) * 64 + lane] = acc[q];
+    __syncthreads();
+    if (wave == 0 && lane < rows) {
+      double old[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) old[q] = q < nq ? yi[(size_t)(q0 + q) * ldy + r0 + lane] : 0.0;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const double sum = part[(0 * 8 + q) * 64 + lane] + part[(1 * 8 + q) * 64 + lane] +
+                           part[(2 * 8 + q) * 64 + lane] + part[(3 * 8 + q) * 64 + lane];
+        if (q < nq) yi[(size_t)(q0 + q) * ldy + r0 + lane] = old[q] - sum;
       }
     }
   }
@@ -885,11 +960,22 @@ __device__ void run_part(const SchedArgs& a, uint32_t task, uint32_t part, doubl
       break;
     }
     case SPX_T_LOAD: {
-      if (d.j == 0 && (int)part < m.nt) {
-        // tile row `part`: every tile (part, tj), tj <= part, in S x S sub-blocks
+      // one part per lower tile (per tile row if the tiles outnumber the part index), then
+      // one for the right-hand sides
+      const int ntiles = m.nt * (m.nt + 1) / 2;
+      const bool per_tile = ntiles <= kLoadTileParts;
+      const int ndata = per_tile ? ntiles : m.nt;
+      if (d.j == 0 && (int)part < ndata) {
         const int S = b < 64 ? b : 64, per = b / S;
-        for (int tj = 0; tj <= (int)part; ++tj)
-          for (int q = 0; q < per * per; ++q) pack_block(m.A, m.lda, m.n, m, part, tj, q / per, q % per, S, lds);
+        int ti = (int)part, tj0 = 0, tj1 = (int)part;  // a tile row
+        if (per_tile) {
+          ti = (int)((sqrt(8.0 * part + 1.0) - 1.0) * 0.5);
+          while (ti * (ti + 1) / 2 > (int)part) --ti;
+          while ((ti + 1) * (ti + 2) / 2 <= (int)part) ++ti;
+          tj0 = tj1 = (int)part - ti * (ti + 1) / 2;
+        }
+        for (int tj = tj0; tj <= tj1; ++tj)
+          for (int q = 0; q < per * per; ++q) pack_block(m.A, m.lda, m.n, m, ti, tj, q / per, q % per, S, lds);
       } else {
         const int64_t total = m.n_pad * m.nrhs;
         for (int64_t e = threadIdx.x; e < total; e += NT) {
