@@ -769,11 +769,16 @@ __device__ void fgemm_part(const double* __restrict__ l, int b, double* __restri
 #pragma unroll
     for (int q = 0; q < 8; ++q) acc[q] = 0.0;
     if (lane < rows) {
+      if (nq == 1) {
+#pragma unroll 32
+        for (int m = wave * mq; m < (wave + 1) * mq; ++m) acc[0] += l[(size_t)m * b + r0 + lane] * ys[m];
+      } else {
 #pragma unroll 16
-      for (int m = wave * mq; m < (wave + 1) * mq; ++m) {
-        const double lv = l[(size_t)m * b + r0 + lane];
+        for (int m = wave * mq; m < (wave + 1) * mq; ++m) {
+          const double lv = l[(size_t)m * b + r0 + lane];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) acc[q] += lv * ys[q * b + m];
+          for (int q = 0; q < 8; ++q) acc[q] += lv * ys[q * b + m];
+        }
       }
     }
 #pragma unroll
@@ -818,13 +823,23 @@ __device__ void bgemm_part(const double* __restrict__ l, int b, double* __restri
     for (int q = 0; q < 8; ++q) acc[q] = 0.0;
     if (lane < rows) {
       const double4* col = reinterpret_cast<const double4*>(l + (size_t)(r0 + lane) * b + wave * mq);
+      if (nq == 1) {
+#pragma unroll 16
+        for (int m4 = 0; m4 < mq / 4; ++m4) {
+          const double4 v = col[m4];
+          const int m = wave * mq + 4 * m4;
+          acc[0] += v.x * ys[m] + v.y * ys[m + 1] + v.z * ys[m + 2] + v.w * ys[m + 3];
+        }
+      } else {
 #pragma unroll 8
-      for (int m4 = 0; m4 < mq / 4; ++m4) {
-        const double4 v = col[m4];
-        const int m = wave * mq + 4 * m4;
+        for (int m4 = 0; m4 < mq / 4; ++m4) {
+          const double4 v = col[m4];
+          const int m = wave * mq + 4 * m4;
 #pragma unroll
-        for (int q = 0; q < 8; ++q)
-          acc[q] += v.x * ys[q * b + m] + v.y * ys[q * b + m + 1] + v.z * ys[q * b + m + 2] + v.w * ys[q * b + m + 3];
+          for (int q = 0; q < 8; ++q)
+            acc[q] += v.x * ys[q * b + m] + v.y * ys[q * b + m + 1] + v.z * ys[q * b + m + 2] +
+                      v.w * ys[q * b + m + 3];
+        }
       }
     }
 #pragma unroll
