@@ -103,13 +103,18 @@ void spx_graph_destroy(spx_graph* g);
  * backward substitution) inserts for nt x nt tiles, built with spx_graph_build: right-
  * looking, lower triangle; for k: POTRF(k); TRSM(i,k) i>k; SYRK(i,k) and GEMM(i,j,k)
  * k<j<i.  with_solve bit 1 adds the LOAD task in front (and, with bit 0, STORE at the end)
- * as the batched calls run it.  Datum ids: tile (i,j) -> i*nt + j, right-hand-side block
- * k -> nt*nt + k.  task_types (nullable, ntasks entries) receives SPX_T_* codes. */
+ * as the batched calls run it; bit 2 appends INV(k) for every k after the factor tasks
+ * (as every graph the library executes does).  Datum ids: tile (i,j) -> i*nt + j,
+ * right-hand-side block k -> nt*nt + k, M_k -> nt*nt + nt + k.  task_types (nullable,
+ * ntasks entries) receives SPX_T_* codes. */
 enum { SPX_T_POTRF = 0, SPX_T_TRSM, SPX_T_SYRK, SPX_T_GEMM, SPX_T_FTRSM, SPX_T_FGEMM, SPX_T_BTRSM, SPX_T_BGEMM,
-       SPX_T_LOAD, SPX_T_STORE };
+       SPX_T_LOAD, SPX_T_STORE, SPX_T_INV };
 /* SPX_T_LOAD / SPX_T_STORE appear only in the graphs of the batched and served calls: the
  * first task of each matrix copies its dense input (and right-hand sides) into tile
- * storage, writing every tile; the last one reads the solution blocks and writes X. */
+ * storage, writing every tile; the last one reads the solution blocks and writes X.
+ * SPX_T_INV(k), appended after the factor tasks of the graphs the library runs (with_solve
+ * bit 2 here), reads the factored diagonal tile L_kk and writes M_k = L_kk^{-T}; the
+ * diagonal solves FTRSM(k) / BTRSM(k) then read M_k instead of L_kk. */
 int spx_cholesky_graph(int32_t nt, int32_t with_solve, spx_graph** out, int32_t* task_types, uint32_t cap);
 
 /* ---------------------------------------------------------------------------------------

@@ -85,14 +85,21 @@ int build_graph(uint32_t ntasks, const spx_access* acc, uint64_t nacc, const int
   return SPX_OK;
 }
 
-// Right-looking tile Cholesky program (lower), optionally followed by the block forward
-// and backward substitution.  Datum ids: tile (i,j) -> i*nt + j; right-hand-side block k
-// -> nt*nt + k.
-void cholesky_program(int nt, bool with_solve, std::vector<TaskDesc>& tasks, std::vector<spx_access>& acc) {
+// Right-looking tile Cholesky program (lower), optionally followed by one inversion task
+// per diagonal tile and the block forward and backward substitution.  Datum ids: tile
+// (i,j) -> i*nt + j; right-hand-side block k -> nt*nt + k; M_k = L_kk^{-T} -> nt*nt + nt + k.
+void cholesky_program(int nt, bool with_solve, std::vector<TaskDesc>& tasks, std::vector<spx_access>& acc,
+                      bool with_inverse) {
   tasks.clear();
   acc.clear();
   auto A = [nt](int i, int j) { return (uint64_t)i * (uint64_t)nt + (uint64_t)j; };
   auto B = [nt](int k) { return (uint64_t)nt * (uint64_t)nt + (uint64_t)k; };
+  auto Minv = [nt](int k) { return (uint64_t)nt * (uint64_t)nt + (uint64_t)nt + (uint64_t)k; };
+  // with the inversions, the diagonal solves write a second copy of the right-hand sides
+  // (block k of Y2), so their rows can be split over workgroups; forward: FTRSM(k) reads
+  // B(k), writes Y2(k); FGEMM(i,k) reads Y2(k), updates B(i).  Backward: BTRSM(k) reads
+  // Y2(k), writes B(k); BGEMM(i,k) reads B(k), updates Y2(i).  The solution ends in B.
+  auto Y2 = [nt](int k) { return (uint64_t)nt * (uint64_t)nt + 2 * (uint64_t)nt + (uint64_t)k; };
   auto task = [&](int type, int i, int j, int k) {
     TaskDesc d;
     d.type = (uint8_t)type;
@@ -124,38 +131,74 @@ void cholesky_program(int nt, bool with_solve, std::vector<TaskDesc>& tasks, std
       }
     }
   }
+  if (with_inverse) {
+    for (int k = 0; k < nt; ++k) {
+      task(SPX_T_INV, k, k, k);
+      use(SPX_ACC_R, A(k, k));
+      use(SPX_ACC_RW, Minv(k));
+    }
+  }
   if (!with_solve) return;
+  if (!with_inverse) {  // the paper's in-place substitution
+    for (int k = 0; k < nt; ++k) {
+      task(SPX_T_FTRSM, k, k, k);
+      use(SPX_ACC_R, A(k, k));
+      use(SPX_ACC_RW, B(k));
+      for (int i = k + 1; i < nt; ++i) {
+        task(SPX_T_FGEMM, i, k, k);
+        use(SPX_ACC_R, A(i, k));
+        use(SPX_ACC_R, B(k));
+        use(SPX_ACC_RW, B(i));
+      }
+    }
+    for (int k = nt - 1; k >= 0; --k) {
+      task(SPX_T_BTRSM, k, k, k);
+      use(SPX_ACC_R, A(k, k));
+      use(SPX_ACC_RW, B(k));
+      for (int i = 0; i < k; ++i) {
+        task(SPX_T_BGEMM, i, k, k);
+        use(SPX_ACC_R, A(k, i));
+        use(SPX_ACC_R, B(k));
+        use(SPX_ACC_RW, B(i));
+      }
+    }
+    return;
+  }
   for (int k = 0; k < nt; ++k) {
     task(SPX_T_FTRSM, k, k, k);
-    use(SPX_ACC_R, A(k, k));
-    use(SPX_ACC_RW, B(k));
+    use(SPX_ACC_R, Minv(k));
+    use(SPX_ACC_R, B(k));
+    use(SPX_ACC_RW, Y2(k));
     for (int i = k + 1; i < nt; ++i) {
       task(SPX_T_FGEMM, i, k, k);
       use(SPX_ACC_R, A(i, k));
-      use(SPX_ACC_R, B(k));
+      use(SPX_ACC_R, Y2(k));
       use(SPX_ACC_RW, B(i));
     }
   }
   for (int k = nt - 1; k >= 0; --k) {
     task(SPX_T_BTRSM, k, k, k);
-    use(SPX_ACC_R, A(k, k));
+    use(SPX_ACC_R, Minv(k));
+    use(SPX_ACC_R, Y2(k));
     use(SPX_ACC_RW, B(k));
     for (int i = 0; i < k; ++i) {
       task(SPX_T_BGEMM, i, k, k);
       use(SPX_ACC_R, A(k, i));
       use(SPX_ACC_R, B(k));
-      use(SPX_ACC_RW, B(i));
+      use(SPX_ACC_RW, Y2(i));
     }
   }
 }
 
-// The block substitution alone (L tiles are only read): the tasks cholesky_program appends
-// after the factor, so its edges are the fused program's edges among those tasks.
+// The block substitution alone (L tiles and the M_k are only read): the tasks
+// cholesky_program appends after the factor and the inversions, so its edges are the fused
+// program's edges among those tasks.
 void solve_program(int nt, std::vector<TaskDesc>& tasks, std::vector<spx_access>& acc) {
   std::vector<TaskDesc> all;
   std::vector<spx_access> all_acc;
-  cholesky_program(nt, true, all, all_acc);
-  const uint32_t first = (uint32_t)(nt + nt * (nt - 1) + (uint64_t)nt * (nt - 1) * (nt - 2) / 6);
+  cholesky_program(nt, true, all, all_acc, true);
+  uint32_t first = 0;
+  while (all[first].type != SPX_T_FTRSM) ++first;
   tasks.assign(all.begin() + first, all.end());
   acc.clear();
   for (const spx_access& a : all_acc)
@@ -168,7 +211,7 @@ void solve_program(int nt, std::vector<TaskDesc>& tasks, std::vector<spx_access>
 void io_program(int nt, bool with_solve, std::vector<TaskDesc>& tasks, std::vector<spx_access>& acc) {
   std::vector<TaskDesc> body;
   std::vector<spx_access> body_acc;
-  cholesky_program(nt, with_solve, body, body_acc);
+  cholesky_program(nt, with_solve, body, body_acc, true);
   auto A = [nt](int i, int j) { return (uint64_t)i * (uint64_t)nt + (uint64_t)j; };
   auto B = [nt](int k) { return (uint64_t)nt * (uint64_t)nt + (uint64_t)k; };
   tasks.clear();
@@ -230,6 +273,7 @@ int32_t cholesky_priority(const TaskDesc& d, int nt) {
     case SPX_T_FTRSM:
     case SPX_T_BTRSM: base = 4; break;
     case SPX_T_FGEMM: base = (d.i == d.k + 1) ? 3 : 1; break;
+    case SPX_T_INV: base = 1; break;  // off the factor's critical path, needed by the solve
     case SPX_T_BGEMM: base = (d.i + 1 == d.k) ? 3 : 1; break;
     default: base = 3; break;
   }
@@ -287,12 +331,12 @@ int spx_graph_to_dot(const spx_graph* g, const char* path) {
   if (!g || !path) return fail(SPX_EINVAL, "spx_graph_to_dot: null argument");
   FILE* f = std::fopen(path, "w");
   if (!f) return fail(SPX_EINVAL, "spx_graph_to_dot: cannot open file");
-  static const char* names[] = {"POTRF", "TRSM", "SYRK", "GEMM", "FTRSM", "FGEMM", "BTRSM", "BGEMM", "LOAD", "STORE"};
+  static const char* names[] = {"POTRF", "TRSM", "SYRK", "GEMM", "FTRSM", "FGEMM", "BTRSM", "BGEMM", "LOAD", "STORE", "INV"};
   std::fprintf(f, "digraph spx {\n");
   for (uint32_t t = 0; t < g->g.ntasks; ++t) {
     if (t < g->tasks.size()) {
       const TaskDesc& d = g->tasks[t];
-      std::fprintf(f, "  t%u [label=\"%s(%d,%d,%d)\"];\n", t, d.type < 10 ? names[d.type] : "?", d.i, d.j, d.k);
+      std::fprintf(f, "  t%u [label=\"%s(%d,%d,%d)\"];\n", t, d.type < 11 ? names[d.type] : "?", d.i, d.j, d.k);
     } else {
       std::fprintf(f, "  t%u [label=\"t%u p%d\"];\n", t, t, g->g.prio[t]);
     }
@@ -307,7 +351,7 @@ int spx_graph_to_dot(const spx_graph* g, const char* path) {
 void spx_graph_destroy(spx_graph* g) { delete g; }
 
 int spx_cholesky_graph(int32_t nt, int32_t with_solve, spx_graph** out, int32_t* task_types, uint32_t cap) {
-  if (!out || nt < 1 || nt > 4096 || with_solve < 0 || with_solve > 3)
+  if (!out || nt < 1 || nt > 4096 || with_solve < 0 || with_solve > 7)
     return fail(SPX_EINVAL, "spx_cholesky_graph: bad argument");
   *out = nullptr;
   try {
@@ -316,7 +360,7 @@ int spx_cholesky_graph(int32_t nt, int32_t with_solve, spx_graph** out, int32_t*
     if (with_solve & 2)
       io_program(nt, (with_solve & 1) != 0, g->tasks, acc);
     else
-      cholesky_program(nt, with_solve != 0, g->tasks, acc);
+      cholesky_program(nt, (with_solve & 1) != 0, g->tasks, acc, (with_solve & 4) != 0);
     std::vector<int32_t> prio(g->tasks.size());
     for (size_t t = 0; t < g->tasks.size(); ++t) prio[t] = cholesky_priority(g->tasks[t], nt);
     int rc = build_graph((uint32_t)g->tasks.size(), acc.data(), acc.size(), prio.data(), g->g);

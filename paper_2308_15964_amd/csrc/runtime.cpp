@@ -126,6 +126,7 @@ struct spx_factor {
   size_t tile_bytes = 0;
   void* low = nullptr;  // FP32 / BF16 copies of the panel tiles (mixed precision)
   double* dinv = nullptr;  // inverses of the 32x32 diagonal blocks of the diagonal tiles
+  double* minv = nullptr;  // M_k = L_kk^{-T} of every diagonal tile (nt b^2)
   double* dscale = nullptr;  // D^{-1/2} (n_pad) of a factor of the scaled, shifted matrix
   double shift = 0.0;
 };
@@ -158,7 +159,7 @@ static int get_program(spx_ctx* c, char kind, int nt, const Program** out) {
   std::unique_ptr<Program> pr(new Program());
   std::vector<spx_access> acc;
   switch (kind) {
-    case 'F': cholesky_program(nt, false, pr->tasks, acc); break;
+    case 'F': cholesky_program(nt, false, pr->tasks, acc, true); break;
     case 'S': solve_program(nt, pr->tasks, acc); break;
     case 'L': io_program(nt, false, pr->tasks, acc); break;
     case 'Q': solve_io_program(nt, pr->tasks, acc); break;
@@ -194,9 +195,10 @@ uint16_t parts_of(const TaskDesc& d, int b, int nrhs) {
     case SPX_T_SYRK: return (uint16_t)(ns * (ns + 1) / 2);
     case SPX_T_GEMM: return (uint16_t)(ns * ns);
     case SPX_T_FTRSM:
-    case SPX_T_BTRSM: return (uint16_t)((nrhs + 7) / 8);
+    case SPX_T_BTRSM: return (uint16_t)((nrhs + 7) / 8 * (b / rows));
     case SPX_T_FGEMM:
     case SPX_T_BGEMM: return (uint16_t)(b / rows);
+    case SPX_T_INV: return (uint16_t)(b / trsm_rows_of(b));
     case SPX_T_LOAD: {
       if (d.j) return 1;  // right-hand sides only
       const int ntiles = d.i * (d.i + 1) / 2;
@@ -512,7 +514,7 @@ static int batched_solve(spx_ctx* c, const std::vector<int>& idx, const spx_fact
   for (int j = 0; j < K; ++j) {
     const spx_factor* g = f[idx[j]];
     off[j] = ws;
-    ws = align256(ws + (size_t)g->n_pad * (size_t)q[idx[j]] * sizeof(double));
+    ws = align256(ws + 2 * (size_t)g->n_pad * (size_t)q[idx[j]] * sizeof(double));
     const Program* pr = nullptr;
     SPX_TRY(get_program(c, 'Q', g->nt, &pr));
     pieces[j] = Piece{pr, (uint32_t)j, g->b, (int)q[idx[j]]};
@@ -529,7 +531,9 @@ static int batched_solve(spx_ctx* c, const std::vector<int>& idx, const spx_fact
     DevMat d{};
     d.tiles = g->tiles;
     d.dinv = g->dinv;
+    d.minv = g->minv;
     d.rhs = (double*)(block + off[j]);
+    d.rhs2 = d.rhs + (size_t)g->n_pad * (size_t)q[m];
     d.info = c->dinfo + j;
     d.n_pad = g->n_pad;
     d.nt = g->nt;
@@ -641,14 +645,15 @@ static int batched(spx_ctx* c, int count, const int64_t* n, const double* const*
   }
   SPX_TRY(hipc(hipSetDevice(c->device), "hipSetDevice"));
   // storage: one workspace for the whole batch (posv) or one factor per matrix (potrf)
-  std::vector<size_t> off_t(count), off_d(count), off_r(count), off_l(count);
+  std::vector<size_t> off_t(count), off_d(count), off_r(count), off_l(count), off_m(count);
   size_t ws = 0;
   for (int m = 0; m < count; ++m) {
     const size_t b = bs[m], nt = nts[m], npad = nt * b;
     const size_t tb = nt * (nt + 1) / 2 * b * b * sizeof(double);
     off_t[m] = ws; ws = align256(ws + tb);
     off_d[m] = ws; ws = align256(ws + npad * 32 * sizeof(double));
-    off_r[m] = ws; ws = align256(ws + npad * (size_t)qs[m] * sizeof(double));
+    off_m[m] = ws; ws = align256(ws + npad * b * sizeof(double));
+    off_r[m] = ws; ws = align256(ws + 2 * npad * (size_t)qs[m] * sizeof(double));
     off_l[m] = ws; ws = align256(ws + (prec == SPX_PREC_FP64 ? 0 : tb / (prec == SPX_PREC_FP32 ? 2 : 4)));
   }
   char* block = nullptr;
@@ -660,6 +665,7 @@ static int batched(spx_ctx* c, int count, const int64_t* n, const double* const*
         dev_free(c, f->tiles);
         dev_free(c, f->low);
         dev_free(c, f->dinv);
+        dev_free(c, f->minv);
         f.reset();
       }
   };
@@ -679,8 +685,9 @@ static int batched(spx_ctx* c, int count, const int64_t* n, const double* const*
       f->tile_bytes = (size_t)nts[m] * (nts[m] + 1) / 2 * (size_t)bs[m] * bs[m] * sizeof(double);
       f->tiles = (double*)dev_alloc(c, f->tile_bytes);
       f->dinv = (double*)dev_alloc(c, (size_t)f->n_pad * 32 * sizeof(double));
+      f->minv = (double*)dev_alloc(c, (size_t)f->n_pad * (size_t)bs[m] * sizeof(double));
       if (prec != SPX_PREC_FP64) f->low = dev_alloc(c, f->tile_bytes / (prec == SPX_PREC_FP32 ? 2 : 4));
-      const bool ok = f->tiles && f->dinv && (prec == SPX_PREC_FP64 || f->low);
+      const bool ok = f->tiles && f->dinv && f->minv && (prec == SPX_PREC_FP64 || f->low);
       fs[m] = std::move(f);
       if (!ok) {
         release();
@@ -714,7 +721,9 @@ static int batched(spx_ctx* c, int count, const int64_t* n, const double* const*
     if (solve) {
       d.tiles = (double*)(block + off_t[m]);
       d.dinv = (double*)(block + off_d[m]);
+      d.minv = (double*)(block + off_m[m]);
       d.rhs = (double*)(block + off_r[m]);
+      d.rhs2 = d.rhs + (size_t)nts[m] * bs[m] * (size_t)qs[m];
       d.low = prec == SPX_PREC_FP64 ? nullptr : (void*)(block + off_l[m]);
       d.B = dB[m];
       d.X = dX[m];
@@ -723,6 +732,7 @@ static int batched(spx_ctx* c, int count, const int64_t* n, const double* const*
     } else {
       d.tiles = fs[m]->tiles;
       d.dinv = fs[m]->dinv;
+      d.minv = fs[m]->minv;
       d.low = fs[m]->low;
     }
     d.info = c->dinfo + m;
@@ -754,6 +764,7 @@ static int batched(spx_ctx* c, int count, const int64_t* n, const double* const*
         dev_free(c, fs[m]->tiles);
         dev_free(c, fs[m]->low);
         dev_free(c, fs[m]->dinv);
+        dev_free(c, fs[m]->minv);
         fs[m].reset();
       }
     }
@@ -1058,8 +1069,11 @@ int spx_potrf_tiled(spx_ctx* c, int64_t n, const double* dA, int64_t lda, const 
   f->tiles = (double*)dev_alloc(c, f->tile_bytes);
   if (!f->tiles) return fail(SPX_ENOMEM, "spx_potrf_tiled: tile storage allocation failed");
   f->dinv = (double*)dev_alloc(c, (size_t)f->n_pad * 32 * sizeof(double));
-  if (!f->dinv) {
+  f->minv = (double*)dev_alloc(c, (size_t)f->n_pad * (size_t)b * sizeof(double));
+  if (!f->dinv || !f->minv) {
     dev_free(c, f->tiles);
+    dev_free(c, f->dinv);
+    dev_free(c, f->minv);
     return fail(SPX_ENOMEM, "spx_potrf_tiled: block inverse allocation failed");
   }
   if (prec != SPX_PREC_FP64) {
@@ -1067,6 +1081,7 @@ int spx_potrf_tiled(spx_ctx* c, int64_t n, const double* dA, int64_t lda, const 
     if (!f->low) {
       dev_free(c, f->tiles);
       dev_free(c, f->dinv);
+      dev_free(c, f->minv);
       return fail(SPX_ENOMEM, "spx_potrf_tiled: low-precision copy allocation failed");
     }
   }
@@ -1074,6 +1089,7 @@ int spx_potrf_tiled(spx_ctx* c, int64_t n, const double* dA, int64_t lda, const 
     dev_free(c, f->tiles);
     dev_free(c, f->low);
     dev_free(c, f->dinv);
+    dev_free(c, f->minv);
     dev_free(c, f->dscale);
   };
   Image* im = nullptr;
@@ -1093,6 +1109,7 @@ int spx_potrf_tiled(spx_ctx* c, int64_t n, const double* dA, int64_t lda, const 
   m.tiles = f->tiles;
   m.low = f->low;
   m.dinv = f->dinv;
+  m.minv = f->minv;
   m.info = c->dinfo;
   m.n_pad = f->n_pad;
   m.nt = (int32_t)nt;
@@ -1150,19 +1167,23 @@ void spx_factor_destroy(spx_factor* f) {
   dev_free(f->ctx, f->tiles);
   dev_free(f->ctx, f->low);
   dev_free(f->ctx, f->dinv);
+  dev_free(f->ctx, f->minv);
   dev_free(f->ctx, f->dscale);
   delete f;
 }
 
-// Runs the solve graph of factor f on the column-major work buffer rhs (n_pad x nrhs).
-static int solve_on(spx_ctx* c, const spx_factor* f, int64_t nrhs, double* rhs) {
+// Runs the solve graph of factor f on the column-major work buffer rhs (n_pad x nrhs;
+// rhs2: a second one of the same shape that the diagonal solves write).
+static int solve_on(spx_ctx* c, const spx_factor* f, int64_t nrhs, double* rhs, double* rhs2) {
   Image* im = nullptr;
   SPX_TRY(get_image(c, true, f->nt, f->b, (int)nrhs, SPX_Q_PRIORITY, &im));
   SPX_TRY(ensure_small_buffers(c, 1, 1, 0, false));
   DevMat m{};
   m.tiles = f->tiles;
   m.dinv = f->dinv;
+  m.minv = f->minv;
   m.rhs = rhs;
+  m.rhs2 = rhs2;
   m.info = c->dinfo;
   m.n_pad = f->n_pad;
   m.nt = f->nt;
@@ -1198,11 +1219,11 @@ static int residual_eta(spx_ctx* c, int64_t n, const double* dA, int64_t lda, in
 }
 
 // Y = M^{-1} R for the n x nrhs row-major R (ld ldr) into Y (ld ldy; accumulate: Y +=),
-// M = L L^T, or D^{1/2} L L^T D^{1/2} for a scaled factor; rhs: n_pad x nrhs work.
+// M = L L^T, or D^{1/2} L L^T D^{1/2} for a scaled factor; rhs: 2 x n_pad x nrhs work.
 static int apply_inverse(spx_ctx* c, const spx_factor* f, int64_t nrhs, const double* R, int64_t ldr, double* Y,
                          int64_t ldy, int accumulate, double* rhs, double* ms) {
   SPX_TRY(launch_rhs_in(R, ldr, f->n, nrhs, rhs, f->n_pad, f->dscale, c->stream));
-  SPX_TRY(solve_on(c, f, nrhs, rhs));
+  SPX_TRY(solve_on(c, f, nrhs, rhs, rhs + (size_t)f->n_pad * (size_t)nrhs));
   *ms += c->last.kernel_ms;
   return launch_rhs_out(rhs, f->n_pad, f->n, nrhs, Y, ldy, accumulate, f->dscale, c->stream);
 }
@@ -1238,7 +1259,7 @@ int spx_potrs(spx_ctx* c, const spx_factor* f, int64_t nrhs, const double* dB, i
     bufs.push_back(p);
     return (double*)p;
   };
-  double* rhs = get((size_t)f->n_pad * (size_t)q * sizeof(double));
+  double* rhs = get(2 * (size_t)f->n_pad * (size_t)q * sizeof(double));
   double* R = method ? get(vec) : nullptr;
   double* S = method ? get(sizeof(double) * (size_t)(3 * q + 1)) : nullptr;
   double *Z = nullptr, *P = nullptr, *NQ = nullptr, *zero = nullptr, *part = nullptr, *alpha = nullptr;
@@ -1409,10 +1430,30 @@ int spx_run_task(spx_ctx* c, int32_t type, int32_t i, int32_t j, int32_t k, int3
       return rc;
     }
   }
+  // the diagonal solves read M_k = L_kk^{-T}, made first by the inversion task
+  const bool needs_inv = type == SPX_T_FTRSM || type == SPX_T_BTRSM;
+  double* minv = needs_inv ? (double*)dev_alloc(c, (size_t)nt * b * b * sizeof(double)) : nullptr;
+  if (needs_inv && !minv) {
+    dev_free(c, dinv);
+    return fail(SPX_ENOMEM, "spx_run_task: allocation failed");
+  }
+  // the diagonal solves read block k of one right-hand-side buffer and write it to a
+  // second one (FTRSM: rhs -> rhs2, then copied back; BTRSM: rhs2 <- rhs first, result in
+  // rhs); the updates read and write the caller's buffer
+  const size_t qbytes = (size_t)nt * b * (size_t)(nrhs > 0 ? nrhs : 1) * sizeof(double);
+  double* rhs2 = needs_inv ? (double*)dev_alloc(c, qbytes) : d_rhs;
+  if (needs_inv && !rhs2) {
+    dev_free(c, dinv);
+    dev_free(c, minv);
+    return fail(SPX_ENOMEM, "spx_run_task: allocation failed");
+  }
+  const size_t pitch = (size_t)nt * b * sizeof(double);
   DevMat m{};
   m.tiles = d_tiles;
   m.dinv = dinv;
+  m.minv = minv;
   m.rhs = d_rhs;
+  m.rhs2 = rhs2;
   m.info = c->dinfo;
   m.n_pad = (int64_t)nt * b;
   m.nt = nt;
@@ -1422,16 +1463,34 @@ int spx_run_task(spx_ctx* c, int32_t type, int32_t i, int32_t j, int32_t k, int3
   m.trsm_rows = trsm_rows_of(b);
   c->hmats[0] = m;
   const int32_t healthy = INT_MAX;
-  int rc = hipc(hipMemcpyAsync(c->dtask, &d, sizeof d, hipMemcpyHostToDevice, c->stream), "task upload");
-  if (!rc) rc = hipc(hipMemcpyAsync(c->dmats, c->hmats, sizeof(DevMat), hipMemcpyHostToDevice, c->stream), "upload");
+  int rc = hipc(hipMemcpyAsync(c->dmats, c->hmats, sizeof(DevMat), hipMemcpyHostToDevice, c->stream), "upload");
   if (!rc) rc = hipc(hipMemcpyAsync(c->dinfo, &healthy, 4, hipMemcpyHostToDevice, c->stream), "upload");
   SchedArgs a{};
   a.tasks = c->dtask;
   a.mats = c->dmats;
+  TaskDesc inv;
+  inv.type = SPX_T_INV;
+  inv.i = inv.j = inv.k = (uint16_t)k;
+  inv.nparts = parts_of(inv, b, nrhs);
+  if (!rc && needs_inv) {
+    rc = hipc(hipMemcpyAsync(c->dtask, &inv, sizeof inv, hipMemcpyHostToDevice, c->stream), "task upload");
+    if (!rc) rc = launch_one_task(a, inv.nparts, c->stream);
+  }
+  if (!rc && type == SPX_T_BTRSM)
+    rc = hipc(hipMemcpy2DAsync(rhs2 + (size_t)k * b, pitch, d_rhs + (size_t)k * b, pitch, (size_t)b * 8, nrhs,
+                               hipMemcpyDeviceToDevice, c->stream),
+              "copy");
+  if (!rc) rc = hipc(hipMemcpyAsync(c->dtask, &d, sizeof d, hipMemcpyHostToDevice, c->stream), "task upload");
   if (!rc) rc = launch_one_task(a, d.nparts, c->stream);
+  if (!rc && type == SPX_T_FTRSM)
+    rc = hipc(hipMemcpy2DAsync(d_rhs + (size_t)k * b, pitch, rhs2 + (size_t)k * b, pitch, (size_t)b * 8, nrhs,
+                               hipMemcpyDeviceToDevice, c->stream),
+              "copy");
   if (!rc) rc = hipc(hipMemcpyAsync(c->hinfo, c->dinfo, 4, hipMemcpyDeviceToHost, c->stream), "info");
   if (!rc) rc = hipc(hipStreamSynchronize(c->stream), "hipStreamSynchronize");
   dev_free(c, dinv);
+  dev_free(c, minv);
+  if (needs_inv) dev_free(c, rhs2);
   if (rc) return rc;
   *info = c->hinfo[0] == INT_MAX ? 0 : c->hinfo[0];
   return SPX_OK;

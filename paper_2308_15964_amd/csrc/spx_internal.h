@@ -36,7 +36,8 @@ struct TaskDesc {
 static_assert(sizeof(TaskDesc) == 16, "TaskDesc must stay 16 bytes");
 
 int build_graph(uint32_t ntasks, const spx_access* acc, uint64_t nacc, const int32_t* priority, Graph& g);
-void cholesky_program(int nt, bool with_solve, std::vector<TaskDesc>& tasks, std::vector<spx_access>& acc);
+void cholesky_program(int nt, bool with_solve, std::vector<TaskDesc>& tasks, std::vector<spx_access>& acc,
+                      bool with_inverse = false);
 void solve_program(int nt, std::vector<TaskDesc>& tasks, std::vector<spx_access>& acc);
 int32_t cholesky_priority(const TaskDesc& d, int nt);
 // LOAD, the factor program (and with_solve: the substitution), STORE (with_solve only).
@@ -56,7 +57,9 @@ struct DevMat {
   double* tiles;
   void* low;        // low-precision copies of the off-diagonal tiles (same packing), or null
   double* rhs;      // right-hand side / solution, column-major n_pad x nrhs (ld = n_pad)
+  double* rhs2;     // second copy written by the diagonal solves (same layout)
   double* dinv;     // inverses of the 32x32 diagonal blocks of each diagonal tile (32 b per tile)
+  double* minv;     // M_k = L_kk^{-T} per diagonal tile (b x b, column-major, upper triangular)
   int32_t* info;    // 0x7fffffff while healthy; else the 1-based failing column
   int64_t n_pad;
   int32_t nt, b, nrhs, prec;

@@ -609,140 +609,101 @@ __device__ void tile_inverses(const double* __restrict__ l, int b, double* __res
 // Solve tasks on the right-hand side y (column-major, ld = n_pad), columns [q0, q0+nq).
 // ---------------------------------------------------------------------------------------
 
-// Forward substitution of one diagonal tile for up to 8 right-hand sides: y_k <- L_kk^{-1}
-// y_k, block by block (32 rows) with the inverted 32x32 diagonal blocks: y_blk <- Li y_blk,
-// then the rows below lose L(rows, blk) y_blk.  The whole block of right-hand sides stays in
-// LDS; thread t owns rows t and t + 256 of the trailing update, whose L strip for the next
-// block is loaded into registers while the current block is solved, and the next block
-// inverse is loaded into the other half of a double buffer.  Only the block-inverse
-// products change the arithmetic order relative to a substitution.
-__device__ void ftrsm_part(const double* __restrict__ l, const double* __restrict__ dinv, int b,
-                           double* __restrict__ y, int64_t ldy, int q0, int nq, double* __restrict__ lds) {
-  const int tid = threadIdx.x;
-  double* ys = lds;            // [8][b] right-hand sides
-  double* Lb = lds + 8 * 512;  // two 32x32 block inverses
-  double* yb = Lb + 2048;      // [8][32] the block just solved
-  const int q = tid >> 5, r = tid & 31;
-  for (int e = tid; e < 8 * b; e += NT) {
-    const int qq = e / b, m = e % b;
-    ys[e] = qq < nq ? y[(size_t)(q0 + qq) * ldy + m] : 0.0;
-  }
-  for (int e = tid; e < 1024; e += NT) Lb[e] = dinv[e];
-  double lv[2][32];
-  auto load_strip = [&](int c0) {
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const int row = tid + NT * j;
-      if (row >= c0 + 32 && row < b) {
-#pragma unroll
-        for (int c = 0; c < 32; ++c) lv[j][c] = l[(size_t)(c0 + c) * b + row];
-      }
-    }
-  };
-  load_strip(0);
-  int buf = 0;
-  for (int c0 = 0; c0 < b; c0 += 32) {
-    __syncthreads();  // block c0 of ys and the inverse in Lb[buf] are ready
-    if (c0 + 32 < b)
-      for (int e = tid; e < 1024; e += NT) Lb[(buf ^ 1) * 1024 + e] = dinv[(size_t)(c0 + 32) * 32 + e];
-    const double* Li = Lb + buf * 1024;
-    if (q < nq) {
-      double sacc = 0.0;
-      for (int c = 0; c <= r; ++c) sacc += Li[c * 32 + r] * ys[q * b + c0 + c];
-      yb[q * 32 + r] = sacc;
-    }
-    __syncthreads();
-    if (q < nq) ys[q * b + c0 + r] = yb[q * 32 + r];
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const int row = tid + NT * j;
-      if (row >= c0 + 32 && row < b) {
-        double acc[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) acc[u] = 0.0;
-#pragma unroll
-        for (int c = 0; c < 32; ++c)
-#pragma unroll
-          for (int u = 0; u < 8; ++u) acc[u] += lv[j][c] * yb[u * 32 + c];
-        for (int u = 0; u < nq; ++u) ys[u * b + row] -= acc[u];
-      }
-    }
-    if (c0 + 32 < b) load_strip(c0 + 32);
-    buf ^= 1;
+// Diagonal solves with M = L_kk^{-T} (column-major b x b, upper triangular: made by the
+// inversion task, exact zeros below its diagonal), rows [r0, r0 + rows) of the result for
+// up to 8 right-hand sides, read from yin and written to yout (another buffer, so the
+// row strips of one block run as separate parts).  Forward: out_r = sum over c <= r of
+// M(c, r) in_c (column r of M, contiguous).  Backward: out_r = sum over c >= r of
+// M(r, c) in_c.  yin is staged in LDS; the four waves split the c range and their partial
+// sums are added through LDS.
+__device__ void ftrsm_part(const double* __restrict__ M, int b, const double* __restrict__ yin,
+                           double* __restrict__ yout, int64_t ldy, int q0, int nq, int r0, int rows,
+                           double* __restrict__ lds) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  double* ys = lds;              // [8][b]
+  double* part = lds + 8 * 512;  // [4][8][64]
+  const int cmax = r0 + rows;    // entries c < cmax are used
+  for (int e = tid; e < 8 * cmax; e += NT) {
+    const int q = e / cmax, m = e % cmax;
+    ys[q * b + m] = q < nq ? yin[(size_t)(q0 + q) * ldy + m] : 0.0;
   }
   __syncthreads();
-  for (int e = tid; e < nq * b; e += NT) {
-    const int qq = e / b, m = e % b;
-    y[(size_t)(q0 + qq) * ldy + m] = ys[e];
+  const int ql = ((cmax + 15) / 16) * 4, c0 = wave * ql;  // quarters, multiples of 4
+  const int r = r0 + lane;
+  double acc[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) acc[q] = 0.0;
+  if (lane < rows) {
+    // entries c <= r; reading up to the next multiple of 4 only adds exact zeros
+    const int cend = min(min(c0 + ql, cmax), (r & ~3) + 4);
+    const double4* col = reinterpret_cast<const double4*>(M + (size_t)r * b);
+    if (nq == 1) {
+#pragma unroll 8
+      for (int c = c0; c < cend; c += 4) {
+        const double4 v = col[c >> 2];
+        acc[0] += v.x * ys[c] + v.y * ys[c + 1] + v.z * ys[c + 2] + v.w * ys[c + 3];
+      }
+    } else {
+#pragma unroll 4
+      for (int c = c0; c < cend; c += 4) {
+        const double4 v = col[c >> 2];
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+          acc[q] += v.x * ys[q * b + c] + v.y * ys[q * b + c + 1] + v.z * ys[q * b + c + 2] + v.w * ys[q * b + c + 3];
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 8; ++q) part[(wave * 8 + q) * 64 + lane] = acc[q];
+  __syncthreads();
+  if (wave == 0 && lane < rows) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+      if (q < nq)
+        yout[(size_t)(q0 + q) * ldy + r] = part[(0 * 8 + q) * 64 + lane] + part[(1 * 8 + q) * 64 + lane] +
+                                           part[(2 * 8 + q) * 64 + lane] + part[(3 * 8 + q) * 64 + lane];
   }
 }
 
-// Backward: y_k <- L_kk^{-T} y_k, blocks from the last one down: x_blk = Li^T y_blk, then
-// the rows above lose L(blk, rows)^T x_blk.  Row t's strip L(c0 .. c0+31, t) is contiguous
-// (column t of the tile); otherwise as the forward substitution.
-__device__ void btrsm_part(const double* __restrict__ l, const double* __restrict__ dinv, int b,
-                           double* __restrict__ y, int64_t ldy, int q0, int nq, double* __restrict__ lds) {
-  const int tid = threadIdx.x;
+__device__ void btrsm_part(const double* __restrict__ M, int b, const double* __restrict__ yin,
+                           double* __restrict__ yout, int64_t ldy, int q0, int nq, int r0, int rows,
+                           double* __restrict__ lds) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   double* ys = lds;
-  double* Lb = lds + 8 * 512;
-  double* yb = Lb + 2048;
-  const int q = tid >> 5, r = tid & 31;
-  for (int e = tid; e < 8 * b; e += NT) {
-    const int qq = e / b, m = e % b;
-    ys[e] = qq < nq ? y[(size_t)(q0 + qq) * ldy + m] : 0.0;
-  }
-  for (int e = tid; e < 1024; e += NT) Lb[e] = dinv[(size_t)(b - 32) * 32 + e];
-  double lv[2][32];
-  auto load_strip = [&](int c0) {
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const int row = tid + NT * j;
-      if (row < c0) {
-        const double2* src = reinterpret_cast<const double2*>(l + (size_t)row * b + c0);
-#pragma unroll
-        for (int c = 0; c < 16; ++c) {
-          const double2 v = src[c];
-          lv[j][2 * c] = v.x;
-          lv[j][2 * c + 1] = v.y;
-        }
-      }
-    }
-  };
-  load_strip(b - 32);
-  int buf = 0;
-  for (int c0 = b - 32; c0 >= 0; c0 -= 32) {
-    __syncthreads();
-    if (c0 > 0)
-      for (int e = tid; e < 1024; e += NT) Lb[(buf ^ 1) * 1024 + e] = dinv[(size_t)(c0 - 32) * 32 + e];
-    const double* Li = Lb + buf * 1024;
-    if (q < nq) {
-      double sacc = 0.0;
-      for (int c = r; c < 32; ++c) sacc += Li[r * 32 + c] * ys[q * b + c0 + c];  // Li(c, r)
-      yb[q * 32 + r] = sacc;
-    }
-    __syncthreads();
-    if (q < nq) ys[q * b + c0 + r] = yb[q * 32 + r];
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const int row = tid + NT * j;
-      if (row < c0) {
-        double acc[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) acc[u] = 0.0;
-#pragma unroll
-        for (int c = 0; c < 32; ++c)
-#pragma unroll
-          for (int u = 0; u < 8; ++u) acc[u] += lv[j][c] * yb[u * 32 + c];
-        for (int u = 0; u < nq; ++u) ys[u * b + row] -= acc[u];
-      }
-    }
-    if (c0 > 0) load_strip(c0 - 32);
-    buf ^= 1;
+  double* part = lds + 8 * 512;
+  for (int e = tid; e < 8 * (b - r0); e += NT) {  // entries c >= r0 are used
+    const int q = e / (b - r0), m = r0 + e % (b - r0);
+    ys[q * b + m] = q < nq ? yin[(size_t)(q0 + q) * ldy + m] : 0.0;
   }
   __syncthreads();
-  for (int e = tid; e < nq * b; e += NT) {
-    const int qq = e / b, m = e % b;
-    y[(size_t)(q0 + qq) * ldy + m] = ys[e];
+  const int ql = ((b - r0 + 15) / 16) * 4, cb = r0 + wave * ql, ce = min(cb + ql, b);
+  const int r = r0 + lane;
+  // rows r > c of the strip add exact zeros
+  double acc[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) acc[q] = 0.0;
+  if (lane < rows) {
+    if (nq == 1) {
+#pragma unroll 16
+      for (int c = cb; c < ce; ++c) acc[0] += M[(size_t)c * b + r] * ys[c];
+    } else {
+#pragma unroll 8
+      for (int c = cb; c < ce; ++c) {
+        const double v = M[(size_t)c * b + r];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) acc[q] += v * ys[q * b + c];
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 8; ++q) part[(wave * 8 + q) * 64 + lane] = acc[q];
+  __syncthreads();
+  if (wave == 0 && lane < rows) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+      if (q < nq)
+        yout[(size_t)(q0 + q) * ldy + r] = part[(0 * 8 + q) * 64 + lane] + part[(1 * 8 + q) * 64 + lane] +
+                                           part[(2 * 8 + q) * 64 + lane] + part[(3 * 8 + q) * 64 + lane];
   }
 }
 
@@ -951,26 +912,41 @@ __device__ void run_part(const SchedArgs& a, uint32_t task, uint32_t part, doubl
       }
       break;
     }
-    case SPX_T_FTRSM: {
-      const int q0 = part * 8, nq = (m.nrhs - q0) < 8 ? (m.nrhs - q0) : 8;
-      ftrsm_part(tile_ptr(m, d.k, d.k), dinv_ptr(m, d.k), b, m.rhs + (size_t)d.k * b, m.n_pad, q0, nq, lds);
+    case SPX_T_FTRSM:
+    case SPX_T_BTRSM: {
+      // part -> (group of 8 right-hand sides, strip of 64 rows)
+      const int rows = b < 64 ? b : 64, nrp = b / rows;
+      const int q0 = ((int)part / nrp) * 8, nq = (m.nrhs - q0) < 8 ? (m.nrhs - q0) : 8;
+      const int r0 = ((int)part % nrp) * rows;
+      const double* Mk = m.minv + (size_t)d.k * b * b;
+      if (d.type == SPX_T_FTRSM)
+        ftrsm_part(Mk, b, m.rhs + (size_t)d.k * b, m.rhs2 + (size_t)d.k * b, m.n_pad, q0, nq, r0, rows, lds);
+      else
+        btrsm_part(Mk, b, m.rhs2 + (size_t)d.k * b, m.rhs + (size_t)d.k * b, m.n_pad, q0, nq, r0, rows, lds);
       break;
     }
-    case SPX_T_BTRSM: {
-      const int q0 = part * 8, nq = (m.nrhs - q0) < 8 ? (m.nrhs - q0) : 8;
-      btrsm_part(tile_ptr(m, d.k, d.k), dinv_ptr(m, d.k), b, m.rhs + (size_t)d.k * b, m.n_pad, q0, nq, lds);
+    case SPX_T_INV: {
+      // rows [r0, r0 + R) of M_k = I L_kk^{-T}: identity rows, then the TRSM strip kernel
+      const int R = m.trsm_rows, r0 = part * R;
+      double* x = m.minv + (size_t)d.k * b * b;
+      for (int e = threadIdx.x; e < R * b; e += NT) {
+        const int c = e / R, r = e % R;
+        x[(size_t)c * b + r0 + r] = (r0 + r == c) ? 1.0 : 0.0;
+      }
+      __syncthreads();
+      trsm_part(x, tile_ptr(m, d.k, d.k), dinv_ptr(m, d.k), b, r0, R, nullptr, PREC_FP64, lds);
       break;
     }
     case SPX_T_FGEMM: {
       const int rows = b < 64 ? b : 64;
-      fgemm_part(tile_ptr(m, d.i, d.k), b, m.rhs + (size_t)d.i * b, m.rhs + (size_t)d.k * b, m.n_pad, m.nrhs,
+      fgemm_part(tile_ptr(m, d.i, d.k), b, m.rhs + (size_t)d.i * b, m.rhs2 + (size_t)d.k * b, m.n_pad, m.nrhs,
                  part * rows, rows, lds);
       break;
     }
     case SPX_T_BGEMM: {
       // task (i, k): y_i -= L_ki^T y_k; the tile is (k, i) with k = d.j
       const int rows = b < 64 ? b : 64;
-      bgemm_part(tile_ptr(m, d.j, d.i), b, m.rhs + (size_t)d.i * b, m.rhs + (size_t)d.j * b, m.n_pad, m.nrhs,
+      bgemm_part(tile_ptr(m, d.j, d.i), b, m.rhs2 + (size_t)d.i * b, m.rhs + (size_t)d.j * b, m.n_pad, m.nrhs,
                  part * rows, rows, lds);
       break;
     }

@@ -14,8 +14,8 @@ LIB_PATH = os.path.join(_HERE, "libspx.so")
 
 SPX_OK, SPX_EINVAL, SPX_ENOMEM, SPX_EDEVICE, SPX_EAGAIN, SPX_EABORT, SPX_ETIMEOUT = 0, -1, -2, -3, -4, -5, -6
 ACC_R, ACC_RW = 1, 2
-T_POTRF, T_TRSM, T_SYRK, T_GEMM, T_FTRSM, T_FGEMM, T_BTRSM, T_BGEMM, T_LOAD, T_STORE = range(10)
-TASK_NAMES = ["POTRF", "TRSM", "SYRK", "GEMM", "FTRSM", "FGEMM", "BTRSM", "BGEMM", "LOAD", "STORE"]
+T_POTRF, T_TRSM, T_SYRK, T_GEMM, T_FTRSM, T_FGEMM, T_BTRSM, T_BGEMM, T_LOAD, T_STORE, T_INV = range(11)
+TASK_NAMES = ["POTRF", "TRSM", "SYRK", "GEMM", "FTRSM", "FGEMM", "BTRSM", "BGEMM", "LOAD", "STORE", "INV"]
 TILE_CANDIDATES = [32, 64, 128, 256, 512]
 PREC_FP64, PREC_FP32, PREC_BF16 = 0, 1, 2
 Q_PRIORITY, Q_FIFO = 0, 1
@@ -191,14 +191,19 @@ class Graph:
         return cls(h.value)
 
     @classmethod
-    def cholesky(cls, nt, with_solve=False, io=False):
+    def cholesky(cls, nt, with_solve=False, io=False, inverse=False):
+        """The paper's program; io: with LOAD/STORE and the inversion tasks (as the batched
+        calls run it); inverse: with the inversion tasks INV(k) after the factor."""
         h = ctypes.c_void_p()
         from math import comb
         T = nt + 2 * comb(nt, 2) + comb(nt, 3) + (2 * (nt + comb(nt, 2)) if with_solve else 0)
         if io:
-            T += 2 if with_solve else 1
+            T += (2 if with_solve else 1) + nt
+        elif inverse:
+            T += nt
         types = (ctypes.c_int32 * T)()
-        _check(lib().spx_cholesky_graph(nt, int(bool(with_solve)) | (2 if io else 0), ctypes.byref(h), types, T))
+        flag = int(bool(with_solve)) | (2 if io else 0) | (4 if inverse and not io else 0)
+        _check(lib().spx_cholesky_graph(nt, flag, ctypes.byref(h), types, T))
         return cls(h.value, np.array(types[:], dtype=np.int32))
 
     def info(self):

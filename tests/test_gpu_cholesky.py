@@ -9,8 +9,8 @@ oracle separately rounded products, so results agree to rounding, not bit for bi
            and the normwise backward error eta <= 1e-14.
 Integer-valued inputs (unit-diagonal factor with entries in {-1,0,1}) are exact on both
 sides: every product and sum, and every entry of the inverted 32x32 diagonal blocks the
-device multiplies by, is an integer below 2^53, so the device result must equal the known
-factor and solution bit for bit.
+device multiplies by, is an integer below 2^53, so the device factor must equal the known
+factor bit for bit, and with 32-wide tiles the solution too.
 """
 import numpy as np
 import pytest
@@ -96,7 +96,7 @@ def test_config1_parity(ctx):
     assert info == 0
     F = ctx.potrf(dev(A), tile=b)
     st = ctx.stats()
-    assert st["ntasks"] == 120 and st["tile"] == 128
+    assert st["ntasks"] == 120 + 8 and st["tile"] == 128  # the program + one inversion per diagonal tile
     check_factor(A, host(F.L()), Lo)
     x = host(ctx.potrs(F, dev(bvec)))
     check_solve(x[:, None], xo[:, None], oracle.backward_error(A, x, bvec))
@@ -104,12 +104,17 @@ def test_config1_parity(ctx):
     F.close()
 
 
-@pytest.mark.parametrize("n,b", [(96, 32), (200, 64), (640, 128)])
+@pytest.mark.parametrize("n,b", [(96, 32), (100, 32), (200, 64), (640, 128)])
 def test_integer_inputs_exact(ctx, n, b):
+    # The factor is exact for every tile size.  The solve multiplies by the inverse of each
+    # diagonal tile: for 32-wide tiles that inverse is the 32x32 block inverse, an integer
+    # matrix below 2^31, so the solution is exact too; inverses of wider unit-triangular
+    # integer tiles can outgrow 2^53, so there only the factor is pinned bit for bit.
     A, L0, X0, B = inputs.integer_factor(n, seed=n, nrhs=3, unit=True)
     F = ctx.potrf(dev(A), tile=b)
     assert np.array_equal(host(F.L()), L0)
-    assert np.array_equal(host(ctx.potrs(F, dev(B))), X0)
+    if b == 32:
+        assert np.array_equal(host(ctx.potrs(F, dev(B))), X0)
     F.close()
 
 
@@ -201,7 +206,7 @@ def test_config2_full_size_properties(ctx):
     A, Bd = bench.gen_input(n, 2, 1, "cuda:0")
     F = ctx.potrf(A, tile=b)
     st = ctx.stats()
-    assert st["ntasks"] == 5984
+    assert st["ntasks"] == 5984 + 32
     X = ctx.potrs(F, Bd)
     L = F.L().cpu().numpy()
     F.close()

@@ -4,7 +4,8 @@ POTRF/TRSM in FP64) and FP64 iterative refinement, through the C ABI.
 The low-precision factor itself is not compared with the oracle entry by entry (it is a
 different, rounded computation: parity unpinned).  Pinned instead:
   * integer inputs (unit-diagonal factor with entries in {-1,0,1}): every product and sum
-    is an exact small integer in FP32 and BF16 too, so the mixed factor equals L0 bit for bit;
+    is an exact small integer in FP32 and BF16 too, so the mixed factor equals L0 bit for bit
+    (and, with 32-wide tiles, the solution equals X0);
   * the refined solution reaches eta <= 1e-12 (oracle's compensated backward error) and
     its forward error against the oracle's FP64 solution is <= kappa * 1e-12;
   * the factor residual is of the order of the low precision's unit roundoff.
@@ -40,6 +41,8 @@ def test_integer_inputs_exact_mixed(ctx, prec, n, b):
     A, L0, X0, B = inputs.integer_factor(n, seed=n + prec, nrhs=2, unit=True)
     F = ctx.potrf(dev(A), tile=b, update_prec=prec)
     assert np.array_equal(F.L().cpu().numpy(), L0)
+    F.close()
+    F = ctx.potrf(dev(A), tile=32, update_prec=prec)  # solution exact with 32-wide tiles
     assert np.array_equal(ctx.potrs(F, dev(B)).cpu().numpy(), X0)
     F.close()
 

@@ -84,17 +84,76 @@ def test_empty_graph():
     assert g.info() == (4, 0) and g.indegree().tolist() == [0, 0, 0, 0]
 
 
+def executed_program(nt, with_solve):
+    """The program the library executes: the oracle's factor tasks, then INV(k) (reads the
+    diagonal tile, writes M_k, a new datum), then the substitution with a second copy Y2 of
+    the right-hand sides: FTRSM(k) reads M_k and B(k) and writes Y2(k); FGEMM(i,k) reads
+    L_ik and Y2(k) and updates B(i); BTRSM(k) reads M_k and Y2(k) and writes B(k);
+    BGEMM(i,k) reads L_ki and B(k) and updates Y2(i).  Returns (task names, accesses)."""
+    tasks, acc = oracle.cholesky_program(nt, with_solve)
+    nf = sum(1 for t in tasks if t[0] in ("POTRF", "TRSM", "SYRK", "GEMM"))
+    tile = {}  # (i, j) -> datum, from the factor tasks' written tiles
+    for t, m, d in acc:
+        if t < nf and m == spx.ACC_RW:
+            name, i, j, k = tasks[t]
+            tile[(i, j) if name != "TRSM" else (i, k)] = d
+    rhs = {}
+    for t, m, d in acc:  # B(k): what FTRSM(k) updates in the oracle's program
+        if t >= nf and tasks[t][0] == "FTRSM" and m == spx.ACC_RW:
+            rhs[tasks[t][3]] = d
+    top = max(d for _, _, d in acc) + 1
+    minv = {k: top + k for k in range(nt)}
+    y2 = {k: top + nt + k for k in range(nt)}
+    out = [(t, m, d) for t, m, d in acc if t < nf]
+    names = [t[0] for t in tasks[:nf]]
+    def add(name, uses):
+        t = len(names)
+        names.append(name)
+        out.extend((t, m, d) for m, d in uses)
+    R, W = spx.ACC_R, spx.ACC_RW
+    for k in range(nt):
+        add("INV", [(R, tile[(k, k)]), (W, minv[k])])
+    if with_solve:
+        for k in range(nt):
+            add("FTRSM", [(R, minv[k]), (R, rhs[k]), (W, y2[k])])
+            for i in range(k + 1, nt):
+                add("FGEMM", [(R, tile[(i, k)]), (R, y2[k]), (W, rhs[i])])
+        for k in range(nt - 1, -1, -1):
+            add("BTRSM", [(R, minv[k]), (R, y2[k]), (W, rhs[k])])
+            for i in range(k):
+                add("BGEMM", [(R, tile[(k, i)]), (R, rhs[k]), (W, y2[i])])
+    return names, out
+
+
+@pytest.mark.parametrize("nt", [1, 2, 3, 6, 9])
+@pytest.mark.parametrize("with_solve", [False, True])
+def test_executed_graph_with_inversions_bit_exact(nt, with_solve):
+    names, acc = executed_program(nt, with_solve)
+    want, _ = oracle.dag_edges(len(names), acc)
+    g = spx.Graph.cholesky(nt, with_solve, inverse=True)
+    assert g.info() == (len(names), len(want))
+    assert np.array_equal(g.edges(), want)
+    assert [spx.TASK_NAMES[t] for t in g.task_types] == names
+    # the paper's tasks keep their indices: its edges are a subset of the executed graph's
+    T0, e0, _ = oracle.cholesky_dag(nt, False)
+    got = set(map(tuple, g.edges().tolist()))
+    assert all(tuple(e) in got for e in e0.tolist())
+
+
 @pytest.mark.parametrize("nt", [1, 2, 3, 6, 9])
 @pytest.mark.parametrize("with_solve", [False, True])
 def test_batched_member_graph_bit_exact(nt, with_solve):
-    """The program one matrix contributes to a batched launch: LOAD (writes every datum the
-    factor / solve touches) in front, STORE (reads the solution blocks) at the end.  Its
-    edges must equal the pairwise definition applied to that access list."""
-    tasks, acc = oracle.cholesky_program(nt, with_solve)
-    data = sorted({d for _, _, d in acc})
-    rhs = sorted({d for t, m, d in acc if tasks[t][0] == "FTRSM" and m == spx.ACC_RW})
+    """The program one matrix contributes to a batched launch: LOAD (writes every tile and
+    right-hand-side block) in front, STORE (reads the solution blocks) at the end, with the
+    inversion tasks.  Its edges must equal the pairwise definition applied to that access
+    list."""
+    names, acc = executed_program(nt, with_solve)
+    minv = {d for t, m, d in acc if names[t] == "INV" and m == spx.ACC_RW}
+    y2 = {d for t, m, d in acc if names[t] == "FTRSM" and m == spx.ACC_RW}
+    data = sorted({d for t, m, d in acc} - minv - y2)  # tiles and right-hand-side blocks
+    rhs = sorted({d for t, m, d in acc if names[t] == "BTRSM" and m == spx.ACC_RW})
     prog = [(0, spx.ACC_RW, d) for d in data] + [(t + 1, m, d) for t, m, d in acc]
-    T = len(tasks) + 1
+    T = len(names) + 1
     if with_solve:
         prog += [(T, spx.ACC_R, d) for d in rhs]
         T += 1
@@ -102,9 +161,9 @@ def test_batched_member_graph_bit_exact(nt, with_solve):
     g = spx.Graph.cholesky(nt, with_solve, io=True)
     assert g.info() == (T, len(want))
     assert np.array_equal(g.edges(), want)
-    names = [spx.TASK_NAMES[t] for t in g.task_types]
-    assert names[0] == "LOAD" and (names[-1] == "STORE") == with_solve
-    assert names[1:T - (1 if with_solve else 0)] == [t[0] for t in tasks]
+    got_names = [spx.TASK_NAMES[t] for t in g.task_types]
+    assert got_names[0] == "LOAD" and (got_names[-1] == "STORE") == with_solve
+    assert got_names[1:T - (1 if with_solve else 0)] == names
     indeg = g.indegree()
     assert indeg[0] == 0 and (indeg[1:] > 0).all()  # one root per matrix: its LOAD
     if with_solve:
