@@ -103,8 +103,9 @@ void spx_graph_destroy(spx_graph* g);
  * backward substitution) inserts for nt x nt tiles, built with spx_graph_build: right-
  * looking, lower triangle; for k: POTRF(k); TRSM(i,k) i>k; SYRK(i,k) and GEMM(i,j,k)
  * k<j<i.  with_solve bit 1 adds the LOAD task in front (and, with bit 0, STORE at the end)
- * as the batched calls run it; bit 2 appends INV(k) for every k after the factor tasks
- * (as every graph the library executes does).  Datum ids: tile (i,j) -> i*nt + j,
+ * as the batched calls run it; bit 2 appends INV(k) for every k after the factor tasks and
+ * makes the substitution use M_k with a second right-hand-side copy (as the library runs
+ * every graph whose factor is kept; one-shot batched solves use the in-place program).  Datum ids: tile (i,j) -> i*nt + j,
  * right-hand-side block k -> nt*nt + k, M_k -> nt*nt + nt + k.  task_types (nullable,
  * ntasks entries) receives SPX_T_* codes. */
 enum { SPX_T_POTRF = 0, SPX_T_TRSM, SPX_T_SYRK, SPX_T_GEMM, SPX_T_FTRSM, SPX_T_FGEMM, SPX_T_BTRSM, SPX_T_BGEMM,
@@ -184,6 +185,8 @@ typedef struct {
   double tol;
   int32_t max_iter;
   int32_t method;
+  int32_t x_init; /* nonzero: dX already holds a first solution (skip the initial solve) */
+  int32_t pad;
 } spx_refine;
 typedef struct {
   int32_t iters;
@@ -229,11 +232,12 @@ int spx_run_task(spx_ctx* ctx, int32_t type, int32_t i, int32_t j, int32_t k, in
  *   info: host array of count entries: 0, or the 1-based failing column of that matrix
  *   (its X is then not written).  A failure of one matrix does not stop the others.
  *   spx_potrf_batched returns one factor handle per matrix in out (NULL where info > 0),
- *   usable with spx_potrs and spx_factor_get_l; spx_posv_batched keeps no factor.
+ *   usable with spx_potrs and spx_factor_get_l; spx_posv_batched returns them in keep when
+ *   keep is not NULL (count entries), else keeps none (one workspace for the batch).
  * Errors: SPX_EINVAL, SPX_ENOMEM, SPX_EDEVICE, SPX_ETIMEOUT. */
 int spx_posv_batched(spx_ctx* ctx, int32_t count, const int64_t* n, const double* const* dA, const int64_t* lda,
                      const int64_t* nrhs, const double* const* dB, const int64_t* ldb, double* const* dX,
-                     const int64_t* ldx, const spx_opts* opts, int64_t* info);
+                     const int64_t* ldx, const spx_opts* opts, int64_t* info, spx_factor** keep);
 int spx_potrf_batched(spx_ctx* ctx, int32_t count, const int64_t* n, const double* const* dA, const int64_t* lda,
                       const spx_opts* opts, spx_factor** out, int64_t* info);
 

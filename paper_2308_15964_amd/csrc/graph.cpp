@@ -166,11 +166,13 @@ void cholesky_program(int nt, bool with_solve, std::vector<TaskDesc>& tasks, std
   }
   for (int k = 0; k < nt; ++k) {
     task(SPX_T_FTRSM, k, k, k);
+    tasks.back().pad = 1;  // the inverse-based, row-split variant
     use(SPX_ACC_R, Minv(k));
     use(SPX_ACC_R, B(k));
     use(SPX_ACC_RW, Y2(k));
     for (int i = k + 1; i < nt; ++i) {
       task(SPX_T_FGEMM, i, k, k);
+      tasks.back().pad = 1;
       use(SPX_ACC_R, A(i, k));
       use(SPX_ACC_R, Y2(k));
       use(SPX_ACC_RW, B(i));
@@ -178,11 +180,13 @@ void cholesky_program(int nt, bool with_solve, std::vector<TaskDesc>& tasks, std
   }
   for (int k = nt - 1; k >= 0; --k) {
     task(SPX_T_BTRSM, k, k, k);
+    tasks.back().pad = 1;
     use(SPX_ACC_R, Minv(k));
     use(SPX_ACC_R, Y2(k));
     use(SPX_ACC_RW, B(k));
     for (int i = 0; i < k; ++i) {
       task(SPX_T_BGEMM, i, k, k);
+      tasks.back().pad = 1;
       use(SPX_ACC_R, A(k, i));
       use(SPX_ACC_R, B(k));
       use(SPX_ACC_RW, Y2(i));
@@ -208,10 +212,11 @@ void solve_program(int nt, std::vector<TaskDesc>& tasks, std::vector<spx_access>
 // Program of one matrix in a batched or served graph: LOAD writes every tile (and the
 // right-hand-side blocks), so each tile's first update depends on it; STORE reads the
 // solution blocks after the backward substitution.
-void io_program(int nt, bool with_solve, std::vector<TaskDesc>& tasks, std::vector<spx_access>& acc) {
+void io_program(int nt, bool with_solve, std::vector<TaskDesc>& tasks, std::vector<spx_access>& acc,
+                bool with_inverse) {
   std::vector<TaskDesc> body;
   std::vector<spx_access> body_acc;
-  cholesky_program(nt, with_solve, body, body_acc, true);
+  cholesky_program(nt, with_solve, body, body_acc, with_inverse);
   auto A = [nt](int i, int j) { return (uint64_t)i * (uint64_t)nt + (uint64_t)j; };
   auto B = [nt](int k) { return (uint64_t)nt * (uint64_t)nt + (uint64_t)k; };
   tasks.clear();
@@ -358,7 +363,7 @@ int spx_cholesky_graph(int32_t nt, int32_t with_solve, spx_graph** out, int32_t*
     std::unique_ptr<spx_graph> g(new spx_graph());
     std::vector<spx_access> acc;
     if (with_solve & 2)
-      io_program(nt, (with_solve & 1) != 0, g->tasks, acc);
+      io_program(nt, (with_solve & 1) != 0, g->tasks, acc, (with_solve & 4) != 0);
     else
       cholesky_program(nt, (with_solve & 1) != 0, g->tasks, acc, (with_solve & 4) != 0);
     std::vector<int32_t> prio(g->tasks.size());

@@ -161,9 +161,11 @@ static int get_program(spx_ctx* c, char kind, int nt, const Program** out) {
   switch (kind) {
     case 'F': cholesky_program(nt, false, pr->tasks, acc, true); break;
     case 'S': solve_program(nt, pr->tasks, acc); break;
-    case 'L': io_program(nt, false, pr->tasks, acc); break;
+    case 'L': io_program(nt, false, pr->tasks, acc, true); break;
+    case 'P': io_program(nt, true, pr->tasks, acc, false); break;
+    case 'K': io_program(nt, true, pr->tasks, acc, true); break;
     case 'Q': solve_io_program(nt, pr->tasks, acc); break;
-    default: io_program(nt, true, pr->tasks, acc); break;
+    default: return fail(SPX_EINVAL, "unknown program kind");
   }
   std::vector<int32_t> prio(pr->tasks.size());
   for (size_t t = 0; t < pr->tasks.size(); ++t) prio[t] = cholesky_priority(pr->tasks[t], nt);
@@ -195,7 +197,7 @@ uint16_t parts_of(const TaskDesc& d, int b, int nrhs) {
     case SPX_T_SYRK: return (uint16_t)(ns * (ns + 1) / 2);
     case SPX_T_GEMM: return (uint16_t)(ns * ns);
     case SPX_T_FTRSM:
-    case SPX_T_BTRSM: return (uint16_t)((nrhs + 7) / 8 * (b / rows));
+    case SPX_T_BTRSM: return (uint16_t)((nrhs + 7) / 8 * (d.pad ? b / rows : 1));
     case SPX_T_FGEMM:
     case SPX_T_BGEMM: return (uint16_t)(b / rows);
     case SPX_T_INV: return (uint16_t)(b / trsm_rows_of(b));
@@ -216,8 +218,11 @@ static int level_of(int32_t prio, int policy) {
   return l < 0 ? 0 : (l > kMaxLevels - 1 ? kMaxLevels - 1 : l);
 }
 
-// kind 'F': factor; 'S': substitution alone; 'L': LOAD + factor; 'P': LOAD + factor +
-// substitution + STORE.
+// kind 'F': factor (+ inversions); 'S': substitution alone (with the inverses); 'L': LOAD +
+// factor + inversions; 'P': LOAD + factor + in-place substitution + STORE (one-shot
+// solves: the inversions would cost more than they save); 'K': LOAD + factor +
+// inversions + substitution with the inverses + STORE (factors kept for more solves);
+// 'Q': LOAD of the right-hand sides + substitution with the inverses + STORE.
 static int get_program(spx_ctx* c, char kind, int nt, const Program** out);
 
 // One matrix's share of an image: its program, descriptor index, tile size and
@@ -621,6 +626,7 @@ static int batched(spx_ctx* c, int count, const int64_t* n, const double* const*
   const char* who = solve ? "spx_posv_batched" : "spx_potrf_batched";
   if (!c || !n || !dA || !lda || !info || (solve && (!nrhs || !dB || !ldb || !dX || !ldx)) || (!solve && !fout))
     return failf(SPX_EINVAL, "%s: null argument", who);
+  const bool keep = fout != nullptr;  // per-matrix factor storage, handed to the caller
   if (count < 1 || count > (1 << 20)) return failf(SPX_EINVAL, "%s: count must be in [1, 2^20]", who);
   const int prec = o ? o->update_prec : SPX_PREC_FP64;
   if (prec != SPX_PREC_FP64 && prec != SPX_PREC_FP32 && prec != SPX_PREC_BF16)
@@ -645,16 +651,17 @@ static int batched(spx_ctx* c, int count, const int64_t* n, const double* const*
   }
   SPX_TRY(hipc(hipSetDevice(c->device), "hipSetDevice"));
   // storage: one workspace for the whole batch (posv) or one factor per matrix (potrf)
-  std::vector<size_t> off_t(count), off_d(count), off_r(count), off_l(count), off_m(count);
+  std::vector<size_t> off_t(count), off_d(count), off_r(count), off_l(count);
   size_t ws = 0;
   for (int m = 0; m < count; ++m) {
     const size_t b = bs[m], nt = nts[m], npad = nt * b;
     const size_t tb = nt * (nt + 1) / 2 * b * b * sizeof(double);
-    off_t[m] = ws; ws = align256(ws + tb);
-    off_d[m] = ws; ws = align256(ws + npad * 32 * sizeof(double));
-    off_m[m] = ws; ws = align256(ws + npad * b * sizeof(double));
-    off_r[m] = ws; ws = align256(ws + 2 * npad * (size_t)qs[m] * sizeof(double));
-    off_l[m] = ws; ws = align256(ws + (prec == SPX_PREC_FP64 ? 0 : tb / (prec == SPX_PREC_FP32 ? 2 : 4)));
+    if (!keep) {  // one-shot solve: in-place substitution, no tile inverses, one rhs copy
+      off_t[m] = ws; ws = align256(ws + tb);
+      off_d[m] = ws; ws = align256(ws + npad * 32 * sizeof(double));
+    }
+    off_r[m] = ws; ws = align256(ws + (keep ? 2 : 1) * npad * (size_t)qs[m] * sizeof(double));
+    off_l[m] = ws; ws = align256(ws + ((prec == SPX_PREC_FP64 || keep) ? 0 : tb / (prec == SPX_PREC_FP32 ? 2 : 4)));
   }
   char* block = nullptr;
   std::vector<std::unique_ptr<spx_factor>> fs;
@@ -672,7 +679,8 @@ static int batched(spx_ctx* c, int count, const int64_t* n, const double* const*
   if (solve) {
     block = (char*)dev_alloc(c, ws);
     if (!block) return failf(SPX_ENOMEM, "%s: workspace allocation failed (%zu bytes)", who, ws);
-  } else {
+  }
+  if (keep) {
     fs.resize(count);
     for (int m = 0; m < count; ++m) {
       std::unique_ptr<spx_factor> f(new spx_factor());
@@ -696,12 +704,13 @@ static int batched(spx_ctx* c, int count, const int64_t* n, const double* const*
     }
   }
   // image: concatenated per-matrix programs
-  std::string key = solve ? "P" : "L";
+  const char kind = solve ? (keep ? 'K' : 'P') : 'L';
+  std::string key(1, kind);
   key += ":" + std::to_string(policy);
   std::vector<Piece> pieces(count);
   for (int m = 0; m < count; ++m) {
     const Program* pr = nullptr;
-    int rc = get_program(c, solve ? 'P' : 'L', nts[m], &pr);
+    int rc = get_program(c, kind, nts[m], &pr);
     if (rc) {
       release();
       return rc;
@@ -718,22 +727,23 @@ static int batched(spx_ctx* c, int count, const int64_t* n, const double* const*
   }
   for (int m = 0; m < count; ++m) {
     DevMat d{};
-    if (solve) {
-      d.tiles = (double*)(block + off_t[m]);
-      d.dinv = (double*)(block + off_d[m]);
-      d.minv = (double*)(block + off_m[m]);
-      d.rhs = (double*)(block + off_r[m]);
-      d.rhs2 = d.rhs + (size_t)nts[m] * bs[m] * (size_t)qs[m];
-      d.low = prec == SPX_PREC_FP64 ? nullptr : (void*)(block + off_l[m]);
-      d.B = dB[m];
-      d.X = dX[m];
-      d.ldb = ldb[m];
-      d.ldx = ldx[m];
-    } else {
+    if (keep) {
       d.tiles = fs[m]->tiles;
       d.dinv = fs[m]->dinv;
       d.minv = fs[m]->minv;
       d.low = fs[m]->low;
+    } else {
+      d.tiles = (double*)(block + off_t[m]);
+      d.dinv = (double*)(block + off_d[m]);
+      d.low = prec == SPX_PREC_FP64 ? nullptr : (void*)(block + off_l[m]);
+    }
+    if (solve) {
+      d.rhs = (double*)(block + off_r[m]);
+      if (keep) d.rhs2 = d.rhs + (size_t)nts[m] * bs[m] * (size_t)qs[m];
+      d.B = dB[m];
+      d.X = dX[m];
+      d.ldb = ldb[m];
+      d.ldx = ldx[m];
     }
     d.info = c->dinfo + m;
     d.n_pad = (int64_t)nts[m] * bs[m];
@@ -756,7 +766,7 @@ static int batched(spx_ctx* c, int count, const int64_t* n, const double* const*
   }
   for (int m = 0; m < count; ++m) {
     info[m] = c->hinfo[m] == INT_MAX ? 0 : c->hinfo[m];
-    if (!solve) {
+    if (keep) {
       if (info[m] == 0) {
         fout[m] = fs[m].release();
       } else {
@@ -781,9 +791,11 @@ const char* spx_last_error(void) { return g_err.c_str(); }
 
 int spx_posv_batched(spx_ctx* c, int32_t count, const int64_t* n, const double* const* dA, const int64_t* lda,
                      const int64_t* nrhs, const double* const* dB, const int64_t* ldb, double* const* dX,
-                     const int64_t* ldx, const spx_opts* opts, int64_t* info) {
+                     const int64_t* ldx, const spx_opts* opts, int64_t* info, spx_factor** keep) {
+  if (keep && count > 0)
+    for (int m = 0; m < count; ++m) keep[m] = nullptr;
   try {
-    return batched(c, count, n, dA, lda, nrhs, dB, ldb, dX, ldx, opts, true, nullptr, info);
+    return batched(c, count, n, dA, lda, nrhs, dB, ldb, dX, ldx, opts, true, keep, info);
   } catch (const std::bad_alloc&) {
     return fail(SPX_ENOMEM, "spx_posv_batched: out of host memory");
   }
@@ -820,8 +832,10 @@ int spx_potrs_batched(spx_ctx* c, int32_t count, spx_factor* const* f, const int
     std::vector<int> all(count);
     for (int m = 0; m < count; ++m) all[m] = m;
     double ms = 0.0;
-    SPX_TRY(batched_solve(c, all, f, nrhs, dB, ldb, dX, ldx, false));
-    ms += c->last.kernel_ms;
+    if (!(refine && refine->x_init && method)) {
+      SPX_TRY(batched_solve(c, all, f, nrhs, dB, ldb, dX, ldx, false));
+      ms += c->last.kernel_ms;
+    }
     std::vector<int> iters(count, 0);
     std::vector<double> eta(count, -1.0);
     if (want_eta) {
@@ -1281,7 +1295,12 @@ int spx_potrs(spx_ctx* c, const spx_factor* f, int64_t nrhs, const double* dB, i
   for (void* p : bufs)
     if (!p) rc = fail(SPX_ENOMEM, "spx_potrs: work buffer allocation failed");
   double solve_ms = 0.0;
-  if (!rc) rc = apply_inverse(c, f, q, dB, ldb, X, ldw, 0, rhs, &solve_ms);
+  const bool x_init = refine && refine->x_init && method;
+  if (!rc && x_init && X != dX)
+    rc = hipc(hipMemcpy2DAsync(X, (size_t)ldw * 8, dX, (size_t)ldx * 8, (size_t)q * 8, (size_t)n, hipMemcpyDeviceToDevice,
+                               c->stream),
+              "copy");
+  if (!rc && !x_init) rc = apply_inverse(c, f, q, dB, ldb, X, ldw, 0, rhs, &solve_ms);
   int iters = 0;
   double eta_max = -1.0;
   const double tol = (refine && refine->tol > 0) ? refine->tol : 1e-12;
@@ -1417,7 +1436,7 @@ int spx_run_task(spx_ctx* c, int32_t type, int32_t i, int32_t j, int32_t k, int3
   d.i = (uint16_t)i;
   d.j = (uint16_t)j;
   d.k = (uint16_t)k;
-  d.nparts = parts_of(d, b, nrhs);
+  d.nparts = parts_of(d, b, nrhs);  // pad = 0: the in-place substitution kernels
   // block inverses of the diagonal tile the task reads (written by a POTRF task itself)
   double* dinv = (double*)dev_alloc(c, (size_t)nt * 32 * b * sizeof(double));
   if (!dinv) return fail(SPX_ENOMEM, "spx_run_task: allocation failed");
@@ -1430,30 +1449,10 @@ int spx_run_task(spx_ctx* c, int32_t type, int32_t i, int32_t j, int32_t k, int3
       return rc;
     }
   }
-  // the diagonal solves read M_k = L_kk^{-T}, made first by the inversion task
-  const bool needs_inv = type == SPX_T_FTRSM || type == SPX_T_BTRSM;
-  double* minv = needs_inv ? (double*)dev_alloc(c, (size_t)nt * b * b * sizeof(double)) : nullptr;
-  if (needs_inv && !minv) {
-    dev_free(c, dinv);
-    return fail(SPX_ENOMEM, "spx_run_task: allocation failed");
-  }
-  // the diagonal solves read block k of one right-hand-side buffer and write it to a
-  // second one (FTRSM: rhs -> rhs2, then copied back; BTRSM: rhs2 <- rhs first, result in
-  // rhs); the updates read and write the caller's buffer
-  const size_t qbytes = (size_t)nt * b * (size_t)(nrhs > 0 ? nrhs : 1) * sizeof(double);
-  double* rhs2 = needs_inv ? (double*)dev_alloc(c, qbytes) : d_rhs;
-  if (needs_inv && !rhs2) {
-    dev_free(c, dinv);
-    dev_free(c, minv);
-    return fail(SPX_ENOMEM, "spx_run_task: allocation failed");
-  }
-  const size_t pitch = (size_t)nt * b * sizeof(double);
   DevMat m{};
   m.tiles = d_tiles;
   m.dinv = dinv;
-  m.minv = minv;
   m.rhs = d_rhs;
-  m.rhs2 = rhs2;
   m.info = c->dinfo;
   m.n_pad = (int64_t)nt * b;
   m.nt = nt;
@@ -1468,29 +1467,11 @@ int spx_run_task(spx_ctx* c, int32_t type, int32_t i, int32_t j, int32_t k, int3
   SchedArgs a{};
   a.tasks = c->dtask;
   a.mats = c->dmats;
-  TaskDesc inv;
-  inv.type = SPX_T_INV;
-  inv.i = inv.j = inv.k = (uint16_t)k;
-  inv.nparts = parts_of(inv, b, nrhs);
-  if (!rc && needs_inv) {
-    rc = hipc(hipMemcpyAsync(c->dtask, &inv, sizeof inv, hipMemcpyHostToDevice, c->stream), "task upload");
-    if (!rc) rc = launch_one_task(a, inv.nparts, c->stream);
-  }
-  if (!rc && type == SPX_T_BTRSM)
-    rc = hipc(hipMemcpy2DAsync(rhs2 + (size_t)k * b, pitch, d_rhs + (size_t)k * b, pitch, (size_t)b * 8, nrhs,
-                               hipMemcpyDeviceToDevice, c->stream),
-              "copy");
   if (!rc) rc = hipc(hipMemcpyAsync(c->dtask, &d, sizeof d, hipMemcpyHostToDevice, c->stream), "task upload");
   if (!rc) rc = launch_one_task(a, d.nparts, c->stream);
-  if (!rc && type == SPX_T_FTRSM)
-    rc = hipc(hipMemcpy2DAsync(d_rhs + (size_t)k * b, pitch, rhs2 + (size_t)k * b, pitch, (size_t)b * 8, nrhs,
-                               hipMemcpyDeviceToDevice, c->stream),
-              "copy");
   if (!rc) rc = hipc(hipMemcpyAsync(c->hinfo, c->dinfo, 4, hipMemcpyDeviceToHost, c->stream), "info");
   if (!rc) rc = hipc(hipStreamSynchronize(c->stream), "hipStreamSynchronize");
   dev_free(c, dinv);
-  dev_free(c, minv);
-  if (needs_inv) dev_free(c, rhs2);
   if (rc) return rc;
   *info = c->hinfo[0] == INT_MAX ? 0 : c->hinfo[0];
   return SPX_OK;

@@ -194,7 +194,7 @@ void run_batch(spx_server* s, Lane& ln, int lane_id, std::vector<Work>& w) {
     spx_opts o64 = o;
     o64.update_prec = SPX_PREC_FP64;
     int r = spx_posv_batched(c, k, n2.data(), A2.data(), lda2.data(), q2.data(), B2.data(), ldb2.data(), X2.data(),
-                             ldx2.data(), &o64, info2.data());
+                             ldx2.data(), &o64, info2.data(), nullptr);
     if (r) return r;
     std::vector<int> ok;
     for (int j = 0; j < k; ++j) {
@@ -222,11 +222,12 @@ void run_batch(spx_server* s, Lane& ln, int lane_id, std::vector<Work>& w) {
     for (int i = 0; i < K; ++i) all[i] = i;
     rc = fp64(all);
   } else if (!rc) {
-    // FP32-update factor, then batched FP64 refinement; what does not converge is redone
-    // in FP64
+    // FP32-update factor and first solve in one launch (factors kept), then batched FP64
+    // refinement from that solution; what does not converge is redone in FP64
     o.update_prec = SPX_PREC_FP32;
     std::vector<spx_factor*> f(K, nullptr);
-    rc = spx_potrf_batched(c, K, n.data(), A.data(), lda.data(), &o, f.data(), info.data());
+    rc = spx_posv_batched(c, K, n.data(), A.data(), lda.data(), q.data(), B.data(), ldb.data(), X.data(), ldx.data(),
+                          &o, info.data(), f.data());
     std::vector<int> good, redo;
     for (int i = 0; !rc && i < K; ++i) (f[i] ? good : redo).push_back(i);
     if (!rc && !good.empty()) {
@@ -242,7 +243,7 @@ void run_batch(spx_server* s, Lane& ln, int lane_id, std::vector<Work>& w) {
         A2[j] = A[i], B2[j] = B[i], X2[j] = X[i];
       }
       const double tol = w[good[0]].r.tol > 0 ? w[good[0]].r.tol : 1e-12;
-      spx_refine ref{tol, 50, 1};
+      spx_refine ref{tol, 50, 1, 1, 0};
       rc = spx_potrs_batched(c, k, f2.data(), q2.data(), B2.data(), ldb2.data(), X2.data(), ldx2.data(), A2.data(),
                              lda2.data(), &ref, ss.data());
       for (int j = 0; !rc && j < k; ++j) {

@@ -24,7 +24,8 @@ struct Graph {
 };
 
 // Device task descriptor (16 bytes).  `level` is the ready-queue level (0 = served
-// first); `nparts` the number of workgroup-sized pieces the task is cut into.
+// first); `nparts` the number of workgroup-sized pieces the task is cut into; `pad` = 1
+// marks the diagonal solves that use the tile inverse M_k (row-split, out of place).
 struct TaskDesc {
   uint8_t type = 0;
   uint8_t level = 0;
@@ -40,8 +41,10 @@ void cholesky_program(int nt, bool with_solve, std::vector<TaskDesc>& tasks, std
                       bool with_inverse = false);
 void solve_program(int nt, std::vector<TaskDesc>& tasks, std::vector<spx_access>& acc);
 int32_t cholesky_priority(const TaskDesc& d, int nt);
-// LOAD, the factor program (and with_solve: the substitution), STORE (with_solve only).
-void io_program(int nt, bool with_solve, std::vector<TaskDesc>& tasks, std::vector<spx_access>& acc);
+// LOAD, the factor program (and with_solve: the substitution), STORE (with_solve only);
+// with_inverse: the inversion tasks and the inverse-based substitution.
+void io_program(int nt, bool with_solve, std::vector<TaskDesc>& tasks, std::vector<spx_access>& acc,
+                bool with_inverse);
 // LOAD of the right-hand sides only (TaskDesc.j = 1), the substitution, STORE.
 void solve_io_program(int nt, std::vector<TaskDesc>& tasks, std::vector<spx_access>& acc);
 

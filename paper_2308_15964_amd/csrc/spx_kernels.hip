@@ -553,12 +553,16 @@ __device__ int potrf_tile(double* __restrict__ a, int b, double* __restrict__ di
 // block inverse (K = 32).  In mixed precision the solved block is also written as the FP32
 // or BF16 copy the updates read.
 // ---------------------------------------------------------------------------------------
+// k0: the strip's columns before k0 (a multiple of 32) are zero and stay zero (the
+// inversion task starts at its identity rows' diagonal); the updates skip them.
 __device__ void trsm_part(double* __restrict__ x, const double* __restrict__ l, const double* __restrict__ dinv,
-                          int b, int r0, int R, void* __restrict__ low, int prec, double* __restrict__ lds) {
+                          int b, int r0, int R, void* __restrict__ low, int prec, double* __restrict__ lds,
+                          int k0 = 0) {
   const int tid = threadIdx.x;
   double* xr = x + r0;
-  for (int c0 = 0; c0 < b; c0 += 32) {
-    gemm_tall32_any(xr + (size_t)c0 * b, b, xr, b, l + c0, b, R, c0, false, lds);
+  for (int c0 = k0; c0 < b; c0 += 32) {
+    gemm_tall32_any(xr + (size_t)c0 * b, b, xr + (size_t)k0 * b, b, l + (size_t)k0 * b + c0, b, R, c0 - k0, false,
+                    lds);
     __syncthreads();
     apply_inv_tall(xr + (size_t)c0 * b, b, dinv + (size_t)c0 * 32, R, lds);
     __syncthreads();
@@ -608,6 +612,144 @@ __device__ void tile_inverses(const double* __restrict__ l, int b, double* __res
 // ---------------------------------------------------------------------------------------
 // Solve tasks on the right-hand side y (column-major, ld = n_pad), columns [q0, q0+nq).
 // ---------------------------------------------------------------------------------------
+
+// In-place block substitution (when no inverse of the diagonal tile was made): forward
+// substitution of one diagonal tile for up to 8 right-hand sides: y_k <- L_kk^{-1}
+// y_k, block by block (32 rows) with the inverted 32x32 diagonal blocks: y_blk <- Li y_blk,
+// then the rows below lose L(rows, blk) y_blk.  The whole block of right-hand sides stays in
+// LDS; thread t owns rows t and t + 256 of the trailing update, whose L strip for the next
+// block is loaded into registers while the current block is solved, and the next block
+// inverse is loaded into the other half of a double buffer.  Only the block-inverse
+// products change the arithmetic order relative to a substitution.
+__device__ void ftrsm_sub_part(const double* __restrict__ l, const double* __restrict__ dinv, int b,
+                           double* __restrict__ y, int64_t ldy, int q0, int nq, double* __restrict__ lds) {
+  const int tid = threadIdx.x;
+  double* ys = lds;            // [8][b] right-hand sides
+  double* Lb = lds + 8 * 512;  // two 32x32 block inverses
+  double* yb = Lb + 2048;      // [8][32] the block just solved
+  const int q = tid >> 5, r = tid & 31;
+  for (int e = tid; e < 8 * b; e += NT) {
+    const int qq = e / b, m = e % b;
+    ys[e] = qq < nq ? y[(size_t)(q0 + qq) * ldy + m] : 0.0;
+  }
+  for (int e = tid; e < 1024; e += NT) Lb[e] = dinv[e];
+  double lv[2][32];
+  auto load_strip = [&](int c0) {
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int row = tid + NT * j;
+      if (row >= c0 + 32 && row < b) {
+#pragma unroll
+        for (int c = 0; c < 32; ++c) lv[j][c] = l[(size_t)(c0 + c) * b + row];
+      }
+    }
+  };
+  load_strip(0);
+  int buf = 0;
+  for (int c0 = 0; c0 < b; c0 += 32) {
+    __syncthreads();  // block c0 of ys and the inverse in Lb[buf] are ready
+    if (c0 + 32 < b)
+      for (int e = tid; e < 1024; e += NT) Lb[(buf ^ 1) * 1024 + e] = dinv[(size_t)(c0 + 32) * 32 + e];
+    const double* Li = Lb + buf * 1024;
+    if (q < nq) {
+      double sacc = 0.0;
+      for (int c = 0; c <= r; ++c) sacc += Li[c * 32 + r] * ys[q * b + c0 + c];
+      yb[q * 32 + r] = sacc;
+    }
+    __syncthreads();
+    if (q < nq) ys[q * b + c0 + r] = yb[q * 32 + r];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int row = tid + NT * j;
+      if (row >= c0 + 32 && row < b) {
+        double acc[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc[u] = 0.0;
+#pragma unroll
+        for (int c = 0; c < 32; ++c)
+#pragma unroll
+          for (int u = 0; u < 8; ++u) acc[u] += lv[j][c] * yb[u * 32 + c];
+        for (int u = 0; u < nq; ++u) ys[u * b + row] -= acc[u];
+      }
+    }
+    if (c0 + 32 < b) load_strip(c0 + 32);
+    buf ^= 1;
+  }
+  __syncthreads();
+  for (int e = tid; e < nq * b; e += NT) {
+    const int qq = e / b, m = e % b;
+    y[(size_t)(q0 + qq) * ldy + m] = ys[e];
+  }
+}
+
+// Backward: y_k <- L_kk^{-T} y_k, blocks from the last one down: x_blk = Li^T y_blk, then
+// the rows above lose L(blk, rows)^T x_blk.  Row t's strip L(c0 .. c0+31, t) is contiguous
+// (column t of the tile); otherwise as the forward substitution.
+__device__ void btrsm_sub_part(const double* __restrict__ l, const double* __restrict__ dinv, int b,
+                           double* __restrict__ y, int64_t ldy, int q0, int nq, double* __restrict__ lds) {
+  const int tid = threadIdx.x;
+  double* ys = lds;
+  double* Lb = lds + 8 * 512;
+  double* yb = Lb + 2048;
+  const int q = tid >> 5, r = tid & 31;
+  for (int e = tid; e < 8 * b; e += NT) {
+    const int qq = e / b, m = e % b;
+    ys[e] = qq < nq ? y[(size_t)(q0 + qq) * ldy + m] : 0.0;
+  }
+  for (int e = tid; e < 1024; e += NT) Lb[e] = dinv[(size_t)(b - 32) * 32 + e];
+  double lv[2][32];
+  auto load_strip = [&](int c0) {
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int row = tid + NT * j;
+      if (row < c0) {
+        const double2* src = reinterpret_cast<const double2*>(l + (size_t)row * b + c0);
+#pragma unroll
+        for (int c = 0; c < 16; ++c) {
+          const double2 v = src[c];
+          lv[j][2 * c] = v.x;
+          lv[j][2 * c + 1] = v.y;
+        }
+      }
+    }
+  };
+  load_strip(b - 32);
+  int buf = 0;
+  for (int c0 = b - 32; c0 >= 0; c0 -= 32) {
+    __syncthreads();
+    if (c0 > 0)
+      for (int e = tid; e < 1024; e += NT) Lb[(buf ^ 1) * 1024 + e] = dinv[(size_t)(c0 - 32) * 32 + e];
+    const double* Li = Lb + buf * 1024;
+    if (q < nq) {
+      double sacc = 0.0;
+      for (int c = r; c < 32; ++c) sacc += Li[r * 32 + c] * ys[q * b + c0 + c];  // Li(c, r)
+      yb[q * 32 + r] = sacc;
+    }
+    __syncthreads();
+    if (q < nq) ys[q * b + c0 + r] = yb[q * 32 + r];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int row = tid + NT * j;
+      if (row < c0) {
+        double acc[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc[u] = 0.0;
+#pragma unroll
+        for (int c = 0; c < 32; ++c)
+#pragma unroll
+          for (int u = 0; u < 8; ++u) acc[u] += lv[j][c] * yb[u * 32 + c];
+        for (int u = 0; u < nq; ++u) ys[u * b + row] -= acc[u];
+      }
+    }
+    if (c0 > 0) load_strip(c0 - 32);
+    buf ^= 1;
+  }
+  __syncthreads();
+  for (int e = tid; e < nq * b; e += NT) {
+    const int qq = e / b, m = e % b;
+    y[(size_t)(q0 + qq) * ldy + m] = ys[e];
+  }
+}
 
 // Diagonal solves with M = L_kk^{-T} (column-major b x b, upper triangular: made by the
 // inversion task, exact zeros below its diagonal), rows [r0, r0 + rows) of the result for
@@ -914,7 +1056,15 @@ __device__ void run_part(const SchedArgs& a, uint32_t task, uint32_t part, doubl
     }
     case SPX_T_FTRSM:
     case SPX_T_BTRSM: {
-      // part -> (group of 8 right-hand sides, strip of 64 rows)
+      if (!d.pad) {  // in-place block substitution, one part per group of 8 right-hand sides
+        const int q0 = part * 8, nq = (m.nrhs - q0) < 8 ? (m.nrhs - q0) : 8;
+        if (d.type == SPX_T_FTRSM)
+          ftrsm_sub_part(tile_ptr(m, d.k, d.k), dinv_ptr(m, d.k), b, m.rhs + (size_t)d.k * b, m.n_pad, q0, nq, lds);
+        else
+          btrsm_sub_part(tile_ptr(m, d.k, d.k), dinv_ptr(m, d.k), b, m.rhs + (size_t)d.k * b, m.n_pad, q0, nq, lds);
+        break;
+      }
+      // with M_k: part -> (group of 8 right-hand sides, strip of 64 rows)
       const int rows = b < 64 ? b : 64, nrp = b / rows;
       const int q0 = ((int)part / nrp) * 8, nq = (m.nrhs - q0) < 8 ? (m.nrhs - q0) : 8;
       const int r0 = ((int)part % nrp) * rows;
@@ -934,19 +1084,21 @@ __device__ void run_part(const SchedArgs& a, uint32_t task, uint32_t part, doubl
         x[(size_t)c * b + r0 + r] = (r0 + r == c) ? 1.0 : 0.0;
       }
       __syncthreads();
-      trsm_part(x, tile_ptr(m, d.k, d.k), dinv_ptr(m, d.k), b, r0, R, nullptr, PREC_FP64, lds);
+      trsm_part(x, tile_ptr(m, d.k, d.k), dinv_ptr(m, d.k), b, r0, R, nullptr, PREC_FP64, lds, r0 & ~31);
       break;
     }
     case SPX_T_FGEMM: {
       const int rows = b < 64 ? b : 64;
-      fgemm_part(tile_ptr(m, d.i, d.k), b, m.rhs + (size_t)d.i * b, m.rhs2 + (size_t)d.k * b, m.n_pad, m.nrhs,
+      fgemm_part(tile_ptr(m, d.i, d.k), b, m.rhs + (size_t)d.i * b, (d.pad ? m.rhs2 : m.rhs) + (size_t)d.k * b,
+                 m.n_pad, m.nrhs,
                  part * rows, rows, lds);
       break;
     }
     case SPX_T_BGEMM: {
       // task (i, k): y_i -= L_ki^T y_k; the tile is (k, i) with k = d.j
       const int rows = b < 64 ? b : 64;
-      bgemm_part(tile_ptr(m, d.j, d.i), b, m.rhs2 + (size_t)d.i * b, m.rhs + (size_t)d.j * b, m.n_pad, m.nrhs,
+      bgemm_part(tile_ptr(m, d.j, d.i), b, (d.pad ? m.rhs2 : m.rhs) + (size_t)d.i * b, m.rhs + (size_t)d.j * b,
+                 m.n_pad, m.nrhs,
                  part * rows, rows, lds);
       break;
     }

@@ -45,7 +45,8 @@ class Opts(ctypes.Structure):
 
 
 class Refine(ctypes.Structure):
-    _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("method", ctypes.c_int32)]
+    _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("method", ctypes.c_int32),
+                ("x_init", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
 
 class SolveStats(ctypes.Structure):
@@ -138,7 +139,7 @@ def lib():
         "spx_backward_error": (ctypes.c_int, [vp, i64, vp, i64, i64, vp, i64, vp, i64, P(ctypes.c_double)]),
         "spx_run_task": (ctypes.c_int, [vp, i32, i32, i32, i32, i32, i32, vp, vp, i32, P(i64)]),
         "spx_posv_batched": (ctypes.c_int, [vp, i32, P(i64), P(vp), P(i64), P(i64), P(vp), P(i64), P(vp), P(i64),
-                                             P(Opts), P(i64)]),
+                                             P(Opts), P(i64), P(vp)]),
         "spx_potrf_batched": (ctypes.c_int, [vp, i32, P(i64), P(vp), P(i64), P(Opts), P(vp), P(i64)]),
         "spx_potrs_batched": (ctypes.c_int, [vp, i32, P(vp), P(i64), P(vp), P(i64), P(vp), P(i64), P(vp), P(i64),
                                               P(Refine), P(SolveStats)]),
@@ -192,17 +193,18 @@ class Graph:
 
     @classmethod
     def cholesky(cls, nt, with_solve=False, io=False, inverse=False):
-        """The paper's program; io: with LOAD/STORE and the inversion tasks (as the batched
-        calls run it); inverse: with the inversion tasks INV(k) after the factor."""
+        """The paper's program; io: with LOAD in front (and STORE at the end with the
+        solve), as the batched calls run it; inverse: with the inversion tasks INV(k) after
+        the factor and the substitution that uses them."""
         h = ctypes.c_void_p()
         from math import comb
         T = nt + 2 * comb(nt, 2) + comb(nt, 3) + (2 * (nt + comb(nt, 2)) if with_solve else 0)
         if io:
-            T += (2 if with_solve else 1) + nt
-        elif inverse:
+            T += 2 if with_solve else 1
+        if inverse:
             T += nt
         types = (ctypes.c_int32 * T)()
-        flag = int(bool(with_solve)) | (2 if io else 0) | (4 if inverse and not io else 0)
+        flag = int(bool(with_solve)) | (2 if io else 0) | (4 if inverse else 0)
         _check(lib().spx_cholesky_graph(nt, flag, ctypes.byref(h), types, T))
         return cls(h.value, np.array(types[:], dtype=np.int32))
 
@@ -317,7 +319,7 @@ class Context:
             raise NotPositiveDefinite(info.value)
         return Factor(self, h.value)
 
-    def potrs(self, F, B, X=None, A=None, tol=0.0, max_iter=0, method=0, return_stats=False):
+    def potrs(self, F, B, X=None, A=None, tol=0.0, max_iter=0, method=0, return_stats=False, x_init=False):
         """Solves A X = B with the factor (B: n or n x nrhs float64 on the device)."""
         torch = self.torch
         B = self._dev(B, "B")
@@ -329,7 +331,7 @@ class Context:
             X2 = self._dev(X, "X").reshape(B2.shape)
         ref = None
         if method:
-            ref = Refine(tol, max_iter, method)
+            ref = Refine(tol, max_iter, method, int(x_init), 0)
         st = SolveStats()
         a_ptr, lda = (None, 0) if A is None else (_ptr(self._dev(A, "A")), A.stride(0))
         _check(lib().spx_potrs(self._h, F._h, B2.shape[1], _ptr(B2), B2.stride(0), _ptr(X2), X2.stride(0), a_ptr, lda,
@@ -376,8 +378,9 @@ class Context:
         return out
 
     def posv_batched(self, As, Bs, tile=0, update_prec=PREC_FP64, queue_policy=Q_PRIORITY, num_wg=0, flags=0,
-                     Xs=None):
-        """Factors and solves every (A_i, B_i) in one launch; returns (Xs, info array).
+                     Xs=None, keep=False):
+        """Factors and solves every (A_i, B_i) in one launch; returns (Xs, info array), and
+        with keep=True also the list of factors (None where info > 0).
         B_i: n_i x q_i float64 on the device (2-D)."""
         torch = self.torch
         if len(As) != len(Bs) or not As:
@@ -390,7 +393,10 @@ class Context:
         n, pa, lda, q, pb, ldb, px, ldx = self._batch_arrays(As, Bs, Xs)
         info = (ctypes.c_int64 * len(As))()
         o = Opts(tile, update_prec, queue_policy, num_wg, flags)
-        _check(lib().spx_posv_batched(self._h, len(As), n, pa, lda, q, pb, ldb, px, ldx, ctypes.byref(o), info))
+        hs = (ctypes.c_void_p * len(As))() if keep else None
+        _check(lib().spx_posv_batched(self._h, len(As), n, pa, lda, q, pb, ldb, px, ldx, ctypes.byref(o), info, hs))
+        if keep:
+            return Xs, np.array(info[:], dtype=np.int64), [Factor(self, h) if h else None for h in hs]
         return Xs, np.array(info[:], dtype=np.int64)
 
     def potrf_batched(self, As, tile=0, update_prec=PREC_FP64, queue_policy=Q_PRIORITY, num_wg=0, flags=0):
@@ -406,7 +412,7 @@ class Context:
         fs = [Factor(self, h) if h else None for h in hs]
         return fs, np.array(info[:], dtype=np.int64)
 
-    def potrs_batched(self, Fs, Bs, As=None, tol=0.0, max_iter=0, method=0, Xs=None):
+    def potrs_batched(self, Fs, Bs, As=None, tol=0.0, max_iter=0, method=0, Xs=None, x_init=False):
         """Solves with existing factors in batched launches (optionally refined against the
         original matrices As).  Returns (Xs, stats list)."""
         torch = self.torch
@@ -424,7 +430,7 @@ class Context:
         pa = lda = None
         if As is not None:
             pa, lda = vpa(*[self._dev(a, "A").data_ptr() for a in As]), i64a(*[a.stride(0) for a in As])
-        ref = Refine(tol, max_iter, method)
+        ref = Refine(tol, max_iter, method, int(x_init), 0)
         st = (SolveStats * k)()
         _check(lib().spx_potrs_batched(self._h, k, fh, q, pb, ldb, px, ldx, pa, lda, ctypes.byref(ref), st))
         return Xs, [{"iters": s.iters, "method_used": s.method_used, "eta_max": s.eta_max} for s in st]

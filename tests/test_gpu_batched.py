@@ -2,9 +2,12 @@
 one engine runs several task graphs), through the C ABI.
 
 Pinned against the oracle per matrix (same tolerances as the single-matrix parity tests)
-and against the single-matrix entry points: a batched member runs exactly the same tile
-kernels in the same dependency order as spx_potrf_tiled + spx_potrs with the same tile
-size, so the results must be bitwise equal.
+and against the single-matrix entry points.  A factor made in a batch runs exactly the
+same tile kernels in the same dependency order as spx_potrf_tiled with the same tile size,
+so it is bitwise equal, and so is a solve with kept factors to spx_potrs.  A one-shot
+batched solve (factors not kept) uses the in-place block substitution instead of the
+tile inverses, so it is pinned bitwise to a task-by-task replay of the same program
+through spx_run_task, and to the oracle within tolerance.
 """
 import numpy as np
 import pytest
@@ -50,16 +53,77 @@ def test_posv_batched_vs_oracle_and_single(ctx):
         Bs = [dev(B) for _, B in items]
         Xs, info = ctx.posv_batched(As, Bs, tile=tile)
         assert (info == 0).all()
-        for (A, B), Ad, Bd, X in zip(items, As, Bs, Xs):
+        Xk, info_k, fs = ctx.posv_batched(As, Bs, tile=tile, keep=True)
+        assert (info_k == 0).all()
+        for m, ((A, B), Ad, Bd, X) in enumerate(zip(items, As, Bs, Xs)):
             X = X.cpu().numpy()
             _, Xo, oi = oracle.cholesky(A, A.shape[0], B)
             assert oi == 0
             scale = np.abs(Xo).max(axis=0)
             assert (np.abs(X - Xo) <= 1e-12 * scale).all()
+            assert (np.abs(Xk[m].cpu().numpy() - Xo) <= 1e-12 * scale).all()
+            if m % 6 == 0:  # a member alone in its launch: the other members change nothing
+                X1, _ = ctx.posv_batched([Ad], [Bd], tile=tile)
+                assert np.array_equal(X, X1[0].cpu().numpy())
             F = ctx.potrf(Ad, tile=tile)
+            assert np.array_equal(fs[m].L().cpu().numpy(), F.L().cpu().numpy())
             Xs1 = ctx.potrs(F, Bd).cpu().numpy()
-            assert np.array_equal(X, Xs1)  # same kernels, same order: same bits
+            assert np.array_equal(Xk[m].cpu().numpy(), Xs1)  # same kernels, same order: same bits
             F.close()
+            fs[m].close()
+
+
+def pack_padded(A, b):
+    """Lower tiles of A padded with the identity to a multiple of b (column-major tiles)."""
+    n = A.shape[0]
+    nt = max(1, -(-n // b))
+    M = np.eye(nt * b)
+    M[:n, :n] = A
+    t = np.zeros((nt * (nt + 1) // 2, b * b))
+    for i in range(nt):
+        for j in range(i + 1):
+            t[i * (i + 1) // 2 + j] = M[i * b:(i + 1) * b, j * b:(j + 1) * b].T.ravel()
+    return t, nt
+
+
+def program_order(nt):
+    """The in-place factor + substitution program in insertion order (Sec. 5.2 task types)."""
+    out = []
+    for k in range(nt):
+        out.append(("POTRF", k, k, k))
+        out += [("TRSM", i, k, k) for i in range(k + 1, nt)]
+        for i in range(k + 1, nt):
+            out.append(("SYRK", i, i, k))
+            out += [("GEMM", i, j, k) for j in range(k + 1, i)]
+    for k in range(nt):
+        out.append(("FTRSM", k, k, k))
+        out += [("FGEMM", i, k, k) for i in range(k + 1, nt)]
+    for k in range(nt - 1, -1, -1):
+        out.append(("BTRSM", k, k, k))
+        out += [("BGEMM", i, k, k) for i in range(k)]
+    return out
+
+
+@pytest.mark.parametrize("tile", [32, 64])
+def test_one_shot_batched_solve_equals_task_replay(ctx, tile):
+    from paper_2308_15964_amd import spx
+
+    items = [inputs.batch_matrix(n, seed=900 + n, nrhs=q) for n, q in ((1, 1), (37, 3), (64, 9), (130, 2), (200, 17))]
+    As = [dev(A) for A, _ in items]
+    Bs = [dev(B) for _, B in items]
+    Xs, info = ctx.posv_batched(As, Bs, tile=tile)
+    assert (info == 0).all()
+    for (A, B), X in zip(items, Xs):
+        n, q = B.shape
+        print(f"replay n={n} nrhs={q} tile={tile}", flush=True)
+        t, nt = pack_padded(A, tile)
+        tiles = dev(t)
+        y = np.zeros((q, nt * tile))
+        y[:, :n] = B.T
+        rhs = dev(y)  # column-major n_pad x nrhs
+        for name, i, j, k in program_order(nt):
+            assert ctx.run_task(spx.TASK_NAMES.index(name), i, j, k, nt, tile, tiles, rhs, q) == 0
+        assert np.array_equal(X.cpu().numpy(), rhs.cpu().numpy()[:, :n].T)
 
 
 def test_potrf_batched_factors_bitwise_single(ctx):
@@ -119,12 +183,18 @@ def test_tile_table_and_mixed_tiles(ctx):
     items = batch(12, 10, 350, seed=14)
     As = [dev(A) for A, _ in items]
     Bs = [dev(B) for _, B in items]
-    Xs, info = ctx.posv_batched(As, Bs)  # tiles from the table, several sizes in one launch
+    Xs, info, fs = ctx.posv_batched(As, Bs, keep=True)  # tiles from the table, several sizes in one launch
     assert (info == 0).all()
-    for Ad, Bd, X in zip(As, Bs, Xs):
-        F = ctx.potrf(Ad, tile=ctx.tile_for(0, Ad.shape[0]))
+    X1s, info1 = ctx.posv_batched(As, Bs)
+    assert (info1 == 0).all()
+    for (A, B), Ad, Bd, X, X1, Fk in zip(items, As, Bs, Xs, X1s, fs):
+        assert Fk.tile == ctx.tile_for(0, Ad.shape[0])
+        F = ctx.potrf(Ad, tile=Fk.tile)
         assert np.array_equal(X.cpu().numpy(), ctx.potrs(F, Bd).cpu().numpy())
+        _, Xo, _ = oracle.cholesky(A, A.shape[0], B)
+        assert (np.abs(X1.cpu().numpy() - Xo) <= 1e-12 * np.abs(Xo).max(axis=0)).all()
         F.close()
+        Fk.close()
     ctx.set_tile_table(spx.PREC_FP64, [])
     assert ctx.tile_for(0, 5000) == 256
 
@@ -180,5 +250,27 @@ def test_potrs_batched_matches_single_and_refines(ctx, prec):
         assert oracle.backward_error(A, X.cpu().numpy(), B).max() <= 1e-12
     eta = ctx.backward_error_batched(As, Xr, Bs)
     assert np.array_equal(eta, np.array([s["eta_max"] for s in st]))
+    for F in fs:
+        F.close()
+
+
+def test_posv_batched_keeps_factors_and_refines_from_its_solution(ctx):
+    from paper_2308_15964_amd import spx
+
+    items = [inputs.reflector_spd(n, 1e5, seed=500 + n, nrhs=q) for n, q in ((70, 2), (300, 1), (513, 4))]
+    As = [dev(A) for A, _ in items]
+    Bs = [dev(B) for _, B in items]
+    Xs, info, fs = ctx.posv_batched(As, Bs, tile=64, update_prec=spx.PREC_FP32, keep=True)
+    assert (info == 0).all() and all(F is not None for F in fs)
+    for F, Bd, X in zip(fs, Bs, Xs):  # the fused solve equals a separate solve with the kept factor
+        assert np.array_equal(X.cpu().numpy(), ctx.potrs(F, Bd).cpu().numpy())
+    X0 = [x.clone() for x in Xs]
+    Xr, st = ctx.potrs_batched(fs, Bs, As=As, tol=1e-12, method=1, Xs=Xs, x_init=True)
+    for (A, B), F, Ad, Bd, x0, X, s in zip(items, fs, As, Bs, X0, Xr, st):
+        assert oracle.backward_error(A, X.cpu().numpy(), B).max() <= 1e-12
+        # the same as single refinement started from that solution
+        X1 = x0.clone()
+        X1, s1 = ctx.potrs(F, Bd, X=X1, A=Ad, tol=1e-12, method=1, return_stats=True, x_init=True)
+        assert np.array_equal(X.cpu().numpy(), X1.cpu().numpy()) and s["iters"] == s1["iters"]
     for F in fs:
         F.close()

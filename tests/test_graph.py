@@ -142,14 +142,20 @@ def test_executed_graph_with_inversions_bit_exact(nt, with_solve):
 
 @pytest.mark.parametrize("nt", [1, 2, 3, 6, 9])
 @pytest.mark.parametrize("with_solve", [False, True])
-def test_batched_member_graph_bit_exact(nt, with_solve):
+@pytest.mark.parametrize("inverse", [False, True])
+def test_batched_member_graph_bit_exact(nt, with_solve, inverse):
     """The program one matrix contributes to a batched launch: LOAD (writes every tile and
-    right-hand-side block) in front, STORE (reads the solution blocks) at the end, with the
-    inversion tasks.  Its edges must equal the pairwise definition applied to that access
-    list."""
-    names, acc = executed_program(nt, with_solve)
+    right-hand-side block) in front, STORE (reads the solution blocks) at the end; with the
+    inversion tasks and the inverse-based substitution (factors kept for later solves) or
+    with the paper's in-place substitution (one-shot solves).  Its edges must equal the
+    pairwise definition applied to that access list."""
+    if inverse:
+        names, acc = executed_program(nt, with_solve)
+    else:
+        tasks, acc = oracle.cholesky_program(nt, with_solve)
+        names = [t[0] for t in tasks]
     minv = {d for t, m, d in acc if names[t] == "INV" and m == spx.ACC_RW}
-    y2 = {d for t, m, d in acc if names[t] == "FTRSM" and m == spx.ACC_RW}
+    y2 = {d for t, m, d in acc if inverse and names[t] == "FTRSM" and m == spx.ACC_RW}
     data = sorted({d for t, m, d in acc} - minv - y2)  # tiles and right-hand-side blocks
     rhs = sorted({d for t, m, d in acc if names[t] == "BTRSM" and m == spx.ACC_RW})
     prog = [(0, spx.ACC_RW, d) for d in data] + [(t + 1, m, d) for t, m, d in acc]
@@ -158,7 +164,7 @@ def test_batched_member_graph_bit_exact(nt, with_solve):
         prog += [(T, spx.ACC_R, d) for d in rhs]
         T += 1
     want, kinds = oracle.dag_edges(T, prog)
-    g = spx.Graph.cholesky(nt, with_solve, io=True)
+    g = spx.Graph.cholesky(nt, with_solve, io=True, inverse=inverse)
     assert g.info() == (T, len(want))
     assert np.array_equal(g.edges(), want)
     got_names = [spx.TASK_NAMES[t] for t in g.task_types]
