@@ -186,7 +186,7 @@ static int default_tile(int64_t n) {
 }
 
 // Parts per task for tile size b and right-hand-side count nrhs.
-int trsm_rows_of(int b) { return b < 64 ? b : 64; }
+int trsm_rows_of(int /*b*/) { return 32; }  // the TRSM and inversion kernels take 32-row strips
 
 uint16_t parts_of(const TaskDesc& d, int b, int nrhs) {
   const int sb = b < 128 ? b : 128, ns = b / sb;

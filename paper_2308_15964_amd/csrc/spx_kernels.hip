@@ -19,7 +19,33 @@
 namespace spx {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef double d2 __attribute__((ext_vector_type(2)));
 typedef unsigned long long u64;
+
+// Global-memory views of the generic pointers the tile kernels receive.  Loads through
+// them compile to global_* instructions, which count only on vmcnt; generic (flat) loads
+// also count on lgkmcnt, so every wait for an LDS read would wait for them too.
+#define GLOBAL __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ const GLOBAL T* gp(const T* p) {
+  return (const GLOBAL T*)p;
+}
+template <class T>
+__device__ __forceinline__ GLOBAL T* gp(T* p) {
+  return (GLOBAL T*)p;
+}
+// LDS views of the generic pointers to the workgroup's shared buffer: in functions the
+// compiler keeps out of line it would otherwise rebuild every LDS address from the 64-bit
+// generic pointer (with a null check) at each access.
+#define LDSAS __attribute__((address_space(3)))
+template <class T>
+__device__ __forceinline__ const LDSAS T* lp(const T* p) {
+  return (const LDSAS T*)p;
+}
+template <class T>
+__device__ __forceinline__ LDSAS T* lp(T* p) {
+  return (LDSAS T*)p;
+}
 
 constexpr int NT = 256;                 // threads per workgroup (4 waves)
 constexpr int LDS_DOUBLES = 12288;      // 96 KiB of LDS per workgroup (one workgroup per CU)
@@ -40,6 +66,41 @@ __device__ __forceinline__ uint32_t ld_rlx(const uint32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Epilogue of the 2x2-wave updates, C -= acc over a wave's NB x NB blocks of 16 x 16.  The
+// products are formed transposed (the B fragment is the matrix core's first operand), so
+// lane l holds rows row0 + 16 i + l%16 of C: sixteen lanes cover sixteen consecutive
+// doubles of one column.  Element v of the accumulator is column col0 + 16 j + cofs(l, v):
+// (l/16 + 4v) for the FP64 form, (4(l/16) + v) for the FP32-accumulating forms.  Every old
+// value is loaded before any is stored, so the loads overlap.
+template <int NB, bool F64_LAYOUT, class ACC>
+__device__ __forceinline__ void update_epilogue(double* C, int ldc, const ACC (&acc)[NB][NB], int row0, int col0,
+                                                int M, int N, bool lower) {
+  const int lane = threadIdx.x & 63;
+  GLOBAL double* Cg = gp(C);
+  double old[NB][NB][4];
+#pragma unroll
+  for (int i = 0; i < NB; ++i)
+#pragma unroll
+    for (int j = 0; j < NB; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = row0 + i * 16 + (lane & 15);
+        const int col = col0 + j * 16 + (F64_LAYOUT ? (lane >> 4) + 4 * v : 4 * (lane >> 4) + v);
+        old[i][j][v] = (row < M && col < N && (!lower || row >= col)) ? Cg[(size_t)col * ldc + row] : 0.0;
+      }
+#pragma unroll
+  for (int i = 0; i < NB; ++i)
+#pragma unroll
+    for (int j = 0; j < NB; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = row0 + i * 16 + (lane & 15);
+        const int col = col0 + j * 16 + (F64_LAYOUT ? (lane >> 4) + 4 * v : 4 * (lane >> 4) + v);
+        if (row < M && col < N && (!lower || row >= col))
+          Cg[(size_t)col * ldc + row] = old[i][j][v] - (double)acc[i][j][v];
+      }
+}
+
 // ---------------------------------------------------------------------------------------
 // FP64 matrix-core update: C[M x N] -= A[M x K] * B[N x K]^T (all column-major).
 // Four waves in a 2x2 arrangement, each owning a WT x WT block of C made of 16x16
@@ -57,8 +118,8 @@ __device__ void gemm_nt_f64(double* __restrict__ C, int ldc, const double* __res
   constexpr int NB = WT / 16;
   constexpr int PAIRS = SB * KC / (2 * NT);  // double2 loads per thread per operand
   static_assert(PAIRS >= 1, "tile too small for one double2 per thread");
-  double* As = lds;
-  double* Bs = lds + KC * SB;
+  LDSAS double* As = lp(lds);
+  LDSAS double* Bs = lp(lds) + KC * SB;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = wave >> 1, wc = wave & 1;
   d4 acc[NB][NB];
@@ -67,22 +128,24 @@ __device__ void gemm_nt_f64(double* __restrict__ C, int ldc, const double* __res
 #pragma unroll
     for (int j = 0; j < NB; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
 
-  double2 ra[PAIRS], rb[PAIRS];
+  d2 ra[PAIRS], rb[PAIRS];
   auto gload = [&](int k0) {
+    const GLOBAL double* Ak = gp(A) + (size_t)k0 * lda;
+    const GLOBAL double* Bk = gp(B) + (size_t)k0 * ldb;
 #pragma unroll
     for (int p = 0; p < PAIRS; ++p) {
       const int e = (tid + p * NT) * 2;
       const int m = e / SB, r = e % SB;
-      ra[p] = (r < M) ? *reinterpret_cast<const double2*>(A + (size_t)(k0 + m) * lda + r) : double2{0.0, 0.0};
-      rb[p] = (r < N) ? *reinterpret_cast<const double2*>(B + (size_t)(k0 + m) * ldb + r) : double2{0.0, 0.0};
+      ra[p] = (r < M) ? *(const GLOBAL d2*)(Ak + m * lda + r) : d2{0.0, 0.0};
+      rb[p] = (r < N) ? *(const GLOBAL d2*)(Bk + m * ldb + r) : d2{0.0, 0.0};
     }
   };
   auto lstore = [&]() {
 #pragma unroll
     for (int p = 0; p < PAIRS; ++p) {
       const int e = (tid + p * NT) * 2;
-      *reinterpret_cast<double2*>(As + e) = ra[p];
-      *reinterpret_cast<double2*>(Bs + e) = rb[p];
+      *(LDSAS d2*)(As + e) = ra[p];
+      *(LDSAS d2*)(Bs + e) = rb[p];
     }
   };
   const int nchunks = K / KC;
@@ -103,7 +166,7 @@ __device__ void gemm_nt_f64(double* __restrict__ C, int ldc, const double* __res
 #pragma unroll
       for (int i = 0; i < NB; ++i)
 #pragma unroll
-        for (int j = 0; j < NB; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+        for (int j = 0; j < NB; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(b[j], a[i], acc[i][j], 0, 0, 0);
     }
     __syncthreads();
     if (c + 1 < nchunks) {
@@ -112,18 +175,9 @@ __device__ void gemm_nt_f64(double* __restrict__ C, int ldc, const double* __res
     }
   }
   // accumulator layout of v_mfma_f64_16x16x4 (measured on gfx950): element v of lane l
-  // holds (row l/16 + 4v, column l%16) of the 16x16 block
-#pragma unroll
-  for (int i = 0; i < NB; ++i)
-#pragma unroll
-    for (int j = 0; j < NB; ++j) {
-      const int col = wc * WT + j * 16 + (lane & 15);
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int row = wr * WT + i * 16 + (lane >> 4) + 4 * v;
-        if (row < M && col < N && (!lower || row >= col)) C[(size_t)col * ldc + row] -= acc[i][j][v];
-      }
-    }
+  // holds (row l/16 + 4v, column l%16) of the 16x16 product, here (B A^T): C row l%16,
+  // C column l/16 + 4v
+  update_epilogue<NB, true>(C, ldc, acc, wr * WT, wc * WT, M, N, lower);
 }
 
 // Dispatch on the block size: M, N <= 128.
@@ -145,6 +199,7 @@ __device__ void gemm_nt_any(double* C, int ldc, const double* A, int lda, const 
 // ---------------------------------------------------------------------------------------
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u4 __attribute__((ext_vector_type(4)));
 
 // FP32 copies, column-major (like the FP64 tiles); v_mfma_f32_16x16x4f32, whose result
 // element v of lane l is (row 4*(l/16)+v, column l%16) of the 16x16 block.
@@ -155,8 +210,8 @@ __device__ void gemm_nt_f32(double* __restrict__ C, int ldc, const float* __rest
   constexpr int SB = 2 * WT, KC = 32, NB = WT / 16;
   constexpr int QUADS = SB * KC / (4 * NT);  // float4 loads per thread per operand
   static_assert(QUADS >= 1, "tile too small");
-  float* As = reinterpret_cast<float*>(lds_d);
-  float* Bs = As + KC * SB;
+  LDSAS float* As = lp(reinterpret_cast<float*>(lds_d));
+  LDSAS float* Bs = As + KC * SB;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = wave >> 1, wc = wave & 1;
   f4 acc[NB][NB];
@@ -164,22 +219,22 @@ __device__ void gemm_nt_f32(double* __restrict__ C, int ldc, const float* __rest
   for (int i = 0; i < NB; ++i)
 #pragma unroll
     for (int j = 0; j < NB; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
-  float4 ra[QUADS], rb[QUADS];
+  f4 ra[QUADS], rb[QUADS];
   auto gload = [&](int k0) {
 #pragma unroll
     for (int p = 0; p < QUADS; ++p) {
       const int e = (tid + p * NT) * 4;
       const int m = e / SB, r = e % SB;
-      ra[p] = (r < M) ? *reinterpret_cast<const float4*>(A + (size_t)(k0 + m) * lda + r) : float4{0.f, 0.f, 0.f, 0.f};
-      rb[p] = (r < N) ? *reinterpret_cast<const float4*>(B + (size_t)(k0 + m) * ldb + r) : float4{0.f, 0.f, 0.f, 0.f};
+      ra[p] = (r < M) ? *(const GLOBAL f4*)(gp(A) + (size_t)(k0 + m) * lda + r) : f4{0.f, 0.f, 0.f, 0.f};
+      rb[p] = (r < N) ? *(const GLOBAL f4*)(gp(B) + (size_t)(k0 + m) * ldb + r) : f4{0.f, 0.f, 0.f, 0.f};
     }
   };
   auto lstore = [&]() {
 #pragma unroll
     for (int p = 0; p < QUADS; ++p) {
       const int e = (tid + p * NT) * 4;
-      *reinterpret_cast<float4*>(As + e) = ra[p];
-      *reinterpret_cast<float4*>(Bs + e) = rb[p];
+      *(LDSAS f4*)(As + e) = ra[p];
+      *(LDSAS f4*)(Bs + e) = rb[p];
     }
   };
   const int nchunks = K / KC;
@@ -200,7 +255,7 @@ __device__ void gemm_nt_f32(double* __restrict__ C, int ldc, const float* __rest
 #pragma unroll
       for (int i = 0; i < NB; ++i)
 #pragma unroll
-        for (int j = 0; j < NB; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], bq[j], acc[i][j], 0, 0, 0);
+        for (int j = 0; j < NB; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(bq[j], a[i], acc[i][j], 0, 0, 0);
     }
     __syncthreads();
     if (c + 1 < nchunks) {
@@ -208,17 +263,7 @@ __device__ void gemm_nt_f32(double* __restrict__ C, int ldc, const float* __rest
       __syncthreads();
     }
   }
-#pragma unroll
-  for (int i = 0; i < NB; ++i)
-#pragma unroll
-    for (int j = 0; j < NB; ++j) {
-      const int col = wc * WT + j * 16 + (lane & 15);
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int row = wr * WT + i * 16 + 4 * (lane >> 4) + v;
-        if (row < M && col < N && (!lower || row >= col)) C[(size_t)col * ldc + row] -= (double)acc[i][j][v];
-      }
-    }
+  update_epilogue<NB, false>(C, ldc, acc, wr * WT, wc * WT, M, N, lower);  // transposed product
 }
 
 // BF16 copies, row-major inside the tile (element (r, k) at r*ld + k) so that the eight
@@ -231,8 +276,8 @@ __device__ void gemm_nt_bf16(double* __restrict__ C, int ldc, const uint16_t* __
   constexpr int SB = 2 * WT, KC = 32, NB = WT / 16, LS = KC + 8;  // padded LDS row
   constexpr int CH = SB * (KC / 8);                                 // 16-byte chunks per operand
   constexpr int PER = (CH + NT - 1) / NT;
-  uint16_t* As = reinterpret_cast<uint16_t*>(lds_d);
-  uint16_t* Bs = As + SB * LS;
+  LDSAS uint16_t* As = lp(reinterpret_cast<uint16_t*>(lds_d));
+  LDSAS uint16_t* Bs = As + SB * LS;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = wave >> 1, wc = wave & 1;
   f4 acc[NB][NB];
@@ -240,15 +285,15 @@ __device__ void gemm_nt_bf16(double* __restrict__ C, int ldc, const uint16_t* __
   for (int i = 0; i < NB; ++i)
 #pragma unroll
     for (int j = 0; j < NB; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
-  uint4 ra[PER], rb[PER];
+  u4 ra[PER], rb[PER];
   auto gload = [&](int k0) {
 #pragma unroll
     for (int p = 0; p < PER; ++p) {
       const int e = tid + p * NT;  // chunk: row e / 4, k offset 8 (e % 4)
       const int r = e >> 2, kq = (e & 3) * 8;
-      const uint4 z = {0u, 0u, 0u, 0u};
-      ra[p] = (e < CH && r < M) ? *reinterpret_cast<const uint4*>(A + (size_t)r * lda + k0 + kq) : z;
-      rb[p] = (e < CH && r < N) ? *reinterpret_cast<const uint4*>(B + (size_t)r * ldb + k0 + kq) : z;
+      const u4 z = {0u, 0u, 0u, 0u};
+      ra[p] = (e < CH && r < M) ? *(const GLOBAL u4*)(gp(A) + (size_t)r * lda + k0 + kq) : z;
+      rb[p] = (e < CH && r < N) ? *(const GLOBAL u4*)(gp(B) + (size_t)r * ldb + k0 + kq) : z;
     }
   };
   auto lstore = [&]() {
@@ -257,8 +302,8 @@ __device__ void gemm_nt_bf16(double* __restrict__ C, int ldc, const uint16_t* __
       const int e = tid + p * NT;
       if (e < CH) {
         const int r = e >> 2, kq = (e & 3) * 8;
-        *reinterpret_cast<uint4*>(As + r * LS + kq) = ra[p];
-        *reinterpret_cast<uint4*>(Bs + r * LS + kq) = rb[p];
+        *(LDSAS u4*)(As + r * LS + kq) = ra[p];
+        *(LDSAS u4*)(Bs + r * LS + kq) = rb[p];
       }
     }
   };
@@ -272,30 +317,20 @@ __device__ void gemm_nt_bf16(double* __restrict__ C, int ldc, const uint16_t* __
     if (c + 1 < nchunks) gload((c + 1) * KC);
     bf8 a[NB], bq[NB];
 #pragma unroll
-    for (int i = 0; i < NB; ++i) a[i] = __builtin_bit_cast(bf8, *reinterpret_cast<const uint4*>(As + (arow + i * 16) * LS + kq));
+    for (int i = 0; i < NB; ++i) a[i] = __builtin_bit_cast(bf8, *(const LDSAS u4*)(As + (arow + i * 16) * LS + kq));
 #pragma unroll
-    for (int j = 0; j < NB; ++j) bq[j] = __builtin_bit_cast(bf8, *reinterpret_cast<const uint4*>(Bs + (bcol + j * 16) * LS + kq));
+    for (int j = 0; j < NB; ++j) bq[j] = __builtin_bit_cast(bf8, *(const LDSAS u4*)(Bs + (bcol + j * 16) * LS + kq));
 #pragma unroll
     for (int i = 0; i < NB; ++i)
 #pragma unroll
-      for (int j = 0; j < NB; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], bq[j], acc[i][j], 0, 0, 0);
+      for (int j = 0; j < NB; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bq[j], a[i], acc[i][j], 0, 0, 0);
     __syncthreads();
     if (c + 1 < nchunks) {
       lstore();
       __syncthreads();
     }
   }
-#pragma unroll
-  for (int i = 0; i < NB; ++i)
-#pragma unroll
-    for (int j = 0; j < NB; ++j) {
-      const int col = wc * WT + j * 16 + (lane & 15);
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int row = wr * WT + i * 16 + 4 * (lane >> 4) + v;
-        if (row < M && col < N && (!lower || row >= col)) C[(size_t)col * ldc + row] -= (double)acc[i][j][v];
-      }
-    }
+  update_epilogue<NB, false>(C, ldc, acc, wr * WT, wc * WT, M, N, lower);  // transposed product
 }
 
 // FP64 -> BF16, round to nearest even, directly from the double (no intermediate FP32
@@ -313,79 +348,89 @@ __device__ __forceinline__ uint16_t to_bf16(double x) {
   return (uint16_t)((sign << 15) | ((unsigned)e << 7) | (unsigned)((u >> 45) & 0x7fu));
 }
 
-// Value of v in lane `src` (a compile-time constant after unrolling), read through the
-// scalar unit: no LDS round trip on the sequential chain.
-__device__ __forceinline__ double lane_bcast(double v, int src) {
-  const long long u = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_readlane((int)(u & 0xffffffffll), src);
-  const int hi = __builtin_amdgcn_readlane((int)(u >> 32), src);
-  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+// Orders a wave's LDS writes before its later LDS reads by other lanes.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// One wave factors the 32x32 lower block D (column-major in LDS, D(r, j) at D[j*32 + r]) and
-// writes its inverse to Z (column-major, zeros above the diagonal).  Lane r keeps row r in
-// registers; every value a step needs from another lane is broadcast through the scalar
-// unit, so a column step costs one sqrt, one division and a few dependent operations.
-// Returns the 1-based column of the first non-positive or NaN pivot (then D and Z are not
-// written), or 0; the same value in every lane.
-__device__ int factor_inverse32(double* __restrict__ D, double* __restrict__ Z) {
+// One wave writes Z = L^{-1} for a factored 32x32 lower block L (LDS, column-major, zeros
+// above the diagonal): lane c forward-substitutes L z = e_c, reading the entries of L as
+// same-address LDS loads (broadcasts).  The reciprocals of the diagonal are made first, in
+// parallel, so the substitution chain holds only multiplications and FMAs.  Z may not be L.
+__device__ void lower_inverse32(const double* __restrict__ Lg, double* __restrict__ Zg) {
   const int lane = threadIdx.x & 63;
-  double row[32];
-#pragma unroll
-  for (int j = 0; j < 32; ++j) row[j] = (lane < 32 && lane >= j) ? D[j * 32 + lane] : 0.0;
-  int bad = 0;
-#pragma unroll
-  for (int c = 0; c < 32; ++c) {
-    const double p = lane_bcast(row[c], c);
-    if (!bad && !(p > 0.0)) bad = c + 1;
-    const double d = bad ? 1.0 : sqrt(p);
-    const double lrc = lane > c ? row[c] / d : (lane == c ? d : 0.0);
-    row[c] = lrc;
-#pragma unroll
-    for (int j = c + 1; j < 32; ++j) row[j] -= lrc * lane_bcast(lrc, j);  // zero above the diagonal
-  }
-  if (bad) return bad;
-  if (lane < 32) {
-#pragma unroll
-    for (int j = 0; j < 32; ++j) D[j * 32 + lane] = lane >= j ? row[j] : 0.0;
-  }
-  // inverse: lane c holds column c of L^{-1}, by forward substitution L z = e_c
+  const LDSAS double* L = lp(Lg);
+  LDSAS double* Z = lp(Zg);
+  LDSAS double* R = Z;  // the 32 reciprocals, in Z until Z is written
+  if (lane < 32) R[lane] = 1.0 / L[lane * 33];
+  wave_lds_sync();
   double z[32];
 #pragma unroll
   for (int m = 0; m < 32; ++m) z[m] = (m == lane) ? 1.0 : 0.0;
 #pragma unroll
   for (int p = 0; p < 32; ++p) {
-    z[p] = z[p] / lane_bcast(row[p], p);
+    z[p] *= R[p];
 #pragma unroll
-    for (int m = p + 1; m < 32; ++m) z[m] -= lane_bcast(row[p], m) * z[p];
+    for (int m = p + 1; m < 32; ++m) z[m] -= L[p * 32 + m] * z[p];
   }
+  wave_lds_sync();  // every read of R is done
   if (lane < 32) {
 #pragma unroll
     for (int m = 0; m < 32; ++m) Z[lane * 32 + m] = m >= lane ? z[m] : 0.0;
   }
+}
+
+// One wave factors the 32x32 lower block D (column-major in LDS, D(r, j) at D[j*32 + r]) in
+// place and writes its inverse to Z (column-major, zeros above the diagonal).  Right-looking
+// by columns: lane r keeps row r in registers; column c, once scaled, is written to D and
+// read back by every lane as same-address LDS loads.  Every lane also carries the updated
+// diagonal (the same FMAs in the same order as the owning lane), so the pivot needs no
+// exchange.  Returns the 1-based column of the first non-positive or NaN pivot (D is then
+// partly overwritten and Z not written), or 0; the same value in every lane.
+__device__ int factor_inverse32(double* __restrict__ Dg, double* __restrict__ Z) {
+  const int lane = threadIdx.x & 63;
+  LDSAS double* D = lp(Dg);
+  double row[32], dg[32];
+#pragma unroll
+  for (int j = 0; j < 32; ++j) {
+    row[j] = (lane < 32 && lane >= j) ? D[j * 32 + lane] : 0.0;
+    dg[j] = D[j * 33];
+  }
+  wave_lds_sync();  // every lane has read D before column 0 is overwritten
+#pragma unroll
+  for (int c = 0; c < 32; ++c) {
+    const double p = dg[c];
+    if (!(p > 0.0)) return c + 1;
+    // r = 1/sqrt(p): the hardware estimate and two Newton steps, so the column scale and
+    // the pivot L(c,c) = p r come from one short chain (no IEEE divide or square root);
+    // exact for p = 1 and within a few ulp otherwise
+    const double hp = 0.5 * p;
+    double r = __builtin_amdgcn_rsq(p);
+    r = fma(r, fma(-hp * r, r, 0.5), r);
+    r = fma(r, fma(-hp * r, r, 0.5), r);
+    const double d = p * r;
+    const double lrc = lane > c ? row[c] * r : (lane == c ? d : 0.0);
+    row[c] = lrc;
+    if (lane < 32) D[c * 32 + lane] = lrc;
+    wave_lds_sync();
+    double col[32];  // all loads issued before the first use
+#pragma unroll
+    for (int j = c + 1; j < 32; ++j) col[j] = D[c * 32 + j];
+#pragma unroll
+    for (int j = c + 1; j < 32; ++j) {
+      row[j] -= lrc * col[j];
+      dg[j] -= col[j] * col[j];
+    }
+  }
+  wave_lds_sync();
+  lower_inverse32(Dg, Z);
   return 0;
 }
 
 // One wave inverts an already factored 32x32 lower block L (LDS, column-major) into Z.
-__device__ void inverse32(const double* __restrict__ L, double* __restrict__ Z) {
-  const int lane = threadIdx.x & 63;
-  double row[32];
-#pragma unroll
-  for (int j = 0; j < 32; ++j) row[j] = (lane < 32 && lane >= j) ? L[j * 32 + lane] : 0.0;
-  double z[32];
-#pragma unroll
-  for (int m = 0; m < 32; ++m) z[m] = (m == lane) ? 1.0 : 0.0;
-#pragma unroll
-  for (int p = 0; p < 32; ++p) {
-    z[p] = z[p] / lane_bcast(row[p], p);
-#pragma unroll
-    for (int m = p + 1; m < 32; ++m) z[m] -= lane_bcast(row[p], m) * z[p];
-  }
-  if (lane < 32) {
-#pragma unroll
-    for (int m = 0; m < 32; ++m) Z[lane * 32 + m] = m >= lane ? z[m] : 0.0;
-  }
-}
+__device__ void inverse32(const double* __restrict__ L, double* __restrict__ Z) { lower_inverse32(L, Z); }
 
 // ---------------------------------------------------------------------------------------
 // Tall FP64 update for the panel steps: C[M x 32] -= A[M x K] * B[32 x K]^T (column-major).
@@ -416,17 +461,17 @@ __device__ void gemm_tall32_f64(double* __restrict__ C, int ldc, const double* _
       const int q = wave + 4 * t;
 #pragma unroll
       for (int s = 0; s < KS; ++s)
-        an[t][s] = q < nblk ? A[(size_t)(k0 + 4 * s + kl) * lda + 16 * q + li] : 0.0;
+        an[t][s] = q < nblk ? gp(A)[(size_t)(k0 + 4 * s + kl) * lda + 16 * q + li] : 0.0;
     }
   };
   auto bload = [&](int k0) {  // element e = tid + 256 i of the KC x 32 chunk: (k = e / 32, j = e % 32)
 #pragma unroll
     for (int i = 0; i < BPT; ++i) {
       const int e = tid + NT * i;
-      bn[i] = B[(size_t)(k0 + (e >> 5)) * ldb + (e & 31)];
+      bn[i] = gp(B)[(size_t)(k0 + (e >> 5)) * ldb + (e & 31)];
     }
   };
-  auto bstore = [&](double* dst) {
+  auto bstore = [&](LDSAS double* dst) {
 #pragma unroll
     for (int i = 0; i < BPT; ++i) dst[tid + NT * i] = bn[i];
   };
@@ -434,7 +479,7 @@ __device__ void gemm_tall32_f64(double* __restrict__ C, int ldc, const double* _
   aload(0);
   bload(0);
   __syncthreads();  // the caller's previous use of LDS is over
-  bstore(lds);
+  bstore(lp(lds));
   __syncthreads();
   for (int c = 0; c < nch; ++c) {
     double acur[NBMAX][KS];
@@ -442,7 +487,7 @@ __device__ void gemm_tall32_f64(double* __restrict__ C, int ldc, const double* _
     for (int t = 0; t < NBMAX; ++t)
 #pragma unroll
       for (int s = 0; s < KS; ++s) acur[t][s] = an[t][s];
-    const double* Bc = lds + (c & 1) * (KC * 32);
+    const LDSAS double* Bc = lp(lds) + (c & 1) * (KC * 32);
     if (c + 1 < nch) {
       aload((c + 1) * KC);
       bload((c + 1) * KC);
@@ -453,31 +498,47 @@ __device__ void gemm_tall32_f64(double* __restrict__ C, int ldc, const double* _
 #pragma unroll
       for (int t = 0; t < NBMAX; ++t) {
         if (wave + 4 * t < nblk) {
-          acc[t][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(acur[t][s], b0, acc[t][0], 0, 0, 0);
-          acc[t][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(acur[t][s], b1, acc[t][1], 0, 0, 0);
+          acc[t][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(b0, acur[t][s], acc[t][0], 0, 0, 0);
+          acc[t][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(b1, acur[t][s], acc[t][1], 0, 0, 0);
         }
       }
     }
-    if (c + 1 < nch) bstore(lds + ((c + 1) & 1) * (KC * 32));
+    if (c + 1 < nch) bstore(lp(lds) + ((c + 1) & 1) * (KC * 32));
     __syncthreads();
+  }
+  // FP64 accumulator layout (l/16 + 4v, l%16) of the transposed product (B A^T): lane l
+  // holds C row 16q + l%16, column 16 jb + l/16 + 4v, so sixteen lanes cover sixteen
+  // consecutive doubles.  Without ASSIGN every old value is loaded before any store.
+  GLOBAL double* Cg = gp(C);
+  double old[NBMAX][2][4];
+  if (!ASSIGN) {
+#pragma unroll
+    for (int t = 0; t < NBMAX; ++t) {
+      const int q = wave + 4 * t;
+#pragma unroll
+      for (int jb = 0; jb < 2; ++jb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = 16 * q + li, col = 16 * jb + kl + 4 * v;
+          old[t][jb][v] = (q < nblk && (!lower || row >= col)) ? Cg[(size_t)col * ldc + row] : 0.0;
+        }
+    }
   }
 #pragma unroll
   for (int t = 0; t < NBMAX; ++t) {
     const int q = wave + 4 * t;
     if (q >= nblk) continue;
 #pragma unroll
-    for (int jb = 0; jb < 2; ++jb) {
-      const int col = 16 * jb + li;
+    for (int jb = 0; jb < 2; ++jb)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int row = 16 * q + kl + 4 * v;  // FP64 accumulator layout: (l/16 + 4v, l%16)
+        const int row = 16 * q + li, col = 16 * jb + kl + 4 * v;
         if (lower && row < col) continue;
         if (ASSIGN)
-          C[(size_t)col * ldc + row] = acc[t][jb][v];
+          Cg[(size_t)col * ldc + row] = acc[t][jb][v];
         else
-          C[(size_t)col * ldc + row] -= acc[t][jb][v];
+          Cg[(size_t)col * ldc + row] = old[t][jb][v] - acc[t][jb][v];
       }
-    }
   }
 }
 
@@ -517,12 +578,14 @@ __device__ int potrf_tile(double* __restrict__ a, int b, double* __restrict__ di
   const int tid = threadIdx.x;
   double* D = lds + LDS_D_OFF;
   double* Z = D + 1024;
+  LDSAS double* Dl = lp(D);
+  LDSAS double* Zl = lp(Z);
   for (int c0 = 0; c0 < b; c0 += 32) {
     gemm_tall32_any(a + (size_t)c0 * b + c0, b, a + c0, b, a + c0, b, b - c0, c0, true, lds);
     __syncthreads();
     for (int e = tid; e < 1024; e += NT) {
       const int r = e & 31, j = e >> 5;
-      D[e] = r >= j ? a[(size_t)(c0 + j) * b + c0 + r] : 0.0;
+      Dl[e] = r >= j ? a[(size_t)(c0 + j) * b + c0 + r] : 0.0;
     }
     if (tid == 0) s_bad = 0;
     __syncthreads();
@@ -535,8 +598,8 @@ __device__ int potrf_tile(double* __restrict__ a, int b, double* __restrict__ di
     double* dblk = dinv + (size_t)c0 * 32;
     for (int e = tid; e < 1024; e += NT) {
       const int r = e & 31, j = e >> 5;
-      if (r >= j) a[(size_t)(c0 + j) * b + c0 + r] = D[e];
-      dblk[e] = Z[e];
+      if (r >= j) a[(size_t)(c0 + j) * b + c0 + r] = Dl[e];
+      dblk[e] = Zl[e];
     }
     __syncthreads();
     apply_inv_tall(a + (size_t)c0 * b + c0 + 32, b, dblk, b - c0 - 32, lds);
@@ -546,40 +609,122 @@ __device__ int potrf_tile(double* __restrict__ a, int b, double* __restrict__ di
 }
 
 // ---------------------------------------------------------------------------------------
-// TRSM part: rows [r0, r0+R) of an off-diagonal tile X <- X * L^{-T}, L the factored
-// diagonal tile of the same block column, dinv the inverses of its 32x32 diagonal blocks.
-// Left-looking over 32-wide column blocks: the block first receives the updates of all
-// solved columns (tall matrix-core update, K = c0), then is multiplied by the transposed
-// block inverse (K = 32).  In mixed precision the solved block is also written as the FP32
-// or BF16 copy the updates read.
+// TRSM part: rows [r0, r0+32) of an off-diagonal tile X <- X L^{-T}, L the factored diagonal
+// tile of the same block column, dinv the inverses Li_c of its 32x32 diagonal blocks.
+// Right-looking over 32-wide column blocks with the strip resident in matrix-core
+// accumulators: 16-column block j of the strip belongs to wave j % 4, as two 16x16 tiles.
+// The products are formed transposed (as in the updates), so a tile's accumulator element
+// v in lane l is X(16 rb + l%16, 16 j + l/16 + 4v), which is also the operand layout of a
+// 4-deep slice: the strip feeds the matrix cores without a transpose.  Step c: the owners
+// of block c stage it in LDS, form X_c <- X_c Li_c^T and publish it (LDS, the tile, and in
+// mixed precision the FP32 or BF16 copy the updates read); then every wave subtracts
+// X_c L(j, c)^T from each of its later blocks j.  k0 (a multiple of 32): the strip's
+// columns before k0 are zero and stay zero (the inversion task starts at its identity
+// rows' diagonal); they are neither read nor written.
 // ---------------------------------------------------------------------------------------
-// k0: the strip's columns before k0 (a multiple of 32) are zero and stay zero (the
-// inversion task starts at its identity rows' diagonal); the updates skip them.
-__device__ void trsm_part(double* __restrict__ x, const double* __restrict__ l, const double* __restrict__ dinv,
-                          int b, int r0, int R, void* __restrict__ low, int prec, double* __restrict__ lds,
-                          int k0 = 0) {
-  const int tid = threadIdx.x;
-  double* xr = x + r0;
+template <int NCB>
+__device__ void trsm_strip32(double* __restrict__ x, const double* __restrict__ l, const double* __restrict__ dinv,
+                             int b, int r0, void* __restrict__ low, int prec, double* __restrict__ lds, int k0) {
+  constexpr int LDX = 34;  // padded LDS column (32 rows)
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, kl = lane >> 4;
+  const int ncb = b / 16;
+  LDSAS double* Xs = lp(lds);             // block c before its diagonal solve, column-major 32 x 32
+  LDSAS double* Xn = lp(lds) + 32 * LDX;  // block c after it
+  GLOBAL double* xg = gp(x) + r0;
+  const GLOBAL double* lg = gp(l);
+  d4 acc[2][NCB];
+#pragma unroll
+  for (int t = 0; t < NCB; ++t) {
+    const int cb = wave + 4 * t;
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        acc[rb][t][v] = (cb < ncb && 16 * cb >= k0) ? xg[(size_t)(16 * cb + kl + 4 * v) * b + 16 * rb + li] : 0.0;
+  }
+  __syncthreads();  // the caller's previous use of LDS is over
   for (int c0 = k0; c0 < b; c0 += 32) {
-    gemm_tall32_any(xr + (size_t)c0 * b, b, xr + (size_t)k0 * b, b, l + (size_t)k0 * b + c0, b, R, c0 - k0, false,
-                    lds);
-    __syncthreads();
-    apply_inv_tall(xr + (size_t)c0 * b, b, dinv + (size_t)c0 * 32, R, lds);
-    __syncthreads();
-    if (prec == PREC_FP32) {
-      float* lf = reinterpret_cast<float*>(low) + r0;
-      for (int e = tid; e < 32 * R; e += NT) {
-        const int r = e % R, c = e / R;
-        lf[(size_t)(c0 + c) * b + r] = (float)xr[(size_t)(c0 + c) * b + r];
+    const int cblk = c0 / 16;
+    // (1) the owners of block c stage it
+#pragma unroll
+    for (int t = 0; t < NCB; ++t) {
+      const int kb = wave + 4 * t - cblk;
+      if (kb == 0 || kb == 1) {
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) Xs[(16 * kb + kl + 4 * v) * LDX + 16 * rb + li] = acc[rb][t][v];
       }
-    } else if (prec == PREC_BF16) {
-      uint16_t* lh = reinterpret_cast<uint16_t*>(low);
-      for (int e = tid; e < 32 * R; e += NT) {
-        const int c = e & 31, r = e >> 5;
-        lh[(size_t)(r0 + r) * b + c0 + c] = to_bf16(xr[(size_t)(c0 + c) * b + r]);
+    }
+    __syncthreads();
+    // (2) X_c Li^T: output 16-column half jb from both input halves kb (Li lower triangular,
+    // so the upper input half does not reach the lower output half)
+#pragma unroll
+    for (int t = 0; t < NCB; ++t) {
+      const int jb = wave + 4 * t - cblk;
+      if (jb == 0 || jb == 1) {
+        const GLOBAL double* Li = gp(dinv) + (size_t)c0 * 32;  // Li(i, j) at [j * 32 + i]
+        double la[2][4];
+#pragma unroll
+        for (int kb = 0; kb < 2; ++kb)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) la[kb][v] = Li[(16 * kb + 4 * v + kl) * 32 + 16 * jb + li];
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb) {
+          d4 nw = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+          for (int kb = 0; kb < 2; ++kb) {
+            if (kb > jb) continue;
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+              nw = __builtin_amdgcn_mfma_f64_16x16x4f64(la[kb][v], Xs[(16 * kb + 4 * v + kl) * LDX + 16 * rb + li], nw,
+                                                        0, 0, 0);
+          }
+          acc[rb][t] = nw;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int lc = 16 * jb + kl + 4 * v, row = 16 * rb + li;
+            Xn[lc * LDX + row] = nw[v];
+            xg[(size_t)(c0 + lc) * b + row] = nw[v];
+            if (prec == PREC_FP32)
+              gp(reinterpret_cast<float*>(low))[(size_t)(c0 + lc) * b + r0 + row] = (float)nw[v];
+            else if (prec == PREC_BF16)
+              gp(reinterpret_cast<uint16_t*>(low))[(size_t)(r0 + row) * b + c0 + lc] = to_bf16(nw[v]);
+          }
+        }
+      }
+    }
+    __syncthreads();
+    // (3) later blocks lose X_c L(j, c)^T
+#pragma unroll
+    for (int t = 0; t < NCB; ++t) {
+      const int cb = wave + 4 * t;
+      if (cb < ncb && cb >= cblk + 2) {
+        double lf[8];
+#pragma unroll
+        for (int s4 = 0; s4 < 8; ++s4) lf[s4] = -lg[(size_t)(c0 + 4 * s4 + kl) * b + 16 * cb + li];
+#pragma unroll
+        for (int s4 = 0; s4 < 8; ++s4)
+#pragma unroll
+          for (int rb = 0; rb < 2; ++rb)
+            acc[rb][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(lf[s4], Xn[(4 * s4 + kl) * LDX + 16 * rb + li],
+                                                              acc[rb][t], 0, 0, 0);
       }
     }
   }
+}
+
+__device__ void trsm_part(double* __restrict__ x, const double* __restrict__ l, const double* __restrict__ dinv,
+                          int b, int r0, void* __restrict__ low, int prec, double* __restrict__ lds, int k0 = 0) {
+  if (b > 256)
+    trsm_strip32<8>(x, l, dinv, b, r0, low, prec, lds, k0);
+  else if (b > 128)
+    trsm_strip32<4>(x, l, dinv, b, r0, low, prec, lds, k0);
+  else if (b > 64)
+    trsm_strip32<2>(x, l, dinv, b, r0, low, prec, lds, k0);
+  else
+    trsm_strip32<1>(x, l, dinv, b, r0, low, prec, lds, k0);
 }
 
 // Inverses of the 32x32 diagonal blocks of an already factored diagonal tile (one block
@@ -624,9 +769,9 @@ __device__ void tile_inverses(const double* __restrict__ l, int b, double* __res
 __device__ void ftrsm_sub_part(const double* __restrict__ l, const double* __restrict__ dinv, int b,
                            double* __restrict__ y, int64_t ldy, int q0, int nq, double* __restrict__ lds) {
   const int tid = threadIdx.x;
-  double* ys = lds;            // [8][b] right-hand sides
-  double* Lb = lds + 8 * 512;  // two 32x32 block inverses
-  double* yb = Lb + 2048;      // [8][32] the block just solved
+  LDSAS double* ys = lp(lds);            // [8][b] right-hand sides
+  LDSAS double* Lb = lp(lds) + 8 * 512;  // two 32x32 block inverses
+  LDSAS double* yb = Lb + 2048;  // [8][32] the block just solved
   const int q = tid >> 5, r = tid & 31;
   for (int e = tid; e < 8 * b; e += NT) {
     const int qq = e / b, m = e % b;
@@ -650,7 +795,7 @@ __device__ void ftrsm_sub_part(const double* __restrict__ l, const double* __res
     __syncthreads();  // block c0 of ys and the inverse in Lb[buf] are ready
     if (c0 + 32 < b)
       for (int e = tid; e < 1024; e += NT) Lb[(buf ^ 1) * 1024 + e] = dinv[(size_t)(c0 + 32) * 32 + e];
-    const double* Li = Lb + buf * 1024;
+    const LDSAS double* Li = Lb + buf * 1024;
     if (q < nq) {
       double sacc = 0.0;
       for (int c = 0; c <= r; ++c) sacc += Li[c * 32 + r] * ys[q * b + c0 + c];
@@ -688,9 +833,9 @@ __device__ void ftrsm_sub_part(const double* __restrict__ l, const double* __res
 __device__ void btrsm_sub_part(const double* __restrict__ l, const double* __restrict__ dinv, int b,
                            double* __restrict__ y, int64_t ldy, int q0, int nq, double* __restrict__ lds) {
   const int tid = threadIdx.x;
-  double* ys = lds;
-  double* Lb = lds + 8 * 512;
-  double* yb = Lb + 2048;
+  LDSAS double* ys = lp(lds);
+  LDSAS double* Lb = lp(lds) + 8 * 512;
+  LDSAS double* yb = Lb + 2048;
   const int q = tid >> 5, r = tid & 31;
   for (int e = tid; e < 8 * b; e += NT) {
     const int qq = e / b, m = e % b;
@@ -719,7 +864,7 @@ __device__ void btrsm_sub_part(const double* __restrict__ l, const double* __res
     __syncthreads();
     if (c0 > 0)
       for (int e = tid; e < 1024; e += NT) Lb[(buf ^ 1) * 1024 + e] = dinv[(size_t)(c0 - 32) * 32 + e];
-    const double* Li = Lb + buf * 1024;
+    const LDSAS double* Li = Lb + buf * 1024;
     if (q < nq) {
       double sacc = 0.0;
       for (int c = r; c < 32; ++c) sacc += Li[r * 32 + c] * ys[q * b + c0 + c];  // Li(c, r)
@@ -762,8 +907,8 @@ __device__ void ftrsm_part(const double* __restrict__ M, int b, const double* __
                            double* __restrict__ yout, int64_t ldy, int q0, int nq, int r0, int rows,
                            double* __restrict__ lds) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  double* ys = lds;              // [8][b]
-  double* part = lds + 8 * 512;  // [4][8][64]
+  LDSAS double* ys = lp(lds);              // [8][b]
+  LDSAS double* part = lp(lds) + 8 * 512;  // [4][8][64]
   const int cmax = r0 + rows;    // entries c < cmax are used
   for (int e = tid; e < 8 * cmax; e += NT) {
     const int q = e / cmax, m = e % cmax;
@@ -811,8 +956,8 @@ __device__ void btrsm_part(const double* __restrict__ M, int b, const double* __
                            double* __restrict__ yout, int64_t ldy, int q0, int nq, int r0, int rows,
                            double* __restrict__ lds) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  double* ys = lds;
-  double* part = lds + 8 * 512;
+  LDSAS double* ys = lp(lds);
+  LDSAS double* part = lp(lds) + 8 * 512;
   for (int e = tid; e < 8 * (b - r0); e += NT) {  // entries c >= r0 are used
     const int q = e / (b - r0), m = r0 + e % (b - r0);
     ys[q * b + m] = q < nq ? yin[(size_t)(q0 + q) * ldy + m] : 0.0;
@@ -857,8 +1002,8 @@ __device__ void fgemm_part(const double* __restrict__ l, int b, double* __restri
                            const double* __restrict__ yk, int64_t ldy, int nrhs, int r0, int rows,
                            double* __restrict__ lds) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  double* ys = lds;             // [8][b]
-  double* part = lds + 8 * 512; // [4][8][64]
+  LDSAS double* ys = lp(lds);             // [8][b]
+  LDSAS double* part = lp(lds) + 8 * 512; // [4][8][64]
   const int mq = b / 4;
   for (int q0 = 0; q0 < nrhs; q0 += 8) {
     const int nq = (nrhs - q0) < 8 ? (nrhs - q0) : 8;
@@ -910,8 +1055,8 @@ __device__ void bgemm_part(const double* __restrict__ l, int b, double* __restri
                            const double* __restrict__ yk, int64_t ldy, int nrhs, int r0, int rows,
                            double* __restrict__ lds) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  double* ys = lds;              // [8][b]
-  double* part = lds + 8 * 512;  // [4][8][64]
+  LDSAS double* ys = lp(lds);              // [8][b]
+  LDSAS double* part = lp(lds) + 8 * 512;  // [4][8][64]
   const int mq = b / 4;
   for (int q0 = 0; q0 < nrhs; q0 += 8) {
     const int nq = (nrhs - q0) < 8 ? (nrhs - q0) : 8;
@@ -1013,7 +1158,7 @@ __device__ void run_part(const SchedArgs& a, uint32_t task, uint32_t part, doubl
       void* low = m.prec == PREC_FP32   ? (void*)(reinterpret_cast<float*>(m.low) + off)
                   : m.prec == PREC_BF16 ? (void*)(reinterpret_cast<uint16_t*>(m.low) + off)
                                         : nullptr;
-      trsm_part(tile_ptr(m, d.i, d.k), tile_ptr(m, d.k, d.k), dinv_ptr(m, d.k), b, part * R, R, low, m.prec, lds);
+      trsm_part(tile_ptr(m, d.i, d.k), tile_ptr(m, d.k, d.k), dinv_ptr(m, d.k), b, part * R, low, m.prec, lds);
       break;
     }
     case SPX_T_SYRK:
@@ -1084,7 +1229,7 @@ __device__ void run_part(const SchedArgs& a, uint32_t task, uint32_t part, doubl
         x[(size_t)c * b + r0 + r] = (r0 + r == c) ? 1.0 : 0.0;
       }
       __syncthreads();
-      trsm_part(x, tile_ptr(m, d.k, d.k), dinv_ptr(m, d.k), b, r0, R, nullptr, PREC_FP64, lds, r0 & ~31);
+      trsm_part(x, tile_ptr(m, d.k, d.k), dinv_ptr(m, d.k), b, r0, nullptr, PREC_FP64, lds, r0 & ~31);
       break;
     }
     case SPX_T_FGEMM: {
