@@ -121,6 +121,7 @@ void cholesky_program(int nt, bool with_solve, std::vector<TaskDesc>& tasks, std
     }
     for (int i = k + 1; i < nt; ++i) {
       task(SPX_T_SYRK, i, i, k);
+      if (i == k + 1) tasks.back().pad = 1;  // on the critical path: cut into finer parts
       use(SPX_ACC_R, A(i, k));
       use(SPX_ACC_RW, A(i, i));
       for (int j = k + 1; j < i; ++j) {

@@ -189,7 +189,8 @@ static int default_tile(int64_t n) {
 int trsm_rows_of(int /*b*/) { return 32; }  // the TRSM and inversion kernels take 32-row strips
 
 uint16_t parts_of(const TaskDesc& d, int b, int nrhs) {
-  const int sb = b < 128 ? b : 128, ns = b / sb;
+  const int sbase = (d.type == SPX_T_SYRK && d.pad) ? 64 : 128;
+  const int sb = b < sbase ? b : sbase, ns = b / sb;
   const int rows = b < 64 ? b : 64;
   switch (d.type) {
     case SPX_T_POTRF: return 1;

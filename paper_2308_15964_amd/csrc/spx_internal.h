@@ -25,7 +25,8 @@ struct Graph {
 
 // Device task descriptor (16 bytes).  `level` is the ready-queue level (0 = served
 // first); `nparts` the number of workgroup-sized pieces the task is cut into; `pad` = 1
-// marks the diagonal solves that use the tile inverse M_k (row-split, out of place).
+// marks the solve tasks that use the tile inverse M_k (row-split, out of place) and the
+// SYRK(k+1, k+1, k) that the next diagonal factorization waits on (64x64 parts).
 struct TaskDesc {
   uint8_t type = 0;
   uint8_t level = 0;

@@ -48,7 +48,7 @@ __device__ __forceinline__ LDSAS T* lp(T* p) {
 }
 
 constexpr int NT = 256;                 // threads per workgroup (4 waves)
-constexpr int LDS_DOUBLES = 12288;      // 96 KiB of LDS per workgroup (one workgroup per CU)
+constexpr int LDS_DOUBLES = 16384;      // 128 KiB of LDS per workgroup (one workgroup per CU)
 constexpr int LDS_D_OFF = 8192;         // 32x32 diagonal block, after the update staging area
 constexpr u64 EMPTY = ~0ull;
 
@@ -104,22 +104,24 @@ __device__ __forceinline__ void update_epilogue(double* C, int ldc, const ACC (&
 // ---------------------------------------------------------------------------------------
 // FP64 matrix-core update: C[M x N] -= A[M x K] * B[N x K]^T (all column-major).
 // Four waves in a 2x2 arrangement, each owning a WT x WT block of C made of 16x16
-// v_mfma_f64_16x16x4 accumulators.  K is staged through LDS in chunks of 32, with the
-// next chunk's global loads in flight while the current one is multiplied.
-// M, N: multiples of 16, at most 2*WT.  K: multiple of 32.  lower: write only the
-// entries with row >= col (diagonal blocks of a symmetric update).
+// v_mfma_f64_16x16x4 accumulators.  K is staged through LDS in chunks of 32, double
+// buffered: while chunk c is multiplied out of one buffer, chunk c+1 (loaded into
+// registers during the previous chunk) is written to the other and chunk c+2's global
+// loads are issued, so each chunk needs one barrier and its loads have a whole chunk of
+// matrix-core work to arrive.  M, N: multiples of 16, at most 2*WT.  K: multiple of 32.
+// lower: write only the entries with row >= col (diagonal blocks of a symmetric update).
 // ---------------------------------------------------------------------------------------
 template <int WT>
 __device__ void gemm_nt_f64(double* __restrict__ C, int ldc, const double* __restrict__ A, int lda,
                             const double* __restrict__ B, int ldb, int M, int N, int K, bool lower,
                             double* __restrict__ lds) {
   constexpr int SB = 2 * WT;
-  constexpr int KC = 32;  // a 32-deep chunk: its MFMAs hide the next chunk's global loads
+  constexpr int KC = 32;
   constexpr int NB = WT / 16;
   constexpr int PAIRS = SB * KC / (2 * NT);  // double2 loads per thread per operand
+  constexpr int BUF = 2 * KC * SB;           // one buffer: the A and B chunks
   static_assert(PAIRS >= 1, "tile too small for one double2 per thread");
-  LDSAS double* As = lp(lds);
-  LDSAS double* Bs = lp(lds) + KC * SB;
+  static_assert(2 * BUF <= LDS_DOUBLES, "two chunk buffers must fit in LDS");
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = wave >> 1, wc = wave & 1;
   d4 acc[NB][NB];
@@ -140,7 +142,9 @@ __device__ void gemm_nt_f64(double* __restrict__ C, int ldc, const double* __res
       rb[p] = (r < N) ? *(const GLOBAL d2*)(Bk + m * ldb + r) : d2{0.0, 0.0};
     }
   };
-  auto lstore = [&]() {
+  auto lstore = [&](int buf) {
+    LDSAS double* As = lp(lds) + buf * BUF;
+    LDSAS double* Bs = As + KC * SB;
 #pragma unroll
     for (int p = 0; p < PAIRS; ++p) {
       const int e = (tid + p * NT) * 2;
@@ -151,11 +155,18 @@ __device__ void gemm_nt_f64(double* __restrict__ C, int ldc, const double* __res
   const int nchunks = K / KC;
   gload(0);
   __syncthreads();  // LDS may still be read by the caller's previous step
-  lstore();
+  lstore(0);
+  if (nchunks > 1) gload(KC);
   __syncthreads();
   const int arow = wr * WT + (lane & 15), bcol = wc * WT + (lane & 15), kl = lane >> 4;
   for (int c = 0; c < nchunks; ++c) {
-    if (c + 1 < nchunks) gload((c + 1) * KC);
+    const int buf = c & 1;
+    if (c + 1 < nchunks) {
+      lstore(buf ^ 1);                          // chunk c+1, loaded during chunk c-1
+      if (c + 2 < nchunks) gload((c + 2) * KC);  // chunk c+2 in flight during chunk c
+    }
+    const LDSAS double* As = lp(lds) + buf * BUF;
+    const LDSAS double* Bs = As + KC * SB;
 #pragma unroll
     for (int kk = 0; kk < KC; kk += 4) {
       double a[NB], b[NB];
@@ -168,11 +179,7 @@ __device__ void gemm_nt_f64(double* __restrict__ C, int ldc, const double* __res
 #pragma unroll
         for (int j = 0; j < NB; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(b[j], a[i], acc[i][j], 0, 0, 0);
     }
-    __syncthreads();
-    if (c + 1 < nchunks) {
-      lstore();
-      __syncthreads();
-    }
+    __syncthreads();  // buffer buf ^ 1 is written; buffer buf may be overwritten next
   }
   // accumulator layout of v_mfma_f64_16x16x4 (measured on gfx950): element v of lane l
   // holds (row l/16 + 4v, column l%16) of the 16x16 product, here (B A^T): C row l%16,
@@ -369,11 +376,26 @@ __device__ void lower_inverse32(const double* __restrict__ Lg, double* __restric
   double z[32];
 #pragma unroll
   for (int m = 0; m < 32; ++m) z[m] = (m == lane) ? 1.0 : 0.0;
+  // software pipeline: column p + 1 of L (and its reciprocal pivot) is loaded while column
+  // p is applied, so the LDS latency overlaps the substitution
+  double cn[32], rn = R[0];
+#pragma unroll
+  for (int m = 1; m < 32; ++m) cn[m] = L[m];
 #pragma unroll
   for (int p = 0; p < 32; ++p) {
-    z[p] *= R[p];
+    double cc[32];
+    const double rp = rn;
 #pragma unroll
-    for (int m = p + 1; m < 32; ++m) z[m] -= L[p * 32 + m] * z[p];
+    for (int m = p + 1; m < 32; ++m) cc[m] = cn[m];
+    if (p + 1 < 32) {
+      rn = R[p + 1];
+#pragma unroll
+      for (int m = p + 2; m < 32; ++m) cn[m] = L[(p + 1) * 32 + m];
+    }
+    __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of this column's arithmetic
+    z[p] *= rp;
+#pragma unroll
+    for (int m = p + 1; m < 32; ++m) z[m] -= cc[m] * z[p];
   }
   wave_lds_sync();  // every read of R is done
   if (lane < 32) {
@@ -1163,8 +1185,10 @@ __device__ void run_part(const SchedArgs& a, uint32_t task, uint32_t part, doubl
     }
     case SPX_T_SYRK:
     case SPX_T_GEMM: {
-      // part -> 128x128 sub-block (I, J) of the output tile; SYRK: lower blocks only
-      const int sb = b < 128 ? b : 128, ns = b / sb;
+      // part -> 128x128 sub-block (I, J) of the output tile (64x64 for the SYRK that the
+      // next diagonal factorization waits on); SYRK: lower blocks only
+      const int sbase = (d.type == SPX_T_SYRK && d.pad) ? 64 : 128;
+      const int sb = b < sbase ? b : sbase, ns = b / sb;
       int I, J;
       if (d.type == SPX_T_SYRK) {
         I = 0;
