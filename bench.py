@@ -34,9 +34,9 @@ PEAK_FP64_TFLOPS = 78.6  # MI355X dense FP64 matrix peak
 # WRITE x 1).  Valid only for the kernel source it was measured on (sha256 below); for any
 # other source the benchmark reports null.
 TRAFFIC_RECORD = {
-    "kernel_sha256": "4715c603a6edac22a26de9b93f39db96765045f9069d6e35780e39a3ba350986",
+    "kernel_sha256": "b27cfdecdc485e02036582d77fffb2ce2cf0c5126812193127f4fe3ff44d6908",
     "n": 16384, "tile": 512,
-    "fetch_kib": 48683521.25, "write_kib": 30776094.71875, "fetch_scale": 2.0, "write_scale": 1.0,
+    "fetch_kib": 46959647.9375, "write_kib": 32018963.59375, "fetch_scale": 2.0, "write_scale": 1.0,
 }
 
 
