@@ -272,7 +272,9 @@ int32_t cholesky_priority(const TaskDesc& d, int nt) {
     case SPX_T_POTRF: base = 4; break;
     case SPX_T_TRSM: base = 3; break;
     case SPX_T_SYRK: base = (d.i == d.k + 1) ? 3 : 1; break;
-    case SPX_T_GEMM: base = (d.j == d.k + 1) ? 2 : 0; break;
+    // updates of the next panel column first, then of the one after it: the last updates
+    // of tile (k+2, k+1) gate TRSM(k+2, k+1) on the critical path
+    case SPX_T_GEMM: base = (d.j == d.k + 1) ? 2 : (d.j == d.k + 2 ? 1 : 0); break;
     case SPX_T_LOAD: base = 0; break;   // a new matrix starts when nothing urgent is ready
     case SPX_T_STORE: base = 4; break;
     // substitution: the diagonal solves and the update of the next block form the chain
