@@ -564,17 +564,147 @@ __device__ void gemm_tall32_f64(double* __restrict__ C, int ldc, const double* _
   }
 }
 
+// Tall update for the POTRF panels: C[M x 32] -= A B^T, barrier-free in its main loop.
+// The waves form 4/KS row groups of KS waves; the waves of a group split K (wave w: row
+// group w / KS, K range (w % KS) K/KS ...), each taking up to NBW 16-row blocks of its
+// group and loading its fragments straight from global memory a group of G 4-deep steps
+// ahead (no LDS, no barrier in the loop, so the four waves drift freely and the latency
+// of one wave's loads hides behind the others' products).  With KS > 1 the partial
+// products meet in LDS and each wave reduces and writes a quarter of the 16x16 tiles.
+// Products transposed as in gemm_tall32_f64 (lane l: row 16q + l%16, column 16 jb + l/16
+// + 4v).  M: multiple of 16, at most 16 NBW 4/KS.  K: multiple of 16 G KS.
+template <int NBW, int G, int KS>
+__device__ void gemm_tall32_split(double* __restrict__ C, int ldc, const double* __restrict__ A, int lda,
+                                  const double* __restrict__ B, int ldb, int M, int K, bool lower,
+                                  double* __restrict__ lds) {
+  constexpr int GROUPS = 4 / KS;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int nblk = M >> 4, kl = lane >> 4, li = lane & 15;
+  const int nbp = (nblk + GROUPS - 1) / GROUPS;  // row blocks per group
+  const int rg = wave / KS, q0 = rg * nbp;
+  const int nmine = nblk - q0 < nbp ? (nblk - q0 > 0 ? nblk - q0 : 0) : nbp;
+  const int kq = K / KS, kb = (wave % KS) * kq;
+  const GLOBAL double* Ag = gp(A);
+  const GLOBAL double* Bg = gp(B);
+  d4 acc[NBW][2];
+#pragma unroll
+  for (int t = 0; t < NBW; ++t) acc[t][0] = acc[t][1] = d4{0.0, 0.0, 0.0, 0.0};
+  double an[G][NBW], bn[G][2];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int s4 = 0; s4 < G; ++s4) {
+      const size_t kr = (size_t)(k0 + 4 * s4 + kl);
+#pragma unroll
+      for (int t = 0; t < NBW; ++t) an[s4][t] = t < nmine ? Ag[kr * lda + 16 * (q0 + t) + li] : 0.0;
+      bn[s4][0] = Bg[kr * ldb + li];
+      bn[s4][1] = Bg[kr * ldb + 16 + li];
+    }
+  };
+  const int ng = kq / (4 * G);
+  if (ng > 0) load(kb);
+  for (int g = 0; g < ng; ++g) {
+    double ac[G][NBW], bc[G][2];
+#pragma unroll
+    for (int s4 = 0; s4 < G; ++s4) {
+#pragma unroll
+      for (int t = 0; t < NBW; ++t) ac[s4][t] = an[s4][t];
+      bc[s4][0] = bn[s4][0];
+      bc[s4][1] = bn[s4][1];
+    }
+    if (g + 1 < ng) load(kb + (g + 1) * 4 * G);
+#pragma unroll
+    for (int s4 = 0; s4 < G; ++s4)
+#pragma unroll
+      for (int t = 0; t < NBW; ++t) {
+        if (t < nmine) {
+          acc[t][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(bc[s4][0], ac[s4][t], acc[t][0], 0, 0, 0);
+          acc[t][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(bc[s4][1], ac[s4][t], acc[t][1], 0, 0, 0);
+        }
+      }
+  }
+  GLOBAL double* Cg = gp(C);
+  if (KS == 1) {  // each wave owns its rows: write them directly, all old values first
+    double old[NBW][2][4];
+#pragma unroll
+    for (int t = 0; t < NBW; ++t)
+#pragma unroll
+      for (int jb = 0; jb < 2; ++jb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = 16 * (q0 + t) + li, col = 16 * jb + kl + 4 * v;
+          old[t][jb][v] = (t < nmine && (!lower || row >= col)) ? Cg[(size_t)col * ldc + row] : 0.0;
+        }
+#pragma unroll
+    for (int t = 0; t < NBW; ++t) {
+      if (t >= nmine) continue;
+#pragma unroll
+      for (int jb = 0; jb < 2; ++jb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = 16 * (q0 + t) + li, col = 16 * jb + kl + 4 * v;
+          if (!lower || row >= col) Cg[(size_t)col * ldc + row] = old[t][jb][v] - acc[t][jb][v];
+        }
+    }
+    return;
+  }
+  // partials: P[w][tile][v][lane], tile = 2 t + jb of the wave's row group
+  LDSAS double* P = lp(lds);
+  constexpr int T = 2 * NBW;
+  __syncthreads();  // the caller's previous use of LDS is over
+#pragma unroll
+  for (int t = 0; t < NBW; ++t)
+#pragma unroll
+    for (int jb = 0; jb < 2; ++jb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) P[((wave * T + 2 * t + jb) * 4 + v) * 64 + lane] = acc[t][jb][v];
+  __syncthreads();
+  for (int tile = wave; tile < 2 * nblk; tile += 4) {
+    const int q = tile >> 1, jb = tile & 1;
+    const int g0 = (q / nbp) * KS, lt = 2 * (q % nbp) + jb;  // first wave of the row group, its tile
+    const int row = 16 * q + li;
+    double sum[4], old[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      double acc_v = 0.0;
+#pragma unroll
+      for (int h = 0; h < KS; ++h) acc_v += P[(((g0 + h) * T + lt) * 4 + v) * 64 + lane];
+      sum[v] = acc_v;
+      const int col = 16 * jb + kl + 4 * v;
+      old[v] = (!lower || row >= col) ? Cg[(size_t)col * ldc + row] : 0.0;
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int col = 16 * jb + kl + 4 * v;
+      if (!lower || row >= col) Cg[(size_t)col * ldc + row] = old[v] - sum[v];
+    }
+  }
+  __syncthreads();  // LDS partials consumed before the caller reuses LDS
+}
+
 __device__ void gemm_tall32_any(double* C, int ldc, const double* A, int lda, const double* B, int ldb, int M, int K,
                                 bool lower, double* lds) {
   if (K <= 0 || M <= 0) return;
-  if (M <= 64 && K % 64 == 0)
+  if (M <= 128 && K % 64 == 0) {  // few rows: K split four ways
+    if (M <= 32) gemm_tall32_split<2, 4, 4>(C, ldc, A, lda, B, ldb, M, K, lower, lds);
+    else if (M <= 64) gemm_tall32_split<4, 4, 4>(C, ldc, A, lda, B, ldb, M, K, lower, lds);
+    else gemm_tall32_split<8, 4, 4>(C, ldc, A, lda, B, ldb, M, K, lower, lds);
+  } else if (M <= 128 && K % 32 == 0) {
+    if (M <= 32) gemm_tall32_split<2, 2, 4>(C, ldc, A, lda, B, ldb, M, K, lower, lds);
+    else if (M <= 64) gemm_tall32_split<4, 2, 4>(C, ldc, A, lda, B, ldb, M, K, lower, lds);
+    else gemm_tall32_split<8, 2, 4>(C, ldc, A, lda, B, ldb, M, K, lower, lds);
+  } else if (M <= 256 && K % 32 == 0) {  // two row groups, K split two ways
+    gemm_tall32_split<8, 4, 2>(C, ldc, A, lda, B, ldb, M, K, lower, lds);
+  } else if (M <= 512 && K % 16 == 0) {  // four row groups
+    gemm_tall32_split<8, 4, 1>(C, ldc, A, lda, B, ldb, M, K, lower, lds);
+  } else if (M <= 64 && K % 64 == 0) {
     gemm_tall32_f64<1, false>(C, ldc, A, lda, B, ldb, M, K, lower, lds);
-  else if (M <= 128 && K % 32 == 0)
+  } else if (M <= 128 && K % 32 == 0) {
     gemm_tall32_f64<2, false>(C, ldc, A, lda, B, ldb, M, K, lower, lds);
-  else if (M <= 256 && K % 32 == 0)
+  } else if (M <= 256 && K % 32 == 0) {
     gemm_tall32_f64<4, false>(C, ldc, A, lda, B, ldb, M, K, lower, lds);
-  else
+  } else {
     gemm_tall32_f64<8, false>(C, ldc, A, lda, B, ldb, M, K, lower, lds);
+  }
 }
 
 // X[M x 32] <- X * Li^T in place, Li a 32x32 block inverse (column-major, ld 32).
