@@ -89,7 +89,7 @@ int build_graph(uint32_t ntasks, const spx_access* acc, uint64_t nacc, const int
 // per diagonal tile and the block forward and backward substitution.  Datum ids: tile
 // (i,j) -> i*nt + j; right-hand-side block k -> nt*nt + k; M_k = L_kk^{-T} -> nt*nt + nt + k.
 void cholesky_program(int nt, bool with_solve, std::vector<TaskDesc>& tasks, std::vector<spx_access>& acc,
-                      bool with_inverse) {
+                      bool with_inverse, int potrf_steps) {
   tasks.clear();
   acc.clear();
   auto A = [nt](int i, int j) { return (uint64_t)i * (uint64_t)nt + (uint64_t)j; };
@@ -112,8 +112,12 @@ void cholesky_program(int nt, bool with_solve, std::vector<TaskDesc>& tasks, std
     acc.push_back(spx_access{(uint32_t)(tasks.size() - 1), mode, datum});
   };
   for (int k = 0; k < nt; ++k) {
-    task(SPX_T_POTRF, k, k, k);
-    use(SPX_ACC_RW, A(k, k));
+    // a diagonal factorization split into steps is a chain of tasks on the same tile
+    for (int st = 0; st < potrf_steps; ++st) {
+      task(SPX_T_POTRF, k, k, k);
+      if (potrf_steps > 1) tasks.back().pad = (uint16_t)(st | (potrf_steps << 8));
+      use(SPX_ACC_RW, A(k, k));
+    }
     for (int i = k + 1; i < nt; ++i) {
       task(SPX_T_TRSM, i, k, k);
       use(SPX_ACC_R, A(k, k));
@@ -214,10 +218,10 @@ void solve_program(int nt, std::vector<TaskDesc>& tasks, std::vector<spx_access>
 // right-hand-side blocks), so each tile's first update depends on it; STORE reads the
 // solution blocks after the backward substitution.
 void io_program(int nt, bool with_solve, std::vector<TaskDesc>& tasks, std::vector<spx_access>& acc,
-                bool with_inverse) {
+                bool with_inverse, int potrf_steps) {
   std::vector<TaskDesc> body;
   std::vector<spx_access> body_acc;
-  cholesky_program(nt, with_solve, body, body_acc, with_inverse);
+  cholesky_program(nt, with_solve, body, body_acc, with_inverse, potrf_steps);
   auto A = [nt](int i, int j) { return (uint64_t)i * (uint64_t)nt + (uint64_t)j; };
   auto B = [nt](int k) { return (uint64_t)nt * (uint64_t)nt + (uint64_t)k; };
   tasks.clear();

@@ -149,8 +149,8 @@ static void dev_free(spx_ctx* c, void* p) {
     (void)hipFree(p);
 }
 
-static int get_program(spx_ctx* c, char kind, int nt, const Program** out) {
-  const std::string key = std::string(1, kind) + ":" + std::to_string(nt);
+static int get_program(spx_ctx* c, char kind, int nt, const Program** out, int psteps) {
+  const std::string key = std::string(1, kind) + ":" + std::to_string(nt) + ":" + std::to_string(psteps);
   auto it = c->programs.find(key);
   if (it != c->programs.end()) {
     *out = it->second.get();
@@ -159,11 +159,11 @@ static int get_program(spx_ctx* c, char kind, int nt, const Program** out) {
   std::unique_ptr<Program> pr(new Program());
   std::vector<spx_access> acc;
   switch (kind) {
-    case 'F': cholesky_program(nt, false, pr->tasks, acc, true); break;
+    case 'F': cholesky_program(nt, false, pr->tasks, acc, true, psteps); break;
     case 'S': solve_program(nt, pr->tasks, acc); break;
-    case 'L': io_program(nt, false, pr->tasks, acc, true); break;
-    case 'P': io_program(nt, true, pr->tasks, acc, false); break;
-    case 'K': io_program(nt, true, pr->tasks, acc, true); break;
+    case 'L': io_program(nt, false, pr->tasks, acc, true, psteps); break;
+    case 'P': io_program(nt, true, pr->tasks, acc, false, psteps); break;
+    case 'K': io_program(nt, true, pr->tasks, acc, true, psteps); break;
     case 'Q': solve_io_program(nt, pr->tasks, acc); break;
     default: return fail(SPX_EINVAL, "unknown program kind");
   }
@@ -188,12 +188,20 @@ static int default_tile(int64_t n) {
 // Parts per task for tile size b and right-hand-side count nrhs.
 int trsm_rows_of(int /*b*/) { return 32; }  // the TRSM and inversion kernels take 32-row strips
 
+// Steps of a diagonal factorization: the large tiles (whose one-workgroup POTRF would
+// dominate the critical path) are factored 32 columns per task, with the rows of each step
+// spread over workgroups.
+int potrf_steps_of(int b) { return b >= 256 ? b / 32 : 1; }
+
 uint16_t parts_of(const TaskDesc& d, int b, int nrhs) {
   const int sbase = (d.type == SPX_T_SYRK && d.pad) ? 64 : 128;
   const int sb = b < sbase ? b : sbase, ns = b / sb;
   const int rows = b < 64 ? b : 64;
   switch (d.type) {
-    case SPX_T_POTRF: return 1;
+    case SPX_T_POTRF: {  // step c: the diagonal part, plus one per 32-row block below c + 1
+      const int steps = d.pad >> 8, c = d.pad & 0xff, rows = steps - c - 2;
+      return (uint16_t)(steps > 1 && c >= 1 && rows > 0 ? 1 + rows : 1);
+    }
     case SPX_T_TRSM: return (uint16_t)(b / trsm_rows_of(b));
     case SPX_T_SYRK: return (uint16_t)(ns * (ns + 1) / 2);
     case SPX_T_GEMM: return (uint16_t)(ns * ns);
@@ -224,7 +232,7 @@ static int level_of(int32_t prio, int policy) {
 // solves: the inversions would cost more than they save); 'K': LOAD + factor +
 // inversions + substitution with the inverses + STORE (factors kept for more solves);
 // 'Q': LOAD of the right-hand sides + substitution with the inverses + STORE.
-static int get_program(spx_ctx* c, char kind, int nt, const Program** out);
+static int get_program(spx_ctx* c, char kind, int nt, const Program** out, int psteps = 1);
 
 // One matrix's share of an image: its program, descriptor index, tile size and
 // right-hand-side count (parts per task depend on both).
@@ -359,7 +367,7 @@ static int get_image(spx_ctx* c, bool solve, int nt, int b, int nrhs, int policy
     return SPX_OK;
   }
   const Program* pr = nullptr;
-  SPX_TRY(get_program(c, solve ? 'S' : 'F', nt, &pr));
+  SPX_TRY(get_program(c, solve ? 'S' : 'F', nt, &pr, solve ? 1 : potrf_steps_of(b)));
   Image* im = nullptr;
   SPX_TRY(make_image(c, {Piece{pr, 0, b, nrhs}}, policy, &im));
   c->images[key] = im;
@@ -711,7 +719,7 @@ static int batched(spx_ctx* c, int count, const int64_t* n, const double* const*
   std::vector<Piece> pieces(count);
   for (int m = 0; m < count; ++m) {
     const Program* pr = nullptr;
-    int rc = get_program(c, kind, nts[m], &pr);
+    int rc = get_program(c, kind, nts[m], &pr, potrf_steps_of(bs[m]));
     if (rc) {
       release();
       return rc;

@@ -38,14 +38,17 @@ struct TaskDesc {
 static_assert(sizeof(TaskDesc) == 16, "TaskDesc must stay 16 bytes");
 
 int build_graph(uint32_t ntasks, const spx_access* acc, uint64_t nacc, const int32_t* priority, Graph& g);
+// potrf_steps > 1: each POTRF(k) becomes that many chained step tasks (TaskDesc.pad =
+// step | (potrf_steps << 8)); the device splits the diagonal factorization at 32 columns
+// per step, so potrf_steps must be b / 32.
 void cholesky_program(int nt, bool with_solve, std::vector<TaskDesc>& tasks, std::vector<spx_access>& acc,
-                      bool with_inverse = false);
+                      bool with_inverse = false, int potrf_steps = 1);
 void solve_program(int nt, std::vector<TaskDesc>& tasks, std::vector<spx_access>& acc);
 int32_t cholesky_priority(const TaskDesc& d, int nt);
 // LOAD, the factor program (and with_solve: the substitution), STORE (with_solve only);
 // with_inverse: the inversion tasks and the inverse-based substitution.
 void io_program(int nt, bool with_solve, std::vector<TaskDesc>& tasks, std::vector<spx_access>& acc,
-                bool with_inverse);
+                bool with_inverse, int potrf_steps = 1);
 // LOAD of the right-hand sides only (TaskDesc.j = 1), the substitution, STORE.
 void solve_io_program(int nt, std::vector<TaskDesc>& tasks, std::vector<spx_access>& acc);
 

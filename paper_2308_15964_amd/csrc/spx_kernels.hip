@@ -716,6 +716,39 @@ __device__ void apply_inv_tall(double* X, int ldx, const double* Li, int M, doub
     gemm_tall32_f64<8, true>(X, ldx, X, ldx, Li, 32, M, 32, false, lds);
 }
 
+// One workgroup factors the updated 32x32 diagonal block at (c0, c0) of a b x b tile in
+// place (one wave, in LDS) and stores its inverse as block c0/32 of dinv.  Returns (to all
+// threads) 0 or the 1-based local column of a non-positive or NaN pivot.
+__device__ int factor_diag32(double* __restrict__ a, int b, int c0, double* __restrict__ dinv,
+                             double* __restrict__ lds) {
+  __shared__ int s_bad;
+  const int tid = threadIdx.x;
+  double* D = lds + LDS_D_OFF;
+  double* Z = D + 1024;
+  LDSAS double* Dl = lp(D);
+  LDSAS double* Zl = lp(Z);
+  for (int e = tid; e < 1024; e += NT) {
+    const int r = e & 31, j = e >> 5;
+    Dl[e] = r >= j ? a[(size_t)(c0 + j) * b + c0 + r] : 0.0;
+  }
+  if (tid == 0) s_bad = 0;
+  __syncthreads();
+  if (tid < 64) {
+    const int bad = factor_inverse32(D, Z);
+    if (bad && tid == 0) s_bad = c0 + bad;
+  }
+  __syncthreads();
+  if (s_bad) return s_bad;
+  double* dblk = dinv + (size_t)c0 * 32;
+  for (int e = tid; e < 1024; e += NT) {
+    const int r = e & 31, j = e >> 5;
+    if (r >= j) a[(size_t)(c0 + j) * b + c0 + r] = Dl[e];
+    dblk[e] = Zl[e];
+  }
+  __syncthreads();
+  return 0;
+}
+
 // ---------------------------------------------------------------------------------------
 // POTRF: in-place lower Cholesky of one b x b tile by one workgroup.  Left-looking over
 // 32-wide panels: the panel (rows c0.., columns c0..c0+31) first receives the updates of
@@ -726,37 +759,58 @@ __device__ void apply_inv_tall(double* X, int ldx, const double* Li, int M, doub
 // threads) 0 or the 1-based local column of a non-positive or NaN pivot.
 // ---------------------------------------------------------------------------------------
 __device__ int potrf_tile(double* __restrict__ a, int b, double* __restrict__ dinv, double* __restrict__ lds) {
-  __shared__ int s_bad;
-  const int tid = threadIdx.x;
-  double* D = lds + LDS_D_OFF;
-  double* Z = D + 1024;
-  LDSAS double* Dl = lp(D);
-  LDSAS double* Zl = lp(Z);
   for (int c0 = 0; c0 < b; c0 += 32) {
     gemm_tall32_any(a + (size_t)c0 * b + c0, b, a + c0, b, a + c0, b, b - c0, c0, true, lds);
     __syncthreads();
-    for (int e = tid; e < 1024; e += NT) {
-      const int r = e & 31, j = e >> 5;
-      Dl[e] = r >= j ? a[(size_t)(c0 + j) * b + c0 + r] : 0.0;
-    }
-    if (tid == 0) s_bad = 0;
-    __syncthreads();
-    if (tid < 64) {
-      const int bad = factor_inverse32(D, Z);
-      if (bad && tid == 0) s_bad = c0 + bad;
-    }
-    __syncthreads();
-    if (s_bad) return s_bad;
-    double* dblk = dinv + (size_t)c0 * 32;
-    for (int e = tid; e < 1024; e += NT) {
-      const int r = e & 31, j = e >> 5;
-      if (r >= j) a[(size_t)(c0 + j) * b + c0 + r] = Dl[e];
-      dblk[e] = Zl[e];
-    }
-    __syncthreads();
-    apply_inv_tall(a + (size_t)c0 * b + c0 + 32, b, dblk, b - c0 - 32, lds);
+    const int bad = factor_diag32(a, b, c0, dinv, lds);
+    if (bad) return bad;
+    apply_inv_tall(a + (size_t)c0 * b + c0 + 32, b, dinv + (size_t)c0 * 32, b - c0 - 32, lds);
     __syncthreads();
   }
+  return 0;
+}
+
+// ---------------------------------------------------------------------------------------
+// POTRF split into b/32 dependent steps, each cut into workgroup parts, for the large
+// diagonal tiles whose single-workgroup factorization would hold up the whole
+// elimination.  The algorithm is the left-looking one above, with the scaling of a
+// column block by the inverse of its diagonal block deferred to the next step, so one
+// step needs no wait inside it.  Step c (c0 = 32 c), with 32-row blocks R_r:
+//   part 0:  R_{c+1}[:, c-1] <- R_{c+1}[:, c-1] Z_{c-1}^T   (if c >= 1 and c + 1 < b/32)
+//            (R_c; R_{c+1})[:, c] -= (R_c; R_{c+1})[:, 0:c0] R_c[:, 0:c0]^T
+//            factor and invert the diagonal block (c, c) -> L_cc, Z_c
+//            R_{c+1}[:, c] <- R_{c+1}[:, c] Z_c^T
+//   part p >= 1 (c >= 1), r = c + 1 + p:
+//            R_r[:, c-1] <- R_r[:, c-1] Z_{c-1}^T
+//            R_r[:, c] -= R_r[:, 0:c0] R_c[:, 0:c0]^T
+// Every block R_c[:, 0:c0] read by the row parts was made final in an earlier step, and
+// part 0 writes only row blocks c and c + 1, which no row part reads, so the parts of a
+// step are independent; successive steps are ordered by the task graph.  The update of a
+// row block may split K differently from potrf_tile's (its kernel depends on the row
+// count), so the two forms agree to rounding, not bitwise.  Returns (to all threads) 0 or
+// the 1-based local column of a bad pivot.
+// ---------------------------------------------------------------------------------------
+__device__ int potrf_step_part(double* __restrict__ a, int b, double* __restrict__ dinv, int c, int part,
+                               double* __restrict__ lds) {
+  const int nb = b >> 5, c0 = 32 * c;
+  if (part > 0) {
+    const int r0 = 32 * (c + 1 + part);
+    if (c < 1 || r0 >= b) return 0;
+    apply_inv_tall(a + (size_t)(c0 - 32) * b + r0, b, dinv + (size_t)(c0 - 32) * 32, 32, lds);
+    __syncthreads();
+    gemm_tall32_any(a + (size_t)c0 * b + r0, b, a + r0, b, a + c0, b, 32, c0, false, lds);
+    return 0;
+  }
+  const bool look = c + 1 < nb;
+  if (c >= 1 && look) {
+    apply_inv_tall(a + (size_t)(c0 - 32) * b + c0 + 32, b, dinv + (size_t)(c0 - 32) * 32, 32, lds);
+    __syncthreads();
+  }
+  gemm_tall32_any(a + (size_t)c0 * b + c0, b, a + c0, b, a + c0, b, look ? 64 : 32, c0, true, lds);
+  __syncthreads();
+  const int bad = factor_diag32(a, b, c0, dinv, lds);
+  if (bad) return bad;
+  if (look) apply_inv_tall(a + (size_t)c0 * b + c0 + 32, b, dinv + (size_t)c0 * 32, 32, lds);
   return 0;
 }
 
@@ -1299,7 +1353,10 @@ __device__ void run_part(const SchedArgs& a, uint32_t task, uint32_t part, doubl
   const int b = m.b;
   switch (d.type) {
     case SPX_T_POTRF: {
-      const int bad = potrf_tile(tile_ptr(m, d.k, d.k), b, dinv_ptr(m, d.k), lds);
+      // pad = step | (steps << 8) when the factorization is split into steps
+      const int steps = d.pad >> 8;
+      const int bad = steps > 1 ? potrf_step_part(tile_ptr(m, d.k, d.k), b, dinv_ptr(m, d.k), d.pad & 0xff, (int)part, lds)
+                                : potrf_tile(tile_ptr(m, d.k, d.k), b, dinv_ptr(m, d.k), lds);
       if (bad && threadIdx.x == 0)
         __hip_atomic_fetch_min(m.info, d.k * b + bad, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       break;

@@ -180,6 +180,52 @@ def test_not_positive_definite(ctx, seed):
     F.close()
 
 
+def test_potrf_steps_integer_exact(ctx):
+    """Tiles of 256 and 512 factor their diagonal tiles in 32-column step tasks spread over
+    workgroups; on an integer factor every rounding order gives the exact L0."""
+    for n, b in [(600, 256), (700, 512)]:
+        print(f"steps n={n} b={b}", flush=True)
+        A, L0, X0, B = inputs.integer_factor(n, seed=n, nrhs=2, unit=True)
+        F = ctx.potrf(dev(A), tile=b)
+        assert np.array_equal(host(F.L()), L0)
+        F.close()
+
+
+@pytest.mark.parametrize("bad", [5, 300, 543])
+def test_potrf_steps_not_positive_definite(ctx, bad):
+    """A pivot that fails inside a step task reports the same 1-based column as the oracle."""
+    from paper_2308_15964_amd import spx
+
+    n = 600
+    A, _ = inputs.gram_spd(n, seed=410)
+    A[bad, bad] = -1.0
+    _, _, info = oracle.cholesky(A, oracle_tile(n))
+    assert info > 0
+    with pytest.raises(spx.NotPositiveDefinite) as e:
+        ctx.potrf(dev(A), tile=256)
+    assert e.value.info == info
+    F = ctx.potrf(dev(inputs.gram_spd(n, seed=5)[0]), tile=256)
+    F.close()
+
+
+def test_potrf_steps_schedules_bitwise_identical(ctx):
+    """With the step tasks every schedule still gives the same bits."""
+    from paper_2308_15964_amd import spx
+
+    A, B = inputs.gram_spd(1024, seed=19, nrhs=1)
+    Ad, Bd = dev(A), dev(B)
+    ref = None
+    for policy, nwg in [(spx.Q_PRIORITY, 0), (spx.Q_FIFO, 0), (spx.Q_PRIORITY, 3), (spx.Q_FIFO, 1)]:
+        F = ctx.potrf(Ad, tile=256, queue_policy=policy, num_wg=nwg)
+        L = host(F.L())
+        if ref is None:
+            ref = L
+            Lo, _, _ = oracle.cholesky(A, oracle_tile(1024))
+            check_factor(A, L, Lo)
+        assert np.array_equal(L, ref), (policy, nwg)
+        F.close()
+
+
 def test_invalid_arguments(ctx):
     from paper_2308_15964_amd import spx
 
@@ -206,7 +252,9 @@ def test_config2_full_size_properties(ctx):
     A, Bd = bench.gen_input(n, 2, 1, "cuda:0")
     F = ctx.potrf(A, tile=b)
     st = ctx.stats()
-    assert st["ntasks"] == 5984 + 32
+    # the program, one inversion per diagonal tile, and each diagonal factorization cut
+    # into b/32 chained steps (15 more tasks per diagonal tile)
+    assert st["ntasks"] == 5984 + 32 + 32 * 15
     X = ctx.potrs(F, Bd)
     L = F.L().cpu().numpy()
     F.close()
