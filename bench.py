@@ -31,26 +31,38 @@ PEAK_FP64_TFLOPS = 78.6  # MI355X dense FP64 matrix peak
 
 # HBM traffic of one factor launch at N=16384, tile 512, from two rocprofv3 PMC runs
 # (FETCH_SIZE, WRITE_SIZE in KiB) scaled by the counts of a 1 GiB device copy (FETCH x 2,
-# WRITE x 1).  Valid only for the kernel source it was measured on (sha256 below); for any
-# other source the benchmark reports null.
+# WRITE x 1).  Valid only for the library sources it was measured on (the kernels, and the
+# graph and scheduler code that decide what the launch runs; sha256 over them below); for
+# any other sources the benchmark reports null.
 TRAFFIC_RECORD = {
-    "kernel_sha256": "b27cfdecdc485e02036582d77fffb2ce2cf0c5126812193127f4fe3ff44d6908",
+    "sources_sha256": "b27cfdecdc485e02036582d77fffb2ce2cf0c5126812193127f4fe3ff44d6908",
     "n": 16384, "tile": 512,
     "fetch_kib": 46959647.9375, "write_kib": 32018963.59375, "fetch_scale": 2.0, "write_scale": 1.0,
 }
 
 
-def recorded_traffic(n, tile):
+def sources_digest():
+    """sha256 over the library's native sources (csrc/, sorted by name), or None."""
     import hashlib
 
-    src = os.path.join(ROOT, "paper_2308_15964_amd", "csrc", "spx_kernels.hip")
+    src = os.path.join(ROOT, "paper_2308_15964_amd", "csrc")
+    h = hashlib.sha256()
     try:
-        with open(src, "rb") as f:
-            digest = hashlib.sha256(f.read()).hexdigest()
+        for name in sorted(os.listdir(src)):
+            if name.endswith((".hip", ".cpp", ".h")):
+                with open(os.path.join(src, name), "rb") as f:
+                    h.update(name.encode() + b"\0" + f.read())
     except OSError:
         return None
+    return h.hexdigest()
+
+
+def recorded_traffic(n, tile):
+    digest = sources_digest()
+    if digest is None:
+        return None
     r = TRAFFIC_RECORD
-    if digest != r["kernel_sha256"] or n != r["n"] or tile != r["tile"]:
+    if digest != r["sources_sha256"] or n != r["n"] or tile != r["tile"]:
         return None
     return round((r["fetch_kib"] * r["fetch_scale"] + r["write_kib"] * r["write_scale"]) * 1024.0)
 

@@ -55,8 +55,8 @@ typedef unsigned long long u64;
 struct Image {
   uint32_t ntasks = 0, total_parts = 0;
   int nlev = 1;
-  uint32_t qbase[kMaxLevels] = {0, 0, 0, 0};
-  uint32_t qcap[kMaxLevels] = {0, 0, 0, 0};
+  uint32_t qbase[kMaxLevels] = {};
+  uint32_t qcap[kMaxLevels] = {};
   uint32_t nroots = 0;
   int nshards = 1;
   void* block = nullptr;  // one allocation for every array below
@@ -188,10 +188,13 @@ static int default_tile(int64_t n) {
 // Parts per task for tile size b and right-hand-side count nrhs.
 int trsm_rows_of(int /*b*/) { return 32; }  // the TRSM and inversion kernels take 32-row strips
 
-// Steps of a diagonal factorization: the large tiles (whose one-workgroup POTRF would
-// dominate the critical path) are factored 32 columns per task, with the rows of each step
-// spread over workgroups.
-int potrf_steps_of(int b) { return b >= 256 ? b / 32 : 1; }
+// Steps of a diagonal factorization: large tiles of a matrix with at least four tile
+// columns (whose one-workgroup POTRFs would dominate the critical path) are factored 32
+// columns per task, with the rows of each step spread over workgroups.  Matrices of one or
+// two tiles are left whole: their steps would only add task hops to a batched launch that
+// other matrices already fill.  The rule depends on (nt, b) alone, so a matrix gets the
+// same tasks, and the same bits, alone and in a batch.
+int potrf_steps_of(int nt, int b) { return b >= 256 && nt >= 4 ? b / 32 : 1; }
 
 uint16_t parts_of(const TaskDesc& d, int b, int nrhs) {
   const int sbase = (d.type == SPX_T_SYRK && d.pad) ? 64 : 128;
@@ -262,7 +265,7 @@ static int make_image(spx_ctx* c, const std::vector<Piece>& pieces, int policy, 
   im->nlev = policy == SPX_Q_FIFO ? 1 : kMaxLevels;
   std::vector<TaskDesc> tasks(T);
   std::vector<uint32_t> off32(T + 1), succ(std::max<size_t>(E, 1)), indeg(T), nparts(T);
-  uint64_t per_level[kMaxLevels] = {0, 0, 0, 0};
+  uint64_t per_level[kMaxLevels] = {};
   uint32_t t0 = 0;
   size_t e0 = 0;
   for (const Piece& pc : pieces) {
@@ -367,7 +370,7 @@ static int get_image(spx_ctx* c, bool solve, int nt, int b, int nrhs, int policy
     return SPX_OK;
   }
   const Program* pr = nullptr;
-  SPX_TRY(get_program(c, solve ? 'S' : 'F', nt, &pr, solve ? 1 : potrf_steps_of(b)));
+  SPX_TRY(get_program(c, solve ? 'S' : 'F', nt, &pr, solve ? 1 : potrf_steps_of(nt, b)));
   Image* im = nullptr;
   SPX_TRY(make_image(c, {Piece{pr, 0, b, nrhs}}, policy, &im));
   c->images[key] = im;
@@ -719,7 +722,7 @@ static int batched(spx_ctx* c, int count, const int64_t* n, const double* const*
   std::vector<Piece> pieces(count);
   for (int m = 0; m < count; ++m) {
     const Program* pr = nullptr;
-    int rc = get_program(c, kind, nts[m], &pr, potrf_steps_of(bs[m]));
+    int rc = get_program(c, kind, nts[m], &pr, potrf_steps_of(nts[m], bs[m]));
     if (rc) {
       release();
       return rc;

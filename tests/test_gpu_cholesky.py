@@ -65,7 +65,8 @@ def check_solve(X, Xo, eta_o, tol=1e-12):
 
 
 CASES = [(32, 32, 1), (64, 32, 2), (100, 32, 3), (128, 64, 9), (200, 64, 1), (256, 128, 4), (384, 128, 1),
-         (500, 128, 2), (512, 256, 1), (512, 512, 3), (700, 256, 1), (1536, 512, 2)]
+         (500, 128, 2), (512, 256, 1), (512, 512, 3), (700, 256, 1), (1536, 512, 2), (1100, 256, 2),
+         (2100, 512, 1)]
 
 
 @pytest.mark.parametrize("n,b,nrhs", CASES)
@@ -181,9 +182,10 @@ def test_not_positive_definite(ctx, seed):
 
 
 def test_potrf_steps_integer_exact(ctx):
-    """Tiles of 256 and 512 factor their diagonal tiles in 32-column step tasks spread over
-    workgroups; on an integer factor every rounding order gives the exact L0."""
-    for n, b in [(600, 256), (700, 512)]:
+    """Tiles of 256 and 512 in matrices of at least four tile columns factor their diagonal
+    tiles in 32-column step tasks spread over workgroups; on an integer factor every
+    rounding order gives the exact L0."""
+    for n, b in [(1000, 256), (1900, 512)]:
         print(f"steps n={n} b={b}", flush=True)
         A, L0, X0, B = inputs.integer_factor(n, seed=n, nrhs=2, unit=True)
         F = ctx.potrf(dev(A), tile=b)
@@ -191,12 +193,12 @@ def test_potrf_steps_integer_exact(ctx):
         F.close()
 
 
-@pytest.mark.parametrize("bad", [5, 300, 543])
+@pytest.mark.parametrize("bad", [5, 300, 543, 990])
 def test_potrf_steps_not_positive_definite(ctx, bad):
     """A pivot that fails inside a step task reports the same 1-based column as the oracle."""
     from paper_2308_15964_amd import spx
 
-    n = 600
+    n = 1000
     A, _ = inputs.gram_spd(n, seed=410)
     A[bad, bad] = -1.0
     _, _, info = oracle.cholesky(A, oracle_tile(n))
