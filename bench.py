@@ -35,9 +35,9 @@ PEAK_FP64_TFLOPS = 78.6  # MI355X dense FP64 matrix peak
 # graph and scheduler code that decide what the launch runs; sha256 over them below); for
 # any other sources the benchmark reports null.
 TRAFFIC_RECORD = {
-    "sources_sha256": "b27cfdecdc485e02036582d77fffb2ce2cf0c5126812193127f4fe3ff44d6908",
+    "sources_sha256": "56ceab1a552abde653367fc74b9803cf176d6a937d43d2c20a34b7a90f8ef789",
     "n": 16384, "tile": 512,
-    "fetch_kib": 46959647.9375, "write_kib": 32018963.59375, "fetch_scale": 2.0, "write_scale": 1.0,
+    "fetch_kib": 37620179.125, "write_kib": 13995508.5, "fetch_scale": 2.0, "write_scale": 1.0,
 }
 
 
@@ -85,6 +85,8 @@ def parse():
     p.add_argument("--serve-requests", type=int, default=4000)
     p.add_argument("--serve-rate", type=float, default=2000.0)
     p.add_argument("--serve-lanes", type=int, default=2)
+    p.add_argument("--chain-trace", action="store_true",
+                   help="trace one factor launch (--n, --tile) and print its critical-chain sums")
     p.add_argument("--copy-probe", action="store_true",
                    help="only copy a 1 GiB device buffer three times (calibrates HBM byte counters)")
     return p.parse_args()
@@ -333,6 +335,59 @@ def bench_serving(ctx, count, rate, lanes, seed=8):
     return res
 
 
+def chain_trace(ctx, spx, A, n, b):
+    """Times the factor's critical chain from the library's per-part trace (100 MHz
+    device clock): per block column k, the span of POTRF(k) (with the hops between its
+    steps when the diagonal factorization is split), the wait of TRSM(k+1,k) after it, and
+    the spans of TRSM(k+1,k) and SYRK(k+1,k+1,k).  Task ids follow the program's insertion
+    order: for each k, POTRF(k) (S chained steps), TRSM(i,k) for i > k, then for each
+    i > k SYRK(i,i,k) followed by GEMM(i,j,k) for k < j < i; the inversions come last."""
+    import torch
+
+    nt = -(-n // b)
+    S = b // 32 if (b >= 256 and nt >= 4) else 1
+    rec = None
+    for _ in range(2):  # the first launch builds and uploads the image
+        F = ctx.potrf(A, tile=b, flags=spx.F_TRACE)
+        torch.cuda.synchronize()
+        rec = ctx.trace()
+        F.close()
+    idx, t = {}, 0
+    for k in range(nt):
+        for s_ in range(S):
+            idx[("P", k, s_)] = t; t += 1
+        for i in range(k + 1, nt):
+            idx[("T", i, k)] = t; t += 1
+        for i in range(k + 1, nt):
+            idx[("S", i, k)] = t; t += 1
+            t += i - k - 1  # the GEMMs of row i
+    t0 = int(rec[:, 2].min())
+    st, en = {}, {}
+    for task, _, s_, e in rec:
+        task = int(task)
+        st[task] = min(st.get(task, 1 << 62), int(s_) - t0)
+        en[task] = max(en.get(task, 0), int(e) - t0)
+    us = lambda x: x / 100.0
+    sums = dict(potrf_ms=0.0, potrf_hops_ms=0.0, trsm_wait_ms=0.0, trsm_ms=0.0, syrk_ms=0.0, syrk_to_potrf_ms=0.0)
+    per_potrf = []
+    for k in range(nt):
+        p0, pl = idx[("P", k, 0)], idx[("P", k, S - 1)]
+        per_potrf.append(us(en[pl] - st[p0]))
+        sums["potrf_ms"] += per_potrf[-1] / 1e3
+        sums["potrf_hops_ms"] += sum(us(st[p0 + s_ + 1] - en[p0 + s_]) for s_ in range(S - 1)) / 1e3
+        if k + 1 < nt:
+            tr, sy, nx = idx[("T", k + 1, k)], idx[("S", k + 1, k)], idx[("P", k + 1, 0)]
+            sums["trsm_wait_ms"] += us(st[tr] - en[pl]) / 1e3
+            sums["trsm_ms"] += us(en[tr] - st[tr]) / 1e3
+            sums["syrk_ms"] += us(en[sy] - st[sy]) / 1e3
+            sums["syrk_to_potrf_ms"] += us(st[nx] - en[sy]) / 1e3
+    out = {k: round(v, 3) for k, v in sums.items()}
+    out.update(n=n, tile=b, potrf_steps=S, launch_ms=round(us(int(rec[:, 3].max()) - t0) / 1e3, 3),
+               potrf_us_min=round(min(per_potrf), 1), potrf_us_max=round(max(per_potrf), 1),
+               idle_frac=round(ctx.stats()["idle_frac"], 4), ntasks=ctx.stats()["ntasks"])
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -357,6 +412,9 @@ def main():
     n, b, nrhs = args.n, args.tile, args.nrhs
     A, B = gen_input(n, args.seed, nrhs, dev)
     ctx = spx.Context(0)
+    if args.chain_trace:
+        print(json.dumps(chain_trace(ctx, spx, A, n, b)), flush=True)
+        return
     flop_factor = n ** 3 / 3.0
     flop_step = flop_factor + 2.0 * n * n * nrhs
 
