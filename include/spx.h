@@ -115,7 +115,10 @@ enum { SPX_T_POTRF = 0, SPX_T_TRSM, SPX_T_SYRK, SPX_T_GEMM, SPX_T_FTRSM, SPX_T_F
  * storage, writing every tile; the last one reads the solution blocks and writes X.
  * SPX_T_INV(k), appended after the factor tasks of the graphs the library runs (with_solve
  * bit 2 here), reads the factored diagonal tile L_kk and writes M_k = L_kk^{-T}; the
- * diagonal solves FTRSM(k) / BTRSM(k) then read M_k instead of L_kk. */
+ * diagonal solves FTRSM(k) / BTRSM(k) then read M_k instead of L_kk.  Bits 8-15 of
+ * with_solve (0 or 1: whole tasks; at most 64): each POTRF(k) becomes that many chained
+ * step tasks on tile (k,k), as the library runs the diagonal tiles of 256 and 512 in
+ * matrices of at least four tile columns (b/32 steps). */
 int spx_cholesky_graph(int32_t nt, int32_t with_solve, spx_graph** out, int32_t* task_types, uint32_t cap);
 
 /* ---------------------------------------------------------------------------------------

@@ -363,16 +363,18 @@ int spx_graph_to_dot(const spx_graph* g, const char* path) {
 void spx_graph_destroy(spx_graph* g) { delete g; }
 
 int spx_cholesky_graph(int32_t nt, int32_t with_solve, spx_graph** out, int32_t* task_types, uint32_t cap) {
-  if (!out || nt < 1 || nt > 4096 || with_solve < 0 || with_solve > 7)
+  if (!out || nt < 1 || nt > 4096 || with_solve < 0 || with_solve > 0xffff || (with_solve & 0xf8))
     return fail(SPX_EINVAL, "spx_cholesky_graph: bad argument");
+  const int steps = (with_solve >> 8) ? (with_solve >> 8) : 1;  // POTRF steps, bits 8-15
+  if (steps > 64) return fail(SPX_EINVAL, "spx_cholesky_graph: at most 64 POTRF steps");
   *out = nullptr;
   try {
     std::unique_ptr<spx_graph> g(new spx_graph());
     std::vector<spx_access> acc;
     if (with_solve & 2)
-      io_program(nt, (with_solve & 1) != 0, g->tasks, acc, (with_solve & 4) != 0);
+      io_program(nt, (with_solve & 1) != 0, g->tasks, acc, (with_solve & 4) != 0, steps);
     else
-      cholesky_program(nt, (with_solve & 1) != 0, g->tasks, acc, (with_solve & 4) != 0);
+      cholesky_program(nt, (with_solve & 1) != 0, g->tasks, acc, (with_solve & 4) != 0, steps);
     std::vector<int32_t> prio(g->tasks.size());
     for (size_t t = 0; t < g->tasks.size(); ++t) prio[t] = cholesky_priority(g->tasks[t], nt);
     int rc = build_graph((uint32_t)g->tasks.size(), acc.data(), acc.size(), prio.data(), g->g);

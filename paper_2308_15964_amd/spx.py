@@ -192,10 +192,11 @@ class Graph:
         return cls(h.value)
 
     @classmethod
-    def cholesky(cls, nt, with_solve=False, io=False, inverse=False):
+    def cholesky(cls, nt, with_solve=False, io=False, inverse=False, potrf_steps=1):
         """The paper's program; io: with LOAD in front (and STORE at the end with the
         solve), as the batched calls run it; inverse: with the inversion tasks INV(k) after
-        the factor and the substitution that uses them."""
+        the factor and the substitution that uses them; potrf_steps > 1: each POTRF(k) as
+        that many chained step tasks."""
         h = ctypes.c_void_p()
         from math import comb
         T = nt + 2 * comb(nt, 2) + comb(nt, 3) + (2 * (nt + comb(nt, 2)) if with_solve else 0)
@@ -203,8 +204,9 @@ class Graph:
             T += 2 if with_solve else 1
         if inverse:
             T += nt
+        T += nt * (potrf_steps - 1)
         types = (ctypes.c_int32 * T)()
-        flag = int(bool(with_solve)) | (2 if io else 0) | (4 if inverse else 0)
+        flag = int(bool(with_solve)) | (2 if io else 0) | (4 if inverse else 0) | (potrf_steps << 8)
         _check(lib().spx_cholesky_graph(nt, flag, ctypes.byref(h), types, T))
         return cls(h.value, np.array(types[:], dtype=np.int32))
 

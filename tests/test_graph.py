@@ -174,3 +174,47 @@ def test_batched_member_graph_bit_exact(nt, with_solve, inverse):
     assert indeg[0] == 0 and (indeg[1:] > 0).all()  # one root per matrix: its LOAD
     if with_solve:
         assert indeg[-1] == nt  # the last write of each solution block
+
+
+def split_potrf(names, acc, steps):
+    """The access list with every POTRF(k) replaced by `steps` tasks that each make the
+    POTRF's accesses (the chained step tasks the library runs on large diagonal tiles)."""
+    first, out_names = [], []
+    for nm in names:
+        first.append(len(out_names))
+        out_names += [nm] * (steps if nm == "POTRF" else 1)
+    out = []
+    for t, m, d in acc:
+        for s in range(steps if names[t] == "POTRF" else 1):
+            out.append((first[t] + s, m, d))
+    out.sort(key=lambda a: a[0])  # grouped by task, each task's accesses in their order
+    return out_names, out, first
+
+
+@pytest.mark.parametrize("nt", [1, 2, 4, 7])
+@pytest.mark.parametrize("with_solve", [False, True])
+@pytest.mark.parametrize("steps", [2, 16])
+def test_executed_graph_with_potrf_steps_bit_exact(nt, with_solve, steps):
+    """Diagonal factorizations split into chained steps: the edges equal the pairwise
+    definition on the expanded access list, the steps of one POTRF form a chain, and
+    contracting every chain gives back the graph with whole POTRF tasks."""
+    names, acc = executed_program(nt, with_solve)
+    snames, sacc, first = split_potrf(names, acc, steps)
+    want, _ = oracle.dag_edges(len(snames), sacc)
+    g = spx.Graph.cholesky(nt, with_solve, inverse=True, potrf_steps=steps)
+    assert g.info() == (len(snames), len(want))
+    assert np.array_equal(g.edges(), want)
+    assert [spx.TASK_NAMES[t] for t in g.task_types] == snames
+    got = set(map(tuple, g.edges().tolist()))
+    owner = np.repeat(np.arange(len(names)), np.diff(np.append(first, len(snames))))
+    for t, nm in enumerate(names):
+        if nm == "POTRF":
+            assert all((first[t] + s, first[t] + s + 1) in got for s in range(steps - 1))
+    contracted = {(int(owner[a]), int(owner[b])) for a, b in got if owner[a] != owner[b]}
+    whole = set(map(tuple, spx.Graph.cholesky(nt, with_solve, inverse=True).edges().tolist()))
+    assert contracted == whole
+
+
+def test_potrf_steps_rejected_above_64():
+    with pytest.raises(spx.SpxError):
+        spx.Graph.cholesky(2, potrf_steps=65)
