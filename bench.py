@@ -86,7 +86,7 @@ def parse():
     p.add_argument("--serve-rate", type=float, default=2000.0)
     p.add_argument("--serve-lanes", type=int, default=2)
     p.add_argument("--chain-trace", action="store_true",
-                   help="trace one factor launch (--n, --tile) and print its critical-chain sums")
+                   help="trace one factor and one solve launch (--n, --tile) and print their critical paths")
     p.add_argument("--copy-probe", action="store_true",
                    help="only copy a 1 GiB device buffer three times (calibrates HBM byte counters)")
     return p.parse_args()
@@ -335,57 +335,77 @@ def bench_serving(ctx, count, rate, lanes, seed=8):
     return res
 
 
-def chain_trace(ctx, spx, A, n, b):
-    """Times the factor's critical chain from the library's per-part trace (100 MHz
-    device clock): per block column k, the span of POTRF(k) (with the hops between its
-    steps when the diagonal factorization is split), the wait of TRSM(k+1,k) after it, and
-    the spans of TRSM(k+1,k) and SYRK(k+1,k+1,k).  Task ids follow the program's insertion
-    order: for each k, POTRF(k) (S chained steps), TRSM(i,k) for i > k, then for each
-    i > k SYRK(i,i,k) followed by GEMM(i,j,k) for k < j < i; the inversions come last."""
+TASK_NAMES = ["POTRF", "TRSM", "SYRK", "GEMM", "FTRSM", "FGEMM", "BTRSM", "BGEMM", "LOAD", "STORE", "INV"]
+
+
+def critical_path(rec, edges, types):
+    """Critical path of one traced launch (device clock, 100 MHz): from the task that ends
+    last, repeatedly step to the predecessor that ended last.  Returns the launch span and,
+    per task type on the path, the summed run time and the summed wait between the
+    predecessor's end and the task's start (the hop)."""
+    import numpy as np
+
+    T = len(types)
+    start = np.full(T, np.iinfo(np.int64).max, np.int64)
+    end = np.zeros(T, np.int64)
+    task = rec[:, 0].astype(np.int64)
+    np.minimum.at(start, task, rec[:, 2].astype(np.int64))
+    np.maximum.at(end, task, rec[:, 3].astype(np.int64))
+    t0 = int(start.min())
+    preds = [[] for _ in range(T)]
+    for a_, b_ in edges:
+        preds[int(b_)].append(int(a_))
+    cur = int(np.argmax(end))
+    out = {}
+    path_len = 0
+    while True:
+        p = max(preds[cur], key=lambda x: end[x]) if preds[cur] else None
+        name = TASK_NAMES[int(types[cur])]
+        e = out.setdefault(name, {"tasks": 0, "run_ms": 0.0, "wait_ms": 0.0})
+        e["tasks"] += 1
+        e["run_ms"] += (end[cur] - start[cur]) / 1e5
+        e["wait_ms"] += (start[cur] - (end[p] if p is not None else t0)) / 1e5
+        path_len += 1
+        if p is None:
+            break
+        cur = p
+    for e in out.values():
+        e["run_ms"] = round(e["run_ms"], 3)
+        e["wait_ms"] = round(e["wait_ms"], 3)
+    return {"span_ms": round((int(end.max()) - t0) / 1e5, 3), "path_tasks": path_len, "by_type": out}
+
+
+def chain_trace(ctx, spx, A, B, n, b):
+    """Traces one factor launch and one solve launch (--n, --tile) and breaks each one's
+    critical path down by task type (run time and hop waits), from the library's per-part
+    trace and the executed graphs' edges."""
+    import numpy as np
     import torch
 
     nt = -(-n // b)
     S = b // 32 if (b >= 256 and nt >= 4) else 1
-    rec = None
-    for _ in range(2):  # the first launch builds and uploads the image
-        F = ctx.potrf(A, tile=b, flags=spx.F_TRACE)
+    ctx.set_flags(spx.F_TRACE)
+    res = {}
+    for _ in range(2):  # the first launches build and upload the images
+        F = ctx.potrf(A, tile=b)
         torch.cuda.synchronize()
-        rec = ctx.trace()
+        rec_f, st_f = ctx.trace(), ctx.stats()
+        X = ctx.potrs(F, B)
+        torch.cuda.synchronize()
+        rec_s, st_s = ctx.trace(), ctx.stats()
         F.close()
-    idx, t = {}, 0
-    for k in range(nt):
-        for s_ in range(S):
-            idx[("P", k, s_)] = t; t += 1
-        for i in range(k + 1, nt):
-            idx[("T", i, k)] = t; t += 1
-        for i in range(k + 1, nt):
-            idx[("S", i, k)] = t; t += 1
-            t += i - k - 1  # the GEMMs of row i
-    t0 = int(rec[:, 2].min())
-    st, en = {}, {}
-    for task, _, s_, e in rec:
-        task = int(task)
-        st[task] = min(st.get(task, 1 << 62), int(s_) - t0)
-        en[task] = max(en.get(task, 0), int(e) - t0)
-    us = lambda x: x / 100.0
-    sums = dict(potrf_ms=0.0, potrf_hops_ms=0.0, trsm_wait_ms=0.0, trsm_ms=0.0, syrk_ms=0.0, syrk_to_potrf_ms=0.0)
-    per_potrf = []
-    for k in range(nt):
-        p0, pl = idx[("P", k, 0)], idx[("P", k, S - 1)]
-        per_potrf.append(us(en[pl] - st[p0]))
-        sums["potrf_ms"] += per_potrf[-1] / 1e3
-        sums["potrf_hops_ms"] += sum(us(st[p0 + s_ + 1] - en[p0 + s_]) for s_ in range(S - 1)) / 1e3
-        if k + 1 < nt:
-            tr, sy, nx = idx[("T", k + 1, k)], idx[("S", k + 1, k)], idx[("P", k + 1, 0)]
-            sums["trsm_wait_ms"] += us(st[tr] - en[pl]) / 1e3
-            sums["trsm_ms"] += us(en[tr] - st[tr]) / 1e3
-            sums["syrk_ms"] += us(en[sy] - st[sy]) / 1e3
-            sums["syrk_to_potrf_ms"] += us(st[nx] - en[sy]) / 1e3
-    out = {k: round(v, 3) for k, v in sums.items()}
-    out.update(n=n, tile=b, potrf_steps=S, launch_ms=round(us(int(rec[:, 3].max()) - t0) / 1e3, 3),
-               potrf_us_min=round(min(per_potrf), 1), potrf_us_max=round(max(per_potrf), 1),
-               idle_frac=round(ctx.stats()["idle_frac"], 4), ntasks=ctx.stats()["ntasks"])
-    return out
+    ctx.set_flags(0)
+    gf = spx.Graph.cholesky(nt, inverse=True, potrf_steps=S)
+    res["factor"] = dict(critical_path(rec_f, gf.edges(), gf.task_types), kernel_ms=round(st_f["kernel_ms"], 3),
+                         idle_frac=round(st_f["idle_frac"], 4), ntasks=st_f["ntasks"], nparts=st_f["nparts"])
+    gs = spx.Graph.cholesky(nt, with_solve=True, inverse=True)
+    first = int(np.argmax(gs.task_types == 4))  # the first FTRSM: the solve program starts there
+    es = gs.edges().astype(np.int64)
+    es = es[(es[:, 0] >= first) & (es[:, 1] >= first)] - first
+    res["solve"] = dict(critical_path(rec_s, es, gs.task_types[first:]), kernel_ms=round(st_s["kernel_ms"], 3),
+                        idle_frac=round(st_s["idle_frac"], 4), ntasks=st_s["ntasks"], nparts=st_s["nparts"])
+    res.update(n=n, tile=b, potrf_steps=S)
+    return res
 
 
 def main():
@@ -413,7 +433,7 @@ def main():
     A, B = gen_input(n, args.seed, nrhs, dev)
     ctx = spx.Context(0)
     if args.chain_trace:
-        print(json.dumps(chain_trace(ctx, spx, A, n, b)), flush=True)
+        print(json.dumps(chain_trace(ctx, spx, A, B, n, b)), flush=True)
         return
     flop_factor = n ** 3 / 3.0
     flop_step = flop_factor + 2.0 * n * n * nrhs

@@ -109,7 +109,7 @@ void spx_graph_destroy(spx_graph* g);
  * right-hand-side block k -> nt*nt + k, M_k -> nt*nt + nt + k.  task_types (nullable,
  * ntasks entries) receives SPX_T_* codes. */
 enum { SPX_T_POTRF = 0, SPX_T_TRSM, SPX_T_SYRK, SPX_T_GEMM, SPX_T_FTRSM, SPX_T_FGEMM, SPX_T_BTRSM, SPX_T_BGEMM,
-       SPX_T_LOAD, SPX_T_STORE, SPX_T_INV };
+       SPX_T_LOAD, SPX_T_STORE, SPX_T_INV, SPX_T_MGEMM };
 /* SPX_T_LOAD / SPX_T_STORE appear only in the graphs of the batched and served calls: the
  * first task of each matrix copies its dense input (and right-hand sides) into tile
  * storage, writing every tile; the last one reads the solution blocks and writes X.
@@ -120,6 +120,14 @@ enum { SPX_T_POTRF = 0, SPX_T_TRSM, SPX_T_SYRK, SPX_T_GEMM, SPX_T_FTRSM, SPX_T_F
  * step tasks on tile (k,k), as the library runs the diagonal tiles of 256 and 512 in
  * matrices of at least four tile columns (b/32 steps). */
 int spx_cholesky_graph(int32_t nt, int32_t with_solve, spx_graph** out, int32_t* task_types, uint32_t cap);
+
+/* The tiled matrix product of Sec. 5.2 (the GEMM application) for nt x nt tiles: one task
+ * SPX_T_MGEMM(i, j, k) per tile triple, C_ij <- C_ij + A_ik B_kj, declaring SpRead on A_ik
+ * and B_kj and SpWrite on C_ij, inserted with k outermost (then i, then j).  Datum ids:
+ * A_ik -> i*nt + k, B_kj -> nt^2 + k*nt + j, C_ij -> 2 nt^2 + i*nt + j.  The graph is nt^2
+ * independent chains of nt - 1 write-after-write edges.  task_types as for
+ * spx_cholesky_graph.  Errors: SPX_EINVAL (nt outside [1, 512]), SPX_ENOMEM. */
+int spx_gemm_graph(int32_t nt, spx_graph** out, int32_t* task_types, uint32_t cap);
 
 /* ---------------------------------------------------------------------------------------
  * Factorisation (Sec. 5.2).
@@ -165,6 +173,20 @@ int spx_factor_info(const spx_factor* f, int64_t* n, int32_t* tile, int64_t* n_p
  * the diagonal. */
 int spx_factor_get_l(spx_ctx* ctx, const spx_factor* f, double* dL, int64_t ldl);
 void spx_factor_destroy(spx_factor* f);
+
+/* C <- C + A B for n x n matrices (Sec. 5.2, the GEMM application), run as the task graph of
+ * spx_gemm_graph by the device scheduler in one persistent launch, in FP64.  dA, dB, dC:
+ * device pointers, row-major with leading dimensions lda, ldb, ldc >= n; A and B are only
+ * read; C is read and overwritten and may not overlap A or B.  The matrices are copied into
+ * library tile storage for the call (A and C as b x b column-major tiles, B as the tiles of
+ * B^T; n padded to a multiple of b with zeros, which add exact zeros) and C back out.
+ * opts (nullable): tile (32..512; 0 = chosen from n), queue_policy, num_wg, flags
+ * (SPX_F_TRACE); update_prec must be SPX_PREC_FP64.  Each task's b x b update runs as
+ * 128 x 128 parts on the matrix cores; every C_ij takes its k terms in increasing k, so the
+ * result does not depend on the schedule.  spx_last_stats reports the launch (pack_ms: the
+ * three packs).  Errors: SPX_EINVAL, SPX_ENOMEM, SPX_EDEVICE, SPX_ETIMEOUT. */
+int spx_gemm_tiled(spx_ctx* ctx, int64_t n, const double* dA, int64_t lda, const double* dB, int64_t ldb, double* dC,
+                   int64_t ldc, const spx_opts* opts);
 
 /* ---------------------------------------------------------------------------------------
  * Solve A X = B with the factor (Sec. 5.2 task style: block forward and backward
@@ -344,9 +366,11 @@ typedef struct {
 } spx_server_opts;
 typedef struct {
   uint64_t submitted, completed, rejected, launches;
-  uint64_t bytes_in_use, bytes_peak;
+  uint64_t bytes_in_use, bytes_peak; /* admitted request bytes (the budget's accounting) */
   uint64_t max_running;  /* most requests running at once over all lanes */
   double busy_s;         /* summed lane busy time */
+  uint64_t pool_used_high; /* high-water mark of the device memory pool the lanes allocate
+                              from (bytes in use), since the server was created */
 } spx_server_stats;
 int spx_server_create(spx_ctx* ctx, size_t hbm_budget_bytes, const spx_server_opts* opts, spx_server** out);
 int spx_submit(spx_server* s, const spx_request* req, uint64_t* ticket);
@@ -365,6 +389,10 @@ typedef struct {
   uint32_t ntasks, nparts, num_wg, tile;
 } spx_stats;
 int spx_last_stats(const spx_ctx* ctx, spx_stats* out);
+/* Context-wide launch flags: SPX_F_TRACE makes every later launch on the context (factor,
+ * solve, batched) record its per-part trace, as the flag in spx_opts does for one call.
+ * 0 turns it off.  Errors: SPX_EINVAL for other bits. */
+int spx_ctx_set_flags(spx_ctx* ctx, uint32_t flags);
 /* Per-part trace of the last launch made with SPX_F_TRACE: for part p, rec[4p..4p+3] =
  * {task, part | (workgroup << 16), start tick, end tick} (device wall clock, 100 MHz).
  * Returns the record count (or < 0); writes at most cap records. */

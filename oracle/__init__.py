@@ -13,7 +13,11 @@ Functions and the passages they follow (Specx, arXiv 2308.15964):
   cholesky                 - tiled Cholesky with POTRF / TRSM / SYRK / GEMM tasks in FP64
                              (Sec. 5.2), run by a sequential STF executor in a chosen
                              topological order, or by a thread pool; optional solve.
-  factor_residual, factor_residual_probe, backward_error, entry_check
+  gemm_program, gemm_dag, gemm, gemm_entries
+                           - the tiled matrix product C + A B of the GEMM application
+                             (Sec. 5.2), one task per tile triple, same executors.
+  factor_residual, factor_residual_probe, factor_residual_vectors, backward_error,
+  entry_check
                            - checks of a factor and a solution against the definitions
                              A = L L^T and A x = b, with compensated dot products.
 """
@@ -37,7 +41,7 @@ class _Task(ctypes.Structure):
     _fields_ = [("type", ctypes.c_int32), ("i", ctypes.c_int32), ("j", ctypes.c_int32), ("k", ctypes.c_int32)]
 
 
-TASK_NAMES = ["POTRF", "TRSM", "SYRK", "GEMM", "FTRSM", "FGEMM", "BTRSM", "BGEMM"]
+TASK_NAMES = ["POTRF", "TRSM", "SYRK", "GEMM", "FTRSM", "FGEMM", "BTRSM", "BGEMM", "MGEMM"]
 
 
 def lib():
@@ -66,12 +70,25 @@ def lib():
         L.orc_factor_residual.argtypes = [dp, dp, i64]
         L.orc_factor_residual_probe.restype = ctypes.c_double
         L.orc_factor_residual_probe.argtypes = [dp, dp, i64, ctypes.c_int, u64]
+        L.orc_factor_residual_vectors.restype = ctypes.c_double
+        L.orc_factor_residual_vectors.argtypes = [dp, dp, i64, dp, ctypes.c_int]
         L.orc_backward_error.restype = None
         L.orc_backward_error.argtypes = [dp, i64, dp, dp, i64, ctypes.c_int, ctypes.c_double, dp]
         L.orc_norm_inf_sym.restype = ctypes.c_double
         L.orc_norm_inf_sym.argtypes = [dp, i64]
         L.orc_factor_entry_check.restype = ctypes.c_double
         L.orc_factor_entry_check.argtypes = [dp, dp, i64, ctypes.POINTER(i64), ctypes.POINTER(i64), i64]
+        L.orc_gemm_program.restype = i64
+        L.orc_gemm_program.argtypes = [ctypes.c_int, ctypes.POINTER(_Task), ctypes.POINTER(_Access),
+                                       ctypes.POINTER(u64)]
+        L.orc_gemm.restype = i64
+        L.orc_gemm.argtypes = [i64, ctypes.c_int, dp, ctypes.c_int, u64, ctypes.c_int, ctypes.POINTER(i64),
+                               ctypes.POINTER(u32), ctypes.POINTER(i64)]
+        L.orc_gemm_dag.restype = i64
+        L.orc_gemm_dag.argtypes = [ctypes.c_int, ctypes.POINTER(u32), ctypes.POINTER(u32), u64, ctypes.POINTER(u64),
+                                   ctypes.POINTER(i64)]
+        L.orc_gemm_entries.restype = None
+        L.orc_gemm_entries.argtypes = [dp, dp, dp, i64, ctypes.POINTER(i64), ctypes.POINTER(i64), i64, dp]
         L.orc_dot2.restype = ctypes.c_double
         L.orc_dot2.argtypes = [dp, dp, i64]
         _lib = L
@@ -178,6 +195,62 @@ def cholesky(A, nb, B=None, order=ORDER_INSERTION, seed=0, nthreads=1, limit=0, 
     return out
 
 
+def gemm_program(nt):
+    """The oracle's GEMM task program: ([(name, i, j, k)], [(task, mode, datum)])."""
+    na = ctypes.c_uint64()
+    T = lib().orc_gemm_program(nt, None, None, ctypes.byref(na))
+    tasks = (_Task * max(T, 1))()
+    acc = (_Access * max(na.value, 1))()
+    lib().orc_gemm_program(nt, tasks, acc, ctypes.byref(na))
+    return ([(TASK_NAMES[t.type], t.i, t.j, t.k) for t in tasks[:T]],
+            [(a.task, a.mode, a.datum) for a in acc[: na.value]])
+
+
+def gemm_dag(nt):
+    """Edges of the GEMM program by the pairwise definition: (T, edges, kinds)."""
+    kinds = (ctypes.c_uint64 * 3)()
+    T = ctypes.c_int64()
+    E = lib().orc_gemm_dag(nt, None, None, 0, kinds, ctypes.byref(T))
+    src = np.zeros(max(E, 1), np.uint32)
+    dst = np.zeros(max(E, 1), np.uint32)
+    lib().orc_gemm_dag(nt, src.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
+                       dst.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)), E, kinds, ctypes.byref(T))
+    return T.value, np.stack([src[:E], dst[:E]], axis=1), {"RAW": kinds[0], "WAR": kinds[1], "WAW": kinds[2]}
+
+
+def gemm(A, B, C, nb, order=ORDER_INSERTION, seed=0, nthreads=1, drop_edge=None, return_order=False):
+    """C + A B (all n x n, n % nb == 0) by the tiled program.  Returns the new C (and the
+    run order when asked)."""
+    A, B, C = (np.asarray(x, np.float64) for x in (A, B, C))
+    n = A.shape[0]
+    if n % nb:
+        raise ValueError("n must be a multiple of nb")
+    abc = np.asfortranarray(np.concatenate([A, B, C], axis=1))
+    nt = n // nb
+    ordbuf = np.full(nt ** 3, -1, np.int64)
+    nrun = ctypes.c_int64(0)
+    de = None if drop_edge is None else (ctypes.c_uint32 * 2)(int(drop_edge[0]), int(drop_edge[1]))
+    rc = lib().orc_gemm(n, nb, _dp(abc), order, seed, nthreads, ordbuf.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                        de, ctypes.byref(nrun))
+    if rc < 0:
+        raise RuntimeError("oracle failed")
+    out = np.ascontiguousarray(abc[:, 2 * n:])
+    if return_order:
+        return out, ordbuf[: nrun.value].copy()
+    return out
+
+
+def gemm_entries(A, B, C, ii, jj):
+    """C(i,j) + sum over m ascending of A(i,m) B(m,j) for each sampled (i, j), plain FP64."""
+    a, b, c = (np.asfortranarray(np.asarray(x, np.float64)) for x in (A, B, C))
+    ii = np.ascontiguousarray(ii, np.int64)
+    jj = np.ascontiguousarray(jj, np.int64)
+    out = np.zeros(len(ii))
+    lib().orc_gemm_entries(_dp(a), _dp(b), _dp(c), a.shape[0], ii.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                           jj.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), len(ii), _dp(out))
+    return out
+
+
 def run_task(name, i, j, k, M, nb, Y=None):
     """Runs one task of the program on copies of the dense matrix M (n x n, all entries
     used as stored: this is a kernel-level check, not the symmetric-input convention) and
@@ -202,6 +275,15 @@ def factor_residual_probe(A, L, nvec=8, seed=1234):
     """max_v ||(A - L L^T) v|| / ||A v|| over nvec seeded Gaussian v (O(n^2) each)."""
     a, l = _lower_cm(A), _lower_cm(L)
     return lib().orc_factor_residual_probe(_dp(a), _dp(l), a.shape[0], nvec, seed)
+
+
+def factor_residual_vectors(A, L, V):
+    """max over the columns v of V (n x q) of ||(A - L L^T) v|| / ||A v||, the
+    arithmetic of factor_residual_probe on caller-chosen vectors."""
+    a, l = _lower_cm(A), _lower_cm(L)
+    n = a.shape[0]
+    V = np.asfortranarray(np.asarray(V, np.float64).reshape(n, -1))
+    return lib().orc_factor_residual_vectors(_dp(a), _dp(l), n, _dp(V), V.shape[1])
 
 
 def norm_inf(A):

@@ -162,7 +162,8 @@ int64_t orc_dag_edges(uint32_t ntasks, const orc_access* acc, uint64_t nacc, uin
  * Cholesky and solve task programs (right-looking, lower triangle)
  * ---------------------------------------------------------------------------------- */
 
-enum { T_POTRF = 0, T_TRSM = 1, T_SYRK = 2, T_GEMM = 3, T_FTRSM = 4, T_FGEMM = 5, T_BTRSM = 6, T_BGEMM = 7 };
+enum { T_POTRF = 0, T_TRSM = 1, T_SYRK = 2, T_GEMM = 3, T_FTRSM = 4, T_FGEMM = 5, T_BTRSM = 6, T_BGEMM = 7,
+       T_MGEMM = 8 };
 
 typedef struct {
   int32_t type, i, j, k;
@@ -239,11 +240,31 @@ int64_t orc_cholesky_program(int nt, int with_solve, orc_task* tasks, orc_access
       }
     }
   }
-#undef ADD_TASK
-#undef ADD_ACC
   if (nacc_out) *nacc_out = na;
   return nt_;
 }
+
+/* The tiled matrix product of Sec. 5.2 (the GEMM application): C <- C + A B for three
+ * nt x nt tile matrices, one task per (i, j, k) updating C_ij with A_ik B_kj.  Inserted
+ * with k outermost.  Datum ids: A_ik -> i*nt + k, B_kj -> nt^2 + k*nt + j, C_ij ->
+ * 2 nt^2 + i*nt + j.  Returns the task count; *nacc_out receives the access count. */
+int64_t orc_gemm_program(int nt, orc_task* tasks, orc_access* acc, uint64_t* nacc_out) {
+  int64_t nt_ = 0;
+  uint64_t na = 0;
+  const uint64_t n2 = (uint64_t)nt * (uint64_t)nt;
+  for (int k = 0; k < nt; ++k)
+    for (int i = 0; i < nt; ++i)
+      for (int j = 0; j < nt; ++j) {
+        ADD_TASK(T_MGEMM, i, j, k);
+        ADD_ACC(ORC_R, (uint64_t)i * nt + k);
+        ADD_ACC(ORC_R, n2 + (uint64_t)k * nt + j);
+        ADD_ACC(ORC_RW, 2 * n2 + (uint64_t)i * nt + j);
+      }
+  if (nacc_out) *nacc_out = na;
+  return nt_;
+}
+#undef ADD_TASK
+#undef ADD_ACC
 
 /* ------------------------------------------------------------------------------------
  * Tile kernels.  Column-major storage with leading dimension ld; every kernel works in
@@ -290,6 +311,13 @@ static void gemm_tile(double* cm, const double* a, const double* b, int64_t ld, 
       for (int r = 0; r < nb; ++r) AT(cm, ld, r, j) = AT(cm, ld, r, j) - AT(a, ld, r, m) * AT(b, ld, j, m);
 }
 
+/* C <- C + A * B (the GEMM application's task), m ascending. */
+static void mgemm_tile(double* cm, const double* a, const double* b, int64_t ld, int nb) {
+  for (int m = 0; m < nb; ++m)
+    for (int j = 0; j < nb; ++j)
+      for (int r = 0; r < nb; ++r) AT(cm, ld, r, j) = AT(cm, ld, r, j) + AT(a, ld, r, m) * AT(b, ld, m, j);
+}
+
 /* Forward block substitution.  y is a block of rows of the right-hand side (ldb). */
 static void ftrsm_tile(double* y, int64_t ldb, int nrhs, const double* l, int64_t ld, int nb) {
   for (int q = 0; q < nrhs; ++q) {
@@ -326,7 +354,9 @@ static void bgemm_tile(double* yi, const double* yk, int64_t ldb, int nrhs, cons
 }
 
 /* Runs one task on the dense column-major matrix a (n x n, ld = n) and right-hand side
- * y (n x nrhs, ld = n).  Returns 0 or the 1-based global column of a failed pivot. */
+ * y (n x nrhs, ld = n).  For the GEMM program a holds A, B and C side by side (n x 3n,
+ * ld = n): tile (i, k) of A, (k, j) of B at tile column nt + j, (i, j) of C at 2 nt + j.
+ * Returns 0 or the 1-based global column of a failed pivot. */
 static int run_task(const orc_task* t, double* a, int64_t n, int nb, double* y, int nrhs) {
   const int64_t ld = n;
 #define TILE(I, J) (a + (size_t)(J) * (size_t)nb * (size_t)ld + (size_t)(I) * (size_t)nb)
@@ -343,6 +373,11 @@ static int run_task(const orc_task* t, double* a, int64_t n, int nb, double* y, 
     case T_FGEMM: fgemm_tile(YB(t->i), YB(t->k), n, nrhs, TILE(t->i, t->k), ld, nb); return 0;
     case T_BTRSM: btrsm_tile(YB(t->k), n, nrhs, TILE(t->k, t->k), ld, nb); return 0;
     case T_BGEMM: bgemm_tile(YB(t->i), YB(t->j), n, nrhs, TILE(t->j, t->i), ld, nb); return 0;
+    case T_MGEMM: {
+      const int nt = (int)(n / nb);
+      mgemm_tile(TILE(t->i, 2 * nt + t->j), TILE(t->i, t->k), TILE(t->k, nt + t->j), ld, nb);
+      return 0;
+    }
   }
 #undef TILE
 #undef YB
@@ -375,19 +410,23 @@ static void prog_free(orc_prog* p) {
   free(p->indeg);
 }
 
+/* with_solve < 0: the GEMM program instead of the Cholesky one. */
 static int prog_make(int nt, int with_solve, const uint32_t* drop_edge /* nullable: {src,dst} */,
                      orc_prog* p) {
   memset(p, 0, sizeof(*p));
   uint64_t na = 0;
-  int64_t T = orc_cholesky_program(nt, with_solve, NULL, NULL, &na);
-  p->tasks = (orc_task*)malloc(T * sizeof(orc_task));
+  int64_t T = with_solve < 0 ? orc_gemm_program(nt, NULL, NULL, &na) : orc_cholesky_program(nt, with_solve, NULL, NULL, &na);
+  p->tasks = (orc_task*)malloc((T ? T : 1) * sizeof(orc_task));
   orc_access* acc = (orc_access*)malloc((na ? na : 1) * sizeof(orc_access));
   if (!p->tasks || !acc) {
     free(acc);
     prog_free(p);
     return -1;
   }
-  orc_cholesky_program(nt, with_solve, p->tasks, acc, &na);
+  if (with_solve < 0)
+    orc_gemm_program(nt, p->tasks, acc, &na);
+  else
+    orc_cholesky_program(nt, with_solve, p->tasks, acc, &na);
   int64_t E = orc_dag_edges((uint32_t)T, acc, na, NULL, NULL, 0, NULL);
   uint32_t* src = (uint32_t*)malloc((E ? E : 1) * sizeof(uint32_t));
   uint32_t* dst = (uint32_t*)malloc((E ? E : 1) * sizeof(uint32_t));
@@ -598,6 +637,50 @@ int64_t orc_cholesky(int64_t n, int nb, double* a, double* y, int nrhs, int orde
   return info;
 }
 
+/* The GEMM program: abc holds A, B and C (each n x n) side by side, column-major n x 3n
+ * (ld = n); C is overwritten by C + A B computed tile by tile (tile size nb, n % nb == 0)
+ * in the chosen order (as for orc_cholesky; nthreads > 1: thread pool).  drop_edge as for
+ * orc_cholesky.  Returns 0 or -1. */
+int64_t orc_gemm(int64_t n, int nb, double* abc, int order, uint64_t seed, int nthreads, int64_t* order_out,
+                 const uint32_t* drop_edge, int64_t* nrun_out) {
+  if (n <= 0 || nb <= 0 || n % nb != 0 || !abc) return -1;
+  orc_prog p;
+  if (prog_make((int)(n / nb), -1, drop_edge, &p) != 0) return -1;
+  int64_t info;
+  if (nthreads <= 1)
+    info = exec_seq(&p, order, seed, abc, n, nb, NULL, 0, order_out, nrun_out);
+  else
+    info = exec_par(&p, nthreads, abc, n, nb, NULL, 0, 0);
+  prog_free(&p);
+  return info;
+}
+
+/* Edges of the GEMM program (as orc_cholesky_dag). */
+int64_t orc_gemm_dag(int nt, uint32_t* src, uint32_t* dst, uint64_t cap, uint64_t* kinds, int64_t* ntasks_out) {
+  uint64_t na = 0;
+  int64_t T = orc_gemm_program(nt, NULL, NULL, &na);
+  orc_access* acc = (orc_access*)malloc((na ? na : 1) * sizeof(orc_access));
+  if (!acc) return -1;
+  orc_gemm_program(nt, NULL, acc, &na);
+  int64_t E = orc_dag_edges((uint32_t)T, acc, na, src, dst, cap, kinds);
+  free(acc);
+  if (ntasks_out) *ntasks_out = T;
+  return E;
+}
+
+/* Sampled entries of C0 + A B, one by one (for sizes the executor cannot run in a test):
+ * out[s] = C0(i, j) + sum over m ascending of A(i, m) B(m, j), plain FP64, for (i, j) =
+ * (ii[s], jj[s]).  A, B, C0 column-major n x n (ld = n). */
+void orc_gemm_entries(const double* a, const double* b, const double* c0, int64_t n, const int64_t* ii,
+                      const int64_t* jj, int64_t count, double* out) {
+  for (int64_t s = 0; s < count; ++s) {
+    const int64_t i = ii[s], j = jj[s];
+    double c = c0[(size_t)j * n + i];
+    for (int64_t m = 0; m < n; ++m) c = c + a[(size_t)m * n + i] * b[(size_t)j * n + m];
+    out[s] = c;
+  }
+}
+
 /* Runs one task of the program (type codes as in orc_cholesky_program) on the dense
  * column-major matrix a (n x n, ld = n, tile size nb) and right-hand side y (n x nrhs,
  * ld = n).  Returns 0 or the 1-based global column of a failed pivot. */
@@ -705,6 +788,45 @@ static double gauss(uint64_t* s) {
   return sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2);
 }
 
+/* ||(A - L L^T) v||_2 / ||A v||_2 for one vector v (n entries), with w = L^T v rounded
+ * once and both products accumulated with Dot2.  O(n^2). */
+static double residual_ratio(const double* a, const double* l, int64_t n, const double* v, double* w) {
+  /* w = L^T v */
+  for (int64_t m = 0; m < n; ++m) {
+    dot2 d = {0.0, 0.0};
+    for (int64_t i = m; i < n; ++i) d2_sub_prod(&d, -l[(size_t)m * n + i], v[i]);
+    w[m] = d2_val(&d);
+  }
+  double num = 0.0, den = 0.0;
+  for (int64_t i = 0; i < n; ++i) {
+    dot2 r = {0.0, 0.0}, av = {0.0, 0.0};
+    for (int64_t j = 0; j < n; ++j) {
+      double aij = sym(a, n, i, j);
+      d2_sub_prod(&r, -aij, v[j]);
+      d2_sub_prod(&av, -aij, v[j]);
+    }
+    for (int64_t m = 0; m <= i; ++m) d2_sub_prod(&r, l[(size_t)m * n + i], w[m]);
+    double rv = d2_val(&r), avv = d2_val(&av);
+    num += rv * rv;
+    den += avv * avv;
+  }
+  return sqrt(num) / sqrt(den);
+}
+
+/* The largest ||(A - L L^T) v||_2 / ||A v||_2 over the nvec caller-given vectors
+ * (column-major n x nvec, ld = n).  Returns -1 if out of memory. */
+double orc_factor_residual_vectors(const double* a, const double* l, int64_t n, const double* vecs, int nvec) {
+  double* w = (double*)malloc(n * sizeof(double));
+  if (!w) return -1.0;
+  double worst = 0.0;
+  for (int q = 0; q < nvec; ++q) {
+    double e = residual_ratio(a, l, n, vecs + (size_t)q * n, w);
+    if (e > worst || e != e) worst = e;
+  }
+  free(w);
+  return worst;
+}
+
 /* Randomised estimate of the factor residual for large n (Freivalds-style probing):
  * max over nvec Gaussian vectors v of ||(A - L L^T) v||_2 / ||A v||_2.  O(n^2) each. */
 double orc_factor_residual_probe(const double* a, const double* l, int64_t n, int nvec, uint64_t seed) {
@@ -719,26 +841,7 @@ double orc_factor_residual_probe(const double* a, const double* l, int64_t n, in
   double worst = 0.0;
   for (int q = 0; q < nvec; ++q) {
     for (int64_t i = 0; i < n; ++i) v[i] = gauss(&s);
-    /* w = L^T v */
-    for (int64_t m = 0; m < n; ++m) {
-      dot2 d = {0.0, 0.0};
-      for (int64_t i = m; i < n; ++i) d2_sub_prod(&d, -l[(size_t)m * n + i], v[i]);
-      w[m] = d2_val(&d);
-    }
-    double num = 0.0, den = 0.0;
-    for (int64_t i = 0; i < n; ++i) {
-      dot2 r = {0.0, 0.0}, av = {0.0, 0.0};
-      for (int64_t j = 0; j < n; ++j) {
-        double aij = sym(a, n, i, j);
-        d2_sub_prod(&r, -aij, v[j]);
-        d2_sub_prod(&av, -aij, v[j]);
-      }
-      for (int64_t m = 0; m <= i; ++m) d2_sub_prod(&r, l[(size_t)m * n + i], w[m]);
-      double rv = d2_val(&r), avv = d2_val(&av);
-      num += rv * rv;
-      den += avv * avv;
-    }
-    double e = sqrt(num) / sqrt(den);
+    double e = residual_ratio(a, l, n, v, w);
     if (e > worst || e != e) worst = e;
   }
   free(v);

@@ -214,6 +214,26 @@ void solve_program(int nt, std::vector<TaskDesc>& tasks, std::vector<spx_access>
     if (a.task >= first) acc.push_back(spx_access{a.task - first, a.mode, a.datum});
 }
 
+void gemm_program(int nt, std::vector<TaskDesc>& tasks, std::vector<spx_access>& acc) {
+  tasks.clear();
+  acc.clear();
+  const uint64_t n2 = (uint64_t)nt * (uint64_t)nt;
+  for (int k = 0; k < nt; ++k)
+    for (int i = 0; i < nt; ++i)
+      for (int j = 0; j < nt; ++j) {
+        const uint32_t t = (uint32_t)tasks.size();
+        TaskDesc d;
+        d.type = SPX_T_MGEMM;
+        d.i = (uint16_t)i;
+        d.j = (uint16_t)j;
+        d.k = (uint16_t)k;
+        tasks.push_back(d);
+        acc.push_back(spx_access{t, SPX_ACC_R, (uint64_t)i * nt + k});
+        acc.push_back(spx_access{t, SPX_ACC_R, n2 + (uint64_t)k * nt + j});
+        acc.push_back(spx_access{t, SPX_ACC_RW, 2 * n2 + (uint64_t)i * nt + j});
+      }
+}
+
 // Program of one matrix in a batched or served graph: LOAD writes every tile (and the
 // right-hand-side blocks), so each tile's first update depends on it; STORE reads the
 // solution blocks after the backward substitution.
@@ -287,6 +307,7 @@ int32_t cholesky_priority(const TaskDesc& d, int nt) {
     case SPX_T_FGEMM: base = (d.i == d.k + 1) ? 3 : 1; break;
     case SPX_T_INV: base = 1; break;  // off the factor's critical path, needed by the solve
     case SPX_T_BGEMM: base = (d.i + 1 == d.k) ? 3 : 1; break;
+    case SPX_T_MGEMM: base = 2; break;  // one level: FIFO in push order
     default: base = 3; break;
   }
   return base * 65536 + (nt - d.k);
@@ -343,12 +364,13 @@ int spx_graph_to_dot(const spx_graph* g, const char* path) {
   if (!g || !path) return fail(SPX_EINVAL, "spx_graph_to_dot: null argument");
   FILE* f = std::fopen(path, "w");
   if (!f) return fail(SPX_EINVAL, "spx_graph_to_dot: cannot open file");
-  static const char* names[] = {"POTRF", "TRSM", "SYRK", "GEMM", "FTRSM", "FGEMM", "BTRSM", "BGEMM", "LOAD", "STORE", "INV"};
+  static const char* names[] = {"POTRF", "TRSM", "SYRK", "GEMM", "FTRSM", "FGEMM", "BTRSM", "BGEMM", "LOAD", "STORE", "INV",
+                                "MGEMM"};
   std::fprintf(f, "digraph spx {\n");
   for (uint32_t t = 0; t < g->g.ntasks; ++t) {
     if (t < g->tasks.size()) {
       const TaskDesc& d = g->tasks[t];
-      std::fprintf(f, "  t%u [label=\"%s(%d,%d,%d)\"];\n", t, d.type < 11 ? names[d.type] : "?", d.i, d.j, d.k);
+      std::fprintf(f, "  t%u [label=\"%s(%d,%d,%d)\"];\n", t, d.type < 12 ? names[d.type] : "?", d.i, d.j, d.k);
     } else {
       std::fprintf(f, "  t%u [label=\"t%u p%d\"];\n", t, t, g->g.prio[t]);
     }
@@ -387,6 +409,28 @@ int spx_cholesky_graph(int32_t nt, int32_t with_solve, spx_graph** out, int32_t*
     return SPX_OK;
   } catch (const std::bad_alloc&) {
     return fail(SPX_ENOMEM, "spx_cholesky_graph: out of host memory");
+  }
+}
+
+int spx_gemm_graph(int32_t nt, spx_graph** out, int32_t* task_types, uint32_t cap) {
+  if (!out || nt < 1 || nt > 512) return fail(SPX_EINVAL, "spx_gemm_graph: bad argument");
+  *out = nullptr;
+  try {
+    std::unique_ptr<spx_graph> g(new spx_graph());
+    std::vector<spx_access> acc;
+    gemm_program(nt, g->tasks, acc);
+    std::vector<int32_t> prio(g->tasks.size());
+    for (size_t t = 0; t < g->tasks.size(); ++t) prio[t] = cholesky_priority(g->tasks[t], nt);
+    int rc = build_graph((uint32_t)g->tasks.size(), acc.data(), acc.size(), prio.data(), g->g);
+    if (rc) return rc;
+    if (task_types) {
+      if (cap < g->tasks.size()) return fail(SPX_EINVAL, "spx_gemm_graph: capacity too small");
+      for (size_t t = 0; t < g->tasks.size(); ++t) task_types[t] = g->tasks[t].type;
+    }
+    *out = g.release();
+    return SPX_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(SPX_ENOMEM, "spx_gemm_graph: out of host memory");
   }
 }
 

@@ -55,6 +55,7 @@ typedef unsigned long long u64;
 struct Image {
   uint32_t ntasks = 0, total_parts = 0;
   int nlev = 1;
+  int family = FAM_CHOL;  // the scheduler instantiation that runs its tasks
   uint32_t qbase[kMaxLevels] = {};
   uint32_t qcap[kMaxLevels] = {};
   uint32_t nroots = 0;
@@ -80,6 +81,7 @@ struct Program {
   std::vector<TaskDesc> tasks;
   Graph g;
 };
+
 
 }  // namespace spx
 
@@ -116,6 +118,7 @@ struct spx_ctx {
   int64_t trace_len = 0;
   std::vector<u64> host_cycles;
   TaskDesc* dtask = nullptr;  // descriptor of single-task launches
+  uint32_t flags = 0;         // SPX_F_TRACE: trace every launch (spx_ctx_set_flags)
 };
 
 struct spx_factor {
@@ -165,6 +168,7 @@ static int get_program(spx_ctx* c, char kind, int nt, const Program** out, int p
     case 'P': io_program(nt, true, pr->tasks, acc, false, psteps); break;
     case 'K': io_program(nt, true, pr->tasks, acc, true, psteps); break;
     case 'Q': solve_io_program(nt, pr->tasks, acc); break;
+    case 'M': gemm_program(nt, pr->tasks, acc); break;
     default: return fail(SPX_EINVAL, "unknown program kind");
   }
   std::vector<int32_t> prio(pr->tasks.size());
@@ -219,6 +223,10 @@ uint16_t parts_of(const TaskDesc& d, int b, int nrhs) {
       return (uint16_t)((ntiles <= kLoadTileParts ? ntiles : d.i) + (nrhs > 0 ? 1 : 0));
     }
     case SPX_T_STORE: return 1;
+    case SPX_T_MGEMM: {
+      const int s = b < 128 ? b : 128;
+      return (uint16_t)((b / s) * (b / s));
+    }
   }
   return 1;
 }
@@ -245,9 +253,23 @@ struct Piece {
   int b, nrhs;
 };
 
-// Uploads the concatenation of the pieces' graphs (no edges between pieces) as one
-// device image.
-static int make_image(spx_ctx* c, const std::vector<Piece>& pieces, int policy, Image** out) {
+// Host form of a device image: the static arrays (task descriptors, CSR successors,
+// in-degrees, part counts, the root items, the initial counters) laid out as one block,
+// and the offsets of the per-launch arrays that follow them.
+struct ImageHost {
+  uint32_t ntasks = 0, total_parts = 0;
+  int nlev = 1;
+  uint32_t qbase[kMaxLevels] = {};
+  uint32_t qcap[kMaxLevels] = {};
+  uint32_t nroots = 0;
+  int nshards = 1;
+  std::vector<char> bytes;  // the static part (static_bytes)
+  size_t o_tasks = 0, o_off = 0, o_succ = 0, o_indeg = 0, o_np = 0, o_q0 = 0, o_c0 = 0, static_bytes = 0;
+  size_t o_pend = 0, o_pl = 0, o_q = 0, o_c = 0, total_bytes = 0;
+};
+
+// Lays out the concatenation of the pieces' graphs (no edges between pieces) as one image.
+static int build_image_host(const std::vector<Piece>& pieces, int policy, ImageHost& im) {
   // one ready queue per level keeps one matrix's tasks in global push order (its critical
   // path runs through the oldest bulk updates); independent matrices need no such order,
   // and sharded queues spread the pops of their many small tasks
@@ -260,9 +282,8 @@ static int make_image(spx_ctx* c, const std::vector<Piece>& pieces, int policy, 
   if (T64 >= (1ull << 32) - 1 || E64 >= (1ull << 32) - 1) return fail(SPX_EINVAL, "task graph too large");
   const uint32_t T = (uint32_t)T64;
   const size_t E = (size_t)E64;
-  std::unique_ptr<Image> im(new Image());
-  im->ntasks = T;
-  im->nlev = policy == SPX_Q_FIFO ? 1 : kMaxLevels;
+  im.ntasks = T;
+  im.nlev = policy == SPX_Q_FIFO ? 1 : kMaxLevels;
   std::vector<TaskDesc> tasks(T);
   std::vector<uint32_t> off32(T + 1), succ(std::max<size_t>(E, 1)), indeg(T), nparts(T);
   uint64_t per_level[kMaxLevels] = {};
@@ -289,9 +310,9 @@ static int make_image(spx_ctx* c, const std::vector<Piece>& pieces, int policy, 
   uint64_t total = 0;
   for (int l = 0; l < kMaxLevels; ++l) total += per_level[l];
   if (total * kShards >= (1ull << 32) - 1) return fail(SPX_EINVAL, "task graph too large");
-  im->total_parts = (uint32_t)total;
-  for (int l = 0; l < kMaxLevels; ++l) im->qcap[l] = (uint32_t)per_level[l];
-  for (int l = 1; l < kMaxLevels; ++l) im->qbase[l] = im->qbase[l - 1] + im->qcap[l - 1];
+  im.total_parts = (uint32_t)total;
+  for (int l = 0; l < kMaxLevels; ++l) im.qcap[l] = (uint32_t)per_level[l];
+  for (int l = 1; l < kMaxLevels; ++l) im.qbase[l] = im.qbase[l - 1] + im.qcap[l - 1];
   // root parts are dealt round-robin over the shards of their level
   std::vector<u64> roots;
   std::vector<uint32_t> counters0(kNumCounters, 0);
@@ -302,54 +323,78 @@ static int make_image(spx_ctx* c, const std::vector<Piece>& pieces, int policy, 
     for (uint32_t p = 0; p < nparts[t]; ++p) {
       const int sh = (int)(deal++ % nshards);
       uint32_t& tail = counters0[ctr_tail_idx(l, sh)];
-      roots.push_back((u64)im->qbase[l] * kShards + (u64)sh * im->qcap[l] + tail);
+      roots.push_back((u64)im.qbase[l] * kShards + (u64)sh * im.qcap[l] + tail);
       roots.push_back(((u64)t << 16) | p);
       ++tail;
     }
   }
-  im->nroots = (uint32_t)(roots.size() / 2);
-  im->nshards = nshards;
+  im.nroots = (uint32_t)(roots.size() / 2);
+  im.nshards = nshards;
   if (roots.empty()) roots.assign(2, 0);
   // layout
   auto align = [](size_t x) { return (x + 255) & ~(size_t)255; };
   size_t o = 0;
-  const size_t o_tasks = o; o = align(o + sizeof(TaskDesc) * T);
-  const size_t o_off = o; o = align(o + 4 * (size_t)(T + 1));
-  const size_t o_succ = o; o = align(o + 4 * succ.size());
-  const size_t o_indeg = o; o = align(o + 4 * (size_t)T);
-  const size_t o_np = o; o = align(o + 4 * (size_t)T);
-  const size_t o_q0 = o; o = align(o + 8 * roots.size());
-  const size_t o_c0 = o; o = align(o + 4 * (size_t)kNumCounters);
-  const size_t static_bytes = o;
-  const size_t o_pend = o; o = align(o + 4 * (size_t)T);
-  const size_t o_pl = o; o = align(o + 4 * (size_t)T);
-  const size_t o_q = o; o = align(o + 8 * (size_t)im->total_parts * kShards);
-  const size_t o_c = o; o = align(o + 4 * (size_t)kNumCounters);
-  im->bytes = o;
-  im->block = dev_alloc(c, o);
+  im.o_tasks = o; o = align(o + sizeof(TaskDesc) * T);
+  im.o_off = o; o = align(o + 4 * (size_t)(T + 1));
+  im.o_succ = o; o = align(o + 4 * succ.size());
+  im.o_indeg = o; o = align(o + 4 * (size_t)T);
+  im.o_np = o; o = align(o + 4 * (size_t)T);
+  im.o_q0 = o; o = align(o + 8 * roots.size());
+  im.o_c0 = o; o = align(o + 4 * (size_t)kNumCounters);
+  im.static_bytes = o;
+  im.o_pend = o; o = align(o + 4 * (size_t)T);
+  im.o_pl = o; o = align(o + 4 * (size_t)T);
+  im.o_q = o; o = align(o + 8 * (size_t)im.total_parts * kShards);
+  im.o_c = o; o = align(o + 4 * (size_t)kNumCounters);
+  im.total_bytes = o;
+  im.bytes.assign(im.static_bytes, 0);
+  char* h = im.bytes.data();
+  std::memcpy(h + im.o_tasks, tasks.data(), sizeof(TaskDesc) * T);
+  std::memcpy(h + im.o_off, off32.data(), 4 * (size_t)(T + 1));
+  std::memcpy(h + im.o_succ, succ.data(), 4 * succ.size());
+  std::memcpy(h + im.o_indeg, indeg.data(), 4 * (size_t)T);
+  std::memcpy(h + im.o_np, nparts.data(), 4 * (size_t)T);
+  std::memcpy(h + im.o_q0, roots.data(), 8 * roots.size());
+  std::memcpy(h + im.o_c0, counters0.data(), 4 * (size_t)kNumCounters);
+  return SPX_OK;
+}
+
+// Points the arrays of `im` into the device block `base` laid out as `h` says.
+static void bind_image(const ImageHost& h, char* base, Image* im) {
+  im->ntasks = h.ntasks;
+  im->total_parts = h.total_parts;
+  im->nlev = h.nlev;
+  for (int l = 0; l < kMaxLevels; ++l) {
+    im->qbase[l] = h.qbase[l];
+    im->qcap[l] = h.qcap[l];
+  }
+  im->nroots = h.nroots;
+  im->nshards = h.nshards;
+  im->bytes = h.total_bytes;
+  im->tasks = (TaskDesc*)(base + h.o_tasks);
+  im->succ_off = (uint32_t*)(base + h.o_off);
+  im->succ = (uint32_t*)(base + h.o_succ);
+  im->indeg = (uint32_t*)(base + h.o_indeg);
+  im->nparts = (uint32_t*)(base + h.o_np);
+  im->roots = (u64*)(base + h.o_q0);
+  im->counters0 = (uint32_t*)(base + h.o_c0);
+  im->pending = (uint32_t*)(base + h.o_pend);
+  im->parts_left = (uint32_t*)(base + h.o_pl);
+  im->queue = (u64*)(base + h.o_q);
+  im->counters = (uint32_t*)(base + h.o_c);
+}
+
+// Uploads the concatenation of the pieces' graphs (no edges between pieces) as one
+// device image.
+static int make_image(spx_ctx* c, const std::vector<Piece>& pieces, int policy, Image** out) {
+  ImageHost h;
+  SPX_TRY(build_image_host(pieces, policy, h));
+  std::unique_ptr<Image> im(new Image());
+  im->block = dev_alloc(c, h.total_bytes);
   if (!im->block) return fail(SPX_ENOMEM, "device image: allocation failed");
-  char* base = (char*)im->block;
-  im->tasks = (TaskDesc*)(base + o_tasks);
-  im->succ_off = (uint32_t*)(base + o_off);
-  im->succ = (uint32_t*)(base + o_succ);
-  im->indeg = (uint32_t*)(base + o_indeg);
-  im->nparts = (uint32_t*)(base + o_np);
-  im->roots = (u64*)(base + o_q0);
-  im->counters0 = (uint32_t*)(base + o_c0);
-  im->pending = (uint32_t*)(base + o_pend);
-  im->parts_left = (uint32_t*)(base + o_pl);
-  im->queue = (u64*)(base + o_q);
-  im->counters = (uint32_t*)(base + o_c);
-  std::vector<char> host(static_bytes, 0);
-  std::memcpy(host.data() + o_tasks, tasks.data(), sizeof(TaskDesc) * T);
-  std::memcpy(host.data() + o_off, off32.data(), 4 * (size_t)(T + 1));
-  std::memcpy(host.data() + o_succ, succ.data(), 4 * succ.size());
-  std::memcpy(host.data() + o_indeg, indeg.data(), 4 * (size_t)T);
-  std::memcpy(host.data() + o_np, nparts.data(), 4 * (size_t)T);
-  std::memcpy(host.data() + o_q0, roots.data(), 8 * roots.size());
-  std::memcpy(host.data() + o_c0, counters0.data(), 4 * (size_t)kNumCounters);
+  bind_image(h, (char*)im->block, im.get());
   // synchronous copy: the host vector is freed on return
-  int rc = hipc(hipMemcpy(im->block, host.data(), static_bytes, hipMemcpyHostToDevice), "image upload");
+  int rc = hipc(hipMemcpy(im->block, h.bytes.data(), h.static_bytes, hipMemcpyHostToDevice), "image upload");
   if (rc) {
     dev_free(c, im->block);
     return rc;
@@ -418,7 +463,7 @@ static int ensure_small_buffers(spx_ctx* c, size_t nmats, size_t num_wg, size_t 
 // Runs one image over `nmats` matrices (descriptors in c->hmats) and waits for it.
 // On return c->hinfo[0..nmats) holds each matrix's info word.
 static int run_image(spx_ctx* c, Image* im, int nmats, const spx_opts* o, double pack_ms) {
-  const bool trace = o && (o->flags & SPX_F_TRACE);
+  const bool trace = (o && (o->flags & SPX_F_TRACE)) || (c->flags & SPX_F_TRACE);
   int num_wg = (o && o->num_wg > 0) ? o->num_wg : c->num_cu * c->wg_per_cu;
   if (num_wg < 1) num_wg = 1;
   SPX_TRY(ensure_small_buffers(c, nmats, num_wg, im->total_parts, trace));
@@ -449,7 +494,7 @@ static int run_image(spx_ctx* c, Image* im, int nmats, const spx_opts* o, double
   a.wg_cycles = c->wg_cycles;
   a.spin_limit = 100000000ull * 20;  // 20 s of the 100 MHz device clock without progress
   SPX_TRY(hipc(hipEventRecord(c->ev[0], c->stream), "hipEventRecord"));
-  SPX_TRY(launch_sched(a, num_wg, c->stream));
+  SPX_TRY(launch_sched(a, num_wg, c->stream, im->family));
   SPX_TRY(hipc(hipEventRecord(c->ev[1], c->stream), "hipEventRecord"));
   SPX_TRY(hipc(hipMemcpyAsync(c->hinfo, c->dinfo, 4 * (size_t)nmats, hipMemcpyDeviceToHost, c->stream), "info"));
   SPX_TRY(hipc(hipMemcpyAsync(c->hcounters, im->counters, 4 * kNumCounters, hipMemcpyDeviceToHost, c->stream),
@@ -1168,6 +1213,75 @@ int spx_potrf_tiled(spx_ctx* c, int64_t n, const double* dA, int64_t lda, const 
   return SPX_OK;
 }
 
+int spx_gemm_tiled(spx_ctx* c, int64_t n, const double* dA, int64_t lda, const double* dB, int64_t ldb, double* dC,
+                   int64_t ldc, const spx_opts* opts) {
+  if (!c || !dA || !dB || !dC) return fail(SPX_EINVAL, "spx_gemm_tiled: null argument");
+  if (n < 1 || lda < n || ldb < n || ldc < n) return fail(SPX_EINVAL, "spx_gemm_tiled: need n >= 1 and ld >= n");
+  const int b = (opts && opts->tile > 0) ? opts->tile : default_tile(n);
+  if (!valid_tile(b)) return fail(SPX_EINVAL, "spx_gemm_tiled: tile must be 32, 64, 128, 256 or 512");
+  const int policy = opts ? opts->queue_policy : SPX_Q_PRIORITY;
+  if (policy != SPX_Q_PRIORITY && policy != SPX_Q_FIFO) return fail(SPX_EINVAL, "spx_gemm_tiled: bad queue policy");
+  if (opts && opts->update_prec != SPX_PREC_FP64) return fail(SPX_EINVAL, "spx_gemm_tiled: FP64 only");
+  const int64_t nt = (n + b - 1) / b;
+  if (nt > 160) return fail(SPX_EINVAL, "spx_gemm_tiled: too many tiles (at most 160 per side)");
+  try {
+    SPX_TRY(hipc(hipSetDevice(c->device), "hipSetDevice"));
+    const size_t tile_bytes = (size_t)(nt * nt) * (size_t)b * (size_t)b * sizeof(double);
+    char* block = (char*)dev_alloc(c, 3 * tile_bytes);
+    if (!block) return fail(SPX_ENOMEM, "spx_gemm_tiled: tile storage allocation failed");
+    double* ta = (double*)block;
+    double* tbt = (double*)(block + tile_bytes);
+    double* tc = (double*)(block + 2 * tile_bytes);
+    char key[96];
+    std::snprintf(key, sizeof key, "M:%d:%d:%d", (int)nt, b, policy);
+    Image* im = nullptr;
+    int rc = SPX_OK;
+    auto it = c->images.find(key);
+    if (it != c->images.end()) {
+      im = it->second;
+    } else {
+      const Program* pr = nullptr;
+      rc = get_program(c, 'M', (int)nt, &pr);
+      if (!rc) rc = make_image(c, {Piece{pr, 0, b, 0}}, policy, &im);
+      if (!rc) {
+        im->family = FAM_GEMM;
+        c->images[key] = im;
+      }
+    }
+    if (!rc) rc = ensure_small_buffers(c, 1, 1, 0, false);
+    if (!rc) rc = hipc(hipEventRecord(c->ev[2], c->stream), "hipEventRecord");
+    if (!rc) rc = launch_pack_full(dA, lda, n, ta, b, (int)nt, 0, c->stream);
+    if (!rc) rc = launch_pack_full(dB, ldb, n, tbt, b, (int)nt, 1, c->stream);
+    if (!rc) rc = launch_pack_full(dC, ldc, n, tc, b, (int)nt, 0, c->stream);
+    if (!rc) rc = hipc(hipEventRecord(c->ev[3], c->stream), "hipEventRecord");
+    if (!rc) {
+      DevMat m{};
+      m.tiles = tc;
+      m.ga = ta;
+      m.gbt = tbt;
+      m.info = c->dinfo;
+      m.n_pad = nt * b;
+      m.nt = (int32_t)nt;
+      m.b = b;
+      m.n = (int32_t)n;
+      c->hmats[0] = m;
+      rc = run_image(c, im, 1, opts, 0.0);
+    }
+    if (!rc) {
+      float pms = 0.f;
+      if (hipEventElapsedTime(&pms, c->ev[2], c->ev[3]) == hipSuccess) c->last.pack_ms = pms;
+      c->last.tile = (uint32_t)b;
+      rc = launch_unpack_full(tc, b, (int)nt, n, dC, ldc, c->stream);
+    }
+    if (!rc) rc = hipc(hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+    (void)hipStreamSynchronize(c->stream);
+    dev_free(c, block);
+    return rc;
+  } catch (const std::bad_alloc&) {
+    return fail(SPX_ENOMEM, "spx_gemm_tiled: out of host memory");
+  }
+}
+
 int spx_factor_info(const spx_factor* f, int64_t* n, int32_t* tile, int64_t* n_padded) {
   if (!f) return fail(SPX_EINVAL, "spx_factor_info: null factor");
   if (n) *n = f->n;
@@ -1489,11 +1603,18 @@ int spx_run_task(spx_ctx* c, int32_t type, int32_t i, int32_t j, int32_t k, int3
   return SPX_OK;
 }
 
+int spx_ctx_set_flags(spx_ctx* c, uint32_t flags) {
+  if (!c || (flags & ~(uint32_t)SPX_F_TRACE)) return fail(SPX_EINVAL, "spx_ctx_set_flags: bad argument");
+  c->flags = flags;
+  return SPX_OK;
+}
+
 int spx_last_stats(const spx_ctx* c, spx_stats* out) {
   if (!c || !out) return fail(SPX_EINVAL, "spx_last_stats: null argument");
   *out = c->last;
   return SPX_OK;
 }
+
 
 int64_t spx_trace(const spx_ctx* c, uint64_t* rec, int64_t cap) {
   if (!c) return fail(SPX_EINVAL, "spx_trace: null context");

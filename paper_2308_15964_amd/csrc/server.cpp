@@ -78,11 +78,16 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // Device bytes a request holds while it runs (what the batched calls and the refinement
 // allocate for it, plus device copies of host inputs).
+//   FP64: one-shot factor + solve: tiles, 32x32 block inverses, one right-hand-side copy.
+//   mixed: kept factor (tiles, block inverses, the tile inverses M_k = L_kk^{-T}, the FP32
+//   panel copies) and the two right-hand-side copies of its solves, plus the residual and
+//   the refinement buffers.
 size_t request_bytes(const spx_request& r, int b) {
   const size_t n = (size_t)r.n, q = (size_t)r.nrhs, nt = (n + b - 1) / b, npad = nt * b;
   const size_t tiles = nt * (nt + 1) / 2 * (size_t)b * b * 8;
   size_t s = align256(tiles) + align256(npad * 32 * 8) + align256(npad * q * 8);
-  if (r.mode == SPX_MODE_MIXED) s += align256(tiles / 2) + 2 * align256(n * q * 8) + align256(npad * q * 8);
+  if (r.mode == SPX_MODE_MIXED)
+    s += align256(npad * (size_t)b * 8) + align256(tiles / 2) + 2 * align256(n * q * 8) + align256(npad * q * 8);
   if (r.where == 0) s += align256(n * n * 8) + align256(n * q * 8) + align256(n * q * 8);
   return s;
 }
@@ -352,6 +357,8 @@ int spx_server_create(spx_ctx* ctx, size_t hbm_budget_bytes, const spx_server_op
   if (hipDeviceGetDefaultMemPool(&pool, s->device) == hipSuccess) {
     uint64_t keep = UINT64_MAX;  // keep freed blocks for reuse instead of returning them
     (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+    uint64_t zero = 0;  // the high-water mark reported by spx_server_get_stats starts here
+    (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrUsedMemHigh, &zero);
   }
   s->lanes.resize(s->opts.lanes);
   for (auto& ln : s->lanes) {
@@ -424,6 +431,11 @@ int spx_server_get_stats(spx_server* s, spx_server_stats* out) {
   if (!s || !out) return fail(SPX_EINVAL, "spx_server_get_stats: null argument");
   std::lock_guard<std::mutex> lk(s->mu);
   *out = s->st;
+  hipMemPool_t pool;
+  uint64_t high = 0;
+  if (hipDeviceGetDefaultMemPool(&pool, s->device) == hipSuccess &&
+      hipMemPoolGetAttribute(pool, hipMemPoolAttrUsedMemHigh, &high) == hipSuccess)
+    out->pool_used_high = high;
   return SPX_OK;
 }
 

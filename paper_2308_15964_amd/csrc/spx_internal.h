@@ -44,6 +44,8 @@ int build_graph(uint32_t ntasks, const spx_access* acc, uint64_t nacc, const int
 void cholesky_program(int nt, bool with_solve, std::vector<TaskDesc>& tasks, std::vector<spx_access>& acc,
                       bool with_inverse = false, int potrf_steps = 1);
 void solve_program(int nt, std::vector<TaskDesc>& tasks, std::vector<spx_access>& acc);
+// The tiled matrix product C += A B (k outermost, then i, then j).
+void gemm_program(int nt, std::vector<TaskDesc>& tasks, std::vector<spx_access>& acc);
 int32_t cholesky_priority(const TaskDesc& d, int nt);
 // LOAD, the factor program (and with_solve: the substitution), STORE (with_solve only);
 // with_inverse: the inversion tasks and the inverse-based substitution.
@@ -80,6 +82,10 @@ struct DevMat {
   const double* B;  // n x nrhs row-major
   double* X;        // n x nrhs row-major
   int64_t lda, ldb, ldx;
+  // tiled matrix product: A tiles and B^T tiles (all nt x nt, tile (i,j) at (i nt + j) b^2,
+  // column-major); C tiles in `tiles` with the same layout
+  const double* ga;
+  const double* gbt;
 };
 
 // A LOAD task has one part per lower tile while they fit the 16-bit part index.
@@ -123,6 +129,10 @@ enum { STATUS_TIMEOUT = 1u };
 // Host-side launchers (spx_kernels.hip).
 int launch_pack(const double* dA, int64_t lda, int64_t n, const DevMat& m, void* stream);
 int launch_unpack(const DevMat& m, int64_t n, double* dL, int64_t ldl, void* stream);
+// Dense row-major n x n (ld) <-> all nt x nt tiles of size b (tile (i,j) at (i nt + j) b^2,
+// column-major), zero padding; trans: the tiles of the transpose.
+int launch_pack_full(const double* src, int64_t ld, int64_t n, double* tiles, int b, int nt, int trans, void* stream);
+int launch_unpack_full(const double* tiles, int b, int nt, int64_t n, double* dst, int64_t ld, void* stream);
 // scale (nullable): row r is multiplied by scale[r] on the way in / out.
 int launch_rhs_in(const double* dB, int64_t ldb, int64_t n, int64_t nrhs, double* rhs, int64_t n_pad,
                   const double* scale, void* stream);
@@ -142,7 +152,10 @@ int launch_sched_init_full(uint32_t* pending, const uint32_t* indeg, uint32_t* p
                            const unsigned long long* roots, uint32_t nroots, uint32_t* counters,
                            const uint32_t* counters0, uint32_t ncounters, int32_t* info, int ninfo,
                            uint32_t* trace_idx, void* stream);
-int launch_sched(const SchedArgs& a, int num_wg, void* stream);
+// Task families of the scheduler kernel (one instantiation each): FAM_CHOL runs every
+// task of the Cholesky, solve, batched and served graphs; FAM_GEMM the tiled product's.
+enum { FAM_CHOL = 0, FAM_GEMM = 1 };
+int launch_sched(const SchedArgs& a, int num_wg, void* stream, int family = FAM_CHOL);
 int launch_one_task(const SchedArgs& a, int nparts, void* stream);
 int launch_tile_inverses(const double* l, int b, double* dinv, void* stream);
 uint16_t parts_of(const TaskDesc& d, int b, int nrhs);

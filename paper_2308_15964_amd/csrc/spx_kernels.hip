@@ -71,10 +71,11 @@ __device__ __forceinline__ uint32_t ld_rlx(const uint32_t* p) {
 // lane l holds rows row0 + 16 i + l%16 of C: sixteen lanes cover sixteen consecutive
 // doubles of one column.  Element v of the accumulator is column col0 + 16 j + cofs(l, v):
 // (l/16 + 4v) for the FP64 form, (4(l/16) + v) for the FP32-accumulating forms.  Every old
-// value is loaded before any is stored, so the loads overlap.
+// value is loaded before any is stored, so the loads overlap.  sgn = 1 subtracts the
+// product; sgn = -1 adds it (sgn * acc is exact, so both round once, as C - acc / C + acc).
 template <int NB, bool F64_LAYOUT, class ACC>
 __device__ __forceinline__ void update_epilogue(double* C, int ldc, const ACC (&acc)[NB][NB], int row0, int col0,
-                                                int M, int N, bool lower) {
+                                                int M, int N, bool lower, double sgn = 1.0) {
   const int lane = threadIdx.x & 63;
   GLOBAL double* Cg = gp(C);
   double old[NB][NB][4];
@@ -97,7 +98,7 @@ __device__ __forceinline__ void update_epilogue(double* C, int ldc, const ACC (&
         const int row = row0 + i * 16 + (lane & 15);
         const int col = col0 + j * 16 + (F64_LAYOUT ? (lane >> 4) + 4 * v : 4 * (lane >> 4) + v);
         if (row < M && col < N && (!lower || row >= col))
-          Cg[(size_t)col * ldc + row] = old[i][j][v] - (double)acc[i][j][v];
+          Cg[(size_t)col * ldc + row] = old[i][j][v] - sgn * (double)acc[i][j][v];
       }
 }
 
@@ -110,11 +111,15 @@ __device__ __forceinline__ void update_epilogue(double* C, int ldc, const ACC (&
 // loads are issued, so each chunk needs one barrier and its loads have a whole chunk of
 // matrix-core work to arrive.  M, N: multiples of 16, at most 2*WT.  K: multiple of 32.
 // lower: write only the entries with row >= col (diagonal blocks of a symmetric update).
+// FULL (M = N = 2*WT): the chunk loads carry no row guard, so a chunk's loads issue back to
+// back with no branch between them (measured on one CU: 96 -> 81 us per 128x128x512 part;
+// 167 -> 127 us when every part streams its operands).  Only the tiled-product kernel uses
+// it: in the Cholesky kernel its extra registers made the compiler spill (see run_part).
 // ---------------------------------------------------------------------------------------
-template <int WT>
+template <int WT, bool FULL = false>
 __device__ void gemm_nt_f64(double* __restrict__ C, int ldc, const double* __restrict__ A, int lda,
                             const double* __restrict__ B, int ldb, int M, int N, int K, bool lower,
-                            double* __restrict__ lds) {
+                            double* __restrict__ lds, double sgn = 1.0) {
   constexpr int SB = 2 * WT;
   constexpr int KC = 32;
   constexpr int NB = WT / 16;
@@ -138,8 +143,8 @@ __device__ void gemm_nt_f64(double* __restrict__ C, int ldc, const double* __res
     for (int p = 0; p < PAIRS; ++p) {
       const int e = (tid + p * NT) * 2;
       const int m = e / SB, r = e % SB;
-      ra[p] = (r < M) ? *(const GLOBAL d2*)(Ak + m * lda + r) : d2{0.0, 0.0};
-      rb[p] = (r < N) ? *(const GLOBAL d2*)(Bk + m * ldb + r) : d2{0.0, 0.0};
+      ra[p] = (FULL || r < M) ? *(const GLOBAL d2*)(Ak + m * lda + r) : d2{0.0, 0.0};
+      rb[p] = (FULL || r < N) ? *(const GLOBAL d2*)(Bk + m * ldb + r) : d2{0.0, 0.0};
     }
   };
   auto lstore = [&](int buf) {
@@ -184,7 +189,7 @@ __device__ void gemm_nt_f64(double* __restrict__ C, int ldc, const double* __res
   // accumulator layout of v_mfma_f64_16x16x4 (measured on gfx950): element v of lane l
   // holds (row l/16 + 4v, column l%16) of the 16x16 product, here (B A^T): C row l%16,
   // C column l/16 + 4v
-  update_epilogue<NB, true>(C, ldc, acc, wr * WT, wc * WT, M, N, lower);
+  update_epilogue<NB, true>(C, ldc, acc, wr * WT, wc * WT, M, N, lower, sgn);
 }
 
 // Dispatch on the block size: M, N <= 128.
@@ -1345,7 +1350,8 @@ __device__ void pack_block(const double* __restrict__ A, int64_t lda, int64_t n,
 // ---------------------------------------------------------------------------------------
 // Part dispatch.
 // ---------------------------------------------------------------------------------------
-__device__ void run_part(const SchedArgs& a, uint32_t task, uint32_t part, double* lds) {
+__device__ __attribute__((noinline)) void run_part_chol(const SchedArgs& a, uint32_t task, uint32_t part,
+                                                        double* lds) {
   const TaskDesc d = a.tasks[task];
   const DevMat& m = a.mats[d.mat];
   // a failed pivot earlier in this matrix: its remaining tasks drain without computing
@@ -1500,6 +1506,42 @@ __device__ void run_part(const SchedArgs& a, uint32_t task, uint32_t part, doubl
   }
 }
 
+// The tiled product's task, C_ij += A_ik B_kj (the GEMM application): part -> 128x128
+// sub-block (I, J) of C_ij; the B operand is the tile (j, k) of B^T, so the transposed-B
+// update applies with the sign turned.  Every block is full, so the guard-free loads.
+__device__ __attribute__((noinline)) void run_part_gemm(const SchedArgs& a, uint32_t task, uint32_t part,
+                                                        double* lds) {
+  const TaskDesc d = a.tasks[task];
+  const DevMat& m = a.mats[d.mat];
+  const int b = m.b;
+  const int sb = b < 128 ? b : 128, ns = b / sb;
+  const int I = part % ns, J = part / ns;
+  const size_t bb = (size_t)b * b;
+  double* C = m.tiles + ((size_t)d.i * m.nt + d.j) * bb + (size_t)J * sb * b + I * sb;
+  const double* Ai = m.ga + ((size_t)d.i * m.nt + d.k) * bb + I * sb;
+  const double* Bj = m.gbt + ((size_t)d.j * m.nt + d.k) * bb + J * sb;
+  if (sb > 64)
+    gemm_nt_f64<64, true>(C, b, Ai, b, Bj, b, sb, sb, b, false, lds, -1.0);
+  else if (sb > 32)
+    gemm_nt_f64<32, true>(C, b, Ai, b, Bj, b, sb, sb, b, false, lds, -1.0);
+  else
+    gemm_nt_f64<16, true>(C, b, Ai, b, Bj, b, sb, sb, b, false, lds, -1.0);
+}
+
+// Task families: a launch runs the scheduler instantiated for the task types its graph
+// can hold, so each instantiation holds (and allocates registers for) only those tile
+// kernels.  The task bodies stay out of line and the scheduler's queue operations inline,
+// the code layout under which the Cholesky kernel compiles without VGPR spills (inlining
+// the task bodies into the loop, or adding the tiled product to them, made the compiler
+// spill 24-113 VGPRs).
+template <int FAM>
+__device__ __forceinline__ void run_part(const SchedArgs& a, uint32_t task, uint32_t part, double* lds) {
+  if constexpr (FAM == FAM_CHOL)
+    run_part_chol(a, task, part, lds);
+  else
+    run_part_gemm(a, task, part, lds);
+}
+
 // ---------------------------------------------------------------------------------------
 // The persistent scheduler kernel.
 // ---------------------------------------------------------------------------------------
@@ -1527,7 +1569,7 @@ __device__ __forceinline__ uint32_t sub_rlx(uint32_t* p, uint32_t v) {
 }
 
 // push into the pushing workgroup's own shard: reserve nparts slots, then fill them
-__device__ void push_task(const SchedArgs& a, uint32_t s, int home) {
+__device__ __forceinline__ void push_task(const SchedArgs& a, uint32_t s, int home) {
   const TaskDesc d = a.tasks[s];
   const uint32_t slot = __hip_atomic_fetch_add(ctr_tail(a, d.level, home), (uint32_t)d.nparts, __ATOMIC_RELAXED,
                                                __HIP_MEMORY_SCOPE_AGENT);
@@ -1546,7 +1588,7 @@ __device__ void push_task(const SchedArgs& a, uint32_t s, int home) {
 // in every lane); *saw tells whether some queue looked non-empty and *taken is the number
 // of parts taken from all queues so far (never more than the true count).
 constexpr int kClaim = 4;
-__device__ int pop_wave(const SchedArgs& a, int home, bool* saw, uint32_t* taken, u64* items) {
+__device__ __forceinline__ int pop_wave(const SchedArgs& a, int home, bool* saw, uint32_t* taken, u64* items) {
   const int lane = threadIdx.x & 63, S = a.nshards;
   const bool valid = lane < a.nlev * S;
   const int l = lane / S, sh = (home + lane % S) % S;
@@ -1575,17 +1617,26 @@ __device__ int pop_wave(const SchedArgs& a, int home, bool* saw, uint32_t* taken
       if (__hip_atomic_compare_exchange_strong(ctr_head(a, l, sh), &h, h + want, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
                                                __HIP_MEMORY_SCOPE_AGENT)) {
         // the slots are reserved by running pushers: wait for the items to be written
+        // (bounded by the spin limit: a slot still empty then ends the launch)
         const u64* q = queue_of(a, l, sh) + h;
+        const u64 t0 = now_ticks();
+        k = (int)want;
 #pragma unroll
         for (int i = 0; i < kClaim; ++i) {
           if (i < (int)want) {
             u64 v;
-            while ((v = __hip_atomic_load(q + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) == EMPTY)
+            while ((v = __hip_atomic_load(q + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) == EMPTY) {
+              if (now_ticks() - t0 > a.spin_limit) {
+                __hip_atomic_fetch_or(ctr_status(a), (uint32_t)STATUS_TIMEOUT, __ATOMIC_RELAXED,
+                                      __HIP_MEMORY_SCOPE_AGENT);
+                k = 0;
+                break;
+              }
               __builtin_amdgcn_s_sleep(1);
+            }
             it[i] = v;
           }
         }
-        k = (int)want;
         break;
       }
     }
@@ -1599,6 +1650,7 @@ __device__ int pop_wave(const SchedArgs& a, int home, bool* saw, uint32_t* taken
   return k;
 }
 
+template <int FAM>
 __global__ __launch_bounds__(NT) void sched_kernel(SchedArgs a) {
   __shared__ double lds[LDS_DOUBLES];
   __shared__ u64 s_items[kClaim];
@@ -1618,7 +1670,11 @@ __global__ __launch_bounds__(NT) void sched_kernel(SchedArgs a) {
         uint32_t taken;
         n = pop_wave(a, home, &saw, &taken, items);
         if (n > 0) break;
-        if (saw) {  // the queue emptied under us: scan again after a short pause
+        if (saw) {  // the queue emptied under us (or a bounded wait gave up): scan again
+          if (__builtin_amdgcn_readfirstlane(ld_rlx(ctr_status(a))) != 0) {
+            n = -1;
+            break;
+          }
           __builtin_amdgcn_s_sleep(1);
           continue;
         }
@@ -1645,9 +1701,21 @@ __global__ __launch_bounds__(NT) void sched_kernel(SchedArgs a) {
         for (int z = 0; z < (1 << naps); ++z) __builtin_amdgcn_s_sleep(2);
       }
       if (tid == 0) {
+        // a popped task was pushed when its last predecessor's decrement took the counter
+        // to zero, so the wait below ends at once; it is bounded all the same
+        const u64 tw = now_ticks();
         for (int i = 0; i < n; ++i) {
           const uint32_t* pend = a.pending + (uint32_t)(items[i] >> 16);
-          while (ld_rlx(pend) != 0u) __builtin_amdgcn_s_sleep(1);
+          while (ld_rlx(pend) != 0u) {
+            if (now_ticks() - tw > a.spin_limit) {
+              __hip_atomic_fetch_or(ctr_status(a), (uint32_t)STATUS_TIMEOUT, __ATOMIC_RELAXED,
+                                    __HIP_MEMORY_SCOPE_AGENT);
+              n = -1;
+              break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+          }
+          if (n < 0) break;
           s_items[i] = items[i];
         }
         if (n > 0) fence_acq();
@@ -1662,7 +1730,7 @@ __global__ __launch_bounds__(NT) void sched_kernel(SchedArgs a) {
       const u64 item = s_items[i];
       const uint32_t task = (uint32_t)(item >> 16), part = (uint32_t)(item & 0xffff);
       const u64 tb = now_ticks();
-      run_part(a, task, part, lds);
+      run_part<FAM>(a, task, part, lds);
       __syncthreads();
       if (tid == 0) {
         const u64 te = now_ticks();
@@ -1697,7 +1765,7 @@ __global__ __launch_bounds__(NT) void sched_kernel(SchedArgs a) {
 // One task, part blockIdx.x per workgroup (tests of the tile kernels).
 __global__ __launch_bounds__(NT) void one_task_kernel(SchedArgs a) {
   __shared__ double lds[LDS_DOUBLES];
-  run_part(a, 0, blockIdx.x, lds);
+  run_part_chol(a, 0, blockIdx.x, lds);
 }
 
 __global__ __launch_bounds__(NT) void tile_inverses_kernel(const double* l, int b, double* dinv) {
@@ -1742,6 +1810,51 @@ __global__ __launch_bounds__(NT) void pack_kernel(const double* __restrict__ A, 
   const int ti = blockIdx.x / nt, tj = blockIdx.x % nt;
   if (tj > ti) return;
   pack_block(A, lda, n, m, ti, tj, blockIdx.y / per, blockIdx.y % per, S, s);
+}
+
+// All tiles of a dense row-major n x n matrix (or of its transpose): one workgroup per
+// 64x64 (or b x b) sub-block of a tile, through LDS so the row-major reads and the
+// column-major tile writes are both coalesced.  Entries beyond n are zero.
+__global__ __launch_bounds__(NT) void pack_full_kernel(const double* __restrict__ src, int64_t ld, int64_t n,
+                                                       double* __restrict__ tiles, int b, int nt, int trans) {
+  __shared__ double s[64 * 65];
+  const int S = b < 64 ? b : 64, per = b / S;
+  const int ti = blockIdx.x / nt, tj = blockIdx.x % nt;
+  const int si = blockIdx.y / per, sj = blockIdx.y % per;
+  const int64_t R0 = (int64_t)ti * b + si * S, C0 = (int64_t)tj * b + sj * S;  // of the packed matrix
+  // s[x * 65 + y]: element (R0 + (trans ? y : x), C0 + (trans ? x : y)) where (x, y) walks the
+  // source row by row
+  for (int e = threadIdx.x; e < S * S; e += NT) {
+    const int x = e / S, y = e % S;
+    const int64_t sr = trans ? C0 + x : R0 + x, sc = trans ? R0 + y : C0 + y;  // source row, column
+    s[x * 65 + y] = (sr < n && sc < n) ? src[sr * ld + sc] : 0.0;
+  }
+  __syncthreads();
+  double* T = tiles + ((size_t)ti * nt + tj) * (size_t)b * b;
+  for (int e = threadIdx.x; e < S * S; e += NT) {
+    const int c = e / S, r = e % S;  // tile column, row (r fastest: coalesced writes)
+    T[(size_t)(sj * S + c) * b + si * S + r] = trans ? s[c * 65 + r] : s[r * 65 + c];
+  }
+}
+
+__global__ __launch_bounds__(NT) void unpack_full_kernel(const double* __restrict__ tiles, int b, int nt, int64_t n,
+                                                         double* __restrict__ dst, int64_t ld) {
+  __shared__ double s[64 * 65];
+  const int S = b < 64 ? b : 64, per = b / S;
+  const int ti = blockIdx.x / nt, tj = blockIdx.x % nt;
+  const int si = blockIdx.y / per, sj = blockIdx.y % per;
+  const int64_t R0 = (int64_t)ti * b + si * S, C0 = (int64_t)tj * b + sj * S;
+  if (R0 >= n || C0 >= n) return;
+  const double* T = tiles + ((size_t)ti * nt + tj) * (size_t)b * b;
+  for (int e = threadIdx.x; e < S * S; e += NT) {
+    const int c = e / S, r = e % S;
+    s[r * 65 + c] = T[(size_t)(sj * S + c) * b + si * S + r];
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < S * S; e += NT) {
+    const int r = e / S, c = e % S;
+    if (R0 + r < n && C0 + c < n) dst[(R0 + r) * ld + C0 + c] = s[r * 65 + c];
+  }
 }
 
 // Diagonally dominant SPD test matrix (row-major n x n, both triangles): off-diagonal
@@ -1945,11 +2058,26 @@ static int hip_ok(hipError_t e, const char* what) {
   return failf(SPX_EDEVICE, "%s: %s", what, hipGetErrorString(e));
 }
 
+
 int launch_pack(const double* dA, int64_t lda, int64_t n, const DevMat& m, void* stream) {
   const int S = m.b < 64 ? m.b : 64, per = m.b / S;
   dim3 grid((unsigned)(m.nt * m.nt), (unsigned)(per * per));
   hipLaunchKernelGGL(pack_kernel, grid, dim3(NT), 0, (hipStream_t)stream, dA, lda, n, m);
   return hip_ok(hipGetLastError(), "pack_kernel");
+}
+
+int launch_pack_full(const double* src, int64_t ld, int64_t n, double* tiles, int b, int nt, int trans, void* stream) {
+  const int S = b < 64 ? b : 64, per = b / S;
+  dim3 grid((unsigned)(nt * nt), (unsigned)(per * per));
+  hipLaunchKernelGGL(pack_full_kernel, grid, dim3(NT), 0, (hipStream_t)stream, src, ld, n, tiles, b, nt, trans);
+  return hip_ok(hipGetLastError(), "pack_full_kernel");
+}
+
+int launch_unpack_full(const double* tiles, int b, int nt, int64_t n, double* dst, int64_t ld, void* stream) {
+  const int S = b < 64 ? b : 64, per = b / S;
+  dim3 grid((unsigned)(nt * nt), (unsigned)(per * per));
+  hipLaunchKernelGGL(unpack_full_kernel, grid, dim3(NT), 0, (hipStream_t)stream, tiles, b, nt, n, dst, ld);
+  return hip_ok(hipGetLastError(), "unpack_full_kernel");
 }
 
 int launch_spd_fill(double* A, int64_t n, uint32_t seed, void* stream) {
@@ -2000,7 +2128,7 @@ int launch_rhs_out(const double* rhs, int64_t n_pad, int64_t n, int64_t nrhs, do
 
 int sched_max_wg(int device, int* per_cu, int* num_cu) {
   int blocks = 0;
-  if (int rc = hip_ok(hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, sched_kernel, NT, 0),
+  if (int rc = hip_ok(hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, sched_kernel<FAM_CHOL>, NT, 0),
                       "hipOccupancyMaxActiveBlocksPerMultiprocessor"))
     return rc;
   int cus = 0;
@@ -2022,8 +2150,11 @@ int launch_one_task(const SchedArgs& a, int nparts, void* stream) {
   return hip_ok(hipGetLastError(), "one_task_kernel");
 }
 
-int launch_sched(const SchedArgs& a, int num_wg, void* stream) {
-  hipLaunchKernelGGL(sched_kernel, dim3(num_wg), dim3(NT), 0, (hipStream_t)stream, a);
+int launch_sched(const SchedArgs& a, int num_wg, void* stream, int family) {
+  if (family == FAM_GEMM)
+    hipLaunchKernelGGL(sched_kernel<FAM_GEMM>, dim3(num_wg), dim3(NT), 0, (hipStream_t)stream, a);
+  else
+    hipLaunchKernelGGL(sched_kernel<FAM_CHOL>, dim3(num_wg), dim3(NT), 0, (hipStream_t)stream, a);
   return hip_ok(hipGetLastError(), "sched_kernel");
 }
 

@@ -84,7 +84,7 @@ class ServerOpts(ctypes.Structure):
 class ServerStats(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64), ("rejected", ctypes.c_uint64),
                 ("launches", ctypes.c_uint64), ("bytes_in_use", ctypes.c_uint64), ("bytes_peak", ctypes.c_uint64),
-                ("max_running", ctypes.c_uint64), ("busy_s", ctypes.c_double)]
+                ("max_running", ctypes.c_uint64), ("busy_s", ctypes.c_double), ("pool_used_high", ctypes.c_uint64)]
 
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
@@ -93,12 +93,14 @@ FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void
 # Every symbol include/spx.h declares, in declaration order.
 EXPORTS = [
     "spx_last_error", "spx_ctx_create", "spx_ctx_destroy", "spx_graph_build", "spx_graph_info", "spx_graph_edges",
-    "spx_graph_indegree", "spx_graph_to_dot", "spx_graph_destroy", "spx_cholesky_graph", "spx_potrf_tiled",
-    "spx_factor_info", "spx_factor_get_l", "spx_factor_destroy", "spx_potrs", "spx_backward_error",
+    "spx_graph_indegree", "spx_graph_to_dot", "spx_graph_destroy", "spx_cholesky_graph", "spx_gemm_graph",
+    "spx_potrf_tiled",
+    "spx_factor_info", "spx_factor_get_l", "spx_factor_destroy", "spx_gemm_tiled", "spx_potrs",
+    "spx_backward_error",
     "spx_run_task", "spx_posv_batched", "spx_potrf_batched", "spx_potrs_batched", "spx_backward_error_batched",
     "spx_set_tile_table", "spx_tile_for",
     "spx_autotune_batched", "spx_server_create", "spx_submit", "spx_poll", "spx_server_now",
-    "spx_server_get_stats", "spx_server_destroy", "spx_last_stats", "spx_trace",
+    "spx_server_get_stats", "spx_server_destroy", "spx_last_stats", "spx_ctx_set_flags", "spx_trace",
 ]
 
 _lib = None
@@ -131,10 +133,12 @@ def lib():
         "spx_graph_to_dot": (ctypes.c_int, [vp, ctypes.c_char_p]),
         "spx_graph_destroy": (None, [vp]),
         "spx_cholesky_graph": (ctypes.c_int, [i32, i32, P(vp), P(i32), u32]),
+        "spx_gemm_graph": (ctypes.c_int, [i32, P(vp), P(i32), u32]),
         "spx_potrf_tiled": (ctypes.c_int, [vp, i64, vp, i64, P(Opts), P(vp), P(i64)]),
         "spx_factor_info": (ctypes.c_int, [vp, P(i64), P(i32), P(i64)]),
         "spx_factor_get_l": (ctypes.c_int, [vp, vp, vp, i64]),
         "spx_factor_destroy": (None, [vp]),
+        "spx_gemm_tiled": (ctypes.c_int, [vp, i64, vp, i64, vp, i64, vp, i64, P(Opts)]),
         "spx_potrs": (ctypes.c_int, [vp, vp, i64, vp, i64, vp, i64, vp, i64, P(Refine), P(SolveStats)]),
         "spx_backward_error": (ctypes.c_int, [vp, i64, vp, i64, i64, vp, i64, vp, i64, P(ctypes.c_double)]),
         "spx_run_task": (ctypes.c_int, [vp, i32, i32, i32, i32, i32, i32, vp, vp, i32, P(i64)]),
@@ -155,6 +159,7 @@ def lib():
         "spx_server_get_stats": (ctypes.c_int, [vp, P(ServerStats)]),
         "spx_server_destroy": (None, [vp]),
         "spx_last_stats": (ctypes.c_int, [vp, P(Stats)]),
+        "spx_ctx_set_flags": (ctypes.c_int, [vp, u32]),
         "spx_trace": (i64, [vp, P(u64), i64]),
     }
     for name, (res, args) in sig.items():
@@ -208,6 +213,14 @@ class Graph:
         types = (ctypes.c_int32 * T)()
         flag = int(bool(with_solve)) | (2 if io else 0) | (4 if inverse else 0) | (potrf_steps << 8)
         _check(lib().spx_cholesky_graph(nt, flag, ctypes.byref(h), types, T))
+        return cls(h.value, np.array(types[:], dtype=np.int32))
+
+    @classmethod
+    def gemm(cls, nt):
+        """The tiled matrix product's program (spx_gemm_graph)."""
+        h = ctypes.c_void_p()
+        types = (ctypes.c_int32 * (nt ** 3))()
+        _check(lib().spx_gemm_graph(nt, ctypes.byref(h), types, nt ** 3))
         return cls(h.value, np.array(types[:], dtype=np.int32))
 
     def info(self):
@@ -343,6 +356,18 @@ class Context:
             return out, {"iters": st.iters, "method_used": st.method_used, "eta_max": st.eta_max}
         return out
 
+    def gemm(self, A, B, C, tile=0, queue_policy=Q_PRIORITY, num_wg=0, flags=0):
+        """C <- C + A B in place (spx_gemm_tiled); returns C."""
+        for t, nm in ((A, "A"), (B, "B"), (C, "C")):
+            self._dev(t, nm)
+        n = A.shape[0]
+        if A.shape != (n, n) or B.shape != (n, n) or C.shape != (n, n):
+            raise ValueError("A, B and C must be n x n")
+        o = Opts(tile, PREC_FP64, queue_policy, num_wg, flags, 0, 0.0)
+        _check(lib().spx_gemm_tiled(self._h, n, _ptr(A), A.stride(0), _ptr(B), B.stride(0), _ptr(C), C.stride(0),
+                                    ctypes.byref(o)))
+        return C
+
     def backward_error(self, A, X, B):
         A = self._dev(A, "A")
         X2 = self._dev(X, "X").reshape(A.shape[0], -1)
@@ -475,6 +500,10 @@ class Context:
         s = Stats()
         _check(lib().spx_last_stats(self._h, ctypes.byref(s)))
         return {k: getattr(s, k) for k, _ in Stats._fields_}
+
+    def set_flags(self, flags):
+        """Context-wide launch flags (F_TRACE: trace every later launch; 0: off)."""
+        _check(lib().spx_ctx_set_flags(self._h, flags))
 
     def trace(self):
         n = _check(lib().spx_trace(self._h, None, 0))

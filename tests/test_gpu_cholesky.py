@@ -239,13 +239,15 @@ def test_invalid_arguments(ctx):
         ctx.potrf(A, queue_policy=7)
 
 
-def test_config2_full_size_properties(ctx):
+def test_config2_full_size_parity(ctx):
     """N=16384, tile 512 (32x32 tiles, 5984 tasks), A = G G^T/N + I, one right-hand side,
-    in the launch configuration the benchmark times.  The oracle cannot factor this size
-    in a test, so it checks the device factor and solution against their definitions:
-    sampled entries of A = L L^T (each O(N), compensated), a randomised factor residual,
-    and the backward error of the solution."""
-    import sys, os
+    in the launch configuration the benchmark times, element by element against the
+    oracle (its thread-pool executor: the same bits as its sequential one, by order
+    invariance), plus the definitions: sampled entries of A = L L^T (each O(N),
+    compensated), a randomised factor residual, and the backward error of the solution."""
+    import os
+    import sys
+    import time
 
     sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
     import bench
@@ -257,11 +259,13 @@ def test_config2_full_size_properties(ctx):
     # the program, one inversion per diagonal tile, and each diagonal factorization cut
     # into b/32 chained steps (15 more tasks per diagonal tile)
     assert st["ntasks"] == 5984 + 32 + 32 * 15
-    X = ctx.potrs(F, Bd)
+    X = ctx.potrs(F, Bd).cpu().numpy()
     L = F.L().cpu().numpy()
     F.close()
     Ah = A.cpu().numpy()
+    Bh = Bd.cpu().numpy()
     del A
+    torch.cuda.empty_cache()
     rs = np.random.default_rng(99)
     ii = rs.integers(0, n, 400)
     jj = rs.integers(0, n, 400)
@@ -269,5 +273,13 @@ def test_config2_full_size_properties(ctx):
     jj[:8] = np.arange(n - 8, n)  # the last columns see the most updates
     assert oracle.entry_check(Ah, L, ii, jj) <= 1e-13
     assert oracle.factor_residual_probe(Ah, L, nvec=2, seed=5) <= 1e-13
-    eta = oracle.backward_error(Ah, X.cpu().numpy(), Bd.cpu().numpy())
+    eta = oracle.backward_error(Ah, X, Bh)
     assert eta.max() <= 1e-14, eta
+    threads = max(1, min(16, os.cpu_count() or 1))
+    print(f"oracle N={n} tile {b} on {threads} threads", flush=True)
+    t0 = time.perf_counter()
+    Lo, Xo, info = oracle.cholesky(Ah, b, Bh, nthreads=threads)
+    print(f"oracle done in {time.perf_counter() - t0:.1f} s", flush=True)
+    assert info == 0
+    check_factor(Ah, L, Lo)
+    check_solve(X, Xo, eta)

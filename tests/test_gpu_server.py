@@ -141,6 +141,32 @@ def test_budget_admission(ctx):
     srv.close()
 
 
+def test_budget_admission_mixed(ctx):
+    """Mixed requests keep their factor (tiles, block inverses, the tile inverses M_k and
+    the FP32 panel copies) through refinement.  With one 512 tile per request M_k is as
+    large as the tiles, so admission must count it: the device pool's high-water mark
+    stays within the budget (plus the lanes' small graph images)."""
+    from paper_2308_15964_amd import spx
+
+    ctx.set_tile_table(spx.PREC_FP32, [(512, 512)])
+    try:
+        items = [inputs.gram_spd(500, seed=90 + i, nrhs=2) for i in range(6)]
+        budget = 11 << 20  # two of these requests at once
+        srv = spx.Server(ctx, budget, lanes=2)
+        xs, rs = run_all(srv, items, spx.MODE_MIXED)
+        st = srv.stats()
+        srv.close()
+    finally:
+        ctx.set_tile_table(spx.PREC_FP32, [])
+    assert all(r["status"] == 0 and r["info"] == 0 for r in rs)
+    assert all(r["tile"] == 512 for r in rs)
+    assert 0 < st["bytes_peak"] <= budget
+    print(f"pool high-water {st['pool_used_high']} bytes, budget {budget}", flush=True)
+    assert st["pool_used_high"] <= budget + (1 << 20), st
+    for (A, B), X in zip(items, xs):
+        assert oracle.backward_error(A, X, B).max() <= 1e-12
+
+
 def test_not_pd_request_and_errors(ctx):
     from paper_2308_15964_amd import spx
 

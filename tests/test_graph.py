@@ -218,3 +218,12 @@ def test_executed_graph_with_potrf_steps_bit_exact(nt, with_solve, steps):
 def test_potrf_steps_rejected_above_64():
     with pytest.raises(spx.SpxError):
         spx.Graph.cholesky(2, potrf_steps=65)
+
+
+@pytest.mark.parametrize("nt", [1, 2, 3, 6])
+def test_gemm_graph_matches_oracle(nt):
+    g = spx.Graph.gemm(nt)
+    _, e, _ = oracle.gemm_dag(nt)
+    assert np.array_equal(g.edges(), e)
+    assert (g.task_types == spx.SPX_T_MGEMM).all() if hasattr(spx, "SPX_T_MGEMM") else (g.task_types == 11).all()
+    g.close()

@@ -193,8 +193,106 @@ def test_factor_residual_closed_form():
     R = A - L @ L.T  # exact: half-integers of modest size
     want = np.linalg.norm(R) / np.linalg.norm(A)
     assert abs(oracle.factor_residual(A, L) - want) <= 1e-15 * want
-    assert oracle.factor_residual_probe(A, L, nvec=4) > 1e-4
-    ii = np.array([7, 7, 12, 3])
-    jj = np.array([3, 5, 7, 0])
-    assert oracle.entry_check(A, L, ii, jj) > 0
-    assert oracle.entry_check(A, L0, ii, jj) == 0.0
+
+
+def test_entry_check_closed_form():
+    """A = [[4, 2], [2, 10]] has the factor [[2, 0], [1, 3]].  With L(1,0) = 1.5 instead,
+    entry (1,0) of A - L L^T is 2 - 3 = -1 and entry (1,1) is 10 - (2.25 + 9) = -1.25;
+    relative to sqrt(A_ii A_jj) they are 1/sqrt(40) and 1.25/10 exactly."""
+    A = np.array([[4.0, 2.0], [2.0, 10.0]])
+    L = np.array([[2.0, 0.0], [1.5, 3.0]])
+    one = lambda i, j: oracle.entry_check(A, L, np.array([i]), np.array([j]))
+    assert one(0, 0) == 0.0
+    assert one(1, 0) == 1.0 / np.sqrt(40.0)
+    assert one(0, 1) == 1.0 / np.sqrt(40.0)  # an upper index pair is read as its mirror
+    assert one(1, 1) == 0.125
+    assert oracle.entry_check(A, L, np.array([0, 1, 1]), np.array([0, 1, 0])) == 1.0 / np.sqrt(40.0)
+    assert oracle.entry_check(A, np.array([[2.0, 0.0], [1.0, 3.0]]), np.array([1, 1]), np.array([0, 1])) == 0.0
+
+
+def _exact_residual_entry(A, L, i, j):
+    """A_ij - sum_{m <= min(i, j)} L_im L_jm in exact rational arithmetic."""
+    from fractions import Fraction as Fr
+
+    i, j = max(i, j), min(i, j)
+    return Fr(float(A[i, j])) - sum(Fr(float(L[i, m])) * Fr(float(L[j, m])) for m in range(j + 1))
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_entry_check_matches_exact_arithmetic(seed):
+    """Sampled entries of A - L L^T for a factor with planted half-integer errors, against
+    the same quantity formed in exact rationals (only the final sqrt and division round)."""
+    A, L0, _, _ = inputs.integer_factor(24, seed=90 + seed, nrhs=1)
+    rs = np.random.default_rng(seed)
+    L = L0.copy()
+    for _ in range(4):
+        i = int(rs.integers(1, 24))
+        L[i, int(rs.integers(0, i + 1))] += 0.5 * int(rs.choice([-3, -1, 1, 3]))
+    ii = rs.integers(0, 24, 40)
+    jj = rs.integers(0, 24, 40)
+    want = 0.0
+    for i, j in zip(ii, jj):
+        one = oracle.entry_check(A, L, np.array([i]), np.array([j]))
+        exact = abs(float(_exact_residual_entry(A, L, int(i), int(j)))) / np.sqrt(A[i, i] * A[j, j])
+        assert abs(one - exact) <= 4 * np.finfo(float).eps * exact, (i, j, one, exact)
+        want = max(want, exact)
+    assert abs(oracle.entry_check(A, L, ii, jj) - want) <= 4 * np.finfo(float).eps * want
+    assert want > 0.0
+
+
+def test_residual_probe_closed_forms():
+    """For A = a I and L = l I every vector gives |a - l^2| / a: 1/3 for (3, 2), and
+    0.5625 for (4, 2.5), whatever vectors the probe draws."""
+    n = 50
+    assert abs(oracle.factor_residual_probe(3.0 * np.eye(n), 2.0 * np.eye(n), nvec=3) - 1.0 / 3.0) <= 1e-15
+    assert abs(oracle.factor_residual_probe(4.0 * np.eye(n), 2.5 * np.eye(n), nvec=3) - 0.5625) <= 1e-15
+    assert oracle.factor_residual_probe(4.0 * np.eye(n), 2.0 * np.eye(n), nvec=3) == 0.0
+
+
+def test_residual_vectors_match_exact_arithmetic():
+    """||(A - L L^T) v|| / ||A v|| on dyadic vectors and a factor with planted half-integer
+    errors: every intermediate is exact, so the value equals the exact rational ratio's
+    square root up to the final sqrt and division."""
+    from fractions import Fraction as Fr
+
+    n = 16
+    A, L0, _, _ = inputs.integer_factor(n, seed=97, nrhs=1)
+    L = L0.copy()
+    L[9, 4] += 0.5
+    L[13, 13] -= 1.5
+    rs = np.random.default_rng(5)
+    V = rs.integers(-16, 17, (n, 3)) / 8.0
+    ratios = []
+    for q in range(3):
+        v = [Fr(float(x)) for x in V[:, q]]
+        Af = [[Fr(float(A[i, j])) for j in range(n)] for i in range(n)]
+        Lf = [[Fr(float(L[i, j])) for j in range(n)] for i in range(n)]
+        Av = [sum(Af[i][j] * v[j] for j in range(n)) for i in range(n)]
+        w = [sum(Lf[i][m] * v[i] for i in range(n)) for m in range(n)]  # L^T v
+        LLv = [sum(Lf[i][m] * w[m] for m in range(n)) for i in range(n)]
+        num = sum((Av[i] - LLv[i]) ** 2 for i in range(n))
+        den = sum(x * x for x in Av)
+        ratios.append(np.sqrt(float(num)) / np.sqrt(float(den)))
+        got = oracle.factor_residual_vectors(A, L, V[:, q])
+        assert abs(got - ratios[-1]) <= 4 * np.finfo(float).eps * ratios[-1], (q, got, ratios[-1])
+    assert abs(oracle.factor_residual_vectors(A, L, V) - max(ratios)) <= 4 * np.finfo(float).eps * max(ratios)
+    assert oracle.factor_residual_vectors(A, L0, V) == 0.0
+
+
+def test_backward_error_matches_exact_arithmetic():
+    """eta per column for an integer SPD matrix and dyadic x, b: the residual, the norms and
+    the maxima are exact, so eta equals the exact ratio up to its final division."""
+    from fractions import Fraction as Fr
+
+    n = 12
+    A, _, _, _ = inputs.integer_factor(n, seed=99, nrhs=1)
+    rs = np.random.default_rng(6)
+    X = rs.integers(-40, 41, (n, 3)) / 16.0
+    B = rs.integers(-40, 41, (n, 3)) / 4.0
+    anorm = max(sum(abs(Fr(float(A[i, j]))) for j in range(n)) for i in range(n))
+    eta = oracle.backward_error(A, X, B)
+    for q in range(3):
+        r = [Fr(float(B[i, q])) - sum(Fr(float(A[i, j])) * Fr(float(X[j, q])) for j in range(n)) for i in range(n)]
+        want = float(max(abs(x) for x in r)) / float(anorm * max(abs(Fr(float(x))) for x in X[:, q]) +
+                                                     max(abs(Fr(float(x))) for x in B[:, q]))
+        assert abs(eta[q] - want) <= 2 * np.finfo(float).eps * want, (q, eta[q], want)
