@@ -221,6 +221,22 @@ typedef struct {
 int spx_potrs(spx_ctx* ctx, const spx_factor* f, int64_t nrhs, const double* dB, int64_t ldb, double* dX,
               int64_t ldx, const double* dA, int64_t lda, const spx_refine* refine, spx_solve_stats* stats);
 
+/* Allocation-free solve, for callers that cannot allocate device memory during the call
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * X = A^{-1} B through the factor f, with the same task graph, kernels and results (bit for
+ * bit) as spx_potrs without refinement.  It calls no hipMalloc, hipFree or allocating
+ * library routine: the graph image, the matrix descriptor, the info word and the two
+ * right-hand-side work copies live in a static device array of the library, 32 MiB per
+ * GPU (kept until the process ends), whose address is looked up once per device by
+ * spx_ctx_create.  dB, dX, ldb, ldx as for spx_potrs (dX may equal dB only if ldx == ldb).
+ * Every call on one GPU uses that GPU's one array and leaves its contents behind (each
+ * call rewrites what it reads), so calls that overlap on one GPU (other host threads, other
+ * contexts or streams) race: the caller serialises them.
+ * Errors: SPX_EINVAL (bad arguments, or a solve that needs more than the 32 MiB: about
+ * 2 n nrhs doubles plus the graph image), SPX_EDEVICE, SPX_ETIMEOUT. */
+int spx_potrs_noalloc(spx_ctx* ctx, const spx_factor* f, int64_t nrhs, const double* dB, int64_t ldb, double* dX,
+                      int64_t ldx);
+
 /* Normwise backward errors eta_q = ||b_q - A x_q||_inf / (||A||_inf ||x_q||_inf +
  * ||b_q||_inf), computed on the device in FP64 (row-major device pointers as above);
  * eta: host array of nrhs doubles. */
@@ -387,6 +403,7 @@ typedef struct {
   double pack_ms;       /* dense -> tile packing */
   double idle_frac;     /* sum of workgroup cycles spent waiting for work / sum of cycles */
   uint32_t ntasks, nparts, num_wg, tile;
+  uint64_t device_allocs; /* device allocations the context has made so far (all calls) */
 } spx_stats;
 int spx_last_stats(const spx_ctx* ctx, spx_stats* out);
 /* Context-wide launch flags: SPX_F_TRACE makes every later launch on the context (factor,

@@ -82,6 +82,7 @@ struct Program {
   Graph g;
 };
 
+struct ImageHost;
 
 }  // namespace spx
 
@@ -119,6 +120,10 @@ struct spx_ctx {
   std::vector<u64> host_cycles;
   TaskDesc* dtask = nullptr;  // descriptor of single-task launches
   uint32_t flags = 0;         // SPX_F_TRACE: trace every launch (spx_ctx_set_flags)
+  uint64_t dev_allocs = 0;    // device allocations made so far
+  // allocation-free solves: host images by shape, host copies of the counters after a launch
+  std::map<std::string, std::shared_ptr<ImageHost>> host_images;
+  std::vector<uint32_t> nc_counters;
 };
 
 struct spx_factor {
@@ -138,6 +143,7 @@ namespace spx {
 
 static void* dev_alloc(spx_ctx* c, size_t bytes) {
   if (bytes == 0) bytes = 256;
+  ++c->dev_allocs;
   if (c->alloc) return c->alloc(bytes, (void*)c->stream, c->user);
   void* p = nullptr;
   if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
@@ -1081,6 +1087,7 @@ int spx_ctx_create(int device, void* hip_stream, spx_alloc_fn alloc, spx_free_fn
   c->user = user;
   SPX_TRY(sched_max_wg(device, &c->wg_per_cu, &c->num_cu));
   if (c->wg_per_cu > 2) c->wg_per_cu = 2;
+  SPX_TRY(scratch_init(device));  // the allocation-free solve's array on this device
   for (auto& e : c->ev) SPX_TRY(hipc(hipEventCreate(&e), "hipEventCreate"));
   *out = c.release();
   return SPX_OK;
@@ -1612,9 +1619,115 @@ int spx_ctx_set_flags(spx_ctx* c, uint32_t flags) {
 int spx_last_stats(const spx_ctx* c, spx_stats* out) {
   if (!c || !out) return fail(SPX_EINVAL, "spx_last_stats: null argument");
   *out = c->last;
+  out->device_allocs = c->dev_allocs;
   return SPX_OK;
 }
 
+int spx_potrs_noalloc(spx_ctx* c, const spx_factor* f, int64_t nrhs, const double* dB, int64_t ldb, double* dX,
+                      int64_t ldx) {
+  if (!c || !f || !dB || !dX) return fail(SPX_EINVAL, "spx_potrs_noalloc: null argument");
+  if (nrhs < 1 || nrhs > 4096 || ldb < nrhs || ldx < nrhs) return fail(SPX_EINVAL, "spx_potrs_noalloc: bad nrhs / ld");
+  if (dX == dB && ldx != ldb) return fail(SPX_EINVAL, "spx_potrs_noalloc: aliased X and B need equal leading dimensions");
+  try {
+    SPX_TRY(hipc(hipSetDevice(c->device), "hipSetDevice"));
+    void* sp = nullptr;
+    SPX_TRY(scratch_get(c->device, &sp));
+    // the host image of the solve graph (host memory only), cached by shape
+    char key[96];
+    std::snprintf(key, sizeof key, "S:%d:%d:%d", f->nt, f->b, (int)((nrhs + 7) / 8));
+    std::shared_ptr<ImageHost>& h = c->host_images[key];
+    if (!h) {
+      const Program* pr = nullptr;
+      SPX_TRY(get_program(c, 'S', f->nt, &pr));
+      std::shared_ptr<ImageHost> nh(new ImageHost());
+      SPX_TRY(build_image_host({Piece{pr, 0, f->b, (int)nrhs}}, SPX_Q_PRIORITY, *nh));
+      h = nh;
+    }
+    // scratch layout: image (static + per-launch arrays), matrix descriptor, info word,
+    // the two right-hand-side copies
+    const size_t o_mat = align256(h->total_bytes);
+    const size_t o_info = o_mat + align256(sizeof(DevMat));
+    const size_t o_rhs = o_info + 256;
+    const size_t rhs_bytes = 2 * (size_t)f->n_pad * (size_t)nrhs * sizeof(double);
+    const size_t need = o_rhs + align256(rhs_bytes);
+    if (need > kScratchBytes)
+      return failf(SPX_EINVAL, "spx_potrs_noalloc: this solve needs %zu bytes of scratch, the limit is %zu", need,
+                   (size_t)kScratchBytes);
+    char* base = (char*)sp;
+    Image im;
+    bind_image(*h, base, &im);
+    DevMat m{};
+    m.tiles = f->tiles;
+    m.dinv = f->dinv;
+    m.minv = f->minv;
+    m.rhs = (double*)(base + o_rhs);
+    m.rhs2 = m.rhs + (size_t)f->n_pad * (size_t)nrhs;
+    m.info = (int32_t*)(base + o_info);
+    m.n_pad = f->n_pad;
+    m.nt = f->nt;
+    m.b = f->b;
+    m.nrhs = (int32_t)nrhs;
+    m.prec = PREC_FP64;
+    m.n = (int32_t)f->n;
+    m.trsm_rows = trsm_rows_of(f->b);
+    hipStream_t st = c->stream;
+    SPX_TRY(hipc(hipMemcpyAsync(base, h->bytes.data(), h->static_bytes, hipMemcpyHostToDevice, st), "image upload"));
+    SPX_TRY(hipc(hipMemcpyAsync(base + o_mat, &m, sizeof m, hipMemcpyHostToDevice, st), "descriptor upload"));
+    SPX_TRY(launch_rhs_in(dB, ldb, f->n, nrhs, m.rhs, f->n_pad, f->dscale, st));
+    SPX_TRY(launch_sched_init_full(im.pending, im.indeg, im.parts_left, im.nparts, im.ntasks, im.queue,
+                                   im.total_parts * kShards, im.roots, im.nroots, im.counters, im.counters0,
+                                   kNumCounters, m.info, 1, nullptr, st));
+    SchedArgs a{};
+    a.tasks = im.tasks;
+    a.succ_off = im.succ_off;
+    a.succ = im.succ;
+    a.pending = im.pending;
+    a.parts_left = im.parts_left;
+    a.queue = im.queue;
+    a.counters = im.counters;
+    for (int l = 0; l < kMaxLevels; ++l) {
+      a.qbase[l] = im.qbase[l];
+      a.qcap[l] = im.qcap[l];
+    }
+    a.total_parts = im.total_parts;
+    a.ntasks = im.ntasks;
+    a.nlev = im.nlev;
+    a.nshards = im.nshards;
+    a.mats = (const DevMat*)(base + o_mat);
+    a.spin_limit = 100000000ull * 20;
+    int num_wg = c->num_cu * c->wg_per_cu;
+    if (num_wg < 1) num_wg = 1;
+    SPX_TRY(hipc(hipEventRecord(c->ev[0], st), "hipEventRecord"));
+    SPX_TRY(launch_sched(a, num_wg, st));
+    SPX_TRY(hipc(hipEventRecord(c->ev[1], st), "hipEventRecord"));
+    SPX_TRY(launch_rhs_out(m.rhs, f->n_pad, f->n, nrhs, dX, ldx, 0, f->dscale, st));
+    c->nc_counters.resize(kNumCounters);
+    SPX_TRY(hipc(hipMemcpyAsync(c->nc_counters.data(), im.counters, 4 * kNumCounters, hipMemcpyDeviceToHost, st),
+                 "counters"));
+    SPX_TRY(hipc(hipStreamSynchronize(st), "hipStreamSynchronize"));
+    float ms = 0.f;
+    SPX_TRY(hipc(hipEventElapsedTime(&ms, c->ev[0], c->ev[1]), "hipEventElapsedTime"));
+    c->last = spx_stats{};
+    c->last.kernel_ms = ms;
+    c->last.ntasks = im.ntasks;
+    c->last.nparts = im.total_parts;
+    c->last.num_wg = (uint32_t)num_wg;
+    c->last.tile = (uint32_t)f->b;
+    c->trace_len = 0;
+    uint64_t done = 0;
+    for (int l = 0; l < kMaxLevels; ++l)
+      for (int sh = 0; sh < kShards; ++sh) done += c->nc_counters[ctr_head_idx(l, sh)];
+    if (c->nc_counters[kStatusIdx] & STATUS_TIMEOUT)
+      return failf(SPX_ETIMEOUT, "device scheduler made no progress (%llu of %u parts started)",
+                   (unsigned long long)done, im.total_parts);
+    if (done != im.total_parts)
+      return failf(SPX_EDEVICE, "device scheduler ended early (%llu of %u parts started)", (unsigned long long)done,
+                   im.total_parts);
+    return SPX_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(SPX_ENOMEM, "spx_potrs_noalloc: out of host memory");
+  }
+}
 
 int64_t spx_trace(const spx_ctx* c, uint64_t* rec, int64_t cap) {
   if (!c) return fail(SPX_EINVAL, "spx_trace: null context");

@@ -175,6 +175,13 @@ int launch_backward_error_batched(const ResDesc* d, const uint32_t* prefix, int 
 int launch_backward_error(int64_t n, const double* dA, int64_t lda, int64_t nrhs, const double* dX, int64_t ldx,
                           const double* dB, int64_t ldb, double* dR, double* dstats, void* stream);
 
+// Scratch array of the allocation-free entry point (a file-scope device array in
+// spx_kernels.hip, one copy per GPU).  scratch_init looks up the calling thread's current
+// device's copy (once per device; `device` must be current); scratch_get returns it.
+constexpr size_t kScratchBytes = 32ull << 20;
+int scratch_init(int device);
+int scratch_get(int device, void** ptr);
+
 // Context internals the serving loop needs.
 int ctx_device(const spx_ctx* c);
 int ctx_copy_tile_tables(const spx_ctx* from, spx_ctx* to);

@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 
 #include <climits>
+#include <mutex>
 
 #include "spx_internal.h"
 
@@ -2058,6 +2059,42 @@ static int hip_ok(hipError_t e, const char* what) {
   return failf(SPX_EDEVICE, "%s: %s", what, hipGetErrorString(e));
 }
 
+// ---------------------------------------------------------------------------------------
+// Scratch memory of the allocation-free entry point (spx_potrs_noalloc): one array per
+// device, part of the loaded code object, held until the process ends.  Host code never
+// uses the array's name as an address (on the host it is only a stand-in for the symbol):
+// the device address of each GPU's copy is looked up once, with that device current, and
+// kept here.
+// ---------------------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+int scratch_init(int device) {
+  if (device < 0 || device >= kMaxDevices) return fail(SPX_EINVAL, "scratch: device ordinal out of range");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[device]) return SPX_OK;
+  int cur = -1;
+  if (int rc = hip_ok(hipGetDevice(&cur), "hipGetDevice")) return rc;
+  if (cur != device) return fail(SPX_EINVAL, "scratch: the device must be current");
+  void* p = nullptr;
+  if (int rc = hip_ok(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)")) return rc;
+  if (!p) return fail(SPX_EDEVICE, "hipGetSymbolAddress(scratch) returned null");
+  g_scratch_ptr[device] = p;
+  return SPX_OK;
+}
+
+int scratch_get(int device, void** ptr) {
+  if (device < 0 || device >= kMaxDevices) return fail(SPX_EINVAL, "scratch: device ordinal out of range");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[device]) return fail(SPX_EINVAL, "scratch: not set up on this device");
+  *ptr = g_scratch_ptr[device];
+  return SPX_OK;
+}
 
 int launch_pack(const double* dA, int64_t lda, int64_t n, const DevMat& m, void* stream) {
   const int S = m.b < 64 ? m.b : 64, per = m.b / S;

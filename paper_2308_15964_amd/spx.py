@@ -56,7 +56,7 @@ class SolveStats(ctypes.Structure):
 class Stats(ctypes.Structure):
     _fields_ = [("kernel_ms", ctypes.c_double), ("pack_ms", ctypes.c_double), ("idle_frac", ctypes.c_double),
                 ("ntasks", ctypes.c_uint32), ("nparts", ctypes.c_uint32), ("num_wg", ctypes.c_uint32),
-                ("tile", ctypes.c_uint32)]
+                ("tile", ctypes.c_uint32), ("device_allocs", ctypes.c_uint64)]
 
 
 MODE_FP64, MODE_MIXED = 0, 1
@@ -95,7 +95,7 @@ EXPORTS = [
     "spx_last_error", "spx_ctx_create", "spx_ctx_destroy", "spx_graph_build", "spx_graph_info", "spx_graph_edges",
     "spx_graph_indegree", "spx_graph_to_dot", "spx_graph_destroy", "spx_cholesky_graph", "spx_gemm_graph",
     "spx_potrf_tiled",
-    "spx_factor_info", "spx_factor_get_l", "spx_factor_destroy", "spx_gemm_tiled", "spx_potrs",
+    "spx_factor_info", "spx_factor_get_l", "spx_factor_destroy", "spx_gemm_tiled", "spx_potrs", "spx_potrs_noalloc",
     "spx_backward_error",
     "spx_run_task", "spx_posv_batched", "spx_potrf_batched", "spx_potrs_batched", "spx_backward_error_batched",
     "spx_set_tile_table", "spx_tile_for",
@@ -140,6 +140,7 @@ def lib():
         "spx_factor_destroy": (None, [vp]),
         "spx_gemm_tiled": (ctypes.c_int, [vp, i64, vp, i64, vp, i64, vp, i64, P(Opts)]),
         "spx_potrs": (ctypes.c_int, [vp, vp, i64, vp, i64, vp, i64, vp, i64, P(Refine), P(SolveStats)]),
+        "spx_potrs_noalloc": (ctypes.c_int, [vp, vp, i64, vp, i64, vp, i64]),
         "spx_backward_error": (ctypes.c_int, [vp, i64, vp, i64, i64, vp, i64, vp, i64, P(ctypes.c_double)]),
         "spx_run_task": (ctypes.c_int, [vp, i32, i32, i32, i32, i32, i32, vp, vp, i32, P(i64)]),
         "spx_posv_batched": (ctypes.c_int, [vp, i32, P(i64), P(vp), P(i64), P(i64), P(vp), P(i64), P(vp), P(i64),
@@ -367,6 +368,17 @@ class Context:
         _check(lib().spx_gemm_tiled(self._h, n, _ptr(A), A.stride(0), _ptr(B), B.stride(0), _ptr(C), C.stride(0),
                                     ctypes.byref(o)))
         return C
+
+    def potrs_noalloc(self, F, B, X):
+        """The allocation-free solve (spx_potrs_noalloc): X = A^{-1} B into the caller's X
+        (same shape as B), with no device allocation; returns X."""
+        n = F.n
+        B2 = self._dev(B, "B").reshape(n, -1)
+        X2 = self._dev(X, "X").reshape(n, -1)
+        if X2.shape != B2.shape:
+            raise ValueError("X must have the shape of B")
+        _check(lib().spx_potrs_noalloc(self._h, F._h, B2.shape[1], _ptr(B2), B2.stride(0), _ptr(X2), X2.stride(0)))
+        return X
 
     def backward_error(self, A, X, B):
         A = self._dev(A, "A")
