@@ -80,11 +80,14 @@ def parse():
     p.add_argument("--skip-mixed", action="store_true")
     p.add_argument("--skip-batched", action="store_true")
     p.add_argument("--skip-serving", action="store_true")
+    p.add_argument("--skip-overhead", action="store_true")
     p.add_argument("--mixed-n", type=int, default=32768)
     p.add_argument("--batch-count", type=int, default=4096)
     p.add_argument("--serve-requests", type=int, default=4000)
     p.add_argument("--serve-rate", type=float, default=2000.0)
     p.add_argument("--serve-lanes", type=int, default=2)
+    p.add_argument("--policy", choices=("priority", "fifo", "sharded"), default="priority",
+                   help="ready-queue policy of the factor and solve launches")
     p.add_argument("--chain-trace", action="store_true",
                    help="trace one factor and one solve launch (--n, --tile) and print their critical paths")
     p.add_argument("--copy-probe", action="store_true",
@@ -335,6 +338,36 @@ def bench_serving(ctx, count, rate, lanes, seed=8):
     return res
 
 
+def bench_overhead(ctx, T=256):
+    """The runtime-overhead pattern of Specx Sec. 5.1 on the device: T workers (persistent
+    workgroups), T chains of N tasks, every task writing the d data of its chain and
+    waiting D; the launch takes N (D + O), O being the scheduler's cost per task, and
+    building the graph takes I per task on the host."""
+    import numpy as np
+
+    from paper_2308_15964_amd import spx
+
+    out = {"workload": f"{T} chains (one per workgroup) of N empty tasks of duration D, d writes per task; "
+                       "one ready queue vs 8 sharded queues",
+           "rows": []}
+    for D_us, N in ((10, 400), (100, 100), (1000, 20)):
+        for d in (1, 5, 10, 20):
+            acc = [(s * T + t, spx.ACC_RW, t * d + q) for s in range(N) for t in range(T) for q in range(d)]
+            t0 = time.perf_counter()
+            g = spx.Graph.build(T * N, acc)
+            build_s = time.perf_counter() - t0
+            ticks = D_us * 100
+            row = {"D_us": D_us, "N": N, "deps": d, "I_us": round(build_s * 1e6 / (T * N), 3)}
+            for name, policy in (("one_queue", spx.Q_PRIORITY), ("sharded", spx.Q_SHARDED)):
+                ctx.run_graph(g, ticks, num_wg=T, queue_policy=policy)  # warm-up: image upload
+                kms = [ctx.run_graph(g, ticks, num_wg=T, queue_policy=policy)["kernel_ms"] for _ in range(3)]
+                km = float(np.median(kms))
+                row[name] = {"kernel_ms": round(km, 3), "O_us": round(km * 1e3 / N - D_us, 3)}
+            g.close()
+            out["rows"].append(row)
+    return out
+
+
 TASK_NAMES = ["POTRF", "TRSM", "SYRK", "GEMM", "FTRSM", "FGEMM", "BTRSM", "BGEMM", "LOAD", "STORE", "INV"]
 
 
@@ -375,7 +408,7 @@ def critical_path(rec, edges, types):
     return {"span_ms": round((int(end.max()) - t0) / 1e5, 3), "path_tasks": path_len, "by_type": out}
 
 
-def chain_trace(ctx, spx, A, B, n, b):
+def chain_trace(ctx, spx, A, B, n, b, policy=0):
     """Traces one factor launch and one solve launch (--n, --tile) and breaks each one's
     critical path down by task type (run time and hop waits), from the library's per-part
     trace and the executed graphs' edges."""
@@ -387,7 +420,7 @@ def chain_trace(ctx, spx, A, B, n, b):
     ctx.set_flags(spx.F_TRACE)
     res = {}
     for _ in range(2):  # the first launches build and upload the images
-        F = ctx.potrf(A, tile=b)
+        F = ctx.potrf(A, tile=b, queue_policy=policy)
         torch.cuda.synchronize()
         rec_f, st_f = ctx.trace(), ctx.stats()
         X = ctx.potrs(F, B)
@@ -432,14 +465,15 @@ def main():
     n, b, nrhs = args.n, args.tile, args.nrhs
     A, B = gen_input(n, args.seed, nrhs, dev)
     ctx = spx.Context(0)
+    policy = {"priority": spx.Q_PRIORITY, "fifo": spx.Q_FIFO, "sharded": spx.Q_SHARDED}[args.policy]
     if args.chain_trace:
-        print(json.dumps(chain_trace(ctx, spx, A, B, n, b)), flush=True)
+        print(json.dumps(chain_trace(ctx, spx, A, B, n, b, policy)), flush=True)
         return
     flop_factor = n ** 3 / 3.0
     flop_step = flop_factor + 2.0 * n * n * nrhs
 
     def step():
-        F = ctx.potrf(A, tile=b)
+        F = ctx.potrf(A, tile=b, queue_policy=policy)
         fs = ctx.stats()
         X = ctx.potrs(F, B)
         ss = ctx.stats()
@@ -501,6 +535,9 @@ def main():
     if not args.skip_batched:
         print("bench: batched", file=sys.stderr, flush=True)
         out["batched"] = bench_batched(ctx, args.batch_count)
+    if not args.skip_overhead:
+        print("bench: overhead", file=sys.stderr, flush=True)
+        out["overhead"] = bench_overhead(ctx)
     if not args.skip_serving:
         print("bench: serving", file=sys.stderr, flush=True)
         out["serving"] = bench_serving(ctx, args.serve_requests, args.serve_rate, args.serve_lanes)

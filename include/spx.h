@@ -99,6 +99,7 @@ int spx_graph_indegree(const spx_graph* g, uint32_t* indeg, uint32_t cap);
 int spx_graph_to_dot(const spx_graph* g, const char* path);
 void spx_graph_destroy(spx_graph* g);
 
+
 /* The task program the factorisation (and, with with_solve bit 0, the block forward and
  * backward substitution) inserts for nt x nt tiles, built with spx_graph_build: right-
  * looking, lower triangle; for k: POTRF(k); TRSM(i,k) i>k; SYRK(i,k) and GEMM(i,j,k)
@@ -109,7 +110,7 @@ void spx_graph_destroy(spx_graph* g);
  * right-hand-side block k -> nt*nt + k, M_k -> nt*nt + nt + k.  task_types (nullable,
  * ntasks entries) receives SPX_T_* codes. */
 enum { SPX_T_POTRF = 0, SPX_T_TRSM, SPX_T_SYRK, SPX_T_GEMM, SPX_T_FTRSM, SPX_T_FGEMM, SPX_T_BTRSM, SPX_T_BGEMM,
-       SPX_T_LOAD, SPX_T_STORE, SPX_T_INV, SPX_T_MGEMM };
+       SPX_T_LOAD, SPX_T_STORE, SPX_T_INV, SPX_T_MGEMM, SPX_T_SPIN };
 /* SPX_T_LOAD / SPX_T_STORE appear only in the graphs of the batched and served calls: the
  * first task of each matrix copies its dense input (and right-hand sides) into tile
  * storage, writing every tile; the last one reads the solution blocks and writes X.
@@ -136,8 +137,11 @@ int spx_gemm_graph(int32_t nt, spx_graph** out, int32_t* task_types, uint32_t ca
  *   update_prec: SPX_PREC_FP64 (all tasks FP64), SPX_PREC_FP32 or SPX_PREC_BF16 (SYRK and
  *     GEMM read FP32 / BF16 copies of the panel tiles and accumulate in FP32 on the matrix
  *     cores; POTRF and TRSM stay FP64; the factor is stored in FP64).
- *   queue_policy: SPX_Q_PRIORITY (panel tasks and the next block column first) or
- *     SPX_Q_FIFO (one ready queue in push order).  Results are bitwise identical.
+ *   queue_policy: SPX_Q_PRIORITY (panel tasks and the next block column first),
+ *     SPX_Q_FIFO (one ready queue in push order) or SPX_Q_SHARDED (the priority levels,
+ *     each split into 8 ready queues; a workgroup serves the shard of its own XCD-sized
+ *     group first, so pops of many small tasks do not serialise on one queue head; the
+ *     global push order within a level is lost).  Results are bitwise identical.
  *   num_wg: persistent workgroups (0 = fill the GPU).
  *   flags: SPX_F_TRACE records per-task device timestamps (spx_trace).
  *     SPX_F_SCALED factors D^{-1/2} A D^{-1/2} + shift I instead of A (D = diag(A)):
@@ -146,7 +150,7 @@ int spx_gemm_graph(int32_t nt, spx_graph** out, int32_t* task_types, uint32_t ca
  *     returns the factor of the scaled, shifted matrix.  Single-matrix calls only.
  * ------------------------------------------------------------------------------------ */
 enum { SPX_PREC_FP64 = 0, SPX_PREC_FP32 = 1, SPX_PREC_BF16 = 2 };
-enum { SPX_Q_PRIORITY = 0, SPX_Q_FIFO = 1 };
+enum { SPX_Q_PRIORITY = 0, SPX_Q_FIFO = 1, SPX_Q_SHARDED = 2 };
 enum { SPX_F_TRACE = 1u, SPX_F_SCALED = 2u };
 typedef struct {
   int32_t tile;
@@ -180,13 +184,25 @@ void spx_factor_destroy(spx_factor* f);
  * read; C is read and overwritten and may not overlap A or B.  The matrices are copied into
  * library tile storage for the call (A and C as b x b column-major tiles, B as the tiles of
  * B^T; n padded to a multiple of b with zeros, which add exact zeros) and C back out.
- * opts (nullable): tile (32..512; 0 = chosen from n), queue_policy, num_wg, flags
- * (SPX_F_TRACE); update_prec must be SPX_PREC_FP64.  Each task's b x b update runs as
+ * opts (nullable; NULL means sharded queues and the defaults below): tile (32..512; 0 =
+ * chosen from n), queue_policy (SPX_Q_SHARDED suits this graph: nt^2 independent chains,
+ * whose pops would otherwise serialise on one queue head), num_wg, flags (SPX_F_TRACE);
+ * update_prec must be SPX_PREC_FP64.  Each task's b x b update runs as
  * 128 x 128 parts on the matrix cores; every C_ij takes its k terms in increasing k, so the
  * result does not depend on the schedule.  spx_last_stats reports the launch (pack_ms: the
  * three packs).  Errors: SPX_EINVAL, SPX_ENOMEM, SPX_EDEVICE, SPX_ETIMEOUT. */
 int spx_gemm_tiled(spx_ctx* ctx, int64_t n, const double* dA, int64_t lda, const double* dB, int64_t ldb, double* dC,
                    int64_t ldc, const spx_opts* opts);
+
+/* Runs a graph built by spx_graph_build on the device scheduler with every task an empty
+ * task (SPX_T_SPIN) that keeps its workgroup busy for spin_ticks ticks of the device's
+ * 100 MHz wall clock: the device form of the runtime-overhead study of Sec. 5.1 (a task
+ * body that only waits a duration D, so the launch time minus the waiting measures what
+ * the runtime adds per task).  The graph's edges and priorities are used as for any
+ * launch; each task is one part (one workgroup).  opts (nullable; NULL means sharded
+ * queues): queue_policy, num_wg, flags (SPX_F_TRACE); the other fields are ignored.  spx_last_stats reports the launch.
+ * spin_ticks <= 10^9 (10 s).  Errors: SPX_EINVAL, SPX_ENOMEM, SPX_EDEVICE, SPX_ETIMEOUT. */
+int spx_run_graph(spx_ctx* ctx, const spx_graph* g, uint64_t spin_ticks, const spx_opts* opts);
 
 /* ---------------------------------------------------------------------------------------
  * Solve A X = B with the factor (Sec. 5.2 task style: block forward and backward

@@ -307,7 +307,7 @@ int32_t cholesky_priority(const TaskDesc& d, int nt) {
     case SPX_T_FGEMM: base = (d.i == d.k + 1) ? 3 : 1; break;
     case SPX_T_INV: base = 1; break;  // off the factor's critical path, needed by the solve
     case SPX_T_BGEMM: base = (d.i + 1 == d.k) ? 3 : 1; break;
-    case SPX_T_MGEMM: base = 2; break;  // one level: FIFO in push order
+    case SPX_T_MGEMM: base = 0; break;  // one bulk level: several parts per claim
     default: base = 3; break;
   }
   return base * 65536 + (nt - d.k);
@@ -365,12 +365,12 @@ int spx_graph_to_dot(const spx_graph* g, const char* path) {
   FILE* f = std::fopen(path, "w");
   if (!f) return fail(SPX_EINVAL, "spx_graph_to_dot: cannot open file");
   static const char* names[] = {"POTRF", "TRSM", "SYRK", "GEMM", "FTRSM", "FGEMM", "BTRSM", "BGEMM", "LOAD", "STORE", "INV",
-                                "MGEMM"};
+                                "MGEMM", "SPIN"};
   std::fprintf(f, "digraph spx {\n");
   for (uint32_t t = 0; t < g->g.ntasks; ++t) {
     if (t < g->tasks.size()) {
       const TaskDesc& d = g->tasks[t];
-      std::fprintf(f, "  t%u [label=\"%s(%d,%d,%d)\"];\n", t, d.type < 12 ? names[d.type] : "?", d.i, d.j, d.k);
+      std::fprintf(f, "  t%u [label=\"%s(%d,%d,%d)\"];\n", t, d.type < 13 ? names[d.type] : "?", d.i, d.j, d.k);
     } else {
       std::fprintf(f, "  t%u [label=\"t%u p%d\"];\n", t, t, g->g.prio[t]);
     }

@@ -233,6 +233,7 @@ uint16_t parts_of(const TaskDesc& d, int b, int nrhs) {
       const int s = b < 128 ? b : 128;
       return (uint16_t)((b / s) * (b / s));
     }
+    case SPX_T_SPIN: return 1;
   }
   return 1;
 }
@@ -279,7 +280,7 @@ static int build_image_host(const std::vector<Piece>& pieces, int policy, ImageH
   // one ready queue per level keeps one matrix's tasks in global push order (its critical
   // path runs through the oldest bulk updates); independent matrices need no such order,
   // and sharded queues spread the pops of their many small tasks
-  const int nshards = pieces.size() > 1 ? kShards : 1;
+  const int nshards = (pieces.size() > 1 || policy == SPX_Q_SHARDED) ? kShards : 1;
   uint64_t T64 = 0, E64 = 0;
   for (const Piece& pc : pieces) {
     T64 += pc.p->g.ntasks;
@@ -695,7 +696,7 @@ static int batched(spx_ctx* c, int count, const int64_t* n, const double* const*
   if (prec != SPX_PREC_FP64 && prec != SPX_PREC_FP32 && prec != SPX_PREC_BF16)
     return failf(SPX_EINVAL, "%s: bad update precision", who);
   const int policy = o ? o->queue_policy : SPX_Q_PRIORITY;
-  if (policy != SPX_Q_PRIORITY && policy != SPX_Q_FIFO) return failf(SPX_EINVAL, "%s: bad queue policy", who);
+  if (policy != SPX_Q_PRIORITY && policy != SPX_Q_FIFO && policy != SPX_Q_SHARDED) return failf(SPX_EINVAL, "%s: bad queue policy", who);
   if (o && o->tile > 0 && !valid_tile(o->tile)) return failf(SPX_EINVAL, "%s: bad tile size", who);
   if (o && (o->flags & SPX_F_SCALED)) return failf(SPX_EINVAL, "%s: scaled factors are single-matrix only", who);
   std::vector<int> bs(count), nts(count), qs(count, 0);
@@ -1127,7 +1128,7 @@ int spx_potrf_tiled(spx_ctx* c, int64_t n, const double* dA, int64_t lda, const 
   const int b = (opts && opts->tile > 0) ? opts->tile : default_tile(n);
   if (!valid_tile(b)) return fail(SPX_EINVAL, "spx_potrf_tiled: tile must be 32, 64, 128, 256 or 512");
   const int policy = opts ? opts->queue_policy : SPX_Q_PRIORITY;
-  if (policy != SPX_Q_PRIORITY && policy != SPX_Q_FIFO) return fail(SPX_EINVAL, "spx_potrf_tiled: bad queue policy");
+  if (policy != SPX_Q_PRIORITY && policy != SPX_Q_FIFO && policy != SPX_Q_SHARDED) return fail(SPX_EINVAL, "spx_potrf_tiled: bad queue policy");
   const int prec = opts ? opts->update_prec : SPX_PREC_FP64;
   if (prec != SPX_PREC_FP64 && prec != SPX_PREC_FP32 && prec != SPX_PREC_BF16)
     return fail(SPX_EINVAL, "spx_potrf_tiled: bad update precision");
@@ -1226,8 +1227,9 @@ int spx_gemm_tiled(spx_ctx* c, int64_t n, const double* dA, int64_t lda, const d
   if (n < 1 || lda < n || ldb < n || ldc < n) return fail(SPX_EINVAL, "spx_gemm_tiled: need n >= 1 and ld >= n");
   const int b = (opts && opts->tile > 0) ? opts->tile : default_tile(n);
   if (!valid_tile(b)) return fail(SPX_EINVAL, "spx_gemm_tiled: tile must be 32, 64, 128, 256 or 512");
-  const int policy = opts ? opts->queue_policy : SPX_Q_PRIORITY;
-  if (policy != SPX_Q_PRIORITY && policy != SPX_Q_FIFO) return fail(SPX_EINVAL, "spx_gemm_tiled: bad queue policy");
+  // default: sharded queues (nt^2 independent chains, no critical path to keep in order)
+  const int policy = opts ? opts->queue_policy : SPX_Q_SHARDED;
+  if (policy != SPX_Q_PRIORITY && policy != SPX_Q_FIFO && policy != SPX_Q_SHARDED) return fail(SPX_EINVAL, "spx_gemm_tiled: bad queue policy");
   if (opts && opts->update_prec != SPX_PREC_FP64) return fail(SPX_EINVAL, "spx_gemm_tiled: FP64 only");
   const int64_t nt = (n + b - 1) / b;
   if (nt > 160) return fail(SPX_EINVAL, "spx_gemm_tiled: too many tiles (at most 160 per side)");
@@ -1286,6 +1288,51 @@ int spx_gemm_tiled(spx_ctx* c, int64_t n, const double* dA, int64_t lda, const d
     return rc;
   } catch (const std::bad_alloc&) {
     return fail(SPX_ENOMEM, "spx_gemm_tiled: out of host memory");
+  }
+}
+
+int spx_run_graph(spx_ctx* c, const spx_graph* g, uint64_t spin_ticks, const spx_opts* opts) {
+  if (!c || !g) return fail(SPX_EINVAL, "spx_run_graph: null argument");
+  if (spin_ticks > 1000000000ull) return fail(SPX_EINVAL, "spx_run_graph: spin_ticks above 10^9");
+  if (g->g.ntasks == 0) return fail(SPX_EINVAL, "spx_run_graph: empty graph");
+  const int policy = opts ? opts->queue_policy : SPX_Q_SHARDED;
+  if (policy != SPX_Q_PRIORITY && policy != SPX_Q_FIFO && policy != SPX_Q_SHARDED) return fail(SPX_EINVAL, "spx_run_graph: bad queue policy");
+  try {
+    SPX_TRY(hipc(hipSetDevice(c->device), "hipSetDevice"));
+    // every task a spin task; the graph's priorities spread over the queue levels (the
+    // largest ones first), ties served in push order
+    Program pr;
+    pr.g = g->g;
+    pr.tasks.assign(g->g.ntasks, TaskDesc());
+    int32_t pmin = INT32_MAX, pmax = INT32_MIN;
+    for (int32_t p : g->g.prio) {
+      pmin = std::min(pmin, p);
+      pmax = std::max(pmax, p);
+    }
+    for (uint32_t t = 0; t < g->g.ntasks; ++t) {
+      pr.tasks[t].type = SPX_T_SPIN;
+      // priority -> base 0..3 for level_of: equal priorities share the first level
+      const int64_t span = (int64_t)pmax - pmin;
+      const int base = span > 0 ? (int)(3 * ((int64_t)g->g.prio[t] - pmin) / span) : 3;
+      pr.g.prio[t] = base << 16;
+    }
+    Image* im = nullptr;
+    SPX_TRY(make_image(c, {Piece{&pr, 0, 32, 0}}, policy, &im));
+    std::unique_ptr<Image> own(im);
+    im->family = FAM_SPIN;
+    int rc = ensure_small_buffers(c, 1, 1, 0, false);
+    if (!rc) {
+      DevMat m{};
+      m.info = c->dinfo;
+      m.spin_ticks = spin_ticks;
+      c->hmats[0] = m;
+      rc = run_image(c, im, 1, opts, 0.0);
+    }
+    (void)hipStreamSynchronize(c->stream);
+    dev_free(c, im->block);
+    return rc;
+  } catch (const std::bad_alloc&) {
+    return fail(SPX_ENOMEM, "spx_run_graph: out of host memory");
   }
 }
 

@@ -86,6 +86,7 @@ struct DevMat {
   // column-major); C tiles in `tiles` with the same layout
   const double* ga;
   const double* gbt;
+  unsigned long long spin_ticks;  // SPX_T_SPIN: device clock ticks each task waits
 };
 
 // A LOAD task has one part per lower tile while they fit the 16-bit part index.
@@ -153,8 +154,9 @@ int launch_sched_init_full(uint32_t* pending, const uint32_t* indeg, uint32_t* p
                            const uint32_t* counters0, uint32_t ncounters, int32_t* info, int ninfo,
                            uint32_t* trace_idx, void* stream);
 // Task families of the scheduler kernel (one instantiation each): FAM_CHOL runs every
-// task of the Cholesky, solve, batched and served graphs; FAM_GEMM the tiled product's.
-enum { FAM_CHOL = 0, FAM_GEMM = 1 };
+// task of the Cholesky, solve, batched and served graphs; FAM_GEMM the tiled product's;
+// FAM_SPIN the empty tasks of spx_run_graph.
+enum { FAM_CHOL = 0, FAM_GEMM = 1, FAM_SPIN = 2 };
 int launch_sched(const SchedArgs& a, int num_wg, void* stream, int family = FAM_CHOL);
 int launch_one_task(const SchedArgs& a, int nparts, void* stream);
 int launch_tile_inverses(const double* l, int b, double* dinv, void* stream);

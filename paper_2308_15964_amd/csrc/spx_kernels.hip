@@ -1529,6 +1529,17 @@ __device__ __attribute__((noinline)) void run_part_gemm(const SchedArgs& a, uint
     gemm_nt_f64<16, true>(C, b, Ai, b, Bj, b, sb, sb, b, false, lds, -1.0);
 }
 
+// The empty task of the overhead study: one lane watches the clock for the task's
+// duration, the other lanes wait at the barrier that ends every part.
+__device__ __attribute__((noinline)) void run_part_spin(const SchedArgs& a, uint32_t task, uint32_t,
+                                                        double*) {
+  const DevMat& m = a.mats[a.tasks[task].mat];
+  if (threadIdx.x == 0) {
+    const u64 t0 = now_ticks();
+    while (now_ticks() - t0 < m.spin_ticks) __builtin_amdgcn_s_sleep(1);
+  }
+}
+
 // Task families: a launch runs the scheduler instantiated for the task types its graph
 // can hold, so each instantiation holds (and allocates registers for) only those tile
 // kernels.  The task bodies stay out of line and the scheduler's queue operations inline,
@@ -1539,8 +1550,10 @@ template <int FAM>
 __device__ __forceinline__ void run_part(const SchedArgs& a, uint32_t task, uint32_t part, double* lds) {
   if constexpr (FAM == FAM_CHOL)
     run_part_chol(a, task, part, lds);
-  else
+  else if constexpr (FAM == FAM_GEMM)
     run_part_gemm(a, task, part, lds);
+  else
+    run_part_spin(a, task, part, lds);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -1745,10 +1758,25 @@ __global__ __launch_bounds__(NT) void sched_kernel(SchedArgs a) {
             a.trace[4 * k + 3] = te;
           }
         }
+      }
+    }
+    // One release for all the parts of this claim (a release writes back the XCD's L2,
+    // about 25 us per call, so a claim of several bulk parts pays it once), then their
+    // parts-left decrements; the tasks they finish take one acquire and one release before
+    // their successors' pending counters are decremented.
+    if (tid == 0) {
+      fence_rel();
+      uint32_t done[kClaim];
+      int nd = 0;
+      for (int i = 0; i < n; ++i) {
+        const uint32_t task = (uint32_t)(s_items[i] >> 16);
+        if (sub_rlx(a.parts_left + task, 1u) == 1u) done[nd++] = task;
+      }
+      if (nd > 0) {
+        fence_acq();
         fence_rel();
-        if (sub_rlx(a.parts_left + task, 1u) == 1u) {
-          fence_acq();
-          fence_rel();
+        for (int i = 0; i < nd; ++i) {
+          const uint32_t task = done[i];
           for (uint32_t e = a.succ_off[task]; e < a.succ_off[task + 1]; ++e) {
             const uint32_t s = a.succ[e];
             if (sub_rlx(a.pending + s, 1u) == 1u) push_task(a, s, home);
@@ -2190,6 +2218,8 @@ int launch_one_task(const SchedArgs& a, int nparts, void* stream) {
 int launch_sched(const SchedArgs& a, int num_wg, void* stream, int family) {
   if (family == FAM_GEMM)
     hipLaunchKernelGGL(sched_kernel<FAM_GEMM>, dim3(num_wg), dim3(NT), 0, (hipStream_t)stream, a);
+  else if (family == FAM_SPIN)
+    hipLaunchKernelGGL(sched_kernel<FAM_SPIN>, dim3(num_wg), dim3(NT), 0, (hipStream_t)stream, a);
   else
     hipLaunchKernelGGL(sched_kernel<FAM_CHOL>, dim3(num_wg), dim3(NT), 0, (hipStream_t)stream, a);
   return hip_ok(hipGetLastError(), "sched_kernel");

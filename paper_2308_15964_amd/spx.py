@@ -18,7 +18,7 @@ T_POTRF, T_TRSM, T_SYRK, T_GEMM, T_FTRSM, T_FGEMM, T_BTRSM, T_BGEMM, T_LOAD, T_S
 TASK_NAMES = ["POTRF", "TRSM", "SYRK", "GEMM", "FTRSM", "FGEMM", "BTRSM", "BGEMM", "LOAD", "STORE", "INV"]
 TILE_CANDIDATES = [32, 64, 128, 256, 512]
 PREC_FP64, PREC_FP32, PREC_BF16 = 0, 1, 2
-Q_PRIORITY, Q_FIFO = 0, 1
+Q_PRIORITY, Q_FIFO, Q_SHARDED = 0, 1, 2
 F_TRACE, F_SCALED = 1, 2
 
 
@@ -95,7 +95,7 @@ EXPORTS = [
     "spx_last_error", "spx_ctx_create", "spx_ctx_destroy", "spx_graph_build", "spx_graph_info", "spx_graph_edges",
     "spx_graph_indegree", "spx_graph_to_dot", "spx_graph_destroy", "spx_cholesky_graph", "spx_gemm_graph",
     "spx_potrf_tiled",
-    "spx_factor_info", "spx_factor_get_l", "spx_factor_destroy", "spx_gemm_tiled", "spx_potrs", "spx_potrs_noalloc",
+    "spx_factor_info", "spx_factor_get_l", "spx_factor_destroy", "spx_gemm_tiled", "spx_run_graph", "spx_potrs", "spx_potrs_noalloc",
     "spx_backward_error",
     "spx_run_task", "spx_posv_batched", "spx_potrf_batched", "spx_potrs_batched", "spx_backward_error_batched",
     "spx_set_tile_table", "spx_tile_for",
@@ -132,6 +132,7 @@ def lib():
         "spx_graph_indegree": (ctypes.c_int, [vp, P(u32), u32]),
         "spx_graph_to_dot": (ctypes.c_int, [vp, ctypes.c_char_p]),
         "spx_graph_destroy": (None, [vp]),
+        "spx_run_graph": (ctypes.c_int, [vp, vp, u64, P(Opts)]),
         "spx_cholesky_graph": (ctypes.c_int, [i32, i32, P(vp), P(i32), u32]),
         "spx_gemm_graph": (ctypes.c_int, [i32, P(vp), P(i32), u32]),
         "spx_potrf_tiled": (ctypes.c_int, [vp, i64, vp, i64, P(Opts), P(vp), P(i64)]),
@@ -357,7 +358,14 @@ class Context:
             return out, {"iters": st.iters, "method_used": st.method_used, "eta_max": st.eta_max}
         return out
 
-    def gemm(self, A, B, C, tile=0, queue_policy=Q_PRIORITY, num_wg=0, flags=0):
+    def run_graph(self, graph, spin_ticks, queue_policy=Q_SHARDED, num_wg=0, flags=0):
+        """Runs every task of graph as an empty task of spin_ticks device clock ticks
+        (100 MHz) with the graph's dependencies (spx_run_graph); returns the stats."""
+        o = Opts(0, PREC_FP64, queue_policy, num_wg, flags, 0, 0.0)
+        _check(lib().spx_run_graph(self._h, graph._h, int(spin_ticks), ctypes.byref(o)))
+        return self.stats()
+
+    def gemm(self, A, B, C, tile=0, queue_policy=Q_SHARDED, num_wg=0, flags=0):
         """C <- C + A B in place (spx_gemm_tiled); returns C."""
         for t, nm in ((A, "A"), (B, "B"), (C, "C")):
             self._dev(t, nm)

@@ -127,7 +127,8 @@ def test_schedules_bitwise_identical(ctx):
     A, B = inputs.gram_spd(1024, seed=9, nrhs=2)
     Ad, Bd = dev(A), dev(B)
     ref_L = ref_X = None
-    for policy, nwg in [(spx.Q_PRIORITY, 0), (spx.Q_FIFO, 0), (spx.Q_PRIORITY, 7), (spx.Q_FIFO, 1), (spx.Q_PRIORITY, 61)]:
+    for policy, nwg in [(spx.Q_PRIORITY, 0), (spx.Q_FIFO, 0), (spx.Q_PRIORITY, 7), (spx.Q_FIFO, 1), (spx.Q_PRIORITY, 61),
+                        (spx.Q_SHARDED, 0), (spx.Q_SHARDED, 13)]:
         F = ctx.potrf(Ad, tile=128, queue_policy=policy, num_wg=nwg)
         L = host(F.L())
         X = host(ctx.potrs(F, Bd))
@@ -217,7 +218,7 @@ def test_potrf_steps_schedules_bitwise_identical(ctx):
     A, B = inputs.gram_spd(1024, seed=19, nrhs=1)
     Ad, Bd = dev(A), dev(B)
     ref = None
-    for policy, nwg in [(spx.Q_PRIORITY, 0), (spx.Q_FIFO, 0), (spx.Q_PRIORITY, 3), (spx.Q_FIFO, 1)]:
+    for policy, nwg in [(spx.Q_PRIORITY, 0), (spx.Q_FIFO, 0), (spx.Q_PRIORITY, 3), (spx.Q_FIFO, 1), (spx.Q_SHARDED, 0)]:
         F = ctx.potrf(Ad, tile=256, queue_policy=policy, num_wg=nwg)
         L = host(F.L())
         if ref is None:

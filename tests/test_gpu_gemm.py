@@ -79,7 +79,7 @@ def test_gemm_schedules_bitwise_identical(ctx):
     A, B, C = rs.standard_normal((3, n, n))
     Ad, Bd = dev(A), dev(B)
     ref = None
-    for policy, nwg in [(spx.Q_PRIORITY, 0), (spx.Q_FIFO, 0), (spx.Q_PRIORITY, 5), (spx.Q_FIFO, 1)]:
+    for policy, nwg in [(spx.Q_PRIORITY, 0), (spx.Q_FIFO, 0), (spx.Q_PRIORITY, 5), (spx.Q_FIFO, 1), (spx.Q_SHARDED, 0)]:
         Cd = dev(C)
         ctx.gemm(Ad, Bd, Cd, tile=128, queue_policy=policy, num_wg=nwg)
         got = Cd.cpu().numpy()

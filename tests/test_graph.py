@@ -227,3 +227,18 @@ def test_gemm_graph_matches_oracle(nt):
     assert np.array_equal(g.edges(), e)
     assert (g.task_types == spx.SPX_T_MGEMM).all() if hasattr(spx, "SPX_T_MGEMM") else (g.task_types == 11).all()
     g.close()
+
+
+@pytest.mark.parametrize("T,N,d", [(1, 5, 1), (3, 4, 2), (4, 6, 5)])
+def test_overhead_pattern_graph(T, N, d):
+    """The overhead study's program (Specx Sec. 5.1): T chains of N tasks, each writing the
+    d data of its chain: T (N - 1) write-after-write edges whatever d is, as the pairwise
+    definition gives."""
+    acc = [(s * T + t, 2, t * d + q) for s in range(N) for t in range(T) for q in range(d)]
+    g = spx.Graph.build(T * N, acc)
+    e = g.edges()
+    want, kinds = oracle.dag_edges(T * N, acc)
+    assert np.array_equal(e, want)
+    assert len(e) == T * (N - 1) and kinds["WAW"] == T * (N - 1) and kinds["RAW"] == 0 and kinds["WAR"] == 0
+    assert all(b - a == T for a, b in e.tolist())
+    g.close()
