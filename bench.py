@@ -86,7 +86,7 @@ def parse():
     p.add_argument("--serve-requests", type=int, default=4000)
     p.add_argument("--serve-rate", type=float, default=2000.0)
     p.add_argument("--serve-lanes", type=int, default=2)
-    p.add_argument("--policy", choices=("priority", "fifo", "sharded"), default="priority",
+    p.add_argument("--policy", choices=("priority", "fifo", "sharded"), default="sharded",
                    help="ready-queue policy of the factor and solve launches")
     p.add_argument("--chain-trace", action="store_true",
                    help="trace one factor and one solve launch (--n, --tile) and print their critical paths")
@@ -111,27 +111,121 @@ def gen_input(n, seed, nrhs, device):
     return A, Bd
 
 
-def cpu_baseline(A_host, n, tile):
-    """The oracle (thread-pool executor over the same task graph) on a bounded sample:
-    the first block-column step k = 0 of the factor graph (POTRF(0), every TRSM(i,0),
-    SYRK(i,0) and GEMM(i,j,0))."""
-    import numpy as np
+def host_cpu():
+    """(cores this process may run on, CPU model name)."""
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        cores = os.cpu_count() or 1
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return cores, model
 
+
+def cpu_baseline(A_host, n, tile, steps=3):
+    """The oracle (thread-pool executor over the same task graph) on a bounded sample of the
+    headline factorization: its first `steps` block-column steps (POTRF(k), every TRSM(i,k),
+    SYRK(i,k) and GEMM(i,j,k) for k < steps, a prefix of the insertion order closed under
+    predecessors), on every host core this process may use; plus the sequential oracle on
+    one core for the N = 1024, tile 128 factorization and solve."""
     import oracle
+    from paper_2308_15964_amd import inputs
 
     nt = n // tile
     tasks, _ = oracle.cholesky_program(nt)
-    limit = sum(1 for t in tasks if t[3] == 0)
+    limit = sum(1 for t in tasks if t[3] < steps)
     b3 = float(tile) ** 3
     flops = {"POTRF": b3 / 3, "TRSM": b3, "SYRK": b3, "GEMM": 2 * b3}
     sample_flop = sum(flops[t[0]] for t in tasks[:limit])
-    cores = min(os.cpu_count() or 1, 16)
+    cores, model = host_cpu()
     t0 = time.perf_counter()
     oracle.cholesky(A_host, tile, nthreads=cores, limit=limit)
     dt = time.perf_counter() - t0
+    # the same graph's first 64 tasks in insertion order on one core
+    lim1 = 64
+    flop1 = sum(flops[t[0]] for t in tasks[:lim1])
+    t2 = time.perf_counter()
+    oracle.cholesky(A_host, tile, nthreads=1, limit=lim1)
+    dt2 = time.perf_counter() - t2
+    A1, b1 = inputs.lower_plus_shift(1024, seed=1)
+    t1 = time.perf_counter()
+    oracle.cholesky(A1, 128, b1)
+    dt1 = time.perf_counter() - t1
     return {"value": sample_flop / dt / 1e12, "unit": "TFLOP/s", "cores": cores, "kind": "oracle",
-            "sample": f"first block-column step (k=0) of the N={n} tile-{tile} factor graph: {limit} tasks, "
-                      f"{sample_flop:.3e} flop, {dt:.1f} s on {cores} host threads"}
+            "cpu_model": model,
+            "sample": f"first {steps} block-column steps (k < {steps}) of the N={n} tile-{tile} factor graph: "
+                      f"{limit} tasks, {sample_flop:.3e} flop, {dt:.1f} s on {cores} host threads ({model})",
+            "one_core": {"workload": "N=1024, tile 128, factor + 1-RHS solve, sequential oracle on 1 core",
+                         "ms": round(dt1 * 1e3, 1),
+                         "tflops": round((1024 ** 3 / 3 + 2 * 1024 ** 2) / dt1 / 1e12, 5)},
+            "one_core_headline_sample": {
+                "workload": f"first {lim1} tasks (insertion order) of the N={n} tile-{tile} factor graph, "
+                            f"sequential oracle on 1 core",
+                "s": round(dt2, 2), "flop": flop1, "tflops": round(flop1 / dt2 / 1e12, 5)}}
+
+
+def bench_config1(ctx, reps=20):
+    """N = 1024, tile 128 (8x8 tiles, 120 factor tasks), A = L0 L0^T + N I, one right-hand
+    side: latency of the factor launch, the solve launch and the whole call pair."""
+    import numpy as np
+    import torch
+
+    from paper_2308_15964_amd import inputs
+
+    A, b = inputs.lower_plus_shift(1024, seed=1)
+    Ad = torch.from_numpy(A).cuda()
+    bd = torch.from_numpy(b).cuda()
+    fk, sk, wall = [], [], []
+    for r in range(reps + 3):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        F = ctx.potrf(Ad, tile=128)
+        fs = ctx.stats()["kernel_ms"]
+        ctx.potrs(F, bd)
+        ss = ctx.stats()["kernel_ms"]
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        F.close()
+        if r >= 3:
+            fk.append(fs)
+            sk.append(ss)
+            wall.append(dt)
+    return {"workload": "N=1024, tile 128, A = L0 L0^T + N I, 1 RHS",
+            "factor_kernel_us": round(float(np.median(fk)) * 1e3, 1),
+            "solve_kernel_us": round(float(np.median(sk)) * 1e3, 1),
+            "call_pair_us_p50": round(float(np.median(wall)) * 1e6, 1),
+            "call_pair_us_p99": round(float(np.percentile(wall, 99)) * 1e6, 1)}
+
+
+def haar_spd(n, kappa, seed, nrhs, device):
+    """A = Q diag(s) Q^T with Q Haar-distributed: the QR factor of a seeded Gaussian
+    matrix with the signs of diag(R) folded in (Mezzadri), formed on the device off the
+    clock; s log-uniform on [1, kappa] with both endpoints present; B iid N(0,1)."""
+    import numpy as np
+    import torch
+
+    from paper_2308_15964_amd import inputs
+
+    g = np.random.default_rng(seed)
+    s = torch.from_numpy(inputs.log_spectrum(n, kappa, g)).to(device)
+    tg = torch.Generator(device=device).manual_seed(seed)
+    Q = torch.randn((n, n), dtype=torch.float64, device=device, generator=tg)
+    Q, R = torch.linalg.qr(Q)
+    Q *= torch.sign(torch.diagonal(R))[None, :]
+    del R
+    A = (Q * s[None, :]) @ Q.T.contiguous()
+    del Q
+    A = ((A + A.T) / 2).contiguous()
+    B = torch.from_numpy(g.standard_normal((n, nrhs))).to(device)
+    torch.cuda.synchronize()
+    return A, B
 
 
 def orthogonal_spd(n, kappa, seed, nrhs, device, k=16):
@@ -164,10 +258,13 @@ def bench_mixed(ctx, n, tile=512, nrhs=16, kappa=1e4, seed=3):
 
     from paper_2308_15964_amd import spx
 
-    A, B = orthogonal_spd(n, kappa, seed, nrhs, "cuda:0")
+    t0 = time.perf_counter()
+    A, B = haar_spd(n, kappa, seed, nrhs, "cuda:0")
+    gen_s = time.perf_counter() - t0
     flop = n ** 3 / 3.0
-    res = {"workload": f"N={n}, tile {tile}, {nrhs} RHS, A = Q diag(s) Q^T (Q: 16 Householder reflectors), "
-                       f"s log-uniform on [1, {kappa:g}], tol 1e-12"}
+    res = {"workload": f"N={n}, tile {tile}, {nrhs} RHS, A = Q diag(s) Q^T (Q Haar: QR of a seeded Gaussian, "
+                       f"signs fixed), s log-uniform on [1, {kappa:g}], tol 1e-12",
+           "input_generation_s": round(gen_s, 1)}
 
     def run(prec, method, shift=None):
         torch.cuda.synchronize()
@@ -234,8 +331,15 @@ def bench_batched(ctx, count, seed=7):
     os.makedirs(os.path.dirname(cache), exist_ok=True)
     res = {"workload": f"{count} matrices, N uniform in [32, 512], 1-8 RHS, A = G G^T/N + I, one launch",
            "sum_flop": flop, "sum_bytes_min": bytes_min}
-    for prec, name in ((spx.PREC_FP64, "fp64"), (spx.PREC_FP32, "fp32_updates")):
-        entry = autotune.ensure(ctx, prec, cache)
+    # the FP32-update run forces at least two tiles per matrix (tile = the power of two
+    # below N), so every matrix has SYRK/GEMM updates that run in FP32
+    forced = [(64, 32), (128, 64), (256, 128), (512, 256)]
+    for prec, name in ((spx.PREC_FP64, "fp64"), (spx.PREC_FP32, "fp32_updates_two_plus_tiles")):
+        if prec == spx.PREC_FP32:
+            ctx.set_tile_table(prec, forced)
+            entry = {"table": forced}
+        else:
+            entry = autotune.ensure(ctx, prec, cache)
         Xs, info = ctx.posv_batched(As, Bs, update_prec=prec)
         kms = []
         for _ in range(3):
@@ -527,6 +631,7 @@ def main():
         A_host = A.cpu().numpy()
         out["cpu_baseline"] = cpu_baseline(A_host, n, b)
         del A_host
+    out["config1"] = bench_config1(ctx)
     del A, B, X
     torch.cuda.empty_cache()
     if not args.skip_mixed:

@@ -137,11 +137,15 @@ int spx_gemm_graph(int32_t nt, spx_graph** out, int32_t* task_types, uint32_t ca
  *   update_prec: SPX_PREC_FP64 (all tasks FP64), SPX_PREC_FP32 or SPX_PREC_BF16 (SYRK and
  *     GEMM read FP32 / BF16 copies of the panel tiles and accumulate in FP32 on the matrix
  *     cores; POTRF and TRSM stay FP64; the factor is stored in FP64).
- *   queue_policy: SPX_Q_PRIORITY (panel tasks and the next block column first),
- *     SPX_Q_FIFO (one ready queue in push order) or SPX_Q_SHARDED (the priority levels,
- *     each split into 8 ready queues; a workgroup serves the shard of its own XCD-sized
- *     group first, so pops of many small tasks do not serialise on one queue head; the
- *     global push order within a level is lost).  Results are bitwise identical.
+ *   queue_policy: the ready queues.  Tasks carry upward-rank priorities (the longest
+ *     chain of work from the task to the end of the graph): the panel chain first, then
+ *     the updates by how soon their tile is consumed.  SPX_Q_SHARDED (the default, 0):
+ *     four priority levels, each split into 8 queues, one per XCD; a task is pushed into
+ *     the queue of the XCD that released its last predecessor, and a workgroup serves its
+ *     own XCD's queue first, so pops spread over 8 queue heads.  SPX_Q_PRIORITY: sixteen
+ *     levels, one queue each (exact push order within a level; every pop contends for one
+ *     queue head, which limits pops to about one per microsecond).  SPX_Q_FIFO: one queue
+ *     in push order.  Results are bitwise identical under every policy.
  *   num_wg: persistent workgroups (0 = fill the GPU).
  *   flags: SPX_F_TRACE records per-task device timestamps (spx_trace).
  *     SPX_F_SCALED factors D^{-1/2} A D^{-1/2} + shift I instead of A (D = diag(A)):
@@ -150,7 +154,7 @@ int spx_gemm_graph(int32_t nt, spx_graph** out, int32_t* task_types, uint32_t ca
  *     returns the factor of the scaled, shifted matrix.  Single-matrix calls only.
  * ------------------------------------------------------------------------------------ */
 enum { SPX_PREC_FP64 = 0, SPX_PREC_FP32 = 1, SPX_PREC_BF16 = 2 };
-enum { SPX_Q_PRIORITY = 0, SPX_Q_FIFO = 1, SPX_Q_SHARDED = 2 };
+enum { SPX_Q_SHARDED = 0, SPX_Q_PRIORITY = 1, SPX_Q_FIFO = 2 };
 enum { SPX_F_TRACE = 1u, SPX_F_SCALED = 2u };
 typedef struct {
   int32_t tile;
@@ -430,6 +434,12 @@ int spx_ctx_set_flags(spx_ctx* ctx, uint32_t flags);
  * {task, part | (workgroup << 16), start tick, end tick} (device wall clock, 100 MHz).
  * Returns the record count (or < 0); writes at most cap records. */
 int64_t spx_trace(const spx_ctx* ctx, uint64_t* rec, int64_t cap);
+/* Push ticks of the same launch: ticks[t] = the device clock when task t's last
+ * predecessor pushed it into a ready queue (0 for the graph's roots, pushed before the
+ * launch).  With spx_trace it splits a task's wait into the scheduler's completion
+ * handling (end of the last predecessor to push) and the queueing (push to first start).
+ * Returns the task count (or < 0); writes at most cap ticks. */
+int64_t spx_trace_push(const spx_ctx* ctx, uint64_t* ticks, int64_t cap);
 
 #ifdef __cplusplus
 }

@@ -286,31 +286,53 @@ void solve_io_program(int nt, std::vector<TaskDesc>& tasks, std::vector<spx_acce
   for (int k = 0; k < nt; ++k) acc.push_back(spx_access{t, SPX_ACC_R, B(k)});
 }
 
-// Default Cholesky priorities (larger = sooner): the panel chain POTRF -> TRSM -> SYRK and
-// the GEMMs that feed the next block column sit on the critical path, as do the diagonal
-// solves and the update of the next block in the substitution; among equals the earlier
-// step k goes first.
-int32_t cholesky_priority(const TaskDesc& d, int nt) {
-  int32_t base;
+// Estimated latency of a task (parts in parallel), in units of one 512-tile update; only
+// the ratios matter.  A step of a split POTRF is one of its b/32 column steps.
+static double task_cost(const TaskDesc& d) {
   switch (d.type) {
-    case SPX_T_POTRF: base = 4; break;
-    case SPX_T_TRSM: base = 3; break;
-    case SPX_T_SYRK: base = (d.i == d.k + 1) ? 3 : 1; break;
-    // updates of the next panel column first, then of the one after it: the last updates
-    // of tile (k+2, k+1) gate TRSM(k+2, k+1) on the critical path
-    case SPX_T_GEMM: base = (d.j == d.k + 1) ? 2 : (d.j == d.k + 2 ? 1 : 0); break;
-    case SPX_T_LOAD: base = 0; break;   // a new matrix starts when nothing urgent is ready
-    case SPX_T_STORE: base = 4; break;
-    // substitution: the diagonal solves and the update of the next block form the chain
+    case SPX_T_POTRF: return (d.pad >> 8) ? 0.3 : 3.0;
+    case SPX_T_TRSM: return 1.2;
+    case SPX_T_SYRK:
+    case SPX_T_GEMM:
+    case SPX_T_INV:
+    case SPX_T_MGEMM: return 1.0;
+    case SPX_T_FGEMM:
+    case SPX_T_BGEMM: return 0.3;
     case SPX_T_FTRSM:
-    case SPX_T_BTRSM: base = 4; break;
-    case SPX_T_FGEMM: base = (d.i == d.k + 1) ? 3 : 1; break;
-    case SPX_T_INV: base = 1; break;  // off the factor's critical path, needed by the solve
-    case SPX_T_BGEMM: base = (d.i + 1 == d.k) ? 3 : 1; break;
-    case SPX_T_MGEMM: base = 0; break;  // one bulk level: several parts per claim
-    default: base = 3; break;
+    case SPX_T_BTRSM: return 0.15;
+    default: return 0.2;
   }
-  return base * 65536 + (nt - d.k);
+}
+
+// Default priorities of the library's programs (larger = sooner): the upward rank, i.e.
+// the task's own latency plus the longest chain of latencies from it to the end of the
+// graph, so that among the ready tasks the one with the most work still chained behind it
+// runs first.  In the tile Cholesky this puts the panel chain first, then the updates by
+// how soon their tile is consumed, and an early update of a tile that still has a long
+// chain of updates ahead of it (the last diagonal tiles) before a late one of a short
+// chain.  The class (priority >> 16, 0..63) grows linearly with the rank; the low bits
+// keep the finer rank.  Two exceptions take class 0: LOAD (a new matrix of a batch starts
+// when nothing urgent is ready) and the tiled product's updates (one bulk class: its
+// chains are all alike, and bulk levels hand out several parts per claim).  Edges run
+// from earlier to later tasks, so one pass in reverse insertion order computes every rank.
+void rank_priorities(const std::vector<TaskDesc>& tasks, Graph& g) {
+  const uint32_t T = g.ntasks;
+  std::vector<double> r(T, 0.0);
+  double mx = 0.0;
+  for (uint32_t t = T; t-- > 0;) {
+    double m = 0.0;
+    for (uint64_t q = g.off[t]; q < g.off[t + 1]; ++q) m = std::max(m, r[g.succ[q]]);
+    r[t] = task_cost(tasks[t]) + m;
+    mx = std::max(mx, r[t]);
+  }
+  g.prio.assign(T, 0);
+  if (mx <= 0.0) return;
+  for (uint32_t t = 0; t < T; ++t) {
+    const double f = r[t] / mx;  // (0, 1]
+    const bool bulk = tasks[t].type == SPX_T_LOAD || tasks[t].type == SPX_T_MGEMM;
+    const int cls = bulk ? 0 : std::min(kMaxLevels - 1, (int)(f * kMaxLevels));
+    g.prio[t] = cls * 65536 + std::min(65535, (int)(f * 65535.0));
+  }
 }
 
 }  // namespace spx
@@ -370,7 +392,8 @@ int spx_graph_to_dot(const spx_graph* g, const char* path) {
   for (uint32_t t = 0; t < g->g.ntasks; ++t) {
     if (t < g->tasks.size()) {
       const TaskDesc& d = g->tasks[t];
-      std::fprintf(f, "  t%u [label=\"%s(%d,%d,%d)\"];\n", t, d.type < 13 ? names[d.type] : "?", d.i, d.j, d.k);
+      std::fprintf(f, "  t%u [label=\"%s(%d,%d,%d) p%d\"];\n", t, d.type < 13 ? names[d.type] : "?", d.i, d.j, d.k,
+                   g->g.prio[t]);
     } else {
       std::fprintf(f, "  t%u [label=\"t%u p%d\"];\n", t, t, g->g.prio[t]);
     }
@@ -397,10 +420,9 @@ int spx_cholesky_graph(int32_t nt, int32_t with_solve, spx_graph** out, int32_t*
       io_program(nt, (with_solve & 1) != 0, g->tasks, acc, (with_solve & 4) != 0, steps);
     else
       cholesky_program(nt, (with_solve & 1) != 0, g->tasks, acc, (with_solve & 4) != 0, steps);
-    std::vector<int32_t> prio(g->tasks.size());
-    for (size_t t = 0; t < g->tasks.size(); ++t) prio[t] = cholesky_priority(g->tasks[t], nt);
-    int rc = build_graph((uint32_t)g->tasks.size(), acc.data(), acc.size(), prio.data(), g->g);
+    int rc = build_graph((uint32_t)g->tasks.size(), acc.data(), acc.size(), nullptr, g->g);
     if (rc) return rc;
+    rank_priorities(g->tasks, g->g);
     if (task_types) {
       if (cap < g->tasks.size()) return fail(SPX_EINVAL, "spx_cholesky_graph: capacity too small");
       for (size_t t = 0; t < g->tasks.size(); ++t) task_types[t] = g->tasks[t].type;
@@ -419,10 +441,9 @@ int spx_gemm_graph(int32_t nt, spx_graph** out, int32_t* task_types, uint32_t ca
     std::unique_ptr<spx_graph> g(new spx_graph());
     std::vector<spx_access> acc;
     gemm_program(nt, g->tasks, acc);
-    std::vector<int32_t> prio(g->tasks.size());
-    for (size_t t = 0; t < g->tasks.size(); ++t) prio[t] = cholesky_priority(g->tasks[t], nt);
-    int rc = build_graph((uint32_t)g->tasks.size(), acc.data(), acc.size(), prio.data(), g->g);
+    int rc = build_graph((uint32_t)g->tasks.size(), acc.data(), acc.size(), nullptr, g->g);
     if (rc) return rc;
+    rank_priorities(g->tasks, g->g);
     if (task_types) {
       if (cap < g->tasks.size()) return fail(SPX_EINVAL, "spx_gemm_graph: capacity too small");
       for (size_t t = 0; t < g->tasks.size(); ++t) task_types[t] = g->tasks[t].type;

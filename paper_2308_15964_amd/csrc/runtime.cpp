@@ -56,8 +56,8 @@ struct Image {
   uint32_t ntasks = 0, total_parts = 0;
   int nlev = 1;
   int family = FAM_CHOL;  // the scheduler instantiation that runs its tasks
-  uint32_t qbase[kMaxLevels] = {};
-  uint32_t qcap[kMaxLevels] = {};
+  uint32_t qbase[kLevels1] = {};
+  uint32_t qcap[kLevels1] = {};
   uint32_t nroots = 0;
   int nshards = 1;
   void* block = nullptr;  // one allocation for every array below
@@ -73,6 +73,7 @@ struct Image {
   uint32_t* parts_left = nullptr;
   u64* queue = nullptr;
   uint32_t* counters = nullptr;
+  uint32_t* ring = nullptr;  // kXcds x total_parts finished-part entries
 };
 
 
@@ -117,6 +118,7 @@ struct spx_ctx {
   uint32_t* trace_idx = nullptr;
   size_t trace_cap = 0;  // parts
   int64_t trace_len = 0;
+  int64_t trace_tasks = 0;  // push ticks after the part records
   std::vector<u64> host_cycles;
   TaskDesc* dtask = nullptr;  // descriptor of single-task launches
   uint32_t flags = 0;         // SPX_F_TRACE: trace every launch (spx_ctx_set_flags)
@@ -177,9 +179,8 @@ static int get_program(spx_ctx* c, char kind, int nt, const Program** out, int p
     case 'M': gemm_program(nt, pr->tasks, acc); break;
     default: return fail(SPX_EINVAL, "unknown program kind");
   }
-  std::vector<int32_t> prio(pr->tasks.size());
-  for (size_t t = 0; t < pr->tasks.size(); ++t) prio[t] = cholesky_priority(pr->tasks[t], nt);
-  SPX_TRY(build_graph((uint32_t)pr->tasks.size(), acc.data(), acc.size(), prio.data(), pr->g));
+  SPX_TRY(build_graph((uint32_t)pr->tasks.size(), acc.data(), acc.size(), nullptr, pr->g));
+  rank_priorities(pr->tasks, pr->g);
   *out = pr.get();
   c->programs[key] = std::move(pr);
   return SPX_OK;
@@ -238,11 +239,12 @@ uint16_t parts_of(const TaskDesc& d, int b, int nrhs) {
   return 1;
 }
 
-static int level_of(int32_t prio, int policy) {
-  if (policy == SPX_Q_FIFO) return 0;
-  const int base = prio >> 16;
-  int l = 3 - base;
-  return l < 0 ? 0 : (l > kMaxLevels - 1 ? kMaxLevels - 1 : l);
+// Priority class (priority >> 16, clamped to 0..63, larger = sooner) -> queue level of an
+// image with nlev levels (level 0 is served first).
+static int level_of(int32_t prio, int nlev) {
+  int cls = prio >> 16;
+  cls = cls < 0 ? 0 : (cls > kMaxLevels - 1 ? kMaxLevels - 1 : cls);
+  return (kMaxLevels - 1 - cls) * nlev / kMaxLevels;
 }
 
 // kind 'F': factor (+ inversions); 'S': substitution alone (with the inverses); 'L': LOAD +
@@ -266,13 +268,13 @@ struct Piece {
 struct ImageHost {
   uint32_t ntasks = 0, total_parts = 0;
   int nlev = 1;
-  uint32_t qbase[kMaxLevels] = {};
-  uint32_t qcap[kMaxLevels] = {};
+  uint32_t qbase[kLevels1] = {};
+  uint32_t qcap[kLevels1] = {};
   uint32_t nroots = 0;
   int nshards = 1;
   std::vector<char> bytes;  // the static part (static_bytes)
   size_t o_tasks = 0, o_off = 0, o_succ = 0, o_indeg = 0, o_np = 0, o_q0 = 0, o_c0 = 0, static_bytes = 0;
-  size_t o_pend = 0, o_pl = 0, o_q = 0, o_c = 0, total_bytes = 0;
+  size_t o_pend = 0, o_pl = 0, o_q = 0, o_c = 0, o_ring = 0, total_bytes = 0;
 };
 
 // Lays out the concatenation of the pieces' graphs (no edges between pieces) as one image.
@@ -290,10 +292,10 @@ static int build_image_host(const std::vector<Piece>& pieces, int policy, ImageH
   const uint32_t T = (uint32_t)T64;
   const size_t E = (size_t)E64;
   im.ntasks = T;
-  im.nlev = policy == SPX_Q_FIFO ? 1 : kMaxLevels;
+  im.nlev = policy == SPX_Q_FIFO ? 1 : (nshards > 1 ? kMaxQueues / nshards : kLevels1);
   std::vector<TaskDesc> tasks(T);
   std::vector<uint32_t> off32(T + 1), succ(std::max<size_t>(E, 1)), indeg(T), nparts(T);
-  uint64_t per_level[kMaxLevels] = {};
+  uint64_t per_level[kLevels1] = {};
   uint32_t t0 = 0;
   size_t e0 = 0;
   for (const Piece& pc : pieces) {
@@ -301,7 +303,7 @@ static int build_image_host(const std::vector<Piece>& pieces, int policy, ImageH
     for (uint32_t t = 0; t < pr.g.ntasks; ++t) {
       TaskDesc d = pr.tasks[t];
       d.nparts = parts_of(d, pc.b, pc.nrhs);
-      d.level = (uint8_t)level_of(pr.g.prio[t], policy);
+      d.level = (uint8_t)level_of(pr.g.prio[t], im.nlev);
       d.mat = pc.mat;
       tasks[t0 + t] = d;
       nparts[t0 + t] = d.nparts;
@@ -315,11 +317,11 @@ static int build_image_host(const std::vector<Piece>& pieces, int policy, ImageH
   }
   off32[T] = (uint32_t)E;
   uint64_t total = 0;
-  for (int l = 0; l < kMaxLevels; ++l) total += per_level[l];
+  for (int l = 0; l < kLevels1; ++l) total += per_level[l];
   if (total * kShards >= (1ull << 32) - 1) return fail(SPX_EINVAL, "task graph too large");
   im.total_parts = (uint32_t)total;
-  for (int l = 0; l < kMaxLevels; ++l) im.qcap[l] = (uint32_t)per_level[l];
-  for (int l = 1; l < kMaxLevels; ++l) im.qbase[l] = im.qbase[l - 1] + im.qcap[l - 1];
+  for (int l = 0; l < kLevels1; ++l) im.qcap[l] = (uint32_t)per_level[l];
+  for (int l = 1; l < kLevels1; ++l) im.qbase[l] = im.qbase[l - 1] + im.qcap[l - 1];
   // root parts are dealt round-robin over the shards of their level
   std::vector<u64> roots;
   std::vector<uint32_t> counters0(kNumCounters, 0);
@@ -329,7 +331,7 @@ static int build_image_host(const std::vector<Piece>& pieces, int policy, ImageH
     const int l = tasks[t].level;
     for (uint32_t p = 0; p < nparts[t]; ++p) {
       const int sh = (int)(deal++ % nshards);
-      uint32_t& tail = counters0[ctr_tail_idx(l, sh)];
+      uint32_t& tail = counters0[ctr_queue_idx(l * nshards + sh) + 1];  // the high half of the word
       roots.push_back((u64)im.qbase[l] * kShards + (u64)sh * im.qcap[l] + tail);
       roots.push_back(((u64)t << 16) | p);
       ++tail;
@@ -353,6 +355,7 @@ static int build_image_host(const std::vector<Piece>& pieces, int policy, ImageH
   im.o_pl = o; o = align(o + 4 * (size_t)T);
   im.o_q = o; o = align(o + 8 * (size_t)im.total_parts * kShards);
   im.o_c = o; o = align(o + 4 * (size_t)kNumCounters);
+  im.o_ring = o; o = align(o + 4 * (size_t)kXcds * im.total_parts);
   im.total_bytes = o;
   im.bytes.assign(im.static_bytes, 0);
   char* h = im.bytes.data();
@@ -371,7 +374,7 @@ static void bind_image(const ImageHost& h, char* base, Image* im) {
   im->ntasks = h.ntasks;
   im->total_parts = h.total_parts;
   im->nlev = h.nlev;
-  for (int l = 0; l < kMaxLevels; ++l) {
+  for (int l = 0; l < kLevels1; ++l) {
     im->qbase[l] = h.qbase[l];
     im->qcap[l] = h.qcap[l];
   }
@@ -389,6 +392,7 @@ static void bind_image(const ImageHost& h, char* base, Image* im) {
   im->parts_left = (uint32_t*)(base + h.o_pl);
   im->queue = (u64*)(base + h.o_q);
   im->counters = (uint32_t*)(base + h.o_c);
+  im->ring = (uint32_t*)(base + h.o_ring);
 }
 
 // Uploads the concatenation of the pieces' graphs (no edges between pieces) as one
@@ -430,7 +434,7 @@ static int get_image(spx_ctx* c, bool solve, int nt, int b, int nrhs, int policy
   return SPX_OK;
 }
 
-static int ensure_small_buffers(spx_ctx* c, size_t nmats, size_t num_wg, size_t parts, bool trace) {
+static int ensure_small_buffers(spx_ctx* c, size_t nmats, size_t num_wg, size_t parts, bool trace, size_t tasks = 0) {
   if (nmats > c->dmats_cap) {
     dev_free(c, c->dmats);
     dev_free(c, c->dinfo);
@@ -456,13 +460,14 @@ static int ensure_small_buffers(spx_ctx* c, size_t nmats, size_t num_wg, size_t 
     if (!c->wg_cycles) return fail(SPX_ENOMEM, "context buffers: allocation failed");
     c->wg_cap = num_wg;
   }
-  if (trace && parts > c->trace_cap) {
+  // four words per part, then one push tick per task
+  if (trace && 4 * parts + tasks > 4 * c->trace_cap) {
     dev_free(c, c->trace);
     dev_free(c, c->trace_idx);
-    c->trace = (u64*)dev_alloc(c, 32 * parts);
+    c->trace = (u64*)dev_alloc(c, 32 * parts + 8 * tasks);
     c->trace_idx = (uint32_t*)dev_alloc(c, 256);
     if (!c->trace || !c->trace_idx) return fail(SPX_ENOMEM, "trace buffer: allocation failed");
-    c->trace_cap = parts;
+    c->trace_cap = parts + (tasks + 3) / 4;
   }
   return SPX_OK;
 }
@@ -473,12 +478,13 @@ static int run_image(spx_ctx* c, Image* im, int nmats, const spx_opts* o, double
   const bool trace = (o && (o->flags & SPX_F_TRACE)) || (c->flags & SPX_F_TRACE);
   int num_wg = (o && o->num_wg > 0) ? o->num_wg : c->num_cu * c->wg_per_cu;
   if (num_wg < 1) num_wg = 1;
-  SPX_TRY(ensure_small_buffers(c, nmats, num_wg, im->total_parts, trace));
+  SPX_TRY(ensure_small_buffers(c, nmats, num_wg, im->total_parts, trace, im->ntasks));
   SPX_TRY(hipc(hipMemcpyAsync(c->dmats, c->hmats, sizeof(DevMat) * nmats, hipMemcpyHostToDevice, c->stream),
                "descriptor upload"));
   SPX_TRY(launch_sched_init_full(im->pending, im->indeg, im->parts_left, im->nparts, im->ntasks, im->queue,
                                  im->total_parts * kShards, im->roots, im->nroots, im->counters, im->counters0,
-                                 kNumCounters, c->dinfo, nmats, trace ? c->trace_idx : nullptr, c->stream));
+                                 kNumCounters, im->ring, kXcds * im->total_parts, c->dinfo, nmats,
+                                 trace ? c->trace_idx : nullptr, c->stream));
   SchedArgs a{};
   a.tasks = im->tasks;
   a.succ_off = im->succ_off;
@@ -487,7 +493,9 @@ static int run_image(spx_ctx* c, Image* im, int nmats, const spx_opts* o, double
   a.parts_left = im->parts_left;
   a.queue = im->queue;
   a.counters = im->counters;
-  for (int l = 0; l < kMaxLevels; ++l) {
+  a.ring = im->ring;
+  a.ring_cap = im->total_parts;
+  for (int l = 0; l < kLevels1; ++l) {
     a.qbase[l] = im->qbase[l];
     a.qcap[l] = im->qcap[l];
   }
@@ -498,6 +506,7 @@ static int run_image(spx_ctx* c, Image* im, int nmats, const spx_opts* o, double
   a.mats = c->dmats;
   a.trace = trace ? c->trace : nullptr;
   a.trace_idx = trace ? c->trace_idx : nullptr;
+  a.trace_push = trace ? c->trace + 4 * (size_t)im->total_parts : nullptr;
   a.wg_cycles = c->wg_cycles;
   a.spin_limit = 100000000ull * 20;  // 20 s of the 100 MHz device clock without progress
   SPX_TRY(hipc(hipEventRecord(c->ev[0], c->stream), "hipEventRecord"));
@@ -525,10 +534,10 @@ static int run_image(spx_ctx* c, Image* im, int nmats, const spx_opts* o, double
   c->last.nparts = im->total_parts;
   c->last.num_wg = (uint32_t)num_wg;
   c->trace_len = trace ? im->total_parts : 0;
+  c->trace_tasks = trace ? im->ntasks : 0;
   const uint32_t status = c->hcounters[kStatusIdx];
   uint64_t done = 0;  // parts taken from the queues; a normal exit means all of them ran
-  for (int l = 0; l < kMaxLevels; ++l)
-    for (int sh = 0; sh < kShards; ++sh) done += c->hcounters[ctr_head_idx(l, sh)];
+  for (int q = 0; q < kMaxQueues; ++q) done += c->hcounters[ctr_queue_idx(q)];
   if (status & STATUS_TIMEOUT)
     return failf(SPX_ETIMEOUT, "device scheduler made no progress (%llu of %u parts started)",
                  (unsigned long long)done, im->total_parts);
@@ -590,7 +599,7 @@ static int batched_solve(spx_ctx* c, const std::vector<int>& idx, const spx_fact
     key += "," + std::to_string(g->nt) + "/" + std::to_string(g->b) + "/" + std::to_string((q[idx[j]] + 7) / 8);
   }
   Image* im = nullptr;
-  SPX_TRY(get_batch_image(c, key, pieces, SPX_Q_PRIORITY, &im));
+  SPX_TRY(get_batch_image(c, key, pieces, SPX_Q_SHARDED, &im));
   SPX_TRY(ensure_small_buffers(c, K, 1, 0, false));
   char* block = (char*)dev_alloc(c, ws);
   if (!block) return fail(SPX_ENOMEM, "batched solve: workspace allocation failed");
@@ -695,7 +704,7 @@ static int batched(spx_ctx* c, int count, const int64_t* n, const double* const*
   const int prec = o ? o->update_prec : SPX_PREC_FP64;
   if (prec != SPX_PREC_FP64 && prec != SPX_PREC_FP32 && prec != SPX_PREC_BF16)
     return failf(SPX_EINVAL, "%s: bad update precision", who);
-  const int policy = o ? o->queue_policy : SPX_Q_PRIORITY;
+  const int policy = o ? o->queue_policy : SPX_Q_SHARDED;
   if (policy != SPX_Q_PRIORITY && policy != SPX_Q_FIFO && policy != SPX_Q_SHARDED) return failf(SPX_EINVAL, "%s: bad queue policy", who);
   if (o && o->tile > 0 && !valid_tile(o->tile)) return failf(SPX_EINVAL, "%s: bad tile size", who);
   if (o && (o->flags & SPX_F_SCALED)) return failf(SPX_EINVAL, "%s: scaled factors are single-matrix only", who);
@@ -1127,7 +1136,7 @@ int spx_potrf_tiled(spx_ctx* c, int64_t n, const double* dA, int64_t lda, const 
   if (n < 1 || lda < n) return fail(SPX_EINVAL, "spx_potrf_tiled: need n >= 1 and lda >= n");
   const int b = (opts && opts->tile > 0) ? opts->tile : default_tile(n);
   if (!valid_tile(b)) return fail(SPX_EINVAL, "spx_potrf_tiled: tile must be 32, 64, 128, 256 or 512");
-  const int policy = opts ? opts->queue_policy : SPX_Q_PRIORITY;
+  const int policy = opts ? opts->queue_policy : SPX_Q_SHARDED;
   if (policy != SPX_Q_PRIORITY && policy != SPX_Q_FIFO && policy != SPX_Q_SHARDED) return fail(SPX_EINVAL, "spx_potrf_tiled: bad queue policy");
   const int prec = opts ? opts->update_prec : SPX_PREC_FP64;
   if (prec != SPX_PREC_FP64 && prec != SPX_PREC_FP32 && prec != SPX_PREC_BF16)
@@ -1311,9 +1320,10 @@ int spx_run_graph(spx_ctx* c, const spx_graph* g, uint64_t spin_ticks, const spx
     }
     for (uint32_t t = 0; t < g->g.ntasks; ++t) {
       pr.tasks[t].type = SPX_T_SPIN;
-      // priority -> base 0..3 for level_of: equal priorities share the first level
+      // priority -> base 0..kMaxLevels-1 for level_of: equal priorities share the first level
       const int64_t span = (int64_t)pmax - pmin;
-      const int base = span > 0 ? (int)(3 * ((int64_t)g->g.prio[t] - pmin) / span) : 3;
+      const int top = kMaxLevels - 1;
+      const int base = span > 0 ? (int)(top * ((int64_t)g->g.prio[t] - pmin) / span) : top;
       pr.g.prio[t] = base << 16;
     }
     Image* im = nullptr;
@@ -1370,7 +1380,7 @@ void spx_factor_destroy(spx_factor* f) {
 // rhs2: a second one of the same shape that the diagonal solves write).
 static int solve_on(spx_ctx* c, const spx_factor* f, int64_t nrhs, double* rhs, double* rhs2) {
   Image* im = nullptr;
-  SPX_TRY(get_image(c, true, f->nt, f->b, (int)nrhs, SPX_Q_PRIORITY, &im));
+  SPX_TRY(get_image(c, true, f->nt, f->b, (int)nrhs, SPX_Q_SHARDED, &im));
   SPX_TRY(ensure_small_buffers(c, 1, 1, 0, false));
   DevMat m{};
   m.tiles = f->tiles;
@@ -1687,7 +1697,7 @@ int spx_potrs_noalloc(spx_ctx* c, const spx_factor* f, int64_t nrhs, const doubl
       const Program* pr = nullptr;
       SPX_TRY(get_program(c, 'S', f->nt, &pr));
       std::shared_ptr<ImageHost> nh(new ImageHost());
-      SPX_TRY(build_image_host({Piece{pr, 0, f->b, (int)nrhs}}, SPX_Q_PRIORITY, *nh));
+      SPX_TRY(build_image_host({Piece{pr, 0, f->b, (int)nrhs}}, SPX_Q_SHARDED, *nh));
       h = nh;
     }
     // scratch layout: image (static + per-launch arrays), matrix descriptor, info word,
@@ -1723,7 +1733,7 @@ int spx_potrs_noalloc(spx_ctx* c, const spx_factor* f, int64_t nrhs, const doubl
     SPX_TRY(launch_rhs_in(dB, ldb, f->n, nrhs, m.rhs, f->n_pad, f->dscale, st));
     SPX_TRY(launch_sched_init_full(im.pending, im.indeg, im.parts_left, im.nparts, im.ntasks, im.queue,
                                    im.total_parts * kShards, im.roots, im.nroots, im.counters, im.counters0,
-                                   kNumCounters, m.info, 1, nullptr, st));
+                                   kNumCounters, im.ring, kXcds * im.total_parts, m.info, 1, nullptr, st));
     SchedArgs a{};
     a.tasks = im.tasks;
     a.succ_off = im.succ_off;
@@ -1732,7 +1742,9 @@ int spx_potrs_noalloc(spx_ctx* c, const spx_factor* f, int64_t nrhs, const doubl
     a.parts_left = im.parts_left;
     a.queue = im.queue;
     a.counters = im.counters;
-    for (int l = 0; l < kMaxLevels; ++l) {
+    a.ring = im.ring;
+    a.ring_cap = im.total_parts;
+    for (int l = 0; l < kLevels1; ++l) {
       a.qbase[l] = im.qbase[l];
       a.qcap[l] = im.qcap[l];
     }
@@ -1762,8 +1774,7 @@ int spx_potrs_noalloc(spx_ctx* c, const spx_factor* f, int64_t nrhs, const doubl
     c->last.tile = (uint32_t)f->b;
     c->trace_len = 0;
     uint64_t done = 0;
-    for (int l = 0; l < kMaxLevels; ++l)
-      for (int sh = 0; sh < kShards; ++sh) done += c->nc_counters[ctr_head_idx(l, sh)];
+    for (int q = 0; q < kMaxQueues; ++q) done += c->nc_counters[ctr_queue_idx(q)];
     if (c->nc_counters[kStatusIdx] & STATUS_TIMEOUT)
       return failf(SPX_ETIMEOUT, "device scheduler made no progress (%llu of %u parts started)",
                    (unsigned long long)done, im.total_parts);
@@ -1785,6 +1796,17 @@ int64_t spx_trace(const spx_ctx* c, uint64_t* rec, int64_t cap) {
       return fail(SPX_EDEVICE, "spx_trace: copy failed");
   }
   return c->trace_len;
+}
+
+int64_t spx_trace_push(const spx_ctx* c, uint64_t* ticks, int64_t cap) {
+  if (!c) return fail(SPX_EINVAL, "spx_trace_push: null context");
+  if (c->trace_len <= 0 || c->trace_tasks <= 0) return 0;
+  const int64_t n = std::min<int64_t>(cap, c->trace_tasks);
+  if (ticks && n > 0) {
+    if (hipMemcpy(ticks, c->trace + 4 * c->trace_len, 8 * (size_t)n, hipMemcpyDeviceToHost) != hipSuccess)
+      return fail(SPX_EDEVICE, "spx_trace_push: copy failed");
+  }
+  return c->trace_tasks;
 }
 
 }  // extern "C"

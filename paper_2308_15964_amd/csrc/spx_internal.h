@@ -46,7 +46,8 @@ void cholesky_program(int nt, bool with_solve, std::vector<TaskDesc>& tasks, std
 void solve_program(int nt, std::vector<TaskDesc>& tasks, std::vector<spx_access>& acc);
 // The tiled matrix product C += A B (k outermost, then i, then j).
 void gemm_program(int nt, std::vector<TaskDesc>& tasks, std::vector<spx_access>& acc);
-int32_t cholesky_priority(const TaskDesc& d, int nt);
+// Sets g.prio to the upward-rank priorities of the program's tasks.
+void rank_priorities(const std::vector<TaskDesc>& tasks, Graph& g);
 // LOAD, the factor program (and with_solve: the substitution), STORE (with_solve only);
 // with_inverse: the inversion tasks and the inverse-based substitution.
 void io_program(int nt, bool with_solve, std::vector<TaskDesc>& tasks, std::vector<spx_access>& acc,
@@ -91,16 +92,23 @@ struct DevMat {
 
 // A LOAD task has one part per lower tile while they fit the 16-bit part index.
 constexpr int kLoadTileParts = 65534;
-constexpr int kMaxLevels = 4;
+constexpr int kMaxQueues = 32;      // ready queues per image: levels x shards (a wave's lanes read them)
+constexpr int kMaxLevels = 64;      // priority classes (priority >> 16)
+constexpr int kLevels1 = 16;        // queue levels with one shard
 constexpr int kShards = 8;          // ready queues per priority level (one per XCD-sized group of workgroups)
 constexpr int kCounterStride = 32;  // 128-byte spacing of hot counters (uint32 units)
-// Counter layout: head and tail of every (level, shard) queue, then the status word.
-constexpr uint32_t ctr_head_idx(int l, int s) { return (uint32_t)(l * kShards + s) * kCounterStride; }
-constexpr uint32_t ctr_tail_idx(int l, int s) {
-  return (uint32_t)((kMaxLevels + l) * kShards + s) * kCounterStride;
-}
-constexpr uint32_t kStatusIdx = 2u * kMaxLevels * kShards * kCounterStride;
-constexpr uint32_t kNumCounters = kStatusIdx + kCounterStride;
+// Counter layout: one 64-bit word per queue q = level x shards + shard (head in the low
+// half, tail in the high half, so one load reads both and one compare-and-swap claims
+// against both), then the status word.
+constexpr uint32_t ctr_queue_idx(int q) { return (uint32_t)q * kCounterStride; }
+constexpr uint32_t kStatusIdx = (uint32_t)kMaxQueues * kCounterStride;
+// Per XCD x (kXcds of them): the tail and head of its ring of finished, not yet released
+// parts, and the lock of its release rounds, each on its own line.
+constexpr int kXcds = 8;
+constexpr uint32_t ctr_ring_tail_idx(int x) { return kStatusIdx + (uint32_t)(1 + 3 * x) * kCounterStride; }
+constexpr uint32_t ctr_ring_head_idx(int x) { return kStatusIdx + (uint32_t)(2 + 3 * x) * kCounterStride; }
+constexpr uint32_t ctr_ring_lock_idx(int x) { return kStatusIdx + (uint32_t)(3 + 3 * x) * kCounterStride; }
+constexpr uint32_t kNumCounters = kStatusIdx + (uint32_t)(1 + 3 * kXcds) * kCounterStride;
 
 // Everything the persistent scheduler kernel needs for one launch.
 struct SchedArgs {
@@ -111,16 +119,19 @@ struct SchedArgs {
   uint32_t* parts_left;      // parts not yet finished per task
   unsigned long long* queue; // item = task << 16 | part; queue (l, s) holds qcap[l] slots
                              // at qbase[l] * kShards + s * qcap[l]
-  uint32_t* counters;        // ctr_head_idx / ctr_tail_idx / kStatusIdx
-  uint32_t qbase[kMaxLevels];
-  uint32_t qcap[kMaxLevels];
+  uint32_t* counters;        // ctr_queue_idx / kStatusIdx / ctr_ring_*_idx
+  uint32_t* ring;            // per XCD x: ring_cap task ids at x * ring_cap (finished parts awaiting release)
+  uint32_t ring_cap;
+  uint32_t qbase[kLevels1];
+  uint32_t qcap[kLevels1];
   uint32_t total_parts;
   uint32_t ntasks;
-  int32_t nlev;
+  int32_t nlev;     // levels in use (nlev x nshards <= kMaxQueues)
   int32_t nshards;  // queues in use per level (1..kShards); the image's roots use the same count
   const DevMat* mats;
   unsigned long long* trace;  // 4 x uint64 per part, or null
   uint32_t* trace_idx;
+  unsigned long long* trace_push;  // per task: the tick its last predecessor pushed it, or null
   unsigned long long* wg_cycles;  // per workgroup: busy, idle (wall clock ticks)
   unsigned long long spin_limit;  // ticks without progress before giving up
 };
@@ -151,8 +162,8 @@ int launch_axpy_cols(int64_t n, int64_t q, const double* alpha, const double* X,
 int launch_sched_init_full(uint32_t* pending, const uint32_t* indeg, uint32_t* parts_left, const uint32_t* nparts,
                            uint32_t ntasks, unsigned long long* queue, uint32_t queue_len,
                            const unsigned long long* roots, uint32_t nroots, uint32_t* counters,
-                           const uint32_t* counters0, uint32_t ncounters, int32_t* info, int ninfo,
-                           uint32_t* trace_idx, void* stream);
+                           const uint32_t* counters0, uint32_t ncounters, uint32_t* ring, uint32_t ring_len,
+                           int32_t* info, int ninfo, uint32_t* trace_idx, void* stream);
 // Task families of the scheduler kernel (one instantiation each): FAM_CHOL runs every
 // task of the Cholesky, solve, batched and served graphs; FAM_GEMM the tiled product's;
 // FAM_SPIN the empty tasks of spx_run_graph.

@@ -52,6 +52,7 @@ constexpr int NT = 256;                 // threads per workgroup (4 waves)
 constexpr int LDS_DOUBLES = 16384;      // 128 KiB of LDS per workgroup (one workgroup per CU)
 constexpr int LDS_D_OFF = 8192;         // 32x32 diagonal block, after the update staging area
 constexpr u64 EMPTY = ~0ull;
+constexpr uint32_t EMPTY32 = ~0u;
 
 __device__ __forceinline__ double* tile_ptr(const DevMat& m, int i, int j) {
   return m.tiles + ((size_t)i * (size_t)(i + 1) / 2 + (size_t)j) * (size_t)m.b * (size_t)m.b;
@@ -1559,8 +1560,9 @@ __device__ __forceinline__ void run_part(const SchedArgs& a, uint32_t task, uint
 // ---------------------------------------------------------------------------------------
 // The persistent scheduler kernel.
 // ---------------------------------------------------------------------------------------
-__device__ __forceinline__ uint32_t* ctr_head(const SchedArgs& a, int l, int s) { return a.counters + ctr_head_idx(l, s); }
-__device__ __forceinline__ uint32_t* ctr_tail(const SchedArgs& a, int l, int s) { return a.counters + ctr_tail_idx(l, s); }
+__device__ __forceinline__ u64* ctr_queue(const SchedArgs& a, int l, int s) {
+  return reinterpret_cast<u64*>(a.counters + ctr_queue_idx(l * a.nshards + s));
+}
 __device__ __forceinline__ uint32_t* ctr_status(const SchedArgs& a) { return a.counters + kStatusIdx; }
 __device__ __forceinline__ u64* queue_of(const SchedArgs& a, int l, int s) {
   return a.queue + (size_t)a.qbase[l] * kShards + (size_t)s * a.qcap[l];
@@ -1568,36 +1570,50 @@ __device__ __forceinline__ u64* queue_of(const SchedArgs& a, int l, int s) {
 
 // Memory ordering.  All counter and queue updates are relaxed; visibility of tile data
 // comes from agent-scope fences, which on this chip write back (release) or invalidate
-// (acquire) the XCD's L2, so they are kept to the minimum:
-//   * a finished part: one release fence, then its decrement of the task's parts_left;
-//   * the task's last part: an acquire fence (the other parts' writes, through the release
-//     sequence of parts_left), a release fence, then relaxed decrements of the successors'
-//     pending counters and relaxed pushes;
-//   * a popped part: the task's pending counter is read (it is 0: the value the last
-//     predecessor's decrement wrote, at the end of the release sequence every predecessor
-//     joined), then one acquire fence makes every predecessor's writes visible.
+// (acquire) the L2 of the XCD that runs them.  A release costs microseconds and the
+// write-backs of one XCD's L2 do not overlap, so a release per finished part would queue
+// every workgroup behind its XCD's other 31; instead each XCD releases in rounds:
+//   * a finished claim appends its tasks to its XCD's ring (its stores are in that XCD's
+//     L2: the barrier before waited for them) and tries the XCD's round lock;
+//   * the lock holder reads the ring's tail, runs one release (which writes back every
+//     part appended before that read, all of them in this L2), then decrements parts_left
+//     for each of them and, for a task's last part, the successors' pending counters,
+//     pushing the ready ones; it repeats while the ring grows, and after unlocking looks
+//     once more, so an entry whose appender found the lock taken is never left behind;
+//   * a popped part: the task's pending counter is read (0: every predecessor's last part
+//     was written back before its decrement), then one acquire fence drops this XCD's
+//     stale lines.
 __device__ __forceinline__ void fence_rel() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
 __device__ __forceinline__ void fence_acq() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
 __device__ __forceinline__ uint32_t sub_rlx(uint32_t* p, uint32_t v) {
   return __hip_atomic_fetch_sub(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// The XCD this wave runs on (hardware register; its low three bits number the XCDs).
+__device__ __forceinline__ int xcd_id() {
+  uint32_t v;
+  asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(v));
+  return (int)(v & (kXcds - 1));
+}
+
 // push into the pushing workgroup's own shard: reserve nparts slots, then fill them
 __device__ __forceinline__ void push_task(const SchedArgs& a, uint32_t s, int home) {
   const TaskDesc d = a.tasks[s];
-  const uint32_t slot = __hip_atomic_fetch_add(ctr_tail(a, d.level, home), (uint32_t)d.nparts, __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_AGENT);
+  const uint32_t slot = (uint32_t)(__hip_atomic_fetch_add(ctr_queue(a, d.level, home), (u64)d.nparts << 32,
+                                                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >> 32);
   u64* q = queue_of(a, d.level, home) + slot;
   for (uint32_t p = 0; p < d.nparts; ++p)
     __hip_atomic_store(q + p, ((u64)s << 16) | p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (a.trace_push) a.trace_push[s] = now_ticks();
 }
 
 // pop, run by all 64 lanes of wave 0: lane i reads the head and tail of queue (level
 // i / S, shard (home + i) % S) for the S shards in use, all in one round trip; the lowest
 // lane with a non-empty queue (highest priority level, own shard first) claims slots with
-// a compare-and-swap, retried in place with the head it returns.  From the two bulk
-// levels it claims several parts at once while the queue is long (fewer operations on
-// the shared head, whose compare-and-swaps serialise); from the critical levels one.
+// a compare-and-swap, retried in place with the head it returns.  From the bulk levels
+// (the lowest quarter) it claims several parts at once while the queue is long (fewer
+// operations on the shared head, whose compare-and-swaps serialise, and fewer release
+// fences); from the others one.
 // Writes up to kClaim items to items[] (lane 0's copy) and returns their number (the same
 // in every lane); *saw tells whether some queue looked non-empty and *taken is the number
 // of parts taken from all queues so far (never more than the true count).
@@ -1606,11 +1622,9 @@ __device__ __forceinline__ int pop_wave(const SchedArgs& a, int home, bool* saw,
   const int lane = threadIdx.x & 63, S = a.nshards;
   const bool valid = lane < a.nlev * S;
   const int l = lane / S, sh = (home + lane % S) % S;
-  uint32_t h = 0, t = 0;
-  if (valid) {
-    h = ld_rlx(ctr_head(a, l, sh));
-    t = ld_rlx(ctr_tail(a, l, sh));
-  }
+  u64 ht = 0;
+  if (valid) ht = __hip_atomic_load(ctr_queue(a, l, sh), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  uint32_t h = (uint32_t)ht, t = (uint32_t)(ht >> 32);
   uint32_t sum = h;
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) sum += __shfl_xor(sum, off);
@@ -1624,12 +1638,15 @@ __device__ __forceinline__ int pop_wave(const SchedArgs& a, int home, bool* saw,
 #pragma unroll
   for (int i = 0; i < kClaim; ++i) it[i] = EMPTY;
   if (lane == win) {
-    const bool bulk = a.nlev > 2 && l >= a.nlev - 2;
-    while (h < t) {
+    const bool bulk = a.nlev > 2 && l >= a.nlev - a.nlev / 4;
+    for (;; h = (uint32_t)ht, t = (uint32_t)(ht >> 32)) {
+      if (h >= t) break;
       const uint32_t avail = t - h;
       const uint32_t want = bulk ? (avail >= 192u ? 4u : avail >= 128u ? 3u : avail >= 64u ? 2u : 1u) : 1u;
-      if (__hip_atomic_compare_exchange_strong(ctr_head(a, l, sh), &h, h + want, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_AGENT)) {
+      // a push between the load and the swap changes the tail half and fails the swap:
+      // retry with the word it returns
+      if (__hip_atomic_compare_exchange_strong(ctr_queue(a, l, sh), &ht, ht + want, __ATOMIC_RELAXED,
+                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
         // the slots are reserved by running pushers: wait for the items to be written
         // (bounded by the spin limit: a slot still empty then ends the launch)
         const u64* q = queue_of(a, l, sh) + h;
@@ -1662,6 +1679,65 @@ __device__ __forceinline__ int pop_wave(const SchedArgs& a, int home, bool* saw,
     items[i] = ((u64)hi << 32) | lo;
   }
   return k;
+}
+
+// The release rounds of XCD x (see the memory-ordering notes above), run by the 64 lanes
+// of one wave: each lane takes one ring entry at a time (its parts_left decrement and,
+// for a task's last part, the successors' decrements and pushes).
+__device__ __noinline__ void release_rounds(const SchedArgs& a, int x, int home) {
+  const int lane = threadIdx.x & 63;
+  uint32_t* lock = a.counters + ctr_ring_lock_idx(x);
+  uint32_t* tailp = a.counters + ctr_ring_tail_idx(x);
+  uint32_t* headp = a.counters + ctr_ring_head_idx(x);
+  const uint32_t* ring = a.ring + (size_t)x * a.ring_cap;
+  for (;;) {
+    uint32_t got = 0u;
+    if (lane == 0) {
+      uint32_t zero = 0u;
+      got = __hip_atomic_compare_exchange_strong(lock, &zero, 1u, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT)
+                ? 1u
+                : 0u;
+    }
+    if (__shfl(got, 0) == 0u) return;  // the holder's next look takes our entries
+    uint32_t h = __builtin_amdgcn_readfirstlane(ld_rlx(headp));
+    for (;;) {
+      const uint32_t t = __builtin_amdgcn_readfirstlane(ld_rlx(tailp));
+      if (t == h) break;
+      fence_rel();
+      const u64 t0 = now_ticks();
+      for (uint32_t e0 = h; e0 < t; e0 += 64) {
+        const uint32_t e = e0 + (uint32_t)lane;
+        if (e >= t) continue;
+        uint32_t task;
+        // the slot was reserved by an appender that writes it next: bounded wait
+        while ((task = __hip_atomic_load(ring + e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) == EMPTY32) {
+          if (now_ticks() - t0 > a.spin_limit) {
+            __hip_atomic_fetch_or(ctr_status(a), (uint32_t)STATUS_TIMEOUT, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
+        }
+        if (task == EMPTY32 || sub_rlx(a.parts_left + task, 1u) != 1u) continue;
+        for (uint32_t q = a.succ_off[task]; q < a.succ_off[task + 1]; ++q) {
+          const uint32_t s = a.succ[q];
+          if (sub_rlx(a.pending + s, 1u) == 1u) push_task(a, s, home);
+        }
+      }
+      h = t;
+      // read-modify-writes, each complete before the next step: the next holder reads
+      // this head only after taking the lock this exchange releases
+      if (lane == 0) __hip_atomic_exchange(headp, h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    // unlock, then look once more: an appender that found the lock taken did so before
+    // this unlock, and its tail increment before that
+    uint32_t again = 0u;
+    if (lane == 0) {
+      __hip_atomic_exchange(lock, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      again = ld_rlx(tailp) != h ? 1u : 0u;
+    }
+    if (__shfl(again, 0) == 0u) return;
+  }
 }
 
 template <int FAM>
@@ -1760,29 +1836,20 @@ __global__ __launch_bounds__(NT) void sched_kernel(SchedArgs a) {
         }
       }
     }
-    // One release for all the parts of this claim (a release writes back the XCD's L2,
-    // about 25 us per call, so a claim of several bulk parts pays it once), then their
-    // parts-left decrements; the tasks they finish take one acquire and one release before
-    // their successors' pending counters are decremented.
-    if (tid == 0) {
-      fence_rel();
-      uint32_t done[kClaim];
-      int nd = 0;
-      for (int i = 0; i < n; ++i) {
-        const uint32_t task = (uint32_t)(s_items[i] >> 16);
-        if (sub_rlx(a.parts_left + task, 1u) == 1u) done[nd++] = task;
-      }
-      if (nd > 0) {
-        fence_acq();
-        fence_rel();
-        for (int i = 0; i < nd; ++i) {
-          const uint32_t task = done[i];
-          for (uint32_t e = a.succ_off[task]; e < a.succ_off[task + 1]; ++e) {
-            const uint32_t s = a.succ[e];
-            if (sub_rlx(a.pending + s, 1u) == 1u) push_task(a, s, home);
-          }
-        }
-      }
+    // hand the claim's parts to this XCD's release rounds (wave 0; the barrier above
+    // waited for every wave's stores)
+    if (tid < 64) {
+      const int x = xcd_id();
+      uint32_t* ring = a.ring + (size_t)x * a.ring_cap;
+      uint32_t slot = 0u;
+      if (tid == 0)
+        slot = __hip_atomic_fetch_add(a.counters + ctr_ring_tail_idx(x), (uint32_t)n, __ATOMIC_RELAXED,
+                                      __HIP_MEMORY_SCOPE_AGENT);
+      slot = __shfl(slot, 0);
+      if (tid < n)
+        __hip_atomic_store(ring + slot + tid, (uint32_t)(s_items[tid] >> 16), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+      release_rounds(a, x, home);
     }
   }
   if (tid == 0 && a.wg_cycles) {
@@ -1807,8 +1874,8 @@ __global__ __launch_bounds__(NT) void tile_inverses_kernel(const double* l, int 
 // launched after this one).
 __global__ void sched_init_kernel(uint32_t* pending, const uint32_t* indeg, uint32_t* parts_left,
                                   const uint32_t* nparts, uint32_t ntasks, u64* queue, uint32_t queue_len,
-                                  uint32_t* counters, const uint32_t* counters0, uint32_t ncounters, int32_t* info,
-                                  int ninfo, uint32_t* trace_idx) {
+                                  uint32_t* counters, const uint32_t* counters0, uint32_t ncounters,
+                                  uint32_t* ring, uint32_t ring_len, int32_t* info, int ninfo, uint32_t* trace_idx) {
   const uint32_t stride = gridDim.x * blockDim.x;
   const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
   for (uint32_t t = g; t < ntasks; t += stride) {
@@ -1817,6 +1884,7 @@ __global__ void sched_init_kernel(uint32_t* pending, const uint32_t* indeg, uint
   }
   for (uint32_t t = g; t < queue_len; t += stride) queue[t] = EMPTY;
   for (uint32_t t = g; t < ncounters; t += stride) counters[t] = counters0[t];
+  for (uint32_t t = g; t < ring_len; t += stride) ring[t] = EMPTY32;
   for (uint32_t t = g; t < (uint32_t)ninfo; t += stride) info[t] = INT_MAX;
   if (g == 0 && trace_idx) *trace_idx = 0;
 }
@@ -2228,10 +2296,11 @@ int launch_sched(const SchedArgs& a, int num_wg, void* stream, int family) {
 int launch_sched_init_full(uint32_t* pending, const uint32_t* indeg, uint32_t* parts_left, const uint32_t* nparts,
                            uint32_t ntasks, unsigned long long* queue, uint32_t queue_len,
                            const unsigned long long* roots, uint32_t nroots, uint32_t* counters,
-                           const uint32_t* counters0, uint32_t ncounters, int32_t* info, int ninfo,
-                           uint32_t* trace_idx, void* stream) {
+                           const uint32_t* counters0, uint32_t ncounters, uint32_t* ring, uint32_t ring_len,
+                           int32_t* info, int ninfo, uint32_t* trace_idx, void* stream) {
   hipLaunchKernelGGL(sched_init_kernel, dim3(1024), dim3(NT), 0, (hipStream_t)stream, pending, indeg, parts_left,
-                     nparts, ntasks, queue, queue_len, counters, counters0, ncounters, info, ninfo, trace_idx);
+                     nparts, ntasks, queue, queue_len, counters, counters0, ncounters, ring, ring_len, info, ninfo,
+                     trace_idx);
   const int rc = hip_ok(hipGetLastError(), "sched_init_kernel");
   if (rc) return rc;
   hipLaunchKernelGGL(roots_kernel, dim3(256), dim3(NT), 0, (hipStream_t)stream, queue, roots, nroots);

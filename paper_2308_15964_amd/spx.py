@@ -18,7 +18,7 @@ T_POTRF, T_TRSM, T_SYRK, T_GEMM, T_FTRSM, T_FGEMM, T_BTRSM, T_BGEMM, T_LOAD, T_S
 TASK_NAMES = ["POTRF", "TRSM", "SYRK", "GEMM", "FTRSM", "FGEMM", "BTRSM", "BGEMM", "LOAD", "STORE", "INV"]
 TILE_CANDIDATES = [32, 64, 128, 256, 512]
 PREC_FP64, PREC_FP32, PREC_BF16 = 0, 1, 2
-Q_PRIORITY, Q_FIFO, Q_SHARDED = 0, 1, 2
+Q_SHARDED, Q_PRIORITY, Q_FIFO = 0, 1, 2
 F_TRACE, F_SCALED = 1, 2
 
 
@@ -101,6 +101,7 @@ EXPORTS = [
     "spx_set_tile_table", "spx_tile_for",
     "spx_autotune_batched", "spx_server_create", "spx_submit", "spx_poll", "spx_server_now",
     "spx_server_get_stats", "spx_server_destroy", "spx_last_stats", "spx_ctx_set_flags", "spx_trace",
+    "spx_trace_push",
 ]
 
 _lib = None
@@ -163,6 +164,7 @@ def lib():
         "spx_last_stats": (ctypes.c_int, [vp, P(Stats)]),
         "spx_ctx_set_flags": (ctypes.c_int, [vp, u32]),
         "spx_trace": (i64, [vp, P(u64), i64]),
+        "spx_trace_push": (i64, [vp, P(u64), i64]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -318,7 +320,7 @@ class Context:
             raise ValueError(f"{name} must have unit stride along its last dimension")
         return t
 
-    def potrf(self, A, tile=0, update_prec=PREC_FP64, queue_policy=Q_PRIORITY, num_wg=0, flags=0, shift=None):
+    def potrf(self, A, tile=0, update_prec=PREC_FP64, queue_policy=Q_SHARDED, num_wg=0, flags=0, shift=None):
         """Factors the lower triangle of the SPD matrix A (n x n float64 on the device).
         shift (not None): factor D^-1/2 A D^-1/2 + shift I instead (a preconditioner)."""
         A = self._dev(A, "A")
@@ -424,7 +426,7 @@ class Context:
                     vpa(*[x.data_ptr() for x in Xs]), i64a(*[x.stride(0) for x in Xs])]
         return out
 
-    def posv_batched(self, As, Bs, tile=0, update_prec=PREC_FP64, queue_policy=Q_PRIORITY, num_wg=0, flags=0,
+    def posv_batched(self, As, Bs, tile=0, update_prec=PREC_FP64, queue_policy=Q_SHARDED, num_wg=0, flags=0,
                      Xs=None, keep=False):
         """Factors and solves every (A_i, B_i) in one launch; returns (Xs, info array), and
         with keep=True also the list of factors (None where info > 0).
@@ -446,7 +448,7 @@ class Context:
             return Xs, np.array(info[:], dtype=np.int64), [Factor(self, h) if h else None for h in hs]
         return Xs, np.array(info[:], dtype=np.int64)
 
-    def potrf_batched(self, As, tile=0, update_prec=PREC_FP64, queue_policy=Q_PRIORITY, num_wg=0, flags=0):
+    def potrf_batched(self, As, tile=0, update_prec=PREC_FP64, queue_policy=Q_SHARDED, num_wg=0, flags=0):
         """Factors every A_i in one launch; returns (list of Factor or None, info array)."""
         if not As:
             raise ValueError("empty batch")
@@ -530,6 +532,13 @@ class Context:
         rec = np.zeros(max(n, 1) * 4, np.uint64)
         _check(lib().spx_trace(self._h, rec.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), n))
         return rec[: 4 * n].reshape(n, 4)
+
+    def trace_push(self):
+        """Per task of the last traced launch: the device tick it was pushed (0: a root)."""
+        n = _check(lib().spx_trace_push(self._h, None, 0))
+        out = np.zeros(max(n, 1), np.uint64)
+        _check(lib().spx_trace_push(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), n))
+        return out[:n]
 
 
 class Factor:
