@@ -47,12 +47,18 @@ enum {
   SPX_ETIMEOUT = -6  /* the device scheduler saw no progress within its spin limit */
 };
 
-/* Access modes (Sec. 4.1): SpRead and SpWrite (read or write). */
-enum { SPX_ACC_R = 1, SPX_ACC_RW = 2 };
+/* Access modes (Sec. 4.1): SpRead, SpWrite (read or write) and SpCommutativeWrite
+ * (Sec. 4.1, Sec. 4.7): a read-modify-write whose order among the commutative writes of
+ * the same datum inserted one after another does not matter.  Such a run (cut into groups
+ * of at most 63 consecutive commutative writes) needs the datum's state before it, the
+ * next other access needs all of it, and its members run one at a time in any order: the
+ * device scheduler takes a lock per group when a member becomes ready and hands it to the
+ * next ready member when the holder finishes. */
+enum { SPX_ACC_R = 1, SPX_ACC_RW = 2, SPX_ACC_CW = 3 };
 
 /* One declared access: task index (insertion order), mode, datum id.  Accesses are given
- * grouped by task in insertion order; a task may name a datum twice (the stronger mode
- * counts). */
+ * grouped by task in insertion order; a task may name a datum twice (the same mode twice
+ * counts once; two different modes count as SPX_ACC_RW). */
 typedef struct {
   uint32_t task;
   uint32_t mode;
@@ -83,7 +89,9 @@ void spx_ctx_destroy(spx_ctx* ctx);
  * Graph building (Sec. 2.1, Sec. 4.1, Sec. 4.7).  Host only, integer only.
  *   spx_graph_build: infers the immediate-dependency edges of ntasks tasks from their
  *   accesses: a read depends on the datum's last writer (RAW); a write depends on every
- *   read since the last write (WAR), or on the last writer if there was none (WAW).
+ *   read since the last write (WAR), or on the last writer if there was none (WAW); a
+ *   commutative write depends on what a write would at the start of its group, and the
+ *   access after a group on all of its members ("last writer" then means every member).
  *   Edges are deduplicated and always point from an earlier to a later task, so the graph
  *   is acyclic.  priority (nullable, ntasks entries): larger runs sooner (Sec. 4.1).
  *   Errors: SPX_EINVAL (task index >= ntasks, bad mode, accesses not grouped by task in
@@ -119,15 +127,20 @@ enum { SPX_T_POTRF = 0, SPX_T_TRSM, SPX_T_SYRK, SPX_T_GEMM, SPX_T_FTRSM, SPX_T_F
  * diagonal solves FTRSM(k) / BTRSM(k) then read M_k instead of L_kk.  Bits 8-15 of
  * with_solve (0 or 1: whole tasks; at most 64): each POTRF(k) becomes that many chained
  * step tasks on tile (k,k), as the library runs the diagonal tiles of 256 and 512 in
- * matrices of at least four tile columns (b/32 steps). */
+ * matrices of at least four tile columns (b/32 steps).  Bit 3: the updates (SYRK and GEMM
+ * on their tile, FGEMM and BGEMM on their right-hand-side block) are commutative writes,
+ * as SPX_F_COMMUTE runs them. */
 int spx_cholesky_graph(int32_t nt, int32_t with_solve, spx_graph** out, int32_t* task_types, uint32_t cap);
 
 /* The tiled matrix product of Sec. 5.2 (the GEMM application) for nt x nt tiles: one task
  * SPX_T_MGEMM(i, j, k) per tile triple, C_ij <- C_ij + A_ik B_kj, declaring SpRead on A_ik
  * and B_kj and SpWrite on C_ij, inserted with k outermost (then i, then j).  Datum ids:
  * A_ik -> i*nt + k, B_kj -> nt^2 + k*nt + j, C_ij -> 2 nt^2 + i*nt + j.  The graph is nt^2
- * independent chains of nt - 1 write-after-write edges.  task_types as for
- * spx_cholesky_graph.  Errors: SPX_EINVAL (nt outside [1, 512]), SPX_ENOMEM. */
+ * independent chains of nt - 1 write-after-write edges.  nt | SPX_GEMM_COMMUTE: the
+ * updates of C_ij are commutative writes instead (no edges; groups of at most 63 updates
+ * of a tile, run one at a time in any order), as SPX_F_COMMUTE runs them.  task_types as
+ * for spx_cholesky_graph.  Errors: SPX_EINVAL (nt outside [1, 512]), SPX_ENOMEM. */
+enum { SPX_GEMM_COMMUTE = 1 << 16 };
 int spx_gemm_graph(int32_t nt, spx_graph** out, int32_t* task_types, uint32_t cap);
 
 /* ---------------------------------------------------------------------------------------
@@ -152,10 +165,17 @@ int spx_gemm_graph(int32_t nt, spx_graph** out, int32_t* task_types, uint32_t ca
  *     a stabilised low-precision factor that spx_potrs uses as a preconditioner (the
  *     factor keeps D^{-1/2} and applies it around every solve).  spx_factor_get_l then
  *     returns the factor of the scaled, shifted matrix.  Single-matrix calls only.
+ *     SPX_F_COMMUTE declares the updates as commutative writes (Sec. 4.1): SYRK and GEMM
+ *     on their tile in the factor, FGEMM and BGEMM on their right-hand-side block in the
+ *     solve (spx_potrs with a factor made under the flag), MGEMM on C_ij in
+ *     spx_gemm_tiled.  The updates of a tile then run in the order they become ready, one
+ *     at a time, instead of in insertion order: the result changes by rounding from
+ *     launch to launch (no longer bitwise reproducible) and stays within the same error
+ *     bounds.  Single-matrix calls only.
  * ------------------------------------------------------------------------------------ */
 enum { SPX_PREC_FP64 = 0, SPX_PREC_FP32 = 1, SPX_PREC_BF16 = 2 };
 enum { SPX_Q_SHARDED = 0, SPX_Q_PRIORITY = 1, SPX_Q_FIFO = 2 };
-enum { SPX_F_TRACE = 1u, SPX_F_SCALED = 2u };
+enum { SPX_F_TRACE = 1u, SPX_F_SCALED = 2u, SPX_F_COMMUTE = 4u };
 typedef struct {
   int32_t tile;
   int32_t update_prec;

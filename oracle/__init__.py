@@ -63,7 +63,7 @@ def lib():
                                        u64, ctypes.POINTER(u64), ctypes.POINTER(i64)]
         L.orc_cholesky.restype = i64
         L.orc_cholesky.argtypes = [i64, ctypes.c_int, dp, dp, ctypes.c_int, ctypes.c_int, u64, ctypes.c_int,
-                                   ctypes.POINTER(i64), i64, ctypes.POINTER(u32), ctypes.POINTER(i64)]
+                                   ctypes.POINTER(i64), i64, ctypes.POINTER(u32), ctypes.POINTER(i64), ctypes.c_int]
         L.orc_run_task.restype = i64
         L.orc_run_task.argtypes = [ctypes.c_int] * 4 + [dp, i64, ctypes.c_int, dp, ctypes.c_int]
         L.orc_factor_residual.restype = ctypes.c_double
@@ -79,14 +79,14 @@ def lib():
         L.orc_factor_entry_check.restype = ctypes.c_double
         L.orc_factor_entry_check.argtypes = [dp, dp, i64, ctypes.POINTER(i64), ctypes.POINTER(i64), i64]
         L.orc_gemm_program.restype = i64
-        L.orc_gemm_program.argtypes = [ctypes.c_int, ctypes.POINTER(_Task), ctypes.POINTER(_Access),
+        L.orc_gemm_program.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(_Task), ctypes.POINTER(_Access),
                                        ctypes.POINTER(u64)]
         L.orc_gemm.restype = i64
         L.orc_gemm.argtypes = [i64, ctypes.c_int, dp, ctypes.c_int, u64, ctypes.c_int, ctypes.POINTER(i64),
-                               ctypes.POINTER(u32), ctypes.POINTER(i64)]
+                               ctypes.POINTER(u32), ctypes.POINTER(i64), ctypes.c_int]
         L.orc_gemm_dag.restype = i64
-        L.orc_gemm_dag.argtypes = [ctypes.c_int, ctypes.POINTER(u32), ctypes.POINTER(u32), u64, ctypes.POINTER(u64),
-                                   ctypes.POINTER(i64)]
+        L.orc_gemm_dag.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(u32), ctypes.POINTER(u32), u64,
+                                   ctypes.POINTER(u64), ctypes.POINTER(i64)]
         L.orc_gemm_entries.restype = None
         L.orc_gemm_entries.argtypes = [dp, dp, dp, i64, ctypes.POINTER(i64), ctypes.POINTER(i64), i64, dp]
         L.orc_dot2.restype = ctypes.c_double
@@ -128,37 +128,42 @@ def dag_edges(ntasks, accesses):
     return np.stack([src[:E], dst[:E]], axis=1), {"RAW": kinds[0], "WAR": kinds[1], "WAW": kinds[2]}
 
 
-def cholesky_program(nt, with_solve=False):
-    """The oracle's task program: ([(name, i, j, k)], [(task, mode, datum)])."""
+def cholesky_program(nt, with_solve=False, commute=False):
+    """The oracle's task program: ([(name, i, j, k)], [(task, mode, datum)]); commute: the
+    updates are commutative writes."""
     na = ctypes.c_uint64()
-    T = lib().orc_cholesky_program(nt, int(with_solve), None, None, ctypes.byref(na))
+    fl = int(bool(with_solve)) | (0x100 if commute else 0)
+    T = lib().orc_cholesky_program(nt, fl, None, None, ctypes.byref(na))
     tasks = (_Task * max(T, 1))()
     acc = (_Access * max(na.value, 1))()
-    lib().orc_cholesky_program(nt, int(with_solve), tasks, acc, ctypes.byref(na))
+    lib().orc_cholesky_program(nt, fl, tasks, acc, ctypes.byref(na))
     return ([(TASK_NAMES[t.type], t.i, t.j, t.k) for t in tasks[:T]],
             [(a.task, a.mode, a.datum) for a in acc[: na.value]])
 
 
-def cholesky_dag(nt, with_solve=False):
+def cholesky_dag(nt, with_solve=False, commute=False):
     """Edges of the oracle's own right-looking Cholesky (+ solve) task program."""
     kinds = (ctypes.c_uint64 * 3)()
     T = ctypes.c_int64()
-    E = lib().orc_cholesky_dag(nt, int(with_solve), None, None, 0, kinds, ctypes.byref(T))
+    fl = int(bool(with_solve)) | (0x100 if commute else 0)
+    E = lib().orc_cholesky_dag(nt, fl, None, None, 0, kinds, ctypes.byref(T))
     src = np.zeros(max(E, 1), np.uint32)
     dst = np.zeros(max(E, 1), np.uint32)
-    lib().orc_cholesky_dag(nt, int(with_solve), src.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
+    lib().orc_cholesky_dag(nt, fl, src.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
                            dst.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)), E, kinds, ctypes.byref(T))
     return T.value, np.stack([src[:E], dst[:E]], axis=1), {"RAW": kinds[0], "WAR": kinds[1], "WAW": kinds[2]}
 
 
-ORDER_INSERTION, ORDER_RANDOM, ORDER_PRIORITY = 0, 1, 2
+ORDER_INSERTION, ORDER_RANDOM, ORDER_PRIORITY, ORDER_GIVEN = 0, 1, 2, 3
 
 
 def cholesky(A, nb, B=None, order=ORDER_INSERTION, seed=0, nthreads=1, limit=0, drop_edge=None,
-             return_order=False):
+             return_order=False, commute=False, given=None):
     """Tile Cholesky (tile size nb, n % nb == 0) of the lower triangle of A, optionally
     followed by the solve of A X = B.  Returns (L, X or None, info[, order]); info is 0
-    or the 1-based global column of the first non-positive pivot."""
+    or the 1-based global column of the first non-positive pivot.  commute: the updates
+    are commutative writes (sequential only).  order=ORDER_GIVEN runs the task order
+    `given` (ValueError if it is not a valid order of the program's DAG)."""
     a = _lower_cm(A)
     n = a.shape[0]
     if n % nb:
@@ -175,12 +180,17 @@ def cholesky(A, nb, B=None, order=ORDER_INSERTION, seed=0, nthreads=1, limit=0, 
     nt = n // nb
     T = nt + 2 * comb(nt, 2) + comb(nt, 3) + (2 * (nt + comb(nt, 2)) if nrhs else 0)
     ordbuf = np.full(T, -1, np.int64)
+    if order == ORDER_GIVEN:
+        ordbuf[:] = np.asarray(given, np.int64)
     nrun = ctypes.c_int64(0)
     de = None
     if drop_edge is not None:
         de = (ctypes.c_uint32 * 2)(int(drop_edge[0]), int(drop_edge[1]))
     info = lib().orc_cholesky(n, nb, _dp(a), _dp(y) if y is not None else None, nrhs, order, seed, nthreads,
-                              ordbuf.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), limit, de, ctypes.byref(nrun))
+                              ordbuf.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), limit, de, ctypes.byref(nrun),
+                              int(bool(commute)))
+    if info == -2:
+        raise ValueError("not a valid order of the program's DAG")
     if info < 0:
         raise RuntimeError("oracle failed")
     L = _cm_to_lower(a)
@@ -195,32 +205,33 @@ def cholesky(A, nb, B=None, order=ORDER_INSERTION, seed=0, nthreads=1, limit=0, 
     return out
 
 
-def gemm_program(nt):
+def gemm_program(nt, commute=False):
     """The oracle's GEMM task program: ([(name, i, j, k)], [(task, mode, datum)])."""
     na = ctypes.c_uint64()
-    T = lib().orc_gemm_program(nt, None, None, ctypes.byref(na))
+    T = lib().orc_gemm_program(nt, int(bool(commute)), None, None, ctypes.byref(na))
     tasks = (_Task * max(T, 1))()
     acc = (_Access * max(na.value, 1))()
-    lib().orc_gemm_program(nt, tasks, acc, ctypes.byref(na))
+    lib().orc_gemm_program(nt, int(bool(commute)), tasks, acc, ctypes.byref(na))
     return ([(TASK_NAMES[t.type], t.i, t.j, t.k) for t in tasks[:T]],
             [(a.task, a.mode, a.datum) for a in acc[: na.value]])
 
 
-def gemm_dag(nt):
+def gemm_dag(nt, commute=False):
     """Edges of the GEMM program by the pairwise definition: (T, edges, kinds)."""
     kinds = (ctypes.c_uint64 * 3)()
     T = ctypes.c_int64()
-    E = lib().orc_gemm_dag(nt, None, None, 0, kinds, ctypes.byref(T))
+    E = lib().orc_gemm_dag(nt, int(bool(commute)), None, None, 0, kinds, ctypes.byref(T))
     src = np.zeros(max(E, 1), np.uint32)
     dst = np.zeros(max(E, 1), np.uint32)
-    lib().orc_gemm_dag(nt, src.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
+    lib().orc_gemm_dag(nt, int(bool(commute)), src.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
                        dst.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)), E, kinds, ctypes.byref(T))
     return T.value, np.stack([src[:E], dst[:E]], axis=1), {"RAW": kinds[0], "WAR": kinds[1], "WAW": kinds[2]}
 
 
-def gemm(A, B, C, nb, order=ORDER_INSERTION, seed=0, nthreads=1, drop_edge=None, return_order=False):
+def gemm(A, B, C, nb, order=ORDER_INSERTION, seed=0, nthreads=1, drop_edge=None, return_order=False,
+         commute=False, given=None):
     """C + A B (all n x n, n % nb == 0) by the tiled program.  Returns the new C (and the
-    run order when asked)."""
+    run order when asked).  commute / given as for cholesky."""
     A, B, C = (np.asarray(x, np.float64) for x in (A, B, C))
     n = A.shape[0]
     if n % nb:
@@ -228,10 +239,14 @@ def gemm(A, B, C, nb, order=ORDER_INSERTION, seed=0, nthreads=1, drop_edge=None,
     abc = np.asfortranarray(np.concatenate([A, B, C], axis=1))
     nt = n // nb
     ordbuf = np.full(nt ** 3, -1, np.int64)
+    if order == ORDER_GIVEN:
+        ordbuf[:] = np.asarray(given, np.int64)
     nrun = ctypes.c_int64(0)
     de = None if drop_edge is None else (ctypes.c_uint32 * 2)(int(drop_edge[0]), int(drop_edge[1]))
     rc = lib().orc_gemm(n, nb, _dp(abc), order, seed, nthreads, ordbuf.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
-                        de, ctypes.byref(nrun))
+                        de, ctypes.byref(nrun), int(bool(commute)))
+    if rc == -2:
+        raise ValueError("not a valid order of the program's DAG")
     if rc < 0:
         raise RuntimeError("oracle failed")
     out = np.ascontiguousarray(abc[:, 2 * n:])

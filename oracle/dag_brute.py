@@ -76,3 +76,54 @@ def closure(ntasks, edge_list):
             reach[a].add(b)
             reach[a] |= reach[b]
     return {(a, b) for a in range(ntasks) for b in reach[a]}
+
+
+CW = 3
+GROUP_MAX = 63
+
+
+def commutative_groups(ntasks, accesses):
+    """Per task, {datum: group id} for its commutative writes: on each datum, a run of
+    consecutive commutative writes (no other use of the datum between them, counting in
+    insertion order) forms a group, cut every GROUP_MAX members."""
+    per = [dict() for _ in range(ntasks)]
+    for t, m, d in accesses:
+        old = per[t].get(d)
+        per[t][d] = m if old is None or old == m else RW
+    groups = [dict() for _ in range(ntasks)]
+    data = sorted({d for p in per for d in p})
+    gid = 0
+    for d in data:
+        users = [t for t in range(ntasks) if d in per[t]]
+        run = 0
+        prev_cw = False
+        for t in users:
+            if per[t][d] == CW:
+                if not prev_cw or run == GROUP_MAX:
+                    gid += 1
+                    run = 0
+                groups[t][d] = gid
+                run += 1
+                prev_cw = True
+            else:
+                prev_cw = False
+    return per, groups
+
+
+def commutative_conflict_closure(ntasks, accesses):
+    """Transitive closure of the order a parallel run must keep (Specx Sec. 4.1): tasks a < b
+    sharing a datum that at least one of them writes, unless both are commutative writes
+    of the same group (those may run in either order).  A set of pairs."""
+    per, groups = commutative_groups(ntasks, accesses)
+    pairs = []
+    for a in range(ntasks):
+        for b in range(a + 1, ntasks):
+            for d, ma in per[a].items():
+                mb = per[b].get(d)
+                if mb is None or (ma == R and mb == R):
+                    continue
+                if ma == CW and mb == CW and groups[a][d] == groups[b][d]:
+                    continue
+                pairs.append((a, b))
+                break
+    return closure(ntasks, pairs)

@@ -10,19 +10,29 @@
  *  - Sec. 2.1 (task-based parallelization, STF): one thread inserts tasks in program
  *    order with their data accesses; the runtime infers the dependencies from that
  *    order and the parallel run must give exactly the sequential result.
- *  - Sec. 4.1 (task insertion): access modes SpRead (read only) and SpWrite (read or
- *    write); a datum is identified by its address (here: an integer id).
+ *  - Sec. 4.1 (task insertion): access modes SpRead (read only), SpWrite (read or
+ *    write) and SpCommutativeWrite (a write whose order among the commutative writes
+ *    inserted one after another does not matter); a datum is identified by its address
+ *    (here: an integer id).
  *  - Sec. 4.7 (internal implementation): per-datum ordered list of the tasks that use
  *    it; a finished task releases the next tasks of each list.
  *  - Sec. 5.2 (numerical applications, Cholesky): the factorisation is split into
  *    tiles and runs as POTRF / TRSM / SYRK / GEMM tasks in FP64.
  *
  * The DAG here is the plain pairwise definition (not the per-datum builder the product
- * uses): for tasks a < b in insertion order, edge (a,b) exists iff some datum d is used
- * by both, at least one of them writes it, and
- *     RAW: a writes d, b only reads d, no task strictly between them writes d;
- *     WAR: a only reads d, b writes d, no task strictly between them writes d;
- *     WAW: both write d, no task strictly between them reads or writes d.
+ * uses).  On each datum, a maximal run of consecutive commutative writes is cut into
+ * groups of at most 63 (the first 63, the next 63, ...); two commutative writes of one
+ * group have no edge (they may run in any order, one at a time).  Otherwise commutative
+ * writes count as writes, and for tasks a < b in insertion order, edge (a,b) exists iff
+ * some datum d is used by both, at least one of them writes it, and
+ *     RAW: a writes d, b only reads d, and every task strictly between them that writes
+ *          d is a commutative write of a's group;
+ *     WAR: a only reads d, b writes d, and every task strictly between them that writes
+ *          d is a commutative write of b's group;
+ *     WAW: both write d (not two members of one group), and every task strictly between
+ *          them is a commutative write of a's group or of b's group.
+ * Without commutative writes these are the plain rules: nothing that writes between a
+ * read and a write, nothing at all between two writes.
  * The Cholesky variant is the right-looking tile algorithm on the lower triangle.
  */
 #include <math.h>
@@ -33,6 +43,8 @@
 
 #define ORC_R 1u  /* SpRead  */
 #define ORC_RW 2u /* SpWrite (read or write) */
+#define ORC_CW 3u /* SpCommutativeWrite */
+#define ORC_GROUP_MAX 63
 
 typedef struct {
   uint32_t task;
@@ -48,6 +60,7 @@ typedef struct {
   uint64_t datum;
   uint32_t task;
   uint32_t mode;
+  int64_t group; /* commutative writes: the group's number on this datum; else -1 */
 } orc_use;
 
 static int cmp_use(const void* x, const void* y) {
@@ -79,7 +92,7 @@ int64_t orc_dag_edges(uint32_t ntasks, const orc_access* acc, uint64_t nacc, uin
   orc_use* use = (orc_use*)malloc((nacc ? nacc : 1) * sizeof(orc_use));
   if (!use) return -1;
   for (uint64_t i = 0; i < nacc; ++i) {
-    if (acc[i].task >= ntasks || (acc[i].mode != ORC_R && acc[i].mode != ORC_RW)) {
+    if (acc[i].task >= ntasks || (acc[i].mode != ORC_R && acc[i].mode != ORC_RW && acc[i].mode != ORC_CW)) {
       free(use);
       return -1;
     }
@@ -88,13 +101,30 @@ int64_t orc_dag_edges(uint32_t ntasks, const orc_access* acc, uint64_t nacc, uin
     use[i].mode = acc[i].mode;
   }
   qsort(use, nacc, sizeof(orc_use), cmp_use);
-  /* one entry per (datum, task): a task that names a datum twice uses the stronger mode */
+  /* one entry per (datum, task): a task that names a datum twice with two different
+   * modes writes it (reading and commutatively writing the same datum is a plain write) */
   uint64_t m = 0;
   for (uint64_t i = 0; i < nacc; ++i) {
     if (m > 0 && use[m - 1].datum == use[i].datum && use[m - 1].task == use[i].task) {
-      if (use[i].mode == ORC_RW) use[m - 1].mode = ORC_RW;
+      if (use[i].mode != use[m - 1].mode) use[m - 1].mode = ORC_RW;
     } else {
       use[m++] = use[i];
+    }
+  }
+  /* groups: runs of consecutive commutative writes of a datum, at most ORC_GROUP_MAX each */
+  {
+    int64_t next = 0, size = 0;
+    for (uint64_t i = 0; i < m; ++i) {
+      use[i].group = -1;
+      if (use[i].mode != ORC_CW) continue;
+      int cont = i > 0 && use[i - 1].datum == use[i].datum && use[i - 1].mode == ORC_CW &&
+                 size < ORC_GROUP_MAX;
+      if (!cont) {
+        ++next;
+        size = 0;
+      }
+      use[i].group = next;
+      ++size;
     }
   }
   uint64_t ecap = 1024, ne = 0;
@@ -109,17 +139,26 @@ int64_t orc_dag_edges(uint32_t ntasks, const orc_access* acc, uint64_t nacc, uin
     while (g1 < m && use[g1].datum == use[g0].datum) ++g1;
     for (uint64_t p = g0; p < g1; ++p) {
       for (uint64_t q = p + 1; q < g1; ++q) {
-        int wp = use[p].mode == ORC_RW, wq = use[q].mode == ORC_RW;
+        int wp = use[p].mode != ORC_R, wq = use[q].mode != ORC_R;
         if (!wp && !wq) continue;
-        int between_w = 0, between_any = 0;
+        int64_t gp = use[p].group, gq = use[q].group;
+        if (gp >= 0 && gp == gq) continue; /* two members of one group */
+        /* what lies strictly between: writes outside a's group, writes outside b's
+         * group, anything outside both groups */
+        int w_not_p = 0, w_not_q = 0, any_not_pq = 0;
         for (uint64_t t = p + 1; t < q; ++t) {
-          between_any = 1;
-          if (use[t].mode == ORC_RW) between_w = 1;
+          int64_t gt = use[t].group;
+          int in_p = gt >= 0 && gt == gp, in_q = gt >= 0 && gt == gq;
+          if (use[t].mode != ORC_R) {
+            if (!in_p) w_not_p = 1;
+            if (!in_q) w_not_q = 1;
+          }
+          if (!in_p && !in_q) any_not_pq = 1;
         }
         int kind = -1;
-        if (wp && !wq && !between_w) kind = 0;      /* RAW */
-        else if (!wp && wq && !between_w) kind = 1; /* WAR */
-        else if (wp && wq && !between_any) kind = 2;/* WAW */
+        if (wp && !wq && !w_not_p) kind = 0;       /* RAW */
+        else if (!wp && wq && !w_not_q) kind = 1;  /* WAR */
+        else if (wp && wq && !any_not_pq) kind = 2;/* WAW */
         if (kind < 0) continue;
         if (ne == ecap) {
           ecap *= 2;
@@ -173,13 +212,17 @@ typedef struct {
 static uint64_t dA(int nt, int i, int j) { return (uint64_t)i * (uint64_t)nt + (uint64_t)j; }
 static uint64_t dB(int nt, int k) { return (uint64_t)nt * (uint64_t)nt + (uint64_t)k; }
 
-/* Writes the task program into tasks/acc (each may be null to count).  with_solve adds
- * the forward (L y = b) and backward (L^T x = y) block substitutions after the factor.
- * Returns the task count; *nacc_out receives the access count. */
+/* Writes the task program into tasks/acc (each may be null to count).  flags bit 0
+ * (with_solve) adds the forward (L y = b) and backward (L^T x = y) block substitutions
+ * after the factor; bit 8 declares the updates (SYRK and GEMM on their tile, FGEMM and
+ * BGEMM on their block of the right-hand side) as commutative writes.  Returns the task
+ * count; *nacc_out receives the access count. */
 int64_t orc_cholesky_program(int nt, int with_solve, orc_task* tasks, orc_access* acc,
                              uint64_t* nacc_out) {
   int64_t nt_ = 0;
   uint64_t na = 0;
+  const uint32_t UPD = (with_solve & 0x100) ? ORC_CW : ORC_RW;
+  with_solve &= 1;
 #define ADD_TASK(TY, I, J, K)                                 \
   do {                                                        \
     if (tasks) {                                              \
@@ -207,12 +250,12 @@ int64_t orc_cholesky_program(int nt, int with_solve, orc_task* tasks, orc_access
     for (int i = k + 1; i < nt; ++i) {
       ADD_TASK(T_SYRK, i, i, k);
       ADD_ACC(ORC_R, dA(nt, i, k));
-      ADD_ACC(ORC_RW, dA(nt, i, i));
+      ADD_ACC(UPD, dA(nt, i, i));
       for (int j = k + 1; j < i; ++j) {
         ADD_TASK(T_GEMM, i, j, k);
         ADD_ACC(ORC_R, dA(nt, i, k));
         ADD_ACC(ORC_R, dA(nt, j, k));
-        ADD_ACC(ORC_RW, dA(nt, i, j));
+        ADD_ACC(UPD, dA(nt, i, j));
       }
     }
   }
@@ -225,7 +268,7 @@ int64_t orc_cholesky_program(int nt, int with_solve, orc_task* tasks, orc_access
         ADD_TASK(T_FGEMM, i, k, k);
         ADD_ACC(ORC_R, dA(nt, i, k));
         ADD_ACC(ORC_R, dB(nt, k));
-        ADD_ACC(ORC_RW, dB(nt, i));
+        ADD_ACC(UPD, dB(nt, i));
       }
     }
     for (int k = nt - 1; k >= 0; --k) {
@@ -236,7 +279,7 @@ int64_t orc_cholesky_program(int nt, int with_solve, orc_task* tasks, orc_access
         ADD_TASK(T_BGEMM, i, k, k);
         ADD_ACC(ORC_R, dA(nt, k, i));
         ADD_ACC(ORC_R, dB(nt, k));
-        ADD_ACC(ORC_RW, dB(nt, i));
+        ADD_ACC(UPD, dB(nt, i));
       }
     }
   }
@@ -247,8 +290,9 @@ int64_t orc_cholesky_program(int nt, int with_solve, orc_task* tasks, orc_access
 /* The tiled matrix product of Sec. 5.2 (the GEMM application): C <- C + A B for three
  * nt x nt tile matrices, one task per (i, j, k) updating C_ij with A_ik B_kj.  Inserted
  * with k outermost.  Datum ids: A_ik -> i*nt + k, B_kj -> nt^2 + k*nt + j, C_ij ->
- * 2 nt^2 + i*nt + j.  Returns the task count; *nacc_out receives the access count. */
-int64_t orc_gemm_program(int nt, orc_task* tasks, orc_access* acc, uint64_t* nacc_out) {
+ * 2 nt^2 + i*nt + j.  commute: the updates of C_ij are commutative writes.  Returns the
+ * task count; *nacc_out receives the access count. */
+int64_t orc_gemm_program(int nt, int commute, orc_task* tasks, orc_access* acc, uint64_t* nacc_out) {
   int64_t nt_ = 0;
   uint64_t na = 0;
   const uint64_t n2 = (uint64_t)nt * (uint64_t)nt;
@@ -258,7 +302,7 @@ int64_t orc_gemm_program(int nt, orc_task* tasks, orc_access* acc, uint64_t* nac
         ADD_TASK(T_MGEMM, i, j, k);
         ADD_ACC(ORC_R, (uint64_t)i * nt + k);
         ADD_ACC(ORC_R, n2 + (uint64_t)k * nt + j);
-        ADD_ACC(ORC_RW, 2 * n2 + (uint64_t)i * nt + j);
+        ADD_ACC(commute ? ORC_CW : ORC_RW, 2 * n2 + (uint64_t)i * nt + j);
       }
   if (nacc_out) *nacc_out = na;
   return nt_;
@@ -410,12 +454,15 @@ static void prog_free(orc_prog* p) {
   free(p->indeg);
 }
 
-/* with_solve < 0: the GEMM program instead of the Cholesky one. */
+/* flags < 0: the GEMM program instead of the Cholesky one (-2: with commutative
+ * updates); otherwise the flags of orc_cholesky_program. */
 static int prog_make(int nt, int with_solve, const uint32_t* drop_edge /* nullable: {src,dst} */,
                      orc_prog* p) {
   memset(p, 0, sizeof(*p));
   uint64_t na = 0;
-  int64_t T = with_solve < 0 ? orc_gemm_program(nt, NULL, NULL, &na) : orc_cholesky_program(nt, with_solve, NULL, NULL, &na);
+  const int gcomm = with_solve == -2;
+  int64_t T = with_solve < 0 ? orc_gemm_program(nt, gcomm, NULL, NULL, &na)
+                             : orc_cholesky_program(nt, with_solve, NULL, NULL, &na);
   p->tasks = (orc_task*)malloc((T ? T : 1) * sizeof(orc_task));
   orc_access* acc = (orc_access*)malloc((na ? na : 1) * sizeof(orc_access));
   if (!p->tasks || !acc) {
@@ -424,7 +471,7 @@ static int prog_make(int nt, int with_solve, const uint32_t* drop_edge /* nullab
     return -1;
   }
   if (with_solve < 0)
-    orc_gemm_program(nt, p->tasks, acc, &na);
+    orc_gemm_program(nt, gcomm, p->tasks, acc, &na);
   else
     orc_cholesky_program(nt, with_solve, p->tasks, acc, &na);
   int64_t E = orc_dag_edges((uint32_t)T, acc, na, NULL, NULL, 0, NULL);
@@ -475,7 +522,8 @@ static int64_t prio_key(const orc_task* t, int64_t idx) {
 }
 
 /* order: 0 = smallest ready index first (the insertion order), 1 = seeded random choice
- * among the ready tasks, 2 = priority (POTRF > TRSM > SYRK > GEMM, then smaller k).
+ * among the ready tasks, 2 = priority (POTRF > TRSM > SYRK > GEMM, then smaller k),
+ * 3 = the order given in order_out (every task must be ready at its turn, else -2).
  * order_out (nullable) receives the executed task indices.
  * Returns 0, a positive 1-based failing column, or a negative error. */
 static int64_t exec_seq(orc_prog* p, int order, uint64_t seed, double* a, int64_t n, int nb,
@@ -493,9 +541,20 @@ static int64_t exec_seq(orc_prog* p, int order, uint64_t seed, double* a, int64_
   for (int64_t t = 0; t < T; ++t)
     if (cnt[t] == 0) ready[nready++] = t;
   uint64_t s = seed;
+  if (order == 3 && !order_out) nready = 0;
   while (nready > 0) {
     int64_t pick = 0;
-    if (order == 0) {
+    if (order == 3) {
+      if (nrun >= T) break;
+      const int64_t want = order_out[nrun];
+      pick = -1;
+      for (int64_t q = 0; q < nready; ++q)
+        if (ready[q] == want) pick = q;
+      if (pick < 0) {
+        info = -2;
+        break;
+      }
+    } else if (order == 0) {
       for (int64_t q = 1; q < nready; ++q)
         if (ready[q] < ready[pick]) pick = q;
     } else if (order == 1) {
@@ -619,13 +678,16 @@ static int64_t exec_par(orc_prog* p, int nthreads, double* a, int64_t n, int nb,
  *   nthreads > 1: parallel executor.
  *   limit > 0 (parallel executor only): run only tasks [0, limit) of the insertion order.
  *   drop_edge (nullable {src,dst}): remove one DAG edge (a planted mistake for tests).
- * Returns 0, the 1-based global column of the first non-positive pivot, or -1. */
+ *   commute: the updates are commutative writes (sequential executor only).
+ * Returns 0, the 1-based global column of the first non-positive pivot, or -1 (-2: a
+ * given order that is not valid). */
 int64_t orc_cholesky(int64_t n, int nb, double* a, double* y, int nrhs, int order, uint64_t seed,
                      int nthreads, int64_t* order_out, int64_t limit, const uint32_t* drop_edge,
-                     int64_t* nrun_out) {
+                     int64_t* nrun_out, int commute) {
   if (n <= 0 || nb <= 0 || n % nb != 0 || !a) return -1;
+  if (commute && nthreads > 1) return -1;
   int nt = (int)(n / nb);
-  int with_solve = (y != NULL && nrhs > 0);
+  int with_solve = (y != NULL && nrhs > 0) | (commute ? 0x100 : 0);
   orc_prog p;
   if (prog_make(nt, with_solve, drop_edge, &p) != 0) return -1;
   int64_t info;
@@ -639,13 +701,14 @@ int64_t orc_cholesky(int64_t n, int nb, double* a, double* y, int nrhs, int orde
 
 /* The GEMM program: abc holds A, B and C (each n x n) side by side, column-major n x 3n
  * (ld = n); C is overwritten by C + A B computed tile by tile (tile size nb, n % nb == 0)
- * in the chosen order (as for orc_cholesky; nthreads > 1: thread pool).  drop_edge as for
- * orc_cholesky.  Returns 0 or -1. */
+ * in the chosen order (as for orc_cholesky; nthreads > 1: thread pool).  drop_edge and
+ * commute as for orc_cholesky.  Returns 0 or -1 (-2: a given order that is not valid). */
 int64_t orc_gemm(int64_t n, int nb, double* abc, int order, uint64_t seed, int nthreads, int64_t* order_out,
-                 const uint32_t* drop_edge, int64_t* nrun_out) {
+                 const uint32_t* drop_edge, int64_t* nrun_out, int commute) {
   if (n <= 0 || nb <= 0 || n % nb != 0 || !abc) return -1;
+  if (commute && nthreads > 1) return -1;
   orc_prog p;
-  if (prog_make((int)(n / nb), -1, drop_edge, &p) != 0) return -1;
+  if (prog_make((int)(n / nb), commute ? -2 : -1, drop_edge, &p) != 0) return -1;
   int64_t info;
   if (nthreads <= 1)
     info = exec_seq(&p, order, seed, abc, n, nb, NULL, 0, order_out, nrun_out);
@@ -656,12 +719,13 @@ int64_t orc_gemm(int64_t n, int nb, double* abc, int order, uint64_t seed, int n
 }
 
 /* Edges of the GEMM program (as orc_cholesky_dag). */
-int64_t orc_gemm_dag(int nt, uint32_t* src, uint32_t* dst, uint64_t cap, uint64_t* kinds, int64_t* ntasks_out) {
+int64_t orc_gemm_dag(int nt, int commute, uint32_t* src, uint32_t* dst, uint64_t cap, uint64_t* kinds,
+                     int64_t* ntasks_out) {
   uint64_t na = 0;
-  int64_t T = orc_gemm_program(nt, NULL, NULL, &na);
+  int64_t T = orc_gemm_program(nt, commute, NULL, NULL, &na);
   orc_access* acc = (orc_access*)malloc((na ? na : 1) * sizeof(orc_access));
   if (!acc) return -1;
-  orc_gemm_program(nt, NULL, acc, &na);
+  orc_gemm_program(nt, commute, NULL, acc, &na);
   int64_t E = orc_dag_edges((uint32_t)T, acc, na, src, dst, cap, kinds);
   free(acc);
   if (ntasks_out) *ntasks_out = T;

@@ -18,10 +18,29 @@
 namespace spx {
 
 namespace {
+// Per datum: the current writer set (the last writer, or every member of the last closed
+// commutative group), the reads since, and the open commutative group (its members and
+// the dependencies every member takes: the state before the group).
 struct DatumState {
-  int64_t last_writer = -1;
-  std::vector<uint32_t> readers;  // since the last write
+  std::vector<uint32_t> writers;
+  std::vector<uint32_t> readers;  // since the writer set
+  int64_t group = -1;             // open group id
+  std::vector<uint32_t> members, pre;
 };
+void close_group(DatumState& s) {
+  if (s.group < 0) return;
+  s.writers.swap(s.members);
+  s.members.clear();
+  s.readers.clear();
+  s.pre.clear();
+  s.group = -1;
+}
+// a task that names a datum more than once: reads and commutative writes together are an
+// ordinary write
+uint32_t merge_mode(uint32_t a, uint32_t b) {
+  if (a == b) return a;
+  return SPX_ACC_RW;
+}
 }  // namespace
 
 int build_graph(uint32_t ntasks, const spx_access* acc, uint64_t nacc, const int32_t* priority, Graph& g) {
@@ -29,15 +48,18 @@ int build_graph(uint32_t ntasks, const spx_access* acc, uint64_t nacc, const int
   g.ntasks = ntasks;
   std::unordered_map<uint64_t, DatumState> state;
   state.reserve(nacc / 2 + 16);
-  std::vector<std::pair<uint32_t, uint32_t>> edges;  // (dst, src) while building
+  std::vector<std::pair<uint32_t, uint32_t>> edges;  // (src, dst) while building
   edges.reserve(nacc * 2);
   std::vector<std::pair<uint64_t, uint32_t>> mine;  // this task's (datum, mode)
   std::vector<uint32_t> preds;
+  std::vector<std::pair<uint32_t, uint32_t>> comm;  // (task, group << 6 | slot)
+  std::vector<std::vector<uint32_t>> gmembers;      // per group: member tasks by slot
   uint64_t p = 0;
   for (uint32_t t = 0; t < ntasks; ++t) {
     mine.clear();
     while (p < nacc && acc[p].task == t) {
-      if (acc[p].mode != SPX_ACC_R && acc[p].mode != SPX_ACC_RW) return fail(SPX_EINVAL, "graph: bad access mode");
+      if (acc[p].mode != SPX_ACC_R && acc[p].mode != SPX_ACC_RW && acc[p].mode != SPX_ACC_CW)
+        return fail(SPX_EINVAL, "graph: bad access mode");
       mine.emplace_back(acc[p].datum, acc[p].mode);
       ++p;
     }
@@ -48,21 +70,34 @@ int build_graph(uint32_t ntasks, const spx_access* acc, uint64_t nacc, const int
       uint64_t d = mine[q].first;
       uint32_t mode = mine[q].second;
       while (q + 1 < mine.size() && mine[q + 1].first == d) {  // same datum named twice
-        mode = std::max(mode, mine[q + 1].second);
+        mode = merge_mode(mode, mine[q + 1].second);
         ++q;
       }
       DatumState& s = state[d];
+      if (mode == SPX_ACC_CW) {
+        if (s.group >= 0 && s.members.size() < (size_t)kGroupMax) {
+          preds.insert(preds.end(), s.pre.begin(), s.pre.end());
+        } else {
+          close_group(s);  // a full group: the next one follows all its members
+          s.pre = s.readers.empty() ? s.writers : s.readers;
+          preds.insert(preds.end(), s.pre.begin(), s.pre.end());
+          s.group = (int64_t)gmembers.size();
+          gmembers.emplace_back();
+        }
+        comm.emplace_back(t, (uint32_t)(s.group << 6) | (uint32_t)s.members.size());
+        gmembers[(size_t)s.group].push_back(t);
+        s.members.push_back(t);
+        continue;
+      }
+      close_group(s);
       if (mode == SPX_ACC_R) {
-        if (s.last_writer >= 0) preds.push_back((uint32_t)s.last_writer);
+        preds.insert(preds.end(), s.writers.begin(), s.writers.end());
         s.readers.push_back(t);
       } else {
-        if (!s.readers.empty()) {
-          preds.insert(preds.end(), s.readers.begin(), s.readers.end());
-        } else if (s.last_writer >= 0) {
-          preds.push_back((uint32_t)s.last_writer);
-        }
+        const std::vector<uint32_t>& dep = s.readers.empty() ? s.writers : s.readers;
+        preds.insert(preds.end(), dep.begin(), dep.end());
         s.readers.clear();
-        s.last_writer = t;
+        s.writers.assign(1, t);
       }
     }
     std::sort(preds.begin(), preds.end());
@@ -70,6 +105,7 @@ int build_graph(uint32_t ntasks, const spx_access* acc, uint64_t nacc, const int
     for (uint32_t s : preds) edges.emplace_back(s, t);
   }
   if (p != nacc) return fail(SPX_EINVAL, "graph: access names a task index >= ntasks");
+  if (gmembers.size() >= (1u << 26)) return fail(SPX_EINVAL, "graph: too many commutative groups");
   std::sort(edges.begin(), edges.end());  // by (src, dst)
   g.off.assign(ntasks + 1, 0);
   g.succ.resize(edges.size());
@@ -82,16 +118,39 @@ int build_graph(uint32_t ntasks, const spx_access* acc, uint64_t nacc, const int
   }
   g.prio.assign(ntasks, 0);
   if (priority) std::copy(priority, priority + ntasks, g.prio.begin());
+  if (!gmembers.empty()) {
+    // comm is in task order; within a task, by datum, so sort each task's list by group
+    g.ngroups = (uint32_t)gmembers.size();
+    g.coff.assign(ntasks + 1, 0);
+    for (auto& c : comm) g.coff[c.first + 1]++;
+    for (uint32_t t = 0; t < ntasks; ++t) g.coff[t + 1] += g.coff[t];
+    g.cent.resize(comm.size());
+    for (size_t i = 0; i < comm.size(); ++i) g.cent[i] = comm[i].second;
+    for (uint32_t t = 0; t < ntasks; ++t) std::sort(g.cent.begin() + g.coff[t], g.cent.begin() + g.coff[t + 1]);
+    g.goff.assign(g.ngroups + 1, 0);
+    for (uint32_t k = 0; k < g.ngroups; ++k) g.goff[k + 1] = g.goff[k] + (uint32_t)gmembers[k].size();
+    g.gtask.resize(g.goff[g.ngroups]);
+    g.gidx.resize(g.goff[g.ngroups]);
+    for (uint32_t t = 0; t < ntasks; ++t)
+      for (uint32_t i = g.coff[t]; i < g.coff[t + 1]; ++i) {
+        const uint32_t grp = g.cent[i] >> 6, slot = g.cent[i] & 63u;
+        g.gtask[g.goff[grp] + slot] = t;
+        g.gidx[g.goff[grp] + slot] = i - g.coff[t];
+      }
+  }
   return SPX_OK;
 }
 
 // Right-looking tile Cholesky program (lower), optionally followed by one inversion task
 // per diagonal tile and the block forward and backward substitution.  Datum ids: tile
 // (i,j) -> i*nt + j; right-hand-side block k -> nt*nt + k; M_k = L_kk^{-T} -> nt*nt + nt + k.
+// commute: the updates (SYRK and GEMM on their tile, FGEMM and BGEMM on their block of the
+// right-hand sides) are commutative writes.
 void cholesky_program(int nt, bool with_solve, std::vector<TaskDesc>& tasks, std::vector<spx_access>& acc,
-                      bool with_inverse, int potrf_steps) {
+                      bool with_inverse, int potrf_steps, bool commute) {
   tasks.clear();
   acc.clear();
+  const uint32_t UPD = commute ? SPX_ACC_CW : SPX_ACC_RW;
   auto A = [nt](int i, int j) { return (uint64_t)i * (uint64_t)nt + (uint64_t)j; };
   auto B = [nt](int k) { return (uint64_t)nt * (uint64_t)nt + (uint64_t)k; };
   auto Minv = [nt](int k) { return (uint64_t)nt * (uint64_t)nt + (uint64_t)nt + (uint64_t)k; };
@@ -127,12 +186,12 @@ void cholesky_program(int nt, bool with_solve, std::vector<TaskDesc>& tasks, std
       task(SPX_T_SYRK, i, i, k);
       if (i == k + 1) tasks.back().pad = 1;  // on the critical path: cut into finer parts
       use(SPX_ACC_R, A(i, k));
-      use(SPX_ACC_RW, A(i, i));
+      use(UPD, A(i, i));
       for (int j = k + 1; j < i; ++j) {
         task(SPX_T_GEMM, i, j, k);
         use(SPX_ACC_R, A(i, k));
         use(SPX_ACC_R, A(j, k));
-        use(SPX_ACC_RW, A(i, j));
+        use(UPD, A(i, j));
       }
     }
   }
@@ -153,7 +212,7 @@ void cholesky_program(int nt, bool with_solve, std::vector<TaskDesc>& tasks, std
         task(SPX_T_FGEMM, i, k, k);
         use(SPX_ACC_R, A(i, k));
         use(SPX_ACC_R, B(k));
-        use(SPX_ACC_RW, B(i));
+        use(UPD, B(i));
       }
     }
     for (int k = nt - 1; k >= 0; --k) {
@@ -164,7 +223,7 @@ void cholesky_program(int nt, bool with_solve, std::vector<TaskDesc>& tasks, std
         task(SPX_T_BGEMM, i, k, k);
         use(SPX_ACC_R, A(k, i));
         use(SPX_ACC_R, B(k));
-        use(SPX_ACC_RW, B(i));
+        use(UPD, B(i));
       }
     }
     return;
@@ -180,7 +239,7 @@ void cholesky_program(int nt, bool with_solve, std::vector<TaskDesc>& tasks, std
       tasks.back().pad = 1;
       use(SPX_ACC_R, A(i, k));
       use(SPX_ACC_R, Y2(k));
-      use(SPX_ACC_RW, B(i));
+      use(UPD, B(i));
     }
   }
   for (int k = nt - 1; k >= 0; --k) {
@@ -194,7 +253,7 @@ void cholesky_program(int nt, bool with_solve, std::vector<TaskDesc>& tasks, std
       tasks.back().pad = 1;
       use(SPX_ACC_R, A(k, i));
       use(SPX_ACC_R, B(k));
-      use(SPX_ACC_RW, Y2(i));
+      use(UPD, Y2(i));
     }
   }
 }
@@ -202,10 +261,10 @@ void cholesky_program(int nt, bool with_solve, std::vector<TaskDesc>& tasks, std
 // The block substitution alone (L tiles and the M_k are only read): the tasks
 // cholesky_program appends after the factor and the inversions, so its edges are the fused
 // program's edges among those tasks.
-void solve_program(int nt, std::vector<TaskDesc>& tasks, std::vector<spx_access>& acc) {
+void solve_program(int nt, std::vector<TaskDesc>& tasks, std::vector<spx_access>& acc, bool commute) {
   std::vector<TaskDesc> all;
   std::vector<spx_access> all_acc;
-  cholesky_program(nt, true, all, all_acc, true);
+  cholesky_program(nt, true, all, all_acc, true, 1, commute);
   uint32_t first = 0;
   while (all[first].type != SPX_T_FTRSM) ++first;
   tasks.assign(all.begin() + first, all.end());
@@ -214,7 +273,7 @@ void solve_program(int nt, std::vector<TaskDesc>& tasks, std::vector<spx_access>
     if (a.task >= first) acc.push_back(spx_access{a.task - first, a.mode, a.datum});
 }
 
-void gemm_program(int nt, std::vector<TaskDesc>& tasks, std::vector<spx_access>& acc) {
+void gemm_program(int nt, std::vector<TaskDesc>& tasks, std::vector<spx_access>& acc, bool commute) {
   tasks.clear();
   acc.clear();
   const uint64_t n2 = (uint64_t)nt * (uint64_t)nt;
@@ -230,7 +289,7 @@ void gemm_program(int nt, std::vector<TaskDesc>& tasks, std::vector<spx_access>&
         tasks.push_back(d);
         acc.push_back(spx_access{t, SPX_ACC_R, (uint64_t)i * nt + k});
         acc.push_back(spx_access{t, SPX_ACC_R, n2 + (uint64_t)k * nt + j});
-        acc.push_back(spx_access{t, SPX_ACC_RW, 2 * n2 + (uint64_t)i * nt + j});
+        acc.push_back(spx_access{t, commute ? (uint32_t)SPX_ACC_CW : (uint32_t)SPX_ACC_RW, 2 * n2 + (uint64_t)i * nt + j});
       }
 }
 
@@ -238,10 +297,10 @@ void gemm_program(int nt, std::vector<TaskDesc>& tasks, std::vector<spx_access>&
 // right-hand-side blocks), so each tile's first update depends on it; STORE reads the
 // solution blocks after the backward substitution.
 void io_program(int nt, bool with_solve, std::vector<TaskDesc>& tasks, std::vector<spx_access>& acc,
-                bool with_inverse, int potrf_steps) {
+                bool with_inverse, int potrf_steps, bool commute) {
   std::vector<TaskDesc> body;
   std::vector<spx_access> body_acc;
-  cholesky_program(nt, with_solve, body, body_acc, with_inverse, potrf_steps);
+  cholesky_program(nt, with_solve, body, body_acc, with_inverse, potrf_steps, commute);
   auto A = [nt](int i, int j) { return (uint64_t)i * (uint64_t)nt + (uint64_t)j; };
   auto B = [nt](int k) { return (uint64_t)nt * (uint64_t)nt + (uint64_t)k; };
   tasks.clear();
@@ -265,10 +324,10 @@ void io_program(int nt, bool with_solve, std::vector<TaskDesc>& tasks, std::vect
   }
 }
 
-void solve_io_program(int nt, std::vector<TaskDesc>& tasks, std::vector<spx_access>& acc) {
+void solve_io_program(int nt, std::vector<TaskDesc>& tasks, std::vector<spx_access>& acc, bool commute) {
   std::vector<TaskDesc> body;
   std::vector<spx_access> body_acc;
-  solve_program(nt, body, body_acc);
+  solve_program(nt, body, body_acc, commute);
   auto B = [nt](int k) { return (uint64_t)nt * (uint64_t)nt + (uint64_t)k; };
   tasks.clear();
   acc.clear();
@@ -408,8 +467,9 @@ int spx_graph_to_dot(const spx_graph* g, const char* path) {
 void spx_graph_destroy(spx_graph* g) { delete g; }
 
 int spx_cholesky_graph(int32_t nt, int32_t with_solve, spx_graph** out, int32_t* task_types, uint32_t cap) {
-  if (!out || nt < 1 || nt > 4096 || with_solve < 0 || with_solve > 0xffff || (with_solve & 0xf8))
+  if (!out || nt < 1 || nt > 4096 || with_solve < 0 || with_solve > 0xffff || (with_solve & 0xf0))
     return fail(SPX_EINVAL, "spx_cholesky_graph: bad argument");
+  const bool commute = (with_solve & 8) != 0;
   const int steps = (with_solve >> 8) ? (with_solve >> 8) : 1;  // POTRF steps, bits 8-15
   if (steps > 64) return fail(SPX_EINVAL, "spx_cholesky_graph: at most 64 POTRF steps");
   *out = nullptr;
@@ -417,9 +477,9 @@ int spx_cholesky_graph(int32_t nt, int32_t with_solve, spx_graph** out, int32_t*
     std::unique_ptr<spx_graph> g(new spx_graph());
     std::vector<spx_access> acc;
     if (with_solve & 2)
-      io_program(nt, (with_solve & 1) != 0, g->tasks, acc, (with_solve & 4) != 0, steps);
+      io_program(nt, (with_solve & 1) != 0, g->tasks, acc, (with_solve & 4) != 0, steps, commute);
     else
-      cholesky_program(nt, (with_solve & 1) != 0, g->tasks, acc, (with_solve & 4) != 0, steps);
+      cholesky_program(nt, (with_solve & 1) != 0, g->tasks, acc, (with_solve & 4) != 0, steps, commute);
     int rc = build_graph((uint32_t)g->tasks.size(), acc.data(), acc.size(), nullptr, g->g);
     if (rc) return rc;
     rank_priorities(g->tasks, g->g);
@@ -435,12 +495,15 @@ int spx_cholesky_graph(int32_t nt, int32_t with_solve, spx_graph** out, int32_t*
 }
 
 int spx_gemm_graph(int32_t nt, spx_graph** out, int32_t* task_types, uint32_t cap) {
+  // nt | SPX_GEMM_COMMUTE: the updates of C_ij are commutative writes
+  const bool commute = (nt & SPX_GEMM_COMMUTE) != 0;
+  nt &= ~SPX_GEMM_COMMUTE;
   if (!out || nt < 1 || nt > 512) return fail(SPX_EINVAL, "spx_gemm_graph: bad argument");
   *out = nullptr;
   try {
     std::unique_ptr<spx_graph> g(new spx_graph());
     std::vector<spx_access> acc;
-    gemm_program(nt, g->tasks, acc);
+    gemm_program(nt, g->tasks, acc, commute);
     int rc = build_graph((uint32_t)g->tasks.size(), acc.data(), acc.size(), nullptr, g->g);
     if (rc) return rc;
     rank_priorities(g->tasks, g->g);

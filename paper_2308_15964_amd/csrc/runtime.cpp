@@ -74,6 +74,10 @@ struct Image {
   u64* queue = nullptr;
   uint32_t* counters = nullptr;
   uint32_t* ring = nullptr;  // kXcds x total_parts finished-part entries
+  // commutative-write groups (null / 0 without them): see Graph
+  uint32_t ngroups = 0, ncroots = 0;
+  uint32_t *coff = nullptr, *cent = nullptr, *goff = nullptr, *gtask = nullptr, *gidx = nullptr, *croots = nullptr;
+  u64* gstate = nullptr;  // per group: lock bit 63, waiting members' bits 0..62
 };
 
 
@@ -139,6 +143,7 @@ struct spx_factor {
   double* minv = nullptr;  // M_k = L_kk^{-T} of every diagonal tile (nt b^2)
   double* dscale = nullptr;  // D^{-1/2} (n_pad) of a factor of the scaled, shifted matrix
   double shift = 0.0;
+  bool commute = false;  // made under SPX_F_COMMUTE: its solves use commutative updates too
 };
 
 namespace spx {
@@ -160,8 +165,9 @@ static void dev_free(spx_ctx* c, void* p) {
     (void)hipFree(p);
 }
 
-static int get_program(spx_ctx* c, char kind, int nt, const Program** out, int psteps) {
-  const std::string key = std::string(1, kind) + ":" + std::to_string(nt) + ":" + std::to_string(psteps);
+static int get_program(spx_ctx* c, char kind, int nt, const Program** out, int psteps, bool commute) {
+  const std::string key = std::string(1, kind) + ":" + std::to_string(nt) + ":" + std::to_string(psteps) +
+                          (commute ? ":c" : "");
   auto it = c->programs.find(key);
   if (it != c->programs.end()) {
     *out = it->second.get();
@@ -170,13 +176,13 @@ static int get_program(spx_ctx* c, char kind, int nt, const Program** out, int p
   std::unique_ptr<Program> pr(new Program());
   std::vector<spx_access> acc;
   switch (kind) {
-    case 'F': cholesky_program(nt, false, pr->tasks, acc, true, psteps); break;
-    case 'S': solve_program(nt, pr->tasks, acc); break;
+    case 'F': cholesky_program(nt, false, pr->tasks, acc, true, psteps, commute); break;
+    case 'S': solve_program(nt, pr->tasks, acc, commute); break;
     case 'L': io_program(nt, false, pr->tasks, acc, true, psteps); break;
     case 'P': io_program(nt, true, pr->tasks, acc, false, psteps); break;
     case 'K': io_program(nt, true, pr->tasks, acc, true, psteps); break;
     case 'Q': solve_io_program(nt, pr->tasks, acc); break;
-    case 'M': gemm_program(nt, pr->tasks, acc); break;
+    case 'M': gemm_program(nt, pr->tasks, acc, commute); break;
     default: return fail(SPX_EINVAL, "unknown program kind");
   }
   SPX_TRY(build_graph((uint32_t)pr->tasks.size(), acc.data(), acc.size(), nullptr, pr->g));
@@ -252,7 +258,7 @@ static int level_of(int32_t prio, int nlev) {
 // solves: the inversions would cost more than they save); 'K': LOAD + factor +
 // inversions + substitution with the inverses + STORE (factors kept for more solves);
 // 'Q': LOAD of the right-hand sides + substitution with the inverses + STORE.
-static int get_program(spx_ctx* c, char kind, int nt, const Program** out, int psteps = 1);
+static int get_program(spx_ctx* c, char kind, int nt, const Program** out, int psteps = 1, bool commute = false);
 
 // One matrix's share of an image: its program, descriptor index, tile size and
 // right-hand-side count (parts per task depend on both).
@@ -272,9 +278,12 @@ struct ImageHost {
   uint32_t qcap[kLevels1] = {};
   uint32_t nroots = 0;
   int nshards = 1;
-  std::vector<char> bytes;  // the static part (static_bytes)
+  std::vector<char> bytes;       // the static part (static_bytes)
+  std::vector<char> comm_bytes;  // the commutative-group arrays, uploaded at o_coff
   size_t o_tasks = 0, o_off = 0, o_succ = 0, o_indeg = 0, o_np = 0, o_q0 = 0, o_c0 = 0, static_bytes = 0;
   size_t o_pend = 0, o_pl = 0, o_q = 0, o_c = 0, o_ring = 0, total_bytes = 0;
+  uint32_t ngroups = 0, ncroots = 0;
+  size_t o_coff = 0, o_cent = 0, o_goff = 0, o_gtask = 0, o_gidx = 0, o_croots = 0, o_gstate = 0;
 };
 
 // Lays out the concatenation of the pieces' graphs (no edges between pieces) as one image.
@@ -298,8 +307,36 @@ static int build_image_host(const std::vector<Piece>& pieces, int policy, ImageH
   uint64_t per_level[kLevels1] = {};
   uint32_t t0 = 0;
   size_t e0 = 0;
+  // commutative groups of all pieces, renumbered
+  uint64_t G64 = 0, C64 = 0;
+  for (const Piece& pc : pieces) {
+    G64 += pc.p->g.ngroups;
+    C64 += pc.p->g.cent.size();
+  }
+  if (G64 >= (1ull << 26)) return fail(SPX_EINVAL, "too many commutative groups");
+  const bool comm = G64 > 0;
+  std::vector<uint32_t> coff(comm ? T + 1 : 0, 0), cent, goff(comm ? G64 + 1 : 0, 0), gtask, gidx, croots;
+  cent.reserve(C64);
+  gtask.reserve(C64);
+  gidx.reserve(C64);
+  uint32_t g0 = 0;
   for (const Piece& pc : pieces) {
     const Program& pr = *pc.p;
+    if (comm) {
+      for (uint32_t t = 0; t < pr.g.ntasks; ++t) {
+        const uint32_t n = pr.g.ngroups ? pr.g.coff[t + 1] - pr.g.coff[t] : 0;
+        coff[t0 + t + 1] = coff[t0 + t] + n;
+        for (uint32_t i = 0; i < n; ++i) cent.push_back(pr.g.cent[pr.g.coff[t] + i] + (g0 << 6));
+      }
+      for (uint32_t k = 0; k < pr.g.ngroups; ++k) {
+        goff[g0 + k + 1] = goff[g0 + k] + (pr.g.goff[k + 1] - pr.g.goff[k]);
+        for (uint32_t m = pr.g.goff[k]; m < pr.g.goff[k + 1]; ++m) {
+          gtask.push_back(t0 + pr.g.gtask[m]);
+          gidx.push_back(pr.g.gidx[m]);
+        }
+      }
+      g0 += pr.g.ngroups;
+    }
     for (uint32_t t = 0; t < pr.g.ntasks; ++t) {
       TaskDesc d = pr.tasks[t];
       d.nparts = parts_of(d, pc.b, pc.nrhs);
@@ -328,6 +365,10 @@ static int build_image_host(const std::vector<Piece>& pieces, int policy, ImageH
   uint32_t deal = 0;
   for (uint32_t t = 0; t < T; ++t) {
     if (indeg[t] != 0) continue;
+    if (comm && coff[t + 1] > coff[t]) {  // takes its locks at the start of the launch
+      croots.push_back(t);
+      continue;
+    }
     const int l = tasks[t].level;
     for (uint32_t p = 0; p < nparts[t]; ++p) {
       const int sh = (int)(deal++ % nshards);
@@ -356,7 +397,21 @@ static int build_image_host(const std::vector<Piece>& pieces, int policy, ImageH
   im.o_q = o; o = align(o + 8 * (size_t)im.total_parts * kShards);
   im.o_c = o; o = align(o + 4 * (size_t)kNumCounters);
   im.o_ring = o; o = align(o + 4 * (size_t)kXcds * im.total_parts);
+  im.ngroups = (uint32_t)G64;
+  im.ncroots = (uint32_t)croots.size();
+  if (comm) {
+    im.o_gstate = o; o = align(o + 8 * (size_t)G64);
+  }
   im.total_bytes = o;
+  if (comm) {  // static arrays after the per-launch ones, to keep the earlier offsets
+    im.o_coff = o; o = align(o + 4 * coff.size());
+    im.o_cent = o; o = align(o + 4 * std::max<size_t>(cent.size(), 1));
+    im.o_goff = o; o = align(o + 4 * goff.size());
+    im.o_gtask = o; o = align(o + 4 * std::max<size_t>(gtask.size(), 1));
+    im.o_gidx = o; o = align(o + 4 * std::max<size_t>(gidx.size(), 1));
+    im.o_croots = o; o = align(o + 4 * std::max<size_t>(croots.size(), 1));
+    im.total_bytes = o;
+  }
   im.bytes.assign(im.static_bytes, 0);
   char* h = im.bytes.data();
   std::memcpy(h + im.o_tasks, tasks.data(), sizeof(TaskDesc) * T);
@@ -366,6 +421,16 @@ static int build_image_host(const std::vector<Piece>& pieces, int policy, ImageH
   std::memcpy(h + im.o_np, nparts.data(), 4 * (size_t)T);
   std::memcpy(h + im.o_q0, roots.data(), 8 * roots.size());
   std::memcpy(h + im.o_c0, counters0.data(), 4 * (size_t)kNumCounters);
+  if (comm) {
+    im.comm_bytes.assign(im.total_bytes - im.o_coff, 0);
+    char* c = im.comm_bytes.data() - im.o_coff;  // addressed by image offsets
+    std::memcpy(c + im.o_coff, coff.data(), 4 * coff.size());
+    std::memcpy(c + im.o_cent, cent.data(), 4 * cent.size());
+    std::memcpy(c + im.o_goff, goff.data(), 4 * goff.size());
+    std::memcpy(c + im.o_gtask, gtask.data(), 4 * gtask.size());
+    std::memcpy(c + im.o_gidx, gidx.data(), 4 * gidx.size());
+    std::memcpy(c + im.o_croots, croots.data(), 4 * croots.size());
+  }
   return SPX_OK;
 }
 
@@ -393,6 +458,17 @@ static void bind_image(const ImageHost& h, char* base, Image* im) {
   im->queue = (u64*)(base + h.o_q);
   im->counters = (uint32_t*)(base + h.o_c);
   im->ring = (uint32_t*)(base + h.o_ring);
+  im->ngroups = h.ngroups;
+  im->ncroots = h.ncroots;
+  if (h.ngroups) {
+    im->gstate = (u64*)(base + h.o_gstate);
+    im->coff = (uint32_t*)(base + h.o_coff);
+    im->cent = (uint32_t*)(base + h.o_cent);
+    im->goff = (uint32_t*)(base + h.o_goff);
+    im->gtask = (uint32_t*)(base + h.o_gtask);
+    im->gidx = (uint32_t*)(base + h.o_gidx);
+    im->croots = (uint32_t*)(base + h.o_croots);
+  }
 }
 
 // Uploads the concatenation of the pieces' graphs (no edges between pieces) as one
@@ -406,6 +482,9 @@ static int make_image(spx_ctx* c, const std::vector<Piece>& pieces, int policy, 
   bind_image(h, (char*)im->block, im.get());
   // synchronous copy: the host vector is freed on return
   int rc = hipc(hipMemcpy(im->block, h.bytes.data(), h.static_bytes, hipMemcpyHostToDevice), "image upload");
+  if (!rc && h.ngroups)
+    rc = hipc(hipMemcpy((char*)im->block + h.o_coff, h.comm_bytes.data(), h.comm_bytes.size(), hipMemcpyHostToDevice),
+              "image upload");
   if (rc) {
     dev_free(c, im->block);
     return rc;
@@ -416,17 +495,19 @@ static int make_image(spx_ctx* c, const std::vector<Piece>& pieces, int policy, 
 
 // Builds (or returns the cached) device image of the factor (solve == false) or solve
 // program for nt x nt tiles of size b.
-static int get_image(spx_ctx* c, bool solve, int nt, int b, int nrhs, int policy, Image** out) {
+static int get_image(spx_ctx* c, bool solve, int nt, int b, int nrhs, int policy, Image** out,
+                     bool commute = false) {
   char key[96];
   const int rhs_parts = (nrhs + 7) / 8;
-  std::snprintf(key, sizeof key, "%c:%d:%d:%d:%d", solve ? 'S' : 'F', nt, b, solve ? rhs_parts : 0, policy);
+  std::snprintf(key, sizeof key, "%c:%d:%d:%d:%d:%d", solve ? 'S' : 'F', nt, b, solve ? rhs_parts : 0, policy,
+                commute ? 1 : 0);
   auto it = c->images.find(key);
   if (it != c->images.end()) {
     *out = it->second;
     return SPX_OK;
   }
   const Program* pr = nullptr;
-  SPX_TRY(get_program(c, solve ? 'S' : 'F', nt, &pr, solve ? 1 : potrf_steps_of(nt, b)));
+  SPX_TRY(get_program(c, solve ? 'S' : 'F', nt, &pr, solve ? 1 : potrf_steps_of(nt, b), commute));
   Image* im = nullptr;
   SPX_TRY(make_image(c, {Piece{pr, 0, b, nrhs}}, policy, &im));
   c->images[key] = im;
@@ -483,8 +564,8 @@ static int run_image(spx_ctx* c, Image* im, int nmats, const spx_opts* o, double
                "descriptor upload"));
   SPX_TRY(launch_sched_init_full(im->pending, im->indeg, im->parts_left, im->nparts, im->ntasks, im->queue,
                                  im->total_parts * kShards, im->roots, im->nroots, im->counters, im->counters0,
-                                 kNumCounters, im->ring, kXcds * im->total_parts, c->dinfo, nmats,
-                                 trace ? c->trace_idx : nullptr, c->stream));
+                                 kNumCounters, im->ring, kXcds * im->total_parts, im->gstate, im->ngroups, c->dinfo,
+                                 nmats, trace ? c->trace_idx : nullptr, c->stream));
   SchedArgs a{};
   a.tasks = im->tasks;
   a.succ_off = im->succ_off;
@@ -495,6 +576,14 @@ static int run_image(spx_ctx* c, Image* im, int nmats, const spx_opts* o, double
   a.counters = im->counters;
   a.ring = im->ring;
   a.ring_cap = im->total_parts;
+  a.coff = im->coff;
+  a.cent = im->cent;
+  a.goff = im->goff;
+  a.gtask = im->gtask;
+  a.gidx = im->gidx;
+  a.gstate = im->gstate;
+  a.croots = im->croots;
+  a.ncroots = im->ncroots;
   for (int l = 0; l < kLevels1; ++l) {
     a.qbase[l] = im->qbase[l];
     a.qcap[l] = im->qcap[l];
@@ -708,6 +797,7 @@ static int batched(spx_ctx* c, int count, const int64_t* n, const double* const*
   if (policy != SPX_Q_PRIORITY && policy != SPX_Q_FIFO && policy != SPX_Q_SHARDED) return failf(SPX_EINVAL, "%s: bad queue policy", who);
   if (o && o->tile > 0 && !valid_tile(o->tile)) return failf(SPX_EINVAL, "%s: bad tile size", who);
   if (o && (o->flags & SPX_F_SCALED)) return failf(SPX_EINVAL, "%s: scaled factors are single-matrix only", who);
+  if (o && (o->flags & SPX_F_COMMUTE)) return failf(SPX_EINVAL, "%s: commutative updates are single-matrix only", who);
   std::vector<int> bs(count), nts(count), qs(count, 0);
   for (int m = 0; m < count; ++m) {
     if (n[m] < 1 || lda[m] < n[m] || !dA[m]) return failf(SPX_EINVAL, "%s: matrix %d: bad n, lda or pointer", who, m);
@@ -1181,7 +1271,8 @@ int spx_potrf_tiled(spx_ctx* c, int64_t n, const double* dA, int64_t lda, const 
     dev_free(c, f->dscale);
   };
   Image* im = nullptr;
-  int rc = get_image(c, false, (int)nt, b, 0, policy, &im);
+  f->commute = opts && (opts->flags & SPX_F_COMMUTE);
+  int rc = get_image(c, false, (int)nt, b, 0, policy, &im, f->commute);
   if (!rc) rc = ensure_small_buffers(c, 1, 1, 0, false);
   if (!rc && scaled) {
     f->shift = opts->shift;
@@ -1251,7 +1342,8 @@ int spx_gemm_tiled(spx_ctx* c, int64_t n, const double* dA, int64_t lda, const d
     double* tbt = (double*)(block + tile_bytes);
     double* tc = (double*)(block + 2 * tile_bytes);
     char key[96];
-    std::snprintf(key, sizeof key, "M:%d:%d:%d", (int)nt, b, policy);
+    const bool commute = opts && (opts->flags & SPX_F_COMMUTE);
+    std::snprintf(key, sizeof key, "M:%d:%d:%d:%d", (int)nt, b, policy, commute ? 1 : 0);
     Image* im = nullptr;
     int rc = SPX_OK;
     auto it = c->images.find(key);
@@ -1259,7 +1351,7 @@ int spx_gemm_tiled(spx_ctx* c, int64_t n, const double* dA, int64_t lda, const d
       im = it->second;
     } else {
       const Program* pr = nullptr;
-      rc = get_program(c, 'M', (int)nt, &pr);
+      rc = get_program(c, 'M', (int)nt, &pr, 1, commute);
       if (!rc) rc = make_image(c, {Piece{pr, 0, b, 0}}, policy, &im);
       if (!rc) {
         im->family = FAM_GEMM;
@@ -1380,7 +1472,7 @@ void spx_factor_destroy(spx_factor* f) {
 // rhs2: a second one of the same shape that the diagonal solves write).
 static int solve_on(spx_ctx* c, const spx_factor* f, int64_t nrhs, double* rhs, double* rhs2) {
   Image* im = nullptr;
-  SPX_TRY(get_image(c, true, f->nt, f->b, (int)nrhs, SPX_Q_SHARDED, &im));
+  SPX_TRY(get_image(c, true, f->nt, f->b, (int)nrhs, SPX_Q_SHARDED, &im, f->commute));
   SPX_TRY(ensure_small_buffers(c, 1, 1, 0, false));
   DevMat m{};
   m.tiles = f->tiles;
@@ -1691,11 +1783,11 @@ int spx_potrs_noalloc(spx_ctx* c, const spx_factor* f, int64_t nrhs, const doubl
     SPX_TRY(scratch_get(c->device, &sp));
     // the host image of the solve graph (host memory only), cached by shape
     char key[96];
-    std::snprintf(key, sizeof key, "S:%d:%d:%d", f->nt, f->b, (int)((nrhs + 7) / 8));
+    std::snprintf(key, sizeof key, "S:%d:%d:%d:%d", f->nt, f->b, (int)((nrhs + 7) / 8), f->commute ? 1 : 0);
     std::shared_ptr<ImageHost>& h = c->host_images[key];
     if (!h) {
       const Program* pr = nullptr;
-      SPX_TRY(get_program(c, 'S', f->nt, &pr));
+      SPX_TRY(get_program(c, 'S', f->nt, &pr, 1, f->commute));
       std::shared_ptr<ImageHost> nh(new ImageHost());
       SPX_TRY(build_image_host({Piece{pr, 0, f->b, (int)nrhs}}, SPX_Q_SHARDED, *nh));
       h = nh;
@@ -1729,11 +1821,16 @@ int spx_potrs_noalloc(spx_ctx* c, const spx_factor* f, int64_t nrhs, const doubl
     m.trsm_rows = trsm_rows_of(f->b);
     hipStream_t st = c->stream;
     SPX_TRY(hipc(hipMemcpyAsync(base, h->bytes.data(), h->static_bytes, hipMemcpyHostToDevice, st), "image upload"));
+    if (h->ngroups)
+      SPX_TRY(hipc(hipMemcpyAsync(base + h->o_coff, h->comm_bytes.data(), h->comm_bytes.size(),
+                                  hipMemcpyHostToDevice, st),
+                   "image upload"));
     SPX_TRY(hipc(hipMemcpyAsync(base + o_mat, &m, sizeof m, hipMemcpyHostToDevice, st), "descriptor upload"));
     SPX_TRY(launch_rhs_in(dB, ldb, f->n, nrhs, m.rhs, f->n_pad, f->dscale, st));
     SPX_TRY(launch_sched_init_full(im.pending, im.indeg, im.parts_left, im.nparts, im.ntasks, im.queue,
                                    im.total_parts * kShards, im.roots, im.nroots, im.counters, im.counters0,
-                                   kNumCounters, im.ring, kXcds * im.total_parts, m.info, 1, nullptr, st));
+                                   kNumCounters, im.ring, kXcds * im.total_parts, im.gstate, im.ngroups, m.info, 1,
+                                   nullptr, st));
     SchedArgs a{};
     a.tasks = im.tasks;
     a.succ_off = im.succ_off;
@@ -1744,6 +1841,14 @@ int spx_potrs_noalloc(spx_ctx* c, const spx_factor* f, int64_t nrhs, const doubl
     a.counters = im.counters;
     a.ring = im.ring;
     a.ring_cap = im.total_parts;
+    a.coff = im.coff;
+    a.cent = im.cent;
+    a.goff = im.goff;
+    a.gtask = im.gtask;
+    a.gidx = im.gidx;
+    a.gstate = im.gstate;
+    a.croots = im.croots;
+    a.ncroots = im.ncroots;
     for (int l = 0; l < kLevels1; ++l) {
       a.qbase[l] = im.qbase[l];
       a.qcap[l] = im.qcap[l];

@@ -15,12 +15,21 @@ int fail(int code, const char* msg);
 int failf(int code, const char* fmt, ...);
 
 // Immediate-dependency graph in CSR form (successors), with in-degrees and priorities.
+// Commutative-write groups: a run of at most kGroupMax consecutive commutative writes of
+// one datum; its members may run in any order, one at a time.
+constexpr int kGroupMax = 63;
 struct Graph {
   uint32_t ntasks = 0;
   std::vector<uint64_t> off;  // ntasks + 1
   std::vector<uint32_t> succ;
   std::vector<uint32_t> indeg;
   std::vector<int32_t> prio;
+  // commutative writes (empty when the graph has none): task t's groups are
+  // cent[coff[t] .. coff[t+1]) = (group << 6) | slot, by increasing group (the order the
+  // task takes their locks in); group g's members are gtask/gidx[goff[g] .. goff[g+1])
+  // (slot s = member goff[g] + s; gidx = the entry's index within its task's list)
+  uint32_t ngroups = 0;
+  std::vector<uint32_t> coff, cent, goff, gtask, gidx;
 };
 
 // Device task descriptor (16 bytes).  `level` is the ready-queue level (0 = served
@@ -41,19 +50,20 @@ int build_graph(uint32_t ntasks, const spx_access* acc, uint64_t nacc, const int
 // potrf_steps > 1: each POTRF(k) becomes that many chained step tasks (TaskDesc.pad =
 // step | (potrf_steps << 8)); the device splits the diagonal factorization at 32 columns
 // per step, so potrf_steps must be b / 32.
+// commute (every program): the updates are commutative writes.
 void cholesky_program(int nt, bool with_solve, std::vector<TaskDesc>& tasks, std::vector<spx_access>& acc,
-                      bool with_inverse = false, int potrf_steps = 1);
-void solve_program(int nt, std::vector<TaskDesc>& tasks, std::vector<spx_access>& acc);
+                      bool with_inverse = false, int potrf_steps = 1, bool commute = false);
+void solve_program(int nt, std::vector<TaskDesc>& tasks, std::vector<spx_access>& acc, bool commute = false);
 // The tiled matrix product C += A B (k outermost, then i, then j).
-void gemm_program(int nt, std::vector<TaskDesc>& tasks, std::vector<spx_access>& acc);
+void gemm_program(int nt, std::vector<TaskDesc>& tasks, std::vector<spx_access>& acc, bool commute = false);
 // Sets g.prio to the upward-rank priorities of the program's tasks.
 void rank_priorities(const std::vector<TaskDesc>& tasks, Graph& g);
 // LOAD, the factor program (and with_solve: the substitution), STORE (with_solve only);
 // with_inverse: the inversion tasks and the inverse-based substitution.
 void io_program(int nt, bool with_solve, std::vector<TaskDesc>& tasks, std::vector<spx_access>& acc,
-                bool with_inverse, int potrf_steps = 1);
+                bool with_inverse, int potrf_steps = 1, bool commute = false);
 // LOAD of the right-hand sides only (TaskDesc.j = 1), the substitution, STORE.
-void solve_io_program(int nt, std::vector<TaskDesc>& tasks, std::vector<spx_access>& acc);
+void solve_io_program(int nt, std::vector<TaskDesc>& tasks, std::vector<spx_access>& acc, bool commute = false);
 
 // ---------------------------------------------------------------------------------------
 // Device-side descriptors (plain data, copied to the GPU).
@@ -122,6 +132,17 @@ struct SchedArgs {
   uint32_t* counters;        // ctr_queue_idx / kStatusIdx / ctr_ring_*_idx
   uint32_t* ring;            // per XCD x: ring_cap task ids at x * ring_cap (finished parts awaiting release)
   uint32_t ring_cap;
+  // commutative-write groups (coff null without them; layout as in Graph): a task with
+  // commutative accesses takes its groups' locks, in group order, once it is ready, and
+  // is pushed when it holds all of them
+  const uint32_t* coff;
+  const uint32_t* cent;
+  const uint32_t* goff;
+  const uint32_t* gtask;
+  const uint32_t* gidx;
+  unsigned long long* gstate;  // per group: lock bit 63, waiting members' bits 0..62
+  const uint32_t* croots;      // root tasks with commutative accesses (take their locks at the start)
+  uint32_t ncroots;
   uint32_t qbase[kLevels1];
   uint32_t qcap[kLevels1];
   uint32_t total_parts;
@@ -163,7 +184,8 @@ int launch_sched_init_full(uint32_t* pending, const uint32_t* indeg, uint32_t* p
                            uint32_t ntasks, unsigned long long* queue, uint32_t queue_len,
                            const unsigned long long* roots, uint32_t nroots, uint32_t* counters,
                            const uint32_t* counters0, uint32_t ncounters, uint32_t* ring, uint32_t ring_len,
-                           int32_t* info, int ninfo, uint32_t* trace_idx, void* stream);
+                           unsigned long long* gstate, uint32_t ngroups, int32_t* info, int ninfo,
+                           uint32_t* trace_idx, void* stream);
 // Task families of the scheduler kernel (one instantiation each): FAM_CHOL runs every
 // task of the Cholesky, solve, batched and served graphs; FAM_GEMM the tiled product's;
 // FAM_SPIN the empty tasks of spx_run_graph.

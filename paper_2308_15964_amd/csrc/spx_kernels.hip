@@ -1681,6 +1681,93 @@ __device__ __forceinline__ int pop_wave(const SchedArgs& a, int home, bool* saw,
   return k;
 }
 
+// ---------------------------------------------------------------------------------------
+// Commutative writes (Sec. 4.1, Sec. 4.7).  The members of a group may run in any order
+// but one at a time.  The group's whole state is one 64-bit word: bit 63 = a member holds
+// the lock, bit s (s < 63) = member s is ready and waiting for it.  Every change is one
+// atomic operation on that word, so a waiter and a releaser cannot miss each other: a
+// waiter that finds the lock held stays in the word, and the holder's release hands the
+// lock to the lowest waiting member (or clears it when none waits).  A task with several
+// commutative data takes their locks one by one in increasing group order, holding the
+// earlier ones while it waits for a later one (ordered acquisition: no cycle of waits);
+// it is pushed into a ready queue when it holds all of them, and releases them when its
+// last part is done.  One thread runs these steps; a grant made for another task is
+// followed by the thread that made it.
+// ---------------------------------------------------------------------------------------
+constexpr u64 kLockBit = 1ull << 63;
+
+// Takes the free lock for the lowest waiting member: its slot + 1, or 0 (lock held, or no
+// waiter).
+__device__ __forceinline__ uint32_t grant_free_lock(u64* st) {
+  u64 cur = __hip_atomic_load(st, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  for (;;) {
+    const u64 w = cur & ~kLockBit;
+    if ((cur & kLockBit) || !w) return 0u;
+    const int s = __ffsll((long long)w) - 1;
+    if (__hip_atomic_compare_exchange_strong(st, &cur, (cur | kLockBit) & ~(1ull << s), __ATOMIC_RELAXED,
+                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+      return (uint32_t)s + 1u;
+  }
+}
+
+// The holder gives the lock up: to the lowest waiting member (its slot + 1 is returned)
+// or, with none waiting, back to free (0).
+__device__ __forceinline__ uint32_t hand_over_lock(u64* st) {
+  u64 cur = __hip_atomic_load(st, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  for (;;) {
+    const u64 w = cur & ~kLockBit;
+    const int s = w ? __ffsll((long long)w) - 1 : -1;
+    const u64 nv = w ? (cur & ~(1ull << s)) : (cur & ~kLockBit);
+    if (__hip_atomic_compare_exchange_strong(st, &cur, nv, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT))
+      return (uint32_t)(s + 1);
+  }
+}
+
+// Task t, holding the locks of its commutative entries before j, waits for the next ones
+// in order; pushes it once it holds them all.  Returns a grant this thread made for
+// another member, (group << 6 | slot) + 1, to follow next, or 0.
+__device__ uint32_t take_locks_from(const SchedArgs& a, uint32_t t, uint32_t j, int home) {
+  const uint32_t c1 = a.coff[t + 1];
+  for (uint32_t i = a.coff[t] + j; i < c1; ++i) {
+    const uint32_t e = a.cent[i], g = e >> 6, s = e & 63u;
+    u64* st = a.gstate + g;
+    const u64 old = __hip_atomic_fetch_or(st, 1ull << s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (old & kLockBit) return 0u;  // waits in the word: the holder hands it over
+    const uint32_t w = grant_free_lock(st);
+    if (w == 0u) return 0u;                     // another thread took it (perhaps for t)
+    if (w - 1u != s) return ((g << 6) | (w - 1u)) + 1u;  // granted to another member
+  }
+  push_task(a, t, home);
+  return 0u;
+}
+
+__device__ void follow_grants(const SchedArgs& a, uint32_t grant, int home) {
+  while (grant) {
+    const uint32_t e = grant - 1u, m = a.goff[e >> 6] + (e & 63u);
+    grant = take_locks_from(a, a.gtask[m], a.gidx[m] + 1u, home);
+  }
+}
+
+// A task whose last predecessor just finished: pushed, or first through its locks.
+__device__ __forceinline__ void start_task(const SchedArgs& a, uint32_t t, int home) {
+  if (!a.coff || a.coff[t] == a.coff[t + 1]) {
+    push_task(a, t, home);
+    return;
+  }
+  follow_grants(a, take_locks_from(a, t, 0u, home), home);
+}
+
+// A task whose last part was just released: its locks go to the next waiting members.
+__device__ __forceinline__ void drop_locks(const SchedArgs& a, uint32_t t, int home) {
+  if (!a.coff) return;
+  for (uint32_t i = a.coff[t]; i < a.coff[t + 1]; ++i) {
+    const uint32_t g = a.cent[i] >> 6;
+    const uint32_t w = hand_over_lock(a.gstate + g);
+    if (w) follow_grants(a, ((g << 6) | (w - 1u)) + 1u, home);
+  }
+}
+
 // The release rounds of XCD x (see the memory-ordering notes above), run by the 64 lanes
 // of one wave: each lane takes one ring entry at a time (its parts_left decrement and,
 // for a task's last part, the successors' decrements and pushes).
@@ -1719,9 +1806,10 @@ __device__ __noinline__ void release_rounds(const SchedArgs& a, int x, int home)
           __builtin_amdgcn_s_sleep(1);
         }
         if (task == EMPTY32 || sub_rlx(a.parts_left + task, 1u) != 1u) continue;
+        drop_locks(a, task, home);
         for (uint32_t q = a.succ_off[task]; q < a.succ_off[task + 1]; ++q) {
           const uint32_t s = a.succ[q];
-          if (sub_rlx(a.pending + s, 1u) == 1u) push_task(a, s, home);
+          if (sub_rlx(a.pending + s, 1u) == 1u) start_task(a, s, home);
         }
       }
       h = t;
@@ -1748,6 +1836,10 @@ __global__ __launch_bounds__(NT) void sched_kernel(SchedArgs a) {
   const int tid = threadIdx.x;
   const int home = blockIdx.x % a.nshards;
   u64 idle = 0, busy = 0;
+  // root tasks with commutative accesses take their locks first (the queues hold the
+  // other roots already)
+  if (blockIdx.x == 0 && tid == 0)
+    for (uint32_t r = 0; r < a.ncroots; ++r) start_task(a, a.croots[r], home);
   for (;;) {
     if (tid < 64) {
       const u64 t0 = now_ticks();
@@ -1875,7 +1967,8 @@ __global__ __launch_bounds__(NT) void tile_inverses_kernel(const double* l, int 
 __global__ void sched_init_kernel(uint32_t* pending, const uint32_t* indeg, uint32_t* parts_left,
                                   const uint32_t* nparts, uint32_t ntasks, u64* queue, uint32_t queue_len,
                                   uint32_t* counters, const uint32_t* counters0, uint32_t ncounters,
-                                  uint32_t* ring, uint32_t ring_len, int32_t* info, int ninfo, uint32_t* trace_idx) {
+                                  uint32_t* ring, uint32_t ring_len, u64* gstate, uint32_t ngroups, int32_t* info,
+                                  int ninfo, uint32_t* trace_idx) {
   const uint32_t stride = gridDim.x * blockDim.x;
   const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
   for (uint32_t t = g; t < ntasks; t += stride) {
@@ -1885,6 +1978,7 @@ __global__ void sched_init_kernel(uint32_t* pending, const uint32_t* indeg, uint
   for (uint32_t t = g; t < queue_len; t += stride) queue[t] = EMPTY;
   for (uint32_t t = g; t < ncounters; t += stride) counters[t] = counters0[t];
   for (uint32_t t = g; t < ring_len; t += stride) ring[t] = EMPTY32;
+  for (uint32_t t = g; t < ngroups; t += stride) gstate[t] = 0ull;
   for (uint32_t t = g; t < (uint32_t)ninfo; t += stride) info[t] = INT_MAX;
   if (g == 0 && trace_idx) *trace_idx = 0;
 }
@@ -2297,10 +2391,11 @@ int launch_sched_init_full(uint32_t* pending, const uint32_t* indeg, uint32_t* p
                            uint32_t ntasks, unsigned long long* queue, uint32_t queue_len,
                            const unsigned long long* roots, uint32_t nroots, uint32_t* counters,
                            const uint32_t* counters0, uint32_t ncounters, uint32_t* ring, uint32_t ring_len,
-                           int32_t* info, int ninfo, uint32_t* trace_idx, void* stream) {
+                           unsigned long long* gstate, uint32_t ngroups, int32_t* info, int ninfo,
+                           uint32_t* trace_idx, void* stream) {
   hipLaunchKernelGGL(sched_init_kernel, dim3(1024), dim3(NT), 0, (hipStream_t)stream, pending, indeg, parts_left,
-                     nparts, ntasks, queue, queue_len, counters, counters0, ncounters, ring, ring_len, info, ninfo,
-                     trace_idx);
+                     nparts, ntasks, queue, queue_len, counters, counters0, ncounters, ring, ring_len, gstate,
+                     ngroups, info, ninfo, trace_idx);
   const int rc = hip_ok(hipGetLastError(), "sched_init_kernel");
   if (rc) return rc;
   hipLaunchKernelGGL(roots_kernel, dim3(256), dim3(NT), 0, (hipStream_t)stream, queue, roots, nroots);

@@ -13,13 +13,14 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libspx.so")
 
 SPX_OK, SPX_EINVAL, SPX_ENOMEM, SPX_EDEVICE, SPX_EAGAIN, SPX_EABORT, SPX_ETIMEOUT = 0, -1, -2, -3, -4, -5, -6
-ACC_R, ACC_RW = 1, 2
+ACC_R, ACC_RW, ACC_CW = 1, 2, 3
 T_POTRF, T_TRSM, T_SYRK, T_GEMM, T_FTRSM, T_FGEMM, T_BTRSM, T_BGEMM, T_LOAD, T_STORE, T_INV = range(11)
 TASK_NAMES = ["POTRF", "TRSM", "SYRK", "GEMM", "FTRSM", "FGEMM", "BTRSM", "BGEMM", "LOAD", "STORE", "INV"]
 TILE_CANDIDATES = [32, 64, 128, 256, 512]
 PREC_FP64, PREC_FP32, PREC_BF16 = 0, 1, 2
 Q_SHARDED, Q_PRIORITY, Q_FIFO = 0, 1, 2
-F_TRACE, F_SCALED = 1, 2
+F_TRACE, F_SCALED, F_COMMUTE = 1, 2, 4
+GEMM_COMMUTE = 1 << 16
 
 
 class SpxError(RuntimeError):
@@ -201,11 +202,11 @@ class Graph:
         return cls(h.value)
 
     @classmethod
-    def cholesky(cls, nt, with_solve=False, io=False, inverse=False, potrf_steps=1):
+    def cholesky(cls, nt, with_solve=False, io=False, inverse=False, potrf_steps=1, commute=False):
         """The paper's program; io: with LOAD in front (and STORE at the end with the
         solve), as the batched calls run it; inverse: with the inversion tasks INV(k) after
         the factor and the substitution that uses them; potrf_steps > 1: each POTRF(k) as
-        that many chained step tasks."""
+        that many chained step tasks; commute: the updates as commutative writes."""
         h = ctypes.c_void_p()
         from math import comb
         T = nt + 2 * comb(nt, 2) + comb(nt, 3) + (2 * (nt + comb(nt, 2)) if with_solve else 0)
@@ -215,16 +216,16 @@ class Graph:
             T += nt
         T += nt * (potrf_steps - 1)
         types = (ctypes.c_int32 * T)()
-        flag = int(bool(with_solve)) | (2 if io else 0) | (4 if inverse else 0) | (potrf_steps << 8)
+        flag = int(bool(with_solve)) | (2 if io else 0) | (4 if inverse else 0) | (8 if commute else 0) | (potrf_steps << 8)
         _check(lib().spx_cholesky_graph(nt, flag, ctypes.byref(h), types, T))
         return cls(h.value, np.array(types[:], dtype=np.int32))
 
     @classmethod
-    def gemm(cls, nt):
+    def gemm(cls, nt, commute=False):
         """The tiled matrix product's program (spx_gemm_graph)."""
         h = ctypes.c_void_p()
         types = (ctypes.c_int32 * (nt ** 3))()
-        _check(lib().spx_gemm_graph(nt, ctypes.byref(h), types, nt ** 3))
+        _check(lib().spx_gemm_graph(nt | (GEMM_COMMUTE if commute else 0), ctypes.byref(h), types, nt ** 3))
         return cls(h.value, np.array(types[:], dtype=np.int32))
 
     def info(self):

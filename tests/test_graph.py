@@ -42,6 +42,42 @@ def test_cholesky_graph_bit_exact(nt, with_solve):
     assert [spx.TASK_NAMES[t] for t in g.task_types] == [t[0] for t in tasks]
 
 
+@pytest.mark.parametrize("seed", range(200))
+def test_random_commutative_programs_bit_exact(seed):
+    rs = np.random.default_rng(7000 + seed)
+    ntasks = int(rs.integers(1, 40))
+    acc = []
+    for t in range(ntasks):
+        for _ in range(rs.integers(1, 4)):
+            acc.append((t, int(rs.choice([1, 2, 3, 3])), int(rs.integers(0, int(rs.integers(1, 9))))))
+    want, _ = oracle.dag_edges(ntasks, acc)
+    g = spx.Graph.build(ntasks, acc)
+    assert np.array_equal(g.edges(), want)
+    assert np.array_equal(g.indegree(), np.bincount(want[:, 1], minlength=ntasks).astype(np.uint32))
+
+
+def test_long_commutative_run_cut_like_the_oracle():
+    acc = [(t, 3, 9) for t in range(130)] + [(130, 1, 9)]
+    want, _ = oracle.dag_edges(131, acc)
+    assert np.array_equal(spx.Graph.build(131, acc).edges(), want)
+
+
+@pytest.mark.parametrize("nt", [1, 2, 3, 5, 8, 13])
+@pytest.mark.parametrize("with_solve", [False, True])
+def test_cholesky_graph_commute_bit_exact(nt, with_solve):
+    T, want, _ = oracle.cholesky_dag(nt, with_solve, commute=True)
+    g = spx.Graph.cholesky(nt, with_solve, commute=True)
+    assert g.info() == (T, len(want))
+    assert np.array_equal(g.edges(), want)
+
+
+@pytest.mark.parametrize("nt", [1, 3, 6])
+def test_gemm_graph_commute(nt):
+    T, want, _ = oracle.gemm_dag(nt, commute=True)
+    g = spx.Graph.gemm(nt, commute=True)
+    assert g.info() == (T, len(want)) == (nt ** 3, 0)
+
+
 def test_cholesky_graph_nt64_counts():
     nt = 64
     g = spx.Graph.cholesky(nt)
@@ -67,7 +103,7 @@ def test_priorities_and_dot(tmp_path):
 
 def test_invalid_inputs_rejected():
     with pytest.raises(spx.SpxError) as e:
-        spx.Graph.build(2, [(0, 3, 1)])
+        spx.Graph.build(2, [(0, 4, 1)])
     assert e.value.code == spx.SPX_EINVAL
     with pytest.raises(spx.SpxError):
         spx.Graph.build(2, [(5, 1, 1)])
