@@ -81,6 +81,7 @@ def parse():
     p.add_argument("--skip-batched", action="store_true")
     p.add_argument("--skip-serving", action="store_true")
     p.add_argument("--skip-overhead", action="store_true")
+    p.add_argument("--skip-commute", action="store_true")
     p.add_argument("--mixed-n", type=int, default=32768)
     p.add_argument("--batch-count", type=int, default=4096)
     p.add_argument("--serve-requests", type=int, default=4000)
@@ -442,6 +443,54 @@ def bench_serving(ctx, count, rate, lanes, seed=8):
     return res
 
 
+def bench_commute(ctx, A, B, n, b, reps=3):
+    """Commutative updates (Sec. 4.1; SPX_F_COMMUTE) against insertion-ordered ones on the
+    headline factor and solve and on the tiled product: kernel times, and how far two
+    commutative runs (and a commutative and a plain run) differ, since the update order,
+    and so the rounding, now changes from launch to launch."""
+    import numpy as np
+    import torch
+
+    from paper_2308_15964_amd import spx
+
+    res = {"workload": f"N={n}, tile {b}: factor + 1-RHS solve, and the tiled product C += A B of "
+                       f"N x N matrices; updates of a tile as commutative writes vs chained in insertion order"}
+    Ls = {}
+    for name, flags in (("plain", 0), ("commutative", spx.F_COMMUTE)):
+        kf, ks = [], []
+        for r in range(reps + 1):
+            F = ctx.potrf(A, tile=b, flags=flags)
+            f_ms = ctx.stats()["kernel_ms"]
+            X = ctx.potrs(F, B)
+            s_ms = ctx.stats()["kernel_ms"]
+            if r > 0:
+                kf.append(f_ms)
+                ks.append(s_ms)
+            if r >= reps - 1:
+                Ls.setdefault(name, []).append(F.L()[::97, ::89].cpu().numpy())
+            F.close()
+        res[name] = {"factor_kernel_ms": round(float(np.median(kf)), 3),
+                     "solve_kernel_ms": round(float(np.median(ks)), 3)}
+    res["max_abs_diff_two_commutative_runs_sampled"] = float(np.abs(Ls["commutative"][0] - Ls["commutative"][1]).max())
+    res["max_abs_diff_commutative_vs_plain_sampled"] = float(np.abs(Ls["commutative"][-1] - Ls["plain"][-1]).max())
+    g = torch.Generator(device="cuda:0").manual_seed(5)
+    Ga = torch.randn((n, n), dtype=torch.float64, device="cuda:0", generator=g)
+    Gb = torch.randn((n, n), dtype=torch.float64, device="cuda:0", generator=g)
+    Gc = torch.zeros((n, n), dtype=torch.float64, device="cuda:0")
+    for name, flags in (("plain", 0), ("commutative", spx.F_COMMUTE)):
+        ks = []
+        for r in range(3):
+            ctx.gemm(Ga, Gb, Gc, tile=b, flags=flags)
+            if r > 0:
+                ks.append(ctx.stats()["kernel_ms"])
+        km = float(np.median(ks))
+        res[name]["gemm_kernel_ms"] = round(km, 3)
+        res[name]["gemm_tflops"] = round(2.0 * n ** 3 / km / 1e9, 3)
+    del Ga, Gb, Gc
+    torch.cuda.empty_cache()
+    return res
+
+
 def bench_overhead(ctx, T=256):
     """The runtime-overhead pattern of Specx Sec. 5.1 on the device: T workers (persistent
     workgroups), T chains of N tasks, every task writing the d data of its chain and
@@ -452,7 +501,7 @@ def bench_overhead(ctx, T=256):
     from paper_2308_15964_amd import spx
 
     out = {"workload": f"{T} chains (one per workgroup) of N empty tasks of duration D, d writes per task; "
-                       "one ready queue vs 8 sharded queues",
+                       "one ready queue vs 8 sharded queues; and the same chains with commutative writes",
            "rows": []}
     for D_us, N in ((10, 400), (100, 100), (1000, 20)):
         for d in (1, 5, 10, 20):
@@ -468,6 +517,17 @@ def bench_overhead(ctx, T=256):
                 km = float(np.median(kms))
                 row[name] = {"kernel_ms": round(km, 3), "O_us": round(km * 1e3 / N - D_us, 3)}
             g.close()
+            # the same chains with commutative writes (Sec. 5.1 compares the two modes): the
+            # tasks of a chain are no longer ordered but still run one at a time
+            acc_c = [(s_, spx.ACC_CW, d_) for (s_, _, d_) in acc]
+            t0 = time.perf_counter()
+            gc = spx.Graph.build(T * N, acc_c)
+            row["I_cw_us"] = round((time.perf_counter() - t0) * 1e6 / (T * N), 3)
+            ctx.run_graph(gc, ticks, num_wg=T)
+            kms = [ctx.run_graph(gc, ticks, num_wg=T)["kernel_ms"] for _ in range(3)]
+            km = float(np.median(kms))
+            row["commutative_sharded"] = {"kernel_ms": round(km, 3), "O_us": round(km * 1e3 / N - D_us, 3)}
+            gc.close()
             out["rows"].append(row)
     return out
 
@@ -628,10 +688,15 @@ def main():
                      "kernel": "sched_kernel (factor graph launch)"},
     }
     if not args.no_cpu_baseline:
+        print("bench: oracle on the host cores", file=sys.stderr, flush=True)
         A_host = A.cpu().numpy()
         out["cpu_baseline"] = cpu_baseline(A_host, n, b)
         del A_host
+    print("bench: N=1024 latency", file=sys.stderr, flush=True)
     out["config1"] = bench_config1(ctx)
+    if not args.skip_commute:
+        print("bench: commutative updates", file=sys.stderr, flush=True)
+        out["commute"] = bench_commute(ctx, A, B, n, b)
     del A, B, X
     torch.cuda.empty_cache()
     if not args.skip_mixed:

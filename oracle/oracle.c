@@ -676,7 +676,8 @@ static int64_t exec_par(orc_prog* p, int nthreads, double* a, int64_t n, int nb,
  *   nthreads <= 1: sequential executor with the given order (0 insertion, 1 seeded
  *   random, 2 priority); order_out (nullable, ntasks entries) receives the run order.
  *   nthreads > 1: parallel executor.
- *   limit > 0 (parallel executor only): run only tasks [0, limit) of the insertion order.
+ *   limit > 0: run only tasks [0, limit) of the insertion order (on the thread pool,
+ *   with one thread if nthreads <= 1).
  *   drop_edge (nullable {src,dst}): remove one DAG edge (a planted mistake for tests).
  *   commute: the updates are commutative writes (sequential executor only).
  * Returns 0, the 1-based global column of the first non-positive pivot, or -1 (-2: a
@@ -685,13 +686,13 @@ int64_t orc_cholesky(int64_t n, int nb, double* a, double* y, int nrhs, int orde
                      int nthreads, int64_t* order_out, int64_t limit, const uint32_t* drop_edge,
                      int64_t* nrun_out, int commute) {
   if (n <= 0 || nb <= 0 || n % nb != 0 || !a) return -1;
-  if (commute && nthreads > 1) return -1;
+  if (commute && (nthreads > 1 || limit > 0)) return -1;
   int nt = (int)(n / nb);
   int with_solve = (y != NULL && nrhs > 0) | (commute ? 0x100 : 0);
   orc_prog p;
   if (prog_make(nt, with_solve, drop_edge, &p) != 0) return -1;
   int64_t info;
-  if (nthreads <= 1)
+  if (nthreads <= 1 && limit <= 0)
     info = exec_seq(&p, order, seed, a, n, nb, y, nrhs, order_out, nrun_out);
   else
     info = exec_par(&p, nthreads, a, n, nb, y, nrhs, limit);

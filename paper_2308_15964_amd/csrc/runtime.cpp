@@ -216,7 +216,6 @@ int potrf_steps_of(int nt, int b) { return b >= 256 && nt >= 4 ? b / 32 : 1; }
 uint16_t parts_of(const TaskDesc& d, int b, int nrhs) {
   const int sbase = (d.type == SPX_T_SYRK && d.pad) ? 64 : 128;
   const int sb = b < sbase ? b : sbase, ns = b / sb;
-  const int rows = b < 64 ? b : 64;
   switch (d.type) {
     case SPX_T_POTRF: {  // step c: the diagonal part, plus one per 32-row block below c + 1
       const int steps = d.pad >> 8, c = d.pad & 0xff, rows = steps - c - 2;
@@ -226,9 +225,9 @@ uint16_t parts_of(const TaskDesc& d, int b, int nrhs) {
     case SPX_T_SYRK: return (uint16_t)(ns * (ns + 1) / 2);
     case SPX_T_GEMM: return (uint16_t)(ns * ns);
     case SPX_T_FTRSM:
-    case SPX_T_BTRSM: return (uint16_t)((nrhs + 7) / 8 * (d.pad ? b / rows : 1));
+    case SPX_T_BTRSM: return (uint16_t)((nrhs + 7) / 8 * (d.pad ? b / (b < 64 ? b : 64) : 1));
     case SPX_T_FGEMM:
-    case SPX_T_BGEMM: return (uint16_t)(b / rows);
+    case SPX_T_BGEMM: return (uint16_t)(b / (b < 64 ? b : 64));
     case SPX_T_INV: return (uint16_t)(b / trsm_rows_of(b));
     case SPX_T_LOAD: {
       if (d.j) return 1;  // right-hand sides only

@@ -102,7 +102,7 @@ struct DevMat {
 
 // A LOAD task has one part per lower tile while they fit the 16-bit part index.
 constexpr int kLoadTileParts = 65534;
-constexpr int kMaxQueues = 32;      // ready queues per image: levels x shards (a wave's lanes read them)
+constexpr int kMaxQueues = 64;      // ready queues per image: levels x shards (one per lane of a wave)
 constexpr int kMaxLevels = 64;      // priority classes (priority >> 16)
 constexpr int kLevels1 = 16;        // queue levels with one shard
 constexpr int kShards = 8;          // ready queues per priority level (one per XCD-sized group of workgroups)

@@ -1109,214 +1109,183 @@ __device__ void btrsm_sub_part(const double* __restrict__ l, const double* __res
   }
 }
 
-// Diagonal solves with M = L_kk^{-T} (column-major b x b, upper triangular: made by the
-// inversion task, exact zeros below its diagonal), rows [r0, r0 + rows) of the result for
-// up to 8 right-hand sides, read from yin and written to yout (another buffer, so the
-// row strips of one block run as separate parts).  Forward: out_r = sum over c <= r of
-// M(c, r) in_c (column r of M, contiguous).  Backward: out_r = sum over c >= r of
-// M(r, c) in_c.  yin is staged in LDS; the four waves split the c range and their partial
-// sums are added through LDS.
-__device__ void ftrsm_part(const double* __restrict__ M, int b, const double* __restrict__ yin,
-                           double* __restrict__ yout, int64_t ldy, int q0, int nq, int r0, int rows,
-                           double* __restrict__ lds) {
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  LDSAS double* ys = lp(lds);              // [8][b]
-  LDSAS double* part = lp(lds) + 8 * 512;  // [4][8][64]
-  const int cmax = r0 + rows;    // entries c < cmax are used
-  for (int e = tid; e < 8 * cmax; e += NT) {
-    const int q = e / cmax, m = e % cmax;
-    ys[q * b + m] = q < nq ? yin[(size_t)(q0 + q) * ldy + m] : 0.0;
-  }
-  __syncthreads();
-  const int ql = ((cmax + 15) / 16) * 4, c0 = wave * ql;  // quarters, multiples of 4
-  const int r = r0 + lane;
-  double acc[8];
+// ---------------------------------------------------------------------------------------
+// Solve parts (few right-hand sides): R output rows per part (64, or 32 for 32-wide
+// tiles).  For rows r in [r0, r0+R) and right-hand sides q < nq:
+//   s(r, q) = sum over k in [kb, ke) of A(r, k) ys[q][k],
+// with A(r, k) at A[k lda + r] (COLS: the rows of a column are contiguous) or at
+// A[r lda + k] (ROWS: a row is contiguous); kb, ke, r0 and lda are multiples of 4.  Every
+// load is 32 bytes (4 rows of a column, or 4 entries of a row), so each thread has only
+// R b / 1024 loads, all independent and issued together: the part costs about one
+// memory round trip instead of a chain of them.  COLS: thread t takes rows 4 (t % (R/4))
+// .. +3 and every G-th k from t / (R/4) (G = 1024 / R groups); ROWS: row t / (256/R) and
+// every 4-entry chunk 4 (t % (256/R)) + 1024/R * s.  The partial sums of a row are added
+// through LDS in a fixed order.  ys: 8 columns of stride ysd in LDS.  Leaves s(r0 + r, q)
+// in sums[q R + r] (LDS) for every thread to read after the closing barrier.
+// ---------------------------------------------------------------------------------------
+template <int R, bool ROWS>
+__device__ void skinny_rows(const double* __restrict__ A, int lda, int r0, int kb, int ke,
+                            const LDSAS double* ys, int ysd, int nq, LDSAS double* partial, LDSAS double* sums) {
+  constexpr int G = ROWS ? NT / R : NT / (R / 4);  // partial sums per row
+  const int tid = threadIdx.x;
+  double acc[4][8];
 #pragma unroll
-  for (int q = 0; q < 8; ++q) acc[q] = 0.0;
-  if (lane < rows) {
-    // entries c <= r; reading up to the next multiple of 4 only adds exact zeros
-    const int cend = min(min(c0 + ql, cmax), (r & ~3) + 4);
-    const double4* col = reinterpret_cast<const double4*>(M + (size_t)r * b);
+  for (int v = 0; v < 4; ++v)
+#pragma unroll
+    for (int q = 0; q < 8; ++q) acc[v][q] = 0.0;
+  int g;
+  if (ROWS) {
+    const int i = tid / G;
+    g = tid % G;
+    const double* row = A + (size_t)(r0 + i) * lda;
+    // acc[v][q]: the four entries of a chunk kept apart, summed at the end (fixed order)
     if (nq == 1) {
 #pragma unroll 8
-      for (int c = c0; c < cend; c += 4) {
-        const double4 v = col[c >> 2];
-        acc[0] += v.x * ys[c] + v.y * ys[c + 1] + v.z * ys[c + 2] + v.w * ys[c + 3];
+      for (int k = kb + 4 * g; k < ke; k += 4 * G) {
+        const double4 a = *reinterpret_cast<const double4*>(row + k);
+        acc[0][0] += a.x * ys[k];
+        acc[1][0] += a.y * ys[k + 1];
+        acc[2][0] += a.z * ys[k + 2];
+        acc[3][0] += a.w * ys[k + 3];
       }
     } else {
-#pragma unroll 4
-      for (int c = c0; c < cend; c += 4) {
-        const double4 v = col[c >> 2];
+#pragma unroll 2
+      for (int k = kb + 4 * g; k < ke; k += 4 * G) {
+        const double4 a = *reinterpret_cast<const double4*>(row + k);
 #pragma unroll
-        for (int q = 0; q < 8; ++q)
-          acc[q] += v.x * ys[q * b + c] + v.y * ys[q * b + c + 1] + v.z * ys[q * b + c + 2] + v.w * ys[q * b + c + 3];
+        for (int q = 0; q < 8; ++q) {
+          acc[0][q] += a.x * ys[q * ysd + k];
+          acc[1][q] += a.y * ys[q * ysd + k + 1];
+          acc[2][q] += a.z * ys[q * ysd + k + 2];
+          acc[3][q] += a.w * ys[q * ysd + k + 3];
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) acc[0][q] = (acc[0][q] + acc[1][q]) + (acc[2][q] + acc[3][q]);
+  } else {
+    const int i4 = tid % (R / 4);
+    g = tid / (R / 4);
+    const double* col = A + r0 + 4 * i4;
+    if (nq == 1) {
+#pragma unroll 8
+      for (int k = kb + g; k < ke; k += G) {
+        const double4 a = *reinterpret_cast<const double4*>(col + (size_t)k * lda);
+        const double y = ys[k];
+        acc[0][0] += a.x * y;
+        acc[1][0] += a.y * y;
+        acc[2][0] += a.z * y;
+        acc[3][0] += a.w * y;
+      }
+    } else {
+#pragma unroll 2
+      for (int k = kb + g; k < ke; k += G) {
+        const double4 a = *reinterpret_cast<const double4*>(col + (size_t)k * lda);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const double y = ys[q * ysd + k];
+          acc[0][q] += a.x * y;
+          acc[1][q] += a.y * y;
+          acc[2][q] += a.z * y;
+          acc[3][q] += a.w * y;
+        }
       }
     }
   }
+  __syncthreads();  // the caller's earlier use of `partial` is over
+  if (ROWS) {
+    const int i = tid / G;
 #pragma unroll
-  for (int q = 0; q < 8; ++q) part[(wave * 8 + q) * 64 + lane] = acc[q];
-  __syncthreads();
-  if (wave == 0 && lane < rows) {
+    for (int q = 0; q < 8; ++q) partial[(q * G + g) * R + i] = acc[0][q];
+  } else {
+    const int i4 = tid % (R / 4);
 #pragma unroll
     for (int q = 0; q < 8; ++q)
-      if (q < nq)
-        yout[(size_t)(q0 + q) * ldy + r] = part[(0 * 8 + q) * 64 + lane] + part[(1 * 8 + q) * 64 + lane] +
-                                           part[(2 * 8 + q) * 64 + lane] + part[(3 * 8 + q) * 64 + lane];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) partial[(q * G + g) * R + 4 * i4 + v] = acc[v][q];
   }
+  __syncthreads();
+  for (int e = tid; e < R * nq; e += NT) {
+    const int ri = e % R, q = e / R;
+    double sum = 0.0;
+#pragma unroll
+    for (int gg = 0; gg < G; ++gg) sum += partial[(q * G + gg) * R + ri];
+    sums[e] = sum;
+  }
+  __syncthreads();
 }
 
-__device__ void btrsm_part(const double* __restrict__ M, int b, const double* __restrict__ yin,
+// Stages columns q0 .. q0+nq-1, entries [kb, ke), of a right-hand-side block into LDS
+// (8 columns of stride b; the other entries are not read).
+__device__ __forceinline__ void stage_rhs(const double* __restrict__ y, int64_t ldy, int q0, int nq, int b, int kb,
+                                          int ke, LDSAS double* ys) {
+  const int w = ke - kb;
+  for (int e = threadIdx.x; e < 8 * w; e += NT) {
+    const int q = e / w, m = kb + e % w;
+    ys[q * b + m] = q < nq ? y[(size_t)(q0 + q) * ldy + m] : 0.0;
+  }
+  __syncthreads();
+}
+
+// ys at lds[0, 4096), the partial sums at [4096, 12288), the sums at [12288, 12800).
+template <bool ROWS>
+__device__ __forceinline__ void skinny(int rows, const double* A, int lda, int r0, int kb, int ke,
+                                       const LDSAS double* ys, int ysd, int nq, LDSAS double* partial,
+                                       LDSAS double* sums) {
+  if (rows == 64)
+    skinny_rows<64, ROWS>(A, lda, r0, kb, ke, ys, ysd, nq, partial, sums);
+  else
+    skinny_rows<32, ROWS>(A, lda, r0, kb, ke, ys, ysd, nq, partial, sums);
+}
+
+// Diagonal solves with M_k = L_kk^{-T} (column-major b x b; upper triangular: made by the
+// inversion task, exact zeros below its diagonal), rows [r0, r0+rows) for one group of up
+// to 8 right-hand sides, from yin to yout (another buffer, so the strips of a block run as
+// separate parts): forward y(r) = sum over c <= r of M(c, r) b(c) (column r of M, read as
+// row r of M^T, contiguous); backward x(r) = sum over c >= r of M(r, c) y(c).
+__device__ void ftrsm_rows(const double* __restrict__ M, int b, const double* __restrict__ yin,
                            double* __restrict__ yout, int64_t ldy, int q0, int nq, int r0, int rows,
                            double* __restrict__ lds) {
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   LDSAS double* ys = lp(lds);
-  LDSAS double* part = lp(lds) + 8 * 512;
-  for (int e = tid; e < 8 * (b - r0); e += NT) {  // entries c >= r0 are used
-    const int q = e / (b - r0), m = r0 + e % (b - r0);
-    ys[q * b + m] = q < nq ? yin[(size_t)(q0 + q) * ldy + m] : 0.0;
-  }
-  __syncthreads();
-  const int ql = ((b - r0 + 15) / 16) * 4, cb = r0 + wave * ql, ce = min(cb + ql, b);
-  const int r = r0 + lane;
-  // rows r > c of the strip add exact zeros
-  double acc[8];
-#pragma unroll
-  for (int q = 0; q < 8; ++q) acc[q] = 0.0;
-  if (lane < rows) {
-    if (nq == 1) {
-#pragma unroll 16
-      for (int c = cb; c < ce; ++c) acc[0] += M[(size_t)c * b + r] * ys[c];
-    } else {
-#pragma unroll 8
-      for (int c = cb; c < ce; ++c) {
-        const double v = M[(size_t)c * b + r];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) acc[q] += v * ys[q * b + c];
-      }
-    }
-  }
-#pragma unroll
-  for (int q = 0; q < 8; ++q) part[(wave * 8 + q) * 64 + lane] = acc[q];
-  __syncthreads();
-  if (wave == 0 && lane < rows) {
-#pragma unroll
-    for (int q = 0; q < 8; ++q)
-      if (q < nq)
-        yout[(size_t)(q0 + q) * ldy + r] = part[(0 * 8 + q) * 64 + lane] + part[(1 * 8 + q) * 64 + lane] +
-                                           part[(2 * 8 + q) * 64 + lane] + part[(3 * 8 + q) * 64 + lane];
-  }
+  LDSAS double* partial = ys + 8 * 512;
+  LDSAS double* sums = partial + 8 * 1024;
+  stage_rhs(yin, ldy, q0, nq, b, 0, r0 + rows, ys);
+  skinny<true>(rows, M, b, r0, 0, r0 + rows, ys, b, nq, partial, sums);
+  for (int e = threadIdx.x; e < rows * nq; e += NT) yout[(size_t)(q0 + e / rows) * ldy + r0 + e % rows] = sums[e];
 }
 
-// Forward update, rows [r0, r0+rows) of block i: y_i -= L_ik y_k.  y_k (8 columns at a
-// time) is staged in LDS; wave w sums over m in its quarter of the block (lane = row, 16
-// loads of 64 contiguous doubles in flight), the four partial sums are added through LDS,
-// and each row's old values are all read before any is written back.
-__device__ void fgemm_part(const double* __restrict__ l, int b, double* __restrict__ yi,
-                           const double* __restrict__ yk, int64_t ldy, int nrhs, int r0, int rows,
+__device__ void btrsm_rows(const double* __restrict__ M, int b, const double* __restrict__ yin,
+                           double* __restrict__ yout, int64_t ldy, int q0, int nq, int r0, int rows,
                            double* __restrict__ lds) {
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  LDSAS double* ys = lp(lds);             // [8][b]
-  LDSAS double* part = lp(lds) + 8 * 512; // [4][8][64]
-  const int mq = b / 4;
-  for (int q0 = 0; q0 < nrhs; q0 += 8) {
-    const int nq = (nrhs - q0) < 8 ? (nrhs - q0) : 8;
-    __syncthreads();
-    for (int e = tid; e < 8 * b; e += NT) {
-      const int q = e / b, m = e % b;
-      ys[e] = q < nq ? yk[(size_t)(q0 + q) * ldy + m] : 0.0;
-    }
-    __syncthreads();
-    double acc[8];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) acc[q] = 0.0;
-    if (lane < rows) {
-      if (nq == 1) {
-#pragma unroll 32
-        for (int m = wave * mq; m < (wave + 1) * mq; ++m) acc[0] += l[(size_t)m * b + r0 + lane] * ys[m];
-      } else {
-#pragma unroll 16
-        for (int m = wave * mq; m < (wave + 1) * mq; ++m) {
-          const double lv = l[(size_t)m * b + r0 + lane];
-#pragma unroll
-          for (int q = 0; q < 8; ++q) acc[q] += lv * ys[q * b + m];
-        }
-      }
-    }
-#pragma unroll
-    for (int q = 0; q < 8; ++q) part[(wave * 8 + q) * 64 + lane] = acc[q];
-    __syncthreads();
-    if (wave == 0 && lane < rows) {
-      double old[8];
-#pragma unroll
-      for (int q = 0; q < 8; ++q) old[q] = q < nq ? yi[(size_t)(q0 + q) * ldy + r0 + lane] : 0.0;
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const double sum = part[(0 * 8 + q) * 64 + lane] + part[(1 * 8 + q) * 64 + lane] +
-                           part[(2 * 8 + q) * 64 + lane] + part[(3 * 8 + q) * 64 + lane];
-        if (q < nq) yi[(size_t)(q0 + q) * ldy + r0 + lane] = old[q] - sum;
-      }
-    }
-  }
+  LDSAS double* ys = lp(lds);
+  LDSAS double* partial = ys + 8 * 512;
+  LDSAS double* sums = partial + 8 * 1024;
+  stage_rhs(yin, ldy, q0, nq, b, r0, b, ys);
+  skinny<false>(rows, M, b, r0, r0, b, ys, b, nq, partial, sums);
+  for (int e = threadIdx.x; e < rows * nq; e += NT) yout[(size_t)(q0 + e / rows) * ldy + r0 + e % rows] = sums[e];
 }
 
-// Backward update, rows [r0, r0+rows) of block i (i < k): y_i -= L_ki^T y_k.  Output row r
-// is the dot product of column r of L_ki (contiguous) with y_k: lane = row, wave w sums
-// its quarter of the column with 32-byte loads (the other lanes' rows are 4 KiB away, so
-// each lane streams its own cache lines), y_k staged in LDS and read by all lanes at the
-// same index; the quarters are added through LDS as in the forward update.
-__device__ void bgemm_part(const double* __restrict__ l, int b, double* __restrict__ yi,
-                           const double* __restrict__ yk, int64_t ldy, int nrhs, int r0, int rows,
-                           double* __restrict__ lds) {
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  LDSAS double* ys = lp(lds);              // [8][b]
-  LDSAS double* part = lp(lds) + 8 * 512;  // [4][8][64]
-  const int mq = b / 4;
+// Off-diagonal updates, rows [r0, r0+rows) of block i, every right-hand side (8 at a
+// time): forward y_i -= L_ik y_k (tile (i,k), rows of a column contiguous); backward
+// y_i -= L_ki^T y_k (tile (k,i): row r of L_ki^T is column r of the tile, contiguous).
+// Each row's old value is read after the sums, by the thread that writes it.
+template <bool BACKWARD>
+__device__ void update_rows(const double* __restrict__ l, int b, double* __restrict__ yi,
+                            const double* __restrict__ yk, int64_t ldy, int nrhs, int r0, int rows,
+                            double* __restrict__ lds) {
+  LDSAS double* ys = lp(lds);
+  LDSAS double* partial = ys + 8 * 512;
+  LDSAS double* sums = partial + 8 * 1024;
   for (int q0 = 0; q0 < nrhs; q0 += 8) {
     const int nq = (nrhs - q0) < 8 ? (nrhs - q0) : 8;
-    __syncthreads();
-    for (int e = tid; e < 8 * b; e += NT) {
-      const int q = e / b, m = e % b;
-      ys[e] = q < nq ? yk[(size_t)(q0 + q) * ldy + m] : 0.0;
+    // (the previous group's reads of ys and sums ended before its closing barrier)
+    stage_rhs(yk, ldy, q0, nq, b, 0, b, ys);
+    skinny<BACKWARD>(rows, l, b, r0, 0, b, ys, b, nq, partial, sums);
+    for (int e = threadIdx.x; e < rows * nq; e += NT) {
+      double* p = yi + (size_t)(q0 + e / rows) * ldy + r0 + e % rows;
+      *p = *p - sums[e];
     }
-    __syncthreads();
-    double acc[8];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) acc[q] = 0.0;
-    if (lane < rows) {
-      const double4* col = reinterpret_cast<const double4*>(l + (size_t)(r0 + lane) * b + wave * mq);
-      if (nq == 1) {
-#pragma unroll 16
-        for (int m4 = 0; m4 < mq / 4; ++m4) {
-          const double4 v = col[m4];
-          const int m = wave * mq + 4 * m4;
-          acc[0] += v.x * ys[m] + v.y * ys[m + 1] + v.z * ys[m + 2] + v.w * ys[m + 3];
-        }
-      } else {
-#pragma unroll 8
-        for (int m4 = 0; m4 < mq / 4; ++m4) {
-          const double4 v = col[m4];
-          const int m = wave * mq + 4 * m4;
-#pragma unroll
-          for (int q = 0; q < 8; ++q)
-            acc[q] += v.x * ys[q * b + m] + v.y * ys[q * b + m + 1] + v.z * ys[q * b + m + 2] +
-                      v.w * ys[q * b + m + 3];
-        }
-      }
-    }
-#pragma unroll
-    for (int q = 0; q < 8; ++q) part[(wave * 8 + q) * 64 + lane] = acc[q];
-    __syncthreads();
-    if (wave == 0 && lane < rows) {
-      double old[8];
-#pragma unroll
-      for (int q = 0; q < 8; ++q) old[q] = q < nq ? yi[(size_t)(q0 + q) * ldy + r0 + lane] : 0.0;
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const double sum = part[(0 * 8 + q) * 64 + lane] + part[(1 * 8 + q) * 64 + lane] +
-                           part[(2 * 8 + q) * 64 + lane] + part[(3 * 8 + q) * 64 + lane];
-        if (q < nq) yi[(size_t)(q0 + q) * ldy + r0 + lane] = old[q] - sum;
-      }
-    }
+    __syncthreads();  // sums read before the next group overwrites ys and sums
   }
 }
 
@@ -1434,9 +1403,9 @@ __device__ __attribute__((noinline)) void run_part_chol(const SchedArgs& a, uint
       const int r0 = ((int)part % nrp) * rows;
       const double* Mk = m.minv + (size_t)d.k * b * b;
       if (d.type == SPX_T_FTRSM)
-        ftrsm_part(Mk, b, m.rhs + (size_t)d.k * b, m.rhs2 + (size_t)d.k * b, m.n_pad, q0, nq, r0, rows, lds);
+        ftrsm_rows(Mk, b, m.rhs + (size_t)d.k * b, m.rhs2 + (size_t)d.k * b, m.n_pad, q0, nq, r0, rows, lds);
       else
-        btrsm_part(Mk, b, m.rhs2 + (size_t)d.k * b, m.rhs + (size_t)d.k * b, m.n_pad, q0, nq, r0, rows, lds);
+        btrsm_rows(Mk, b, m.rhs2 + (size_t)d.k * b, m.rhs + (size_t)d.k * b, m.n_pad, q0, nq, r0, rows, lds);
       break;
     }
     case SPX_T_INV: {
@@ -1451,19 +1420,17 @@ __device__ __attribute__((noinline)) void run_part_chol(const SchedArgs& a, uint
       trsm_part(x, tile_ptr(m, d.k, d.k), dinv_ptr(m, d.k), b, r0, nullptr, PREC_FP64, lds, r0 & ~31);
       break;
     }
-    case SPX_T_FGEMM: {
+    case SPX_T_FGEMM: {  // one strip of 64 rows per part
       const int rows = b < 64 ? b : 64;
-      fgemm_part(tile_ptr(m, d.i, d.k), b, m.rhs + (size_t)d.i * b, (d.pad ? m.rhs2 : m.rhs) + (size_t)d.k * b,
-                 m.n_pad, m.nrhs,
-                 part * rows, rows, lds);
+      update_rows<false>(tile_ptr(m, d.i, d.k), b, m.rhs + (size_t)d.i * b,
+                         (d.pad ? m.rhs2 : m.rhs) + (size_t)d.k * b, m.n_pad, m.nrhs, (int)part * rows, rows, lds);
       break;
     }
     case SPX_T_BGEMM: {
       // task (i, k): y_i -= L_ki^T y_k; the tile is (k, i) with k = d.j
       const int rows = b < 64 ? b : 64;
-      bgemm_part(tile_ptr(m, d.j, d.i), b, (d.pad ? m.rhs2 : m.rhs) + (size_t)d.i * b, m.rhs + (size_t)d.j * b,
-                 m.n_pad, m.nrhs,
-                 part * rows, rows, lds);
+      update_rows<true>(tile_ptr(m, d.j, d.i), b, (d.pad ? m.rhs2 : m.rhs) + (size_t)d.i * b,
+                        m.rhs + (size_t)d.j * b, m.n_pad, m.nrhs, (int)part * rows, rows, lds);
       break;
     }
     case SPX_T_LOAD: {
@@ -1836,10 +1803,10 @@ __global__ __launch_bounds__(NT) void sched_kernel(SchedArgs a) {
   const int tid = threadIdx.x;
   const int home = blockIdx.x % a.nshards;
   u64 idle = 0, busy = 0;
-  // root tasks with commutative accesses take their locks first (the queues hold the
-  // other roots already)
-  if (blockIdx.x == 0 && tid == 0)
-    for (uint32_t r = 0; r < a.ncroots; ++r) start_task(a, a.croots[r], home);
+  // root tasks with commutative accesses take their locks first, spread over the
+  // workgroups (the queues hold the other roots already)
+  if (tid == 0)
+    for (uint32_t r = blockIdx.x; r < a.ncroots; r += gridDim.x) start_task(a, a.croots[r], home);
   for (;;) {
     if (tid < 64) {
       const u64 t0 = now_ticks();
