@@ -364,8 +364,8 @@ static double task_cost(const TaskDesc& d) {
 }
 
 // Default priorities of the library's programs (larger = sooner): the upward rank, i.e.
-// the task's own latency plus the longest chain of latencies from it to the end of the
-// graph, so that among the ready tasks the one with the most work still chained behind it
+// the task's own latency plus the longest chain of latencies (tasks and hops) from it to
+// the end of the graph, so that among the ready tasks the one with the most work still chained behind it
 // runs first.  In the tile Cholesky this puts the panel chain first, then the updates by
 // how soon their tile is consumed, and an early update of a tile that still has a long
 // chain of updates ahead of it (the last diagonal tiles) before a late one of a short
@@ -378,9 +378,12 @@ void rank_priorities(const std::vector<TaskDesc>& tasks, Graph& g) {
   const uint32_t T = g.ntasks;
   std::vector<double> r(T, 0.0);
   double mx = 0.0;
+  // every edge also costs a hop (completion, push and pop: about a third of an update),
+  // so of two chains with the same work the one with more hand-overs ranks higher
+  constexpr double kHop = 0.3;
   for (uint32_t t = T; t-- > 0;) {
     double m = 0.0;
-    for (uint64_t q = g.off[t]; q < g.off[t + 1]; ++q) m = std::max(m, r[g.succ[q]]);
+    for (uint64_t q = g.off[t]; q < g.off[t + 1]; ++q) m = std::max(m, kHop + r[g.succ[q]]);
     r[t] = task_cost(tasks[t]) + m;
     mx = std::max(mx, r[t]);
   }

@@ -347,7 +347,15 @@ static int build_image_host(const std::vector<Piece>& pieces, int policy, ImageH
       off32[t0 + t] = (uint32_t)(e0 + pr.g.off[t]);
       per_level[d.level] += d.nparts;
     }
-    for (size_t e = 0; e < pr.g.succ.size(); ++e) succ[e0 + e] = t0 + pr.g.succ[e];
+    // each task's successors by decreasing priority: those made ready by one completion are
+    // pushed in that order, so within a queue level the most urgent one comes out first
+    for (uint32_t t = 0; t < pr.g.ntasks; ++t) {
+      const uint64_t a = pr.g.off[t], z = pr.g.off[t + 1];
+      for (uint64_t e = a; e < z; ++e) succ[e0 + e] = t0 + pr.g.succ[e];
+      std::stable_sort(succ.begin() + (e0 + a), succ.begin() + (e0 + z), [&](uint32_t x, uint32_t y) {
+        return pr.g.prio[x - t0] > pr.g.prio[y - t0];
+      });
+    }
     t0 += pr.g.ntasks;
     e0 += pr.g.succ.size();
   }
