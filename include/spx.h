@@ -373,12 +373,15 @@ int spx_autotune_batched(spx_ctx* ctx, int32_t prec, int32_t nsizes, const int64
  *   mode SPX_MODE_MIXED: FP32-update factor (spx_potrf_batched), then FP64 classical
  *   iterative refinement to tol (spx_potrs_batched method 1); a request whose low-precision
  *   factor breaks down or whose refinement does not reach tol is redone in FP64
- *   (method_used = 0 reports the fallback).
+ *   (method_used = 0 reports the fallback).  Requests with n < opts.mixed_min_n run the
+ *   FP64 path directly (method_used = 0): there the updates are too small a share of the
+ *   work for FP32 to save what a refinement step costs.
  * The result of a request does not depend on what else is in the same batch or lane: a
  * batched member runs the same kernels in the same dependency order as when alone.
  *   A, B, X: n x n, n x nrhs, n x nrhs row-major with leading dimensions lda, ldb, ldx;
  *   where = 0: host memory (copied in and out by the lane; pinned memory copies faster),
- *   where = 1: device memory of the context's GPU.  The caller keeps them alive and A, B
+ *   where = 1: device memory of the context's GPU, where = 2: A and B in device memory, X
+ *   in host memory (solved into a device copy, then copied back).  The caller keeps them alive and A, B
  *   unmodified until spx_poll returns SPX_OK for the ticket (or the server is destroyed).
  *   tol <= 0 means 1e-12.  tag: returned in the result.
  * spx_submit never blocks: it records the request and returns a ticket; SPX_ENOMEM if the
@@ -387,7 +390,13 @@ int spx_autotune_batched(spx_ctx* ctx, int32_t prec, int32_t nsizes, const int64
  * done, SPX_EINVAL for an unknown ticket.  out->status: SPX_OK, SPX_EDEVICE, ... for the
  * request itself; out->info > 0: not positive definite at that column.
  * Times (seconds on the server's steady clock, spx_server_now): submit, admission, start
- * of the launch that ran it, result available (X written back).
+ * of the launch that ran it, batch finished (t_done: X written back and every diagnostic
+ * of the batch done; spx_poll answers from then on), and t_ready: this request's X was
+ * final in the caller's memory.  In FP64 mode each request's STORE task, once released,
+ * raises a host-visible flag; a monitor thread of the server sees it while the batch is
+ * still running and, for host memory, copies X back at once, so t_ready is per request
+ * (t_ready <= t_done).  In mixed mode X is final only after the batched refinement:
+ * t_ready = t_done.
  * spx_server_destroy: requests not yet started end with status SPX_EABORT; running
  * batches finish first. */
 enum { SPX_MODE_FP64 = 0, SPX_MODE_MIXED = 1 };
@@ -413,12 +422,13 @@ typedef struct {
   uint64_t tag;
   int32_t batch_size;
   int32_t lane;
+  double t_ready;
 } spx_result;
 typedef struct {
   int32_t lanes;      /* worker lanes (streams); <= 0: 2 */
   int32_t max_batch;  /* requests per launch; <= 0: 4096 */
   int32_t num_wg;     /* workgroups per launch; <= 0: fill the GPU */
-  int32_t pad;
+  int32_t mixed_min_n; /* mixed-mode requests with n below this run in FP64; <= 0: 4096 */
 } spx_server_opts;
 typedef struct {
   uint64_t submitted, completed, rejected, launches;

@@ -40,7 +40,7 @@ int failf(int code, const char* fmt, ...) {
 
 static int hipc(hipError_t e, const char* what) {
   if (e == hipSuccess) return SPX_OK;
-  return failf(SPX_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+  return failf(e == hipErrorOutOfMemory ? SPX_ENOMEM : SPX_EDEVICE, "%s: %s", what, hipGetErrorString(e));
 }
 
 #define SPX_TRY(x)              \
@@ -95,6 +95,8 @@ using namespace spx;
 
 struct spx_ctx {
   int device = 0;
+  // per-matrix completion flags for the next batched solve (the serving loop sets them)
+  unsigned int* const* store_flags = nullptr;
   hipStream_t stream = nullptr;
   spx_alloc_fn alloc = nullptr;
   spx_free_fn freef = nullptr;
@@ -780,6 +782,8 @@ static int batched_eta(spx_ctx* c, const std::vector<int>& idx, const int64_t* n
   return SPX_OK;
 }
 
+void ctx_set_store_flags(spx_ctx* c, unsigned int* const* flags) { c->store_flags = flags; }
+
 int ctx_device(const spx_ctx* c) { return c->device; }
 
 int ctx_copy_tile_tables(const spx_ctx* from, spx_ctx* to) {
@@ -914,6 +918,7 @@ static int batched(spx_ctx* c, int count, const int64_t* n, const double* const*
       d.X = dX[m];
       d.ldb = ldb[m];
       d.ldx = ldx[m];
+      d.done_flag = c->store_flags ? c->store_flags[m] : nullptr;
     }
     d.info = c->dinfo + m;
     d.n_pad = (int64_t)nts[m] * bs[m];

@@ -6,6 +6,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
+#include <cstdio>
 #include <chrono>
 #include <climits>
 #include <cmath>
@@ -37,6 +39,23 @@ struct Lane {
   std::thread th;
 };
 
+// One FP64 request of a running batch, watched by the monitor thread: its STORE task
+// raises *hflag once X is final in device memory; for host-memory requests the monitor
+// then copies X back on its own stream.
+struct Watch {
+  volatile unsigned int* hflag = nullptr;
+  bool copy = false;
+  void* dst = nullptr;
+  size_t dpitch = 0, spitch = 0, width = 0, height = 0;
+  const void* src = nullptr;
+  hipEvent_t ev = nullptr;
+  std::atomic<int> state{0};  // 0 running, 1 copy issued, 2 X in place
+  double t_ready = 0.0;
+};
+
+constexpr int kFlagSlots = 1 << 16;  // completion flags in pinned host memory
+constexpr int64_t kMixedMinN = 4096;  // default: mixed-mode requests below this size run in FP64
+
 // Stream-ordered device allocations from the device's default memory pool, so lanes do
 // not serialise on the allocator and freed blocks are reused.
 void* pool_alloc(size_t bytes, void* stream, void*) {
@@ -66,6 +85,15 @@ struct spx_server {
   std::vector<Lane> lanes;
   spx_server_stats st{};
   uint64_t running = 0;
+  // completion flags (pinned, device-visible) and the monitor that watches them
+  unsigned int* flags_h = nullptr;
+  unsigned int* flags_d = nullptr;
+  std::vector<int> free_slots;  // guarded by mu
+  std::mutex mon_mu;
+  std::vector<Watch*> watches;  // guarded by mon_mu
+  std::atomic<bool> mon_stop{false};
+  hipStream_t mon_stream = nullptr;
+  std::thread monitor;
   spx_ctx* tuner = nullptr;  // holds the tile tables (copied from the creating context)
 
   double now() const { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); }
@@ -89,6 +117,7 @@ size_t request_bytes(const spx_request& r, int b) {
   if (r.mode == SPX_MODE_MIXED)
     s += align256(npad * (size_t)b * 8) + align256(tiles / 2) + 2 * align256(n * q * 8) + align256(npad * q * 8);
   if (r.where == 0) s += align256(n * n * 8) + align256(n * q * 8) + align256(n * q * 8);
+  if (r.where == 2) s += align256(n * q * 8);  // the device copy of X
   return s;
 }
 
@@ -148,6 +177,20 @@ void run_batch(spx_server* s, Lane& ln, int lane_id, std::vector<Work>& w) {
       x.lda = x.r.lda;
       x.ldb = x.r.ldb;
       x.ldx = x.r.ldx;
+      continue;
+    }
+    if (x.r.where == 2) {  // inputs on the device, X to host memory through a device copy
+      x.A = x.r.A;
+      x.B = x.r.B;
+      x.lda = x.r.lda;
+      x.ldb = x.r.ldb;
+      x.own[2] = pool_alloc(n * q * 8, st, nullptr);
+      if (!x.own[2]) {
+        rc = SPX_ENOMEM;
+        break;
+      }
+      x.X = (double*)x.own[2];
+      x.ldx = (int64_t)q;
       continue;
     }
     x.own[0] = pool_alloc(n * n * 8, st, nullptr);
@@ -222,19 +265,74 @@ void run_batch(spx_server* s, Lane& ln, int lane_id, std::vector<Work>& w) {
     for (int t = 0; !r && t < kk; ++t) w[sel[ok[t]]].res.eta_max = eta[t];
     return r;
   };
+  // FP64 mode: per-request completion flags and watches
+  std::vector<std::unique_ptr<Watch>> watch(K);
+  std::vector<int> slots;
+  std::vector<unsigned int*> dflags(K, nullptr);
+  if (!rc && !mixed && s->flags_h) {
+    {
+      std::lock_guard<std::mutex> lk(s->mu);
+      for (int i = 0; i < K && !s->free_slots.empty(); ++i) {
+        slots.push_back(s->free_slots.back());
+        s->free_slots.pop_back();
+      }
+    }
+    for (int i = 0; i < (int)slots.size(); ++i) {
+      Watch* wt = new Watch();
+      watch[i].reset(wt);
+      wt->hflag = s->flags_h + slots[i];
+      *wt->hflag = 0u;
+      dflags[i] = s->flags_d + slots[i];
+      const Work& x = w[i];
+      if (x.r.where != 1) {
+        wt->copy = hipEventCreateWithFlags(&wt->ev, hipEventDisableTiming) == hipSuccess;
+        wt->dst = x.r.X;
+        wt->dpitch = (size_t)x.r.ldx * 8;
+        wt->src = x.X;
+        wt->spitch = wt->width = (size_t)x.r.nrhs * 8;
+        wt->height = (size_t)x.r.n;
+        if (!wt->copy) dflags[i] = nullptr, watch[i].reset();  // no event: copied at the end
+      }
+    }
+    std::atomic_thread_fence(std::memory_order_seq_cst);  // flags cleared before the launch
+    std::lock_guard<std::mutex> lk(s->mon_mu);
+    for (auto& wt : watch)
+      if (wt) s->watches.push_back(wt.get());
+  }
   if (!rc && !mixed) {
     std::vector<int> all(K);
     for (int i = 0; i < K; ++i) all[i] = i;
+    ctx_set_store_flags(c, dflags.data());
     rc = fp64(all);
+    ctx_set_store_flags(c, nullptr);
   } else if (!rc) {
     // FP32-update factor and first solve in one launch (factors kept), then batched FP64
-    // refinement from that solution; what does not converge is redone in FP64
+    // refinement from that solution; what does not converge is redone in FP64.  Systems
+    // below opts.mixed_min_n go straight to FP64: their updates are too small a share of
+    // the work for FP32 to save what a refinement step costs.
+    std::vector<int> low, redo;
+    const int64_t min_n = s->opts.mixed_min_n > 0 ? s->opts.mixed_min_n : kMixedMinN;
+    for (int i = 0; i < K; ++i) (n[i] >= min_n ? low : redo).push_back(i);
     o.update_prec = SPX_PREC_FP32;
+    const int KL = (int)low.size();
     std::vector<spx_factor*> f(K, nullptr);
-    rc = spx_posv_batched(c, K, n.data(), A.data(), lda.data(), q.data(), B.data(), ldb.data(), X.data(), ldx.data(),
-                          &o, info.data(), f.data());
-    std::vector<int> good, redo;
-    for (int i = 0; !rc && i < K; ++i) (f[i] ? good : redo).push_back(i);
+    if (KL > 0) {
+      std::vector<int64_t> nl(KL), ldal(KL), ql(KL), ldbl(KL), ldxl(KL), infol(KL);
+      std::vector<const double*> Al(KL), Bl(KL);
+      std::vector<double*> Xl(KL);
+      std::vector<spx_factor*> fl(KL, nullptr);
+      for (int j = 0; j < KL; ++j) {
+        const int i = low[j];
+        nl[j] = n[i], ldal[j] = lda[i], ql[j] = q[i], ldbl[j] = ldb[i], ldxl[j] = ldx[i];
+        Al[j] = A[i], Bl[j] = B[i], Xl[j] = X[i];
+      }
+      rc = spx_posv_batched(c, KL, nl.data(), Al.data(), ldal.data(), ql.data(), Bl.data(), ldbl.data(), Xl.data(),
+                            ldxl.data(), &o, infol.data(), fl.data());
+      for (int j = 0; j < KL; ++j) f[low[j]] = fl[j];
+    }
+    std::vector<int> good;
+    for (int i : low)
+      if (!rc) (f[i] ? good : redo).push_back(i);
     if (!rc && !good.empty()) {
       const int k = (int)good.size();
       std::vector<spx_factor*> f2(k);
@@ -267,23 +365,113 @@ void run_batch(spx_server* s, Lane& ln, int lane_id, std::vector<Work>& w) {
       rc = fp64(redo);
     }
   }
-  // results back to the caller
-  for (auto& x : w) {
-    if (rc || x.r.where == 1 || x.res.info) continue;
+  // the launches are done (every STORE released): wait for the monitor to finish with
+  // this batch's watches, so its copies are complete before the buffers are freed
+  const int rc_k = hip_status(hipStreamSynchronize(st));
+  if (!rc) rc = rc_k;
+  for (auto& wt : watch) {
+    if (!wt) continue;
+    const auto tw = std::chrono::steady_clock::now();
+    // (after a failed launch a flag may never rise)
+    while (wt->state.load() != 2 && !(rc && wt->state.load() == 0) &&
+           std::chrono::steady_clock::now() - tw < std::chrono::seconds(10))
+      std::this_thread::sleep_for(std::chrono::microseconds(20));
+  }
+  bool copying = false;
+  {
+    std::lock_guard<std::mutex> lk(s->mon_mu);
+    for (auto& wt : watch)
+      if (wt) {
+        s->watches.erase(std::find(s->watches.begin(), s->watches.end(), wt.get()));
+        copying |= wt->state.load() == 1;
+      }
+  }
+  if (copying) (void)hipStreamSynchronize(s->mon_stream);  // a copy still in flight
+  // results back to the caller (those the monitor has not copied)
+  for (int i = 0; i < K; ++i) {
+    Work& x = w[i];
+    if (watch[i] && watch[i]->state.load() == 2) x.res.t_ready = watch[i]->t_ready;
+    const bool copied = watch[i] && watch[i]->copy && watch[i]->state.load() == 2;
+    if (rc || x.r.where == 1 || x.res.info || copied) continue;
     const size_t nn = (size_t)x.r.n, qq = (size_t)x.r.nrhs;
     rc = hip_status(hipMemcpy2DAsync(x.r.X, (size_t)x.r.ldx * 8, x.X, qq * 8, qq * 8, nn, hipMemcpyDeviceToHost, st));
     if (rc) break;
   }
   const int rc_sync = hip_status(hipStreamSynchronize(st));
   if (!rc) rc = rc_sync;
+  for (auto& wt : watch)
+    if (wt && wt->ev) (void)hipEventDestroy(wt->ev);
+  if (!slots.empty()) {
+    std::lock_guard<std::mutex> lk(s->mu);
+    for (int sl : slots) s->free_slots.push_back(sl);
+  }
   for (auto& x : w)
     for (void* p : x.own)
       if (p) pool_free(p, st, nullptr);
   const double t_done = s->now();
+  if (rc) std::fprintf(stderr, "spx server: lane %d: a batch of %d requests failed (%d): %s\n", lane_id, K, rc,
+                       spx_last_error());
   for (auto& x : w) {
     if (rc) x.res.status = rc;
     x.res.t_done = t_done;
+    if (!(x.res.t_ready > 0.0) || x.res.status != SPX_OK) x.res.t_ready = t_done;
   }
+}
+
+// Watches the completion flags of the running FP64 batches (every 20 us): a risen flag
+// marks the request's X final in device memory; for host memory its copy back is issued
+// on the monitor's stream and the request is ready when that copy completes.
+void monitor_main(spx_server* s) {
+  (void)hipSetDevice(s->device);
+  while (!s->mon_stop.load()) {
+    {
+      std::lock_guard<std::mutex> lk(s->mon_mu);
+      for (Watch* w : s->watches) {
+        const int st = w->state.load();
+        if (st == 0 && *w->hflag != 0u) {
+          if (w->copy) {
+            const bool ok = hipMemcpy2DAsync(w->dst, w->dpitch, w->src, w->spitch, w->width, w->height,
+                                             hipMemcpyDeviceToHost, s->mon_stream) == hipSuccess &&
+                            hipEventRecord(w->ev, s->mon_stream) == hipSuccess;
+            if (ok) {
+              w->state.store(1);
+            } else {  // leave the copy to the lane
+              w->copy = false;
+              w->t_ready = s->now();
+              w->state.store(2);
+            }
+          } else {
+            w->t_ready = s->now();
+            w->state.store(2);
+          }
+        } else if (st == 1 && hipEventQuery(w->ev) == hipSuccess) {
+          w->t_ready = s->now();
+          w->state.store(2);
+        }
+      }
+    }
+    std::this_thread::sleep_for(std::chrono::microseconds(20));
+  }
+}
+
+// Runs a batch; if device memory runs out (the budget counts the requests' own arrays, not
+// the graph image or what other users of the device hold), runs each half on its own.
+void run_batch_split(spx_server* s, Lane& ln, int lane_id, std::vector<Work>& w) {
+  run_batch(s, ln, lane_id, w);
+  const bool oom = std::all_of(w.begin(), w.end(), [](const Work& x) { return x.res.status == SPX_ENOMEM; });
+  if (!oom || w.size() < 2) return;
+  std::vector<Work> a(w.begin(), w.begin() + w.size() / 2), b(w.begin() + w.size() / 2, w.end());
+  for (auto* part : {&a, &b})
+    for (auto& x : *part) {
+      x.A = x.B = nullptr;
+      x.X = nullptr;
+      x.own[0] = x.own[1] = x.own[2] = nullptr;
+      x.res.status = SPX_OK;
+    }
+  run_batch_split(s, ln, lane_id, a);
+  run_batch_split(s, ln, lane_id, b);
+  std::copy(a.begin(), a.end(), w.begin());
+  std::copy(b.begin(), b.end(), w.begin() + a.size());
 }
 
 void lane_main(spx_server* s, int id) {
@@ -298,12 +486,16 @@ void lane_main(spx_server* s, int id) {
       const spx_request& head = s->reqs[s->admitted.front()].r;
       const int mode = head.mode;
       const double tol = head.tol;
+      // a batch holds at most the budget's share of one lane (its workspace is one block)
+      const size_t cap = s->budget / s->lanes.size();
+      size_t taken = 0;
       for (auto it = s->admitted.begin(); it != s->admitted.end() && (int)w.size() < s->opts.max_batch;) {
         Req& q = s->reqs[*it];
-        if (q.r.mode != mode || (mode == SPX_MODE_MIXED && q.r.tol != tol)) {
+        if (q.r.mode != mode || (mode == SPX_MODE_MIXED && q.r.tol != tol) || (!w.empty() && taken + q.bytes > cap)) {
           ++it;
           continue;
         }
+        taken += q.bytes;
         q.state = RUNNING;
         Work x;
         x.ticket = *it;
@@ -318,7 +510,7 @@ void lane_main(spx_server* s, int id) {
       s->st.launches++;
     }
     const double t0 = s->now();
-    run_batch(s, ln, id, w);
+    run_batch_split(s, ln, id, w);
     {
       std::lock_guard<std::mutex> lk(s->mu);
       s->st.busy_s += s->now() - t0;
@@ -374,7 +566,24 @@ int spx_server_create(spx_ctx* ctx, size_t hbm_budget_bytes, const spx_server_op
     }
   }
   s->tuner = s->lanes[0].ctx;
+  // completion flags: pinned, coherent host memory the kernel writes at system scope
+  // (without them, every request of a batch gets the batch's end as t_ready)
+  void* fh = nullptr;
+  if (hipHostMalloc(&fh, sizeof(unsigned int) * kFlagSlots, hipHostMallocMapped | hipHostMallocCoherent) ==
+      hipSuccess) {
+    void* fd = nullptr;
+    if (hipHostGetDevicePointer(&fd, fh, 0) == hipSuccess &&
+        hipStreamCreateWithFlags(&s->mon_stream, hipStreamNonBlocking) == hipSuccess) {
+      s->flags_h = (unsigned int*)fh;
+      s->flags_d = (unsigned int*)fd;
+      s->free_slots.reserve(kFlagSlots);
+      for (int i = kFlagSlots - 1; i >= 0; --i) s->free_slots.push_back(i);
+    } else {
+      (void)hipHostFree(fh);
+    }
+  }
   spx_server* raw = s.release();
+  if (raw->flags_h) raw->monitor = std::thread(monitor_main, raw);
   for (int i = 0; i < (int)raw->lanes.size(); ++i) raw->lanes[i].th = std::thread(lane_main, raw, i);
   *out = raw;
   return SPX_OK;
@@ -384,7 +593,7 @@ int spx_submit(spx_server* s, const spx_request* r, uint64_t* ticket) {
   if (!s || !r || !ticket) return fail(SPX_EINVAL, "spx_submit: null argument");
   if (r->n < 1 || r->n > 65536 || r->nrhs < 1 || r->nrhs > 4096 || !r->A || !r->B || !r->X || r->lda < r->n ||
       r->ldb < r->nrhs || r->ldx < r->nrhs || (r->mode != SPX_MODE_FP64 && r->mode != SPX_MODE_MIXED) ||
-      (r->where != 0 && r->where != 1) || (const double*)r->X == r->B)
+      r->where < 0 || r->where > 2 || (const double*)r->X == r->B)
     return fail(SPX_EINVAL, "spx_submit: bad request");
   int32_t b = 0;
   const int rc = spx_tile_for(s->tuner, r->mode == SPX_MODE_MIXED ? SPX_PREC_FP32 : SPX_PREC_FP64, r->n, &b);
@@ -463,11 +672,18 @@ void spx_server_destroy(spx_server* s) {
   s->cv.notify_all();
   for (auto& ln : s->lanes)
     if (ln.th.joinable()) ln.th.join();
+  s->mon_stop.store(true);
+  if (s->monitor.joinable()) s->monitor.join();
   for (auto& ln : s->lanes) {
     spx_ctx_destroy(ln.ctx);
     (void)hipStreamSynchronize(ln.stream);
     (void)hipStreamDestroy(ln.stream);
   }
+  if (s->mon_stream) {
+    (void)hipStreamSynchronize(s->mon_stream);
+    (void)hipStreamDestroy(s->mon_stream);
+  }
+  if (s->flags_h) (void)hipHostFree(s->flags_h);
   delete s;
 }
 

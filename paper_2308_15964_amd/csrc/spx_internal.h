@@ -98,6 +98,9 @@ struct DevMat {
   const double* ga;
   const double* gbt;
   unsigned long long spin_ticks;  // SPX_T_SPIN: device clock ticks each task waits
+  // set to 1 (system scope) when the matrix's STORE has been released: its X is final in
+  // device memory (host-visible flag of the serving loop), or null
+  unsigned int* done_flag;
 };
 
 // A LOAD task has one part per lower tile while they fit the 16-bit part index.
@@ -219,6 +222,9 @@ int scratch_get(int device, void** ptr);
 
 // Context internals the serving loop needs.
 int ctx_device(const spx_ctx* c);
+// Per-matrix completion flags (device-visible pointers, one per matrix, entries may be
+// null) for the next batched solve on the context; null clears them.
+void ctx_set_store_flags(spx_ctx* c, unsigned int* const* flags);
 int ctx_copy_tile_tables(const spx_ctx* from, spx_ctx* to);
 
 }  // namespace spx

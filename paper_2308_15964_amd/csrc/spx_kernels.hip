@@ -1774,6 +1774,11 @@ __device__ __noinline__ void release_rounds(const SchedArgs& a, int x, int home)
         }
         if (task == EMPTY32 || sub_rlx(a.parts_left + task, 1u) != 1u) continue;
         drop_locks(a, task, home);
+        if (a.tasks[task].type == SPX_T_STORE) {
+          // the release above wrote the STORE's X back: tell the host this matrix is done
+          unsigned int* flag = a.mats[a.tasks[task].mat].done_flag;
+          if (flag) __hip_atomic_store(flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        }
         for (uint32_t q = a.succ_off[task]; q < a.succ_off[task + 1]; ++q) {
           const uint32_t s = a.succ[q];
           if (sub_rlx(a.pending + s, 1u) == 1u) start_task(a, s, home);
@@ -2213,7 +2218,8 @@ __global__ __launch_bounds__(NT) void residual_batched_kernel(const ResDesc* __r
 // ---------------------------------------------------------------------------------------
 static int hip_ok(hipError_t e, const char* what) {
   if (e == hipSuccess) return SPX_OK;
-  return failf(SPX_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+  // a launch that cannot get its scratch memory reports out of memory: the caller may retry smaller
+  return failf(e == hipErrorOutOfMemory ? SPX_ENOMEM : SPX_EDEVICE, "%s: %s", what, hipGetErrorString(e));
 }
 
 // ---------------------------------------------------------------------------------------

@@ -74,12 +74,12 @@ class Result(ctypes.Structure):
                 ("tile", ctypes.c_int32), ("info", ctypes.c_int64), ("eta_max", ctypes.c_double),
                 ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double), ("t_start", ctypes.c_double),
                 ("t_done", ctypes.c_double), ("tag", ctypes.c_uint64), ("batch_size", ctypes.c_int32),
-                ("lane", ctypes.c_int32)]
+                ("lane", ctypes.c_int32), ("t_ready", ctypes.c_double)]
 
 
 class ServerOpts(ctypes.Structure):
     _fields_ = [("lanes", ctypes.c_int32), ("max_batch", ctypes.c_int32), ("num_wg", ctypes.c_int32),
-                ("pad", ctypes.c_int32)]
+                ("mixed_min_n", ctypes.c_int32)]
 
 
 class ServerStats(ctypes.Structure):
@@ -575,25 +575,28 @@ class Server:
     Tensors passed to submit() must stay alive and unmodified until the ticket is done;
     the server keeps a reference to them until poll() returns the result."""
 
-    def __init__(self, ctx, hbm_budget_bytes, lanes=2, max_batch=0, num_wg=0):
+    def __init__(self, ctx, hbm_budget_bytes, lanes=2, max_batch=0, num_wg=0, mixed_min_n=0):
         self.ctx = ctx
         h = ctypes.c_void_p()
-        o = ServerOpts(lanes, max_batch, num_wg, 0)
+        o = ServerOpts(lanes, max_batch, num_wg, mixed_min_n)
         _check(lib().spx_server_create(ctx._h, int(hbm_budget_bytes), ctypes.byref(o), ctypes.byref(h)))
         self._h = h
         self._keep = {}
 
     def submit(self, A, B, X, mode=MODE_FP64, tol=0.0, tag=0):
-        """A: n x n, B and X: n x nrhs float64, all on the device or all on the host
-        (host tensors are best pinned).  Returns the ticket."""
+        """A: n x n, B and X: n x nrhs float64, all on the device, all on the host, or A and
+        B on the device and X on the host (host tensors are best pinned).  Returns the ticket."""
         torch = self.ctx.torch
         ts = (A, B, X)
         if not all(isinstance(t, torch.Tensor) and t.dtype == torch.float64 and t.dim() == 2 and t.stride(1) == 1
                    for t in ts):
             raise TypeError("A, B, X must be 2-D float64 tensors with unit column stride")
-        where = 1 if A.is_cuda else 0
-        if any(t.is_cuda != A.is_cuda for t in ts):
-            raise ValueError("A, B and X must all be on the device or all on the host")
+        if A.is_cuda and B.is_cuda and not X.is_cuda:
+            where = 2  # inputs on the device, the solution to host memory
+        elif all(t.is_cuda == A.is_cuda for t in ts):
+            where = 1 if A.is_cuda else 0
+        else:
+            raise ValueError("A, B, X: all on the device, all on the host, or A and B on the device and X on the host")
         r = Request(A.shape[0], B.shape[1], A.data_ptr(), B.data_ptr(), X.data_ptr(), A.stride(0), B.stride(0),
                     X.stride(0), mode, where, tol, tag)
         t = ctypes.c_uint64()

@@ -10,6 +10,8 @@ Pins:
   * admission: peak bytes in use never exceed the budget; a request larger than the
     budget is refused at submission.
 """
+import time
+
 import numpy as np
 import pytest
 
@@ -92,7 +94,7 @@ def test_fp64_alone_equals_mix_and_oracle(ctx):
 def test_mixed_refined_alone_equals_mix(ctx):
     from paper_2308_15964_amd import spx
 
-    srv = spx.Server(ctx, 8 << 30, lanes=3)
+    srv = spx.Server(ctx, 8 << 30, lanes=3, mixed_min_n=1)  # every request through FP32 + refinement
     target = inputs.reflector_spd(257, 1e5, seed=9, nrhs=2)
     [x_alone], [r_alone] = run_all(srv, [target], spx.MODE_MIXED, tol=1e-12)
     items = mixture(20, seed=6, kappa=1e4)
@@ -152,7 +154,7 @@ def test_budget_admission_mixed(ctx):
     try:
         items = [inputs.gram_spd(500, seed=90 + i, nrhs=2) for i in range(6)]
         budget = 11 << 20  # two of these requests at once
-        srv = spx.Server(ctx, budget, lanes=2)
+        srv = spx.Server(ctx, budget, lanes=2, mixed_min_n=1)
         xs, rs = run_all(srv, items, spx.MODE_MIXED)
         st = srv.stats()
         srv.close()
@@ -196,3 +198,87 @@ def test_destroy_with_requests_in_flight(ctx):
         srv.submit(Ad, Bd, X)
     srv.close()  # running batches finish, the rest end aborted; no hang, no fault
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("host", [False, True])
+def test_per_request_completion(ctx, host):
+    """One FP64 batch holding an N=4096 system and small ones: each small request's STORE
+    raises its completion flag while the large factorization is still running, so its X
+    is in place (t_ready) well before the large one's and before the batch ends (t_done);
+    every result is still the oracle's, and the large one's backward error is tiny.  A
+    larger request submitted first keeps the single lane busy while the others arrive, so
+    they are taken as one batch."""
+    from paper_2308_15964_amd import spx
+
+    blocker = inputs.gram_spd(6144, seed=40, nrhs=1)
+    items = [inputs.gram_spd(4096, seed=41, nrhs=1)] + mixture(6, seed=42)
+
+    def tensors(A, B):
+        if host:
+            Ad = torch.from_numpy(np.ascontiguousarray(A)).pin_memory()
+            Bd = torch.from_numpy(np.ascontiguousarray(B)).pin_memory()
+            return Ad, Bd, torch.empty(B.shape, dtype=torch.float64).pin_memory()
+        Ad, Bd = dev(A), dev(B)
+        return Ad, Bd, torch.empty_like(Bd)
+
+    srv = spx.Server(ctx, 16 << 30, lanes=1)
+    try:
+        run_all(srv, [blocker] + items, spx.MODE_FP64, host=host)  # warm-up: images, pool
+        tb = tensors(*blocker)
+        ts = [tensors(A, B) for A, B in items]
+        torch.cuda.synchronize()
+        launches = srv.stats()["launches"]
+        t0 = srv.submit(*tb, mode=spx.MODE_FP64)
+        while srv.stats()["launches"] == launches:  # the blocker's batch has started
+            time.sleep(0.0001)
+        tickets = [srv.submit(*t, mode=spx.MODE_FP64) for t in ts]
+        srv.wait(t0)
+        res = [srv.wait(t) for t in tickets]
+        Xs = [t[2].cpu().numpy() for t in ts]
+    finally:
+        srv.close()
+    assert len({r["t_start"] for r in res}) == 1  # one batch
+    big, small = res[0], res[1:]
+    for r in res:
+        assert r["status"] == 0 and r["info"] == 0
+        assert r["t_start"] <= r["t_ready"] <= r["t_done"]
+    assert max(r["t_ready"] for r in small) < big["t_ready"]
+    for (A, B), X in zip(items[1:], Xs[1:]):
+        _, Xo, info = oracle.cholesky(A, A.shape[0], B)
+        assert info == 0
+        assert (np.abs(X.reshape(Xo.shape) - Xo) <= 1e-12 * np.abs(Xo).max(axis=0)).all()
+    A, B = items[0]
+    assert oracle.backward_error(A, Xs[0], B).max() <= 1e-14
+
+
+def test_mixed_ready_at_batch_end(ctx):
+    from paper_2308_15964_amd import spx
+
+    srv = spx.Server(ctx, 4 << 30, lanes=1)
+    try:
+        _, res = run_all(srv, mixture(4, seed=43, kappa=1e3), spx.MODE_MIXED, tol=1e-12)
+    finally:
+        srv.close()
+    for r in res:
+        assert r["status"] == 0 and r["t_ready"] == r["t_done"]
+
+
+def test_device_inputs_host_results(ctx):
+    """where = 2 (A, B on the device, X in host memory) gives the device-only bits."""
+    from paper_2308_15964_amd import spx
+
+    items = mixture(8, seed=44)
+    srv = spx.Server(ctx, 4 << 30, lanes=2)
+    try:
+        X1, _ = run_all(srv, items, spx.MODE_FP64)
+        tickets, outs = [], []
+        for A, B in items:
+            X = torch.empty(B.shape, dtype=torch.float64).pin_memory()
+            tickets.append(srv.submit(dev(A), dev(B), X, mode=spx.MODE_FP64))
+            outs.append(X)
+        res = [srv.wait(t) for t in tickets]
+    finally:
+        srv.close()
+    for x1, x2, r in zip(X1, outs, res):
+        assert r["status"] == 0 and r["t_ready"] <= r["t_done"]
+        assert np.array_equal(x1, x2.numpy())
