@@ -461,7 +461,8 @@ int spx_last_stats(const spx_ctx* ctx, spx_stats* out);
  * 0 turns it off.  Errors: SPX_EINVAL for other bits. */
 int spx_ctx_set_flags(spx_ctx* ctx, uint32_t flags);
 /* Per-part trace of the last launch made with SPX_F_TRACE: for part p, rec[4p..4p+3] =
- * {task, part | (workgroup << 16), start tick, end tick} (device wall clock, 100 MHz).
+ * {task, part | (workgroup << 16) | (task type << 32), start tick, end tick} (device wall
+ * clock, 100 MHz).
  * Returns the record count (or < 0); writes at most cap records. */
 int64_t spx_trace(const spx_ctx* ctx, uint64_t* rec, int64_t cap);
 /* Push ticks of the same launch: ticks[t] = the device clock when task t's last

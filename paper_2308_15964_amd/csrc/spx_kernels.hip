@@ -1290,8 +1290,65 @@ __device__ void update_rows(const double* __restrict__ l, int b, double* __restr
 }
 
 // Sub-block (si, sj) of size S x S of tile (ti, tj); s: 64 x 65 doubles of LDS.
+// Every thread's S*S/NT elements are loaded (all loads issued together) before any is
+// stored to LDS, and read back from LDS before any global store: one memory round trip
+// each way per sub-block.
+template <int S>
+__device__ void pack_block_s(const double* __restrict__ A, int64_t lda, int64_t n, const DevMat& m, int ti, int tj,
+                             int si, int sj, double* __restrict__ s) {
+  constexpr int PER = S * S / NT;
+  const int b = m.b;
+  const int64_t R0 = (int64_t)ti * b + si * S, C0 = (int64_t)tj * b + sj * S;
+  LDSAS double* sl = lp(s);
+  const GLOBAL double* Ag = gp(A);
+  double v[PER];
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int e = threadIdx.x + i * NT, rr = e / S, cc = e % S;  // cc fastest: row-major reads
+    const int64_t R = R0 + rr, C = C0 + cc;
+    v[i] = (R < n && C < n) ? (R >= C ? Ag[R * lda + C] : 0.0) : (R == C ? 1.0 : 0.0);
+  }
+  if (m.dscale) {
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int e = threadIdx.x + i * NT, rr = e / S, cc = e % S;
+      const int64_t R = R0 + rr, C = C0 + cc;
+      if (R < n && C < n) {
+        v[i] = v[i] * m.dscale[R] * m.dscale[C];
+        if (R == C) v[i] += m.shift;
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int e = threadIdx.x + i * NT;
+    sl[(e / S) * 65 + e % S] = v[i];
+  }
+  __syncthreads();
+  GLOBAL double* T = gp(tile_ptr(m, ti, tj));
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int e = threadIdx.x + i * NT, cc = e / S, rr = e % S;  // rr fastest: column-major writes
+    v[i] = sl[rr * 65 + cc];
+  }
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int e = threadIdx.x + i * NT, cc = e / S, rr = e % S;
+    T[(size_t)(sj * S + cc) * b + si * S + rr] = v[i];
+  }
+  __syncthreads();
+}
+
 __device__ void pack_block(const double* __restrict__ A, int64_t lda, int64_t n, const DevMat& m, int ti, int tj,
                            int si, int sj, int S, double* __restrict__ s) {
+  if (S == 64) {
+    pack_block_s<64>(A, lda, n, m, ti, tj, si, sj, s);
+    return;
+  }
+  if (S == 32) {
+    pack_block_s<32>(A, lda, n, m, ti, tj, si, sj, s);
+    return;
+  }
   const int b = m.b;
   const int64_t R0 = (int64_t)ti * b + si * S, C0 = (int64_t)tj * b + sj * S;
   for (int e = threadIdx.x; e < S * S; e += NT) {
@@ -1893,7 +1950,7 @@ __global__ __launch_bounds__(NT) void sched_kernel(SchedArgs a) {
           const uint32_t k = atomicAdd(a.trace_idx, 1u);
           if (k < a.total_parts) {
             a.trace[4 * k + 0] = task;
-            a.trace[4 * k + 1] = part | ((u64)blockIdx.x << 16);
+            a.trace[4 * k + 1] = part | ((u64)blockIdx.x << 16) | ((u64)a.tasks[task].type << 32);
             a.trace[4 * k + 2] = tb;
             a.trace[4 * k + 3] = te;
           }
