@@ -411,50 +411,83 @@ __device__ void lower_inverse32(const double* __restrict__ Lg, double* __restric
   }
 }
 
+// A double from one lane of the wave, as a uniform (scalar) value.
+__device__ __forceinline__ double lane_value(double v, int l) {
+  const unsigned long long u = __double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)u, l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), l);
+  return __longlong_as_double(((unsigned long long)hi << 32) | lo);
+}
+
 // One wave factors the 32x32 lower block D (column-major in LDS, D(r, j) at D[j*32 + r]) in
-// place and writes its inverse to Z (column-major, zeros above the diagonal).  Right-looking
-// by columns: lane r keeps row r in registers; column c, once scaled, is written to D and
-// read back by every lane as same-address LDS loads.  Every lane also carries the updated
-// diagonal (the same FMAs in the same order as the owning lane), so the pivot needs no
-// exchange.  Returns the 1-based column of the first non-positive or NaN pivot (D is then
-// partly overwritten and Z not written), or 0; the same value in every lane.
-__device__ int factor_inverse32(double* __restrict__ Dg, double* __restrict__ Z) {
-  const int lane = threadIdx.x & 63;
+// place and writes its inverse to Z (column-major, zeros above the diagonal), in one
+// right-looking pass over the columns.  Lanes 0-31 hold row r of the block being factored,
+// lanes 32-63 column r of Z = L^{-1} (starting from e_r); column c of L, once scaled, is
+// applied by both halves alike (v[j] -= a L(j, c) for j > c, with a = L(r, c) in a factor
+// lane and Z(c, r) in an inverse lane), so the inverse rides on the factorization's
+// broadcasts.  The pivot and L(c+1, c) move between lanes as uniform values, and the rest
+// of column c goes through LDS and is applied one column later, so the LDS round trip is
+// off the pivot chain; every entry still takes its updates in column order.  Column scale
+// r: the hardware reciprocal square root refined by two Newton steps, L(c, c) = p r (no
+// IEEE square root).  Returns the 1-based column of the first non-positive or NaN pivot (D
+// and Z then hold partial values), or 0; the same value in every lane.
+__device__ __forceinline__ int factor_inverse32(double* __restrict__ Dg, double* __restrict__ Zg) {
+  const int lane = threadIdx.x & 63, r = lane & 31;
+  const bool inv = lane >= 32;
   LDSAS double* D = lp(Dg);
-  double row[32], dg[32];
+  LDSAS double* Z = lp(Zg);
+  double v[32];
 #pragma unroll
   for (int j = 0; j < 32; ++j) {
-    row[j] = (lane < 32 && lane >= j) ? D[j * 32 + lane] : 0.0;
-    dg[j] = D[j * 33];
+    const double x = D[j * 32 + r];
+    v[j] = inv ? (j == r ? 1.0 : 0.0) : (r >= j ? x : 0.0);
   }
   wave_lds_sync();  // every lane has read D before column 0 is overwritten
+  double col[32];   // column c - 1 of L, rows c + 1 .. 31, from LDS
+  double aprev = 0.0;
 #pragma unroll
   for (int c = 0; c < 32; ++c) {
-    const double p = dg[c];
+    const double p = lane_value(v[c], c);
+    // a uniform branch; it also ends the column's basic block, which keeps the compiler
+    // from sinking the column's updates to their last use
     if (!(p > 0.0)) return c + 1;
-    // r = 1/sqrt(p): the hardware estimate and two Newton steps, so the column scale and
-    // the pivot L(c,c) = p r come from one short chain (no IEEE divide or square root);
-    // exact for p = 1 and within a few ulp otherwise
     const double hp = 0.5 * p;
-    double r = __builtin_amdgcn_rsq(p);
-    r = fma(r, fma(-hp * r, r, 0.5), r);
-    r = fma(r, fma(-hp * r, r, 0.5), r);
-    const double d = p * r;
-    const double lrc = lane > c ? row[c] * r : (lane == c ? d : 0.0);
-    row[c] = lrc;
-    if (lane < 32) D[c * 32 + lane] = lrc;
-    wave_lds_sync();
-    double col[32];  // all loads issued before the first use
+    double rs = __builtin_amdgcn_rsq(p);
+    rs = fma(rs, fma(-hp * rs, rs, 0.5), rs);
+    rs = fma(rs, fma(-hp * rs, rs, 0.5), rs);
+    // factor lanes: L(r, c) = v[c] rs below the diagonal and L(c, c) = p rs on it (v[c] = p
+    // in lane c), 0 above; inverse lanes: Z(c, r) = v[c] / L(c, c) (0 for c < r), an IEEE
+    // quotient as a substitution with the stored factor makes it
+    const double af = r >= c ? v[c] * rs : 0.0;
+    const double a = inv ? v[c] * (1.0 / (p * rs)) : af;
+    v[c] = a;
+    // row c + 1 first (the next pivot): column c - 1's update, then column c's, with
+    // L(c + 1, c) taken from lane c + 1 (af: the quotient stays off the pivot chain); then
+    // column c - 1 on the rows after it
+    if (c >= 1 && c + 1 < 32) v[c + 1] -= aprev * col[c + 1];
+    if (c + 1 < 32) v[c + 1] -= a * lane_value(af, c + 1);
+    if (c >= 1) {
 #pragma unroll
-    for (int j = c + 1; j < 32; ++j) col[j] = D[c * 32 + j];
-#pragma unroll
-    for (int j = c + 1; j < 32; ++j) {
-      row[j] -= lrc * col[j];
-      dg[j] -= col[j] * col[j];
+      for (int j = c + 2; j < 32; ++j) v[j] -= aprev * col[j];
     }
+    // column c of L to LDS; the inverse lanes store theirs into Z, which the end
+    // overwrites (an address select rather than a divergent branch)
+    (inv ? Z : D)[c * 32 + r] = a;
+    wave_lds_sync();
+    const LDSAS d2* C2 = (const LDSAS d2*)(D + c * 32);
+#pragma unroll
+    for (int h = (c + 2) >> 1; h < 16; ++h) {
+      const d2 t = C2[h];
+      col[2 * h] = t[0];
+      col[2 * h + 1] = t[1];
+    }
+    aprev = a;
+  }
+  if (inv) {
+#pragma unroll
+    for (int m = 0; m < 32; ++m) Z[r * 32 + m] = m >= r ? v[m] : 0.0;
   }
   wave_lds_sync();
-  lower_inverse32(Dg, Z);
   return 0;
 }
 
@@ -473,7 +506,7 @@ __device__ void inverse32(const double* __restrict__ L, double* __restrict__ Z) 
 // may then be A itself, since each wave reads all of its rows before writing them.
 // ---------------------------------------------------------------------------------------
 template <int NBMAX, bool ASSIGN>
-__device__ void gemm_tall32_f64(double* __restrict__ C, int ldc, const double* __restrict__ A, int lda,
+__device__ __forceinline__ void gemm_tall32_f64(double* __restrict__ C, int ldc, const double* __restrict__ A, int lda,
                                 const double* __restrict__ B, int ldb, int M, int K, bool lower,
                                 double* __restrict__ lds) {
   constexpr int KC = NBMAX >= 8 ? 16 : (NBMAX >= 2 ? 32 : 64), KS = KC / 4;  // more depth for fewer blocks
@@ -581,7 +614,7 @@ __device__ void gemm_tall32_f64(double* __restrict__ C, int ldc, const double* _
 // Products transposed as in gemm_tall32_f64 (lane l: row 16q + l%16, column 16 jb + l/16
 // + 4v).  M: multiple of 16, at most 16 NBW 4/KS.  K: multiple of 16 G KS.
 template <int NBW, int G, int KS>
-__device__ void gemm_tall32_split(double* __restrict__ C, int ldc, const double* __restrict__ A, int lda,
+__device__ __forceinline__ void gemm_tall32_split(double* __restrict__ C, int ldc, const double* __restrict__ A, int lda,
                                   const double* __restrict__ B, int ldb, int M, int K, bool lower,
                                   double* __restrict__ lds) {
   constexpr int GROUPS = 4 / KS;
@@ -688,7 +721,7 @@ __device__ void gemm_tall32_split(double* __restrict__ C, int ldc, const double*
   __syncthreads();  // LDS partials consumed before the caller reuses LDS
 }
 
-__device__ void gemm_tall32_any(double* C, int ldc, const double* A, int lda, const double* B, int ldb, int M, int K,
+__device__ __forceinline__ void gemm_tall32_any(double* C, int ldc, const double* A, int lda, const double* B, int ldb, int M, int K,
                                 bool lower, double* lds) {
   if (K <= 0 || M <= 0) return;
   if (M <= 128 && K % 64 == 0) {  // few rows: K split four ways
@@ -715,7 +748,7 @@ __device__ void gemm_tall32_any(double* C, int ldc, const double* A, int lda, co
 }
 
 // X[M x 32] <- X * Li^T in place, Li a 32x32 block inverse (column-major, ld 32).
-__device__ void apply_inv_tall(double* X, int ldx, const double* Li, int M, double* lds) {
+__device__ __forceinline__ void apply_inv_tall(double* X, int ldx, const double* Li, int M, double* lds) {
   if (M <= 0) return;
   if (M <= 128)
     gemm_tall32_f64<2, true>(X, ldx, X, ldx, Li, 32, M, 32, false, lds);
@@ -726,7 +759,7 @@ __device__ void apply_inv_tall(double* X, int ldx, const double* Li, int M, doub
 // One workgroup factors the updated 32x32 diagonal block at (c0, c0) of a b x b tile in
 // place (one wave, in LDS) and stores its inverse as block c0/32 of dinv.  Returns (to all
 // threads) 0 or the 1-based local column of a non-positive or NaN pivot.
-__device__ int factor_diag32(double* __restrict__ a, int b, int c0, double* __restrict__ dinv,
+__device__ __forceinline__ int factor_diag32(double* __restrict__ a, int b, int c0, double* __restrict__ dinv,
                              double* __restrict__ lds) {
   __shared__ int s_bad;
   const int tid = threadIdx.x;
@@ -765,7 +798,7 @@ __device__ int factor_diag32(double* __restrict__ a, int b, int c0, double* __re
 // dinv (b/32 column-major 32x32 blocks) for the TRSM and solve tasks.  Returns (to all
 // threads) 0 or the 1-based local column of a non-positive or NaN pivot.
 // ---------------------------------------------------------------------------------------
-__device__ int potrf_tile(double* __restrict__ a, int b, double* __restrict__ dinv, double* __restrict__ lds) {
+__device__ __noinline__ int potrf_tile(double* __restrict__ a, int b, double* __restrict__ dinv, double* __restrict__ lds) {
   for (int c0 = 0; c0 < b; c0 += 32) {
     gemm_tall32_any(a + (size_t)c0 * b + c0, b, a + c0, b, a + c0, b, b - c0, c0, true, lds);
     __syncthreads();
@@ -797,7 +830,7 @@ __device__ int potrf_tile(double* __restrict__ a, int b, double* __restrict__ di
 // count), so the two forms agree to rounding, not bitwise.  Returns (to all threads) 0 or
 // the 1-based local column of a bad pivot.
 // ---------------------------------------------------------------------------------------
-__device__ int potrf_step_part(double* __restrict__ a, int b, double* __restrict__ dinv, int c, int part,
+__device__ __noinline__ int potrf_step_part(double* __restrict__ a, int b, double* __restrict__ dinv, int c, int part,
                                double* __restrict__ lds) {
   const int nb = b >> 5, c0 = 32 * c;
   if (part > 0) {
@@ -836,7 +869,7 @@ __device__ int potrf_step_part(double* __restrict__ a, int b, double* __restrict
 // rows' diagonal); they are neither read nor written.
 // ---------------------------------------------------------------------------------------
 template <int NCB>
-__device__ void trsm_strip32(double* __restrict__ x, const double* __restrict__ l, const double* __restrict__ dinv,
+__device__ __forceinline__ void trsm_strip32(double* __restrict__ x, const double* __restrict__ l, const double* __restrict__ dinv,
                              int b, int r0, void* __restrict__ low, int prec, double* __restrict__ lds, int k0) {
   constexpr int LDX = 34;  // padded LDS column (32 rows)
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -928,7 +961,7 @@ __device__ void trsm_strip32(double* __restrict__ x, const double* __restrict__ 
   }
 }
 
-__device__ void trsm_part(double* __restrict__ x, const double* __restrict__ l, const double* __restrict__ dinv,
+__device__ __noinline__ void trsm_part(double* __restrict__ x, const double* __restrict__ l, const double* __restrict__ dinv,
                           int b, int r0, void* __restrict__ low, int prec, double* __restrict__ lds, int k0 = 0) {
   if (b > 256)
     trsm_strip32<8>(x, l, dinv, b, r0, low, prec, lds, k0);
