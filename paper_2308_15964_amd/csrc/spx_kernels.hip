@@ -62,6 +62,12 @@ __device__ __forceinline__ u64 now_ticks() { return wall_clock64(); }
 
 // Inverses of the 32x32 diagonal blocks of diagonal tile k: b/32 column-major blocks.
 __device__ __forceinline__ double* dinv_ptr(const DevMat& m, int k) { return m.dinv + (size_t)k * 32 * m.b; }
+// Rows (and columns) of tile row k that hold the matrix, rounded up to 32: the rest of the
+// last tile row is identity padding.
+__device__ __forceinline__ int tile_active(const DevMat& m, int k) {
+  const int rem = m.n - k * m.b;
+  return rem >= m.b ? m.b : ((rem + 31) & ~31);
+}
 
 // Relaxed agent-scope load of a scheduler counter (ordering comes from explicit fences).
 __device__ __forceinline__ uint32_t ld_rlx(const uint32_t* p) {
@@ -119,7 +125,7 @@ __device__ __forceinline__ void update_epilogue(double* C, int ldc, const ACC (&
 // it: in the Cholesky kernel its extra registers made the compiler spill (see run_part).
 // ---------------------------------------------------------------------------------------
 template <int WT, bool FULL = false>
-__device__ void gemm_nt_f64(double* __restrict__ C, int ldc, const double* __restrict__ A, int lda,
+__device__ __forceinline__ void gemm_nt_f64(double* __restrict__ C, int ldc, const double* __restrict__ A, int lda,
                             const double* __restrict__ B, int ldb, int M, int N, int K, bool lower,
                             double* __restrict__ lds, double sgn = 1.0) {
   constexpr int SB = 2 * WT;
@@ -195,7 +201,7 @@ __device__ void gemm_nt_f64(double* __restrict__ C, int ldc, const double* __res
 }
 
 // Dispatch on the block size: M, N <= 128.
-__device__ void gemm_nt_any(double* C, int ldc, const double* A, int lda, const double* B, int ldb, int M, int N,
+__device__ __forceinline__ void gemm_nt_any(double* C, int ldc, const double* A, int lda, const double* B, int ldb, int M, int N,
                             int K, bool lower, double* lds) {
   const int mx = M > N ? M : N;
   if (mx > 64)
@@ -503,16 +509,18 @@ __device__ void inverse32(const double* __restrict__ L, double* __restrict__ Z) 
 // chunk carries enough matrix-core work to cover the next chunk's loads.  M: multiple of
 // 16, at most 64 * NBMAX.  K: multiple of 64 / NBMAX (of 16 for NBMAX >= 8).
 // lower: write only row >= col (C starts on the diagonal).  ASSIGN: C = A * B^T instead; C
-// may then be A itself, since each wave reads all of its rows before writing them.
+// may then be A itself, since each wave reads all of its rows before writing them.  Ma
+// (a multiple of 16): only rows below Ma are read and written; the work split and each
+// computed row's arithmetic are those of the full M.
 // ---------------------------------------------------------------------------------------
 template <int NBMAX, bool ASSIGN>
 __device__ __forceinline__ void gemm_tall32_f64(double* __restrict__ C, int ldc, const double* __restrict__ A, int lda,
                                 const double* __restrict__ B, int ldb, int M, int K, bool lower,
-                                double* __restrict__ lds) {
+                                double* __restrict__ lds, int Ma = 1 << 30) {
   constexpr int KC = NBMAX >= 8 ? 16 : (NBMAX >= 2 ? 32 : 64), KS = KC / 4;  // more depth for fewer blocks
   constexpr int BPT = KC * 32 / NT;                                            // B elements per thread
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int nblk = M >> 4, kl = lane >> 4, li = lane & 15;
+  const int nblk = (Ma < M ? Ma : M) >> 4, kl = lane >> 4, li = lane & 15;
   d4 acc[NBMAX][2];
 #pragma unroll
   for (int t = 0; t < NBMAX; ++t) acc[t][0] = acc[t][1] = d4{0.0, 0.0, 0.0, 0.0};
@@ -612,17 +620,20 @@ __device__ __forceinline__ void gemm_tall32_f64(double* __restrict__ C, int ldc,
 // of one wave's loads hides behind the others' products).  With KS > 1 the partial
 // products meet in LDS and each wave reduces and writes a quarter of the 16x16 tiles.
 // Products transposed as in gemm_tall32_f64 (lane l: row 16q + l%16, column 16 jb + l/16
-// + 4v).  M: multiple of 16, at most 16 NBW 4/KS.  K: multiple of 16 G KS.
+// + 4v).  M: multiple of 16, at most 16 NBW 4/KS.  K: multiple of 16 G KS.  Ma (a
+// multiple of 16): only rows below Ma are read and written, with the work split and the
+// per-row arithmetic of the full M.
 template <int NBW, int G, int KS>
 __device__ __forceinline__ void gemm_tall32_split(double* __restrict__ C, int ldc, const double* __restrict__ A, int lda,
                                   const double* __restrict__ B, int ldb, int M, int K, bool lower,
-                                  double* __restrict__ lds) {
+                                  double* __restrict__ lds, int Ma = 1 << 30) {
   constexpr int GROUPS = 4 / KS;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int nblk = M >> 4, kl = lane >> 4, li = lane & 15;
   const int nbp = (nblk + GROUPS - 1) / GROUPS;  // row blocks per group
   const int rg = wave / KS, q0 = rg * nbp;
-  const int nmine = nblk - q0 < nbp ? (nblk - q0 > 0 ? nblk - q0 : 0) : nbp;
+  const int nlive = (Ma < M ? Ma : M) >> 4;  // row blocks read and written
+  const int nmine = nlive - q0 < nbp ? (nlive - q0 > 0 ? nlive - q0 : 0) : nbp;
   const int kq = K / KS, kb = (wave % KS) * kq;
   const GLOBAL double* Ag = gp(A);
   const GLOBAL double* Bg = gp(B);
@@ -698,7 +709,7 @@ __device__ __forceinline__ void gemm_tall32_split(double* __restrict__ C, int ld
 #pragma unroll
       for (int v = 0; v < 4; ++v) P[((wave * T + 2 * t + jb) * 4 + v) * 64 + lane] = acc[t][jb][v];
   __syncthreads();
-  for (int tile = wave; tile < 2 * nblk; tile += 4) {
+  for (int tile = wave; tile < 2 * nlive; tile += 4) {
     const int q = tile >> 1, jb = tile & 1;
     const int g0 = (q / nbp) * KS, lt = 2 * (q % nbp) + jb;  // first wave of the row group, its tile
     const int row = 16 * q + li;
@@ -722,38 +733,40 @@ __device__ __forceinline__ void gemm_tall32_split(double* __restrict__ C, int ld
 }
 
 __device__ __forceinline__ void gemm_tall32_any(double* C, int ldc, const double* A, int lda, const double* B, int ldb, int M, int K,
-                                bool lower, double* lds) {
+                                bool lower, double* lds, int Ma = 1 << 30) {
   if (K <= 0 || M <= 0) return;
   if (M <= 128 && K % 64 == 0) {  // few rows: K split four ways
-    if (M <= 32) gemm_tall32_split<2, 4, 4>(C, ldc, A, lda, B, ldb, M, K, lower, lds);
-    else if (M <= 64) gemm_tall32_split<4, 4, 4>(C, ldc, A, lda, B, ldb, M, K, lower, lds);
-    else gemm_tall32_split<8, 4, 4>(C, ldc, A, lda, B, ldb, M, K, lower, lds);
+    if (M <= 32) gemm_tall32_split<2, 4, 4>(C, ldc, A, lda, B, ldb, M, K, lower, lds, Ma);
+    else if (M <= 64) gemm_tall32_split<4, 4, 4>(C, ldc, A, lda, B, ldb, M, K, lower, lds, Ma);
+    else gemm_tall32_split<8, 4, 4>(C, ldc, A, lda, B, ldb, M, K, lower, lds, Ma);
   } else if (M <= 128 && K % 32 == 0) {
-    if (M <= 32) gemm_tall32_split<2, 2, 4>(C, ldc, A, lda, B, ldb, M, K, lower, lds);
-    else if (M <= 64) gemm_tall32_split<4, 2, 4>(C, ldc, A, lda, B, ldb, M, K, lower, lds);
-    else gemm_tall32_split<8, 2, 4>(C, ldc, A, lda, B, ldb, M, K, lower, lds);
+    if (M <= 32) gemm_tall32_split<2, 2, 4>(C, ldc, A, lda, B, ldb, M, K, lower, lds, Ma);
+    else if (M <= 64) gemm_tall32_split<4, 2, 4>(C, ldc, A, lda, B, ldb, M, K, lower, lds, Ma);
+    else gemm_tall32_split<8, 2, 4>(C, ldc, A, lda, B, ldb, M, K, lower, lds, Ma);
   } else if (M <= 256 && K % 32 == 0) {  // two row groups, K split two ways
-    gemm_tall32_split<8, 4, 2>(C, ldc, A, lda, B, ldb, M, K, lower, lds);
+    gemm_tall32_split<8, 4, 2>(C, ldc, A, lda, B, ldb, M, K, lower, lds, Ma);
   } else if (M <= 512 && K % 16 == 0) {  // four row groups
-    gemm_tall32_split<8, 4, 1>(C, ldc, A, lda, B, ldb, M, K, lower, lds);
+    gemm_tall32_split<8, 4, 1>(C, ldc, A, lda, B, ldb, M, K, lower, lds, Ma);
   } else if (M <= 64 && K % 64 == 0) {
-    gemm_tall32_f64<1, false>(C, ldc, A, lda, B, ldb, M, K, lower, lds);
+    gemm_tall32_f64<1, false>(C, ldc, A, lda, B, ldb, M, K, lower, lds, Ma);
   } else if (M <= 128 && K % 32 == 0) {
-    gemm_tall32_f64<2, false>(C, ldc, A, lda, B, ldb, M, K, lower, lds);
+    gemm_tall32_f64<2, false>(C, ldc, A, lda, B, ldb, M, K, lower, lds, Ma);
   } else if (M <= 256 && K % 32 == 0) {
-    gemm_tall32_f64<4, false>(C, ldc, A, lda, B, ldb, M, K, lower, lds);
+    gemm_tall32_f64<4, false>(C, ldc, A, lda, B, ldb, M, K, lower, lds, Ma);
   } else {
-    gemm_tall32_f64<8, false>(C, ldc, A, lda, B, ldb, M, K, lower, lds);
+    gemm_tall32_f64<8, false>(C, ldc, A, lda, B, ldb, M, K, lower, lds, Ma);
   }
 }
 
-// X[M x 32] <- X * Li^T in place, Li a 32x32 block inverse (column-major, ld 32).
-__device__ __forceinline__ void apply_inv_tall(double* X, int ldx, const double* Li, int M, double* lds) {
-  if (M <= 0) return;
+// X[M x 32] <- X * Li^T in place, Li a 32x32 block inverse (column-major, ld 32); rows
+// from Ma on are left alone.
+__device__ __forceinline__ void apply_inv_tall(double* X, int ldx, const double* Li, int M, double* lds,
+                                               int Ma = 1 << 30) {
+  if (M <= 0 || Ma <= 0) return;
   if (M <= 128)
-    gemm_tall32_f64<2, true>(X, ldx, X, ldx, Li, 32, M, 32, false, lds);
+    gemm_tall32_f64<2, true>(X, ldx, X, ldx, Li, 32, M, 32, false, lds, Ma);
   else
-    gemm_tall32_f64<8, true>(X, ldx, X, ldx, Li, 32, M, 32, false, lds);
+    gemm_tall32_f64<8, true>(X, ldx, X, ldx, Li, 32, M, 32, false, lds, Ma);
 }
 
 // One workgroup factors the updated 32x32 diagonal block at (c0, c0) of a b x b tile in
@@ -795,18 +808,24 @@ __device__ __forceinline__ int factor_diag32(double* __restrict__ a, int b, int 
 // every factored column (tall matrix-core update, K = c0); one wave then factors its 32x32
 // diagonal block in LDS and inverts it; the rows below are multiplied by the transposed
 // inverse on the matrix cores (K = 32).  The inverses of the diagonal blocks are stored in
-// dinv (b/32 column-major 32x32 blocks) for the TRSM and solve tasks.  Returns (to all
+// dinv (b/32 column-major 32x32 blocks) for the TRSM and solve tasks.  na (a multiple of
+// 32): the tile's rows and columns from na on are the identity padding of the matrix's
+// last tile, which factors to itself: they are not touched, and their diagonal blocks'
+// inverses are written as identities.  The rows below na take exactly the arithmetic of
+// the full tile (the update kernels are chosen by the full row count).  Returns (to all
 // threads) 0 or the 1-based local column of a non-positive or NaN pivot.
 // ---------------------------------------------------------------------------------------
-__device__ __noinline__ int potrf_tile(double* __restrict__ a, int b, double* __restrict__ dinv, double* __restrict__ lds) {
-  for (int c0 = 0; c0 < b; c0 += 32) {
-    gemm_tall32_any(a + (size_t)c0 * b + c0, b, a + c0, b, a + c0, b, b - c0, c0, true, lds);
+__device__ __noinline__ int potrf_tile(double* __restrict__ a, int b, double* __restrict__ dinv, double* __restrict__ lds,
+                                       int na) {
+  for (int c0 = 0; c0 < na; c0 += 32) {
+    gemm_tall32_any(a + (size_t)c0 * b + c0, b, a + c0, b, a + c0, b, b - c0, c0, true, lds, na - c0);
     __syncthreads();
     const int bad = factor_diag32(a, b, c0, dinv, lds);
     if (bad) return bad;
-    apply_inv_tall(a + (size_t)c0 * b + c0 + 32, b, dinv + (size_t)c0 * 32, b - c0 - 32, lds);
+    apply_inv_tall(a + (size_t)c0 * b + c0 + 32, b, dinv + (size_t)c0 * 32, b - c0 - 32, lds, na - c0 - 32);
     __syncthreads();
   }
+  for (int e = threadIdx.x; e < (b - na) * 32; e += NT) dinv[(size_t)na * 32 + e] = ((e & 31) == ((e >> 5) & 31)) ? 1.0 : 0.0;
   return 0;
 }
 
@@ -827,30 +846,36 @@ __device__ __noinline__ int potrf_tile(double* __restrict__ a, int b, double* __
 // part 0 writes only row blocks c and c + 1, which no row part reads, so the parts of a
 // step are independent; successive steps are ordered by the task graph.  The update of a
 // row block may split K differently from potrf_tile's (its kernel depends on the row
-// count), so the two forms agree to rounding, not bitwise.  Returns (to all threads) 0 or
-// the 1-based local column of a bad pivot.
+// count), so the two forms agree to rounding, not bitwise.  na: as for potrf_tile, rows
+// and columns from na on are identity padding; the steps and row blocks there only write
+// identity block inverses.  Returns (to all threads) 0 or the 1-based local column of a
+// bad pivot.
 // ---------------------------------------------------------------------------------------
 __device__ __noinline__ int potrf_step_part(double* __restrict__ a, int b, double* __restrict__ dinv, int c, int part,
-                               double* __restrict__ lds) {
+                                            double* __restrict__ lds, int na) {
   const int nb = b >> 5, c0 = 32 * c;
   if (part > 0) {
     const int r0 = 32 * (c + 1 + part);
-    if (c < 1 || r0 >= b) return 0;
+    if (c < 1 || r0 >= na) return 0;
     apply_inv_tall(a + (size_t)(c0 - 32) * b + r0, b, dinv + (size_t)(c0 - 32) * 32, 32, lds);
     __syncthreads();
     gemm_tall32_any(a + (size_t)c0 * b + r0, b, a + r0, b, a + c0, b, 32, c0, false, lds);
     return 0;
   }
+  if (c0 >= na) {  // a step of the identity padding: its block inverse is the identity
+    for (int e = threadIdx.x; e < 1024; e += NT) dinv[(size_t)c0 * 32 + e] = ((e & 31) == (e >> 5)) ? 1.0 : 0.0;
+    return 0;
+  }
   const bool look = c + 1 < nb;
   if (c >= 1 && look) {
-    apply_inv_tall(a + (size_t)(c0 - 32) * b + c0 + 32, b, dinv + (size_t)(c0 - 32) * 32, 32, lds);
+    apply_inv_tall(a + (size_t)(c0 - 32) * b + c0 + 32, b, dinv + (size_t)(c0 - 32) * 32, 32, lds, na - c0 - 32);
     __syncthreads();
   }
-  gemm_tall32_any(a + (size_t)c0 * b + c0, b, a + c0, b, a + c0, b, look ? 64 : 32, c0, true, lds);
+  gemm_tall32_any(a + (size_t)c0 * b + c0, b, a + c0, b, a + c0, b, look ? 64 : 32, c0, true, lds, na - c0);
   __syncthreads();
   const int bad = factor_diag32(a, b, c0, dinv, lds);
   if (bad) return bad;
-  if (look) apply_inv_tall(a + (size_t)c0 * b + c0 + 32, b, dinv + (size_t)c0 * 32, 32, lds);
+  if (look) apply_inv_tall(a + (size_t)c0 * b + c0 + 32, b, dinv + (size_t)c0 * 32, 32, lds, na - c0 - 32);
   return 0;
 }
 
@@ -1013,7 +1038,7 @@ __device__ void tile_inverses(const double* __restrict__ l, int b, double* __res
 // inverse is loaded into the other half of a double buffer.  Only the block-inverse
 // products change the arithmetic order relative to a substitution.
 __device__ void ftrsm_sub_part(const double* __restrict__ l, const double* __restrict__ dinv, int b,
-                           double* __restrict__ y, int64_t ldy, int q0, int nq, double* __restrict__ lds) {
+                           double* __restrict__ y, int64_t ldy, int q0, int nq, double* __restrict__ lds, int na) {
   const int tid = threadIdx.x;
   LDSAS double* ys = lp(lds);            // [8][b] right-hand sides
   LDSAS double* Lb = lp(lds) + 8 * 512;  // two 32x32 block inverses
@@ -1021,7 +1046,7 @@ __device__ void ftrsm_sub_part(const double* __restrict__ l, const double* __res
   const int q = tid >> 5, r = tid & 31;
   for (int e = tid; e < 8 * b; e += NT) {
     const int qq = e / b, m = e % b;
-    ys[e] = qq < nq ? y[(size_t)(q0 + qq) * ldy + m] : 0.0;
+    ys[e] = qq < nq && m < na ? y[(size_t)(q0 + qq) * ldy + m] : 0.0;
   }
   for (int e = tid; e < 1024; e += NT) Lb[e] = dinv[e];
   double lv[2][32];
@@ -1029,7 +1054,7 @@ __device__ void ftrsm_sub_part(const double* __restrict__ l, const double* __res
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
       const int row = tid + NT * j;
-      if (row >= c0 + 32 && row < b) {
+      if (row >= c0 + 32 && row < na) {
 #pragma unroll
         for (int c = 0; c < 32; ++c) lv[j][c] = l[(size_t)(c0 + c) * b + row];
       }
@@ -1037,9 +1062,9 @@ __device__ void ftrsm_sub_part(const double* __restrict__ l, const double* __res
   };
   load_strip(0);
   int buf = 0;
-  for (int c0 = 0; c0 < b; c0 += 32) {
+  for (int c0 = 0; c0 < na; c0 += 32) {
     __syncthreads();  // block c0 of ys and the inverse in Lb[buf] are ready
-    if (c0 + 32 < b)
+    if (c0 + 32 < na)
       for (int e = tid; e < 1024; e += NT) Lb[(buf ^ 1) * 1024 + e] = dinv[(size_t)(c0 + 32) * 32 + e];
     const LDSAS double* Li = Lb + buf * 1024;
     if (q < nq) {
@@ -1052,7 +1077,7 @@ __device__ void ftrsm_sub_part(const double* __restrict__ l, const double* __res
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
       const int row = tid + NT * j;
-      if (row >= c0 + 32 && row < b) {
+      if (row >= c0 + 32 && row < na) {
         double acc[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) acc[u] = 0.0;
@@ -1063,21 +1088,22 @@ __device__ void ftrsm_sub_part(const double* __restrict__ l, const double* __res
         for (int u = 0; u < nq; ++u) ys[u * b + row] -= acc[u];
       }
     }
-    if (c0 + 32 < b) load_strip(c0 + 32);
+    if (c0 + 32 < na) load_strip(c0 + 32);
     buf ^= 1;
   }
   __syncthreads();
   for (int e = tid; e < nq * b; e += NT) {
     const int qq = e / b, m = e % b;
-    y[(size_t)(q0 + qq) * ldy + m] = ys[e];
+    if (m < na) y[(size_t)(q0 + qq) * ldy + m] = ys[e];
   }
 }
 
 // Backward: y_k <- L_kk^{-T} y_k, blocks from the last one down: x_blk = Li^T y_blk, then
 // the rows above lose L(blk, rows)^T x_blk.  Row t's strip L(c0 .. c0+31, t) is contiguous
-// (column t of the tile); otherwise as the forward substitution.
+// (column t of the tile); otherwise as the forward substitution (the padding blocks are
+// zero and contribute nothing, so starting at the block below na changes no bit).
 __device__ void btrsm_sub_part(const double* __restrict__ l, const double* __restrict__ dinv, int b,
-                           double* __restrict__ y, int64_t ldy, int q0, int nq, double* __restrict__ lds) {
+                           double* __restrict__ y, int64_t ldy, int q0, int nq, double* __restrict__ lds, int na) {
   const int tid = threadIdx.x;
   LDSAS double* ys = lp(lds);
   LDSAS double* Lb = lp(lds) + 8 * 512;
@@ -1085,9 +1111,9 @@ __device__ void btrsm_sub_part(const double* __restrict__ l, const double* __res
   const int q = tid >> 5, r = tid & 31;
   for (int e = tid; e < 8 * b; e += NT) {
     const int qq = e / b, m = e % b;
-    ys[e] = qq < nq ? y[(size_t)(q0 + qq) * ldy + m] : 0.0;
+    ys[e] = qq < nq && m < na ? y[(size_t)(q0 + qq) * ldy + m] : 0.0;
   }
-  for (int e = tid; e < 1024; e += NT) Lb[e] = dinv[(size_t)(b - 32) * 32 + e];
+  for (int e = tid; e < 1024; e += NT) Lb[e] = dinv[(size_t)(na - 32) * 32 + e];
   double lv[2][32];
   auto load_strip = [&](int c0) {
 #pragma unroll
@@ -1104,9 +1130,9 @@ __device__ void btrsm_sub_part(const double* __restrict__ l, const double* __res
       }
     }
   };
-  load_strip(b - 32);
+  load_strip(na - 32);
   int buf = 0;
-  for (int c0 = b - 32; c0 >= 0; c0 -= 32) {
+  for (int c0 = na - 32; c0 >= 0; c0 -= 32) {
     __syncthreads();
     if (c0 > 0)
       for (int e = tid; e < 1024; e += NT) Lb[(buf ^ 1) * 1024 + e] = dinv[(size_t)(c0 - 32) * 32 + e];
@@ -1138,7 +1164,7 @@ __device__ void btrsm_sub_part(const double* __restrict__ l, const double* __res
   __syncthreads();
   for (int e = tid; e < nq * b; e += NT) {
     const int qq = e / b, m = e % b;
-    y[(size_t)(q0 + qq) * ldy + m] = ys[e];
+    if (m < na) y[(size_t)(q0 + qq) * ldy + m] = ys[e];
   }
 }
 
@@ -1422,8 +1448,9 @@ __device__ __attribute__((noinline)) void run_part_chol(const SchedArgs& a, uint
     case SPX_T_POTRF: {
       // pad = step | (steps << 8) when the factorization is split into steps
       const int steps = d.pad >> 8;
-      const int bad = steps > 1 ? potrf_step_part(tile_ptr(m, d.k, d.k), b, dinv_ptr(m, d.k), d.pad & 0xff, (int)part, lds)
-                                : potrf_tile(tile_ptr(m, d.k, d.k), b, dinv_ptr(m, d.k), lds);
+      const int na = tile_active(m, d.k);
+      const int bad = steps > 1 ? potrf_step_part(tile_ptr(m, d.k, d.k), b, dinv_ptr(m, d.k), d.pad & 0xff, (int)part, lds, na)
+                                : potrf_tile(tile_ptr(m, d.k, d.k), b, dinv_ptr(m, d.k), lds, na);
       if (bad && threadIdx.x == 0)
         __hip_atomic_fetch_min(m.info, d.k * b + bad, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       break;
@@ -1434,7 +1461,18 @@ __device__ __attribute__((noinline)) void run_part_chol(const SchedArgs& a, uint
       void* low = m.prec == PREC_FP32   ? (void*)(reinterpret_cast<float*>(m.low) + off)
                   : m.prec == PREC_BF16 ? (void*)(reinterpret_cast<uint16_t*>(m.low) + off)
                                         : nullptr;
-      trsm_part(tile_ptr(m, d.i, d.k), tile_ptr(m, d.k, d.k), dinv_ptr(m, d.k), b, part * R, low, m.prec, lds);
+      const int r0 = (int)part * R;
+      if (r0 >= tile_active(m, d.i)) {  // a strip of zero padding rows: X stays zero
+        if (low) {  // its low-precision copy is read by the updates: clear it
+          for (int e = threadIdx.x; e < R * b; e += NT) {
+            const size_t at = (size_t)(e / R) * b + r0 + e % R;
+            if (m.prec == PREC_FP32) reinterpret_cast<float*>(low)[at] = 0.0f;
+            else reinterpret_cast<uint16_t*>(low)[at] = 0;
+          }
+        }
+        break;
+      }
+      trsm_part(tile_ptr(m, d.i, d.k), tile_ptr(m, d.k, d.k), dinv_ptr(m, d.k), b, r0, low, m.prec, lds);
       break;
     }
     case SPX_T_SYRK:
@@ -1452,6 +1490,8 @@ __device__ __attribute__((noinline)) void run_part_chol(const SchedArgs& a, uint
         I = part % ns;
         J = part / ns;
       }
+      // a sub-block of the last tile row's padding rows or columns: its entries stay
+      if (I * sb >= tile_active(m, d.i) || J * sb >= tile_active(m, d.j)) break;
       double* C = tile_ptr(m, d.i, d.j) + (size_t)J * sb * b + I * sb;
       const bool lower = d.type == SPX_T_SYRK && I == J;
       const size_t oi = ((size_t)d.i * (d.i + 1) / 2 + d.k) * (size_t)b * b;
@@ -1482,9 +1522,11 @@ __device__ __attribute__((noinline)) void run_part_chol(const SchedArgs& a, uint
       if (!d.pad) {  // in-place block substitution, one part per group of 8 right-hand sides
         const int q0 = part * 8, nq = (m.nrhs - q0) < 8 ? (m.nrhs - q0) : 8;
         if (d.type == SPX_T_FTRSM)
-          ftrsm_sub_part(tile_ptr(m, d.k, d.k), dinv_ptr(m, d.k), b, m.rhs + (size_t)d.k * b, m.n_pad, q0, nq, lds);
+          ftrsm_sub_part(tile_ptr(m, d.k, d.k), dinv_ptr(m, d.k), b, m.rhs + (size_t)d.k * b, m.n_pad, q0, nq, lds,
+                         tile_active(m, d.k));
         else
-          btrsm_sub_part(tile_ptr(m, d.k, d.k), dinv_ptr(m, d.k), b, m.rhs + (size_t)d.k * b, m.n_pad, q0, nq, lds);
+          btrsm_sub_part(tile_ptr(m, d.k, d.k), dinv_ptr(m, d.k), b, m.rhs + (size_t)d.k * b, m.n_pad, q0, nq, lds,
+                         tile_active(m, d.k));
         break;
       }
       // with M_k: part -> (group of 8 right-hand sides, strip of 64 rows)
