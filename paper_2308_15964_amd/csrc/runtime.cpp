@@ -368,11 +368,24 @@ static int build_image_host(const std::vector<Piece>& pieces, int policy, ImageH
   im.total_parts = (uint32_t)total;
   for (int l = 0; l < kLevels1; ++l) im.qcap[l] = (uint32_t)per_level[l];
   for (int l = 1; l < kLevels1; ++l) im.qbase[l] = im.qbase[l - 1] + im.qcap[l - 1];
-  // root parts are dealt round-robin over the shards of their level
+  // root parts are dealt round-robin over the shards of their level, the largest pieces
+  // first (task count times b^3, about their work): ranks are relative to each piece's own
+  // graph, so across independent matrices this queue order is what starts the longest
+  // ones first (and leaves the short ones for the end of the launch)
+  std::vector<uint32_t> porder(pieces.size()), pstart(pieces.size() + 1, 0);
+  for (size_t i = 0; i < pieces.size(); ++i) {
+    porder[i] = (uint32_t)i;
+    pstart[i + 1] = pstart[i] + pieces[i].p->g.ntasks;
+  }
+  std::stable_sort(porder.begin(), porder.end(), [&](uint32_t x, uint32_t y) {
+    const auto w = [&](uint32_t i) { return (double)pieces[i].p->g.ntasks * pieces[i].b * pieces[i].b * pieces[i].b; };
+    return w(x) > w(y);
+  });
   std::vector<u64> roots;
   std::vector<uint32_t> counters0(kNumCounters, 0);
   uint32_t deal = 0;
-  for (uint32_t t = 0; t < T; ++t) {
+  for (uint32_t pi : porder)
+  for (uint32_t t = pstart[pi]; t < pstart[pi + 1]; ++t) {
     if (indeg[t] != 0) continue;
     if (comm && coff[t + 1] > coff[t]) {  // takes its locks at the start of the launch
       croots.push_back(t);

@@ -1398,6 +1398,64 @@ __device__ void pack_block_s(const double* __restrict__ A, int64_t lda, int64_t 
   __syncthreads();
 }
 
+// A whole tile (ti, tj) by one workgroup, as pack_block_s<64> does each 64x64 block, with
+// the next block's loads issued before the current one goes through LDS, so about two
+// blocks of reads are in flight instead of one.
+__device__ __noinline__ void pack_tile64(const double* __restrict__ A, int64_t lda, int64_t n, const DevMat& m,
+                                         int ti, int tj, double* __restrict__ s) {
+  constexpr int S = 64, PER = S * S / NT;
+  const int b = m.b, per = b / S, nblk = per * per;
+  LDSAS double* sl = lp(s);
+  const GLOBAL double* Ag = gp(A);
+  GLOBAL double* T = gp(tile_ptr(m, ti, tj));
+  double cur[PER], nxt[PER];
+  auto load = [&](int q, double (&v)[PER]) {
+    const int64_t R0 = (int64_t)ti * b + (q / per) * S, C0 = (int64_t)tj * b + (q % per) * S;
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int e = threadIdx.x + i * NT, rr = e / S, cc = e % S;  // cc fastest: row-major reads
+      const int64_t R = R0 + rr, C = C0 + cc;
+      v[i] = (R < n && C < n) ? (R >= C ? Ag[R * lda + C] : 0.0) : (R == C ? 1.0 : 0.0);
+    }
+  };
+  load(0, cur);
+  for (int q = 0; q < nblk; ++q) {
+    if (q + 1 < nblk) load(q + 1, nxt);
+    const int si = q / per, sj = q % per;
+    if (m.dscale) {
+      const int64_t R0 = (int64_t)ti * b + si * S, C0 = (int64_t)tj * b + sj * S;
+#pragma unroll
+      for (int i = 0; i < PER; ++i) {
+        const int e = threadIdx.x + i * NT, rr = e / S, cc = e % S;
+        const int64_t R = R0 + rr, C = C0 + cc;
+        if (R < n && C < n) {
+          cur[i] = cur[i] * m.dscale[R] * m.dscale[C];
+          if (R == C) cur[i] += m.shift;
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int e = threadIdx.x + i * NT;
+      sl[(e / S) * 65 + e % S] = cur[i];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int e = threadIdx.x + i * NT, cc = e / S, rr = e % S;  // rr fastest: column-major writes
+      cur[i] = sl[rr * 65 + cc];
+    }
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int e = threadIdx.x + i * NT, cc = e / S, rr = e % S;
+      T[(size_t)(sj * S + cc) * b + si * S + rr] = cur[i];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < PER; ++i) cur[i] = nxt[i];
+  }
+}
+
 __device__ void pack_block(const double* __restrict__ A, int64_t lda, int64_t n, const DevMat& m, int ti, int tj,
                            int si, int sj, int S, double* __restrict__ s) {
   if (S == 64) {
@@ -1580,8 +1638,11 @@ __device__ __attribute__((noinline)) void run_part_chol(const SchedArgs& a, uint
           while ((ti + 1) * (ti + 2) / 2 <= (int)part) ++ti;
           tj0 = tj1 = (int)part - ti * (ti + 1) / 2;
         }
-        for (int tj = tj0; tj <= tj1; ++tj)
-          for (int q = 0; q < per * per; ++q) pack_block(m.A, m.lda, m.n, m, ti, tj, q / per, q % per, S, lds);
+        for (int tj = tj0; tj <= tj1; ++tj) {
+          if (S == 64) pack_tile64(m.A, m.lda, m.n, m, ti, tj, lds);
+          else
+            for (int q = 0; q < per * per; ++q) pack_block(m.A, m.lda, m.n, m, ti, tj, q / per, q % per, S, lds);
+        }
       } else {
         const int64_t total = m.n_pad * m.nrhs;
         for (int64_t e = threadIdx.x; e < total; e += NT) {
