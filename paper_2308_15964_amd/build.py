@@ -11,7 +11,12 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["graph.cpp", "runtime.cpp", "server.cpp", "spx_kernels.hip"]
 # -packed-fp32-ops: keep the compiler from emitting packed FP32 VALU instructions.
-DEVICE_FLAGS = ["--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+# -amdgpu-mfma-vgpr-form: matrix-core accumulators in ordinary VGPRs.  Without it the FP64
+# tile product keeps its accumulators in AGPRs inside the K loop but in VGPRs across the
+# loop's back edge, copying all 128 of them twice per 32-deep chunk, and the out-of-line
+# task bodies save more callee-saved registers to scratch.
+DEVICE_FLAGS = ["--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+                "-mllvm", "-amdgpu-mfma-vgpr-form"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 
 

@@ -180,17 +180,27 @@ __device__ __forceinline__ void gemm_nt_f64(double* __restrict__ C, int ldc, con
     }
     const LDSAS double* As = lp(lds) + buf * BUF;
     const LDSAS double* Bs = As + KC * SB;
+    // fragments double-buffered in registers: those of the next 4-deep step are read
+    // from LDS before this step's products are issued, so their latency is covered
+    double a[2][NB], b[2][NB];
+#pragma unroll
+    for (int i = 0; i < NB; ++i) a[0][i] = As[kl * SB + arow + i * 16];
+#pragma unroll
+    for (int j = 0; j < NB; ++j) b[0][j] = Bs[kl * SB + bcol + j * 16];
 #pragma unroll
     for (int kk = 0; kk < KC; kk += 4) {
-      double a[NB], b[NB];
+      const int cb = (kk >> 2) & 1;
+      if (kk + 4 < KC) {
 #pragma unroll
-      for (int i = 0; i < NB; ++i) a[i] = As[(kk + kl) * SB + arow + i * 16];
+        for (int i = 0; i < NB; ++i) a[cb ^ 1][i] = As[(kk + 4 + kl) * SB + arow + i * 16];
 #pragma unroll
-      for (int j = 0; j < NB; ++j) b[j] = Bs[(kk + kl) * SB + bcol + j * 16];
+        for (int j = 0; j < NB; ++j) b[cb ^ 1][j] = Bs[(kk + 4 + kl) * SB + bcol + j * 16];
+      }
 #pragma unroll
       for (int i = 0; i < NB; ++i)
 #pragma unroll
-        for (int j = 0; j < NB; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(b[j], a[i], acc[i][j], 0, 0, 0);
+        for (int j = 0; j < NB; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(b[cb][j], a[cb][i], acc[i][j], 0, 0, 0);
     }
     __syncthreads();  // buffer buf ^ 1 is written; buffer buf may be overwritten next
   }
