@@ -153,9 +153,12 @@ int spx_gemm_graph(int32_t nt, spx_graph** out, int32_t* task_types, uint32_t ca
  *   queue_policy: the ready queues.  Tasks carry upward-rank priorities (the longest
  *     chain of work from the task to the end of the graph): the panel chain first, then
  *     the updates by how soon their tile is consumed.  SPX_Q_SHARDED (the default, 0):
- *     four priority levels, each split into 8 queues, one per XCD; a task is pushed into
- *     the queue of the XCD that released its last predecessor, and a workgroup serves its
- *     own XCD's queue first, so pops spread over 8 queue heads.  SPX_Q_PRIORITY: sixteen
+ *     sixteen priority levels, each split into 4 queues (shards), one per pair of XCDs; a
+ *     task is pushed into the shard of the XCD that released its last predecessor, and a
+ *     workgroup serves the highest non-empty level, its own shard first, so pops spread
+ *     over 4 queue heads per level (environment SPX_QUEUE_SHARDS = 2, 4 or 8 trades
+ *     shards for levels: 32, 16 or 8 levels; batched launches always use 8 x 8).
+ *     SPX_Q_PRIORITY: sixteen
  *     levels, one queue each (exact push order within a level; every pop contends for one
  *     queue head, which limits pops to about one per microsecond).  SPX_Q_FIFO: one queue
  *     in push order.  Results are bitwise identical under every policy.

@@ -14,6 +14,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <cstdlib>
 #include <map>
 #include <mutex>
 
@@ -56,8 +57,8 @@ struct Image {
   uint32_t ntasks = 0, total_parts = 0;
   int nlev = 1;
   int family = FAM_CHOL;  // the scheduler instantiation that runs its tasks
-  uint32_t qbase[kLevels1] = {};
-  uint32_t qcap[kLevels1] = {};
+  uint32_t qbase[kLevelsMax] = {};
+  uint32_t qcap[kLevelsMax] = {};
   uint32_t nroots = 0;
   int nshards = 1;
   void* block = nullptr;  // one allocation for every array below
@@ -275,8 +276,8 @@ struct Piece {
 struct ImageHost {
   uint32_t ntasks = 0, total_parts = 0;
   int nlev = 1;
-  uint32_t qbase[kLevels1] = {};
-  uint32_t qcap[kLevels1] = {};
+  uint32_t qbase[kLevelsMax] = {};
+  uint32_t qcap[kLevelsMax] = {};
   uint32_t nroots = 0;
   int nshards = 1;
   std::vector<char> bytes;       // the static part (static_bytes)
@@ -287,12 +288,29 @@ struct ImageHost {
   size_t o_coff = 0, o_cent = 0, o_goff = 0, o_gtask = 0, o_gidx = 0, o_croots = 0, o_gstate = 0;
 };
 
+// Ready-queue shards of the sharded policy for one graph (environment SPX_QUEUE_SHARDS =
+// 2, 4 or 8; default 4): the 64 queue words are split into shards x levels (at most kLevelsMax
+// levels).  Four shards of sixteen levels measured best on the N = 16384 factor (43.5 ms;
+// 8 x 8: 44.8 ms, where a panel task queues behind updates of up to four steps earlier in
+// its level; 2 x 32: 45.2 ms, pops contend).
+static int queue_shards() {
+  static const int s = [] {
+    const char* e = std::getenv("SPX_QUEUE_SHARDS");
+    const int v = e ? std::atoi(e) : 4;
+    return (v == 2 || v == 4 || v == 8) ? v : 4;
+  }();
+  return s;
+}
+
 // Lays out the concatenation of the pieces' graphs (no edges between pieces) as one image.
 static int build_image_host(const std::vector<Piece>& pieces, int policy, ImageHost& im) {
   // one ready queue per level keeps one matrix's tasks in global push order (its critical
   // path runs through the oldest bulk updates); independent matrices need no such order,
   // and sharded queues spread the pops of their many small tasks
-  const int nshards = (pieces.size() > 1 || policy == SPX_Q_SHARDED) ? kShards : 1;
+  // batched images keep 8 shards of 8 levels: their ranks are relative to each matrix, and
+  // finer levels put every matrix's first tasks ahead of the later tasks of the matrices
+  // already running (4096 two-tile matrices: 20.3 ms with 8 levels, 30.8 ms with 16)
+  const int nshards = pieces.size() > 1 ? kShards : (policy == SPX_Q_SHARDED ? queue_shards() : 1);
   uint64_t T64 = 0, E64 = 0;
   for (const Piece& pc : pieces) {
     T64 += pc.p->g.ntasks;
@@ -305,7 +323,7 @@ static int build_image_host(const std::vector<Piece>& pieces, int policy, ImageH
   im.nlev = policy == SPX_Q_FIFO ? 1 : (nshards > 1 ? kMaxQueues / nshards : kLevels1);
   std::vector<TaskDesc> tasks(T);
   std::vector<uint32_t> off32(T + 1), succ(std::max<size_t>(E, 1)), indeg(T), nparts(T);
-  uint64_t per_level[kLevels1] = {};
+  uint64_t per_level[kLevelsMax] = {};
   uint32_t t0 = 0;
   size_t e0 = 0;
   // commutative groups of all pieces, renumbered
@@ -363,11 +381,11 @@ static int build_image_host(const std::vector<Piece>& pieces, int policy, ImageH
   }
   off32[T] = (uint32_t)E;
   uint64_t total = 0;
-  for (int l = 0; l < kLevels1; ++l) total += per_level[l];
+  for (int l = 0; l < kLevelsMax; ++l) total += per_level[l];
   if (total * kShards >= (1ull << 32) - 1) return fail(SPX_EINVAL, "task graph too large");
   im.total_parts = (uint32_t)total;
-  for (int l = 0; l < kLevels1; ++l) im.qcap[l] = (uint32_t)per_level[l];
-  for (int l = 1; l < kLevels1; ++l) im.qbase[l] = im.qbase[l - 1] + im.qcap[l - 1];
+  for (int l = 0; l < kLevelsMax; ++l) im.qcap[l] = (uint32_t)per_level[l];
+  for (int l = 1; l < kLevelsMax; ++l) im.qbase[l] = im.qbase[l - 1] + im.qcap[l - 1];
   // root parts are dealt round-robin over the shards of their level, the largest pieces
   // first (task count times b^3, about their work): ranks are relative to each piece's own
   // graph, so across independent matrices this queue order is what starts the longest
@@ -461,7 +479,7 @@ static void bind_image(const ImageHost& h, char* base, Image* im) {
   im->ntasks = h.ntasks;
   im->total_parts = h.total_parts;
   im->nlev = h.nlev;
-  for (int l = 0; l < kLevels1; ++l) {
+  for (int l = 0; l < kLevelsMax; ++l) {
     im->qbase[l] = h.qbase[l];
     im->qcap[l] = h.qcap[l];
   }
@@ -606,7 +624,7 @@ static int run_image(spx_ctx* c, Image* im, int nmats, const spx_opts* o, double
   a.gstate = im->gstate;
   a.croots = im->croots;
   a.ncroots = im->ncroots;
-  for (int l = 0; l < kLevels1; ++l) {
+  for (int l = 0; l < kLevelsMax; ++l) {
     a.qbase[l] = im->qbase[l];
     a.qcap[l] = im->qcap[l];
   }
@@ -1874,7 +1892,7 @@ int spx_potrs_noalloc(spx_ctx* c, const spx_factor* f, int64_t nrhs, const doubl
     a.gstate = im.gstate;
     a.croots = im.croots;
     a.ncroots = im.ncroots;
-    for (int l = 0; l < kLevels1; ++l) {
+    for (int l = 0; l < kLevelsMax; ++l) {
       a.qbase[l] = im.qbase[l];
       a.qcap[l] = im.qcap[l];
     }

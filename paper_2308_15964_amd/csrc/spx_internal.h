@@ -108,6 +108,7 @@ constexpr int kLoadTileParts = 65534;
 constexpr int kMaxQueues = 64;      // ready queues per image: levels x shards (one per lane of a wave)
 constexpr int kMaxLevels = 64;      // priority classes (priority >> 16)
 constexpr int kLevels1 = 16;        // queue levels with one shard
+constexpr int kLevelsMax = 32;      // most levels any policy uses (2 shards x 32 levels)
 constexpr int kShards = 8;          // ready queues per priority level (one per XCD-sized group of workgroups)
 constexpr int kCounterStride = 32;  // 128-byte spacing of hot counters (uint32 units)
 // Counter layout: one 64-bit word per queue q = level x shards + shard (head in the low
@@ -146,8 +147,8 @@ struct SchedArgs {
   unsigned long long* gstate;  // per group: lock bit 63, waiting members' bits 0..62
   const uint32_t* croots;      // root tasks with commutative accesses (take their locks at the start)
   uint32_t ncroots;
-  uint32_t qbase[kLevels1];
-  uint32_t qcap[kLevels1];
+  uint32_t qbase[kLevelsMax];
+  uint32_t qcap[kLevelsMax];
   uint32_t total_parts;
   uint32_t ntasks;
   int32_t nlev;     // levels in use (nlev x nshards <= kMaxQueues)
