@@ -157,7 +157,10 @@ int spx_gemm_graph(int32_t nt, spx_graph** out, int32_t* task_types, uint32_t ca
  *     task is pushed into the shard of the XCD that released its last predecessor, and a
  *     workgroup serves the highest non-empty level, its own shard first, so pops spread
  *     over 4 queue heads per level (environment SPX_QUEUE_SHARDS = 2, 4 or 8 trades
- *     shards for levels: 32, 16 or 8 levels; batched launches always use 8 x 8).
+ *     shards for levels: 32, 16 or 8 levels).  This split, and pops that claim up to 4
+ *     parts from a long queue, apply to one graph whose tasks average at least two parts;
+ *     batched launches and graphs of single-part tasks use 8 shards of 8 levels and
+ *     single claims.
  *     SPX_Q_PRIORITY: sixteen
  *     levels, one queue each (exact push order within a level; every pop contends for one
  *     queue head, which limits pops to about one per microsecond).  SPX_Q_FIFO: one queue

@@ -302,20 +302,36 @@ static int queue_shards() {
   return s;
 }
 
+// Parts a pop may claim at once outside the bulk levels: several where tasks average at
+// least two parts (the factor, the solve, the tiled product), where long queues of parts
+// otherwise leave workgroups idle behind the compare-and-swaps on one head; one where
+// tasks are single parts (chains of small tasks, one-tile batches), where a claim of
+// several tasks would run them one after the other while other workgroups wait.
+static uint32_t claim_limit(uint32_t total_parts, uint32_t ntasks) {
+  return (uint64_t)total_parts >= 2ull * ntasks ? 4u : 1u;
+}
+
 // Lays out the concatenation of the pieces' graphs (no edges between pieces) as one image.
 static int build_image_host(const std::vector<Piece>& pieces, int policy, ImageHost& im) {
   // one ready queue per level keeps one matrix's tasks in global push order (its critical
   // path runs through the oldest bulk updates); independent matrices need no such order,
   // and sharded queues spread the pops of their many small tasks
-  // batched images keep 8 shards of 8 levels: their ranks are relative to each matrix, and
-  // finer levels put every matrix's first tasks ahead of the later tasks of the matrices
-  // already running (4096 two-tile matrices: 20.3 ms with 8 levels, 30.8 ms with 16)
-  const int nshards = pieces.size() > 1 ? kShards : (policy == SPX_Q_SHARDED ? queue_shards() : 1);
-  uint64_t T64 = 0, E64 = 0;
+  uint64_t T64 = 0, E64 = 0, P64 = 0;
   for (const Piece& pc : pieces) {
     T64 += pc.p->g.ntasks;
     E64 += pc.p->g.succ.size();
+    for (const TaskDesc& d : pc.p->tasks) P64 += parts_of(d, pc.b, pc.nrhs);
   }
+  // the finer levels of queue_shards() pay where priorities decide the makespan and
+  // multi-part claims keep the pops ahead: one graph of multi-part tasks.  Batched images
+  // keep 8 shards of 8 levels (their ranks are relative to each matrix, and finer levels
+  // put every matrix's first tasks ahead of the later tasks of the matrices already
+  // running: 4096 two-tile matrices 20.3 ms with 8 levels, 30.8 ms with 16), and so do
+  // graphs of single-part tasks, whose pops need the spread (256 chains of 10 us tasks:
+  // 17 us overhead per task with 8 shards, 58 us with 4)
+  const bool fine = pieces.size() == 1 && claim_limit((uint32_t)std::min<uint64_t>(P64, UINT32_MAX),
+                                                      (uint32_t)std::min<uint64_t>(T64, UINT32_MAX)) > 1;
+  const int nshards = policy != SPX_Q_SHARDED && pieces.size() == 1 ? 1 : (fine ? queue_shards() : kShards);
   if (T64 >= (1ull << 32) - 1 || E64 >= (1ull << 32) - 1) return fail(SPX_EINVAL, "task graph too large");
   const uint32_t T = (uint32_t)T64;
   const size_t E = (size_t)E64;
@@ -630,6 +646,7 @@ static int run_image(spx_ctx* c, Image* im, int nmats, const spx_opts* o, double
   }
   a.total_parts = im->total_parts;
   a.ntasks = im->ntasks;
+  a.max_claim = claim_limit(im->total_parts, im->ntasks);
   a.nlev = im->nlev;
   a.nshards = im->nshards;
   a.mats = c->dmats;
@@ -1898,6 +1915,7 @@ int spx_potrs_noalloc(spx_ctx* c, const spx_factor* f, int64_t nrhs, const doubl
     }
     a.total_parts = im.total_parts;
     a.ntasks = im.ntasks;
+    a.max_claim = claim_limit(im.total_parts, im.ntasks);
     a.nlev = im.nlev;
     a.nshards = im.nshards;
     a.mats = (const DevMat*)(base + o_mat);

@@ -1780,10 +1780,13 @@ __device__ __forceinline__ void push_task(const SchedArgs& a, uint32_t s, int ho
 // pop, run by all 64 lanes of wave 0: lane i reads the head and tail of queue (level
 // i / S, shard (home + i) % S) for the S shards in use, all in one round trip; the lowest
 // lane with a non-empty queue (highest priority level, own shard first) claims slots with
-// a compare-and-swap, retried in place with the head it returns.  From the bulk levels
-// (the lowest quarter) it claims several parts at once while the queue is long (fewer
-// operations on the shared head, whose compare-and-swaps serialise, and fewer release
-// fences); from the others one.
+// a compare-and-swap, retried in place with the head it returns.  It claims several parts
+// at once while the queue is long (2 from 32 waiting, 4 from 128 on any level where the
+// launch allows it, a.max_claim; from 64, 128 and 192 on the bulk levels, the lowest
+// quarter): the compare-and-swaps on one shared
+// head serialise at about one per microsecond, which with single claims left a tenth to
+// a half of the workgroups idle while thousands of parts waited (N = 16384 factor: 43.5
+// -> 40.1 ms), and each claim costs one release fence.
 // Writes up to kClaim items to items[] (lane 0's copy) and returns their number (the same
 // in every lane); *saw tells whether some queue looked non-empty and *taken is the number
 // of parts taken from all queues so far (never more than the true count).
@@ -1812,7 +1815,8 @@ __device__ __forceinline__ int pop_wave(const SchedArgs& a, int home, bool* saw,
     for (;; h = (uint32_t)ht, t = (uint32_t)(ht >> 32)) {
       if (h >= t) break;
       const uint32_t avail = t - h;
-      const uint32_t want = bulk ? (avail >= 192u ? 4u : avail >= 128u ? 3u : avail >= 64u ? 2u : 1u) : 1u;
+      const uint32_t want = bulk ? (avail >= 192u ? 4u : avail >= 128u ? 3u : avail >= 64u ? 2u : 1u)
+                                 : (a.max_claim < 2u ? 1u : avail >= 128u ? 4u : avail >= 32u ? 2u : 1u);
       // a push between the load and the swap changes the tail half and fails the swap:
       // retry with the word it returns
       if (__hip_atomic_compare_exchange_strong(ctr_queue(a, l, sh), &ht, ht + want, __ATOMIC_RELAXED,
