@@ -31,27 +31,31 @@ PEAK_FP64_TFLOPS = 78.6  # MI355X dense FP64 matrix peak
 
 # HBM traffic of one factor launch at N=16384, tile 512, from two rocprofv3 PMC runs
 # (FETCH_SIZE, WRITE_SIZE in KiB) scaled by the counts of a 1 GiB device copy (FETCH x 2,
-# WRITE x 1).  Valid only for the library sources it was measured on (the kernels, and the
-# graph and scheduler code that decide what the launch runs; sha256 over them below); for
-# any other sources the benchmark reports null.
+# WRITE x 1).  Valid only for the library sources it was measured on (the kernels, the
+# graph and scheduler code that decide what the launch runs, and the compiler flags of the
+# build script; sha256 over them below); for any other sources the benchmark reports null.
 TRAFFIC_RECORD = {
-    "sources_sha256": "370f3f8e5ae68520f81bc01d79b880be6a327a8f2a6ea363ac2cbf2475d32945",
+    "sources_sha256": "2de11b31ea0e44d8814ae0cf1da8ed7c814b371ea90c9f5634b96d49dbc63290",
     "n": 16384, "tile": 512,
-    "fetch_kib": 26937004.0, "write_kib": 14020576.0, "fetch_scale": 2.0, "write_scale": 1.0,
+    "fetch_kib": 32938323.625, "write_kib": 12754673.125, "fetch_scale": 2.0, "write_scale": 1.0,
 }
 
 
 def sources_digest():
-    """sha256 over the library's native sources (csrc/, sorted by name), or None."""
+    """sha256 over the library's native sources (csrc/, sorted by name) and its build script
+    (the compiler flags), or None."""
     import hashlib
 
-    src = os.path.join(ROOT, "paper_2308_15964_amd", "csrc")
+    pkg = os.path.join(ROOT, "paper_2308_15964_amd")
+    src = os.path.join(pkg, "csrc")
     h = hashlib.sha256()
     try:
         for name in sorted(os.listdir(src)):
             if name.endswith((".hip", ".cpp", ".h")):
                 with open(os.path.join(src, name), "rb") as f:
                     h.update(name.encode() + b"\0" + f.read())
+        with open(os.path.join(pkg, "build.py"), "rb") as f:
+            h.update(b"build.py\0" + f.read())
     except OSError:
         return None
     return h.hexdigest()
