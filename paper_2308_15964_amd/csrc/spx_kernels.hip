@@ -1531,11 +1531,13 @@ __device__ __attribute__((noinline)) void run_part_chol(const SchedArgs& a, uint
                                         : nullptr;
       const int r0 = (int)part * R;
       if (r0 >= tile_active(m, d.i)) {  // a strip of zero padding rows: X stays zero
-        if (low) {  // its low-precision copy is read by the updates: clear it
+        if (low) {  // its low-precision copy is read by the updates: clear it (the FP32
+                    // copy is column-major, the BF16 copy row-major, as the TRSM writes them)
           for (int e = threadIdx.x; e < R * b; e += NT) {
-            const size_t at = (size_t)(e / R) * b + r0 + e % R;
-            if (m.prec == PREC_FP32) reinterpret_cast<float*>(low)[at] = 0.0f;
-            else reinterpret_cast<uint16_t*>(low)[at] = 0;
+            if (m.prec == PREC_FP32)
+              reinterpret_cast<float*>(low)[(size_t)(e / R) * b + r0 + e % R] = 0.0f;
+            else
+              reinterpret_cast<uint16_t*>(low)[(size_t)(r0 + e / b) * b + e % b] = 0;
           }
         }
         break;

@@ -88,6 +88,36 @@ def test_bf16_updates_refined_to_1e12(ctx):
     F.close()
 
 
+@pytest.mark.parametrize("prec", [1, 2])
+def test_ragged_last_tile_mixed_refined(ctx, prec):
+    """N = 1100 with 256-wide tiles: the last tile row holds 76 rows (96 live after rounding
+    to 32), so the step-split POTRF of the last diagonal tile has identity steps, the TRSM
+    strips and update sub-blocks of the padding are skipped, and the skipped strips' low-
+    precision copies are cleared.  A larger factor made first leaves stale values in the
+    reused device memory.  The refined solution must reach eta <= 1e-12 (oracle)."""
+    from paper_2308_15964_amd import spx
+
+    big, _ = inputs.gram_spd(1280, seed=90 + prec)
+    F = ctx.potrf(dev(big), tile=256, update_prec=prec)
+    F.close()
+    n, b, nrhs = 1100, 256, 2
+    print(f"ragged mixed prec={prec} n={n} tile={b}", flush=True)
+    A, B = inputs.gram_spd(n, seed=91 + prec, nrhs=nrhs)
+    _, Xo, info = oracle.cholesky(A, 100, B)  # the oracle's tile divides n
+    assert info == 0
+    Ad, Bd = dev(A), dev(B)
+    F = ctx.potrf(Ad, tile=b, update_prec=prec)
+    L = F.L().cpu().numpy()
+    assert np.isfinite(L).all()
+    assert oracle.factor_residual(A, L) <= (1e-5 if prec == spx.PREC_FP32 else 5e-2)
+    X, st = ctx.potrs(F, Bd, A=Ad, tol=1e-12, max_iter=50, method=1, return_stats=True)
+    X = X.cpu().numpy()
+    eta = oracle.backward_error(A, X, B)
+    assert eta.max() <= 1e-12, (eta, st)
+    assert np.abs(X - Xo).max() / np.abs(Xo).max() <= 1e-11
+    F.close()
+
+
 @pytest.mark.parametrize("prec", [0, 1, 2])
 def test_mixed_schedules_bitwise_identical(ctx, prec):
     from paper_2308_15964_amd import spx
