@@ -2329,72 +2329,186 @@ __global__ void axpy_cols_kernel(int64_t total, int64_t q, const double* __restr
 // stats: per column q: [3q] max|r|, [3q+1] max|x|, [3q+2] max|b| (as non-negative
 // doubles compared through their bit patterns); the last slot holds ||A||_inf.
 // ---------------------------------------------------------------------------------------
+// Right-hand sides per pass of the residual kernels over A (each pass reads the matrix).
+constexpr int kResQ = 16;
+
 __device__ __forceinline__ void atomic_max_nonneg(double* p, double v) {
   atomicMax(reinterpret_cast<unsigned long long*>(p), (unsigned long long)__double_as_longlong(v));
 }
 
-__device__ void residual_rows(int64_t n, const double* __restrict__ A, int64_t lda, int64_t nrhs,
+__device__ __forceinline__ void residual_rows(int64_t n, const double* __restrict__ A, int64_t lda, int64_t nrhs,
                               const double* __restrict__ X, int64_t ldx, const double* __restrict__ Bv, int64_t ldb,
                               double* __restrict__ R, double* __restrict__ stats, int64_t i0,
-                              double (*part)[64][9]) {
+                              double (*part)[64][kResQ + 1]) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int64_t q0 = 0; q0 < nrhs; q0 += 8) {
-    const int nq = (nrhs - q0) < 8 ? (int)(nrhs - q0) : 8;
-    double acc[9];  // 8 right-hand sides + the absolute row sum
+  constexpr int Q = kResQ;  // right-hand sides per pass over A
+  for (int64_t q0 = 0; q0 < nrhs; q0 += Q) {
+    const int nq = (nrhs - q0) < Q ? (int)(nrhs - q0) : Q;
+    double acc[Q + 1];  // Q right-hand sides + the absolute row sum
 #pragma unroll
-    for (int q = 0; q < 9; ++q) acc[q] = 0.0;
+    for (int q = 0; q <= Q; ++q) acc[q] = 0.0;
     const int64_t i = i0 + lane;
-    // part 1: columns j < i0, read along rows; wave w takes rows i0 + w, i0 + w + 4, ...
-    // (lane-strided over j, reduced across the wave)
-    for (int rr = wave; rr < 64; rr += 4) {
-      const int64_t ii = i0 + rr;
-      if (ii >= n) break;
-      double s[9];
+    // part 1: columns j < i0, read along rows.  Wave w takes rows i0 + w + 4 t (t < 16),
+    // four at a time; the rows of X for 256 columns at a time are staged in LDS (in the
+    // buffer of the closing reduction, which has the same size) and shared by the waves,
+    // so X is read once per four rows instead of once per row and never gathered from
+    // global memory.  Lane l sums the columns j = l mod 64 in increasing order, and the
+    // lanes are reduced with the same butterfly, as a row-by-row loop would.
+    {
+      constexpr int CH = 256, XS = Q + 1, RG = 2;
+      static_assert(CH * XS <= 4 * 64 * (Q + 1), "a chunk of X fits the reduction buffer");
+      LDSAS double* xs = lp(&part[0][0][0]);
+      for (int g = 0; g < 16 / RG; ++g) {
+        double sp[RG][Q + 1];
 #pragma unroll
-      for (int q = 0; q < 9; ++q) s[q] = 0.0;
-      for (int64_t j = lane; j < i0; j += 64) {
-        const double aij = A[ii * lda + j];
+        for (int t = 0; t < RG; ++t)
 #pragma unroll
-        for (int q = 0; q < 8; ++q)
-          if (q < nq) s[q] += aij * X[j * ldx + q0 + q];
-        s[8] += fabs(aij);
+          for (int q = 0; q <= Q; ++q) sp[t][q] = 0.0;
+        for (int64_t j0 = 0; j0 < i0; j0 += CH) {
+          __syncthreads();  // the previous chunk (or the buffer's earlier use) is done with
+          {
+            const int t = threadIdx.x;
+            const int64_t j = j0 + t;
+            if (j < i0) {
+#pragma unroll
+              for (int q = 0; q < Q; ++q) xs[t * XS + q] = q < nq ? X[j * ldx + q0 + q] : 0.0;
+            }
+          }
+          __syncthreads();
+          double a[CH / 64][RG];  // every load of the chunk issued before the first use
+#pragma unroll
+          for (int k = 0; k < CH / 64; ++k)
+#pragma unroll
+            for (int t = 0; t < RG; ++t) {
+              const int64_t ii = i0 + wave + 4 * (RG * g + t), j = j0 + lane + 64 * k;
+              a[k][t] = (ii < n && j < i0) ? A[ii * lda + j] : 0.0;
+            }
+#pragma unroll
+          for (int k = 0; k < CH / 64; ++k) {
+            const int c = lane + 64 * k;
+            if (j0 + c < i0) {
+              double xv[Q];
+#pragma unroll
+              for (int q = 0; q < Q; ++q) xv[q] = xs[c * XS + q];
+#pragma unroll
+              for (int t = 0; t < RG; ++t) {
+                const int64_t ii = i0 + wave + 4 * (RG * g + t);
+                if (ii < n) {
+                  const double aij = a[k][t];
+#pragma unroll
+                  for (int q = 0; q < Q; ++q)
+                    if (q < nq) sp[t][q] += aij * xv[q];
+                  sp[t][Q] += fabs(aij);
+                }
+              }
+            }
+          }
+        }
+#pragma unroll
+        for (int t = 0; t < RG; ++t) {
+          const int rr = wave + 4 * (RG * g + t);
+          if (i0 + rr >= n) continue;
+#pragma unroll
+          for (int q = 0; q <= Q; ++q)
+#pragma unroll
+            for (int off = 32; off >= 1; off >>= 1) sp[t][q] += __shfl_xor(sp[t][q], off);
+          if (lane == rr) {
+#pragma unroll
+            for (int q = 0; q <= Q; ++q) acc[q] += sp[t][q];
+          }
+        }
       }
-#pragma unroll
-      for (int q = 0; q < 9; ++q)
-#pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) s[q] += __shfl_xor(s[q], off);
-      if (lane == rr) {
-#pragma unroll
-        for (int q = 0; q < 9; ++q) acc[q] += s[q];
-      }
-      // lane rr of this wave now holds row ii's partial for part 1; move it to the lane
-      // that owns row ii (lane rr) -- same lane index, so nothing to move
+      __syncthreads();  // the reduction buffer is free again
     }
     // part 2: columns j >= i0; lane owns row i, wave w takes j = i0 + w, i0 + w + 4, ...
-    if (i < n) {
-      for (int64_t j = i0 + wave; j < n; j += 4) {
-        const double aij = (j >= i) ? A[j * lda + i] : A[i * lda + j];
+    // in increasing order.  X again comes through LDS 256 rows at a time (read by a wave
+    // at one address per row: a broadcast), and the loads of A (row j's 64 entries of the
+    // block, contiguous) are issued eight rows at a time, so a wave has eight in flight
+    // instead of waiting for each.
+    {
+      constexpr int CH = 256, XS = Q + 1, U = 8;
+      LDSAS double* xs = lp(&part[0][0][0]);
+      for (int64_t j0 = i0; j0 < n; j0 += CH) {
+        __syncthreads();
+        {
+          const int t = threadIdx.x;
+          const int64_t j = j0 + t;
+          if (j < n) {
 #pragma unroll
-        for (int q = 0; q < 8; ++q)
-          if (q < nq) acc[q] += aij * X[j * ldx + q0 + q];
-        acc[8] += fabs(aij);
+            for (int q = 0; q < Q; ++q) xs[t * XS + q] = q < nq ? X[j * ldx + q0 + q] : 0.0;
+          }
+        }
+        __syncthreads();
+        if (i < n) {
+          for (int k0 = wave; k0 < CH; k0 += 4 * U) {
+            double a[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+              const int64_t j = j0 + k0 + 4 * u;
+              a[u] = (k0 + 4 * u < CH && j < n) ? ((j >= i) ? A[j * lda + i] : A[i * lda + j]) : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+              const int c = k0 + 4 * u;
+              if (c < CH && j0 + c < n) {
+                const double aij = a[u];
+#pragma unroll
+                for (int q = 0; q < Q; ++q)
+                  if (q < nq) acc[q] += aij * xs[c * XS + q];
+                acc[Q] += fabs(aij);
+              }
+            }
+          }
+        }
       }
+      __syncthreads();  // the buffer is free for the partial sums
     }
 #pragma unroll
-    for (int q = 0; q < 9; ++q) part[wave][lane][q] = acc[q];
+    for (int q = 0; q <= Q; ++q) part[wave][lane][q] = acc[q];
     __syncthreads();
-    if (wave == 0 && i < n) {
-      double tot[9];
+    if (wave == 0) {
+      // the block's 64 rows: residuals, then the maxima of |r|, |x|, |b| per right-hand
+      // side and of the absolute row sums reduced across the wave on their bit patterns (as
+      // atomic_max_nonneg compares them; a NaN stays the maximum), so each workgroup makes
+      // one atomic per statistic (a max: the order does not change the result).  One
+      // column at a time, its sums read back from LDS, to keep few registers live.
+      auto wave_max = [&](double v) {
+        unsigned long long bits = (unsigned long long)__double_as_longlong(v);
 #pragma unroll
-      for (int q = 0; q < 9; ++q) tot[q] = part[0][lane][q] + part[1][lane][q] + part[2][lane][q] + part[3][lane][q];
-      for (int q = 0; q < nq; ++q) {
-        const double r = Bv[i * ldb + q0 + q] - tot[q];
-        R[i * nrhs + q0 + q] = r;
-        atomic_max_nonneg(stats + 3 * (q0 + q) + 0, fabs(r));
-        atomic_max_nonneg(stats + 3 * (q0 + q) + 1, fabs(X[i * ldx + q0 + q]));
-        atomic_max_nonneg(stats + 3 * (q0 + q) + 2, fabs(Bv[i * ldb + q0 + q]));
+        for (int off = 32; off >= 1; off >>= 1) {
+          const unsigned long long o = __shfl_xor(bits, off);
+          bits = o > bits ? o : bits;
+        }
+        return __longlong_as_double((long long)bits);
+      };
+      for (int q = 0; q <= nq; ++q) {
+        const int c = q < nq ? q : Q;  // the last round: the absolute row sums
+        double v0 = 0.0, v1 = 0.0, v2 = 0.0;
+        if (i < n) {
+          const double tot = part[0][lane][c] + part[1][lane][c] + part[2][lane][c] + part[3][lane][c];
+          if (q < nq) {
+            const double r = Bv[i * ldb + q0 + q] - tot;
+            R[i * nrhs + q0 + q] = r;
+            v0 = fabs(r);
+            v1 = fabs(X[i * ldx + q0 + q]);
+            v2 = fabs(Bv[i * ldb + q0 + q]);
+          } else {
+            v0 = tot;
+          }
+        }
+        v0 = wave_max(v0);
+        if (q < nq) {
+          v1 = wave_max(v1);
+          v2 = wave_max(v2);
+          if (lane == 0) {
+            atomic_max_nonneg(stats + 3 * (q0 + q) + 0, v0);
+            atomic_max_nonneg(stats + 3 * (q0 + q) + 1, v1);
+            atomic_max_nonneg(stats + 3 * (q0 + q) + 2, v2);
+          }
+        } else if (lane == 0 && q0 == 0) {
+          atomic_max_nonneg(stats + 3 * nrhs, v0);
+        }
       }
-      if (q0 == 0) atomic_max_nonneg(stats + 3 * nrhs, tot[8]);
     }
     __syncthreads();
   }
@@ -2404,13 +2518,13 @@ __global__ __launch_bounds__(NT) void residual_kernel(int64_t n, const double* _
                                                       int64_t nrhs, const double* __restrict__ X, int64_t ldx,
                                                       const double* __restrict__ Bv, int64_t ldb,
                                                       double* __restrict__ R, double* __restrict__ stats) {
-  __shared__ double part[4][64][9];
+  __shared__ double part[4][64][kResQ + 1];
   residual_rows(n, A, lda, nrhs, X, ldx, Bv, ldb, R, stats, (int64_t)blockIdx.x * 64, part);
 }
 
 __global__ __launch_bounds__(NT) void residual_batched_kernel(const ResDesc* __restrict__ d,
                                                               const uint32_t* __restrict__ prefix, int count) {
-  __shared__ double part[4][64][9];
+  __shared__ double part[4][64][kResQ + 1];
   const uint32_t blk = blockIdx.x;
   int lo = 0, hi = count - 1;  // last m with prefix[m] <= blk
   while (lo < hi) {
