@@ -33,16 +33,18 @@ PEAK_FP64_TFLOPS = 78.6  # MI355X dense FP64 matrix peak
 # (FETCH_SIZE, WRITE_SIZE in KiB) scaled by the counts of a 1 GiB device copy (FETCH x 2,
 # WRITE x 1).  Valid only for the library sources it was measured on (the kernels, the
 # graph and scheduler code that decide what the launch runs, and the compiler flags of the
-# build script; sha256 over them below); for any other sources the benchmark reports null.
+# build script, not the serving loop; sha256 over them below); for any other sources the
+# benchmark reports null.
 TRAFFIC_RECORD = {
-    "sources_sha256": "3e8aed2d65d4eb3ce316c5a38f032214da297de78b138d021654f6d9e6e56fd8",
+    "sources_sha256": "d3ec84a16665126c0a8853eec82ace658b25a17efadb7d6fc404f75714b102e8",
     "n": 16384, "tile": 512,
     "fetch_kib": 32918487.75, "write_kib": 12747953.3125, "fetch_scale": 2.0, "write_scale": 1.0,
 }
 
 
 def sources_digest():
-    """sha256 over the library's native sources (csrc/, sorted by name) and its build script
+    """sha256 over the library's native sources that decide what a factor launch runs
+    (csrc/, sorted by name, without the serving loop's server.cpp) and its build script
     (the compiler flags), or None."""
     import hashlib
 
@@ -51,7 +53,7 @@ def sources_digest():
     h = hashlib.sha256()
     try:
         for name in sorted(os.listdir(src)):
-            if name.endswith((".hip", ".cpp", ".h")):
+            if name.endswith((".hip", ".cpp", ".h")) and name != "server.cpp":
                 with open(os.path.join(src, name), "rb") as f:
                     h.update(name.encode() + b"\0" + f.read())
         with open(os.path.join(pkg, "build.py"), "rb") as f:

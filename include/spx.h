@@ -434,7 +434,7 @@ typedef struct {
   int32_t lanes;      /* worker lanes (streams); <= 0: 2 */
   int32_t max_batch;  /* requests per launch; <= 0: 4096 */
   int32_t num_wg;     /* workgroups per launch; <= 0: fill the GPU */
-  int32_t mixed_min_n; /* mixed-mode requests with n below this run in FP64; <= 0: 4096 */
+  int32_t mixed_min_n; /* mixed-mode requests with n below this run in FP64; <= 0: 16384 */
 } spx_server_opts;
 typedef struct {
   uint64_t submitted, completed, rejected, launches;

@@ -252,15 +252,28 @@ def test_per_request_completion(ctx, host):
 
 
 def test_mixed_ready_at_batch_end(ctx):
+    """Mixed-mode requests that go through the FP32 factor and the batched refinement are
+    final only at the end of their batch; those below mixed_min_n take the FP64 path and
+    complete on their own, as in FP64 mode, with the FP64 mode's bits."""
     from paper_2308_15964_amd import spx
 
-    srv = spx.Server(ctx, 4 << 30, lanes=1)
+    items = mixture(4, seed=43, kappa=1e3)
+    srv = spx.Server(ctx, 4 << 30, lanes=1, mixed_min_n=1)
     try:
-        _, res = run_all(srv, mixture(4, seed=43, kappa=1e3), spx.MODE_MIXED, tol=1e-12)
+        _, res = run_all(srv, items, spx.MODE_MIXED, tol=1e-12)
     finally:
         srv.close()
     for r in res:
         assert r["status"] == 0 and r["t_ready"] == r["t_done"]
+    srv = spx.Server(ctx, 4 << 30, lanes=1)  # default threshold: every request below it
+    try:
+        xs, res = run_all(srv, items, spx.MODE_MIXED, tol=1e-12)
+        xs64, _ = run_all(srv, items, spx.MODE_FP64)
+    finally:
+        srv.close()
+    for x, x64, r in zip(xs, xs64, res):
+        assert r["status"] == 0 and r["method_used"] == 0 and r["t_ready"] <= r["t_done"]
+        assert np.array_equal(x, x64)
 
 
 def test_device_inputs_host_results(ctx):
