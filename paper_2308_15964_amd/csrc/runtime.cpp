@@ -976,6 +976,10 @@ static int batched(spx_ctx* c, int count, const int64_t* n, const double* const*
     d.prec = prec;
     d.n = (int32_t)n[m];
     d.trsm_rows = trsm_rows_of(bs[m]);
+    // a one-shot solve of a one-tile matrix reads only the tile's live lower part (POTRF
+    // and the substitutions stop at the last live row and never read above the
+    // diagonal), so its LOAD packs only the 64x64 blocks there
+    d.load_live = kind == 'P' && nts[m] == 1 ? 1 : 0;
     d.A = dA[m];
     d.lda = lda[m];
     c->hmats[m] = d;

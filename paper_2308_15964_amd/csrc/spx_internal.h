@@ -85,7 +85,8 @@ struct DevMat {
   int32_t nt, b, nrhs, prec;
   int32_t n, trsm_rows;
   int32_t store_acc;  // STORE adds the solution to X instead of overwriting it
-  int32_t pad1;
+  int32_t load_live;  // LOAD packs only the live lower 64x64 blocks of the matrix's one tile
+                      // (a one-shot solve: nothing reads the upper triangle or the padding)
   // caller's dense arrays, used by the LOAD / STORE tasks of batched and served graphs
   const double* dscale;  // packing: A(i,j) d_i d_j (+ shift on the diagonal), or null
   double shift;

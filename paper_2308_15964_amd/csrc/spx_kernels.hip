@@ -1410,11 +1410,22 @@ __device__ void pack_block_s(const double* __restrict__ A, int64_t lda, int64_t 
 
 // A whole tile (ti, tj) by one workgroup, as pack_block_s<64> does each 64x64 block, with
 // the next block's loads issued before the current one goes through LDS, so about two
-// blocks of reads are in flight instead of one.
+// blocks of reads are in flight instead of one.  live_rows > 0: only the blocks on or
+// below the diagonal whose rows start below live_rows are packed (the others are never
+// read by the launch).
 __device__ __noinline__ void pack_tile64(const double* __restrict__ A, int64_t lda, int64_t n, const DevMat& m,
-                                         int ti, int tj, double* __restrict__ s) {
+                                         int ti, int tj, double* __restrict__ s, int live_rows = 0) {
   constexpr int S = 64, PER = S * S / NT;
   const int b = m.b, per = b / S, nblk = per * per;
+  auto live = [&](int q) {
+    const int si = q / per, sj = q % per;
+    return live_rows <= 0 || (sj <= si && si * S < live_rows);
+  };
+  auto next_live = [&](int q) {
+    do ++q;
+    while (q < nblk && !live(q));
+    return q;
+  };
   LDSAS double* sl = lp(s);
   const GLOBAL double* Ag = gp(A);
   GLOBAL double* T = gp(tile_ptr(m, ti, tj));
@@ -1428,9 +1439,11 @@ __device__ __noinline__ void pack_tile64(const double* __restrict__ A, int64_t l
       v[i] = (R < n && C < n) ? (R >= C ? Ag[R * lda + C] : 0.0) : (R == C ? 1.0 : 0.0);
     }
   };
-  load(0, cur);
-  for (int q = 0; q < nblk; ++q) {
-    if (q + 1 < nblk) load(q + 1, nxt);
+  int q = live(0) ? 0 : next_live(0);
+  if (q < nblk) load(q, cur);
+  while (q < nblk) {
+    const int qn = next_live(q);
+    if (qn < nblk) load(qn, nxt);
     const int si = q / per, sj = q % per;
     if (m.dscale) {
       const int64_t R0 = (int64_t)ti * b + si * S, C0 = (int64_t)tj * b + sj * S;
@@ -1463,6 +1476,7 @@ __device__ __noinline__ void pack_tile64(const double* __restrict__ A, int64_t l
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < PER; ++i) cur[i] = nxt[i];
+    q = qn;
   }
 }
 
@@ -1651,7 +1665,7 @@ __device__ __attribute__((noinline)) void run_part_chol(const SchedArgs& a, uint
           tj0 = tj1 = (int)part - ti * (ti + 1) / 2;
         }
         for (int tj = tj0; tj <= tj1; ++tj) {
-          if (S == 64) pack_tile64(m.A, m.lda, m.n, m, ti, tj, lds);
+          if (S == 64) pack_tile64(m.A, m.lda, m.n, m, ti, tj, lds, m.load_live ? tile_active(m, ti) : 0);
           else
             for (int q = 0; q < per * per; ++q) pack_block(m.A, m.lda, m.n, m, ti, tj, q / per, q % per, S, lds);
         }
