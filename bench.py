@@ -36,9 +36,9 @@ PEAK_FP64_TFLOPS = 78.6  # MI355X dense FP64 matrix peak
 # build script, not the serving loop; sha256 over them below); for any other sources the
 # benchmark reports null.
 TRAFFIC_RECORD = {
-    "sources_sha256": "d3ec84a16665126c0a8853eec82ace658b25a17efadb7d6fc404f75714b102e8",
+    "sources_sha256": "ba6ee2989f4e43d5be1e100c3b0fa85ac0dc2fb1497596d8f0bd39111d451c11",
     "n": 16384, "tile": 512,
-    "fetch_kib": 32918487.75, "write_kib": 12747953.3125, "fetch_scale": 2.0, "write_scale": 1.0,
+    "fetch_kib": 33084325.75, "write_kib": 12752533.90625, "fetch_scale": 2.0, "write_scale": 1.0,
 }
 
 
