@@ -152,6 +152,7 @@ struct SchedArgs {
   uint32_t qcap[kLevelsMax];
   uint32_t total_parts;
   uint32_t max_claim;  // parts one pop may claim outside the bulk levels (1 or 4)
+  uint32_t spread_max;  // a task of at most this many parts deals them over the shards (0: none)
   uint32_t ntasks;
   int32_t nlev;     // levels in use (nlev x nshards <= kMaxQueues)
   int32_t nshards;  // queues in use per level (1..kShards); the image's roots use the same count

@@ -1782,15 +1782,42 @@ __device__ __forceinline__ int xcd_id() {
   return (int)(v & (kXcds - 1));
 }
 
-// push into the pushing workgroup's own shard: reserve nparts slots, then fill them
-__device__ __forceinline__ void push_task(const SchedArgs& a, uint32_t s, int home) {
-  const TaskDesc d = a.tasks[s];
-  const uint32_t slot = (uint32_t)(__hip_atomic_fetch_add(ctr_queue(a, d.level, home), (u64)d.nparts << 32,
-                                                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >> 32);
-  u64* q = queue_of(a, d.level, home) + slot;
-  for (uint32_t p = 0; p < d.nparts; ++p)
-    __hip_atomic_store(q + p, ((u64)s << 16) | p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+// Push task s (descriptor d) at shard home of its level: reserve slots, then fill them.
+// In a launch that allows it, a task of at most a.spread_max (<= kSpreadMax) parts deals
+// them over the shards, part p into shard (home + p % w) % S with w = min(nparts, S): the
+// claims of its parts then go to w queue heads at once instead of one after another on a
+// single head (the claims on one head serialise at a microsecond or more each, which
+// spread the starts of a latency-bound substitution's eight-part tasks over up to 30 us).
+// Larger tasks keep their parts together, where multi-part claims take them.
+constexpr uint32_t kSpreadMax = 8;
+__device__ __forceinline__ void push_task(const SchedArgs& a, uint32_t s, const TaskDesc& d, int home) {
+  const uint32_t S = (uint32_t)a.nshards, np = d.nparts;
+  const uint32_t w = np > 1u && np <= a.spread_max && np <= kSpreadMax ? (np < S ? np : S) : 1u;
+  uint32_t slot[kSpreadMax];
+#pragma unroll
+  for (uint32_t k = 0; k < kSpreadMax; ++k) {
+    if (k < w) {
+      uint32_t sh = (uint32_t)home + k;
+      sh -= sh >= S ? S : 0u;
+      const uint32_t cnt = (np - k + w - 1u) / w;  // parts k, k + w, ...
+      slot[k] = (uint32_t)(__hip_atomic_fetch_add(ctr_queue(a, d.level, (int)sh), (u64)cnt << 32, __ATOMIC_RELAXED,
+                                                  __HIP_MEMORY_SCOPE_AGENT) >> 32);
+    }
+  }
+#pragma unroll
+  for (uint32_t k = 0; k < kSpreadMax; ++k) {
+    if (k < w) {
+      uint32_t sh = (uint32_t)home + k;
+      sh -= sh >= S ? S : 0u;
+      u64* q = queue_of(a, d.level, (int)sh) + slot[k];
+      for (uint32_t p = k, e = 0; p < np; p += w, ++e)
+        __hip_atomic_store(q + e, ((u64)s << 16) | p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
   if (a.trace_push) a.trace_push[s] = now_ticks();
+}
+__device__ __forceinline__ void push_task(const SchedArgs& a, uint32_t s, int home) {
+  push_task(a, s, a.tasks[s], home);
 }
 
 // pop, run by all 64 lanes of wave 0: lane i reads the head and tail of queue (level
@@ -1939,13 +1966,17 @@ __device__ void follow_grants(const SchedArgs& a, uint32_t grant, int home) {
   }
 }
 
-// A task whose last predecessor just finished: pushed, or first through its locks.
-__device__ __forceinline__ void start_task(const SchedArgs& a, uint32_t t, int home) {
+// A task whose last predecessor just finished (descriptor d): pushed, or first through its
+// locks.
+__device__ __forceinline__ void start_task(const SchedArgs& a, uint32_t t, const TaskDesc& d, int home) {
   if (!a.coff || a.coff[t] == a.coff[t + 1]) {
-    push_task(a, t, home);
+    push_task(a, t, d, home);
     return;
   }
   follow_grants(a, take_locks_from(a, t, 0u, home), home);
+}
+__device__ __forceinline__ void start_task(const SchedArgs& a, uint32_t t, int home) {
+  start_task(a, t, a.tasks[t], home);
 }
 
 // A task whose last part was just released: its locks go to the next waiting members.
@@ -1959,8 +1990,14 @@ __device__ __forceinline__ void drop_locks(const SchedArgs& a, uint32_t t, int h
 }
 
 // The release rounds of XCD x (see the memory-ordering notes above), run by the 64 lanes
-// of one wave: each lane takes one ring entry at a time (its parts_left decrement and,
-// for a task's last part, the successors' decrements and pushes).
+// of one wave: each lane takes one ring entry at a time (its parts_left decrement and, for
+// a task's last part, the task's locks and done flag); then the successors of every task
+// finished in that pass are dealt over the lanes, one (task, successor) pair per lane, so
+// a panel's fan-out is decremented and pushed in one round of atomics rather than one
+// successor after another.  The j-th successor of a task is pushed into shard (home + j) %
+// S: the siblings of a fan-out wait on several queue heads, whose claims proceed in
+// parallel, while a lone successor stays in the releasing XCD's own shard (with shared
+// shards, every chain task of the overhead study took four times as long).
 __device__ __noinline__ void release_rounds(const SchedArgs& a, int x, int home) {
   const int lane = threadIdx.x & 63;
   uint32_t* lock = a.counters + ctr_ring_lock_idx(x);
@@ -1985,26 +2022,55 @@ __device__ __noinline__ void release_rounds(const SchedArgs& a, int x, int home)
       const u64 t0 = now_ticks();
       for (uint32_t e0 = h; e0 < t; e0 += 64) {
         const uint32_t e = e0 + (uint32_t)lane;
-        if (e >= t) continue;
-        uint32_t task;
-        // the slot was reserved by an appender that writes it next: bounded wait
-        while ((task = __hip_atomic_load(ring + e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) == EMPTY32) {
-          if (now_ticks() - t0 > a.spin_limit) {
-            __hip_atomic_fetch_or(ctr_status(a), (uint32_t)STATUS_TIMEOUT, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            break;
+        uint32_t task = EMPTY32;
+        if (e < t) {
+          // the slot was reserved by an appender that writes it next: bounded wait
+          while ((task = __hip_atomic_load(ring + e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) == EMPTY32) {
+            if (now_ticks() - t0 > a.spin_limit) {
+              __hip_atomic_fetch_or(ctr_status(a), (uint32_t)STATUS_TIMEOUT, __ATOMIC_RELAXED,
+                                    __HIP_MEMORY_SCOPE_AGENT);
+              break;
+            }
+            __builtin_amdgcn_s_sleep(1);
           }
-          __builtin_amdgcn_s_sleep(1);
         }
-        if (task == EMPTY32 || sub_rlx(a.parts_left + task, 1u) != 1u) continue;
-        drop_locks(a, task, home);
-        if (a.tasks[task].type == SPX_T_STORE) {
-          // the release above wrote the STORE's X back: tell the host this matrix is done
-          unsigned int* flag = a.mats[a.tasks[task].mat].done_flag;
-          if (flag) __hip_atomic_store(flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        uint32_t cnt = 0u, first = 0u, last = 0u;
+        if (task != EMPTY32) {  // loaded alongside the decrement
+          first = a.succ_off[task];
+          last = a.succ_off[task + 1];
         }
-        for (uint32_t q = a.succ_off[task]; q < a.succ_off[task + 1]; ++q) {
-          const uint32_t s = a.succ[q];
-          if (sub_rlx(a.pending + s, 1u) == 1u) start_task(a, s, home);
+        if (task != EMPTY32 && sub_rlx(a.parts_left + task, 1u) == 1u) {
+          drop_locks(a, task, home);
+          if (a.tasks[task].type == SPX_T_STORE) {
+            // the release above wrote the STORE's X back: tell the host this matrix is done
+            unsigned int* flag = a.mats[a.tasks[task].mat].done_flag;
+            if (flag) __hip_atomic_store(flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+          }
+          cnt = last - first;
+        }
+        // number the pairs: lane L's finished task owns pairs [off(L), off(L) + cnt(L))
+        uint32_t off = cnt;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+          const uint32_t y = __shfl_up(off, d);
+          if (lane >= d) off += y;
+        }
+        const uint32_t total = __shfl(off, 63);
+        off -= cnt;
+        for (uint32_t i0 = 0; i0 < total; i0 += 64) {
+          const uint32_t i = i0 + (uint32_t)lane;
+          // the owner of pair i: the last lane whose first pair is at most i (offsets do not
+          // decrease over the lanes, and a lane with no pairs shares the next lane's offset)
+          int L = 0;
+#pragma unroll
+          for (int step = 32; step >= 1; step >>= 1)
+            if (__shfl(off, L + step) <= i) L += step;
+          const uint32_t j = i - __shfl(off, L), q = __shfl(first, L) + j;  // successor j of lane L's task
+          if (i < total) {
+            const uint32_t s = a.succ[q];
+            const TaskDesc ds = a.tasks[s];  // loaded alongside the decrement
+            if (sub_rlx(a.pending + s, 1u) == 1u) start_task(a, s, ds, (int)((home + j) % (uint32_t)a.nshards));
+          }
         }
       }
       h = t;
