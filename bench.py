@@ -36,9 +36,9 @@ PEAK_FP64_TFLOPS = 78.6  # MI355X dense FP64 matrix peak
 # build script, not the serving loop; sha256 over them below); for any other sources the
 # benchmark reports null.
 TRAFFIC_RECORD = {
-    "sources_sha256": "9b8d34a5e0e00aaae3d1bf8240d913512cd2a349a3b319d433d13cf306021e1e",
+    "sources_sha256": "6f0868e3f8738ee972d3048a48208c7dd5cbdd6ac2ebe00b511cb305714b4cfb",
     "n": 16384, "tile": 512,
-    "fetch_kib": 33731362.0625, "write_kib": 12753769.15625, "fetch_scale": 2.0, "write_scale": 1.0,
+    "fetch_kib": 33959049.0, "write_kib": 12753931.5, "fetch_scale": 2.0, "write_scale": 1.0,
 }
 
 

@@ -156,7 +156,8 @@ int spx_gemm_graph(int32_t nt, spx_graph** out, int32_t* task_types, uint32_t ca
  *     sixteen priority levels, each split into 4 queues (shards), one per pair of XCDs; a
  *     task is pushed into the shard of the XCD that released its last predecessor (the
  *     j-th successor of one finished task into the j-th shard after it, and in a launch of
- *     one graph the parts of a task of at most 8 parts dealt over the shards), and a
+ *     one graph the parts of a task of at most 8 parts, or a substitution task of at most
+ *     16, dealt over the shards), and a
  *     workgroup serves the highest non-empty level, its own shard first, so pops spread
  *     over 4 queue heads per level (environment SPX_QUEUE_SHARDS = 2, 4 or 8 trades
  *     shards for levels: 32, 16 or 8 levels).  This split, and pops that claim up to 4

@@ -1788,14 +1788,18 @@ __device__ __forceinline__ int xcd_id() {
 // claims of its parts then go to w queue heads at once instead of one after another on a
 // single head (the claims on one head serialise at a microsecond or more each, which
 // spread the starts of a latency-bound substitution's eight-part tasks over up to 30 us).
-// Larger tasks keep their parts together, where multi-part claims take them.
+// Larger tasks keep their parts together, where multi-part claims take them; the
+// substitution tasks, latency-bound, spread up to twice as many (a diagonal solve of 9 to
+// 16 right-hand sides has 16 parts).
 constexpr uint32_t kSpreadMax = 8;
 __device__ __forceinline__ void push_task(const SchedArgs& a, uint32_t s, const TaskDesc& d, int home) {
   const uint32_t S = (uint32_t)a.nshards, np = d.nparts;
-  const uint32_t w = np > 1u && np <= a.spread_max && np <= kSpreadMax ? (np < S ? np : S) : 1u;
-  uint32_t slot[kSpreadMax];
+  const bool subst = d.type >= SPX_T_FTRSM && d.type <= SPX_T_BGEMM;
+  const uint32_t lim = subst ? 2u * a.spread_max : a.spread_max;
+  const uint32_t w = np > 1u && np <= lim && np <= 2u * kSpreadMax ? (np < S ? np : S) : 1u;
+  uint32_t slot[kShards];
 #pragma unroll
-  for (uint32_t k = 0; k < kSpreadMax; ++k) {
+  for (uint32_t k = 0; k < (uint32_t)kShards; ++k) {
     if (k < w) {
       uint32_t sh = (uint32_t)home + k;
       sh -= sh >= S ? S : 0u;
@@ -1805,7 +1809,7 @@ __device__ __forceinline__ void push_task(const SchedArgs& a, uint32_t s, const 
     }
   }
 #pragma unroll
-  for (uint32_t k = 0; k < kSpreadMax; ++k) {
+  for (uint32_t k = 0; k < (uint32_t)kShards; ++k) {
     if (k < w) {
       uint32_t sh = (uint32_t)home + k;
       sh -= sh >= S ? S : 0u;
