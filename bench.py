@@ -36,7 +36,7 @@ PEAK_FP64_TFLOPS = 78.6  # MI355X dense FP64 matrix peak
 # build script, not the serving loop; sha256 over them below); for any other sources the
 # benchmark reports null.
 TRAFFIC_RECORD = {
-    "sources_sha256": "6f0868e3f8738ee972d3048a48208c7dd5cbdd6ac2ebe00b511cb305714b4cfb",
+    "sources_sha256": "4ffbe45b5116fdb37bde4e5e2db5ea6beebcc6374a28566cea19253bd1132ded",
     "n": 16384, "tile": 512,
     "fetch_kib": 33959049.0, "write_kib": 12753931.5, "fetch_scale": 2.0, "write_scale": 1.0,
 }

@@ -2000,8 +2000,9 @@ __device__ __forceinline__ void drop_locks(const SchedArgs& a, uint32_t t, int h
 // a panel's fan-out is decremented and pushed in one round of atomics rather than one
 // successor after another.  The j-th successor of a task is pushed into shard (home + j) %
 // S: the siblings of a fan-out wait on several queue heads, whose claims proceed in
-// parallel, while a lone successor stays in the releasing XCD's own shard (with shared
-// shards, every chain task of the overhead study took four times as long).
+// parallel, while a lone successor stays in the releasing XCD's own shard (dealt to the
+// other shards as well, by its place among the pass's pairs, it left its XCD, and every
+// chain task of the overhead study took four times as long).
 __device__ __noinline__ void release_rounds(const SchedArgs& a, int x, int home) {
   const int lane = threadIdx.x & 63;
   uint32_t* lock = a.counters + ctr_ring_lock_idx(x);
